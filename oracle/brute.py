@@ -1,0 +1,141 @@
+"""TEST INFRASTRUCTURE ONLY: a brute-force IMF for tiny grids, in Python.
+
+Independent of ``imf_oracle.c``: its own rasterizer (exact rational arithmetic,
+lattice directions only) and the definitions applied literally:
+
+* collision measure of placing the tool so that sharp point k touches x:
+  the number (or density) of occupied voxels among {x - k + o : o in T_R}
+  (Eq. access_meas / Eq. imf_1 of Sec. 2.1.3);
+* IMF: the minimum over orientations and sharp points (Eq. imf_1);
+* accessibility: x is accessible iff some collision-free placement puts a sharp
+  point on x (Eq. access_def), enumerated as the union of K placed at every
+  free translation (Eq. sweep).
+"""
+from __future__ import annotations
+
+from fractions import Fraction
+
+import numpy as np
+
+
+def _in_tool(kind, r, L, rh, Lh, o, v):
+    """Exact membership of integer offset o for lattice direction v.
+
+    Returns (in_tool, in_cutter).  Let a = o.v/|v| (axial coordinate) and
+    q^2 = |o|^2 - a^2 (squared distance from the axis)."""
+    r, L, rh, LH = Fraction(r), Fraction(L), Fraction(rh), Fraction(L) + Fraction(Lh)
+    dot = sum(int(a) * int(b) for a, b in zip(o, v))
+    n = sum(int(b) * int(b) for b in v)
+    o2 = sum(int(a) * int(a) for a in o)
+    a2 = Fraction(dot * dot, n)            # a^2 (a has the sign of dot)
+    q2 = Fraction(o2) - a2
+
+    def a_lt(c):   # a < c for c > 0
+        return dot < 0 or a2 < c * c
+
+    def a_ge(c):   # a >= c for c >= 0
+        return dot >= 0 and a2 >= c * c
+
+    cyl = a_lt(L) and q2 <= r * r
+    if kind == 1:
+        # ball of radius r centred at r*d:  |o|^2 - 2 r a <= 0
+        ball = dot >= 0 and Fraction(o2) * Fraction(o2) <= 4 * r * r * a2
+        cut = ball or (a_ge(r) and cyl)
+    else:
+        cut = a_ge(0) and cyl
+    hold = a_ge(L) and a_lt(LH) and q2 <= rh * rh
+    return (cut or hold), cut
+
+
+def raster(tool, v):
+    """Sets T (tool) and K (cutter) of integer offsets, as sorted lists of tuples."""
+    v = [int(c) for c in v]
+    ndim = len(v)
+    r, L, rh, Lh = tool["cutter_r"], tool["cutter_len"], tool["holder_r"], tool["holder_len"]
+    ext = int(np.ceil(max(L + Lh, 2 * r) + max(r, rh))) + 2
+    rng = range(-ext, ext + 1)
+    T, K = [], []
+    if ndim == 2:
+        pts = ((x, y, 0) for y in rng for x in rng)
+    else:
+        pts = ((x, y, z) for z in rng for y in rng for x in rng)
+    for p in pts:
+        t, k = _in_tool(tool["kind"], r, L, rh, Lh, p[:ndim], v)
+        if t:
+            T.append(p)
+        if k:
+            K.append(p)
+    return T, K
+
+
+def _shift_sum(field, offsets, lo, dims):
+    """S(t) = sum_{o in offsets} field(t + o) for t in the box lo + [0, dims)."""
+    nz, ny, nx = field.shape
+    out = np.zeros((dims[2], dims[1], dims[0]), dtype=np.int64)
+    tz = np.arange(dims[2]) + lo[2]
+    ty = np.arange(dims[1]) + lo[1]
+    tx = np.arange(dims[0]) + lo[0]
+    for (ox, oy, oz) in offsets:
+        zz, yy, xx = tz + oz, ty + oy, tx + ox
+        mz = (zz >= 0) & (zz < nz)
+        my = (yy >= 0) & (yy < ny)
+        mx = (xx >= 0) & (xx < nx)
+        sub = field[np.ix_(zz.clip(0, nz - 1), yy.clip(0, ny - 1), xx.clip(0, nx - 1))]
+        out += sub * (mz[:, None, None] & my[None, :, None] & mx[None, None, :])
+    return out
+
+
+def imf(design, fixture, tool, dirs, lam=0.0, tau=0.5, scale=1):
+    """Brute-force f, F_max, fbar, Gamma and accessible masks (bool [nR, ...]).
+
+    ``design`` holds integers in fixed point (``scale`` = 1 for binary)."""
+    design = np.asarray(design, dtype=np.int64)
+    ndim = design.ndim
+    d3 = design.reshape((1,) * (3 - ndim) + design.shape)
+    fix = np.zeros_like(d3) if fixture is None else \
+        np.asarray(fixture).reshape(d3.shape).astype(np.int64)
+    rhoO = np.where(fix > 0, scale, d3)
+    omega0 = fix == 0
+    nz, ny, nx = d3.shape
+    f = np.full(d3.shape, np.iinfo(np.int64).max, dtype=np.int64)
+    gammas, frees = [], []
+    for v in dirs:
+        T, K = raster(tool, v)
+        # gamma_R(x) = min over k of the overlap of the tool placed with k on x
+        gam = np.full(d3.shape, np.iinfo(np.int64).max, dtype=np.int64)
+        for k in K:
+            placed = [(o[0] - k[0], o[1] - k[1], o[2] - k[2]) for o in T]
+            ov = _shift_sum(rhoO, placed, (0, 0, 0), (nx, ny, nz))
+            gam = np.minimum(gam, ov)
+        gammas.append(gam)
+        f = np.minimum(f, gam)
+        frees.append((T, K))
+    fmax = int(f[omega0].max()) if omega0.any() else 0
+    thB = lam * float(fmax)
+    B = omega0 & (f.astype(np.float64) > thB)
+    fbar = np.where(B, f / float(fmax) if fmax else 0.0, 0.0).astype(np.float32)
+    solid = d3.astype(np.float64) > tau * scale
+    gamma_set = B & ~solid
+    # accessibility by sweeping free translations (threshold theta = lambda F_max)
+    masks = []
+    for (T, K) in frees:
+        Tarr = np.array(T)
+        lo = tuple(int(-Tarr[:, a].max()) for a in range(3))
+        dims = tuple(int((nx, ny, nz)[a] + Tarr[:, a].max() - Tarr[:, a].min())
+                     for a in range(3))
+        g = _shift_sum(rhoO, T, lo, dims)
+        free = g.astype(np.float64) <= thB
+        acc = np.zeros(d3.shape, dtype=bool)
+        fz, fy, fx = np.nonzero(free)
+        for k in K:
+            x = fx + lo[0] + k[0]
+            y = fy + lo[1] + k[1]
+            z = fz + lo[2] + k[2]
+            m = (x >= 0) & (x < nx) & (y >= 0) & (y < ny) & (z >= 0) & (z < nz)
+            acc[z[m], y[m], x[m]] = True
+        masks.append(acc & omega0)
+    shp = design.shape
+    return {"imf": f.reshape(shp), "F_max": fmax, "imf_norm": fbar.reshape(shp),
+            "secluded": gamma_set.reshape(shp),
+            "masks": np.stack([m.reshape(shp) for m in masks]),
+            "gammas": np.stack([g.reshape(shp) for g in gammas])}

@@ -1,0 +1,428 @@
+"""Pins of the CPU oracle against things other than itself: closed forms,
+invariants the paper states, and brute force on tiny grids."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute
+from workloads import (TOOL_BALL, TOOL_FLAT, TOOL_RECT2D, circle8, fixture_plate,
+                       lattice26, tool)
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def gauss_counts():
+    out = {}
+    for line in open(os.path.join(GOLD, "gauss_circle.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        r, c = line.split()
+        out[int(r)] = int(c)
+    return out
+
+
+def offsets_set(offs):
+    return set(map(tuple, np.asarray(offs).tolist()))
+
+
+# ---------------------------------------------------------------------------
+# rasterizer
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("r", [3, 4, 10, 12, 14])
+def test_raster_axis_slices_match_gauss_circle(r):
+    """Each slice of an axis-aligned flat cutter is a lattice disc (Gauss circle)."""
+    gc = gauss_counts()
+    L = 7
+    for d, kind in [((0, 0, 1), 1), ((0, 0, 1.0), 0), ((1, 0, 0), 1), ((0, -1, 0), 1)]:
+        dd = np.array(d, dtype=np.int32 if kind == 1 else np.float64)
+        offs, cut = oracle.raster(tool(TOOL_FLAT, r, L, 0, 0), dd, kind)
+        assert cut.all()
+        assert len(offs) == gc[r] * L
+        ax = int(np.nonzero(np.asarray(d))[0][0])
+        sgn = int(np.sign(np.asarray(d)[ax]))
+        vals, counts = np.unique(offs[:, ax] * sgn, return_counts=True)
+        assert list(vals) == list(range(L)) and (counts == gc[r]).all()
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_raster_totals_of_the_workload_tools(kind):
+    """Axis-aligned voxel totals of the three tools of the 3D workloads.
+
+    Flat r3 L40: 29*40 = 1160; holder r10 L40: 317*40 = 12680.  Ball r4 L60:
+    cylinder 49*56 = 2744 plus the lower half-ball slices 45+37+21+1 = 104 ->
+    2848; holder r14 L60: 613*60 = 36780.  Flat r3 L80: 2320; holder r12 L80:
+    441*80 = 35280."""
+    d = np.array([0, 0, 1], dtype=np.int32 if kind == 1 else np.float64)
+    for tl, nk, nh in [(tool(TOOL_FLAT, 3, 40, 10, 40), 1160, 12680),
+                       (tool(TOOL_BALL, 4, 60, 14, 60), 2848, 36780),
+                       (tool(TOOL_FLAT, 3, 80, 12, 80), 2320, 35280)]:
+        offs, cut = oracle.raster(tl, d, kind)
+        assert cut.sum() == nk and len(offs) - cut.sum() == nh
+
+
+def test_raster_ball_end_lowest_point_is_origin():
+    offs, cut = oracle.raster(tool(TOOL_BALL, 4, 60, 14, 60), np.array([0, 0, 1], np.int32))
+    assert offs[:, 2].min() == 0
+    assert offsets_set(offs[offs[:, 2] == 0]) == {(0, 0, 0)}
+
+
+def test_raster_2d_rectangles():
+    """C1 tool along +y: cutter 3 x 24 and holder 9 x 30 (half-open axial test)."""
+    offs, cut = oracle.raster(tool(TOOL_RECT2D, 1.5, 24, 4.5, 30), np.array([0, 1], np.int32))
+    assert cut.sum() == 3 * 24 and len(offs) == 3 * 24 + 9 * 30
+    k = offs[cut]
+    assert set(k[:, 0]) == {-1, 0, 1} and k[:, 1].min() == 0 and k[:, 1].max() == 23
+    h = offs[~cut]
+    assert h[:, 1].min() == 24 and h[:, 1].max() == 53 and set(h[:, 0]) == set(range(-4, 5))
+
+
+def test_raster_antipodal_symmetry_lattice():
+    """raster(-v) = -raster(v) for every lattice direction (exact integer forms)."""
+    for tl in [tool(TOOL_FLAT, 3, 40, 10, 40), tool(TOOL_BALL, 4, 20, 6, 10)]:
+        for v in lattice26():
+            a, ca = oracle.raster(tl, v)
+            b, cb = oracle.raster(tl, -v)
+            assert offsets_set(a) == offsets_set(-b)
+            assert offsets_set(a[ca]) == offsets_set(-b[cb])
+
+
+def test_raster_axis_permutation_symmetry_lattice():
+    """Permuting the axes of v permutes the raster."""
+    tl = tool(TOOL_BALL, 3, 12, 5, 6)
+    for v in [(1, 1, 0), (1, 1, 1), (0, 1, -1), (1, 0, 0)]:
+        v = np.array(v, np.int32)
+        a, _ = oracle.raster(tl, v)
+        for perm in [(1, 2, 0), (2, 0, 1), (1, 0, 2)]:
+            b, _ = oracle.raster(tl, v[list(perm)])
+            assert offsets_set(a[:, list(perm)]) == offsets_set(b)
+
+
+def test_raster_lattice_matches_exact_rational_brute_force():
+    for tl in [tool(TOOL_FLAT, 1.5, 5, 3, 4), tool(TOOL_BALL, 2, 6, 3.5, 3)]:
+        for v in lattice26()[::3]:
+            T, K = brute.raster(tl, v)
+            offs, cut = oracle.raster(tl, v)
+            assert offsets_set(offs) == set(T)
+            assert offsets_set(offs[cut]) == set(K)
+    for v in circle8():
+        tl = tool(TOOL_RECT2D, 1.5, 6, 2.5, 4)
+        T, K = brute.raster(tl, v)
+        offs, cut = oracle.raster(tl, v)
+        assert {p[:2] for p in offsets_set(offs)} == {p[:2] for p in T}
+
+
+def test_raster_float_axis_equals_lattice_axis():
+    tl = tool(TOOL_BALL, 4, 60, 14, 60)
+    for ax in range(3):
+        for s in (1, -1):
+            v = np.zeros(3, np.int32)
+            v[ax] = s
+            a, ca = oracle.raster(tl, v, 1)
+            b, cb = oracle.raster(tl, v.astype(np.float64), 0)
+            assert offsets_set(a) == offsets_set(b) and ca.sum() == cb.sum()
+
+
+def test_raster_rejects_bad_input():
+    with pytest.raises(ValueError):
+        oracle.raster(tool(TOOL_FLAT, 3, 40, 10, 40), np.array([0, 0, 1.1]), 0)
+    with pytest.raises(ValueError):
+        oracle.raster(tool(TOOL_RECT2D, 1.5, 4, 3, 3), np.array([0, 0, 1], np.int32), 1)
+    with pytest.raises(ValueError):   # lattice mode needs half-integer sizes
+        oracle.raster(tool(TOOL_FLAT, 3.3, 40, 10, 40), np.array([0, 0, 1], np.int32), 1)
+
+
+# ---------------------------------------------------------------------------
+# overlap (collision measure) closed forms
+# ---------------------------------------------------------------------------
+
+def _interval_overlap(a0, a1, b0, b1):
+    return max(0, min(a1, b1) - max(a0, b0))
+
+
+def test_overlap_box_design_rect_tool_closed_form():
+    """Box design x rectangle-union tool: g is a sum of products of 1D interval
+    overlaps (Eq. ident as vol[O n (t + T)])."""
+    n = 40
+    d = np.zeros((n, n), np.uint8)
+    bx0, bx1, by0, by1 = 7, 19, 11, 30
+    d[by0:by1, bx0:bx1] = 1
+    tl = tool(TOOL_RECT2D, 1.5, 6, 3.5, 5)   # cutter x in [-1,1], y in [0,6); holder x in [-3,3], y in [6,11)
+    req = oracle.Request(d, tools=tl, dirs=np.array([[0, 1]], np.int32), dir_kind=1)
+    g, lo = oracle.overlap_full(req, 0)
+    rects = [(-1, 2, 0, 6), (-3, 4, 6, 11)]
+    for ty in range(g.shape[1]):
+        for tx in range(g.shape[2]):
+            t = (tx + lo[0], ty + lo[1])
+            exp = sum(_interval_overlap(t[0] + x0, t[0] + x1, bx0, bx1) *
+                      _interval_overlap(t[1] + y0, t[1] + y1, by0, by1)
+                      for (x0, x1, y0, y1) in rects)
+            assert g[0, ty, tx] == exp
+
+
+def test_overlap_sum_rule_and_minkowski_support():
+    """sum_t g(t) = (sum rho_O) |T|, and {g > 0} = O (+) (-T) exactly."""
+    rng = np.random.default_rng(3)
+    d = (rng.random((12, 13, 14)) < 0.2).astype(np.uint8)
+    tl = tool(TOOL_BALL, 2, 6, 3, 3)
+    for v in [(0, 0, 1), (1, 1, 1), (-1, 0, 1)]:
+        req = oracle.Request(d, tools=tl, dirs=np.array([v], np.int32), dir_kind=1)
+        g, lo = oracle.overlap_full(req, 0)
+        offs, _ = oracle.raster(tl, np.array(v, np.int32))
+        assert g.sum() == int(d.sum()) * len(offs)
+        occ = np.argwhere(d)[:, ::-1]   # (x, y, z)
+        mink = {tuple(p - o) for p in occ for o in offs}
+        got = {(x + lo[0], y + lo[1], z + lo[2]) for z, y, x in np.argwhere(g > 0)}
+        assert got == mink
+
+
+def test_single_voxel_tool_gives_rho():
+    """A one-voxel tool: g = rho_O and f = rho_O (with fixture union as max)."""
+    rng = np.random.default_rng(5)
+    d = (rng.integers(0, 1 << 24, size=(9, 10, 11)) / float(1 << 24)).astype(np.float32)
+    fx = fixture_plate(d.shape, 2)
+    tl = tool(TOOL_FLAT, 0.5, 0.5, 0, 0)
+    offs, _ = oracle.raster(tl, np.array([0, 0, 1], np.int32))
+    assert offsets_set(offs) == {(0, 0, 0)}
+    req = oracle.Request(d, fx, tools=tl, dirs=np.array([[0, 0, 1]], np.int32), dir_kind=1)
+    out = oracle.imf(req, masks=False)
+    rho_o = np.where(fx > 0, 1.0, d.astype(np.float64))
+    assert np.array_equal(out["imf"], rho_o)
+
+
+# ---------------------------------------------------------------------------
+# full IMF against brute force
+# ---------------------------------------------------------------------------
+
+def _compare_with_brute(d, fx, tl, dirs, lam=0.0, scale=1):
+    b = brute.imf((np.asarray(d, np.float64) * scale).astype(np.int64), fx, tl, dirs,
+                  lam=lam, scale=scale)
+    req = oracle.Request(d, fx, tools=tl, dirs=dirs, dir_kind=1, lam=lam,
+                         density=(scale != 1))
+    o = oracle.imf(req)
+    nx = req.nx
+    assert np.array_equal(o["imf"] * scale, b["imf"].astype(np.float64))
+    assert o["F_max"] * scale == b["F_max"]
+    assert np.array_equal(o["imf_norm"], b["imf_norm"])
+    assert np.array_equal(o["secluded"].astype(bool), b["secluded"])
+    m = oracle.unpack_masks(o["masks"], nx).reshape(b["masks"].shape)
+    md = oracle.unpack_masks(o["masks_dil"], nx).reshape(b["masks"].shape)
+    assert np.array_equal(m, b["masks"])
+    assert np.array_equal(md, b["masks"])
+    return o
+
+
+def test_oracle_equals_brute_force_3d_binary():
+    rng = np.random.default_rng(11)
+    d = (rng.random((8, 8, 8)) < 0.25).astype(np.uint8)
+    fx = fixture_plate(d.shape, 2)
+    _compare_with_brute(d, fx, tool(TOOL_FLAT, 1, 3, 2, 2), lattice26()[::2])
+
+
+def test_oracle_equals_brute_force_2d_binary():
+    rng = np.random.default_rng(12)
+    d = (rng.random((12, 12)) < 0.3).astype(np.uint8)
+    fx = fixture_plate(d.shape, 2)
+    _compare_with_brute(d, fx, tool(TOOL_RECT2D, 1.5, 4, 2.5, 3), circle8())
+
+
+def test_oracle_equals_brute_force_2d_density_with_allowance():
+    rng = np.random.default_rng(13)
+    d = (rng.integers(0, (1 << 24) + 1, size=(12, 12)) / float(1 << 24)).astype(np.float32)
+    fx = fixture_plate(d.shape, 1)
+    _compare_with_brute(d, fx, tool(TOOL_RECT2D, 1.5, 4, 2.5, 3), circle8(), lam=0.05,
+                        scale=1 << 24)
+
+
+def test_oracle_equals_brute_force_ball_tool():
+    rng = np.random.default_rng(14)
+    d = (rng.random((7, 8, 9)) < 0.2).astype(np.uint8)
+    _compare_with_brute(d, None, tool(TOOL_BALL, 1.5, 4, 2, 2), lattice26()[1::3])
+
+
+# ---------------------------------------------------------------------------
+# invariants stated by the paper
+# ---------------------------------------------------------------------------
+
+def _req3(d, fx=None, dirs=None, tl=None, **kw):
+    tl = tl or tool(TOOL_FLAT, 1.5, 5, 3, 4)
+    dirs = lattice26() if dirs is None else dirs
+    return oracle.Request(d, fx, tools=tl, dirs=dirs, dir_kind=1, **kw)
+
+
+def test_empty_design_is_fully_accessible():
+    d = np.zeros((10, 11, 12), np.uint8)
+    o = oracle.imf(_req3(d))
+    assert (o["imf"] == 0).all() and o["F_max"] == 0 and (o["imf_norm"] == 0).all()
+    assert not o["secluded"].any()
+    m = oracle.unpack_masks(o["masks"], 12)
+    assert m.all()
+
+
+def test_imf_bounds_and_part_is_inaccessible():
+    """f >= rho_O (the sharp point itself lies in the tool), so Omega is in B and
+    never accessible; fbar in [0, 1] with maximum exactly 1."""
+    rng = np.random.default_rng(21)
+    d = (rng.random((10, 10, 10)) < 0.3).astype(np.uint8)
+    fx = fixture_plate(d.shape, 2)
+    o = oracle.imf(_req3(d, fx))
+    rho_o = np.maximum(d, fx)
+    assert (o["imf"] >= rho_o).all()
+    part = (d > 0) & (fx == 0)
+    assert (o["imf"][part] > 0).all()
+    m = oracle.unpack_masks(o["masks"], 10)
+    assert not (m & part[None]).any()
+    nb = o["imf_norm"]
+    assert nb.min() >= 0 and nb.max() == 1.0
+    assert not (o["secluded"].astype(bool) & (d > 0)).any()
+
+
+def test_masks_union_is_complement_of_B():
+    """union_R A_R = Omega_0 minus B (Algorithm 1 classification vs Eq. A)."""
+    rng = np.random.default_rng(22)
+    d = (rng.random((10, 10, 10)) < 0.3).astype(np.uint8)
+    fx = fixture_plate(d.shape, 2)
+    o = oracle.imf(_req3(d, fx))
+    acc = oracle.unpack_masks(o["masks"], 10).any(axis=0)
+    B = (fx == 0) & (o["imf"] > 0)
+    assert np.array_equal(acc, (fx == 0) & ~B)
+    assert np.array_equal(o["secluded"].astype(bool), B & (d == 0))
+
+
+def test_more_orientations_never_increase_imf():
+    rng = np.random.default_rng(23)
+    d = (rng.random((10, 10, 10)) < 0.3).astype(np.uint8)
+    dirs = lattice26()
+    prev = None
+    prev_acc = None
+    for k in (3, 9, 18, 26):
+        o = oracle.imf(_req3(d, dirs=dirs[:k]))
+        acc = oracle.unpack_masks(o["masks"], 10).any(axis=0)
+        if prev is not None:
+            assert (o["imf"] <= prev).all()
+            assert (acc >= prev_acc).all()
+        prev, prev_acc = o["imf"], acc
+
+
+def test_more_sharp_points_never_increase_imf():
+    """Sec. 2.1.5: sampling the cutter more densely can only lower the IMF
+    (tip subset of boundary subset of all cutter voxels)."""
+    rng = np.random.default_rng(24)
+    d = (rng.random((10, 10, 10)) < 0.3).astype(np.uint8)
+    f = {s: oracle.imf(_req3(d, sharp=s), masks=False)["imf"] for s in (0, 1, 2)}
+    assert (f[0] <= f[1]).all() and (f[1] <= f[2]).all()
+    assert (f[0] < f[2]).any()
+
+
+def test_adding_material_never_decreases_imf():
+    rng = np.random.default_rng(25)
+    d = (rng.random((10, 10, 10)) < 0.2).astype(np.uint8)
+    d2 = d | (rng.random(d.shape) < 0.1).astype(np.uint8)
+    f1 = oracle.imf(_req3(d), masks=False)["imf"]
+    f2 = oracle.imf(_req3(d2), masks=False)["imf"]
+    assert (f2 >= f1).all()
+
+
+def test_translation_equivariance():
+    rng = np.random.default_rng(26)
+    core = (rng.random((6, 6, 6)) < 0.4).astype(np.uint8)
+    a = np.zeros((14, 14, 14), np.uint8)
+    b = np.zeros_like(a)
+    a[3:9, 4:10, 2:8] = core
+    b[5:11, 4:10, 5:11] = core          # shift (dx, dy, dz) = (3, 0, 2)
+    fa = oracle.imf(_req3(a), masks=False)["imf"]
+    fb = oracle.imf(_req3(b), masks=False)["imf"]
+    assert np.array_equal(fa[:-2, :, :-3], fb[2:, :, 3:])
+
+
+def test_density_imf_is_between_binary_thresholds():
+    """Scaling a binary design by a density c in (0, 1] scales f exactly by c."""
+    rng = np.random.default_rng(27)
+    d = (rng.random((9, 9, 9)) < 0.3).astype(np.uint8)
+    c = 0.375   # on the 2^-24 grid
+    fb = oracle.imf(_req3(d), masks=False)["imf"]
+    fd = oracle.imf(_req3((d * c).astype(np.float32)), masks=False)["imf"]
+    assert np.array_equal(fd, fb * c)
+
+
+# ---------------------------------------------------------------------------
+# accessibility closed forms
+# ---------------------------------------------------------------------------
+
+def test_slot_depth_closed_form_2d():
+    """A 5-wide slot of depth 20 in a solid block, tool from above (d = +y):
+    the 3-wide cutter fits, the 9-wide holder stops at the top face, so slot
+    voxels are reachable exactly down to L = 8 below the top."""
+    nx, ny = 40, 60
+    d = np.zeros((ny, nx), np.uint8)
+    d[:40, :] = 1
+    d[20:40, 18:23] = 0
+    tl = tool(TOOL_RECT2D, 1.5, 8, 4.5, 10)
+    req = oracle.Request(d, tools=tl, dirs=np.array([[0, 1]], np.int32), dir_kind=1)
+    o = oracle.imf(req)
+    acc = oracle.unpack_masks(o["masks"], nx)[0, 0]
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    slot = (yy >= 20) & (yy < 40) & (xx >= 18) & (xx < 23)
+    expect = (yy >= 40) | (slot & (yy >= 32))
+    assert np.array_equal(acc, expect)
+    assert np.array_equal(o["secluded"].astype(bool), slot & (yy < 32))
+
+
+def test_pocket_corners_closed_form_3d():
+    """A 5x5 square pocket entered from above by a radius-1 flat cutter (a plus
+    shaped raster): the pocket's 4 corner columns are never touched, and the
+    reachable depth is L below the top face."""
+    n = 20
+    d = np.zeros((n + 12, n, n), np.uint8)
+    d[:16] = 1
+    c = 10
+    d[4:16, c - 2:c + 3, c - 2:c + 3] = 0
+    tl = tool(TOOL_FLAT, 1, 5, 4, 6)
+    req = oracle.Request(d, tools=tl, dirs=np.array([[0, 0, 1]], np.int32), dir_kind=1)
+    o = oracle.imf(req)
+    acc = oracle.unpack_masks(o["masks"], n)[0]
+    zz, yy, xx = np.mgrid[0:n + 12, 0:n, 0:n]
+    pocket = (zz >= 4) & (zz < 16) & (abs(xx - c) <= 2) & (abs(yy - c) <= 2)
+    corner = (abs(xx - c) == 2) & (abs(yy - c) == 2)
+    expect = (zz >= 16) | (pocket & (zz >= 11) & ~corner)
+    assert np.array_equal(acc, expect)
+
+
+def test_sealed_cavity_is_secluded_and_large_cavity_is_not():
+    """A closed shell: a cavity smaller than the tool is secluded in every
+    orientation.  A cavity that holds the whole tool is reported accessible:
+    the measure has no path-connectedness test (Sec. 4 limitation)."""
+    tl = tool(TOOL_FLAT, 1, 3, 1, 2)   # whole tool fits a 3x3x5 box
+    small = np.ones((12, 12, 12), np.uint8)
+    small[5:8, 5:8, 5:7] = 0
+    o = oracle.imf(_req3(small, tl=tl))
+    cav = small == 0
+    assert o["secluded"].astype(bool)[cav].all()
+    big = np.ones((20, 20, 20), np.uint8)
+    big[4:16, 4:16, 4:16] = 0
+    o = oracle.imf(_req3(big, tl=tl))
+    cav = big == 0
+    acc = oracle.unpack_masks(o["masks"], 20).any(axis=0)
+    zz, yy, xx = np.mgrid[0:20, 0:20, 0:20]
+    inner = (zz >= 8) & (zz < 12) & (yy >= 8) & (yy < 12) & (xx >= 8) & (xx < 12)
+    assert acc[inner].all() and not o["secluded"].astype(bool)[inner].any()
+    assert cav[inner].all()
+
+
+def test_fixture_blocks_tools_from_below():
+    """With a fixture plate at the bottom, a tool coming from below (d = -z)
+    collides with it unless the whole tool clears the plate."""
+    d = np.zeros((16, 10, 10), np.uint8)
+    fx = fixture_plate(d.shape, 3)
+    tl = tool(TOOL_FLAT, 1, 3, 2, 3)
+    req = oracle.Request(d, fx, tools=tl, dirs=np.array([[0, 0, -1], [0, 0, 1]], np.int32),
+                         dir_kind=1)
+    o = oracle.imf(req)
+    m = oracle.unpack_masks(o["masks"], 10)
+    # tip + cutter + holder span 6 slices below the touched voxel's tip: a voxel
+    # is reachable from below only if the lowest tool slice clears z = 3
+    assert not m[0, 3:6].any() and m[0, 6:].all()
+    assert m[1, 3:].all()               # from above everything off the plate
+    assert not m[:, :3].any()           # fixture voxels are outside Omega_0

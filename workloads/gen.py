@@ -1,0 +1,306 @@
+"""Seeded generators for designs, fixtures, tools and orientation sets.
+
+Conventions shared by every consumer:
+
+* arrays are indexed ``[z][y][x]`` (``[y][x]`` in 2D), x fastest, voxel centres
+  at integer indices;
+* the random source is ``numpy.random.Generator(PCG64(seed))``; when a fill band
+  is missed the draw is repeated with ``seed + 1000*k`` (k = 1, 2, ...);
+* density designs are float32 values on the 2**-24 grid in [0, 1], so every
+  overlap sum is an exact multiple of 2**-24;
+* a direction is the unit tool axis pointing from the cutter tip toward the
+  holder (the tool approaches the part along ``-d``).
+
+The workloads stand in for the paper's parts (cantilever, GE bracket,
+quadcopter and support bracket of the Results section), whose geometry is not
+available: the grids span the paper's scales up to 384^3.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# tool kinds, same numbering as the C interface
+TOOL_FLAT = 0
+TOOL_BALL = 1
+TOOL_RECT2D = 2
+
+Q24 = float(1 << 24)
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+# --------------------------------------------------------------------------
+# tools
+# --------------------------------------------------------------------------
+
+def tool(kind: int, cutter_r: float, cutter_len: float, holder_r: float,
+         holder_len: float) -> dict:
+    """A cutter of radius/half-width ``cutter_r`` occupying axial [0, L) and a
+    holder of radius/half-width ``holder_r`` occupying axial [L, L+holder_len)."""
+    return {"kind": int(kind), "cutter_r": float(cutter_r),
+            "cutter_len": float(cutter_len), "holder_r": float(holder_r),
+            "holder_len": float(holder_len)}
+
+
+TOOL_C1 = tool(TOOL_RECT2D, 1.5, 24.0, 4.5, 30.0)   # 3x24 cutter, 9x30 holder
+TOOL_C2 = tool(TOOL_FLAT, 3.0, 40.0, 10.0, 40.0)    # flat end mill
+TOOL_C3 = tool(TOOL_BALL, 4.0, 60.0, 14.0, 60.0)    # ball end mill
+TOOL_C5 = tool(TOOL_FLAT, 3.0, 80.0, 12.0, 80.0)
+
+
+# --------------------------------------------------------------------------
+# orientation sets (input data, shared byte for byte)
+# --------------------------------------------------------------------------
+
+def circle8() -> np.ndarray:
+    """The 8 lattice directions of the plane, as int32 [8, 2] (x, y)."""
+    return np.array([(1, 0), (1, 1), (0, 1), (-1, 1), (-1, 0), (-1, -1),
+                     (0, -1), (1, -1)], dtype=np.int32)
+
+
+def lattice26() -> np.ndarray:
+    """The 26 face/edge/corner directions of the cube, int32 [26, 3] (x, y, z)."""
+    out = []
+    for z in (-1, 0, 1):
+        for y in (-1, 0, 1):
+            for x in (-1, 0, 1):
+                if (x, y, z) != (0, 0, 0):
+                    out.append((x, y, z))
+    return np.array(out, dtype=np.int32)
+
+
+def fib_hemisphere(n: int) -> np.ndarray:
+    """n directions on the upper hemisphere, float64 [n, 3] (x, y, z).
+
+    z_i = 1 - (i + 1/2)/n, phi_i = i*pi*(3 - sqrt 5)."""
+    i = np.arange(n, dtype=np.float64)
+    z = 1.0 - (i + 0.5) / n
+    phi = i * math.pi * (3.0 - math.sqrt(5.0))
+    s = np.sqrt(1.0 - z * z)
+    return np.stack([s * np.cos(phi), s * np.sin(phi), z], axis=1)
+
+
+def unit_rows(v: np.ndarray) -> np.ndarray:
+    v = np.asarray(v, dtype=np.float64)
+    return v / np.linalg.norm(v, axis=1, keepdims=True)
+
+
+# --------------------------------------------------------------------------
+# designs
+# --------------------------------------------------------------------------
+
+def design_2d_discs_rects(n: int = 128, seed: int = 7627001,
+                          band=(0.35, 0.45)) -> np.ndarray:
+    """Union of 12 discs and 8 axis-aligned rectangles, u8 [n, n]."""
+    s = n / 128.0
+    yy, xx = np.mgrid[0:n, 0:n]
+    for k in range(64):
+        r = _rng(seed + 1000 * k)
+        img = np.zeros((n, n), dtype=bool)
+        for _ in range(12):
+            cx, cy = r.uniform(0, n, size=2)
+            rad = r.uniform(6, 20) * s
+            img |= (xx - cx) ** 2 + (yy - cy) ** 2 <= rad * rad
+        for _ in range(8):
+            cx, cy = r.uniform(0, n, size=2)
+            w, h = (r.integers(8, 41, size=2) * s).round().astype(int)
+            w, h = max(w, 1), max(h, 1)
+            x0, y0 = int(math.floor(cx - w / 2)), int(math.floor(cy - h / 2))
+            img[max(y0, 0):max(y0 + h, 0), max(x0, 0):max(x0 + w, 0)] = True
+        fill = img.mean()
+        if band[0] <= fill <= band[1]:
+            return img.astype(np.uint8)
+    raise RuntimeError("fill band not reached")
+
+
+def design_3d_boxes_cyls(n: int = 128, seed: int = 7627002,
+                         band=(0.25, 0.35)) -> np.ndarray:
+    """10 boxes and 10 cylinders minus 10 through-holes, u8 [n, n, n]."""
+    s = n / 128.0
+    zz, yy, xx = np.meshgrid(np.arange(n), np.arange(n), np.arange(n),
+                             indexing="ij")
+    coords = (xx, yy, zz)
+    for k in range(64):
+        r = _rng(seed + 1000 * k)
+        vol = np.zeros((n, n, n), dtype=bool)
+        for _ in range(10):
+            c = r.uniform(0, n, size=3)
+            sides = np.maximum((r.integers(16, 65, size=3) * s).round(), 1)
+            m = np.ones_like(vol)
+            for a in range(3):
+                lo = int(math.floor(c[a] - sides[a] / 2))
+                m &= (coords[a] >= lo) & (coords[a] < lo + int(sides[a]))
+            vol |= m
+        for _ in range(10):
+            ax = int(r.integers(0, 3))
+            rad = r.uniform(4, 14) * s
+            ln = max(int(round(r.uniform(20, 96) * s)), 1)
+            c = r.uniform(0, n, size=3)
+            p, q = [a for a in range(3) if a != ax]
+            m = (coords[p] - c[p]) ** 2 + (coords[q] - c[q]) ** 2 <= rad * rad
+            lo = int(math.floor(c[ax] - ln / 2))
+            m &= (coords[ax] >= lo) & (coords[ax] < lo + ln)
+            vol |= m
+        for _ in range(10):
+            ax = int(r.integers(0, 3))
+            rad = r.uniform(2, 6) * s
+            c = r.uniform(0, n, size=3)
+            p, q = [a for a in range(3) if a != ax]
+            vol &= ~((coords[p] - c[p]) ** 2 + (coords[q] - c[q]) ** 2
+                     <= rad * rad)
+        fill = vol.mean()
+        if band[0] <= fill <= band[1]:
+            return vol.astype(np.uint8)
+    raise RuntimeError("fill band not reached")
+
+
+def _periodic_gauss_filter(a: np.ndarray, sigma: float) -> np.ndarray:
+    """Separable Gaussian filter (truncated at 4 sigma) with periodic wrap."""
+    out = np.fft.rfftn(a)
+    half = int(math.ceil(4 * sigma))
+    taps = np.exp(-0.5 * (np.arange(-half, half + 1) / sigma) ** 2)
+    taps /= taps.sum()
+    for ax in range(a.ndim):
+        n = a.shape[ax]
+        ker = np.zeros(n)
+        for j, t in zip(range(-half, half + 1), taps):
+            ker[j % n] += t
+        kf = np.fft.rfft(ker) if ax == a.ndim - 1 else np.fft.fft(ker)
+        shape = [1] * a.ndim
+        shape[ax] = kf.shape[0]
+        out = out * kf.reshape(shape)
+    return np.fft.irfftn(out, s=a.shape, axes=tuple(range(a.ndim)))
+
+
+def quantize_q24(rho: np.ndarray) -> np.ndarray:
+    """Round to the 2**-24 grid and clip to [0, 1]; float32 (exactly)."""
+    q = np.rint(np.clip(rho, 0.0, 1.0) * Q24) / Q24
+    return q.astype(np.float32)
+
+
+def smooth_noise(shape, seed: int, sigma: float = 4.0) -> np.ndarray:
+    """Standardized Gaussian-filtered white noise (float64)."""
+    r = _rng(seed)
+    n = _periodic_gauss_filter(r.standard_normal(shape), sigma)
+    n -= n.mean()
+    n /= n.std()
+    return n
+
+
+def design_density(n: int = 256, seed: int = 7627003, mean: float = 0.35,
+                   ndim: int = 3, sigma: float = 4.0) -> np.ndarray:
+    """Sigmoid of smooth noise with mean ``mean`` (+-0.001), on the 2**-24 grid."""
+    shape = (n,) * ndim
+    nz = smooth_noise(shape, seed, sigma).astype(np.float32)
+    lo, hi = -6.0, 6.0
+    for _ in range(60):
+        c = 0.5 * (lo + hi)
+        m = float(np.mean(1.0 / (1.0 + np.exp(-6.0 * (nz - np.float32(c)))),
+                          dtype=np.float64))
+        if abs(m - mean) <= 0.0005:
+            break
+        if m > mean:
+            lo = c
+        else:
+            hi = c
+    rho = 1.0 / (1.0 + np.exp(-6.0 * (nz.astype(np.float64) - c)))
+    return quantize_q24(rho)
+
+
+def perturb_density(rho: np.ndarray, seed: int, amp: float = 0.05) -> np.ndarray:
+    """One TO-loop update stand-in: rho + amp * smooth noise, clipped, quantized."""
+    n = smooth_noise(rho.shape, seed)
+    return quantize_q24(rho.astype(np.float64) + amp * n)
+
+
+# --------------------------------------------------------------------------
+# fixtures
+# --------------------------------------------------------------------------
+
+def fixture_plate(shape, thickness: int = 6) -> np.ndarray:
+    """A plate on the low end of the last axis (z < t in 3D, y < t in 2D)."""
+    f = np.zeros(shape, dtype=np.uint8)
+    f[:thickness] = 1
+    return f
+
+
+def fixture_plate_clamps(n: int = 384) -> np.ndarray:
+    """Plate z < 6 plus clamp blocks x in [0,16) and [n-16,n), z in [6,48)."""
+    f = fixture_plate((n, n, n), 6)
+    s = n / 384.0
+    w, zt = int(round(16 * s)), int(round(48 * s))
+    f[6:zt, :, :w] = 1
+    f[6:zt, :, n - w:] = 1
+    return f
+
+
+# --------------------------------------------------------------------------
+# named workloads
+# --------------------------------------------------------------------------
+
+@dataclass
+class Workload:
+    name: str
+    ndim: int
+    design: np.ndarray
+    fixture: np.ndarray | None
+    tool: dict
+    dir_kind: int          # 0 = float64 unit vectors, 1 = int32 lattice vectors
+    dirs: np.ndarray
+    density: bool
+    lam: float
+    tau: float = 0.5
+    extra: dict = field(default_factory=dict)
+
+
+def c1(n: int = 128) -> Workload:
+    """2D n^2 binary design, 8 lattice directions, direct correlation."""
+    d = design_2d_discs_rects(n)
+    return Workload("c1_2d_%d_x8" % n, 2, d, fixture_plate(d.shape, 4),
+                    TOOL_C1, 1, circle8(), False, 0.0)
+
+
+def c2(n: int = 128, tool_=None) -> Workload:
+    """3D n^3 binary design, 26 lattice directions."""
+    d = design_3d_boxes_cyls(n)
+    return Workload("c2_3d_%d_x26" % n, 3, d, fixture_plate(d.shape, 6),
+                    tool_ or TOOL_C2, 1, lattice26(), False, 0.0)
+
+
+def c3(n: int = 256, n_dirs: int = 130, tool_=None) -> Workload:
+    """3D n^3 density design, Fibonacci-hemisphere directions, lambda 0.01."""
+    d = design_density(n)
+    return Workload("c3_3d_density_%d_x%d" % (n, n_dirs), 3, d,
+                    fixture_plate(d.shape, 6), tool_ or TOOL_C3, 0,
+                    fib_hemisphere(n_dirs), True, 0.01)
+
+
+def c5(n: int = 384, n_dirs: int = 512) -> Workload:
+    d = design_density(n, seed=7627005)
+    return Workload("c5_3d_density_%d_x%d" % (n, n_dirs), 3, d,
+                    fixture_plate_clamps(n), TOOL_C5, 0, fib_hemisphere(n_dirs),
+                    True, 0.01)
+
+
+def serving_stream(n_req: int = 64, seed: int = 7627004, rate: float = 1.0,
+                   sizes=(64, 96, 128, 192, 256), master_dirs: int = 130):
+    """Request descriptors for the serving mix: Poisson arrival times (seconds at
+    ``rate`` requests/s), grid size, binary/density, tool and direction subset."""
+    r = _rng(seed)
+    t = np.cumsum(r.exponential(1.0 / rate, size=n_req))
+    out = []
+    for i in range(n_req):
+        n = int(r.choice(sizes))
+        density = bool(r.integers(0, 2))
+        ball = bool(r.integers(0, 2))
+        k = int(r.integers(6, master_dirs + 1))
+        sub = np.sort(r.choice(master_dirs, size=k, replace=False))
+        out.append({"t": float(t[i]), "n": n, "density": density,
+                    "tool": TOOL_C3 if ball else TOOL_C2, "dir_index": sub,
+                    "seed": seed * 100 + i})
+    return out
