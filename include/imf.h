@@ -1,0 +1,177 @@
+/*
+ * imf.h -- C interface of the MI355X (gfx950) inaccessibility-measure-field
+ * library.
+ *
+ * The library computes the inaccessibility measure field (IMF) of
+ * Mirzendehdel, Behandish and Nelaturi, "Topology Optimization with
+ * Accessibility Constraint for Multi-Axis Machining": Algorithm 1 of
+ * Sec. 2.1.5, with Eqs. imf_2 / imf_4 (the IMF as the minimum over orientations
+ * and sharp points of shifted convolutions), Eq. imf_3 / imf_5 (minimum over
+ * tools), Eq. ident (overlap as a convolution) and Eqs. sweep / A (accessible
+ * region as the sweep of the collision-free translations by the cutter).
+ *
+ * Conventions
+ *   - Grids are [nz][ny][nx], x fastest, contiguous; voxel centres at integer
+ *     coordinates.  2D problems use ndim = 2 and nz = 1.
+ *   - A tool is axisymmetric: cutter K (radius cutter_r, axial [0, cutter_len))
+ *     and holder H (radius holder_r, axial [cutter_len, cutter_len +
+ *     holder_len)); a direction d is the unit tool axis from the cutter tip
+ *     toward the holder; the tip is the origin.  Rasterization is analytic at
+ *     voxel centres (radial test closed, axial test half-open).
+ *   - Outside the grid is empty space.  Translations are integer voxel
+ *     offsets on the same grid.
+ *   - Density designs are float32 in [0, 1] on the 2^-24 grid (k / 2^24).
+ *
+ * Ownership: every input and output pointer is owned by the caller and only
+ * used during the call (imf_compute) or until imf_wait returns (imf_submit).
+ * Device pointers are HIP device memory of the context's device; "host"
+ * arrays are ordinary host memory copied during the call.  The context owns
+ * its workspace and caches, bounded by hbm_budget_bytes.
+ *
+ * Errors: every function returns an imf_status and never throws.  On error the
+ * outputs are undefined and imf_last_error() (thread-local) describes it.  The
+ * context stays usable unless the status is IMF_EDEVICE.  Functions are
+ * thread-safe per context (calls on one context serialize internally).
+ */
+#ifndef IMF_H_
+#define IMF_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  IMF_OK = 0,
+  IMF_EINVAL = 1,      /* invalid argument (message says which) */
+  IMF_ENOMEM = 2,      /* device memory or the context budget exhausted */
+  IMF_EDEVICE = 3,     /* a HIP call failed */
+  IMF_EBUSY = 4,       /* serving queue full */
+  IMF_ETIMEOUT = 5,    /* imf_wait timed out (the request keeps running) */
+  IMF_ECANCELLED = 6,  /* the request was cancelled */
+  IMF_EACCURACY = 7,   /* the guard band overflowed its recheck buffer */
+  IMF_ENOTIMPL = 8
+} imf_status;
+
+typedef struct imf_ctx imf_ctx;
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes bounds the
+ * context's own allocations (0: 90% of the free device memory). */
+imf_status imf_create(int device, size_t hbm_budget_bytes, imf_ctx** ctx);
+imf_status imf_destroy(imf_ctx* ctx);
+/* Message of the last error of the calling thread (never NULL). */
+const char* imf_last_error(void);
+
+/* ---------------------------------------------------------------- tools -- */
+enum { IMF_TOOL_FLAT = 0, IMF_TOOL_BALL = 1, IMF_TOOL_RECT2D = 2 };
+typedef struct {
+  int kind;                /* IMF_TOOL_*; RECT2D is 2D only (radii are half-widths) */
+  double cutter_r, cutter_len, holder_r, holder_len; /* voxels */
+} imf_tool;
+/* Register a tool (Sec. 2.1: T = H u K).  Returns an id for requests. */
+imf_status imf_tool_register(imf_ctx* ctx, const imf_tool* tool, int* tool_id);
+
+/* -------------------------------------------------------------- request -- */
+enum { IMF_DIR_F64 = 0, IMF_DIR_LATTICE = 1 };
+/* sharp points: all cutter voxels (Algorithm 1: Support([1_K])), the cutter's
+ * boundary voxels, or the tip voxel only (sparser sampling, Sec. 2.1.5) */
+enum { IMF_SHARP_ALL = 0, IMF_SHARP_BOUNDARY = 1, IMF_SHARP_TIP = 2 };
+enum { IMF_METHOD_AUTO = 0, IMF_METHOD_FFT = 1, IMF_METHOD_DIRECT = 2 };
+/* flags */
+#define IMF_FLAG_PLAIN 1u        /* one orientation per batch, no spectrum cache */
+#define IMF_FLAG_MASK_SWEEP 2u   /* masks by sweeping D^c with the cutter (bit rows) */
+#define IMF_FLAG_NO_CACHE 4u     /* do not keep tool spectra */
+
+typedef struct {
+  int ndim, nx, ny, nz;
+  int design_is_density;       /* 0: uint8 {0,1}; 1: float32 on the 2^-24 grid */
+  const void* design;          /* device [nz][ny][nx] */
+  const uint8_t* fixture;      /* device [nz][ny][nx] or NULL (Sec. 2.1: O = Omega u F) */
+  const uint8_t* domain;       /* device Omega_0 mask or NULL (= not fixture) */
+  int n_tools;                 /* >= 1 (Eq. imf_3) */
+  const int* tool_ids;         /* host [n_tools] */
+  const int* n_dirs;           /* host [n_tools], each >= 1 */
+  int dir_kind;                /* IMF_DIR_F64: float64 unit vectors; IMF_DIR_LATTICE: int32
+                                  vectors, exact integer rasterization (sizes must be
+                                  multiples of 1/2) */
+  const void* dirs;            /* host [sum n_dirs][ndim] (x, y[, z]) */
+  int sharp;                   /* IMF_SHARP_* */
+  double lambda;               /* allowance: B = Omega_0 and f > lambda F_max */
+  double tau;                  /* Omega = [rho > tau] for the secluded set (0.5) */
+  double mask_theta_abs;       /* >= 0: masks use gamma <= theta (voxel units);
+                                  < 0: theta = lambda F_max (two-phase) */
+  int method;                  /* IMF_METHOD_* */
+  int batch;                   /* orientations per batch, 0: automatic */
+  unsigned flags;              /* IMF_FLAG_* */
+} imf_request;
+
+typedef struct {
+  float* imf;          /* device [N] f (voxel-volume units), or NULL */
+  float* imf_norm;     /* device [N] fbar * 1_B, or NULL */
+  uint8_t* secluded;   /* device [N] Gamma = B minus Omega, or NULL */
+  uint64_t* acc_masks; /* device [n_orient][nz][ny][ceil(nx/64)] accessible masks A_R,
+                          bit x%64 of word x/64, or NULL */
+  float* debug_overlap;  /* device, g of orientation debug_orient over its query box, or NULL */
+  int debug_orient;
+  int debug_box[6];      /* out: lo (x,y,z) and dims of that box */
+} imf_outputs;
+
+typedef struct {
+  double F_max;          /* max of f over Omega_0 */
+  long long guard_flags; /* overlaps recomputed exactly (guard band) */
+  float max_frac_err;    /* max |g - rint g| seen before rounding (binary) */
+  double guard_band;     /* density: band around theta that is rechecked */
+  double t_ms[8];        /* raster, forward, tool spectra, inverse, recheck, min, finalize, total */
+  double model_bytes;    /* algorithmic HBM bytes of the request (cost model) */
+  int P[3];              /* transform sizes */
+  int n_orient, method, batch;
+  int cache_hits, cache_misses;
+} imf_stats;
+
+/* Bytes of device workspace the request needs (admission control). */
+imf_status imf_query_footprint(imf_ctx* ctx, const imf_request* req, size_t* bytes);
+/* Compute the IMF, masks and secluded set of one request, stream-ordered on
+ * `stream` (a hipStream_t, NULL = default); returns after completion. */
+imf_status imf_compute(imf_ctx* ctx, const imf_request* req, const imf_outputs* out,
+                       imf_stats* stats, void* stream);
+
+/* -------------------------------------------------------------- serving -- */
+/* Enqueue a request; the library admits it when its footprint fits the budget
+ * and runs it on its own stream, overlapping with other admitted requests.
+ * Host arrays of `req` are copied; device buffers must stay valid until wait. */
+imf_status imf_submit(imf_ctx* ctx, const imf_request* req, const imf_outputs* out,
+                      uint64_t* ticket);
+/* Wait for a request (timeout_ms < 0: forever).  Fills stats; latency in t_ms[7]. */
+imf_status imf_wait(imf_ctx* ctx, uint64_t ticket, int timeout_ms, imf_stats* stats);
+/* Cancel a request that has not started; returns IMF_EBUSY if it is running. */
+imf_status imf_cancel(imf_ctx* ctx, uint64_t ticket);
+
+/* Time candidate batch widths for a request shape and remember the fastest
+ * (used by later requests with batch = 0). */
+imf_status imf_autotune(imf_ctx* ctx, const imf_request* req, const imf_outputs* out,
+                        int* best_batch);
+
+/* ------------------------------------------------- single steps (checks) -- */
+/* Raster of one oriented tool (the Rotate step): offsets (x, y, z) in z, y, x
+ * order into host arrays (voxels of the tool and the sharp points); flags bit 0 =
+ * tool, bit 1 = cutter, bit 2 = sharp point. */
+imf_status imf_raster(imf_ctx* ctx, int ndim, const imf_tool* tool, int dir_kind,
+                      const void* dir, int sharp, int32_t* offsets, uint8_t* flags,
+                      long long cap, long long* count);
+/* Complex FFT of `batch` columns of length n laid out [n][batch] (interleaved
+ * float re, im), device pointers, unnormalized, sign -1 (inverse: +1). */
+imf_status imf_fft_c2c(imf_ctx* ctx, int n, int batch, const float* in, float* out,
+                       int inverse, void* stream);
+/* 3D real-to-complex FFT of a real [nz][ny][nx] grid zero-padded to
+ * (px, py, pz); output layout [py][px/2+1][pz] complex. */
+imf_status imf_fft_r2c_3d(imf_ctx* ctx, int nx, int ny, int nz, int px, int py, int pz,
+                          const float* in, float* out, void* stream);
+/* Smallest supported transform length >= n. */
+int imf_fft_size(int n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IMF_H_ */

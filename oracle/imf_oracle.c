@@ -266,13 +266,17 @@ static int otool_build(oriented_tool *o, int ndim, const or_tool *t, int dir_kin
   }
   o->nT = or_raster(ndim, t, dir_kind, dirs, index, o->T, cut, n);
   o->nS = 0;
-  for (long long i = 0; i < o->nT; i++) {
+  if (sharp == 2) {
+    /* the tip alone: the origin, which a ball cutter's raster may miss by
+     * rounding because it lies exactly on the sphere */
+    o->S[0] = o->S[1] = o->S[2] = 0;
+    o->nS = 1;
+  }
+  for (long long i = 0; i < o->nT && sharp != 2; i++) {
     if (!cut[i]) continue;
     const int x = o->T[3 * i], y = o->T[3 * i + 1], z = o->T[3 * i + 2];
     int keep = 1;
-    if (sharp == 2) {
-      keep = (x == 0 && y == 0 && z == 0);
-    } else if (sharp == 1) {
+    if (sharp == 1) {
       /* boundary voxel of the cutter raster: some axis neighbour is not cutter */
       keep = 0;
       for (int a = 0; a < ndim && !keep; a++)

@@ -1,0 +1,1398 @@
+// Host runtime and C interface of the IMF library (include/imf.h).
+//
+// One request runs Algorithm 1 of Sec. 2.1.5 on the device:
+//   rasterize the oriented tools (cached per tool and direction),
+//   forward transform of rho_O once, then per batch of orientations: tool
+//   spectra (cached or regenerated), fused product + inverse transform over the
+//   query box, exact rounding / guard-band recheck, sharp-point minimum with
+//   the running minimum and the masks; finally F_max, fbar, B and Gamma.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/imf.h"
+#include "imf_internal.h"
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err = "no error";
+
+static imf_status fail(imf_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+static imf_status fail(imf_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIPCHK(call)                                                                    \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(e_ == hipErrorOutOfMemory ? IMF_ENOMEM : IMF_EDEVICE, "%s: %s (%s:%d)", \
+                  #call, hipGetErrorString(e_), __FILE__, __LINE__);                    \
+  } while (0)
+
+#define STCHK(call)                    \
+  do {                                 \
+    imf_status s_ = (call);            \
+    if (s_ != IMF_OK) return s_;       \
+  } while (0)
+
+extern "C" const char* imf_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// FFT sizes: 2^a 3^b 5^c 7^d with a >= 1, up to 1024
+// ---------------------------------------------------------------------------
+static imf_fft_len make_len(int n) {
+  imf_fft_len L{};
+  L.n = n;
+  int m = n;
+  auto push = [&](int r) { L.radix[L.nstages++] = r; m /= r; };
+  while (m % 8 == 0 && L.nstages < 8) push(8);
+  while (m % 4 == 0 && L.nstages < 8) push(4);
+  while (m % 2 == 0 && L.nstages < 8) push(2);
+  while (m % 3 == 0 && L.nstages < 8) push(3);
+  while (m % 5 == 0 && L.nstages < 8) push(5);
+  while (m % 7 == 0 && L.nstages < 8) push(7);
+  if (m != 1) L.nstages = -1;
+  return L;
+}
+
+static bool smooth(int n) {
+  if (n < 2 || n % 2) return false;
+  int m = n;
+  for (int p : {2, 3, 5, 7})
+    while (m % p == 0) m /= p;
+  return m == 1;
+}
+
+extern "C" int imf_fft_size(int n) {
+  if (n <= 1) return 1;
+  // cheapest smooth length in [n, 1.3 n]: cost n log n with a surcharge for
+  // the slower radix-5/7 stages
+  double best = 1e300;
+  int pick = -1;
+  for (int m = std::max(n, 2); m <= 1024 && m <= (int)(1.3 * n) + 2; m++) {
+    if (!smooth(m)) continue;
+    imf_fft_len L = make_len(m);
+    if (L.nstages < 0) continue;
+    int slow = 0;
+    for (int s = 0; s < L.nstages; s++) slow += (L.radix[s] == 5 || L.radix[s] == 7);
+    const double c = m * std::log2((double)m) * (1.0 + 0.15 * slow) * (1.0 + 0.02 * L.nstages);
+    if (c < best) {
+      best = c;
+      pick = m;
+    }
+  }
+  return pick;
+}
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+struct OrientEntry {
+  int ext[IMF_EXT_INTS];
+  int s_axis;
+  const imf_run* truns;
+  const imf_run* sruns;
+  const imf_run* sxruns;
+};
+
+struct SpecEntry {
+  float2* ptr;
+  size_t bytes;
+  uint64_t tick;
+  hipEvent_t ready;  // recorded after the spectrum is written
+};
+
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  unsigned int* host = nullptr;  // pinned: counters copied back at the end
+};
+
+struct Request;  // serving
+
+struct imf_ctx {
+  int device = 0;
+  size_t budget = 0;
+  size_t spec_bytes = 0, arena_bytes = 0, raster_bytes = 0;
+  std::recursive_mutex mu;
+  std::vector<imf_tool> tools;
+  std::map<std::string, OrientEntry> rasters;
+  std::vector<void*> raster_pools;
+  std::map<std::string, SpecEntry> spectra;
+  std::map<int, float2*> twiddles;
+  std::map<std::string, int> tuned_batch;
+  uint64_t tick = 0;
+  Arena arena;
+  hipStream_t internal = nullptr;
+  // serving
+  std::mutex smu;
+  std::condition_variable scv;
+  std::deque<std::shared_ptr<Request>> queue;
+  std::map<uint64_t, std::shared_ptr<Request>> reqs;
+  std::vector<std::thread> workers;
+  bool stop = false;
+  uint64_t next_ticket = 1;
+  size_t inflight_bytes = 0;
+  int max_inflight = 4;
+  int n_running = 0;
+};
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static imf_status arena_reserve(imf_ctx* c, Arena& a, size_t bytes) {
+  if (!a.host) HIPCHK(hipHostMalloc((void**)&a.host, 1 << 16, hipHostMallocDefault));
+  if (a.cap >= bytes) {
+    a.used = 0;
+    return IMF_OK;
+  }
+  if (a.base) {
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipFree(a.base));
+    c->arena_bytes -= a.cap;
+    a.base = nullptr;
+    a.cap = 0;
+  }
+  const size_t others = c->spec_bytes + c->arena_bytes + c->raster_bytes;
+  if (others + bytes > c->budget)
+    return fail(IMF_ENOMEM, "workspace of %zu bytes exceeds the context budget (%zu used of %zu)",
+                bytes, others, c->budget);
+  HIPCHK(hipMalloc(&a.base, bytes));
+  a.cap = bytes;
+  a.used = 0;
+  c->arena_bytes += bytes;
+  return IMF_OK;
+}
+
+template <class T>
+static T* carve(Arena& a, size_t count) {
+  T* p = (T*)(a.base + a.used);
+  a.used += align256(count * sizeof(T));
+  return p;
+}
+
+static imf_status get_twiddles(imf_ctx* c, int n, const float2** out) {
+  auto it = c->twiddles.find(n);
+  if (it != c->twiddles.end()) {
+    *out = it->second;
+    return IMF_OK;
+  }
+  float2* p = nullptr;
+  HIPCHK(hipMalloc(&p, sizeof(float2) * std::max(n, 1)));
+  HIPCHK(imf_launch_twiddles(p, n, c->internal));
+  HIPCHK(hipStreamSynchronize(c->internal));
+  c->twiddles[n] = p;
+  *out = p;
+  return IMF_OK;
+}
+
+extern "C" imf_status imf_create(int device, size_t hbm_budget_bytes, imf_ctx** ctx) {
+  if (!ctx) return fail(IMF_EINVAL, "ctx is NULL");
+  int n = 0;
+  HIPCHK(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return fail(IMF_EINVAL, "device %d of %d", device, n);
+  HIPCHK(hipSetDevice(device));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, device));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(IMF_EDEVICE, "device %d is %s; this library is built for gfx950", device,
+                prop.gcnArchName);
+  size_t fr = 0, tot = 0;
+  HIPCHK(hipMemGetInfo(&fr, &tot));
+  imf_ctx* c = new imf_ctx();
+  c->device = device;
+  c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)fr);
+  if (hipStreamCreateWithFlags(&c->internal, hipStreamNonBlocking) != hipSuccess) {
+    delete c;
+    return fail(IMF_EDEVICE, "stream creation failed");
+  }
+  *ctx = c;
+  return IMF_OK;
+}
+
+static void serve_shutdown(imf_ctx* c);
+
+extern "C" imf_status imf_destroy(imf_ctx* c) {
+  if (!c) return IMF_OK;
+  serve_shutdown(c);
+  hipSetDevice(c->device);
+  hipDeviceSynchronize();
+  for (auto& kv : c->spectra) {
+    hipFree(kv.second.ptr);
+    if (kv.second.ready) hipEventDestroy(kv.second.ready);
+  }
+  if (c->arena.host) hipHostFree(c->arena.host);
+  for (void* p : c->raster_pools) hipFree(p);
+  for (auto& kv : c->twiddles) hipFree(kv.second);
+  if (c->arena.base) hipFree(c->arena.base);
+  if (c->internal) hipStreamDestroy(c->internal);
+  delete c;
+  return IMF_OK;
+}
+
+extern "C" imf_status imf_tool_register(imf_ctx* c, const imf_tool* t, int* id) {
+  if (!c || !t || !id) return fail(IMF_EINVAL, "NULL argument");
+  if (t->kind < 0 || t->kind > 2) return fail(IMF_EINVAL, "unknown tool kind %d", t->kind);
+  if (!(t->cutter_r > 0 && t->cutter_len > 0 && t->holder_r >= 0 && t->holder_len >= 0) ||
+      !std::isfinite(t->cutter_r + t->cutter_len + t->holder_r + t->holder_len))
+    return fail(IMF_EINVAL, "tool sizes must be positive (holder may be empty)");
+  if (t->cutter_len + t->holder_len > 400 || t->cutter_r > 200 || t->holder_r > 200)
+    return fail(IMF_EINVAL, "tool larger than 400 voxels");
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  c->tools.push_back(*t);
+  *id = (int)c->tools.size() - 1;
+  return IMF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// orientations of a request
+// ---------------------------------------------------------------------------
+struct Orient {
+  int tool;
+  double d[3];
+  long long v[3];
+  std::string key;
+};
+
+static bool is_half_int(double x) { return std::fabs(x * 2 - std::rint(x * 2)) == 0 && std::fabs(x) < 1e6; }
+
+static imf_status enumerate(imf_ctx* c, const imf_request* r, std::vector<Orient>& out) {
+  out.clear();
+  const int nd = r->ndim;
+  size_t k = 0;
+  for (int i = 0; i < r->n_tools; i++) {
+    const int tid = r->tool_ids[i];
+    if (tid < 0 || tid >= (int)c->tools.size()) return fail(IMF_EINVAL, "unknown tool id %d", tid);
+    const imf_tool& t = c->tools[tid];
+    if (t.kind == IMF_TOOL_RECT2D && nd != 2)
+      return fail(IMF_EINVAL, "RECT2D tools are 2D only");
+    if (r->dir_kind == IMF_DIR_LATTICE &&
+        !(is_half_int(t.cutter_r) && is_half_int(t.cutter_len) && is_half_int(t.holder_r) &&
+          is_half_int(t.holder_len)))
+      return fail(IMF_EINVAL, "lattice directions need tool sizes that are multiples of 1/2");
+    if (r->n_dirs[i] < 1) return fail(IMF_EINVAL, "tool %d has no directions", i);
+    for (int j = 0; j < r->n_dirs[i]; j++, k++) {
+      Orient o{};
+      o.tool = tid;
+      if (r->dir_kind == IMF_DIR_LATTICE) {
+        const int32_t* v = (const int32_t*)r->dirs + k * nd;
+        long long n2 = 0;
+        for (int a = 0; a < nd; a++) {
+          o.v[a] = v[a];
+          n2 += (long long)v[a] * v[a];
+        }
+        if (n2 == 0) return fail(IMF_EINVAL, "direction %zu is zero", k);
+        if (n2 > 1000000) return fail(IMF_EINVAL, "lattice direction %zu too long", k);
+        for (int a = 0; a < nd; a++) o.d[a] = (double)o.v[a] / std::sqrt((double)n2);
+      } else if (r->dir_kind == IMF_DIR_F64) {
+        const double* v = (const double*)r->dirs + k * nd;
+        double n2 = 0;
+        for (int a = 0; a < nd; a++) {
+          o.d[a] = v[a];
+          n2 += v[a] * v[a];
+        }
+        if (!(std::fabs(std::sqrt(n2) - 1.0) <= 1e-12))
+          return fail(IMF_EINVAL, "direction %zu is not a unit vector", k);
+      } else {
+        return fail(IMF_EINVAL, "unknown dir_kind %d", r->dir_kind);
+      }
+      char buf[160];
+      if (r->dir_kind == IMF_DIR_LATTICE)
+        snprintf(buf, sizeof buf, "%d|%d|L|%d|%lld,%lld,%lld", tid, nd, r->sharp, o.v[0], o.v[1],
+                 o.v[2]);
+      else
+        snprintf(buf, sizeof buf, "%d|%d|F|%d|%a,%a,%a", tid, nd, r->sharp, o.d[0], o.d[1], o.d[2]);
+      o.key = buf;
+      out.push_back(o);
+    }
+  }
+  return IMF_OK;
+}
+
+static void raster_desc_for(const imf_tool& t, const Orient& o, int nd, int lattice, int sharp,
+                            imf_raster_desc& d) {
+  std::memset(&d, 0, sizeof d);
+  d.kind = t.kind;
+  d.ndim = nd;
+  d.lattice = lattice;
+  d.sharp = sharp;
+  d.r = t.cutter_r;
+  d.L = t.cutter_len;
+  d.rh = t.holder_r;
+  d.LH = t.cutter_len + t.holder_len;
+  for (int a = 0; a < 3; a++) {
+    d.d[a] = a < nd ? o.d[a] : 0.0;
+    d.v[a] = a < nd ? o.v[a] : 0;
+  }
+  d.vn = d.v[0] * d.v[0] + d.v[1] * d.v[1] + d.v[2] * d.v[2];
+  d.r2 = (long long)std::llround(2 * t.cutter_r);
+  d.L2 = (long long)std::llround(2 * t.cutter_len);
+  d.rh2 = (long long)std::llround(2 * t.holder_r);
+  d.LH2 = (long long)std::llround(2 * (t.cutter_len + t.holder_len));
+  // conservative bounding box: every tool point is a d + p, a in [0, len], |p| <= rmax
+  const double len = std::max(t.cutter_len + t.holder_len, 2 * t.cutter_r);
+  const double rmax = std::max(t.cutter_r, t.holder_r);
+  int best = 0;
+  for (int a = 0; a < 3; a++) {
+    if (a >= nd) {
+      d.lo[a] = 0;
+      d.dim[a] = 1;
+      continue;
+    }
+    const double e = len * d.d[a];
+    const int lo = (int)std::floor(std::min(e, 0.0) - rmax) - 1;
+    const int hi = (int)std::ceil(std::max(e, 0.0) + rmax) + 1;
+    d.lo[a] = lo;
+    d.dim[a] = hi - lo + 1;
+    if (std::fabs(d.d[a]) > std::fabs(d.d[best])) best = a;
+  }
+  d.s_axis = best;
+}
+
+static int rows_of(const imf_raster_desc& d) {
+  const int u = (d.s_axis + 1) % 3, w = (d.s_axis + 2) % 3;
+  return std::max(d.dim[1] * d.dim[2], d.dim[u] * d.dim[w]);
+}
+
+// Rasterize every orientation of `os` that is not cached yet.
+static imf_status ensure_rasters(imf_ctx* c, const imf_request* r, const std::vector<Orient>& os,
+                                 hipStream_t s) {
+  std::vector<const Orient*> miss;
+  std::map<std::string, int> seen;
+  for (auto& o : os)
+    if (!c->rasters.count(o.key) && !seen.count(o.key)) {
+      seen[o.key] = 1;
+      miss.push_back(&o);
+    }
+  if (miss.empty()) return IMF_OK;
+  const int n = (int)miss.size();
+  std::vector<imf_raster_desc> hd(n);
+  long long flags_total = 0, rows_total = 0;
+  int max_vol = 0, max_rows = 0;
+  for (int i = 0; i < n; i++) {
+    raster_desc_for(c->tools[miss[i]->tool], *miss[i], r->ndim, r->dir_kind == IMF_DIR_LATTICE,
+                    r->sharp, hd[i]);
+    const long long vol = (long long)hd[i].dim[0] * hd[i].dim[1] * hd[i].dim[2];
+    if (vol > (1LL << 30)) return fail(IMF_EINVAL, "tool raster box too large");
+    hd[i].flags_off = flags_total;
+    flags_total += (vol + 3) & ~3LL;
+    hd[i].rows_off = rows_total;
+    const int rw = rows_of(hd[i]);
+    rows_total += rw;
+    max_vol = std::max(max_vol, (int)vol);
+    max_rows = std::max(max_rows, rw);
+  }
+  imf_raster_desc* dd = nullptr;
+  uint8_t* flags = nullptr;
+  int* ext = nullptr;
+  imf_run* slots = nullptr;
+  int* cnt = nullptr;
+  long long* base = nullptr;
+  imf_run* pool = nullptr;
+  auto cleanup = [&]() {
+    hipFree(dd);
+    hipFree(flags);
+    hipFree(ext);
+    hipFree(slots);
+    hipFree(cnt);
+    hipFree(base);
+  };
+  std::vector<int> hext((size_t)n * IMF_EXT_INTS);
+  for (int i = 0; i < n; i++) {
+    int* e = &hext[(size_t)i * IMF_EXT_INTS];
+    for (int a = 0; a < IMF_EXT_INTS; a++) e[a] = 0;
+    for (int a = 0; a < 3; a++) {
+      e[a] = e[6 + a] = 1 << 29;
+      e[3 + a] = e[9 + a] = -(1 << 29);
+    }
+  }
+  hipError_t he = hipSuccess;
+  if ((he = hipMalloc(&dd, sizeof(imf_raster_desc) * n)) == hipSuccess &&
+      (he = hipMalloc(&flags, flags_total)) == hipSuccess &&
+      (he = hipMalloc(&ext, sizeof(int) * hext.size())) == hipSuccess &&
+      (he = hipMalloc(&slots, sizeof(imf_run) * rows_total * 3 * IMF_MAX_RUNS_PER_ROW)) ==
+          hipSuccess &&
+      (he = hipMalloc(&cnt, sizeof(int) * rows_total * 3)) == hipSuccess &&
+      (he = hipMalloc(&base, sizeof(long long) * n * 3)) == hipSuccess) {
+  }
+  if (he != hipSuccess) {
+    cleanup();
+    return fail(IMF_ENOMEM, "raster workspace: %s", hipGetErrorString(he));
+  }
+#define RCHK(call)                                                                        \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess) {                                                               \
+      cleanup();                                                                          \
+      return fail(IMF_EDEVICE, "%s: %s", #call, hipGetErrorString(e_));                   \
+    }                                                                                     \
+  } while (0)
+  RCHK(hipMemcpyAsync(dd, hd.data(), sizeof(imf_raster_desc) * n, hipMemcpyHostToDevice, s));
+  RCHK(hipMemcpyAsync(ext, hext.data(), sizeof(int) * hext.size(), hipMemcpyHostToDevice, s));
+  RCHK(imf_launch_raster(dd, n, max_vol, flags, ext, s));
+  RCHK(imf_launch_sharp_subset(dd, n, max_vol, flags, ext, s));
+  RCHK(imf_launch_runs(dd, n, max_rows, flags, slots, cnt, ext, s));
+  RCHK(hipMemcpyAsync(hext.data(), ext, sizeof(int) * hext.size(), hipMemcpyDeviceToHost, s));
+  RCHK(hipStreamSynchronize(s));
+  std::vector<long long> hb((size_t)n * 3);
+  long long total = 0;
+  for (int i = 0; i < n; i++) {
+    const int* e = &hext[(size_t)i * IMF_EXT_INTS];
+    if (e[14]) {
+      cleanup();
+      return fail(IMF_EINVAL, "tool raster has more than %d runs in a row", IMF_MAX_RUNS_PER_ROW);
+    }
+    if (e[12] <= 0 || e[13] <= 0) {
+      cleanup();
+      return fail(IMF_EINVAL, "oriented tool %s has no voxels or no sharp points",
+                  miss[i]->key.c_str());
+    }
+    for (int k = 0; k < 3; k++) {
+      hb[(size_t)i * 3 + k] = total;
+      total += e[15 + k];
+    }
+  }
+  if (hipMalloc(&pool, sizeof(imf_run) * std::max(total, 1LL)) != hipSuccess) {
+    cleanup();
+    return fail(IMF_ENOMEM, "raster run pool");
+  }
+  c->raster_pools.push_back(pool);
+  c->raster_bytes += sizeof(imf_run) * std::max(total, 1LL);
+  RCHK(hipMemcpyAsync(base, hb.data(), sizeof(long long) * hb.size(), hipMemcpyHostToDevice, s));
+  RCHK(imf_launch_compact(dd, n, max_rows, slots, cnt, base, pool, s));
+  RCHK(hipStreamSynchronize(s));
+#undef RCHK
+  for (int i = 0; i < n; i++) {
+    OrientEntry e;
+    std::memcpy(e.ext, &hext[(size_t)i * IMF_EXT_INTS], sizeof e.ext);
+    e.s_axis = hd[i].s_axis;
+    e.truns = pool + hb[(size_t)i * 3 + 0];
+    e.sruns = pool + hb[(size_t)i * 3 + 1];
+    e.sxruns = pool + hb[(size_t)i * 3 + 2];
+    c->rasters[miss[i]->key] = e;
+  }
+  cleanup();
+  return IMF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// planning
+// ---------------------------------------------------------------------------
+struct Plan {
+  int nd, n[3];
+  long long N;
+  int words;
+  int method;  // FFT or DIRECT
+  int P[3];
+  imf_fft_len fl[3];
+  int B;
+  int nO;
+  std::vector<imf_orient_desc> desc;
+  std::vector<imf_orient_desc> sweep_desc;
+  std::vector<const OrientEntry*> ent;
+  std::vector<std::string> keys;
+  int max_m[3];
+  long long max_vol;
+  int max_t[3];
+  int nlvl;
+  bool theta_known, two_phase, masks, sweep, cache;
+  double theta;
+  double band;
+  // workspace layout (bytes)
+  size_t ws_bytes;
+  long long spec_elems;
+};
+
+static imf_status validate(const imf_request* r) {
+  if (!r) return fail(IMF_EINVAL, "request is NULL");
+  if (r->ndim != 2 && r->ndim != 3) return fail(IMF_EINVAL, "ndim must be 2 or 3");
+  if (r->nx < 1 || r->ny < 1 || r->nz < 1) return fail(IMF_EINVAL, "empty grid");
+  if (r->ndim == 2 && r->nz != 1) return fail(IMF_EINVAL, "2D grids need nz = 1");
+  if (r->nx > 1024 || r->ny > 1024 || r->nz > 1024)
+    return fail(IMF_EINVAL, "grid larger than 1024 per axis");
+  if (!r->design) return fail(IMF_EINVAL, "design is NULL");
+  if (r->n_tools < 1 || !r->tool_ids || !r->n_dirs || !r->dirs)
+    return fail(IMF_EINVAL, "no tools or directions");
+  if (r->sharp < 0 || r->sharp > 2) return fail(IMF_EINVAL, "unknown sharp-point mode");
+  if (!(r->lambda >= 0 && r->lambda < 1)) return fail(IMF_EINVAL, "lambda must be in [0, 1)");
+  if (!std::isfinite(r->tau)) return fail(IMF_EINVAL, "tau is not finite");
+  if (r->method < 0 || r->method > 2) return fail(IMF_EINVAL, "unknown method");
+  if (r->batch < 0 || r->batch > 64) return fail(IMF_EINVAL, "batch must be in [0, 64]");
+  return IMF_OK;
+}
+
+static imf_status make_plan(imf_ctx* c, const imf_request* r, const imf_outputs* out,
+                            const std::vector<Orient>& os, Plan& p) {
+  p.nd = r->ndim;
+  p.n[0] = r->nx;
+  p.n[1] = r->ny;
+  p.n[2] = r->nz;
+  p.N = (long long)r->nx * r->ny * r->nz;
+  p.words = (r->nx + 63) / 64;
+  p.nO = (int)os.size();
+  p.desc.resize(p.nO);
+  p.ent.resize(p.nO);
+  p.keys.resize(p.nO);
+  long long need[3] = {1, 1, 1};
+  for (int a = 0; a < 3; a++) {
+    p.max_m[a] = 1;
+    p.max_t[a] = 1;
+  }
+  p.max_vol = 1;
+  int max_sdim = 1;
+  for (int q = 0; q < p.nO; q++) {
+    const OrientEntry& e = c->rasters.at(os[q].key);
+    p.ent[q] = &e;
+    p.keys[q] = os[q].key;
+    imf_orient_desc& d = p.desc[q];
+    std::memset(&d, 0, sizeof d);
+    long long vol = 1;
+    for (int a = 0; a < 3; a++) {
+      const int omin = e.ext[a], omax = e.ext[3 + a], kmin = e.ext[6 + a], kmax = e.ext[9 + a];
+      d.box_lo[a] = -kmax;
+      d.box_dim[a] = p.n[a] + kmax - kmin;
+      d.tlo[a] = omin;
+      d.tdim[a] = omax - omin + 1;
+      need[a] = std::max(need[a], (long long)p.n[a] + std::max(kmax - omin, omax - kmin));
+      p.max_m[a] = std::max(p.max_m[a], d.box_dim[a]);
+      p.max_t[a] = std::max(p.max_t[a], d.tdim[a]);
+      vol *= d.box_dim[a];
+    }
+    p.max_vol = std::max(p.max_vol, vol);
+    d.s_axis = e.s_axis;
+    d.n_sruns = e.ext[16];
+    d.n_truns = e.ext[15];
+    d.sruns = e.sruns;
+    d.truns = e.truns;
+    d.spec = nullptr;
+    max_sdim = std::max(max_sdim, e.ext[9 + e.s_axis] - e.ext[6 + e.s_axis] + 1);
+  }
+  if (p.max_vol > (1LL << 31) - 1) return fail(IMF_EINVAL, "query box too large");
+  p.nlvl = 0;
+  while ((2 << p.nlvl) <= max_sdim) p.nlvl++;
+  // method
+  p.method = r->method;
+  if (p.method == IMF_METHOD_AUTO) p.method = (p.nd == 2 || p.N <= 32 * 32 * 32) ? IMF_METHOD_DIRECT : IMF_METHOD_FFT;
+  for (int a = 0; a < 3; a++) {
+    p.P[a] = 1;
+    p.fl[a] = make_len(1);
+  }
+  if (p.method == IMF_METHOD_FFT) {
+    for (int a = 0; a < p.nd; a++) {
+      const int m = imf_fft_size((int)need[a]);
+      if (m < 0) return fail(IMF_EINVAL, "transform length %lld along axis %d exceeds 1024",
+                             need[a], a);
+      p.P[a] = m;
+      p.fl[a] = make_len(m);
+    }
+  }
+  // batch width
+  const bool plain = (r->flags & IMF_FLAG_PLAIN) != 0;
+  p.B = r->batch;
+  if (p.B == 0) {
+    char key[96];
+    snprintf(key, sizeof key, "%d|%d,%d,%d|%d,%d,%d", p.method, p.n[0], p.n[1], p.n[2], p.P[0],
+             p.P[1], p.P[2]);
+    auto it = c->tuned_batch.find(key);
+    p.B = it != c->tuned_batch.end() ? it->second : 8;
+  }
+  if (plain) p.B = 1;
+  p.B = std::max(1, std::min(p.B, p.nO));
+  // thresholds
+  p.masks = out && out->acc_masks;
+  p.sweep = p.masks && (r->flags & IMF_FLAG_MASK_SWEEP);
+  p.cache = p.method == IMF_METHOD_FFT && !plain && !(r->flags & IMF_FLAG_NO_CACHE);
+  if (r->mask_theta_abs >= 0) {
+    p.theta_known = true;
+    p.theta = r->mask_theta_abs;
+  } else if (r->lambda == 0) {
+    p.theta_known = true;
+    p.theta = 0;
+  } else {
+    p.theta_known = false;
+    p.theta = 0;
+  }
+  p.two_phase = p.masks && !p.theta_known;
+  if (p.two_phase && p.sweep)
+    return fail(IMF_EINVAL, "the sweep mask route needs a known threshold (mask_theta_abs >= 0 or lambda = 0)");
+  // density guard band: 2 E with E a bound on the float32 transform error,
+  // u * log2(P^3) * sqrt(N |T|) (|rho| <= 1)
+  p.band = 0;
+  if (r->design_is_density && p.method == IMF_METHOD_FFT) {
+    long long maxT = 1;
+    for (auto* e : p.ent) maxT = std::max<long long>(maxT, e->ext[12]);
+    const double u = 5.96e-8;
+    const double lg = std::log2((double)p.P[0] * p.P[1] * p.P[2]);
+    p.band = 2.0 * u * lg * std::sqrt((double)p.N * (double)maxT);
+  }
+  const int h = p.P[0] / 2 + 1;
+  p.spec_elems = (long long)p.P[1] * h * p.P[2];
+  // workspace
+  size_t b = 0;
+  auto add = [&](size_t bytes) { b += align256(bytes); };
+  const long long N = p.N;
+  add(sizeof(float) * N);                              // f
+  add(N);                                              // omega0
+  add(sizeof(long long) * (r->nx + 1) * (long long)r->ny * r->nz);  // prefix sums
+  add(256);                                            // fmax + max_err
+  const int nb = (p.nO + p.B - 1) / p.B;
+  add(sizeof(int) * (nb + 1));                         // per-batch flag counters
+  add(sizeof(int2) * (size_t)(1 << 20));               // flag list
+  add(sizeof(imf_orient_desc) * p.nO * 2);             // descriptors (+ sweep)
+  add(sizeof(float) * p.B * p.max_vol);                // g
+  add(sizeof(float) * p.B * std::max(p.nlvl, 1) * p.max_vol);  // levels
+  if (p.two_phase) add(sizeof(float) * N * p.nO);      // gamma stack
+  if (p.sweep) add(sizeof(uint64_t) * p.B * ((p.max_m[0] + 63) / 64) * (long long)p.max_m[1] * p.max_m[2]);
+  if (p.method == IMF_METHOD_FFT) {
+    add(sizeof(float2) * p.spec_elems);                                  // rho_hat
+    add(sizeof(float2) * (long long)r->nz * r->ny * h);                  // fwd work1
+    add(sizeof(float2) * (long long)r->nz * p.P[1] * h);                 // fwd work2
+    add(sizeof(float2) * p.B * (long long)p.max_t[2] * p.max_t[1] * h);  // tool work1
+    add(sizeof(float2) * p.B * (long long)p.max_t[2] * p.P[1] * h);      // tool work2
+    add(sizeof(float2) * p.B * p.spec_elems);                            // batch spectra
+    add(sizeof(float2) * p.B * (long long)p.max_m[2] * p.P[1] * h);      // inverse w1
+    add(sizeof(float2) * p.B * (long long)p.max_m[2] * p.max_m[1] * h);  // inverse w2
+  }
+  p.ws_bytes = b + 4096;
+  return IMF_OK;
+}
+
+extern "C" imf_status imf_query_footprint(imf_ctx* c, const imf_request* r, size_t* bytes) {
+  if (!c || !bytes) return fail(IMF_EINVAL, "NULL argument");
+  STCHK(validate(r));
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  HIPCHK(hipSetDevice(c->device));
+  std::vector<Orient> os;
+  STCHK(enumerate(c, r, os));
+  STCHK(ensure_rasters(c, r, os, c->internal));
+  Plan p;
+  imf_outputs o{};
+  STCHK(make_plan(c, r, &o, os, p));
+  *bytes = p.ws_bytes;
+  return IMF_OK;
+}
+
+// cost model of the algorithmic HBM traffic (bytes) of one request
+static double model_bytes(const Plan& p) {
+  const double S = 8.0 * p.spec_elems;
+  double tot = 0;
+  for (int q = 0; q < p.nO; q++) {
+    const imf_orient_desc& d = p.desc[q];
+    const double M3 = (double)d.box_dim[0] * d.box_dim[1] * d.box_dim[2];
+    if (p.method == IMF_METHOD_FFT) {
+      const double fz = (double)d.box_dim[2] / p.P[2], fy = (double)d.box_dim[1] / p.P[1];
+      tot += S + S / p.B + 2 * S * fz + 2 * S * fz * fy;
+    }
+    tot += 4 * M3 + 4 * M3;         // write g, read g in the min filter
+    tot += 8.0 * p.N / p.B;          // running min read + write
+    if (p.masks) tot += p.N / 8.0;   // mask bits
+  }
+  tot += 13.0 * p.N;                 // finalize
+  return tot;
+}
+
+// ---------------------------------------------------------------------------
+// compute
+// ---------------------------------------------------------------------------
+struct Timer {
+  std::vector<hipEvent_t> ev;
+  std::vector<int> phase;
+  hipStream_t s;
+  void mark(int ph) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    hipEventRecord(e, s);
+    ev.push_back(e);
+    phase.push_back(ph);
+  }
+  void collect(double* t) {
+    for (size_t i = 1; i < ev.size(); i++) {
+      float ms = 0;
+      hipEventElapsedTime(&ms, ev[i - 1], ev[i]);
+      if (phase[i] >= 0 && phase[i] < 7) t[phase[i]] += ms;
+    }
+    if (ev.size() > 1) {
+      float ms = 0;
+      hipEventElapsedTime(&ms, ev.front(), ev.back());
+      t[7] = ms;
+    }
+    for (auto e : ev) hipEventDestroy(e);
+    ev.clear();
+  }
+};
+
+static imf_status spectrum_slot(imf_ctx* c, const Plan& p, const std::string& key,
+                                SpecEntry** hit, float2** ptr) {
+  char buf[64];
+  snprintf(buf, sizeof buf, "|%d,%d,%d", p.P[0], p.P[1], p.P[2]);
+  const std::string k = key + buf;
+  auto it = c->spectra.find(k);
+  if (it != c->spectra.end()) {
+    it->second.tick = ++c->tick;
+    *hit = &it->second;
+    *ptr = it->second.ptr;
+    return IMF_OK;
+  }
+  *hit = nullptr;
+  *ptr = nullptr;
+  const size_t bytes = sizeof(float2) * p.spec_elems;
+  if (c->spec_bytes + c->arena_bytes + c->raster_bytes + bytes > c->budget) return IMF_OK;
+  float2* q = nullptr;
+  if (hipMalloc(&q, bytes) != hipSuccess) {
+    hipGetLastError();
+    return IMF_OK;
+  }
+  hipEvent_t ev = nullptr;
+  HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  c->spectra[k] = SpecEntry{q, bytes, ++c->tick, ev};
+  c->spec_bytes += bytes;
+  *ptr = q;
+  return IMF_OK;
+}
+
+// Work of one request between its launch and its completion.
+struct Pending {
+  Plan p;
+  Timer tm;
+  hipStream_t s;
+  int nb = 0, flag_cap = 0, hits = 0, misses = 0;
+  unsigned int* host = nullptr;  // [0..1] fmax, max_err; [2..] per-batch flag counts
+  std::chrono::steady_clock::time_point t_start;
+  imf_outputs* out = nullptr;
+};
+
+// Enqueue the whole request on stream s (no host synchronization after the
+// rasters exist).  The caller holds the context lock.
+static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_outputs* out,
+                                 hipStream_t s, Arena& ar, Pending& pd) {
+  STCHK(validate(r));
+  if (!out) return fail(IMF_EINVAL, "outputs is NULL");
+  HIPCHK(hipSetDevice(c->device));
+  pd.t_start = std::chrono::steady_clock::now();
+  pd.s = s;
+  pd.out = const_cast<imf_outputs*>(out);
+  std::vector<Orient> os;
+  STCHK(enumerate(c, r, os));
+  Timer& tm = pd.tm;
+  tm.s = s;
+  tm.mark(-1);
+  STCHK(ensure_rasters(c, r, os, s));
+  tm.mark(0);
+  Plan& p = pd.p;
+  STCHK(make_plan(c, r, out, os, p));
+  if (out->debug_overlap && (out->debug_orient < 0 || out->debug_orient >= p.nO))
+    return fail(IMF_EINVAL, "debug_orient out of range");
+  STCHK(arena_reserve(c, ar, p.ws_bytes));
+  const long long N = p.N;
+  const int h = p.P[0] / 2 + 1;
+  const int nb = (p.nO + p.B - 1) / p.B;
+  pd.nb = nb;
+  if (nb + 2 > (1 << 14)) return fail(IMF_EINVAL, "too many batches");
+  // carve the workspace (same order as make_plan)
+  float* f = carve<float>(ar, N);
+  uint8_t* om = carve<uint8_t>(ar, N);
+  long long* ps = carve<long long>(ar, (r->nx + 1) * (long long)r->ny * r->nz);
+  unsigned int* misc = carve<unsigned int>(ar, 64);
+  unsigned int* fmax_bits = misc;
+  unsigned int* maxerr_bits = misc + 1;
+  int* flag_cnt = carve<int>(ar, nb + 1);
+  const int flag_cap = 1 << 20;
+  pd.flag_cap = flag_cap;
+  int2* flags = carve<int2>(ar, flag_cap);
+  imf_orient_desc* d_desc = carve<imf_orient_desc>(ar, (size_t)p.nO * 2);
+  imf_orient_desc* d_sweep = d_desc + p.nO;
+  float* g = carve<float>(ar, p.B * p.max_vol);
+  float* lvl = carve<float>(ar, (size_t)p.B * std::max(p.nlvl, 1) * p.max_vol);
+  float* gstack = p.two_phase ? carve<float>(ar, (size_t)N * p.nO) : nullptr;
+  const long long dc_stride = ((p.max_m[0] + 63) / 64) * (long long)p.max_m[1] * p.max_m[2];
+  uint64_t* dc = p.sweep ? carve<uint64_t>(ar, p.B * dc_stride) : nullptr;
+  float2 *rho_hat = nullptr, *fw1 = nullptr, *fw2 = nullptr, *tw1 = nullptr, *tw2 = nullptr,
+         *bspec = nullptr, *w1 = nullptr, *w2 = nullptr;
+  const long long tw1_stride = (long long)p.max_t[2] * p.max_t[1] * h;
+  const long long tw2_stride = (long long)p.max_t[2] * p.P[1] * h;
+  const long long w1_stride = (long long)p.max_m[2] * p.P[1] * h;
+  const long long w2_stride = (long long)p.max_m[2] * p.max_m[1] * h;
+  if (p.method == IMF_METHOD_FFT) {
+    rho_hat = carve<float2>(ar, p.spec_elems);
+    fw1 = carve<float2>(ar, (long long)r->nz * r->ny * h);
+    fw2 = carve<float2>(ar, (long long)r->nz * p.P[1] * h);
+    tw1 = carve<float2>(ar, p.B * tw1_stride);
+    tw2 = carve<float2>(ar, p.B * tw2_stride);
+    bspec = carve<float2>(ar, p.B * p.spec_elems);
+    w1 = carve<float2>(ar, p.B * w1_stride);
+    w2 = carve<float2>(ar, p.B * w2_stride);
+  }
+  imf_orient_desc* d_miss = nullptr;
+  if (p.method == IMF_METHOD_FFT) d_miss = carve<imf_orient_desc>(ar, (size_t)nb * p.B);
+  if (ar.used > ar.cap) return fail(IMF_EDEVICE, "workspace layout mismatch");
+  // spectra: cached slots (or the batch buffer); wait for cached spectra that
+  // another stream may still be writing
+  std::vector<char> need_fft(p.nO, 0);
+  std::vector<SpecEntry*> fresh(p.nO, nullptr);
+  if (p.method == IMF_METHOD_FFT) {
+    for (int q = 0; q < p.nO; q++) {
+      SpecEntry* hit = nullptr;
+      float2* ptr = nullptr;
+      if (p.cache) STCHK(spectrum_slot(c, p, p.keys[q], &hit, &ptr));
+      if (hit) {
+        pd.hits++;
+        p.desc[q].spec = ptr;
+        HIPCHK(hipStreamWaitEvent(s, hit->ready, 0));
+      } else {
+        pd.misses++;
+        need_fft[q] = 1;
+        if (ptr) {
+          char buf[64];
+          snprintf(buf, sizeof buf, "|%d,%d,%d", p.P[0], p.P[1], p.P[2]);
+          fresh[q] = &c->spectra.at(p.keys[q] + buf);
+        }
+        p.desc[q].spec = ptr ? ptr : bspec + (long long)(q % p.B) * p.spec_elems;
+      }
+    }
+  }
+  p.sweep_desc = p.desc;
+  for (int q = 0; q < p.nO; q++) {
+    p.sweep_desc[q].sruns = p.ent[q]->sxruns;
+    p.sweep_desc[q].n_sruns = p.ent[q]->ext[17];
+  }
+  // descriptors: all of them, and per batch the orientations whose spectra are computed
+  std::vector<imf_orient_desc> hall(p.desc);
+  hall.insert(hall.end(), p.sweep_desc.begin(), p.sweep_desc.end());
+  std::vector<int> nmiss(nb, 0);
+  std::vector<imf_orient_desc> hmiss;
+  if (d_miss) {
+    hmiss.resize((size_t)nb * p.B);
+    for (int b = 0; b < nb; b++)
+      for (int q = b * p.B; q < std::min(p.nO, (b + 1) * p.B); q++)
+        if (need_fft[q]) hmiss[(size_t)b * p.B + nmiss[b]++] = p.desc[q];
+  }
+  HIPCHK(hipMemcpy(d_desc, hall.data(), sizeof(imf_orient_desc) * hall.size(),
+                   hipMemcpyHostToDevice));
+  if (d_miss)
+    HIPCHK(hipMemcpy(d_miss, hmiss.data(), sizeof(imf_orient_desc) * hmiss.size(),
+                     hipMemcpyHostToDevice));
+  const float2 *twx = nullptr, *twy = nullptr, *twz = nullptr;
+  if (p.method == IMF_METHOD_FFT) {
+    STCHK(get_twiddles(c, p.P[0], &twx));
+    STCHK(get_twiddles(c, p.P[1], &twy));
+    STCHK(get_twiddles(c, p.P[2], &twz));
+  }
+  // setup
+  HIPCHK(hipMemsetAsync(misc, 0, 256, s));
+  HIPCHK(hipMemsetAsync(flag_cnt, 0, sizeof(int) * (nb + 1), s));
+  HIPCHK(imf_launch_omega0(r->fixture, r->domain, om, N, s));
+  HIPCHK(imf_launch_fill_f(f, N, INFINITY, s));
+  HIPCHK(imf_launch_prefix_x(r->design, r->design_is_density, r->fixture, r->nx, r->ny, r->nz, ps,
+                             s));
+  tm.mark(6);
+  if (p.method == IMF_METHOD_FFT) {
+    imf_fwd_design_args fa{r->design, r->design_is_density, r->fixture, r->nx, r->ny, r->nz,
+                           p.P[0], p.P[1], p.P[2], fw1, fw2, rho_hat};
+    HIPCHK(imf_launch_fwd_design(fa, p.fl[0], p.fl[1], p.fl[2], twx, twy, twz, s));
+    tm.mark(1);
+  }
+  for (int b = 0; b < nb; b++) {
+    const int q0 = b * p.B;
+    const int nq = std::min(p.B, p.nO - q0);
+    const imf_orient_desc* bd = d_desc + q0;
+    if (p.method == IMF_METHOD_FFT) {
+      if (nmiss[b]) {
+        imf_tool_fft_args ta{d_miss + (size_t)b * p.B, nmiss[b], p.P[0], p.P[1], p.P[2],
+                             p.max_t[1], p.max_t[2], tw1, tw2, tw1_stride, tw2_stride};
+        HIPCHK(imf_launch_tool_fft(ta, p.fl[1], p.fl[2], twx, twy, twz, s));
+        for (int q = q0; q < q0 + nq; q++)
+          if (fresh[q]) HIPCHK(hipEventRecord(fresh[q]->ready, s));
+        tm.mark(2);
+      }
+      imf_inv_args ia{};
+      ia.desc = bd;
+      ia.nq = nq;
+      ia.rho_hat = rho_hat;
+      ia.px = p.P[0];
+      ia.py = p.P[1];
+      ia.pz = p.P[2];
+      ia.max_mx = p.max_m[0];
+      ia.max_my = p.max_m[1];
+      ia.max_mz = p.max_m[2];
+      ia.w1 = w1;
+      ia.w1_stride = w1_stride;
+      ia.w2 = w2;
+      ia.w2_stride = w2_stride;
+      ia.g = g;
+      ia.g_stride = p.max_vol;
+      ia.binary = !r->design_is_density;
+      ia.delta = 0.25f;
+      ia.theta_known = r->design_is_density && p.theta_known && p.masks;
+      ia.theta = p.theta;
+      ia.band = p.band;
+      ia.max_err_bits = maxerr_bits;
+      ia.flag_cnt = flag_cnt + b;
+      ia.flag_cap = flag_cap;
+      ia.flags = flags;
+      HIPCHK(imf_launch_inverse(ia, p.fl[0], p.fl[1], p.fl[2], twx, twy, twz, s));
+      tm.mark(3);
+      if (ia.binary || ia.theta_known) {
+        HIPCHK(imf_launch_recheck(bd, ps, r->nx, r->ny, r->nz, r->design_is_density, flag_cnt + b,
+                                  flags, flag_cap, ia.theta_known, p.theta, g, p.max_vol, s));
+        tm.mark(4);
+      }
+    } else {
+      HIPCHK(imf_launch_direct(bd, nq, ps, r->nx, r->ny, r->nz, r->design_is_density, g,
+                               p.max_vol, (int)p.max_vol, s));
+      tm.mark(3);
+    }
+    if (out->debug_overlap && out->debug_orient >= q0 && out->debug_orient < q0 + nq) {
+      const imf_orient_desc& d = p.desc[out->debug_orient];
+      const long long vol = (long long)d.box_dim[0] * d.box_dim[1] * d.box_dim[2];
+      HIPCHK(hipMemcpyAsync(out->debug_overlap, g + (long long)(out->debug_orient - q0) * p.max_vol,
+                            sizeof(float) * vol, hipMemcpyDeviceToDevice, s));
+    }
+    imf_min_args ma{};
+    ma.desc = bd;
+    ma.nq = nq;
+    ma.g = g;
+    ma.g_stride = p.max_vol;
+    ma.lvl = lvl;
+    ma.lvl_stride = (long long)std::max(p.nlvl, 1) * p.max_vol;
+    ma.nlvl = p.nlvl;
+    ma.nx = r->nx;
+    ma.ny = r->ny;
+    ma.nz = r->nz;
+    ma.f = f;
+    ma.omega0 = om;
+    ma.masks_on = p.masks && p.theta_known && !p.sweep;
+    ma.theta = p.theta;
+    ma.masks = out->acc_masks;
+    ma.mask_q0 = q0;
+    ma.gamma_stack = gstack;
+    ma.gamma_q0 = q0;
+    HIPCHK(imf_launch_minfilter(ma, s));
+    if (p.sweep) {
+      imf_sweep_args sa{d_sweep + q0, nq, g, p.max_vol, p.theta, r->nx, r->ny, r->nz, om, dc,
+                        dc_stride, out->acc_masks, q0};
+      HIPCHK(imf_launch_sweep(sa, s));
+    }
+    tm.mark(5);
+  }
+  HIPCHK(imf_launch_fmax(f, om, N, fmax_bits, s));
+  HIPCHK(imf_launch_finalize(f, om, r->design, r->design_is_density, N, fmax_bits, r->lambda,
+                             r->tau, out->imf, out->imf_norm, out->secluded, s));
+  if (p.two_phase)
+    HIPCHK(imf_launch_masks_from_gamma(gstack, p.nO, om, r->nx, r->ny, r->nz, fmax_bits,
+                                       r->lambda, out->acc_masks, s));
+  tm.mark(6);
+  pd.host = ar.host;
+  HIPCHK(hipMemcpyAsync(pd.host, misc, 2 * sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(pd.host + 2, flag_cnt, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
+  if (out->debug_overlap) {
+    const imf_orient_desc& d = p.desc[out->debug_orient];
+    for (int a = 0; a < 3; a++) {
+      pd.out->debug_box[a] = d.box_lo[a];
+      pd.out->debug_box[3 + a] = d.box_dim[a];
+    }
+  }
+  return IMF_OK;
+}
+
+// Wait for the request and report its statistics (no context lock needed).
+static imf_status compute_finish(Pending& pd, imf_stats* st) {
+  hipError_t e = hipStreamSynchronize(pd.s);
+  if (e != hipSuccess) {
+    for (auto ev : pd.tm.ev) hipEventDestroy(ev);
+    return fail(IMF_EDEVICE, "request failed on the device: %s", hipGetErrorString(e));
+  }
+  const Plan& p = pd.p;
+  long long total_flags = 0;
+  for (int b = 0; b < pd.nb; b++) {
+    const int n = (int)pd.host[2 + b];
+    if (n > pd.flag_cap) {
+      for (auto ev : pd.tm.ev) hipEventDestroy(ev);
+      return fail(IMF_EACCURACY, "guard band of batch %d flagged %d overlaps (capacity %d)", b, n,
+                  pd.flag_cap);
+    }
+    total_flags += n;
+  }
+  auto ord2f = [](unsigned u) {
+    unsigned b = (u & 0x80000000u) ? (u & 0x7fffffffu) : ~u;
+    float f;
+    std::memcpy(&f, &b, 4);
+    return f;
+  };
+  if (st) {
+    std::memset(st, 0, sizeof *st);
+    st->F_max = ord2f(pd.host[0]);
+    float me;
+    std::memcpy(&me, &pd.host[1], 4);
+    st->max_frac_err = me;
+    st->guard_flags = total_flags;
+    st->guard_band = p.band;
+    pd.tm.collect(st->t_ms);
+    st->t_ms[7] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
+                                                            pd.t_start).count();
+    st->model_bytes = model_bytes(p);
+    for (int a = 0; a < 3; a++) st->P[a] = p.P[a];
+    st->n_orient = p.nO;
+    st->method = p.method;
+    st->batch = p.B;
+    st->cache_hits = pd.hits;
+    st->cache_misses = pd.misses;
+  } else {
+    for (auto ev : pd.tm.ev) hipEventDestroy(ev);
+  }
+  return IMF_OK;
+}
+
+static imf_status compute_impl(imf_ctx* c, const imf_request* r, const imf_outputs* out,
+                               imf_stats* st, hipStream_t s, Arena& ar) {
+  Pending pd;
+  imf_status e = compute_launch(c, r, out, s, ar, pd);
+  if (e != IMF_OK) {
+    hipStreamSynchronize(s);
+    for (auto ev : pd.tm.ev) hipEventDestroy(ev);
+    return e;
+  }
+  return compute_finish(pd, st);
+}
+
+extern "C" imf_status imf_compute(imf_ctx* c, const imf_request* r, const imf_outputs* out,
+                                  imf_stats* st, void* stream) {
+  if (!c) return fail(IMF_EINVAL, "ctx is NULL");
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  return compute_impl(c, r, out, st, (hipStream_t)stream, c->arena);
+}
+
+// ---------------------------------------------------------------------------
+// single steps
+// ---------------------------------------------------------------------------
+extern "C" imf_status imf_raster(imf_ctx* c, int ndim, const imf_tool* tool, int dir_kind,
+                                 const void* dir, int sharp, int32_t* offsets, uint8_t* flags_out,
+                                 long long cap, long long* count) {
+  if (!c || !tool || !dir || !count) return fail(IMF_EINVAL, "NULL argument");
+  if (ndim != 2 && ndim != 3) return fail(IMF_EINVAL, "ndim must be 2 or 3");
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  HIPCHK(hipSetDevice(c->device));
+  int tid;
+  STCHK(imf_tool_register(c, tool, &tid));
+  imf_request r{};
+  r.ndim = ndim;
+  r.n_tools = 1;
+  r.tool_ids = &tid;
+  int one = 1;
+  r.n_dirs = &one;
+  r.dir_kind = dir_kind;
+  r.dirs = dir;
+  r.sharp = sharp;
+  std::vector<Orient> os;
+  STCHK(enumerate(c, &r, os));
+  imf_raster_desc hd;
+  raster_desc_for(*tool, os[0], ndim, dir_kind == IMF_DIR_LATTICE, sharp, hd);
+  const long long vol = (long long)hd.dim[0] * hd.dim[1] * hd.dim[2];
+  hd.flags_off = 0;
+  hd.rows_off = 0;
+  imf_raster_desc* dd = nullptr;
+  uint8_t* fl = nullptr;
+  int* ext = nullptr;
+  HIPCHK(hipMalloc(&dd, sizeof hd));
+  HIPCHK(hipMalloc(&fl, (vol + 3) & ~3LL));
+  HIPCHK(hipMalloc(&ext, sizeof(int) * IMF_EXT_INTS));
+  std::vector<int> hext(IMF_EXT_INTS, 0);
+  for (int a = 0; a < 3; a++) {
+    hext[a] = hext[6 + a] = 1 << 29;
+    hext[3 + a] = hext[9 + a] = -(1 << 29);
+  }
+  hipStream_t s = c->internal;
+  std::vector<uint8_t> hf(vol);
+  hipError_t e = hipMemcpyAsync(dd, &hd, sizeof hd, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ext, hext.data(), sizeof(int) * IMF_EXT_INTS, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = imf_launch_raster(dd, 1, (int)vol, fl, ext, s);
+  if (e == hipSuccess) e = imf_launch_sharp_subset(dd, 1, (int)vol, fl, ext, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(hf.data(), fl, vol, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  hipFree(dd);
+  hipFree(fl);
+  hipFree(ext);
+  if (e != hipSuccess) return fail(IMF_EDEVICE, "raster: %s", hipGetErrorString(e));
+  long long n = 0;
+  for (long long i = 0; i < vol; i++) {
+    if (!(hf[i] & 5)) continue;
+    if (n < cap) {
+      const int x = (int)(i % hd.dim[0]), y = (int)((i / hd.dim[0]) % hd.dim[1]),
+                z = (int)(i / ((long long)hd.dim[0] * hd.dim[1]));
+      if (offsets) {
+        offsets[3 * n] = x + hd.lo[0];
+        offsets[3 * n + 1] = y + hd.lo[1];
+        offsets[3 * n + 2] = z + hd.lo[2];
+      }
+      if (flags_out) flags_out[n] = hf[i];
+    }
+    n++;
+  }
+  *count = n;
+  if (n > cap) return fail(IMF_EINVAL, "capacity %lld < %lld voxels", cap, n);
+  return IMF_OK;
+}
+
+extern "C" imf_status imf_fft_c2c(imf_ctx* c, int n, int batch, const float* in, float* out,
+                                  int inverse, void* stream) {
+  if (!c || !in || !out) return fail(IMF_EINVAL, "NULL argument");
+  imf_fft_len L = make_len(n);
+  if (n < 1 || n > 1024 || L.nstages < 0) return fail(IMF_EINVAL, "unsupported length %d", n);
+  if (batch < 1) return fail(IMF_EINVAL, "batch must be >= 1");
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  HIPCHK(hipSetDevice(c->device));
+  const float2* tw;
+  STCHK(get_twiddles(c, n, &tw));
+  // columns are the batch index (stride 1), elements j at j * batch
+  HIPCHK(imf_launch_columns((const float2*)in, (float2*)out, batch, batch, L, tw, inverse,
+                            (hipStream_t)stream));
+  HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+  return IMF_OK;
+}
+
+extern "C" imf_status imf_fft_r2c_3d(imf_ctx* c, int nx, int ny, int nz, int px, int py, int pz,
+                                     const float* in, float* out, void* stream) {
+  if (!c || !in || !out) return fail(IMF_EINVAL, "NULL argument");
+  const imf_fft_len fx = make_len(px), fy = make_len(py), fz = make_len(pz);
+  if (fx.nstages < 0 || fy.nstages < 0 || fz.nstages < 0 || px % 2 || px > 1024 || py > 1024 ||
+      pz > 1024)
+    return fail(IMF_EINVAL, "unsupported transform sizes");
+  if (nx > px || ny > py || nz > pz || nx < 1 || ny < 1 || nz < 1)
+    return fail(IMF_EINVAL, "grid larger than the transform");
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  HIPCHK(hipSetDevice(c->device));
+  const float2 *twx, *twy, *twz;
+  STCHK(get_twiddles(c, px, &twx));
+  STCHK(get_twiddles(c, py, &twy));
+  STCHK(get_twiddles(c, pz, &twz));
+  const int h = px / 2 + 1;
+  float2 *w1 = nullptr, *w2 = nullptr;
+  HIPCHK(hipMalloc(&w1, sizeof(float2) * (size_t)nz * ny * h));
+  HIPCHK(hipMalloc(&w2, sizeof(float2) * (size_t)nz * py * h));
+  imf_fwd_design_args a{in, 1, nullptr, nx, ny, nz, px, py, pz, w1, w2, (float2*)out};
+  hipError_t e = imf_launch_fwd_design(a, fx, fy, fz, twx, twy, twz, (hipStream_t)stream);
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+  hipFree(w1);
+  hipFree(w2);
+  if (e != hipSuccess) return fail(IMF_EDEVICE, "fft: %s", hipGetErrorString(e));
+  return IMF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotune: time batch widths on a real request and keep the fastest
+// ---------------------------------------------------------------------------
+extern "C" imf_status imf_autotune(imf_ctx* c, const imf_request* r, const imf_outputs* out,
+                                   int* best_batch) {
+  if (!c || !r || !out) return fail(IMF_EINVAL, "NULL argument");
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  double best = 1e300;
+  int pick = 8;
+  Plan p0;
+  std::vector<Orient> os;
+  STCHK(enumerate(c, r, os));
+  STCHK(ensure_rasters(c, r, os, c->internal));
+  STCHK(make_plan(c, r, out, os, p0));
+  for (int B : {1, 2, 4, 8, 12, 16}) {
+    if (B > p0.nO && B != 1) break;
+    imf_request rr = *r;
+    rr.batch = B;
+    imf_stats st;
+    // warm (spectra cached), then timed
+    imf_status s1 = compute_impl(c, &rr, out, &st, c->internal, c->arena);
+    if (s1 == IMF_ENOMEM) break;
+    STCHK(s1);
+    STCHK(compute_impl(c, &rr, out, &st, c->internal, c->arena));
+    if (st.t_ms[7] < best) {
+      best = st.t_ms[7];
+      pick = B;
+    }
+  }
+  char key[96];
+  snprintf(key, sizeof key, "%d|%d,%d,%d|%d,%d,%d", p0.method, p0.n[0], p0.n[1], p0.n[2],
+           p0.P[0], p0.P[1], p0.P[2]);
+  c->tuned_batch[key] = pick;
+  if (best_batch) *best_batch = pick;
+  return IMF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// serving: a queue of requests, admitted by workspace footprint, each run on
+// a worker with its own stream and workspace (continuous batching: a request
+// starts as soon as a worker and memory are free)
+// ---------------------------------------------------------------------------
+struct Request {
+  uint64_t ticket;
+  imf_request req;
+  imf_outputs out;
+  std::vector<int> tool_ids, n_dirs;
+  std::vector<char> dirs;
+  size_t footprint = 0;
+  int state = 0;  // 0 queued, 1 running, 2 done, 3 cancelled
+  imf_status status = IMF_OK;
+  std::string err;
+  imf_stats stats{};
+  std::chrono::steady_clock::time_point t_submit;
+};
+
+static void serve_worker(imf_ctx* c) {
+  hipSetDevice(c->device);
+  hipStream_t s;
+  hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  Arena ar;
+  for (;;) {
+    std::shared_ptr<Request> rq;
+    {
+      std::unique_lock<std::mutex> lk(c->smu);
+      c->scv.wait(lk, [&] {
+        if (c->stop) return true;
+        if (c->queue.empty()) return false;
+        auto& h = c->queue.front();
+        return c->inflight_bytes + h->footprint <= c->budget / 2 || c->n_running == 0;
+      });
+      if (c->stop) break;
+      rq = c->queue.front();
+      c->queue.pop_front();
+      rq->state = 1;
+      c->inflight_bytes += rq->footprint;
+      c->n_running++;
+    }
+    imf_status st;
+    {
+      // planning and caches are shared: hold the context lock while the
+      // request is planned and launched, then wait without it, so kernels of
+      // different workers overlap on the device through their streams
+      Pending pd;
+      {
+        std::lock_guard<std::recursive_mutex> lk(c->mu);
+        st = compute_launch(c, &rq->req, &rq->out, s, ar, pd);
+        if (st != IMF_OK) {
+          hipStreamSynchronize(s);
+          for (auto ev : pd.tm.ev) hipEventDestroy(ev);
+        }
+      }
+      if (st == IMF_OK) st = compute_finish(pd, &rq->stats);
+    }
+    {
+      std::lock_guard<std::mutex> lk(c->smu);
+      rq->status = st;
+      if (st != IMF_OK) rq->err = g_err;
+      rq->stats.t_ms[7] = std::chrono::duration<double, std::milli>(
+                              std::chrono::steady_clock::now() - rq->t_submit)
+                              .count();
+      rq->state = 2;
+      c->inflight_bytes -= rq->footprint;
+      c->n_running--;
+    }
+    c->scv.notify_all();
+  }
+  hipStreamSynchronize(s);
+  if (ar.base) {
+    hipFree(ar.base);
+    std::lock_guard<std::recursive_mutex> lk(c->mu);
+    c->arena_bytes -= ar.cap;
+  }
+  if (ar.host) hipHostFree(ar.host);
+  hipStreamDestroy(s);
+}
+
+static void serve_shutdown(imf_ctx* c) {
+  {
+    std::lock_guard<std::mutex> lk(c->smu);
+    c->stop = true;
+  }
+  c->scv.notify_all();
+  for (auto& t : c->workers) t.join();
+  c->workers.clear();
+}
+
+extern "C" imf_status imf_submit(imf_ctx* c, const imf_request* r, const imf_outputs* out,
+                                 uint64_t* ticket) {
+  if (!c || !r || !out || !ticket) return fail(IMF_EINVAL, "NULL argument");
+  STCHK(validate(r));
+  auto rq = std::make_shared<Request>();
+  rq->req = *r;
+  rq->out = *out;
+  rq->tool_ids.assign(r->tool_ids, r->tool_ids + r->n_tools);
+  rq->n_dirs.assign(r->n_dirs, r->n_dirs + r->n_tools);
+  long long nd = 0;
+  for (int i = 0; i < r->n_tools; i++) nd += r->n_dirs[i];
+  const size_t esz = r->dir_kind == IMF_DIR_LATTICE ? sizeof(int32_t) : sizeof(double);
+  rq->dirs.assign((const char*)r->dirs, (const char*)r->dirs + nd * r->ndim * esz);
+  rq->req.tool_ids = rq->tool_ids.data();
+  rq->req.n_dirs = rq->n_dirs.data();
+  rq->req.dirs = rq->dirs.data();
+  STCHK(imf_query_footprint(c, &rq->req, &rq->footprint));
+  rq->t_submit = std::chrono::steady_clock::now();
+  {
+    std::lock_guard<std::mutex> lk(c->smu);
+    if (c->queue.size() >= 4096) return fail(IMF_EBUSY, "serving queue full");
+    if (c->workers.empty())
+      for (int i = 0; i < c->max_inflight; i++) c->workers.emplace_back(serve_worker, c);
+    rq->ticket = c->next_ticket++;
+    c->reqs[rq->ticket] = rq;
+    c->queue.push_back(rq);
+    *ticket = rq->ticket;
+  }
+  c->scv.notify_all();
+  return IMF_OK;
+}
+
+extern "C" imf_status imf_wait(imf_ctx* c, uint64_t ticket, int timeout_ms, imf_stats* st) {
+  if (!c) return fail(IMF_EINVAL, "ctx is NULL");
+  std::unique_lock<std::mutex> lk(c->smu);
+  auto it = c->reqs.find(ticket);
+  if (it == c->reqs.end()) return fail(IMF_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+  auto rq = it->second;
+  auto done = [&] { return rq->state >= 2; };
+  if (timeout_ms < 0) {
+    c->scv.wait(lk, done);
+  } else if (!c->scv.wait_for(lk, std::chrono::milliseconds(timeout_ms), done)) {
+    return fail(IMF_ETIMEOUT, "request %llu still running", (unsigned long long)ticket);
+  }
+  c->reqs.erase(ticket);
+  if (st) *st = rq->stats;
+  if (rq->state == 3) return fail(IMF_ECANCELLED, "request %llu was cancelled", (unsigned long long)ticket);
+  if (rq->status != IMF_OK) {
+    g_err = rq->err;
+    return rq->status;
+  }
+  return IMF_OK;
+}
+
+extern "C" imf_status imf_cancel(imf_ctx* c, uint64_t ticket) {
+  if (!c) return fail(IMF_EINVAL, "ctx is NULL");
+  std::lock_guard<std::mutex> lk(c->smu);
+  auto it = c->reqs.find(ticket);
+  if (it == c->reqs.end()) return fail(IMF_EINVAL, "unknown ticket");
+  auto rq = it->second;
+  if (rq->state != 0) return fail(IMF_EBUSY, "request already started");
+  for (auto q = c->queue.begin(); q != c->queue.end(); ++q)
+    if ((*q)->ticket == ticket) {
+      c->queue.erase(q);
+      break;
+    }
+  rq->state = 3;
+  c->scv.notify_all();
+  return IMF_OK;
+}

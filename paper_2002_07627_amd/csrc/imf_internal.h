@@ -1,0 +1,176 @@
+// Internal declarations shared by the HIP kernels and the host runtime of the
+// IMF library.  Not part of the public interface (include/imf.h is).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define IMF_MAX_RUNS_PER_ROW 4
+#define IMF_WG 256
+
+// A run of voxels of an oriented tool raster: offsets start + j * e_axis,
+// 0 <= j < len.  Offsets are relative to the cutter tip (the origin).
+struct imf_run {
+  int x, y, z, len;
+};
+
+// Geometry of one oriented tool, as the raster kernels need it.
+struct imf_raster_desc {
+  int kind;            // 0 flat, 1 ball, 2 2D rectangle
+  int ndim;
+  int lattice;         // 1: exact integer predicate on v, 0: float64 on d
+  int sharp;           // 0 all cutter voxels, 1 boundary voxels, 2 tip voxel
+  double r, L, rh, LH; // cutter radius/half-width, cutter length, holder radius, L + holder length
+  double d[3];         // unit direction (tip toward holder)
+  long long v[3];      // lattice direction
+  long long vn;        // |v|^2
+  long long r2, L2, rh2, LH2;  // doubled sizes (lattice mode)
+  int lo[3], dim[3];   // bounding box of the raster in offsets
+  int s_axis;          // axis along which the sharp-point runs are formed
+  long long flags_off; // byte offset of this orientation's flag volume
+  long long rows_off;  // offset (in rows) of this orientation's row slots
+};
+
+// Extents reported by the raster kernels (atomics): [0..2] min of T, [3..5]
+// max of T, [6..8] min of S, [9..11] max of S, [12] |T|, [13] |S|, [14] run
+// slot overflow flag, [15] number of x-runs of T, [16] number of runs of S
+// along s_axis, [17] number of x-runs of S.
+#define IMF_EXT_INTS 20
+
+// Per-orientation data used by the correlation, min filter and masks.
+struct imf_orient_desc {
+  int box_lo[3];       // first translation of the query box (t = x - k)
+  int box_dim[3];      // query box size M per axis
+  int s_axis;          // axis of the sharp-point runs
+  int n_sruns;         // number of sharp-point runs
+  int n_truns;         // number of tool x-runs
+  int tlo[3], tdim[3]; // bounding box of the tool raster (offsets)
+  const imf_run* sruns;  // sharp-point runs along s_axis (x-runs for the sweep route)
+  const imf_run* truns;  // x-runs of the tool T, row order (z, y)
+  float2* spec;          // this orientation's tool spectrum [py][px/2+1][pz]
+};
+
+// FFT plan for one transform length.
+struct imf_fft_len {
+  int n;               // length
+  int nstages;
+  int radix[8];
+};
+
+// ---------------------------------------------------------------------------
+// launchers (defined in the .hip files)
+// ---------------------------------------------------------------------------
+hipError_t imf_launch_raster(const imf_raster_desc* d_desc, int n_orient, int max_vol,
+                             uint8_t* flags, int* ext, hipStream_t s);
+hipError_t imf_launch_sharp_subset(const imf_raster_desc* d_desc, int n_orient, int max_vol,
+                                   uint8_t* flags, int* ext, hipStream_t s);
+// Runs of one kind for every orientation: list 0 = x-runs of T, list 1 =
+// runs of S along s_axis, list 2 = x-runs of S.  Row slots hold up to
+// IMF_MAX_RUNS_PER_ROW runs per row; rows_off of the descriptor indexes them.
+hipError_t imf_launch_runs(const imf_raster_desc* d_desc, int n_orient, int max_rows,
+                           const uint8_t* flags, imf_run* slots, int* cnt, int* ext,
+                           hipStream_t s);
+// Compact the row slots into one list per (orientation, kind) at out_base.
+hipError_t imf_launch_compact(const imf_raster_desc* d_desc, int n_orient, int max_rows,
+                              const imf_run* slots, const int* cnt,
+                              const long long* out_base /* [n_orient][3] */, imf_run* out,
+                              hipStream_t s);
+
+hipError_t imf_launch_twiddles(float2* tw, int n, hipStream_t s);
+// transform the columns of a [n][ncols] complex array (element j at j * jstride)
+hipError_t imf_launch_columns(const float2* in, float2* out, int ncols, long long jstride,
+                              const imf_fft_len& L, const float2* tw, int inverse, hipStream_t s);
+
+// forward R2C 3D FFT of the obstacle field rho_O = max(design, fixture)
+struct imf_fwd_design_args {
+  const void* design; int density; const uint8_t* fixture;
+  int nx, ny, nz;
+  int px, py, pz;
+  float2* work1;  // [nz][ny][px/2+1]
+  float2* work2;  // [nz][py][px/2+1]
+  float2* out;    // [py][px/2+1][pz]
+};
+hipError_t imf_launch_fwd_design(const imf_fwd_design_args& a, const imf_fft_len& fx,
+                                 const imf_fft_len& fy, const imf_fft_len& fz,
+                                 const float2* twx, const float2* twy, const float2* twz,
+                                 hipStream_t s);
+
+// tool spectra of a batch of orientations into desc.spec
+struct imf_tool_fft_args {
+  const imf_orient_desc* desc; int nq;
+  int px, py, pz;
+  int max_ty, max_tz;     // max tool bbox extents over the batch
+  float2* work1;          // per q: [max_tz][max_ty][px/2+1]
+  float2* work2;          // per q: [max_tz][py][px/2+1]
+  long long w1_stride, w2_stride;
+};
+hipError_t imf_launch_tool_fft(const imf_tool_fft_args& a, const imf_fft_len& fy,
+                               const imf_fft_len& fz, const float2* twx, const float2* twy,
+                               const float2* twz, hipStream_t s);
+
+// inverse: g_q = C2R3D(rho_hat * conj(T_q)) / (px py pz), over the query boxes
+struct imf_inv_args {
+  const imf_orient_desc* desc; int nq;
+  const float2* rho_hat;  // [py][px/2+1][pz]
+  int px, py, pz;
+  int max_mx, max_my, max_mz;
+  float2* w1; long long w1_stride;   // per q: [max_mz][py][px/2+1]
+  float2* w2; long long w2_stride;   // per q: [max_mz][max_my][px/2+1]
+  float* g; long long g_stride;      // per q: [mz][my][mx] packed with the q's own dims
+  // epilogue
+  int binary;           // 1: round to integers and flag |g - rint g| > delta
+  float delta;
+  int theta_known;      // density: flag |g - theta| <= band
+  double theta, band;
+  unsigned int* max_err_bits;        // atomic max of |g - rint g| (binary)
+  int* flag_cnt; int flag_cap; int2* flags;   // (q, linear box index)
+};
+hipError_t imf_launch_inverse(const imf_inv_args& a, const imf_fft_len& fx,
+                              const imf_fft_len& fy, const imf_fft_len& fz, const float2* twx,
+                              const float2* twy, const float2* twz, hipStream_t s);
+
+// exact overlap by prefix sums along x (direct correlation and guard-band recheck)
+hipError_t imf_launch_prefix_x(const void* design, int density, const uint8_t* fixture, int nx,
+                               int ny, int nz, long long* ps, hipStream_t s);
+hipError_t imf_launch_direct(const imf_orient_desc* desc, int nq, const long long* ps, int nx, int ny, int nz, int density, float* g,
+                             long long g_stride, int max_vol, hipStream_t s);
+hipError_t imf_launch_recheck(const imf_orient_desc* desc, const long long* ps, int nx, int ny, int nz, int density,
+                              const int* flag_cnt, const int2* flags, int flag_cap,
+                              int theta_known, double theta, float* g, long long g_stride,
+                              hipStream_t s);
+
+// sharp-point min filter with running minimum, masks, optional gamma stack
+struct imf_min_args {
+  const imf_orient_desc* desc; int nq;
+  const float* g; long long g_stride;
+  float* lvl; long long lvl_stride; int nlvl;   // sparse-table levels per q
+  int nx, ny, nz;
+  float* f;                 // running min [nz][ny][nx]
+  const uint8_t* omega0;    // [nz][ny][nx]
+  int masks_on; double theta; uint64_t* masks; int mask_q0;  // masks for orientations mask_q0 + q
+  float* gamma_stack; int gamma_q0;   // optional
+};
+hipError_t imf_launch_minfilter(const imf_min_args& a, hipStream_t s);
+
+// sweep route: A = Omega_0 and (D^c dilated by S) with D^c = {g <= theta}
+struct imf_sweep_args {
+  const imf_orient_desc* desc; int nq;   // sruns hold the x-runs of S
+  const float* g; long long g_stride; double theta;
+  int nx, ny, nz; const uint8_t* omega0;
+  uint64_t* dc; long long dc_stride;   // scratch bitset per q over the box
+  uint64_t* masks; int mask_q0;
+};
+hipError_t imf_launch_sweep(const imf_sweep_args& a, hipStream_t s);
+
+// finalize
+hipError_t imf_launch_fill_f(float* f, long long n, float v, hipStream_t s);
+hipError_t imf_launch_omega0(const uint8_t* fixture, const uint8_t* domain, uint8_t* omega0,
+                             long long n, hipStream_t s);
+hipError_t imf_launch_fmax(const float* f, const uint8_t* omega0, long long n,
+                           unsigned int* fmax_bits, hipStream_t s);
+hipError_t imf_launch_finalize(const float* f, const uint8_t* omega0, const void* design,
+                               int density, long long n, const unsigned int* fmax_bits,
+                               double lambda, double tau, float* imf_out, float* imf_norm,
+                               uint8_t* secluded, hipStream_t s);
+hipError_t imf_launch_masks_from_gamma(const float* gamma_stack, int nq, const uint8_t* omega0,
+                                       int nx, int ny, int nz, const unsigned int* fmax_bits,
+                                       double lambda, uint64_t* masks, hipStream_t s);

@@ -1,0 +1,693 @@
+// FFT-based correlation (the Convolve step of Algorithm 1 and App. B: two
+// forward transforms, a pointwise product, one inverse transform).
+//
+// All transforms are hand-written for gfx950: a tile of CT columns of length
+// n is staged in LDS, transformed there by self-sorting (Stockham) radix stages
+// (radices 2, 3, 4, 5, 7, 8; twiddles computed in float64, stored as float32
+// and kept in LDS), and written back.  Columns are chosen so that every global
+// access moves CT consecutive complex values (128 bytes for CT = 16) or whole
+// contiguous columns.
+//
+// Spectrum layout: [ky][kx][kz] with kx in [0, px/2] (real-to-complex along x)
+// and kz fastest, so the fused product + inverse z pass reads both spectra as
+// contiguous columns.  The reflection of the tool (its conjugate-symmetric
+// image) is the complex conjugate of its spectrum (Algorithm 1's Reflect).
+#include "imf_internal.h"
+
+#define CT_MAX 16
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+// multiply by -i (forward) or +i (inverse)
+__device__ __forceinline__ float2 mul_mi(float2 a, bool inv) {
+  return inv ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+// ---------------------------------------------------------------------------
+// small DFTs, y_k = sum_j v_j exp(-+ 2 pi i jk / R)
+// ---------------------------------------------------------------------------
+template <int R>
+struct dft_consts;
+template <>
+struct dft_consts<5> {
+  static constexpr float c[5] = {1.0f, 0.30901699437494745f, -0.8090169943749473f,
+                                 -0.8090169943749476f, 0.30901699437494723f};
+  static constexpr float s[5] = {0.0f, 0.9510565162951535f, 0.5877852522924732f,
+                                 -0.587785252292473f, -0.9510565162951536f};
+};
+template <>
+struct dft_consts<7> {
+  static constexpr float c[7] = {1.0f, 0.6234898018587336f, -0.22252093395631434f,
+                                 -0.900968867902419f, -0.9009688679024191f,
+                                 -0.2225209339563146f, 0.6234898018587334f};
+  static constexpr float s[7] = {0.0f, 0.7818314824680298f, 0.9749279121818236f,
+                                 0.43388373911755823f, -0.433883739117558f,
+                                 -0.9749279121818236f, -0.7818314824680299f};
+};
+
+template <int R>
+__device__ __forceinline__ void dft(float2* v, bool inv);
+
+template <>
+__device__ __forceinline__ void dft<2>(float2* v, bool) {
+  const float2 a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+template <>
+__device__ __forceinline__ void dft<4>(float2* v, bool inv) {
+  const float2 s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+  const float2 s13 = cadd(v[1], v[3]), d13 = mul_mi(csub(v[1], v[3]), inv);
+  v[0] = cadd(s02, s13);
+  v[2] = csub(s02, s13);
+  v[1] = cadd(d02, d13);
+  v[3] = csub(d02, d13);
+}
+template <>
+__device__ __forceinline__ void dft<8>(float2* v, bool inv) {
+  const float h = 0.7071067811865476f;
+  float2 a[4], b[4];
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    a[k] = cadd(v[k], v[k + 4]);
+    b[k] = csub(v[k], v[k + 4]);
+  }
+  // b_k *= W8^k
+  b[1] = inv ? make_float2(h * (b[1].x - b[1].y), h * (b[1].x + b[1].y))
+             : make_float2(h * (b[1].x + b[1].y), h * (b[1].y - b[1].x));
+  b[2] = mul_mi(b[2], inv);
+  b[3] = inv ? make_float2(-h * (b[3].x + b[3].y), h * (b[3].x - b[3].y))
+             : make_float2(h * (b[3].y - b[3].x), -h * (b[3].x + b[3].y));
+  dft<4>(a, inv);
+  dft<4>(b, inv);
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    v[2 * k] = a[k];
+    v[2 * k + 1] = b[k];
+  }
+}
+template <>
+__device__ __forceinline__ void dft<3>(float2* v, bool inv) {
+  const float s3 = 0.8660254037844386f;
+  const float2 t1 = cadd(v[1], v[2]);
+  const float2 t2 = make_float2(v[0].x - 0.5f * t1.x, v[0].y - 0.5f * t1.y);
+  const float2 d = csub(v[1], v[2]);
+  // -i s3 d (forward) / +i s3 d (inverse)
+  const float2 t3 = mul_mi(make_float2(s3 * d.x, s3 * d.y), inv);
+  v[0] = cadd(v[0], t1);
+  v[1] = cadd(t2, t3);
+  v[2] = csub(t2, t3);
+}
+template <int R>
+__device__ __forceinline__ void dft_generic(float2* v, bool inv) {
+  float2 y[R];
+#pragma unroll
+  for (int k = 0; k < R; k++) {
+    float2 acc = v[0];
+#pragma unroll
+    for (int j = 1; j < R; j++) {
+      const int m = (j * k) % R;
+      const float c = dft_consts<R>::c[m];
+      const float s = inv ? dft_consts<R>::s[m] : -dft_consts<R>::s[m];
+      acc.x += v[j].x * c - v[j].y * s;
+      acc.y += v[j].x * s + v[j].y * c;
+    }
+    y[k] = acc;
+  }
+#pragma unroll
+  for (int k = 0; k < R; k++) v[k] = y[k];
+}
+template <>
+__device__ __forceinline__ void dft<5>(float2* v, bool inv) { dft_generic<5>(v, inv); }
+template <>
+__device__ __forceinline__ void dft<7>(float2* v, bool inv) { dft_generic<7>(v, inv); }
+
+// ---------------------------------------------------------------------------
+// one Stockham stage over a tile of CT columns held in LDS (in place: every
+// thread keeps its butterflies in registers across the barrier)
+// ---------------------------------------------------------------------------
+template <int R, int CT, int MAXE>
+__device__ __forceinline__ void fft_stage(float2* X, int stride, const float2* tw, int n, int Ns,
+                                          bool inv) {
+  constexpr int IT = (MAXE + R - 1) / R;
+  float2 reg[IT * R];
+  const int nb = n / R;
+  const int items = CT * nb;
+  const int step = n / (Ns * R);
+#pragma unroll
+  for (int it = 0; it < IT; it++) {
+    const int item = threadIdx.x + it * IMF_WG;
+    if (item < items) {
+      const int c = item / nb;
+      const int j = item - c * nb;
+      const float2* col = X + c * stride;
+      float2 v[R];
+#pragma unroll
+      for (int k = 0; k < R; k++) v[k] = col[j + k * nb];
+      if (Ns > 1) {
+        const int jm = j % Ns;
+#pragma unroll
+        for (int k = 1; k < R; k++) {
+          float2 w = tw[jm * k * step];
+          if (inv) w.y = -w.y;
+          v[k] = cmul(v[k], w);
+        }
+      }
+      dft<R>(v, inv);
+#pragma unroll
+      for (int k = 0; k < R; k++) reg[it * R + k] = v[k];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < IT; it++) {
+    const int item = threadIdx.x + it * IMF_WG;
+    if (item < items) {
+      const int c = item / nb;
+      const int j = item - c * nb;
+      const int jm = j % Ns;
+      const int idx = (j - jm) * R + jm;
+      float2* col = X + c * stride;
+#pragma unroll
+      for (int k = 0; k < R; k++) col[idx + k * Ns] = reg[it * R + k];
+    }
+  }
+  __syncthreads();
+}
+
+// Transform all CT columns of the tile (length L.n, stride `stride`).
+template <int CT, int MAXE>
+__device__ void fft_tile(float2* X, int stride, const float2* tw, const imf_fft_len& L, bool inv) {
+  int Ns = 1;
+  for (int s = 0; s < L.nstages; s++) {
+    const int R = L.radix[s];
+    switch (R) {
+      case 8: fft_stage<8, CT, MAXE>(X, stride, tw, L.n, Ns, inv); break;
+      case 4: fft_stage<4, CT, MAXE>(X, stride, tw, L.n, Ns, inv); break;
+      case 2: fft_stage<2, CT, MAXE>(X, stride, tw, L.n, Ns, inv); break;
+      case 3: fft_stage<3, CT, MAXE>(X, stride, tw, L.n, Ns, inv); break;
+      case 5: fft_stage<5, CT, MAXE>(X, stride, tw, L.n, Ns, inv); break;
+      case 7: fft_stage<7, CT, MAXE>(X, stride, tw, L.n, Ns, inv); break;
+      default: break;
+    }
+    Ns *= R;
+  }
+}
+
+__device__ __forceinline__ void load_twiddles(float2* tw_lds, const float2* tw, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) tw_lds[i] = tw[i];
+}
+
+__device__ __forceinline__ int pmod(long long a, int n) {
+  long long r = a % n;
+  return (int)(r < 0 ? r + n : r);
+}
+
+// ---------------------------------------------------------------------------
+// twiddle tables: tw[m] = exp(-2 pi i m / n), computed in float64
+// ---------------------------------------------------------------------------
+__global__ void k_twiddles(float2* tw, int n) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m < n) {
+    double s, c;
+    sincospi(2.0 * (double)m / (double)n, &s, &c);
+    tw[m] = make_float2((float)c, (float)-s);
+  }
+}
+
+hipError_t imf_launch_twiddles(float2* tw, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_twiddles, dim3((n + 255) / 256), dim3(256), 0, s, tw, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// (1) forward x pass of the obstacle field: rho_O = max(design, fixture),
+//     two real rows per complex column, output rows of px/2 + 1 values
+// ---------------------------------------------------------------------------
+template <int CT, int MAXE>
+__global__ void __launch_bounds__(IMF_WG) k_fwd_x_r2c(imf_fwd_design_args a, imf_fft_len L,
+                                                      const float2* __restrict__ twg) {
+  extern __shared__ float2 smem[];
+  const int n = L.n, stride = n + 1, h = n / 2 + 1;
+  float2* X = smem;
+  float2* tw = smem + CT * stride;
+  load_twiddles(tw, twg, n);
+  const long long rows = (long long)a.ny * a.nz;
+  const long long row0 = (long long)blockIdx.x * 2 * CT;
+  for (int i = threadIdx.x; i < 2 * CT * n; i += IMF_WG) {
+    const int rr = i / n, x = i - rr * n;
+    const long long row = row0 + rr;
+    float v = 0.f;
+    if (row < rows && x < a.nx) {
+      const long long idx = row * a.nx + x;
+      const float d = a.density ? ((const float*)a.design)[idx]
+                                : (float)((const uint8_t*)a.design)[idx];
+      const bool fx = a.fixture && a.fixture[idx];
+      v = fx ? 1.0f : d;
+    }
+    float* p = (float*)&X[(rr >> 1) * stride + x];
+    p[rr & 1] = v;
+  }
+  __syncthreads();
+  fft_tile<CT, MAXE>(X, stride, tw, L, false);
+  for (int i = threadIdx.x; i < 2 * CT * h; i += IMF_WG) {
+    const int rr = i / h, k = i - rr * h;
+    const long long row = row0 + rr;
+    if (row >= rows) continue;
+    const float2* col = X + (rr >> 1) * stride;
+    const float2 A = col[k];
+    const float2 Bc = col[k == 0 ? 0 : n - k];
+    const float2 B = make_float2(Bc.x, -Bc.y);
+    float2 out;
+    if ((rr & 1) == 0) {
+      out = make_float2(0.5f * (A.x + B.x), 0.5f * (A.y + B.y));
+    } else {
+      const float2 d = csub(A, B);
+      out = make_float2(0.5f * d.y, -0.5f * d.x);
+    }
+    a.work1[row * h + k] = out;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// (2) generic strided pass: columns are CT consecutive elements (stride 1)
+//     of a plane; element j of a column sits at j * jstride.
+//     Input j < n_in goes to position (j + shift_in) mod n; output j' < n_out
+//     comes from position (j' + shift_out) mod n.
+// ---------------------------------------------------------------------------
+struct strided_io {
+  const float2* in;
+  long long in_q, in_plane, in_j;
+  float2* out;
+  long long out_q, out_plane, out_j;
+  int ncols;
+};
+
+// pass kinds for the per-orientation geometry
+enum { PASS_DESIGN_Y = 0, PASS_TOOL_Y = 1, PASS_INV_Y = 2 };
+
+template <int CT, int MAXE, int KIND>
+__global__ void __launch_bounds__(IMF_WG) k_pass_strided(strided_io io, imf_fft_len L,
+                                                         const float2* __restrict__ twg,
+                                                         const imf_orient_desc* __restrict__ desc,
+                                                         int planes_fixed, int n_in_fixed,
+                                                         int n_out_fixed, int inv) {
+  extern __shared__ float2 smem[];
+  const int n = L.n, stride = n + 1;
+  const int q = blockIdx.z, plane = blockIdx.y;
+  int planes = planes_fixed, n_in = n_in_fixed, n_out = n_out_fixed, sh_in = 0, sh_out = 0;
+  if (KIND == PASS_TOOL_Y) {
+    planes = desc[q].tdim[2];
+    n_in = desc[q].tdim[1];
+    sh_in = pmod(desc[q].tlo[1], n);
+  } else if (KIND == PASS_INV_Y) {
+    planes = desc[q].box_dim[2];
+    n_out = desc[q].box_dim[1];
+    sh_out = pmod(desc[q].box_lo[1], n);
+  }
+  if (plane >= planes) return;
+  float2* X = smem;
+  float2* tw = smem + CT * stride;
+  load_twiddles(tw, twg, n);
+  const int c0 = blockIdx.x * CT;
+  const float2* in = io.in + q * io.in_q + plane * io.in_plane + c0;
+  for (int i = threadIdx.x; i < CT * n; i += IMF_WG) {
+    const int j = i / CT, c = i - j * CT;
+    float2 v = make_float2(0.f, 0.f);
+    if (j < n_in && c0 + c < io.ncols) v = in[j * io.in_j + c];
+    int pos = j + sh_in;
+    if (pos >= n) pos -= n;
+    X[c * stride + pos] = v;
+  }
+  __syncthreads();
+  fft_tile<CT, MAXE>(X, stride, tw, L, inv != 0);
+  float2* out = io.out + q * io.out_q + plane * io.out_plane + c0;
+  for (int i = threadIdx.x; i < CT * n_out; i += IMF_WG) {
+    const int j = i / CT, c = i - j * CT;
+    if (c0 + c >= io.ncols) continue;
+    int pos = j + sh_out;
+    if (pos >= n) pos -= n;
+    out[j * io.out_j + c] = X[c * stride + pos];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// (3) forward z pass: strided input (plane stride), contiguous output columns
+//     out[ky][kx][kz].  The tile is CT consecutive kx at one ky.
+// ---------------------------------------------------------------------------
+template <int CT, int MAXE, int TOOL>
+__global__ void __launch_bounds__(IMF_WG) k_pass_z_fwd(const float2* __restrict__ in,
+                                                       long long in_q, long long in_j,
+                                                       float2* __restrict__ out, int h,
+                                                       int n_in_fixed, imf_fft_len L,
+                                                       const float2* __restrict__ twg,
+                                                       const imf_orient_desc* __restrict__ desc,
+                                                       long long spec_q_fixed) {
+  extern __shared__ float2 smem[];
+  const int n = L.n, stride = n + 1;
+  const int q = blockIdx.z, ky = blockIdx.y;
+  int n_in = n_in_fixed, sh = 0;
+  float2* obase = out + q * spec_q_fixed;
+  if (TOOL) {
+    n_in = desc[q].tdim[2];
+    sh = pmod(desc[q].tlo[2], n);
+    obase = desc[q].spec;
+  }
+  float2* X = smem;
+  float2* tw = smem + CT * stride;
+  load_twiddles(tw, twg, n);
+  const int c0 = blockIdx.x * CT;
+  // element (j, ky, kx) of the input at j * in_j + ky * h + kx
+  const float2* src = in + q * in_q + (long long)ky * h + c0;
+  for (int i = threadIdx.x; i < CT * n; i += IMF_WG) {
+    const int j = i / CT, c = i - j * CT;
+    float2 v = make_float2(0.f, 0.f);
+    if (j < n_in && c0 + c < h) v = src[j * in_j + c];
+    int pos = j + sh;
+    if (pos >= n) pos -= n;
+    X[c * stride + pos] = v;
+  }
+  __syncthreads();
+  fft_tile<CT, MAXE>(X, stride, tw, L, false);
+  float2* dst = obase + ((long long)ky * h + c0) * n;
+  const int ncol = min(CT, h - c0);
+  for (int i = threadIdx.x; i < ncol * n; i += IMF_WG) {
+    const int c = i / n, k = i - c * n;
+    dst[(long long)c * n + k] = X[c * stride + k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// (4) tool x pass: direct DFT of the x-runs of T.  One thread per (run, kx)
+//     sums all runs of its row when it holds the row's first run.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(IMF_WG) k_tool_x(const imf_orient_desc* __restrict__ desc,
+                                                   const float2* __restrict__ tw, int px,
+                                                   float2* __restrict__ work1, long long w1_q,
+                                                   int max_ty) {
+  const int q = blockIdx.y;
+  const imf_orient_desc& d = desc[q];
+  const int h = px / 2 + 1;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long r = idx / h;
+  const int k = (int)(idx - r * h);
+  if (r >= d.n_truns) return;
+  const imf_run* rl = d.truns;
+  const imf_run me = rl[r];
+  if (r > 0 && rl[r - 1].y == me.y && rl[r - 1].z == me.z) return;
+  float2 acc = make_float2(0.f, 0.f);
+  for (long long rr = r; rr < d.n_truns; rr++) {
+    const imf_run u = rl[rr];
+    if (u.y != me.y || u.z != me.z) break;
+    int m = pmod((long long)k * u.x, px);
+    for (int j = 0; j < u.len; j++) {
+      const float2 w = tw[m];
+      acc.x += w.x;
+      acc.y += w.y;
+      m += k;
+      if (m >= px) m -= px;
+    }
+  }
+  const int iy = me.y - d.tlo[1], iz = me.z - d.tlo[2];
+  work1[q * w1_q + ((long long)iz * max_ty + iy) * h + k] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// (5) fused spectral product + inverse z pass.  rho_hat and the tool spectrum
+//     are read as contiguous columns; Y = rho_hat conj(T) / (px py pz) is
+//     inverted along z and the query-box range of z is written strided.
+//     The rho_hat tile is kept in registers and reused for every orientation
+//     of the batch.
+// ---------------------------------------------------------------------------
+template <int CT, int MAXE>
+__global__ void __launch_bounds__(IMF_WG) k_inv_z_product(imf_inv_args a, imf_fft_len L,
+                                                          const float2* __restrict__ twg) {
+  extern __shared__ float2 smem[];
+  const int n = L.n, stride = n + 1;
+  const int h = a.px / 2 + 1;
+  const int ky = blockIdx.y;
+  const int c0 = blockIdx.x * CT;
+  const int ncol = min(CT, h - c0);
+  float2* X = smem;
+  float2* tw = smem + CT * stride;
+  load_twiddles(tw, twg, n);
+  const float scale = 1.0f / ((float)a.px * (float)a.py * (float)a.pz);
+  const float2* rsrc = a.rho_hat + ((long long)ky * h + c0) * n;
+  float2 rho[MAXE];
+#pragma unroll
+  for (int e = 0; e < MAXE; e++) {
+    const int i = threadIdx.x + e * IMF_WG;
+    rho[e] = i < ncol * n ? rsrc[i] : make_float2(0.f, 0.f);
+  }
+  for (int q = 0; q < a.nq; q++) {
+    const imf_orient_desc& d = a.desc[q];
+    const float2* tsrc = d.spec + ((long long)ky * h + c0) * n;
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < MAXE; e++) {
+      const int i = threadIdx.x + e * IMF_WG;
+      if (i < CT * n) {
+        const int c = i / n, k = i - c * n;
+        float2 v = make_float2(0.f, 0.f);
+        if (c < ncol) {
+          const float2 t = tsrc[i];
+          const float2 r = rho[e];
+          // r * conj(t) * scale
+          v = make_float2((r.x * t.x + r.y * t.y) * scale, (r.y * t.x - r.x * t.y) * scale);
+        }
+        X[c * stride + k] = v;
+      }
+    }
+    __syncthreads();
+    fft_tile<CT, MAXE>(X, stride, tw, L, true);
+    const int mz = d.box_dim[2];
+    const int sh = pmod(d.box_lo[2], n);
+    float2* dst = a.w1 + q * a.w1_stride + (long long)ky * h + c0;
+    const long long zs = (long long)a.py * h;
+    for (int i = threadIdx.x; i < CT * mz; i += IMF_WG) {
+      const int z = i / CT, c = i - z * CT;
+      if (c >= ncol) continue;
+      int pos = z + sh;
+      if (pos >= n) pos -= n;
+      dst[z * zs + c] = X[c * stride + pos];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// (6) inverse x pass (complex-to-real, two rows per complex column) with the
+//     rounding / guard-band epilogue.  Writes g over the query box.
+// ---------------------------------------------------------------------------
+template <int CT, int MAXE>
+__global__ void __launch_bounds__(IMF_WG) k_inv_x_c2r(imf_inv_args a, imf_fft_len L,
+                                                      const float2* __restrict__ twg) {
+  extern __shared__ float2 smem[];
+  const int n = L.n, stride = n + 1, h = n / 2 + 1;
+  const int q = blockIdx.z;
+  const imf_orient_desc& d = a.desc[q];
+  const int mx = d.box_dim[0], my = d.box_dim[1], mz = d.box_dim[2];
+  const long long rows = (long long)my * mz;
+  const long long row0 = (long long)blockIdx.x * 2 * CT;
+  if (row0 >= rows) return;
+  float2* X = smem;
+  float2* tw = smem + CT * stride;
+  load_twiddles(tw, twg, n);
+  const float2* src = a.w2 + q * a.w2_stride;
+  for (int i = threadIdx.x; i < CT * h; i += IMF_WG) {
+    const int c = i / h, k = i - c * h;
+    const long long ra = row0 + 2 * c, rb = ra + 1;
+    float2 A = make_float2(0.f, 0.f), B = make_float2(0.f, 0.f);
+    if (ra < rows) {
+      const long long zz = ra / my, yy = ra - zz * my;
+      A = src[(zz * a.max_my + yy) * h + k];
+    }
+    if (rb < rows) {
+      const long long zz = rb / my, yy = rb - zz * my;
+      B = src[(zz * a.max_my + yy) * h + k];
+    }
+    // Z(k) = A + iB;  Z(n-k) = conj(A) + i conj(B)
+    X[c * stride + k] = make_float2(A.x - B.y, A.y + B.x);
+    if (k > 0 && k < n - k) X[c * stride + n - k] = make_float2(A.x + B.y, B.x - A.y);
+  }
+  __syncthreads();
+  fft_tile<CT, MAXE>(X, stride, tw, L, true);
+  const int sh = pmod(d.box_lo[0], n);
+  float* dst = a.g + q * a.g_stride;
+  float local_err = 0.f;
+  for (int i = threadIdx.x; i < 2 * CT * mx; i += IMF_WG) {
+    const int rr = i / mx, x = i - rr * mx;
+    const long long row = row0 + rr;
+    if (row >= rows) continue;
+    int pos = x + sh;
+    if (pos >= n) pos -= n;
+    const float2 z = X[(rr >> 1) * stride + pos];
+    float v = (rr & 1) ? z.y : z.x;
+    const long long li = row * mx + x;
+    if (a.binary) {
+      const float G = rintf(v);
+      const float e = fabsf(v - G);
+      local_err = fmaxf(local_err, e);
+      if (e > a.delta) {
+        const int slot = atomicAdd(a.flag_cnt, 1);
+        if (slot < a.flag_cap) a.flags[slot] = make_int2(q, (int)li);
+      }
+      v = G;
+    } else if (a.theta_known) {
+      if (fabs((double)v - a.theta) <= a.band) {
+        const int slot = atomicAdd(a.flag_cnt, 1);
+        if (slot < a.flag_cap) a.flags[slot] = make_int2(q, (int)li);
+      }
+    }
+    dst[li] = v;
+  }
+  if (a.binary) {
+    for (int o = 32; o > 0; o >>= 1) local_err = fmaxf(local_err, __shfl_xor(local_err, o));
+    if ((threadIdx.x & 63) == 0) atomicMax(a.max_err_bits, __float_as_uint(local_err));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// dispatch on the transform length (CT columns x MAXE elements per thread)
+// ---------------------------------------------------------------------------
+#define DISPATCH(n, ...)                                   \
+  do {                                                     \
+    if ((n) <= 256) {                                      \
+      constexpr int CT = 16, MAXE = 16;                    \
+      __VA_ARGS__;                                         \
+    } else if ((n) <= 512) {                               \
+      constexpr int CT = 16, MAXE = 32;                    \
+      __VA_ARGS__;                                         \
+    } else {                                               \
+      constexpr int CT = 8, MAXE = 32;                     \
+      __VA_ARGS__;                                         \
+    }                                                      \
+  } while (0)
+
+static size_t smem_bytes(int n, int ct) { return (size_t)(ct * (n + 1) + n) * sizeof(float2); }
+
+static hipError_t set_smem(const void* fn, size_t bytes) {
+  if (bytes > 64 * 1024)
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  return hipSuccess;
+}
+
+hipError_t imf_launch_fwd_design(const imf_fwd_design_args& a, const imf_fft_len& fx,
+                                 const imf_fft_len& fy, const imf_fft_len& fz,
+                                 const float2* twx, const float2* twy, const float2* twz,
+                                 hipStream_t s) {
+  const int h = a.px / 2 + 1;
+  hipError_t e;
+  DISPATCH(fx.n, {
+    const long long rows = (long long)a.ny * a.nz;
+    const size_t sm = smem_bytes(fx.n, CT);
+    auto k = k_fwd_x_r2c<CT, MAXE>;
+    if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3((unsigned)((rows + 2 * CT - 1) / (2 * CT))), dim3(IMF_WG), sm, s,
+                       a, fx, twx);
+  });
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  DISPATCH(fy.n, {
+    strided_io io{a.work1, 0, (long long)a.ny * h, h, a.work2, 0, (long long)a.py * h, h, h};
+    const size_t sm = smem_bytes(fy.n, CT);
+    auto k = k_pass_strided<CT, MAXE, PASS_DESIGN_Y>;
+    if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3((h + CT - 1) / CT, a.nz, 1), dim3(IMF_WG), sm, s, io, fy, twy,
+                       (const imf_orient_desc*)nullptr, a.nz, a.ny, a.py, 0);
+  });
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  DISPATCH(fz.n, {
+    const size_t sm = smem_bytes(fz.n, CT);
+    auto k = k_pass_z_fwd<CT, MAXE, 0>;
+    if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3((h + CT - 1) / CT, a.py, 1), dim3(IMF_WG), sm, s, a.work2, 0LL,
+                       (long long)a.py * h, a.out, h, a.nz, fz, twz,
+                       (const imf_orient_desc*)nullptr, 0LL);
+  });
+  return hipGetLastError();
+}
+
+hipError_t imf_launch_tool_fft(const imf_tool_fft_args& a, const imf_fft_len& fy,
+                               const imf_fft_len& fz, const float2* twx, const float2* twy,
+                               const float2* twz, hipStream_t s) {
+  const int h = a.px / 2 + 1;
+  hipError_t e = hipMemsetAsync(a.work1, 0, sizeof(float2) * a.w1_stride * a.nq, s);
+  if (e != hipSuccess) return e;
+  // x: direct DFT of the runs (rows without runs stay zero)
+  {
+    const long long max_runs = (long long)a.max_ty * a.max_tz * IMF_MAX_RUNS_PER_ROW;
+    dim3 grid((unsigned)((max_runs * h + IMF_WG - 1) / IMF_WG), a.nq);
+    hipLaunchKernelGGL(k_tool_x, grid, dim3(IMF_WG), 0, s, a.desc, twx, a.px, a.work1,
+                       a.w1_stride, a.max_ty);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  DISPATCH(fy.n, {
+    strided_io io{a.work1, a.w1_stride, (long long)a.max_ty * h, h,
+                  a.work2, a.w2_stride, (long long)a.py * h, h, h};
+    const size_t sm = smem_bytes(fy.n, CT);
+    auto k = k_pass_strided<CT, MAXE, PASS_TOOL_Y>;
+    if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3((h + CT - 1) / CT, a.max_tz, a.nq), dim3(IMF_WG), sm, s, io, fy,
+                       twy, a.desc, 0, 0, a.py, 0);
+  });
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  DISPATCH(fz.n, {
+    const size_t sm = smem_bytes(fz.n, CT);
+    auto k = k_pass_z_fwd<CT, MAXE, 1>;
+    if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3((h + CT - 1) / CT, a.py, a.nq), dim3(IMF_WG), sm, s, a.work2,
+                       a.w2_stride, (long long)a.py * h, (float2*)nullptr, h, 0, fz, twz, a.desc,
+                       0LL);
+  });
+  return hipGetLastError();
+}
+
+hipError_t imf_launch_inverse(const imf_inv_args& a, const imf_fft_len& fx,
+                              const imf_fft_len& fy, const imf_fft_len& fz, const float2* twx,
+                              const float2* twy, const float2* twz, hipStream_t s) {
+  const int h = a.px / 2 + 1;
+  hipError_t e;
+  DISPATCH(fz.n, {
+    const size_t sm = smem_bytes(fz.n, CT);
+    auto k = k_inv_z_product<CT, MAXE>;
+    if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3((h + CT - 1) / CT, a.py, 1), dim3(IMF_WG), sm, s, a, fz, twz);
+  });
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  DISPATCH(fy.n, {
+    strided_io io{a.w1, a.w1_stride, (long long)a.py * h, h,
+                  a.w2, a.w2_stride, (long long)a.max_my * h, h, h};
+    const size_t sm = smem_bytes(fy.n, CT);
+    auto k = k_pass_strided<CT, MAXE, PASS_INV_Y>;
+    if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3((h + CT - 1) / CT, a.max_mz, a.nq), dim3(IMF_WG), sm, s, io, fy,
+                       twy, a.desc, 0, a.py, 0, 1);
+  });
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  DISPATCH(fx.n, {
+    const size_t sm = smem_bytes(fx.n, CT);
+    auto k = k_inv_x_c2r<CT, MAXE>;
+    if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
+    const long long rows = (long long)a.max_my * a.max_mz;
+    hipLaunchKernelGGL(k, dim3((unsigned)((rows + 2 * CT - 1) / (2 * CT)), 1, a.nq),
+                       dim3(IMF_WG), sm, s, a, fx, twx);
+  });
+  return hipGetLastError();
+}
+
+// columns of a [n][ncols] complex array (single-step check entry point)
+hipError_t imf_launch_columns(const float2* in, float2* out, int ncols, long long jstride,
+                              const imf_fft_len& L, const float2* tw, int inverse, hipStream_t s) {
+  hipError_t e;
+  DISPATCH(L.n, {
+    strided_io io{in, 0, 0, jstride, out, 0, 0, jstride, ncols};
+    const size_t sm = smem_bytes(L.n, CT);
+    auto k = k_pass_strided<CT, MAXE, PASS_DESIGN_Y>;
+    if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3((ncols + CT - 1) / CT, 1, 1), dim3(IMF_WG), sm, s, io, L, tw,
+                       (const imf_orient_desc*)nullptr, 1, L.n, L.n, inverse);
+  });
+  return hipGetLastError();
+}

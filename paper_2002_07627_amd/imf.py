@@ -1,0 +1,333 @@
+"""ctypes binding of libimf.so: argument marshalling only.
+
+Every step of the computation runs in the HIP kernels of the library.  When the
+library has not been built, or cannot be loaded, importing works but any call
+raises: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libimf.so")
+
+TOOL_FLAT, TOOL_BALL, TOOL_RECT2D = 0, 1, 2
+DIR_F64, DIR_LATTICE = 0, 1
+SHARP_ALL, SHARP_BOUNDARY, SHARP_TIP = 0, 1, 2
+METHOD_AUTO, METHOD_FFT, METHOD_DIRECT = 0, 1, 2
+FLAG_PLAIN, FLAG_MASK_SWEEP, FLAG_NO_CACHE = 1, 2, 4
+
+_STATUS = {0: "IMF_OK", 1: "IMF_EINVAL", 2: "IMF_ENOMEM", 3: "IMF_EDEVICE", 4: "IMF_EBUSY",
+           5: "IMF_ETIMEOUT", 6: "IMF_ECANCELLED", 7: "IMF_EACCURACY", 8: "IMF_ENOTIMPL"}
+
+
+class IMFError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (_STATUS.get(status, status), msg))
+        self.status = status
+
+
+class _Tool(C.Structure):
+    _fields_ = [("kind", C.c_int), ("cutter_r", C.c_double), ("cutter_len", C.c_double),
+                ("holder_r", C.c_double), ("holder_len", C.c_double)]
+
+
+class _Request(C.Structure):
+    _fields_ = [("ndim", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+                ("design_is_density", C.c_int), ("design", C.c_void_p), ("fixture", C.c_void_p),
+                ("domain", C.c_void_p), ("n_tools", C.c_int), ("tool_ids", C.c_void_p),
+                ("n_dirs", C.c_void_p), ("dir_kind", C.c_int), ("dirs", C.c_void_p),
+                ("sharp", C.c_int), ("lam", C.c_double), ("tau", C.c_double),
+                ("mask_theta_abs", C.c_double), ("method", C.c_int), ("batch", C.c_int),
+                ("flags", C.c_uint)]
+
+
+class _Outputs(C.Structure):
+    _fields_ = [("imf", C.c_void_p), ("imf_norm", C.c_void_p), ("secluded", C.c_void_p),
+                ("acc_masks", C.c_void_p), ("debug_overlap", C.c_void_p),
+                ("debug_orient", C.c_int), ("debug_box", C.c_int * 6)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("F_max", C.c_double), ("guard_flags", C.c_longlong),
+                ("max_frac_err", C.c_float), ("guard_band", C.c_double),
+                ("t_ms", C.c_double * 8), ("model_bytes", C.c_double), ("P", C.c_int * 3),
+                ("n_orient", C.c_int), ("method", C.c_int), ("batch", C.c_int),
+                ("cache_hits", C.c_int), ("cache_misses", C.c_int)]
+
+
+@dataclass
+class Stats:
+    F_max: float
+    guard_flags: int
+    max_frac_err: float
+    guard_band: float
+    t_ms: list
+    model_bytes: float
+    P: tuple
+    n_orient: int
+    method: int
+    batch: int
+    cache_hits: int
+    cache_misses: int
+
+    @classmethod
+    def _from(cls, s: _Stats):
+        return cls(s.F_max, s.guard_flags, s.max_frac_err, s.guard_band, list(s.t_ms),
+                   s.model_bytes, tuple(s.P), s.n_orient, s.method, s.batch, s.cache_hits,
+                   s.cache_misses)
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def _L():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError("libimf.so is not built (run __graft_entry__.build() or "
+                              "python paper_2002_07627_amd/build.py)")
+        L = C.CDLL(_LIB_PATH)
+        L.imf_last_error.restype = C.c_char_p
+        L.imf_fft_size.restype = C.c_int
+        for name in ("imf_create", "imf_destroy", "imf_tool_register", "imf_query_footprint",
+                     "imf_compute", "imf_submit", "imf_wait", "imf_cancel", "imf_autotune",
+                     "imf_raster", "imf_fft_c2c", "imf_fft_r2c_3d"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(st):
+    if st != 0:
+        raise IMFError(st, _L().imf_last_error().decode())
+
+
+def fft_size(n: int) -> int:
+    return int(_L().imf_fft_size(int(n)))
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """A library context on one GPU: workspace, tool-raster and spectrum caches."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 0):
+        self._ctx = C.c_void_p()
+        self.device = device
+        _check(_L().imf_create(int(device), C.c_size_t(budget_bytes), C.byref(self._ctx)))
+        self._tools = {}
+        self._pending = {}
+
+    def close(self):
+        if self._ctx:
+            _L().imf_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def tool(self, t: dict) -> int:
+        key = (t["kind"], t["cutter_r"], t["cutter_len"], t["holder_r"], t["holder_len"])
+        if key not in self._tools:
+            tid = C.c_int()
+            ct = _Tool(*key)
+            _check(_L().imf_tool_register(self._ctx, C.byref(ct), C.byref(tid)))
+            self._tools[key] = tid.value
+        return self._tools[key]
+
+    # ------------------------------------------------------------------ request
+    def _request(self, design, fixture, domain, tools, dirs, dir_kind, sharp, lam, tau,
+                 mask_theta_abs, method, batch, flags):
+        import torch
+        if not design.is_cuda:
+            raise ValueError("design must be a device tensor")
+        ndim = design.dim()
+        if ndim == 2:
+            nz, (ny, nx) = 1, design.shape
+        else:
+            nz, ny, nx = design.shape
+        density = design.dtype == torch.float32
+        if not density and design.dtype != torch.uint8:
+            raise ValueError("design must be uint8 {0,1} or float32 density")
+        for t in (fixture, domain):
+            if t is not None and (t.dtype != torch.uint8 or t.numel() != design.numel()
+                                  or not t.is_cuda or not t.is_contiguous()):
+                raise ValueError("fixture/domain must be contiguous uint8 device tensors "
+                                 "of the design's shape")
+        if not design.is_contiguous():
+            raise ValueError("design must be contiguous")
+        if isinstance(tools, dict):
+            tools, dirs = [tools], [dirs]
+        ids = np.array([self.tool(t) for t in tools], dtype=np.int32)
+        dirs = [np.asarray(d) for d in dirs]
+        nd = np.array([len(d) for d in dirs], dtype=np.int32)
+        dt = np.int32 if dir_kind == DIR_LATTICE else np.float64
+        dd = np.ascontiguousarray(np.concatenate(dirs, axis=0), dtype=dt)
+        if dd.shape[1] != ndim:
+            raise ValueError("directions must have %d components" % ndim)
+        r = _Request()
+        r.ndim, r.nx, r.ny, r.nz = ndim, nx, ny, nz
+        r.design_is_density = int(density)
+        r.design, r.fixture, r.domain = _ptr(design), _ptr(fixture), _ptr(domain)
+        r.n_tools = len(ids)
+        r.tool_ids = ids.ctypes.data_as(C.c_void_p)
+        r.n_dirs = nd.ctypes.data_as(C.c_void_p)
+        r.dir_kind = dir_kind
+        r.dirs = dd.ctypes.data_as(C.c_void_p)
+        r.sharp, r.lam, r.tau, r.mask_theta_abs = sharp, lam, tau, mask_theta_abs
+        r.method, r.batch, r.flags = method, batch, flags
+        keep = (ids, nd, dd, design, fixture, domain)
+        return r, keep, (nz, ny, nx), int(nd.sum())
+
+    def _outputs(self, shape, n_orient, masks, debug_orient, device, debug_numel=0):
+        import torch
+        nz, ny, nx = shape
+        o = {"imf": torch.empty(shape, dtype=torch.float32, device=device),
+             "imf_norm": torch.empty(shape, dtype=torch.float32, device=device),
+             "secluded": torch.empty(shape, dtype=torch.uint8, device=device)}
+        if masks:
+            o["masks"] = torch.empty((n_orient, nz, ny, (nx + 63) // 64), dtype=torch.int64,
+                                     device=device)
+        co = _Outputs()
+        co.imf, co.imf_norm, co.secluded = _ptr(o["imf"]), _ptr(o["imf_norm"]), \
+            _ptr(o["secluded"])
+        co.acc_masks = _ptr(o.get("masks"))
+        co.debug_orient = debug_orient
+        if debug_orient >= 0:
+            o["debug"] = torch.empty(debug_numel, dtype=torch.float32, device=device)
+            co.debug_overlap = _ptr(o["debug"])
+        return o, co
+
+    def footprint(self, design, fixture=None, domain=None, *, tools, dirs, dir_kind=DIR_F64,
+                  sharp=SHARP_ALL, lam=0.0, tau=0.5, mask_theta_abs=-1.0, method=METHOD_AUTO,
+                  batch=0, flags=0) -> int:
+        r, keep, _, _ = self._request(design, fixture, domain, tools, dirs, dir_kind, sharp, lam,
+                                      tau, mask_theta_abs, method, batch, flags)
+        b = C.c_size_t()
+        _check(_L().imf_query_footprint(self._ctx, C.byref(r), C.byref(b)))
+        return b.value
+
+    def compute(self, design, fixture=None, domain=None, *, tools, dirs, dir_kind=DIR_F64,
+                sharp=SHARP_ALL, lam=0.0, tau=0.5, mask_theta_abs=-1.0, method=METHOD_AUTO,
+                batch=0, flags=0, masks=True, debug_orient=-1, debug_numel=0, stream=None):
+        """Run one request; returns a dict of device tensors and a Stats."""
+        r, keep, shape, n_orient = self._request(design, fixture, domain, tools, dirs,
+                                                 dir_kind, sharp, lam, tau, mask_theta_abs,
+                                                 method, batch, flags)
+        o, co = self._outputs(shape, n_orient, masks, debug_orient, design.device, debug_numel)
+        st = _Stats()
+        _check(_L().imf_compute(self._ctx, C.byref(r), C.byref(co), C.byref(st),
+                                _stream_handle(stream)))
+        if debug_orient >= 0:
+            o["debug_box"] = tuple(co.debug_box)
+        if design.dim() == 2:
+            for k in ("imf", "imf_norm", "secluded"):
+                o[k] = o[k].reshape(shape[1:])
+        return o, Stats._from(st)
+
+    def submit(self, design, fixture=None, domain=None, *, tools, dirs, dir_kind=DIR_F64,
+               sharp=SHARP_ALL, lam=0.0, tau=0.5, mask_theta_abs=-1.0, method=METHOD_AUTO,
+               batch=0, flags=0, masks=True):
+        """Enqueue a request in the serving loop; returns a ticket."""
+        r, keep, shape, n_orient = self._request(design, fixture, domain, tools, dirs,
+                                                 dir_kind, sharp, lam, tau, mask_theta_abs,
+                                                 method, batch, flags)
+        o, co = self._outputs(shape, n_orient, masks, -1, design.device)
+        t = C.c_uint64()
+        _check(_L().imf_submit(self._ctx, C.byref(r), C.byref(co), C.byref(t)))
+        self._pending[t.value] = (o, keep, co, design.dim(), shape)
+        return t.value
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        st = _Stats()
+        try:
+            _check(_L().imf_wait(self._ctx, C.c_uint64(ticket), int(timeout_ms), C.byref(st)))
+        except IMFError as e:
+            if e.status != 5:
+                self._pending.pop(ticket, None)
+            raise
+        o, keep, co, ndim, shape = self._pending.pop(ticket)
+        if ndim == 2:
+            for k in ("imf", "imf_norm", "secluded"):
+                o[k] = o[k].reshape(shape[1:])
+        return o, Stats._from(st)
+
+    def cancel(self, ticket: int):
+        _check(_L().imf_cancel(self._ctx, C.c_uint64(ticket)))
+
+    def autotune(self, design, fixture=None, domain=None, *, tools, dirs, **kw) -> int:
+        masks = kw.pop("masks", True)
+        r, keep, shape, n_orient = self._request(
+            design, fixture, domain, tools, dirs, kw.get("dir_kind", DIR_F64),
+            kw.get("sharp", SHARP_ALL), kw.get("lam", 0.0), kw.get("tau", 0.5),
+            kw.get("mask_theta_abs", -1.0), kw.get("method", METHOD_AUTO), 0,
+            kw.get("flags", 0))
+        o, co = self._outputs(shape, n_orient, masks, -1, design.device)
+        b = C.c_int()
+        _check(_L().imf_autotune(self._ctx, C.byref(r), C.byref(co), C.byref(b)))
+        return b.value
+
+    # -------------------------------------------------------------- single steps
+    def raster(self, tool: dict, d, dir_kind=None, sharp=SHARP_ALL):
+        """(offsets int32 [n, 3] as x, y, z; flags uint8 [n]) of one oriented tool."""
+        d = np.asarray(d)
+        if dir_kind is None:
+            dir_kind = DIR_LATTICE if d.dtype.kind in "iu" else DIR_F64
+        ndim = d.shape[-1]
+        dd = np.ascontiguousarray(d.reshape(1, ndim),
+                                  dtype=np.int32 if dir_kind == DIR_LATTICE else np.float64)
+        ct = _Tool(tool["kind"], tool["cutter_r"], tool["cutter_len"], tool["holder_r"],
+                   tool["holder_len"])
+        n = C.c_longlong()
+        st = _L().imf_raster(self._ctx, ndim, C.byref(ct), dir_kind,
+                             dd.ctypes.data_as(C.c_void_p), sharp, None, None, 0, C.byref(n))
+        if st not in (0, 1) or n.value <= 0:
+            _check(st)
+        offs = np.zeros((n.value, 3), np.int32)
+        fl = np.zeros(n.value, np.uint8)
+        _check(_L().imf_raster(self._ctx, ndim, C.byref(ct), dir_kind,
+                               dd.ctypes.data_as(C.c_void_p), sharp,
+                               offs.ctypes.data_as(C.c_void_p), fl.ctypes.data_as(C.c_void_p),
+                               n.value, C.byref(n)))
+        return offs, fl
+
+    def fft_c2c(self, x, inverse=False, stream=None):
+        """FFT of the columns of a complex64 device tensor [n, batch]."""
+        import torch
+        if x.dtype != torch.complex64 or x.dim() != 2 or not x.is_contiguous():
+            raise ValueError("expected a contiguous complex64 [n, batch] tensor")
+        y = torch.empty_like(x)
+        _check(_L().imf_fft_c2c(self._ctx, x.shape[0], x.shape[1], _ptr(x), _ptr(y),
+                                int(inverse), _stream_handle(stream)))
+        return y
+
+    def fft_r2c_3d(self, x, P, stream=None):
+        """R2C transform of a float32 [nz, ny, nx] tensor zero-padded to P = (px, py, pz);
+        returns complex64 [py, px//2+1, pz]."""
+        import torch
+        nz, ny, nx = x.shape
+        px, py, pz = P
+        y = torch.empty((py, px // 2 + 1, pz), dtype=torch.complex64, device=x.device)
+        _check(_L().imf_fft_r2c_3d(self._ctx, nx, ny, nz, px, py, pz, _ptr(x), _ptr(y),
+                                   _stream_handle(stream)))
+        return y

@@ -1,0 +1,279 @@
+"""GPU parity: the HIP library, called through its C interface, against the
+CPU oracle on the same seeded inputs.
+
+Bar: overlap counts, masks, f, fbar and Gamma bit-exact for binary designs;
+density f within 1e-4 * max(|f_ref|, lambda * F_max_ref) per voxel, with the
+masks bit-exact when the threshold is given and outside the ambiguity band
+when it is lambda * F_max (two-phase)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2002_07627_amd as imf
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = imf.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def masks_u64(t):
+    return host(t).view(np.uint64)
+
+
+def random_boxes(shape, n, seed, lo=3, hi=12):
+    rng = np.random.default_rng(seed)
+    d = np.zeros(shape, np.uint8)
+    for _ in range(n):
+        c = [rng.integers(0, s) for s in shape]
+        e = [rng.integers(lo, hi) for _ in shape]
+        sl = tuple(slice(max(ci - ei // 2, 0), ci + ei - ei // 2) for ci, ei in zip(c, e))
+        d[sl] = 1
+    return d
+
+
+def check_binary(out, ref, n_orient=None):
+    f = host(out["imf"]).astype(np.float64)
+    assert np.array_equal(f, ref["imf"].reshape(f.shape)), \
+        "f differs at %d voxels" % int((f != ref["imf"].reshape(f.shape)).sum())
+    assert np.array_equal(host(out["imf_norm"]), ref["imf_norm"].reshape(f.shape))
+    assert np.array_equal(host(out["secluded"]), ref["secluded"].reshape(f.shape))
+    if "masks" in out:
+        m = masks_u64(out["masks"])
+        assert np.array_equal(m, ref["masks"].reshape(m.shape)), "masks differ"
+
+
+# ---------------------------------------------------------------------------
+# single steps
+# ---------------------------------------------------------------------------
+
+def test_raster_bit_exact(ctx):
+    import paper_2002_07627_amd as imf
+    cases = [(W.TOOL_C2, W.lattice26()), (W.TOOL_C3, W.fib_hemisphere(40)),
+             (W.TOOL_C5, W.fib_hemisphere(512)[::37]), (W.TOOL_C1, W.circle8()),
+             (W.tool(W.TOOL_BALL, 2.5, 9, 4, 7), W.lattice26())]
+    for tl, dirs in cases:
+        for d in dirs:
+            kind = 1 if dirs.dtype.kind in "iu" else 0
+            go, gf = ctx.raster(tl, d, kind)
+            oo, oc = oracle.raster(tl, d, kind)
+            a = {tuple(p): int(f) & 3 for p, f in zip(go.tolist(), gf)}
+            b = {tuple(p): 1 | (2 if c else 0) for p, c in zip(oo.tolist(), oc)}
+            assert a == b, (tl, d)
+    # sharp subsets: tip and boundary of the cutter raster
+    tl = W.tool(W.TOOL_BALL, 3, 12, 5, 6)
+    for d in W.fib_hemisphere(10):
+        oo, oc = oracle.raster(tl, d, 0)
+        cut = {tuple(p) for p, c in zip(oo.tolist(), oc) if c}
+        bnd = {p for p in cut if any((p[0] + e[0], p[1] + e[1], p[2] + e[2]) not in cut
+                                     for e in [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0),
+                                               (0, 0, 1), (0, 0, -1)])}
+        go, gf = ctx.raster(tl, d, 0, sharp=imf.SHARP_BOUNDARY)
+        assert {tuple(p) for p, f in zip(go.tolist(), gf) if f & 4} == bnd
+        go, gf = ctx.raster(tl, d, 0, sharp=imf.SHARP_TIP)
+        assert {tuple(p) for p, f in zip(go.tolist(), gf) if f & 4} == {(0, 0, 0)}
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 7, 8, 12, 16, 48, 60, 105, 128, 216, 256, 384, 560,
+                               576, 1024])
+def test_fft_c2c_against_float64_dft(ctx, n):
+    rng = np.random.default_rng(n)
+    x = (rng.standard_normal((n, 37)) + 1j * rng.standard_normal((n, 37))).astype(np.complex64)
+    ref = np.fft.fft(x.astype(np.complex128), axis=0)
+    y = host(ctx.fft_c2c(dev(x)))
+    err = np.abs(y - ref).max() / np.abs(ref).max()
+    assert err < 3e-7 * max(np.log2(n), 1) * 4, err
+    yi = host(ctx.fft_c2c(dev(x), inverse=True))
+    refi = np.fft.ifft(x.astype(np.complex128), axis=0) * n
+    assert np.abs(yi - refi).max() / np.abs(refi).max() < 3e-7 * max(np.log2(n), 1) * 4
+
+
+def test_fft_r2c_3d_against_numpy(ctx):
+    rng = np.random.default_rng(9)
+    x = rng.random((20, 22, 24)).astype(np.float32)
+    P = (48, 40, 30)
+    y = host(ctx.fft_r2c_3d(dev(x), P))
+    xp = np.zeros((P[2], P[1], P[0]))
+    xp[:20, :22, :24] = x
+    ref = np.fft.rfftn(xp)                      # [pz][py][px/2+1]
+    ref = np.transpose(ref, (1, 2, 0))          # [py][px/2+1][pz]
+    assert np.abs(y - ref).max() / np.abs(ref).max() < 1e-6
+
+
+# ---------------------------------------------------------------------------
+# whole requests
+# ---------------------------------------------------------------------------
+
+def test_c1_direct_2d_bit_exact(ctx):
+    import paper_2002_07627_amd as imf
+    w = W.c1()
+    out, st = ctx.compute(dev(w.design), dev(w.fixture), tools=w.tool, dirs=w.dirs,
+                          dir_kind=imf.DIR_LATTICE, method=imf.METHOD_DIRECT)
+    ref = oracle.imf(oracle.Request(w.design, w.fixture, tools=w.tool, dirs=w.dirs, dir_kind=1))
+    check_binary(out, ref)
+    assert st.method == imf.METHOD_DIRECT and st.F_max == ref["F_max"]
+
+
+@pytest.mark.parametrize("method", ["fft", "direct"])
+def test_small_3d_binary_bit_exact(ctx, method):
+    import paper_2002_07627_amd as imf
+    d = random_boxes((30, 34, 40), 14, 5)
+    fx = W.fixture_plate(d.shape, 3)
+    tl = W.tool(W.TOOL_FLAT, 1.5, 6, 3, 5)
+    dirs = W.lattice26()
+    m = imf.METHOD_FFT if method == "fft" else imf.METHOD_DIRECT
+    req = oracle.Request(d, fx, tools=tl, dirs=dirs, dir_kind=1)
+    ref = oracle.imf(req, debug_orient=7)
+    info = oracle.orient_info(req, 7)
+    box = [n + info["kmax"][a] - info["kmin"][a] for a, n in enumerate((40, 34, 30))]
+    out, st = ctx.compute(dev(d), dev(fx), tools=tl, dirs=dirs, dir_kind=imf.DIR_LATTICE,
+                          method=m, debug_orient=7, debug_numel=int(np.prod(box)))
+    check_binary(out, ref)
+    g = host(out["debug"]).reshape(box[2], box[1], box[0])
+    assert np.array_equal(g.astype(np.int64), ref["g_debug"])
+    assert tuple(out["debug_box"][:3]) == ref["debug_lo"]
+    if method == "fft":
+        assert st.max_frac_err < 0.05
+
+
+def test_plain_batched_and_cached_are_identical(ctx):
+    import paper_2002_07627_amd as imf
+    d = random_boxes((32, 32, 32), 12, 6)
+    tl = W.tool(W.TOOL_BALL, 2, 7, 3.5, 5)
+    dirs = W.fib_hemisphere(20)
+    kw = dict(tools=tl, dirs=dirs, dir_kind=imf.DIR_F64, method=imf.METHOD_FFT)
+    a, sa = ctx.compute(dev(d), **kw, flags=imf.FLAG_PLAIN)
+    b, sb = ctx.compute(dev(d), **kw, batch=8)
+    c, sc = ctx.compute(dev(d), **kw, batch=5)
+    assert sb.cache_misses == 20 and sc.cache_hits == 20
+    for k in ("imf", "imf_norm", "secluded", "masks"):
+        assert torch.equal(a[k], b[k]) and torch.equal(a[k], c[k]), k
+    ref = oracle.imf(oracle.Request(d, None, tools=tl, dirs=dirs, dir_kind=0))
+    check_binary(b, ref)
+
+
+def test_sweep_route_equals_threshold_route(ctx):
+    import paper_2002_07627_amd as imf
+    d = random_boxes((28, 30, 33), 10, 7)
+    fx = W.fixture_plate(d.shape, 2)
+    tl = W.tool(W.TOOL_FLAT, 1.5, 6, 3, 5)
+    dirs = W.lattice26()
+    kw = dict(tools=tl, dirs=dirs, dir_kind=imf.DIR_LATTICE, method=imf.METHOD_FFT)
+    a, _ = ctx.compute(dev(d), dev(fx), **kw)
+    b, _ = ctx.compute(dev(d), dev(fx), **kw, flags=imf.FLAG_MASK_SWEEP)
+    assert torch.equal(a["masks"], b["masks"])
+    ref = oracle.imf(oracle.Request(d, fx, tools=tl, dirs=dirs, dir_kind=1))
+    assert np.array_equal(masks_u64(b["masks"]), ref["masks_dil"])
+
+
+@pytest.mark.parametrize("sharp", [1, 2])
+def test_sharp_point_subsets(ctx, sharp):
+    import paper_2002_07627_amd as imf
+    d = random_boxes((26, 28, 30), 10, 8)
+    tl = W.tool(W.TOOL_FLAT, 1.5, 6, 3, 5)
+    dirs = W.lattice26()[::2]
+    out, _ = ctx.compute(dev(d), tools=tl, dirs=dirs, dir_kind=imf.DIR_LATTICE, sharp=sharp,
+                         method=imf.METHOD_FFT)
+    ref = oracle.imf(oracle.Request(d, None, tools=tl, dirs=dirs, dir_kind=1, sharp=sharp))
+    check_binary(out, ref)
+
+
+def test_two_tools_take_the_minimum(ctx):
+    import paper_2002_07627_amd as imf
+    d = random_boxes((26, 26, 26), 9, 9)
+    t1 = W.tool(W.TOOL_FLAT, 1, 5, 3, 4)
+    t2 = W.tool(W.TOOL_BALL, 1.5, 4, 2.5, 3)
+    dirs1, dirs2 = W.lattice26()[:13], W.lattice26()[13:]
+    out, st = ctx.compute(dev(d), tools=[t1, t2], dirs=[dirs1, dirs2],
+                          dir_kind=imf.DIR_LATTICE, method=imf.METHOD_FFT)
+    ref = oracle.imf(oracle.Request(d, None, tools=[t1, t2], dirs=[dirs1, dirs2], dir_kind=1))
+    check_binary(out, ref)
+    assert st.n_orient == 26
+
+
+def test_density_within_tolerance_and_masks_exact(ctx):
+    import paper_2002_07627_amd as imf
+    d = W.design_density(36, seed=11)
+    fx = W.fixture_plate(d.shape, 3)
+    tl = W.tool(W.TOOL_BALL, 2, 8, 4, 6)
+    dirs = W.fib_hemisphere(12)
+    lam = 0.01
+    req = oracle.Request(d, fx, tools=tl, dirs=dirs, dir_kind=0, lam=lam)
+    ref = oracle.imf(req)
+    fref = ref["imf"]
+    theta = 0.5 * float(np.median(fref))
+    out, st = ctx.compute(dev(d), dev(fx), tools=tl, dirs=dirs, dir_kind=imf.DIR_F64, lam=lam,
+                          mask_theta_abs=theta, method=imf.METHOD_FFT)
+    f = host(out["imf"]).astype(np.float64)
+    tol = 1e-4 * np.maximum(np.abs(fref), lam * ref["F_max"])
+    assert (np.abs(f - fref) <= tol).all(), np.abs(f - fref).max()
+    assert abs(st.F_max - ref["F_max"]) <= 1e-4 * ref["F_max"]
+    # masks with an absolute threshold: bit-exact through the guard band
+    ref_t = oracle.imf(oracle.Request(d, fx, tools=tl, dirs=dirs, dir_kind=0, lam=lam,
+                                      mask_theta_abs=theta))
+    assert np.array_equal(masks_u64(out["masks"]), ref_t["masks"])
+    # B and Gamma: equal wherever f is outside the ambiguity band of the threshold
+    fbar_ref = ref["imf_norm"]
+    band = np.abs(fref - lam * ref["F_max"]) <= 2 * tol + 1e-9
+    sec = host(out["secluded"]).astype(bool)
+    assert np.array_equal(sec[~band], ref["secluded"].astype(bool)[~band])
+    nb = host(out["imf_norm"])
+    assert np.all(np.abs(nb - fbar_ref)[~band] <= 3e-4)
+
+
+def test_density_two_phase_masks(ctx):
+    import paper_2002_07627_amd as imf
+    d = W.design_density(32, seed=12)
+    fx = W.fixture_plate(d.shape, 3)
+    tl = W.tool(W.TOOL_BALL, 2, 8, 4, 6)
+    dirs = W.fib_hemisphere(10)
+    lam = 0.05
+    out, st = ctx.compute(dev(d), dev(fx), tools=tl, dirs=dirs, lam=lam, method=imf.METHOD_FFT)
+    ref = oracle.imf(oracle.Request(d, fx, tools=tl, dirs=dirs, dir_kind=0, lam=lam))
+    m = oracle.unpack_masks(masks_u64(out["masks"]), 32)
+    mr = oracle.unpack_masks(ref["masks"], 32)
+    # union of the masks is the complement of B within Omega_0 (same threshold)
+    acc = m.any(axis=0)
+    B = host(out["imf_norm"]) > 0
+    om = W.fixture_plate(d.shape, 3) == 0
+    assert not (acc & B).any() and ((acc | B) == om).all()
+    assert (m != mr).mean() < 1e-3
+
+
+def test_rejects_invalid_requests(ctx):
+    import paper_2002_07627_amd as imf
+    d = dev(np.zeros((8, 8, 8), np.uint8))
+    with pytest.raises(imf.IMFError):
+        ctx.compute(d, tools=W.TOOL_C2, dirs=np.array([[0, 0, 1.5]]))
+    with pytest.raises(imf.IMFError):
+        ctx.compute(d, tools=W.TOOL_C1, dirs=np.array([[0, 0, 1]], np.int32),
+                    dir_kind=imf.DIR_LATTICE)
+    with pytest.raises(imf.IMFError):
+        ctx.compute(d, tools=W.tool(W.TOOL_FLAT, 3.3, 4, 1, 1),
+                    dirs=np.array([[0, 0, 1]], np.int32), dir_kind=imf.DIR_LATTICE)
+
+
+def test_empty_design_all_accessible(ctx):
+    import paper_2002_07627_amd as imf
+    d = dev(np.zeros((20, 21, 22), np.uint8))
+    out, st = ctx.compute(d, tools=W.tool(W.TOOL_FLAT, 1.5, 5, 3, 4), dirs=W.lattice26(),
+                          dir_kind=imf.DIR_LATTICE, method=imf.METHOD_FFT)
+    assert st.F_max == 0 and (host(out["imf"]) == 0).all()
+    m = oracle.unpack_masks(masks_u64(out["masks"]), 22)
+    assert m.all()
