@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""Throughput of the IMF hot path on one MI355X.
+
+One step is one whole request of Algorithm 1 (Sec. 2.1.5) on the 256^3
+density workload: rasters (cached), forward transform of rho_O, tool spectra
+(cached after the warm-up), 130 fused product + inverse transforms, rounding /
+guard band, sharp-point minimum with the running minimum over orientations,
+F_max, fbar, B, Gamma and the 130 accessible masks (threshold lambda F_max).
+Inputs are resident in HBM before the timed region.
+
+Prints one JSON line: value = voxel-orientations per second (256^3 * 130 per
+step / seconds per step), the roofline of the dominant kernel (algorithmic
+bytes / its event-timed duration), the plain per-orientation path on the same
+GPU, and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, target_s=15.0):
+    """The CPU oracle as it stands on a crop of the same workload: the full
+    pipeline (exact overlaps over the query box, sharp-point minimum, masks off)
+    for one orientation of the 130, on an n^3 corner crop of the 256^3 design
+    and fixture; n is chosen from a short calibration run to take ~target_s."""
+    import numpy as np
+
+    import oracle
+
+    def run(n, k):
+        d = np.ascontiguousarray(w.design[:n, :n, :n])
+        fx = np.ascontiguousarray(w.fixture[:n, :n, :n])
+        req = oracle.Request(d, fx, tools=w.tool, dirs=w.dirs[k:k + 1], dir_kind=0,
+                             lam=w.lam)
+        t = time.perf_counter()
+        oracle.imf(req, masks=False)
+        return time.perf_counter() - t
+
+    k = 64
+    n0 = 40
+    t0 = run(n0, k)
+    # cost ~ (n + e)^3 |T| with e ~ 60 for this tool: solve for the crop size
+    n = n0
+    for cand in range(n0, 257, 8):
+        pred = t0 * ((cand + 60.0) / (n0 + 60.0)) ** 3
+        if pred > target_s:
+            break
+        n = cand
+    t = run(n, k)
+    cores = len(os.sched_getaffinity(0))
+    omp = os.environ.get("OMP_NUM_THREADS")
+    if omp:
+        cores = min(cores, int(omp))
+    return {"value": n ** 3 / t, "unit": "voxel-orientations/s", "cores": cores,
+            "kind": "oracle",
+            "sample": "%d^3 corner crop of the 256^3 design + fixture, orientation %d of 130, "
+                      "full oracle pipeline (int64 overlaps over the query box, sharp-point "
+                      "min), %.1f s" % (n, k, t)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--batch", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the IMF path here runs on a single MI355X "
+              "(--gpus %d is not supported; orientation sharding across GPUs is a design "
+              "note, not built)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2002_07627_amd as imf
+    import workloads as W
+
+    log("generating the 256^3 density workload")
+    w = W.c3()
+    N = int(np.prod(w.design.shape))
+    nR = len(w.dirs)
+    dev = torch.device("cuda:0")
+    design = torch.from_numpy(w.design).to(dev)
+    fixture = torch.from_numpy(w.fixture).to(dev)
+    ctx = imf.Context(0)
+    kw = dict(tools=w.tool, dirs=w.dirs, dir_kind=imf.DIR_F64, lam=w.lam, tau=w.tau,
+              method=imf.METHOD_FFT, batch=args.batch)
+    for i in range(args.warmup):
+        _, st = ctx.compute(design, fixture, **kw)
+        log("warmup %d: %.1f ms (cache hits %d, misses %d)" % (i, st.t_ms[7], st.cache_hits,
+                                                                 st.cache_misses))
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        _, st = ctx.compute(design, fixture, **kw, flags=imf.FLAG_PROFILE)
+        stats.append(st)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms = 1000 * el / args.steps
+    value = N * nR / (el / args.steps)
+    log("timed: %.2f ms/step, %.3e voxel-orientations/s" % (ms, value))
+
+    # per kernel class over the timed steps
+    kms, kn, kb = {}, {}, {}
+    for st in stats:
+        for k, v in st.kernel_ms.items():
+            kms[k] = kms.get(k, 0) + v
+            kn[k] = kn.get(k, 0) + st.kernel_launches[k]
+            kb[k] = kb.get(k, 0) + st.kernel_bytes[k]
+    dom = max(kms, key=kms.get)
+    avg_ms = kms[dom] / kn[dom]
+    bytes_per_launch = kb[dom] / kn[dom]
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    kernels = {k: {"ms_per_step": kms[k] / args.steps, "launches_per_step": kn[k] / args.steps,
+                   "GBps": (kb[k] / (kms[k] * 1e-3) / 1e9) if kms[k] > 0 else None}
+               for k in sorted(kms, key=kms.get, reverse=True)}
+    for k, v in kernels.items():
+        log("  %-14s %8.2f ms/step  %5.1f launches  %s GB/s" %
+            (k, v["ms_per_step"], v["launches_per_step"],
+             "%.0f" % v["GBps"] if v["GBps"] else "-"))
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "traffic_%s_c3.json" % dom)
+    if os.path.exists(tfile):
+        traffic = json.load(open(tfile)).get("bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": dom, "avg_launch_ms": round(avg_ms, 4),
+                "algorithmic_bytes_per_launch": bytes_per_launch}
+
+    plain = None
+    if not args.no_plain:
+        t1 = time.perf_counter()
+        _, sp = ctx.compute(design, fixture, **dict(kw, batch=0), flags=imf.FLAG_PLAIN)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t1
+        plain = {"value": N * nR / tp, "ms_per_step": 1000 * tp,
+                 "speedup": (N * nR / (el / args.steps)) / (N * nR / tp)}
+        log("plain path: %.1f ms" % (1000 * tp))
+    ctx.close()
+    del design, fixture
+    torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        cpu = cpu_baseline(w)
+        log("cpu oracle: %.3e voxel-orientations/s (%s)" % (cpu["value"], cpu["sample"]))
+
+    last = stats[-1]
+    line = {
+        "metric": "IMF voxel-orientations/s at 256^3x130 orientations",
+        "value": value, "unit": "voxel-orientations/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "256^3 density (sigmoid of sigma-4 smoothed noise, mean 0.35, "
+                               "2^-24 grid), fixture plate z<6, ball cutter r4 L60 + holder "
+                               "r14 L60, 130 Fibonacci-hemisphere orientations, lambda 0.01, "
+                               "masks at lambda*F_max",
+                   "grid": list(w.design.shape), "orientations": nR, "P": list(last.P),
+                   "batch": last.batch, "spectra": "cached (warm)"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "plain": plain,
+        "kernels": kernels,
+        "guard": {"F_max": last.F_max, "max_frac_err": last.max_frac_err,
+                  "flags": last.guard_flags},
+        "model_bytes_per_step": last.model_bytes,
+        "model_GBps": last.model_bytes / (ms * 1e-3) / 1e9,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -83,6 +83,7 @@ enum { IMF_METHOD_AUTO = 0, IMF_METHOD_FFT = 1, IMF_METHOD_DIRECT = 2 };
 #define IMF_FLAG_PLAIN 1u        /* one orientation per batch, no spectrum cache */
 #define IMF_FLAG_MASK_SWEEP 2u   /* masks by sweeping D^c with the cutter (bit rows) */
 #define IMF_FLAG_NO_CACHE 4u     /* do not keep tool spectra */
+#define IMF_FLAG_PROFILE 8u      /* time every kernel class with events (k_ms, k_n) */
 
 typedef struct {
   int ndim, nx, ny, nz;
@@ -128,6 +129,13 @@ typedef struct {
   int P[3];              /* transform sizes */
   int n_orient, method, batch;
   int cache_hits, cache_misses;
+  /* with IMF_FLAG_PROFILE: device time and launches per kernel class: 0 raster,
+   * 1 setup, 2 forward design transform, 3-5 tool spectrum x/y/z, 6 product +
+   * inverse z, 7 inverse y, 8 inverse x + rounding, 9 recheck, 10 window-min
+   * levels, 11 sharp-point minimum, 12 sweep, 13 finalize, 14 copies */
+  double k_ms[16];
+  int k_n[16];
+  double k_bytes[16];    /* algorithmic bytes of each class (compulsory reads + writes) */
 } imf_stats;
 
 /* Bytes of device workspace the request needs (admission control). */

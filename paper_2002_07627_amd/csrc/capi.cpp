@@ -673,6 +673,7 @@ static imf_status make_plan(imf_ctx* c, const imf_request* r, const imf_outputs*
     add(sizeof(float2) * p.B * p.spec_elems);                            // batch spectra
     add(sizeof(float2) * p.B * (long long)p.max_m[2] * p.P[1] * h);      // inverse w1
     add(sizeof(float2) * p.B * (long long)p.max_m[2] * p.max_m[1] * h);  // inverse w2
+    add(sizeof(imf_orient_desc) * (size_t)nb * p.B);                      // per-batch miss lists
   }
   p.ws_bytes = b + 4096;
   return IMF_OK;
@@ -715,30 +716,44 @@ static double model_bytes(const Plan& p) {
 // ---------------------------------------------------------------------------
 // compute
 // ---------------------------------------------------------------------------
+// Events on the request's stream between kernel classes.  Without profiling
+// only the class boundaries of the coarse phases are marked.
 struct Timer {
   std::vector<hipEvent_t> ev;
-  std::vector<int> phase;
+  std::vector<int> cls;
   hipStream_t s;
-  void mark(int ph) {
+  bool fine = false;
+  void mark(int k) {
+    static const bool coarse_mark[16] = {1, 1, 1, 0, 0, 1, 0, 0, 1, 1, 0, 1, 1, 1, 1, 1};
+    if (!fine && !coarse_mark[k & 15]) return;
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return;
-    hipEventRecord(e, s);
+    if (hipEventRecord(e, s) != hipSuccess) {
+      hipEventDestroy(e);
+      return;
+    }
     ev.push_back(e);
-    phase.push_back(ph);
+    cls.push_back(k);
   }
-  void collect(double* t) {
+  void collect(imf_stats* st) {
+    static const int coarse[16] = {0, 6, 1, 2, 2, 2, 3, 3, 3, 4, 5, 5, 5, 6, 6, 6};
     for (size_t i = 1; i < ev.size(); i++) {
       float ms = 0;
       hipEventElapsedTime(&ms, ev[i - 1], ev[i]);
-      if (phase[i] >= 0 && phase[i] < 7) t[phase[i]] += ms;
+      const int k = cls[i];
+      if (k < 0 || k > 15) continue;
+      st->t_ms[coarse[k]] += ms;
+      if (fine) {
+        st->k_ms[k] += ms;
+        st->k_n[k] += 1;
+      }
     }
-    if (ev.size() > 1) {
-      float ms = 0;
-      hipEventElapsedTime(&ms, ev.front(), ev.back());
-      t[7] = ms;
-    }
+    release();
+  }
+  void release() {
     for (auto e : ev) hipEventDestroy(e);
     ev.clear();
+    cls.clear();
   }
 };
 
@@ -780,6 +795,7 @@ struct Pending {
   unsigned int* host = nullptr;  // [0..1] fmax, max_err; [2..] per-batch flag counts
   std::chrono::steady_clock::time_point t_start;
   imf_outputs* out = nullptr;
+  double kbytes[16] = {0};  // algorithmic bytes per kernel class
 };
 
 // Enqueue the whole request on stream s (no host synchronization after the
@@ -796,7 +812,8 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
   STCHK(enumerate(c, r, os));
   Timer& tm = pd.tm;
   tm.s = s;
-  tm.mark(-1);
+  tm.fine = (r->flags & IMF_FLAG_PROFILE) != 0;
+  tm.mark(15);
   STCHK(ensure_rasters(c, r, os, s));
   tm.mark(0);
   Plan& p = pd.p;
@@ -905,25 +922,58 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
   HIPCHK(imf_launch_fill_f(f, N, INFINITY, s));
   HIPCHK(imf_launch_prefix_x(r->design, r->design_is_density, r->fixture, r->nx, r->ny, r->nz, ps,
                              s));
-  tm.mark(6);
+  tm.mark(1);
+  const double esz = r->design_is_density ? 4.0 : 1.0;
+  const double S = 8.0 * (double)p.spec_elems;
+  pd.kbytes[1] = (double)N * (esz + 2 + 4) + 8.0 * (r->nx + 1) * (double)r->ny * r->nz;
   if (p.method == IMF_METHOD_FFT) {
+    pd.kbytes[2] = (double)N * (esz + (r->fixture ? 1 : 0)) + S;
     imf_fwd_design_args fa{r->design, r->design_is_density, r->fixture, r->nx, r->ny, r->nz,
                            p.P[0], p.P[1], p.P[2], fw1, fw2, rho_hat};
     HIPCHK(imf_launch_fwd_design(fa, p.fl[0], p.fl[1], p.fl[2], twx, twy, twz, s));
-    tm.mark(1);
+    tm.mark(2);
   }
   for (int b = 0; b < nb; b++) {
     const int q0 = b * p.B;
     const int nq = std::min(p.B, p.nO - q0);
     const imf_orient_desc* bd = d_desc + q0;
+    // algorithmic bytes of this batch, per kernel class
+    for (int q = q0; q < q0 + nq; q++) {
+      const imf_orient_desc& d = p.desc[q];
+      const double M3 = (double)d.box_dim[0] * d.box_dim[1] * d.box_dim[2];
+      if (p.method == IMF_METHOD_FFT) {
+        if (need_fft[q]) {
+          const double tx = 8.0 * d.tdim[2] * d.tdim[1] * h, ty = 8.0 * d.tdim[2] * p.P[1] * h;
+          pd.kbytes[3] += tx + 16.0 * d.n_truns;
+          pd.kbytes[4] += tx + ty;
+          pd.kbytes[5] += ty + S;
+        }
+        const double w1b = 8.0 * d.box_dim[2] * p.P[1] * h;
+        const double w2b = 8.0 * d.box_dim[2] * d.box_dim[1] * h;
+        pd.kbytes[6] += S + w1b;
+        pd.kbytes[7] += w1b + w2b;
+        pd.kbytes[8] += w2b + 4.0 * M3;
+      } else {
+        pd.kbytes[8] += 4.0 * M3 + 16.0 * d.n_truns;
+      }
+      pd.kbytes[10] += 2.0 * 4.0 * M3 * p.nlvl;
+      pd.kbytes[11] += 4.0 * M3 + 16.0 * d.n_sruns +
+                       (p.masks && p.theta_known && !p.sweep ? N / 8.0 : 0.0) +
+                       (p.two_phase ? 4.0 * N : 0.0);
+      if (p.sweep) pd.kbytes[12] += 4.0 * M3 + N / 8.0 + N;
+    }
+    if (p.method == IMF_METHOD_FFT) pd.kbytes[6] += S;  // rho_hat, once per batch
+    pd.kbytes[11] += 9.0 * N;                          // f read + write, Omega_0
     if (p.method == IMF_METHOD_FFT) {
       if (nmiss[b]) {
         imf_tool_fft_args ta{d_miss + (size_t)b * p.B, nmiss[b], p.P[0], p.P[1], p.P[2],
                              p.max_t[1], p.max_t[2], tw1, tw2, tw1_stride, tw2_stride};
-        HIPCHK(imf_launch_tool_fft(ta, p.fl[1], p.fl[2], twx, twy, twz, s));
+        for (int stage = 0; stage < 3; stage++) {
+          HIPCHK(imf_launch_tool_fft(ta, p.fl[1], p.fl[2], twx, twy, twz, s, stage));
+          tm.mark(3 + stage);
+        }
         for (int q = q0; q < q0 + nq; q++)
           if (fresh[q]) HIPCHK(hipEventRecord(fresh[q]->ready, s));
-        tm.mark(2);
       }
       imf_inv_args ia{};
       ia.desc = bd;
@@ -950,23 +1000,26 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
       ia.flag_cnt = flag_cnt + b;
       ia.flag_cap = flag_cap;
       ia.flags = flags;
-      HIPCHK(imf_launch_inverse(ia, p.fl[0], p.fl[1], p.fl[2], twx, twy, twz, s));
-      tm.mark(3);
+      for (int stage = 0; stage < 3; stage++) {
+        HIPCHK(imf_launch_inverse(ia, p.fl[0], p.fl[1], p.fl[2], twx, twy, twz, s, stage));
+        tm.mark(6 + stage);
+      }
       if (ia.binary || ia.theta_known) {
         HIPCHK(imf_launch_recheck(bd, ps, r->nx, r->ny, r->nz, r->design_is_density, flag_cnt + b,
                                   flags, flag_cap, ia.theta_known, p.theta, g, p.max_vol, s));
-        tm.mark(4);
+        tm.mark(9);
       }
     } else {
       HIPCHK(imf_launch_direct(bd, nq, ps, r->nx, r->ny, r->nz, r->design_is_density, g,
                                p.max_vol, (int)p.max_vol, s));
-      tm.mark(3);
+      tm.mark(8);
     }
     if (out->debug_overlap && out->debug_orient >= q0 && out->debug_orient < q0 + nq) {
       const imf_orient_desc& d = p.desc[out->debug_orient];
       const long long vol = (long long)d.box_dim[0] * d.box_dim[1] * d.box_dim[2];
       HIPCHK(hipMemcpyAsync(out->debug_overlap, g + (long long)(out->debug_orient - q0) * p.max_vol,
                             sizeof(float) * vol, hipMemcpyDeviceToDevice, s));
+      tm.mark(14);
     }
     imf_min_args ma{};
     ma.desc = bd;
@@ -987,13 +1040,16 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
     ma.mask_q0 = q0;
     ma.gamma_stack = gstack;
     ma.gamma_q0 = q0;
-    HIPCHK(imf_launch_minfilter(ma, s));
+    HIPCHK(imf_launch_minfilter(ma, s, 0));
+    tm.mark(10);
+    HIPCHK(imf_launch_minfilter(ma, s, 1));
+    tm.mark(11);
     if (p.sweep) {
       imf_sweep_args sa{d_sweep + q0, nq, g, p.max_vol, p.theta, r->nx, r->ny, r->nz, om, dc,
                         dc_stride, out->acc_masks, q0};
       HIPCHK(imf_launch_sweep(sa, s));
+      tm.mark(12);
     }
-    tm.mark(5);
   }
   HIPCHK(imf_launch_fmax(f, om, N, fmax_bits, s));
   HIPCHK(imf_launch_finalize(f, om, r->design, r->design_is_density, N, fmax_bits, r->lambda,
@@ -1001,7 +1057,10 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
   if (p.two_phase)
     HIPCHK(imf_launch_masks_from_gamma(gstack, p.nO, om, r->nx, r->ny, r->nz, fmax_bits,
                                        r->lambda, out->acc_masks, s));
-  tm.mark(6);
+  tm.mark(13);
+  pd.kbytes[13] = (double)N * (4 + 1 + esz + (out->imf ? 4 : 0) + (out->imf_norm ? 4 : 0) +
+                               (out->secluded ? 1 : 0)) +
+                  (p.two_phase ? (4.0 * N + N / 8.0) * p.nO : 0.0);
   pd.host = ar.host;
   HIPCHK(hipMemcpyAsync(pd.host, misc, 2 * sizeof(unsigned int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(pd.host + 2, flag_cnt, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
@@ -1019,7 +1078,7 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
 static imf_status compute_finish(Pending& pd, imf_stats* st) {
   hipError_t e = hipStreamSynchronize(pd.s);
   if (e != hipSuccess) {
-    for (auto ev : pd.tm.ev) hipEventDestroy(ev);
+    pd.tm.release();
     return fail(IMF_EDEVICE, "request failed on the device: %s", hipGetErrorString(e));
   }
   const Plan& p = pd.p;
@@ -1027,7 +1086,7 @@ static imf_status compute_finish(Pending& pd, imf_stats* st) {
   for (int b = 0; b < pd.nb; b++) {
     const int n = (int)pd.host[2 + b];
     if (n > pd.flag_cap) {
-      for (auto ev : pd.tm.ev) hipEventDestroy(ev);
+      pd.tm.release();
       return fail(IMF_EACCURACY, "guard band of batch %d flagged %d overlaps (capacity %d)", b, n,
                   pd.flag_cap);
     }
@@ -1047,7 +1106,9 @@ static imf_status compute_finish(Pending& pd, imf_stats* st) {
     st->max_frac_err = me;
     st->guard_flags = total_flags;
     st->guard_band = p.band;
-    pd.tm.collect(st->t_ms);
+    pd.tm.collect(st);
+    if (pd.tm.fine)
+      for (int k = 0; k < 16; k++) st->k_bytes[k] = pd.kbytes[k];
     st->t_ms[7] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
                                                             pd.t_start).count();
     st->model_bytes = model_bytes(p);
@@ -1058,7 +1119,7 @@ static imf_status compute_finish(Pending& pd, imf_stats* st) {
     st->cache_hits = pd.hits;
     st->cache_misses = pd.misses;
   } else {
-    for (auto ev : pd.tm.ev) hipEventDestroy(ev);
+    pd.tm.release();
   }
   return IMF_OK;
 }
@@ -1069,7 +1130,7 @@ static imf_status compute_impl(imf_ctx* c, const imf_request* r, const imf_outpu
   imf_status e = compute_launch(c, r, out, s, ar, pd);
   if (e != IMF_OK) {
     hipStreamSynchronize(s);
-    for (auto ev : pd.tm.ev) hipEventDestroy(ev);
+    pd.tm.release();
     return e;
   }
   return compute_finish(pd, st);
@@ -1288,7 +1349,7 @@ static void serve_worker(imf_ctx* c) {
         st = compute_launch(c, &rq->req, &rq->out, s, ar, pd);
         if (st != IMF_OK) {
           hipStreamSynchronize(s);
-          for (auto ev : pd.tm.ev) hipEventDestroy(ev);
+          pd.tm.release();
         }
       }
       if (st == IMF_OK) st = compute_finish(pd, &rq->stats);

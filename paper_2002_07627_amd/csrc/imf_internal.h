@@ -103,9 +103,10 @@ struct imf_tool_fft_args {
   float2* work2;          // per q: [max_tz][py][px/2+1]
   long long w1_stride, w2_stride;
 };
+// stage: -1 all, 0 x (direct DFT of the runs), 1 y pass, 2 z pass
 hipError_t imf_launch_tool_fft(const imf_tool_fft_args& a, const imf_fft_len& fy,
                                const imf_fft_len& fz, const float2* twx, const float2* twy,
-                               const float2* twz, hipStream_t s);
+                               const float2* twz, hipStream_t s, int stage = -1);
 
 // inverse: g_q = C2R3D(rho_hat * conj(T_q)) / (px py pz), over the query boxes
 struct imf_inv_args {
@@ -124,9 +125,11 @@ struct imf_inv_args {
   unsigned int* max_err_bits;        // atomic max of |g - rint g| (binary)
   int* flag_cnt; int flag_cap; int2* flags;   // (q, linear box index)
 };
+// stage: -1 all, 0 product + z pass, 1 y pass, 2 x pass (complex-to-real) + epilogue
 hipError_t imf_launch_inverse(const imf_inv_args& a, const imf_fft_len& fx,
                               const imf_fft_len& fy, const imf_fft_len& fz, const float2* twx,
-                              const float2* twy, const float2* twz, hipStream_t s);
+                              const float2* twy, const float2* twz, hipStream_t s,
+                              int stage = -1);
 
 // exact overlap by prefix sums along x (direct correlation and guard-band recheck)
 hipError_t imf_launch_prefix_x(const void* design, int density, const uint8_t* fixture, int nx,
@@ -149,7 +152,8 @@ struct imf_min_args {
   int masks_on; double theta; uint64_t* masks; int mask_q0;  // masks for orientations mask_q0 + q
   float* gamma_stack; int gamma_q0;   // optional
 };
-hipError_t imf_launch_minfilter(const imf_min_args& a, hipStream_t s);
+// stage: -1 all, 0 sparse-table levels, 1 the minimum filter
+hipError_t imf_launch_minfilter(const imf_min_args& a, hipStream_t s, int stage = -1);
 
 // sweep route: A = Omega_0 and (D^c dilated by S) with D^c = {g <= theta}
 struct imf_sweep_args {

@@ -611,19 +611,20 @@ hipError_t imf_launch_fwd_design(const imf_fwd_design_args& a, const imf_fft_len
 
 hipError_t imf_launch_tool_fft(const imf_tool_fft_args& a, const imf_fft_len& fy,
                                const imf_fft_len& fz, const float2* twx, const float2* twy,
-                               const float2* twz, hipStream_t s) {
+                               const float2* twz, hipStream_t s, int stage) {
   const int h = a.px / 2 + 1;
-  hipError_t e = hipMemsetAsync(a.work1, 0, sizeof(float2) * a.w1_stride * a.nq, s);
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
   // x: direct DFT of the runs (rows without runs stay zero)
-  {
+  if (stage < 0 || stage == 0) {
+    if ((e = hipMemsetAsync(a.work1, 0, sizeof(float2) * a.w1_stride * a.nq, s)) != hipSuccess)
+      return e;
     const long long max_runs = (long long)a.max_ty * a.max_tz * IMF_MAX_RUNS_PER_ROW;
     dim3 grid((unsigned)((max_runs * h + IMF_WG - 1) / IMF_WG), a.nq);
     hipLaunchKernelGGL(k_tool_x, grid, dim3(IMF_WG), 0, s, a.desc, twx, a.px, a.work1,
                        a.w1_stride, a.max_ty);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  DISPATCH(fy.n, {
+  if (stage < 0 || stage == 1) DISPATCH(fy.n, {
     strided_io io{a.work1, a.w1_stride, (long long)a.max_ty * h, h,
                   a.work2, a.w2_stride, (long long)a.py * h, h, h};
     const size_t sm = smem_bytes(fy.n, CT);
@@ -633,7 +634,7 @@ hipError_t imf_launch_tool_fft(const imf_tool_fft_args& a, const imf_fft_len& fy
                        twy, a.desc, 0, 0, a.py, 0);
   });
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  DISPATCH(fz.n, {
+  if (stage < 0 || stage == 2) DISPATCH(fz.n, {
     const size_t sm = smem_bytes(fz.n, CT);
     auto k = k_pass_z_fwd<CT, MAXE, 1>;
     if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
@@ -646,17 +647,17 @@ hipError_t imf_launch_tool_fft(const imf_tool_fft_args& a, const imf_fft_len& fy
 
 hipError_t imf_launch_inverse(const imf_inv_args& a, const imf_fft_len& fx,
                               const imf_fft_len& fy, const imf_fft_len& fz, const float2* twx,
-                              const float2* twy, const float2* twz, hipStream_t s) {
+                              const float2* twy, const float2* twz, hipStream_t s, int stage) {
   const int h = a.px / 2 + 1;
-  hipError_t e;
-  DISPATCH(fz.n, {
+  hipError_t e = hipSuccess;
+  if (stage < 0 || stage == 0) DISPATCH(fz.n, {
     const size_t sm = smem_bytes(fz.n, CT);
     auto k = k_inv_z_product<CT, MAXE>;
     if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3((h + CT - 1) / CT, a.py, 1), dim3(IMF_WG), sm, s, a, fz, twz);
   });
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  DISPATCH(fy.n, {
+  if (stage < 0 || stage == 1) DISPATCH(fy.n, {
     strided_io io{a.w1, a.w1_stride, (long long)a.py * h, h,
                   a.w2, a.w2_stride, (long long)a.max_my * h, h, h};
     const size_t sm = smem_bytes(fy.n, CT);
@@ -666,7 +667,7 @@ hipError_t imf_launch_inverse(const imf_inv_args& a, const imf_fft_len& fx,
                        twy, a.desc, 0, a.py, 0, 1);
   });
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  DISPATCH(fx.n, {
+  if (stage < 0 || stage == 2) DISPATCH(fx.n, {
     const size_t sm = smem_bytes(fx.n, CT);
     auto k = k_inv_x_c2r<CT, MAXE>;
     if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;

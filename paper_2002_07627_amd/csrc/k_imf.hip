@@ -244,15 +244,16 @@ __global__ void __launch_bounds__(IMF_WG) k_minfilter(imf_min_args a) {
   if (valid) a.f[vi] = fmin;
 }
 
-hipError_t imf_launch_minfilter(const imf_min_args& a, hipStream_t s) {
+hipError_t imf_launch_minfilter(const imf_min_args& a, hipStream_t s, int stage) {
   hipError_t e;
   // levels (all orientations of the batch; the grid covers the largest box)
-  for (int level = 1; level <= a.nlvl; level++) {
+  for (int level = 1; level <= a.nlvl && (stage < 0 || stage == 0); level++) {
     const long long vol = a.g_stride;
     hipLaunchKernelGGL(k_level, dim3((unsigned)((vol + IMF_WG - 1) / IMF_WG), a.nq),
                        dim3(IMF_WG), 0, s, a.desc, a.g, a.g_stride, a.lvl, a.lvl_stride, level);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
+  if (stage == 0) return hipSuccess;
   const int words = (a.nx + 63) >> 6;
   const long long nwaves = (long long)words * a.ny * a.nz;
   const int per = IMF_WG / 64;

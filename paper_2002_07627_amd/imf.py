@@ -19,7 +19,10 @@ TOOL_FLAT, TOOL_BALL, TOOL_RECT2D = 0, 1, 2
 DIR_F64, DIR_LATTICE = 0, 1
 SHARP_ALL, SHARP_BOUNDARY, SHARP_TIP = 0, 1, 2
 METHOD_AUTO, METHOD_FFT, METHOD_DIRECT = 0, 1, 2
-FLAG_PLAIN, FLAG_MASK_SWEEP, FLAG_NO_CACHE = 1, 2, 4
+FLAG_PLAIN, FLAG_MASK_SWEEP, FLAG_NO_CACHE, FLAG_PROFILE = 1, 2, 4, 8
+KERNEL_CLASSES = ("raster", "setup", "fwd_design", "tool_x", "tool_y", "tool_z",
+                  "inv_z_product", "inv_y", "inv_x_c2r", "recheck", "levels", "minfilter",
+                  "sweep", "finalize", "copies", "unused")
 
 _STATUS = {0: "IMF_OK", 1: "IMF_EINVAL", 2: "IMF_ENOMEM", 3: "IMF_EDEVICE", 4: "IMF_EBUSY",
            5: "IMF_ETIMEOUT", 6: "IMF_ECANCELLED", 7: "IMF_EACCURACY", 8: "IMF_ENOTIMPL"}
@@ -57,7 +60,9 @@ class _Stats(C.Structure):
                 ("max_frac_err", C.c_float), ("guard_band", C.c_double),
                 ("t_ms", C.c_double * 8), ("model_bytes", C.c_double), ("P", C.c_int * 3),
                 ("n_orient", C.c_int), ("method", C.c_int), ("batch", C.c_int),
-                ("cache_hits", C.c_int), ("cache_misses", C.c_int)]
+                ("cache_hits", C.c_int), ("cache_misses", C.c_int),
+                ("k_ms", C.c_double * 16), ("k_n", C.c_int * 16),
+                ("k_bytes", C.c_double * 16)]
 
 
 @dataclass
@@ -74,12 +79,18 @@ class Stats:
     batch: int
     cache_hits: int
     cache_misses: int
+    kernel_ms: dict
+    kernel_launches: dict
+    kernel_bytes: dict
 
     @classmethod
     def _from(cls, s: _Stats):
+        kms = {k: s.k_ms[i] for i, k in enumerate(KERNEL_CLASSES) if s.k_n[i]}
+        kn = {k: s.k_n[i] for i, k in enumerate(KERNEL_CLASSES) if s.k_n[i]}
+        kb = {k: s.k_bytes[i] for i, k in enumerate(KERNEL_CLASSES) if s.k_n[i]}
         return cls(s.F_max, s.guard_flags, s.max_frac_err, s.guard_band, list(s.t_ms),
                    s.model_bytes, tuple(s.P), s.n_orient, s.method, s.batch, s.cache_hits,
-                   s.cache_misses)
+                   s.cache_misses, kms, kn, kb)
 
 
 _lib = None
