@@ -77,6 +77,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--batch", type=int, default=0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also time a plain 1 GiB device copy (stream-copy bandwidth; the "
+                         "reference kernel for the FETCH_SIZE / WRITE_SIZE counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the IMF path here runs on a single MI355X "
@@ -90,6 +93,19 @@ def main():
     import paper_2002_07627_amd as imf
     import workloads as W
 
+    copy_gbs = None
+    if args.copy_probe:
+        x = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(10):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        copy_gbs = 10 * 2 * x.numel() * 4 / (time.perf_counter() - t) / 1e9
+        log("stream copy (1 GiB read + 1 GiB write): %.0f GB/s" % copy_gbs)
+        del x, y
     log("generating the 256^3 density workload")
     w = W.c3()
     N = int(np.prod(w.design.shape))
@@ -180,6 +196,7 @@ def main():
         "kernels": kernels,
         "guard": {"F_max": last.F_max, "max_frac_err": last.max_frac_err,
                   "flags": last.guard_flags},
+        "stream_copy_GBps": copy_gbs,
         "model_bytes_per_step": last.model_bytes,
         "model_GBps": last.model_bytes / (ms * 1e-3) / 1e9,
     }

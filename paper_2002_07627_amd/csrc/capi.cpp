@@ -1029,6 +1029,17 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
     ma.lvl = lvl;
     ma.lvl_stride = (long long)std::max(p.nlvl, 1) * p.max_vol;
     ma.nlvl = p.nlvl;
+    ma.max_m = 1;
+    ma.max_lines = 1;
+    for (int q = q0; q < q0 + nq; q++) {
+      const imf_orient_desc& d = p.desc[q];
+      const int ax = d.s_axis;
+      ma.max_m = std::max(ma.max_m, d.box_dim[ax]);
+      const long long lines =
+          ax == 0 ? ((long long)d.box_dim[1] * d.box_dim[2] + 3) / 4
+                  : (long long)((d.box_dim[0] + 15) / 16) * (ax == 1 ? d.box_dim[2] : d.box_dim[1]);
+      ma.max_lines = std::max(ma.max_lines, lines);
+    }
     ma.nx = r->nx;
     ma.ny = r->ny;
     ma.nz = r->nz;

@@ -146,6 +146,8 @@ struct imf_min_args {
   const imf_orient_desc* desc; int nq;
   const float* g; long long g_stride;
   float* lvl; long long lvl_stride; int nlvl;   // sparse-table levels per q
+  int max_m;                // largest box extent along any run axis (LDS of the level pass)
+  long long max_lines;      // workgroups of the level pass
   int nx, ny, nz;
   float* f;                 // running min [nz][ny][nx]
   const uint8_t* omega0;    // [nz][ny][nx]

@@ -170,96 +170,214 @@ hipError_t imf_launch_recheck(const imf_orient_desc* desc, const long long* ps, 
 // min g[p, p + 2^s) along the axis; a run of length l reads two level-s
 // windows, s = floor(log2 l).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(IMF_WG) k_level(const imf_orient_desc* __restrict__ desc,
-                                                  const float* __restrict__ g, long long g_stride,
-                                                  float* __restrict__ lvl, long long lvl_stride,
-                                                  int level) {
-  const int q = blockIdx.y;
+// All sparse-table levels of one orientation in one pass: lines along the run
+// axis are staged in LDS (ping-pong), each level is formed there and written
+// out.  A workgroup holds LT lines of length m = box extent along the axis;
+// for the x axis the lines are rows, otherwise LT consecutive x columns.
+#define LVL_LT 16
+__global__ void __launch_bounds__(IMF_WG) k_levels(const imf_orient_desc* __restrict__ desc,
+                                                   const float* __restrict__ g,
+                                                   long long g_stride, float* __restrict__ lvl,
+                                                   long long lvl_stride, int nlvl) {
+  extern __shared__ float lds[];
+  const int q = blockIdx.z;
   const imf_orient_desc& d = desc[q];
-  const long long vol = (long long)d.box_dim[0] * d.box_dim[1] * d.box_dim[2];
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= vol) return;
-  const float* src = level == 1 ? g + q * g_stride : lvl + q * lvl_stride + (level - 2) * g_stride;
-  float* dst = lvl + q * lvl_stride + (level - 1) * g_stride;
   const int ax = d.s_axis;
-  const long long st = ax == 0 ? 1 : (ax == 1 ? d.box_dim[0] : (long long)d.box_dim[0] * d.box_dim[1]);
-  const int coord = (int)((i / st) % d.box_dim[ax]);
-  const int half = 1 << (level - 1);
-  float v = src[i];
-  if (coord + half < d.box_dim[ax]) v = fminf(v, src[i + half * st]);
-  dst[i] = v;
+  const int mx = d.box_dim[0], my = d.box_dim[1], mz = d.box_dim[2];
+  const int m = d.box_dim[ax];
+  const long long sa = ax == 0 ? 1 : (ax == 1 ? (long long)mx : (long long)mx * my);
+  // lines: for ax == 0, rows (y, z); else groups of LVL_LT consecutive x at a
+  // fixed coordinate of the third axis
+  long long nlines;
+  if (ax == 0) nlines = (long long)my * mz;
+  else nlines = (long long)((mx + LVL_LT - 1) / LVL_LT) * (ax == 1 ? mz : my);
+  const long long gid = blockIdx.x;
+  const int lines_per_wg = ax == 0 ? 4 : 1;
+  if (gid * lines_per_wg >= nlines) return;
+  float* A = lds;
+  float* B = lds + LVL_LT * m;
+  const float* src = g + q * g_stride;
+  float* dstb = lvl + q * lvl_stride;
+  // element (line l, position i) -> box index
+  auto index_of = [&](int l, int i, bool& ok) -> long long {
+    ok = true;
+    if (ax == 0) {
+      const long long row = gid * 4 + l;
+      if (row >= nlines) { ok = false; return 0; }
+      return row * mx + i;
+    }
+    const long long grp = gid;
+    const int nxg = (mx + LVL_LT - 1) / LVL_LT;
+    const int x = (int)(grp % nxg) * LVL_LT + l;
+    const int o = (int)(grp / nxg);
+    if (x >= mx) { ok = false; return 0; }
+    return ax == 1 ? ((long long)o * my * mx + x + (long long)i * sa)
+                   : ((long long)o * mx + x + (long long)i * sa);
+  };
+  const int nl = ax == 0 ? 4 : LVL_LT;
+  // load: for ax != 0 consecutive threads take consecutive x (coalesced)
+  for (int t = threadIdx.x; t < nl * m; t += IMF_WG) {
+    int l, i;
+    if (ax == 0) { l = t / m; i = t - l * m; }
+    else { i = t / nl; l = t - i * nl; }
+    bool ok;
+    const long long gi = index_of(l, i, ok);
+    A[l * m + i] = ok ? src[gi] : INFINITY;
+  }
+  __syncthreads();
+  for (int s = 1; s <= nlvl; s++) {
+    const int h = 1 << (s - 1);
+    float* dst = dstb + (long long)(s - 1) * g_stride;
+    for (int t = threadIdx.x; t < nl * m; t += IMF_WG) {
+      int l, i;
+      if (ax == 0) { l = t / m; i = t - l * m; }
+      else { i = t / nl; l = t - i * nl; }
+      float v = A[l * m + i];
+      if (i + h < m) v = fminf(v, A[l * m + i + h]);
+      B[l * m + i] = v;
+      bool ok;
+      const long long gi = index_of(l, i, ok);
+      if (ok) dst[gi] = v;
+    }
+    __syncthreads();
+    float* tmp = A;
+    A = B;
+    B = tmp;
+  }
 }
 
 __device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }
 
-__global__ void __launch_bounds__(IMF_WG) k_minfilter(imf_min_args a) {
+// Sharp-point minimum of ONE orientation (Eq. imf_2): one wave per 64
+// consecutive x of a row; f is updated in place (one orientation per launch,
+// so every voxel has a single writer).  The runs are turned into box-index
+// offsets in LDS once per workgroup, and the run loop is unrolled so that 16
+// independent gathers are in flight per wave.
+#define MF_LDS_RUNS 1024
+#define MF_BY 16
+#define MF_BZ 16
+// Wave -> output mapping.  The hardware hands workgroups to the 8 XCDs round
+// robin, so workgroup b runs on XCD b % 8.  Each XCD is given a contiguous range
+// of bricks (one 64-wide x chunk by MF_BY rows by MF_BZ planes, y fastest), so
+// the waves resident on one XCD cover a compact region and share its L2.
+__device__ __forceinline__ bool mf_map(int nx, int ny, int nz, int& w, int& y, int& z) {
+  const int words = (nx + 63) >> 6;
+  const int nby = (ny + MF_BY - 1) / MF_BY, nbz = (nz + MF_BZ - 1) / MF_BZ;
+  const long long nbricks = (long long)words * nby * nbz;
+  const int wg_per_brick = MF_BY * MF_BZ / (IMF_WG / 64);
+  const long long nwg = nbricks * wg_per_brick;
+  const long long per_xcd = (nwg + 7) / 8;
+  const long long b = blockIdx.x;
+  const long long lg = (b % 8) * per_xcd + b / 8;
+  if (lg >= nwg) return false;
+  const long long brick = lg / wg_per_brick;
+  const int wib = (int)(lg % wg_per_brick) * (IMF_WG / 64) + (threadIdx.x >> 6);
+  const int yb = (int)(brick % nby);
+  const long long r = brick / nby;
+  const int zb = (int)(r % nbz);
+  w = (int)(r / nbz);
+  y = yb * MF_BY + wib % MF_BY;
+  z = zb * MF_BZ + wib / MF_BY;
+  return y < ny && z < nz;
+}
+
+__global__ void __launch_bounds__(IMF_WG) k_minfilter(imf_min_args a, int qi) {
+  __shared__ int4 rr[MF_LDS_RUNS];
+  const imf_orient_desc& d = a.desc[qi];
+  const int nr = d.n_sruns;
+  const int ax = d.s_axis;
+  const long long sx = 1, sy = d.box_dim[0], sz = (long long)d.box_dim[0] * d.box_dim[1];
+  const long long sa = ax == 0 ? sx : (ax == 1 ? sy : sz);
+  for (int r = threadIdx.x; r < nr && r < MF_LDS_RUNS; r += IMF_WG) {
+    const imf_run u = d.sruns[r];
+    const int sl = ilog2(u.len);
+    rr[r] = make_int4((int)(-(u.x * sx + u.y * sy + u.z * sz) - (long long)(u.len - 1) * sa), sl,
+                      (int)((long long)(u.len - (1 << sl)) * sa), 0);
+  }
+  __syncthreads();
   const int words = (a.nx + 63) >> 6;
-  const long long wave = (long long)blockIdx.x * (IMF_WG / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const long long nwaves = (long long)words * a.ny * a.nz;
-  if (wave >= nwaves) return;
-  const int w = (int)(wave % words);
-  const long long yz = wave / words;
-  const int y = (int)(yz % a.ny), z = (int)(yz / a.ny);
+  int w, y, z;
+  if (!mf_map(a.nx, a.ny, a.nz, w, y, z)) return;
   const int x = w * 64 + lane;
   const bool valid = x < a.nx;
   const long long vi = ((long long)z * a.ny + y) * a.nx + x;
-  float fmin = valid ? a.f[vi] : 0.f;
-  const bool om = valid && a.omega0[vi];
-  for (int q = 0; q < a.nq; q++) {
-    const imf_orient_desc& d = a.desc[q];
-    const imf_run* rl = d.sruns;
-    const int ax = d.s_axis;
-    const long long sx = 1, sy = d.box_dim[0], sz = (long long)d.box_dim[0] * d.box_dim[1];
-    const long long sa = ax == 0 ? sx : (ax == 1 ? sy : sz);
-    const float* g = a.g + q * a.g_stride;
-    const float* lv = a.lvl + q * a.lvl_stride;
-    float gam = INFINITY;
-    if (valid) {
-      // translation t = x - k; box index of t
-      const long long base = (long long)(x - d.box_lo[0]) + (long long)(y - d.box_lo[1]) * sy +
-                             (long long)(z - d.box_lo[2]) * sz;
-      for (int r = 0; r < d.n_sruns; r++) {
-        const imf_run u = rl[r];
-        const long long p = base - u.x * sx - u.y * sy - u.z * sz - (long long)(u.len - 1) * sa;
-        if (u.len == 1) {
-          gam = fminf(gam, g[p]);
-        } else {
-          const int s = ilog2(u.len);
-          const float* L = lv + (long long)(s - 1) * a.g_stride;
-          gam = fminf(gam, fminf(L[p], L[p + (long long)(u.len - (1 << s)) * sa]));
-        }
-      }
+  const float* g = a.g + qi * a.g_stride;
+  const float* lv = a.lvl + qi * a.lvl_stride - a.g_stride;  // level s at lv + s * g_stride
+  float gam = INFINITY;
+  // translation t = x - k; box index of t for k = 0 (invalid lanes read a
+  // clamped in-box position and are discarded)
+  const int xc = valid ? x : a.nx - 1;
+  const long long base = (long long)(xc - d.box_lo[0]) + (long long)(y - d.box_lo[1]) * sy +
+                         (long long)(z - d.box_lo[2]) * sz;
+  const int nl = nr < MF_LDS_RUNS ? nr : MF_LDS_RUNS;
+  int r = 0;
+  for (; r + 8 <= nl; r += 8) {
+    float v[16];
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+      const int4 u = rr[r + j];
+      const float* L = u.y == 0 ? g : lv + (long long)u.y * a.g_stride;
+      const long long p = base + u.x;
+      v[2 * j] = L[p];
+      v[2 * j + 1] = L[p + u.z];
     }
-    fmin = fminf(fmin, gam);
-    if (a.gamma_stack && valid)
-      a.gamma_stack[(long long)(a.gamma_q0 + q) * a.nx * a.ny * a.nz + vi] = gam;
-    if (a.masks_on) {
-      const unsigned long long bits = __ballot(om && (double)gam <= a.theta);
-      if (lane == 0)
-        a.masks[((long long)(a.mask_q0 + q) * a.nz + z) * a.ny * words + (long long)y * words + w] =
-            bits;
-    }
+#pragma unroll
+    for (int j = 0; j < 8; j++) gam = fminf(gam, fminf(v[2 * j], v[2 * j + 1]));
   }
-  if (valid) a.f[vi] = fmin;
+  for (; r < nl; r++) {
+    const int4 u = rr[r];
+    const float* L = u.y == 0 ? g : lv + (long long)u.y * a.g_stride;
+    const long long p = base + u.x;
+    gam = fminf(gam, fminf(L[p], L[p + u.z]));
+  }
+  for (r = MF_LDS_RUNS; r < nr; r++) {  // beyond the LDS capacity: read the runs directly
+    const imf_run u = d.sruns[r];
+    const int sl = ilog2(u.len);
+    const float* L = sl == 0 ? g : lv + (long long)sl * a.g_stride;
+    const long long p = base - (u.x * sx + u.y * sy + u.z * sz) - (long long)(u.len - 1) * sa;
+    gam = fminf(gam, fminf(L[p], L[p + (long long)(u.len - (1 << sl)) * sa]));
+  }
+  if (valid) {
+    const float fo = a.f[vi];
+    if (gam < fo) a.f[vi] = gam;
+    if (a.gamma_stack)
+      a.gamma_stack[(long long)(a.gamma_q0 + qi) * a.nx * a.ny * a.nz + vi] = gam;
+  }
+  if (a.masks_on) {
+    const bool om = valid && a.omega0[vi];
+    const unsigned long long bits = __ballot(om && (double)gam <= a.theta);
+    if (lane == 0)
+      a.masks[((long long)(a.mask_q0 + qi) * a.nz + z) * a.ny * words + (long long)y * words + w] =
+          bits;
+  }
 }
 
 hipError_t imf_launch_minfilter(const imf_min_args& a, hipStream_t s, int stage) {
   hipError_t e;
-  // levels (all orientations of the batch; the grid covers the largest box)
-  for (int level = 1; level <= a.nlvl && (stage < 0 || stage == 0); level++) {
-    const long long vol = a.g_stride;
-    hipLaunchKernelGGL(k_level, dim3((unsigned)((vol + IMF_WG - 1) / IMF_WG), a.nq),
-                       dim3(IMF_WG), 0, s, a.desc, a.g, a.g_stride, a.lvl, a.lvl_stride, level);
+  if ((stage < 0 || stage == 0) && a.nlvl > 0) {
+    // one launch for all orientations of the batch; the grid covers the
+    // largest line count (rows for x runs, x groups otherwise)
+    const size_t sm = (size_t)2 * LVL_LT * a.max_m * sizeof(float);
+    if (sm > 64 * 1024)
+      if ((e = hipFuncSetAttribute((const void*)k_levels,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm)) !=
+          hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_levels, dim3((unsigned)a.max_lines, 1, a.nq), dim3(IMF_WG), sm, s, a.desc, a.g, a.g_stride, a.lvl, a.lvl_stride, a.nlvl);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (stage == 0) return hipSuccess;
   const int words = (a.nx + 63) >> 6;
-  const long long nwaves = (long long)words * a.ny * a.nz;
-  const int per = IMF_WG / 64;
-  hipLaunchKernelGGL(k_minfilter, dim3((unsigned)((nwaves + per - 1) / per)), dim3(IMF_WG), 0, s,
-                     a);
-  return hipGetLastError();
+  const long long nbricks = (long long)words * ((a.ny + MF_BY - 1) / MF_BY) *
+                            ((a.nz + MF_BZ - 1) / MF_BZ);
+  const long long nwg = nbricks * (MF_BY * MF_BZ / (IMF_WG / 64));
+  const long long grid = (nwg + 7) / 8 * 8;
+  for (int q = 0; q < a.nq; q++) {
+    hipLaunchKernelGGL(k_minfilter, dim3((unsigned)grid), dim3(IMF_WG), 0, s, a, q);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------
