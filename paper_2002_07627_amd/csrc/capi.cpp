@@ -73,7 +73,17 @@ static imf_fft_len make_len(int n) {
   while (m % 3 == 0 && L.nstages < 8) push(3);
   while (m % 5 == 0 && L.nstages < 8) push(5);
   while (m % 7 == 0 && L.nstages < 8) push(7);
-  if (m != 1) L.nstages = -1;
+  if (m != 1) {
+    L.nstages = -1;
+    return L;
+  }
+  int ns = 1;
+  for (int s = 0; s < L.nstages; s++) {
+    L.Ns[s] = ns;
+    L.invNs[s] = 1.0f / (float)ns;
+    L.step[s] = n / (ns * L.radix[s]);
+    ns *= L.radix[s];
+  }
   return L;
 }
 
@@ -87,6 +97,14 @@ static bool smooth(int n) {
 
 extern "C" int imf_fft_size(int n) {
   if (n <= 1) return 1;
+  // lengths with compile-time transform kernels, when within 25% of n
+  static const int fast[] = {64, 96, 128, 160, 192, 216, 224, 256, 288, 320,
+                             384, 448, 512, 576, 640, 768, 1024};
+  for (int m : fast)
+    if (m >= n) {
+      if (m <= n + n / 4) return m;
+      break;
+    }
   // cheapest smooth length in [n, 1.3 n]: cost n log n with a surcharge for
   // the slower radix-5/7 stages
   double best = 1e300;

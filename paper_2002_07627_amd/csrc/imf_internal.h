@@ -49,11 +49,16 @@ struct imf_orient_desc {
   float2* spec;          // this orientation's tool spectrum [py][px/2+1][pz]
 };
 
-// FFT plan for one transform length.
+// FFT plan for one transform length: stages of the self-sorting transform.
+// Stage s has radix[s], Ns[s] = product of the earlier radices, and
+// step[s] = n / (Ns[s] * radix[s]) (twiddle index stride).
 struct imf_fft_len {
   int n;               // length
   int nstages;
   int radix[8];
+  int Ns[8];
+  int step[8];
+  float invNs[8];
 };
 
 // ---------------------------------------------------------------------------

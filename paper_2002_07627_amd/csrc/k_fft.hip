@@ -126,29 +126,38 @@ template <>
 __device__ __forceinline__ void dft<7>(float2* v, bool inv) { dft_generic<7>(v, inv); }
 
 // ---------------------------------------------------------------------------
-// one Stockham stage over a tile of CT columns held in LDS (in place: every
-// thread keeps its butterflies in registers across the barrier)
+// LDS tile: CT columns of length n, interleaved: element j of column c at
+// j * (CT + 1) + c.  Threads take (column, row) = (t % CT, t / CT), so both the
+// strided global accesses (CT consecutive columns) and the butterflies touch
+// consecutive LDS words.
 // ---------------------------------------------------------------------------
+#define LIDX(j, c) ((j) * (CT + 1) + (c))
+
+// one self-sorting (Stockham) stage, in place: every thread keeps its
+// butterflies in registers across the barrier
 template <int R, int CT, int MAXE>
-__device__ __forceinline__ void fft_stage(float2* X, int stride, const float2* tw, int n, int Ns,
-                                          bool inv) {
+__device__ __forceinline__ void fft_stage(float2* X, const float2* tw, const imf_fft_len& L,
+                                          int s, bool inv) {
+  constexpr int JR = IMF_WG / CT;
   constexpr int IT = (MAXE + R - 1) / R;
   float2 reg[IT * R];
+  const int n = L.n;
   const int nb = n / R;
-  const int items = CT * nb;
-  const int step = n / (Ns * R);
+  const int Ns = L.Ns[s];
+  const float invNs = L.invNs[s];
+  const int step = L.step[s];
+  const int c = threadIdx.x % CT;
+  const int j0 = threadIdx.x / CT;
 #pragma unroll
   for (int it = 0; it < IT; it++) {
-    const int item = threadIdx.x + it * IMF_WG;
-    if (item < items) {
-      const int c = item / nb;
-      const int j = item - c * nb;
-      const float2* col = X + c * stride;
+    const int j = j0 + it * JR;
+    if (j < nb) {
       float2 v[R];
 #pragma unroll
-      for (int k = 0; k < R; k++) v[k] = col[j + k * nb];
+      for (int k = 0; k < R; k++) v[k] = X[LIDX(j + k * nb, c)];
       if (Ns > 1) {
-        const int jm = j % Ns;
+        const int jd = (int)(((float)j + 0.5f) * invNs);
+        const int jm = j - jd * Ns;
 #pragma unroll
         for (int k = 1; k < R; k++) {
           float2 w = tw[jm * k * step];
@@ -164,36 +173,112 @@ __device__ __forceinline__ void fft_stage(float2* X, int stride, const float2* t
   __syncthreads();
 #pragma unroll
   for (int it = 0; it < IT; it++) {
-    const int item = threadIdx.x + it * IMF_WG;
-    if (item < items) {
-      const int c = item / nb;
-      const int j = item - c * nb;
-      const int jm = j % Ns;
-      const int idx = (j - jm) * R + jm;
-      float2* col = X + c * stride;
+    const int j = j0 + it * JR;
+    if (j < nb) {
+      const int jd = (int)(((float)j + 0.5f) * invNs);
+      const int jm = j - jd * Ns;
+      const int idx = jd * Ns * R + jm;
 #pragma unroll
-      for (int k = 0; k < R; k++) col[idx + k * Ns] = reg[it * R + k];
+      for (int k = 0; k < R; k++) X[LIDX(idx + k * Ns, c)] = reg[it * R + k];
     }
   }
   __syncthreads();
 }
 
-// Transform all CT columns of the tile (length L.n, stride `stride`).
-template <int CT, int MAXE>
-__device__ void fft_tile(float2* X, int stride, const float2* tw, const imf_fft_len& L, bool inv) {
-  int Ns = 1;
-  for (int s = 0; s < L.nstages; s++) {
-    const int R = L.radix[s];
-    switch (R) {
-      case 8: fft_stage<8, CT, MAXE>(X, stride, tw, L.n, Ns, inv); break;
-      case 4: fft_stage<4, CT, MAXE>(X, stride, tw, L.n, Ns, inv); break;
-      case 2: fft_stage<2, CT, MAXE>(X, stride, tw, L.n, Ns, inv); break;
-      case 3: fft_stage<3, CT, MAXE>(X, stride, tw, L.n, Ns, inv); break;
-      case 5: fft_stage<5, CT, MAXE>(X, stride, tw, L.n, Ns, inv); break;
-      case 7: fft_stage<7, CT, MAXE>(X, stride, tw, L.n, Ns, inv); break;
-      default: break;
+// compile-time stage plan of a length n: radices 8, 4, 2, 3, 5, 7 in that order
+constexpr int ct_radix(int n, int idx) {
+  int s = 0;
+  const int rs[6] = {8, 4, 2, 3, 5, 7};
+  for (int r = 0; r < 6; r++)
+    while (n % rs[r] == 0) {
+      if (s == idx) return rs[r];
+      n /= rs[r];
+      s++;
     }
-    Ns *= R;
+  return 1;
+}
+constexpr int ct_nstages(int n) {
+  int s = 0;
+  while (ct_radix(n, s) > 1) s++;
+  return s;
+}
+constexpr int ct_ns(int n, int idx) {
+  int p = 1;
+  for (int i = 0; i < idx; i++) p *= ct_radix(n, i);
+  return p;
+}
+
+// one stage with every size known at compile time
+template <int R, int N, int NS, int CT>
+__device__ __forceinline__ void fft_stage_ct(float2* X, const float2* tw, bool inv) {
+  constexpr int JR = IMF_WG / CT;
+  constexpr int NB = N / R;
+  constexpr int IT = (NB + JR - 1) / JR;
+  constexpr int STEP = N / (NS * R);
+  float2 reg[IT * R];
+  const int c = threadIdx.x % CT;
+  const int j0 = threadIdx.x / CT;
+#pragma unroll
+  for (int it = 0; it < IT; it++) {
+    const int j = j0 + it * JR;
+    if (IT * JR == NB || j < NB) {
+      float2 v[R];
+#pragma unroll
+      for (int k = 0; k < R; k++) v[k] = X[LIDX(j + k * NB, c)];
+      if (NS > 1) {
+        const int jm = j % NS;
+#pragma unroll
+        for (int k = 1; k < R; k++) {
+          float2 w = tw[jm * k * STEP];
+          if (inv) w.y = -w.y;
+          v[k] = cmul(v[k], w);
+        }
+      }
+      dft<R>(v, inv);
+#pragma unroll
+      for (int k = 0; k < R; k++) reg[it * R + k] = v[k];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < IT; it++) {
+    const int j = j0 + it * JR;
+    if (IT * JR == NB || j < NB) {
+      const int jm = j % NS;
+      const int idx = (j - jm) * R + jm;
+#pragma unroll
+      for (int k = 0; k < R; k++) X[LIDX(idx + k * NS, c)] = reg[it * R + k];
+    }
+  }
+  __syncthreads();
+}
+
+template <int N, int CT, int S>
+__device__ __forceinline__ void fft_stages_ct(float2* X, const float2* tw, bool inv) {
+  if constexpr (S < ct_nstages(N)) {
+    fft_stage_ct<ct_radix(N, S), N, ct_ns(N, S), CT>(X, tw, inv);
+    fft_stages_ct<N, CT, S + 1>(X, tw, inv);
+  }
+}
+
+// Transform all CT columns of the tile: NT > 0 is a compile-time length,
+// NT == 0 the run-time plan L.
+template <int CT, int MAXE, int NT>
+__device__ void fft_tile(float2* X, const float2* tw, const imf_fft_len& L, bool inv) {
+  if constexpr (NT > 0) {
+    fft_stages_ct<NT, CT, 0>(X, tw, inv);
+  } else {
+    for (int s = 0; s < L.nstages; s++) {
+      switch (L.radix[s]) {
+        case 8: fft_stage<8, CT, MAXE>(X, tw, L, s, inv); break;
+        case 4: fft_stage<4, CT, MAXE>(X, tw, L, s, inv); break;
+        case 2: fft_stage<2, CT, MAXE>(X, tw, L, s, inv); break;
+        case 3: fft_stage<3, CT, MAXE>(X, tw, L, s, inv); break;
+        case 5: fft_stage<5, CT, MAXE>(X, tw, L, s, inv); break;
+        case 7: fft_stage<7, CT, MAXE>(X, tw, L, s, inv); break;
+        default: break;
+      }
+    }
   }
 }
 
@@ -227,13 +312,13 @@ hipError_t imf_launch_twiddles(float2* tw, int n, hipStream_t s) {
 // (1) forward x pass of the obstacle field: rho_O = max(design, fixture),
 //     two real rows per complex column, output rows of px/2 + 1 values
 // ---------------------------------------------------------------------------
-template <int CT, int MAXE>
+template <int CT, int MAXE, int NT>
 __global__ void __launch_bounds__(IMF_WG) k_fwd_x_r2c(imf_fwd_design_args a, imf_fft_len L,
                                                       const float2* __restrict__ twg) {
   extern __shared__ float2 smem[];
-  const int n = L.n, stride = n + 1, h = n / 2 + 1;
+  const int n = L.n, h = n / 2 + 1;
   float2* X = smem;
-  float2* tw = smem + CT * stride;
+  float2* tw = smem + (CT + 1) * n;
   load_twiddles(tw, twg, n);
   const long long rows = (long long)a.ny * a.nz;
   const long long row0 = (long long)blockIdx.x * 2 * CT;
@@ -248,18 +333,17 @@ __global__ void __launch_bounds__(IMF_WG) k_fwd_x_r2c(imf_fwd_design_args a, imf
       const bool fx = a.fixture && a.fixture[idx];
       v = fx ? 1.0f : d;
     }
-    float* p = (float*)&X[(rr >> 1) * stride + x];
+    float* p = (float*)&X[LIDX(x, rr >> 1)];
     p[rr & 1] = v;
   }
   __syncthreads();
-  fft_tile<CT, MAXE>(X, stride, tw, L, false);
+  fft_tile<CT, MAXE, NT>(X, tw, L, false);
   for (int i = threadIdx.x; i < 2 * CT * h; i += IMF_WG) {
     const int rr = i / h, k = i - rr * h;
     const long long row = row0 + rr;
     if (row >= rows) continue;
-    const float2* col = X + (rr >> 1) * stride;
-    const float2 A = col[k];
-    const float2 Bc = col[k == 0 ? 0 : n - k];
+    const float2 A = X[LIDX(k, rr >> 1)];
+    const float2 Bc = X[LIDX(k == 0 ? 0 : n - k, rr >> 1)];
     const float2 B = make_float2(Bc.x, -Bc.y);
     float2 out;
     if ((rr & 1) == 0) {
@@ -289,14 +373,14 @@ struct strided_io {
 // pass kinds for the per-orientation geometry
 enum { PASS_DESIGN_Y = 0, PASS_TOOL_Y = 1, PASS_INV_Y = 2 };
 
-template <int CT, int MAXE, int KIND>
+template <int CT, int MAXE, int NT, int KIND>
 __global__ void __launch_bounds__(IMF_WG) k_pass_strided(strided_io io, imf_fft_len L,
                                                          const float2* __restrict__ twg,
                                                          const imf_orient_desc* __restrict__ desc,
                                                          int planes_fixed, int n_in_fixed,
                                                          int n_out_fixed, int inv) {
   extern __shared__ float2 smem[];
-  const int n = L.n, stride = n + 1;
+  const int n = L.n;
   const int q = blockIdx.z, plane = blockIdx.y;
   int planes = planes_fixed, n_in = n_in_fixed, n_out = n_out_fixed, sh_in = 0, sh_out = 0;
   if (KIND == PASS_TOOL_Y) {
@@ -310,7 +394,7 @@ __global__ void __launch_bounds__(IMF_WG) k_pass_strided(strided_io io, imf_fft_
   }
   if (plane >= planes) return;
   float2* X = smem;
-  float2* tw = smem + CT * stride;
+  float2* tw = smem + (CT + 1) * n;
   load_twiddles(tw, twg, n);
   const int c0 = blockIdx.x * CT;
   const float2* in = io.in + q * io.in_q + plane * io.in_plane + c0;
@@ -320,17 +404,17 @@ __global__ void __launch_bounds__(IMF_WG) k_pass_strided(strided_io io, imf_fft_
     if (j < n_in && c0 + c < io.ncols) v = in[j * io.in_j + c];
     int pos = j + sh_in;
     if (pos >= n) pos -= n;
-    X[c * stride + pos] = v;
+    X[LIDX(pos, c)] = v;
   }
   __syncthreads();
-  fft_tile<CT, MAXE>(X, stride, tw, L, inv != 0);
+  fft_tile<CT, MAXE, NT>(X, tw, L, inv != 0);
   float2* out = io.out + q * io.out_q + plane * io.out_plane + c0;
   for (int i = threadIdx.x; i < CT * n_out; i += IMF_WG) {
     const int j = i / CT, c = i - j * CT;
     if (c0 + c >= io.ncols) continue;
     int pos = j + sh_out;
     if (pos >= n) pos -= n;
-    out[j * io.out_j + c] = X[c * stride + pos];
+    out[j * io.out_j + c] = X[LIDX(pos, c)];
   }
 }
 
@@ -338,7 +422,7 @@ __global__ void __launch_bounds__(IMF_WG) k_pass_strided(strided_io io, imf_fft_
 // (3) forward z pass: strided input (plane stride), contiguous output columns
 //     out[ky][kx][kz].  The tile is CT consecutive kx at one ky.
 // ---------------------------------------------------------------------------
-template <int CT, int MAXE, int TOOL>
+template <int CT, int MAXE, int NT, int TOOL>
 __global__ void __launch_bounds__(IMF_WG) k_pass_z_fwd(const float2* __restrict__ in,
                                                        long long in_q, long long in_j,
                                                        float2* __restrict__ out, int h,
@@ -347,7 +431,7 @@ __global__ void __launch_bounds__(IMF_WG) k_pass_z_fwd(const float2* __restrict_
                                                        const imf_orient_desc* __restrict__ desc,
                                                        long long spec_q_fixed) {
   extern __shared__ float2 smem[];
-  const int n = L.n, stride = n + 1;
+  const int n = L.n;
   const int q = blockIdx.z, ky = blockIdx.y;
   int n_in = n_in_fixed, sh = 0;
   float2* obase = out + q * spec_q_fixed;
@@ -357,7 +441,7 @@ __global__ void __launch_bounds__(IMF_WG) k_pass_z_fwd(const float2* __restrict_
     obase = desc[q].spec;
   }
   float2* X = smem;
-  float2* tw = smem + CT * stride;
+  float2* tw = smem + (CT + 1) * n;
   load_twiddles(tw, twg, n);
   const int c0 = blockIdx.x * CT;
   // element (j, ky, kx) of the input at j * in_j + ky * h + kx
@@ -368,15 +452,15 @@ __global__ void __launch_bounds__(IMF_WG) k_pass_z_fwd(const float2* __restrict_
     if (j < n_in && c0 + c < h) v = src[j * in_j + c];
     int pos = j + sh;
     if (pos >= n) pos -= n;
-    X[c * stride + pos] = v;
+    X[LIDX(pos, c)] = v;
   }
   __syncthreads();
-  fft_tile<CT, MAXE>(X, stride, tw, L, false);
+  fft_tile<CT, MAXE, NT>(X, tw, L, false);
   float2* dst = obase + ((long long)ky * h + c0) * n;
   const int ncol = min(CT, h - c0);
   for (int i = threadIdx.x; i < ncol * n; i += IMF_WG) {
     const int c = i / n, k = i - c * n;
-    dst[(long long)c * n + k] = X[c * stride + k];
+    dst[(long long)c * n + k] = X[LIDX(k, c)];
   }
 }
 
@@ -422,23 +506,24 @@ __global__ void __launch_bounds__(IMF_WG) k_tool_x(const imf_orient_desc* __rest
 //     The rho_hat tile is kept in registers and reused for every orientation
 //     of the batch.
 // ---------------------------------------------------------------------------
-template <int CT, int MAXE>
+template <int CT, int MAXE, int NT>
 __global__ void __launch_bounds__(IMF_WG) k_inv_z_product(imf_inv_args a, imf_fft_len L,
                                                           const float2* __restrict__ twg) {
   extern __shared__ float2 smem[];
-  const int n = L.n, stride = n + 1;
+  const int n = L.n;
   const int h = a.px / 2 + 1;
   const int ky = blockIdx.y;
   const int c0 = blockIdx.x * CT;
   const int ncol = min(CT, h - c0);
   float2* X = smem;
-  float2* tw = smem + CT * stride;
+  float2* tw = smem + (CT + 1) * n;
   load_twiddles(tw, twg, n);
   const float scale = 1.0f / ((float)a.px * (float)a.py * (float)a.pz);
   const float2* rsrc = a.rho_hat + ((long long)ky * h + c0) * n;
-  float2 rho[MAXE];
+  constexpr int RE = NT > 0 ? (CT * NT + IMF_WG - 1) / IMF_WG : MAXE;
+  float2 rho[RE];
 #pragma unroll
-  for (int e = 0; e < MAXE; e++) {
+  for (int e = 0; e < RE; e++) {
     const int i = threadIdx.x + e * IMF_WG;
     rho[e] = i < ncol * n ? rsrc[i] : make_float2(0.f, 0.f);
   }
@@ -447,7 +532,7 @@ __global__ void __launch_bounds__(IMF_WG) k_inv_z_product(imf_inv_args a, imf_ff
     const float2* tsrc = d.spec + ((long long)ky * h + c0) * n;
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < MAXE; e++) {
+    for (int e = 0; e < RE; e++) {
       const int i = threadIdx.x + e * IMF_WG;
       if (i < CT * n) {
         const int c = i / n, k = i - c * n;
@@ -458,11 +543,11 @@ __global__ void __launch_bounds__(IMF_WG) k_inv_z_product(imf_inv_args a, imf_ff
           // r * conj(t) * scale
           v = make_float2((r.x * t.x + r.y * t.y) * scale, (r.y * t.x - r.x * t.y) * scale);
         }
-        X[c * stride + k] = v;
+        X[LIDX(k, c)] = v;
       }
     }
     __syncthreads();
-    fft_tile<CT, MAXE>(X, stride, tw, L, true);
+    fft_tile<CT, MAXE, NT>(X, tw, L, true);
     const int mz = d.box_dim[2];
     const int sh = pmod(d.box_lo[2], n);
     float2* dst = a.w1 + q * a.w1_stride + (long long)ky * h + c0;
@@ -472,7 +557,7 @@ __global__ void __launch_bounds__(IMF_WG) k_inv_z_product(imf_inv_args a, imf_ff
       if (c >= ncol) continue;
       int pos = z + sh;
       if (pos >= n) pos -= n;
-      dst[z * zs + c] = X[c * stride + pos];
+      dst[z * zs + c] = X[LIDX(pos, c)];
     }
   }
 }
@@ -481,11 +566,11 @@ __global__ void __launch_bounds__(IMF_WG) k_inv_z_product(imf_inv_args a, imf_ff
 // (6) inverse x pass (complex-to-real, two rows per complex column) with the
 //     rounding / guard-band epilogue.  Writes g over the query box.
 // ---------------------------------------------------------------------------
-template <int CT, int MAXE>
+template <int CT, int MAXE, int NT>
 __global__ void __launch_bounds__(IMF_WG) k_inv_x_c2r(imf_inv_args a, imf_fft_len L,
                                                       const float2* __restrict__ twg) {
   extern __shared__ float2 smem[];
-  const int n = L.n, stride = n + 1, h = n / 2 + 1;
+  const int n = L.n, h = n / 2 + 1;
   const int q = blockIdx.z;
   const imf_orient_desc& d = a.desc[q];
   const int mx = d.box_dim[0], my = d.box_dim[1], mz = d.box_dim[2];
@@ -493,7 +578,7 @@ __global__ void __launch_bounds__(IMF_WG) k_inv_x_c2r(imf_inv_args a, imf_fft_le
   const long long row0 = (long long)blockIdx.x * 2 * CT;
   if (row0 >= rows) return;
   float2* X = smem;
-  float2* tw = smem + CT * stride;
+  float2* tw = smem + (CT + 1) * n;
   load_twiddles(tw, twg, n);
   const float2* src = a.w2 + q * a.w2_stride;
   for (int i = threadIdx.x; i < CT * h; i += IMF_WG) {
@@ -509,11 +594,11 @@ __global__ void __launch_bounds__(IMF_WG) k_inv_x_c2r(imf_inv_args a, imf_fft_le
       B = src[(zz * a.max_my + yy) * h + k];
     }
     // Z(k) = A + iB;  Z(n-k) = conj(A) + i conj(B)
-    X[c * stride + k] = make_float2(A.x - B.y, A.y + B.x);
-    if (k > 0 && k < n - k) X[c * stride + n - k] = make_float2(A.x + B.y, B.x - A.y);
+    X[LIDX(k, c)] = make_float2(A.x - B.y, A.y + B.x);
+    if (k > 0 && k < n - k) X[LIDX(n - k, c)] = make_float2(A.x + B.y, B.x - A.y);
   }
   __syncthreads();
-  fft_tile<CT, MAXE>(X, stride, tw, L, true);
+  fft_tile<CT, MAXE, NT>(X, tw, L, true);
   const int sh = pmod(d.box_lo[0], n);
   float* dst = a.g + q * a.g_stride;
   float local_err = 0.f;
@@ -523,7 +608,7 @@ __global__ void __launch_bounds__(IMF_WG) k_inv_x_c2r(imf_inv_args a, imf_fft_le
     if (row >= rows) continue;
     int pos = x + sh;
     if (pos >= n) pos -= n;
-    const float2 z = X[(rr >> 1) * stride + pos];
+    const float2 z = X[LIDX(pos, rr >> 1)];
     float v = (rr & 1) ? z.y : z.x;
     const long long li = row * mx + x;
     if (a.binary) {
@@ -552,21 +637,49 @@ __global__ void __launch_bounds__(IMF_WG) k_inv_x_c2r(imf_inv_args a, imf_fft_le
 // ---------------------------------------------------------------------------
 // dispatch on the transform length (CT columns x MAXE elements per thread)
 // ---------------------------------------------------------------------------
+// Dispatch on the transform length: compile-time plans for the lengths the
+// planner prefers, the run-time plan otherwise.  CT columns per tile; MAXE
+// elements per thread bound the run-time path's registers.
+#define CASE_N(NV, CTV, MAXEV, ...)                   \
+  case NV: {                                          \
+    constexpr int NT = NV, CT = CTV, MAXE = MAXEV;    \
+    __VA_ARGS__;                                      \
+  } break;
 #define DISPATCH(n, ...)                                   \
   do {                                                     \
-    if ((n) <= 256) {                                      \
-      constexpr int CT = 16, MAXE = 16;                    \
-      __VA_ARGS__;                                         \
-    } else if ((n) <= 512) {                               \
-      constexpr int CT = 16, MAXE = 32;                    \
-      __VA_ARGS__;                                         \
-    } else {                                               \
-      constexpr int CT = 8, MAXE = 32;                     \
-      __VA_ARGS__;                                         \
+    switch (n) {                                           \
+      CASE_N(64, 16, 16, __VA_ARGS__)                      \
+      CASE_N(96, 16, 16, __VA_ARGS__)                      \
+      CASE_N(128, 16, 16, __VA_ARGS__)                     \
+      CASE_N(160, 16, 16, __VA_ARGS__)                     \
+      CASE_N(192, 16, 16, __VA_ARGS__)                     \
+      CASE_N(216, 16, 16, __VA_ARGS__)                     \
+      CASE_N(224, 16, 16, __VA_ARGS__)                     \
+      CASE_N(256, 16, 16, __VA_ARGS__)                     \
+      CASE_N(288, 8, 16, __VA_ARGS__)                      \
+      CASE_N(320, 8, 16, __VA_ARGS__)                      \
+      CASE_N(384, 8, 16, __VA_ARGS__)                      \
+      CASE_N(448, 8, 16, __VA_ARGS__)                      \
+      CASE_N(512, 8, 16, __VA_ARGS__)                      \
+      CASE_N(576, 8, 32, __VA_ARGS__)                      \
+      CASE_N(640, 8, 32, __VA_ARGS__)                      \
+      CASE_N(768, 8, 32, __VA_ARGS__)                      \
+      CASE_N(1024, 8, 32, __VA_ARGS__)                     \
+      default:                                             \
+        if ((n) <= 256) {                                  \
+          constexpr int NT = 0, CT = 16, MAXE = 16;        \
+          __VA_ARGS__;                                     \
+        } else if ((n) <= 512) {                           \
+          constexpr int NT = 0, CT = 16, MAXE = 32;        \
+          __VA_ARGS__;                                     \
+        } else {                                           \
+          constexpr int NT = 0, CT = 8, MAXE = 32;         \
+          __VA_ARGS__;                                     \
+        }                                                  \
     }                                                      \
   } while (0)
 
-static size_t smem_bytes(int n, int ct) { return (size_t)(ct * (n + 1) + n) * sizeof(float2); }
+static size_t smem_bytes(int n, int ct) { return (size_t)((ct + 1) * n + n) * sizeof(float2); }
 
 static hipError_t set_smem(const void* fn, size_t bytes) {
   if (bytes > 64 * 1024)
@@ -583,7 +696,7 @@ hipError_t imf_launch_fwd_design(const imf_fwd_design_args& a, const imf_fft_len
   DISPATCH(fx.n, {
     const long long rows = (long long)a.ny * a.nz;
     const size_t sm = smem_bytes(fx.n, CT);
-    auto k = k_fwd_x_r2c<CT, MAXE>;
+    auto k = k_fwd_x_r2c<CT, MAXE, NT>;
     if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3((unsigned)((rows + 2 * CT - 1) / (2 * CT))), dim3(IMF_WG), sm, s,
                        a, fx, twx);
@@ -592,7 +705,7 @@ hipError_t imf_launch_fwd_design(const imf_fwd_design_args& a, const imf_fft_len
   DISPATCH(fy.n, {
     strided_io io{a.work1, 0, (long long)a.ny * h, h, a.work2, 0, (long long)a.py * h, h, h};
     const size_t sm = smem_bytes(fy.n, CT);
-    auto k = k_pass_strided<CT, MAXE, PASS_DESIGN_Y>;
+    auto k = k_pass_strided<CT, MAXE, NT, PASS_DESIGN_Y>;
     if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3((h + CT - 1) / CT, a.nz, 1), dim3(IMF_WG), sm, s, io, fy, twy,
                        (const imf_orient_desc*)nullptr, a.nz, a.ny, a.py, 0);
@@ -600,7 +713,7 @@ hipError_t imf_launch_fwd_design(const imf_fwd_design_args& a, const imf_fft_len
   if ((e = hipGetLastError()) != hipSuccess) return e;
   DISPATCH(fz.n, {
     const size_t sm = smem_bytes(fz.n, CT);
-    auto k = k_pass_z_fwd<CT, MAXE, 0>;
+    auto k = k_pass_z_fwd<CT, MAXE, NT, 0>;
     if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3((h + CT - 1) / CT, a.py, 1), dim3(IMF_WG), sm, s, a.work2, 0LL,
                        (long long)a.py * h, a.out, h, a.nz, fz, twz,
@@ -628,7 +741,7 @@ hipError_t imf_launch_tool_fft(const imf_tool_fft_args& a, const imf_fft_len& fy
     strided_io io{a.work1, a.w1_stride, (long long)a.max_ty * h, h,
                   a.work2, a.w2_stride, (long long)a.py * h, h, h};
     const size_t sm = smem_bytes(fy.n, CT);
-    auto k = k_pass_strided<CT, MAXE, PASS_TOOL_Y>;
+    auto k = k_pass_strided<CT, MAXE, NT, PASS_TOOL_Y>;
     if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3((h + CT - 1) / CT, a.max_tz, a.nq), dim3(IMF_WG), sm, s, io, fy,
                        twy, a.desc, 0, 0, a.py, 0);
@@ -636,7 +749,7 @@ hipError_t imf_launch_tool_fft(const imf_tool_fft_args& a, const imf_fft_len& fy
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (stage < 0 || stage == 2) DISPATCH(fz.n, {
     const size_t sm = smem_bytes(fz.n, CT);
-    auto k = k_pass_z_fwd<CT, MAXE, 1>;
+    auto k = k_pass_z_fwd<CT, MAXE, NT, 1>;
     if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3((h + CT - 1) / CT, a.py, a.nq), dim3(IMF_WG), sm, s, a.work2,
                        a.w2_stride, (long long)a.py * h, (float2*)nullptr, h, 0, fz, twz, a.desc,
@@ -652,7 +765,7 @@ hipError_t imf_launch_inverse(const imf_inv_args& a, const imf_fft_len& fx,
   hipError_t e = hipSuccess;
   if (stage < 0 || stage == 0) DISPATCH(fz.n, {
     const size_t sm = smem_bytes(fz.n, CT);
-    auto k = k_inv_z_product<CT, MAXE>;
+    auto k = k_inv_z_product<CT, MAXE, NT>;
     if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3((h + CT - 1) / CT, a.py, 1), dim3(IMF_WG), sm, s, a, fz, twz);
   });
@@ -661,7 +774,7 @@ hipError_t imf_launch_inverse(const imf_inv_args& a, const imf_fft_len& fx,
     strided_io io{a.w1, a.w1_stride, (long long)a.py * h, h,
                   a.w2, a.w2_stride, (long long)a.max_my * h, h, h};
     const size_t sm = smem_bytes(fy.n, CT);
-    auto k = k_pass_strided<CT, MAXE, PASS_INV_Y>;
+    auto k = k_pass_strided<CT, MAXE, NT, PASS_INV_Y>;
     if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3((h + CT - 1) / CT, a.max_mz, a.nq), dim3(IMF_WG), sm, s, io, fy,
                        twy, a.desc, 0, a.py, 0, 1);
@@ -669,7 +782,7 @@ hipError_t imf_launch_inverse(const imf_inv_args& a, const imf_fft_len& fx,
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (stage < 0 || stage == 2) DISPATCH(fx.n, {
     const size_t sm = smem_bytes(fx.n, CT);
-    auto k = k_inv_x_c2r<CT, MAXE>;
+    auto k = k_inv_x_c2r<CT, MAXE, NT>;
     if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
     const long long rows = (long long)a.max_my * a.max_mz;
     hipLaunchKernelGGL(k, dim3((unsigned)((rows + 2 * CT - 1) / (2 * CT)), 1, a.nq),
@@ -685,7 +798,7 @@ hipError_t imf_launch_columns(const float2* in, float2* out, int ncols, long lon
   DISPATCH(L.n, {
     strided_io io{in, 0, 0, jstride, out, 0, 0, jstride, ncols};
     const size_t sm = smem_bytes(L.n, CT);
-    auto k = k_pass_strided<CT, MAXE, PASS_DESIGN_Y>;
+    auto k = k_pass_strided<CT, MAXE, NT, PASS_DESIGN_Y>;
     if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3((ncols + CT - 1) / CT, 1, 1), dim3(IMF_WG), sm, s, io, L, tw,
                        (const imf_orient_desc*)nullptr, 1, L.n, L.n, inverse);
