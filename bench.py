@@ -29,6 +29,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE / WRITE_SIZE
+    summary, or None when the kernel's source changed since it was measured."""
+    import hashlib
+    f = os.path.join(ROOT, "profiles", "traffic_c3_256x130.json")
+    if not os.path.exists(f):
+        return None
+    e = json.load(open(f)).get(kernel)
+    if not e:
+        return None
+    src = os.path.join(ROOT, e["source"])
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != e["sha256"]:
+        return None
+    return e["bytes_per_launch"]
+
+
 def cpu_baseline(w, target_s=15.0):
     """The CPU oracle as it stands on a crop of the same workload: the full
     pipeline (exact overlaps over the query box, sharp-point minimum, masks off)
@@ -133,12 +149,13 @@ def main():
     log("timed: %.2f ms/step, %.3e voxel-orientations/s" % (ms, value))
 
     # per kernel class over the timed steps
-    kms, kn, kb = {}, {}, {}
+    kms, kn, kb, ko = {}, {}, {}, {}
     for st in stats:
         for k, v in st.kernel_ms.items():
             kms[k] = kms.get(k, 0) + v
             kn[k] = kn.get(k, 0) + st.kernel_launches[k]
             kb[k] = kb.get(k, 0) + st.kernel_bytes[k]
+            ko[k] = ko.get(k, 0) + st.kernel_ops[k]
     dom = max(kms, key=kms.get)
     avg_ms = kms[dom] / kn[dom]
     bytes_per_launch = kb[dom] / kn[dom]
@@ -150,14 +167,21 @@ def main():
         log("  %-14s %8.2f ms/step  %5.1f launches  %s GB/s" %
             (k, v["ms_per_step"], v["launches_per_step"],
              "%.0f" % v["GBps"] if v["GBps"] else "-"))
-    traffic = None
-    tfile = os.path.join(ROOT, "profiles", "traffic_%s_c3.json" % dom)
-    if os.path.exists(tfile):
-        traffic = json.load(open(tfile)).get("bytes_per_launch")
+    traffic = measured_traffic(dom)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": dom, "avg_launch_ms": round(avg_ms, 4),
                 "algorithmic_bytes_per_launch": bytes_per_launch}
+    # the sharp-point minimum is bound by its gathers: every lookup is one
+    # 4-byte lane load through the vector memory pipeline, whose address rate is
+    # 16 lanes per clock per CU (256 CUs, 2.4 GHz -> 9.83e12 lane loads/s)
+    gather = None
+    if ko.get("minfilter"):
+        lps = ko["minfilter"] / (kms["minfilter"] * 1e-3)
+        peak = 256 * 16 * 2.4e9
+        gather = {"bound": "vmem-gather", "kernel": "minfilter", "achieved": lps,
+                  "peak": peak, "unit": "lane-loads/s", "frac": round(lps / peak, 4),
+                  "lookups_per_step": ko["minfilter"] / args.steps}
 
     plain = None
     if not args.no_plain:
@@ -191,6 +215,7 @@ def main():
                    "grid": list(w.design.shape), "orientations": nR, "P": list(last.P),
                    "batch": last.batch, "spectra": "cached (warm)"},
         "roofline": roofline,
+        "roofline_gather": gather,
         "cpu_baseline": cpu,
         "plain": plain,
         "kernels": kernels,

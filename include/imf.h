@@ -136,6 +136,7 @@ typedef struct {
   double k_ms[16];
   int k_n[16];
   double k_bytes[16];    /* algorithmic bytes of each class (compulsory reads + writes) */
+  double k_ops[16];      /* class 11: window-minimum lookups (gathered floats) */
 } imf_stats;
 
 /* Bytes of device workspace the request needs (admission control). */

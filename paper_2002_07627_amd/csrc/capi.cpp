@@ -604,7 +604,10 @@ static imf_status make_plan(imf_ctx* c, const imf_request* r, const imf_outputs*
     d.sruns = e.sruns;
     d.truns = e.truns;
     d.spec = nullptr;
-    max_sdim = std::max(max_sdim, e.ext[9 + e.s_axis] - e.ext[6 + e.s_axis] + 1);
+    const int sdim = e.ext[9 + e.s_axis] - e.ext[6 + e.s_axis] + 1;
+    max_sdim = std::max(max_sdim, sdim);
+    d.nlvl = 0;
+    while ((2 << d.nlvl) <= sdim) d.nlvl++;
   }
   if (p.max_vol > (1LL << 31) - 1) return fail(IMF_EINVAL, "query box too large");
   p.nlvl = 0;
@@ -814,6 +817,7 @@ struct Pending {
   std::chrono::steady_clock::time_point t_start;
   imf_outputs* out = nullptr;
   double kbytes[16] = {0};  // algorithmic bytes per kernel class
+  double kops[16] = {0};    // gathered floats of the minimum filter
 };
 
 // Enqueue the whole request on stream s (no host synchronization after the
@@ -974,7 +978,8 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
       } else {
         pd.kbytes[8] += 4.0 * M3 + 16.0 * d.n_truns;
       }
-      pd.kbytes[10] += 2.0 * 4.0 * M3 * p.nlvl;
+      pd.kbytes[10] += 4.0 * M3 * (1 + d.nlvl);
+      pd.kops[11] += 2.0 * (double)N * d.n_sruns;
       pd.kbytes[11] += 4.0 * M3 + 16.0 * d.n_sruns +
                        (p.masks && p.theta_known && !p.sweep ? N / 8.0 : 0.0) +
                        (p.two_phase ? 4.0 * N : 0.0);
@@ -1137,7 +1142,10 @@ static imf_status compute_finish(Pending& pd, imf_stats* st) {
     st->guard_band = p.band;
     pd.tm.collect(st);
     if (pd.tm.fine)
-      for (int k = 0; k < 16; k++) st->k_bytes[k] = pd.kbytes[k];
+      for (int k = 0; k < 16; k++) {
+        st->k_bytes[k] = pd.kbytes[k];
+        st->k_ops[k] = pd.kops[k];
+      }
     st->t_ms[7] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
                                                             pd.t_start).count();
     st->model_bytes = model_bytes(p);

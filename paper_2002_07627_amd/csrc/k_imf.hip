@@ -225,7 +225,8 @@ __global__ void __launch_bounds__(IMF_WG) k_levels(const imf_orient_desc* __rest
     A[l * m + i] = ok ? src[gi] : INFINITY;
   }
   __syncthreads();
-  for (int s = 1; s <= nlvl; s++) {
+  const int nl_q = d.nlvl < nlvl ? d.nlvl : nlvl;
+  for (int s = 1; s <= nl_q; s++) {
     const int h = 1 << (s - 1);
     float* dst = dstb + (long long)(s - 1) * g_stride;
     for (int t = threadIdx.x; t < nl * m; t += IMF_WG) {

@@ -62,7 +62,7 @@ class _Stats(C.Structure):
                 ("n_orient", C.c_int), ("method", C.c_int), ("batch", C.c_int),
                 ("cache_hits", C.c_int), ("cache_misses", C.c_int),
                 ("k_ms", C.c_double * 16), ("k_n", C.c_int * 16),
-                ("k_bytes", C.c_double * 16)]
+                ("k_bytes", C.c_double * 16), ("k_ops", C.c_double * 16)]
 
 
 @dataclass
@@ -82,15 +82,17 @@ class Stats:
     kernel_ms: dict
     kernel_launches: dict
     kernel_bytes: dict
+    kernel_ops: dict
 
     @classmethod
     def _from(cls, s: _Stats):
         kms = {k: s.k_ms[i] for i, k in enumerate(KERNEL_CLASSES) if s.k_n[i]}
         kn = {k: s.k_n[i] for i, k in enumerate(KERNEL_CLASSES) if s.k_n[i]}
         kb = {k: s.k_bytes[i] for i, k in enumerate(KERNEL_CLASSES) if s.k_n[i]}
+        ko = {k: s.k_ops[i] for i, k in enumerate(KERNEL_CLASSES) if s.k_n[i]}
         return cls(s.F_max, s.guard_flags, s.max_frac_err, s.guard_band, list(s.t_ms),
                    s.model_bytes, tuple(s.P), s.n_orient, s.method, s.batch, s.cache_hits,
-                   s.cache_misses, kms, kn, kb)
+                   s.cache_misses, kms, kn, kb, ko)
 
 
 _lib = None
