@@ -286,6 +286,27 @@ __device__ __forceinline__ void load_twiddles(float2* tw_lds, const float2* tw, 
   for (int i = threadIdx.x; i < n; i += blockDim.x) tw_lds[i] = tw[i];
 }
 
+// The hardware deals workgroups to the 8 XCDs round robin.  Column-tile
+// kernels are launched on a flat grid of 8 * ceil(GX*GY*GZ / 8) workgroups and
+// remap so that each XCD walks a contiguous range of (tile, plane, orientation)
+// triples: neighbouring column tiles, which share 128-byte lines, meet in the
+// same L2.
+__device__ __forceinline__ bool xcd_blocks(int GX, int GY, int GZ, int& bx, int& by, int& bz) {
+  const long long total = (long long)GX * GY * GZ;
+  const long long per = (total + 7) / 8;
+  const long long id = blockIdx.x;
+  const long long lg = (id % 8) * per + id / 8;
+  if (lg >= total) return false;
+  bx = (int)(lg % GX);
+  const long long r = lg / GX;
+  by = (int)(r % GY);
+  bz = (int)(r / GY);
+  return true;
+}
+static inline unsigned xcd_grid(long long GX, long long GY, long long GZ) {
+  return (unsigned)((GX * GY * GZ + 7) / 8 * 8);
+}
+
 __device__ __forceinline__ int pmod(long long a, int n) {
   long long r = a % n;
   return (int)(r < 0 ? r + n : r);
@@ -378,10 +399,12 @@ __global__ void __launch_bounds__(IMF_WG) k_pass_strided(strided_io io, imf_fft_
                                                          const float2* __restrict__ twg,
                                                          const imf_orient_desc* __restrict__ desc,
                                                          int planes_fixed, int n_in_fixed,
-                                                         int n_out_fixed, int inv) {
+                                                         int n_out_fixed, int inv, int GX, int GY,
+                                                         int GZ) {
   extern __shared__ float2 smem[];
   const int n = L.n;
-  const int q = blockIdx.z, plane = blockIdx.y;
+  int bx, plane, q;
+  if (!xcd_blocks(GX, GY, GZ, bx, plane, q)) return;
   int planes = planes_fixed, n_in = n_in_fixed, n_out = n_out_fixed, sh_in = 0, sh_out = 0;
   if (KIND == PASS_TOOL_Y) {
     planes = desc[q].tdim[2];
@@ -396,7 +419,7 @@ __global__ void __launch_bounds__(IMF_WG) k_pass_strided(strided_io io, imf_fft_
   float2* X = smem;
   float2* tw = smem + (CT + 1) * n;
   load_twiddles(tw, twg, n);
-  const int c0 = blockIdx.x * CT;
+  const int c0 = bx * CT;
   const float2* in = io.in + q * io.in_q + plane * io.in_plane + c0;
   for (int i = threadIdx.x; i < CT * n; i += IMF_WG) {
     const int j = i / CT, c = i - j * CT;
@@ -429,10 +452,12 @@ __global__ void __launch_bounds__(IMF_WG) k_pass_z_fwd(const float2* __restrict_
                                                        int n_in_fixed, imf_fft_len L,
                                                        const float2* __restrict__ twg,
                                                        const imf_orient_desc* __restrict__ desc,
-                                                       long long spec_q_fixed) {
+                                                       long long spec_q_fixed, int GX, int GY,
+                                                       int GZ) {
   extern __shared__ float2 smem[];
   const int n = L.n;
-  const int q = blockIdx.z, ky = blockIdx.y;
+  int bx, ky, q;
+  if (!xcd_blocks(GX, GY, GZ, bx, ky, q)) return;
   int n_in = n_in_fixed, sh = 0;
   float2* obase = out + q * spec_q_fixed;
   if (TOOL) {
@@ -443,7 +468,7 @@ __global__ void __launch_bounds__(IMF_WG) k_pass_z_fwd(const float2* __restrict_
   float2* X = smem;
   float2* tw = smem + (CT + 1) * n;
   load_twiddles(tw, twg, n);
-  const int c0 = blockIdx.x * CT;
+  const int c0 = bx * CT;
   // element (j, ky, kx) of the input at j * in_j + ky * h + kx
   const float2* src = in + q * in_q + (long long)ky * h + c0;
   for (int i = threadIdx.x; i < CT * n; i += IMF_WG) {
@@ -508,12 +533,14 @@ __global__ void __launch_bounds__(IMF_WG) k_tool_x(const imf_orient_desc* __rest
 // ---------------------------------------------------------------------------
 template <int CT, int MAXE, int NT>
 __global__ void __launch_bounds__(IMF_WG) k_inv_z_product(imf_inv_args a, imf_fft_len L,
-                                                          const float2* __restrict__ twg) {
+                                                          const float2* __restrict__ twg, int GX,
+                                                          int GY) {
   extern __shared__ float2 smem[];
   const int n = L.n;
   const int h = a.px / 2 + 1;
-  const int ky = blockIdx.y;
-  const int c0 = blockIdx.x * CT;
+  int bx, ky, bz;
+  if (!xcd_blocks(GX, GY, 1, bx, ky, bz)) return;
+  const int c0 = bx * CT;
   const int ncol = min(CT, h - c0);
   float2* X = smem;
   float2* tw = smem + (CT + 1) * n;
@@ -707,17 +734,19 @@ hipError_t imf_launch_fwd_design(const imf_fwd_design_args& a, const imf_fft_len
     const size_t sm = smem_bytes(fy.n, CT);
     auto k = k_pass_strided<CT, MAXE, NT, PASS_DESIGN_Y>;
     if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k, dim3((h + CT - 1) / CT, a.nz, 1), dim3(IMF_WG), sm, s, io, fy, twy,
-                       (const imf_orient_desc*)nullptr, a.nz, a.ny, a.py, 0);
+    const int GX = (h + CT - 1) / CT;
+    hipLaunchKernelGGL(k, dim3(xcd_grid(GX, a.nz, 1)), dim3(IMF_WG), sm, s, io, fy, twy,
+                       (const imf_orient_desc*)nullptr, a.nz, a.ny, a.py, 0, GX, a.nz, 1);
   });
   if ((e = hipGetLastError()) != hipSuccess) return e;
   DISPATCH(fz.n, {
     const size_t sm = smem_bytes(fz.n, CT);
     auto k = k_pass_z_fwd<CT, MAXE, NT, 0>;
     if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k, dim3((h + CT - 1) / CT, a.py, 1), dim3(IMF_WG), sm, s, a.work2, 0LL,
+    const int GX = (h + CT - 1) / CT;
+    hipLaunchKernelGGL(k, dim3(xcd_grid(GX, a.py, 1)), dim3(IMF_WG), sm, s, a.work2, 0LL,
                        (long long)a.py * h, a.out, h, a.nz, fz, twz,
-                       (const imf_orient_desc*)nullptr, 0LL);
+                       (const imf_orient_desc*)nullptr, 0LL, GX, a.py, 1);
   });
   return hipGetLastError();
 }
@@ -743,17 +772,19 @@ hipError_t imf_launch_tool_fft(const imf_tool_fft_args& a, const imf_fft_len& fy
     const size_t sm = smem_bytes(fy.n, CT);
     auto k = k_pass_strided<CT, MAXE, NT, PASS_TOOL_Y>;
     if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k, dim3((h + CT - 1) / CT, a.max_tz, a.nq), dim3(IMF_WG), sm, s, io, fy,
-                       twy, a.desc, 0, 0, a.py, 0);
+    const int GX = (h + CT - 1) / CT;
+    hipLaunchKernelGGL(k, dim3(xcd_grid(GX, a.max_tz, a.nq)), dim3(IMF_WG), sm, s, io, fy, twy,
+                       a.desc, 0, 0, a.py, 0, GX, a.max_tz, a.nq);
   });
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (stage < 0 || stage == 2) DISPATCH(fz.n, {
     const size_t sm = smem_bytes(fz.n, CT);
     auto k = k_pass_z_fwd<CT, MAXE, NT, 1>;
     if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k, dim3((h + CT - 1) / CT, a.py, a.nq), dim3(IMF_WG), sm, s, a.work2,
+    const int GX = (h + CT - 1) / CT;
+    hipLaunchKernelGGL(k, dim3(xcd_grid(GX, a.py, a.nq)), dim3(IMF_WG), sm, s, a.work2,
                        a.w2_stride, (long long)a.py * h, (float2*)nullptr, h, 0, fz, twz, a.desc,
-                       0LL);
+                       0LL, GX, a.py, a.nq);
   });
   return hipGetLastError();
 }
@@ -767,7 +798,8 @@ hipError_t imf_launch_inverse(const imf_inv_args& a, const imf_fft_len& fx,
     const size_t sm = smem_bytes(fz.n, CT);
     auto k = k_inv_z_product<CT, MAXE, NT>;
     if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k, dim3((h + CT - 1) / CT, a.py, 1), dim3(IMF_WG), sm, s, a, fz, twz);
+    const int GX = (h + CT - 1) / CT;
+    hipLaunchKernelGGL(k, dim3(xcd_grid(GX, a.py, 1)), dim3(IMF_WG), sm, s, a, fz, twz, GX, a.py);
   });
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (stage < 0 || stage == 1) DISPATCH(fy.n, {
@@ -776,8 +808,9 @@ hipError_t imf_launch_inverse(const imf_inv_args& a, const imf_fft_len& fx,
     const size_t sm = smem_bytes(fy.n, CT);
     auto k = k_pass_strided<CT, MAXE, NT, PASS_INV_Y>;
     if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k, dim3((h + CT - 1) / CT, a.max_mz, a.nq), dim3(IMF_WG), sm, s, io, fy,
-                       twy, a.desc, 0, a.py, 0, 1);
+    const int GX = (h + CT - 1) / CT;
+    hipLaunchKernelGGL(k, dim3(xcd_grid(GX, a.max_mz, a.nq)), dim3(IMF_WG), sm, s, io, fy, twy,
+                       a.desc, 0, a.py, 0, 1, GX, a.max_mz, a.nq);
   });
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (stage < 0 || stage == 2) DISPATCH(fx.n, {
@@ -800,8 +833,9 @@ hipError_t imf_launch_columns(const float2* in, float2* out, int ncols, long lon
     const size_t sm = smem_bytes(L.n, CT);
     auto k = k_pass_strided<CT, MAXE, NT, PASS_DESIGN_Y>;
     if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k, dim3((ncols + CT - 1) / CT, 1, 1), dim3(IMF_WG), sm, s, io, L, tw,
-                       (const imf_orient_desc*)nullptr, 1, L.n, L.n, inverse);
+    const int GX = (ncols + CT - 1) / CT;
+    hipLaunchKernelGGL(k, dim3(xcd_grid(GX, 1, 1)), dim3(IMF_WG), sm, s, io, L, tw,
+                       (const imf_orient_desc*)nullptr, 1, L.n, L.n, inverse, GX, 1, 1);
   });
   return hipGetLastError();
 }
