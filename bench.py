@@ -147,6 +147,10 @@ def main():
     ms = 1000 * el / args.steps
     value = N * nR / (el / args.steps)
     log("timed: %.2f ms/step, %.3e voxel-orientations/s" % (ms, value))
+    if stats[-1].bound_blocks:
+        log("bound: %d of %d (block, orientation) pairs skipped (%.1f%%)" % (
+            stats[-1].bound_skipped, stats[-1].bound_blocks,
+            100.0 * stats[-1].bound_skipped / stats[-1].bound_blocks))
 
     # per kernel class over the timed steps
     kms, kn, kb, ko = {}, {}, {}, {}
@@ -221,6 +225,8 @@ def main():
         "kernels": kernels,
         "guard": {"F_max": last.F_max, "max_frac_err": last.max_frac_err,
                   "flags": last.guard_flags},
+        "bound": {"blocks": last.bound_blocks, "skipped": last.bound_skipped,
+                  "frac": (last.bound_skipped / last.bound_blocks) if last.bound_blocks else None},
         "stream_copy_GBps": copy_gbs,
         "model_bytes_per_step": last.model_bytes,
         "model_GBps": last.model_bytes / (ms * 1e-3) / 1e9,

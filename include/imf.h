@@ -84,6 +84,7 @@ enum { IMF_METHOD_AUTO = 0, IMF_METHOD_FFT = 1, IMF_METHOD_DIRECT = 2 };
 #define IMF_FLAG_MASK_SWEEP 2u   /* masks by sweeping D^c with the cutter (bit rows) */
 #define IMF_FLAG_NO_CACHE 4u     /* do not keep tool spectra */
 #define IMF_FLAG_PROFILE 8u      /* time every kernel class with events (k_ms, k_n) */
+#define IMF_FLAG_NO_BOUND 16u    /* no branch and bound in the sharp-point minimum */
 
 typedef struct {
   int ndim, nx, ny, nz;
@@ -137,6 +138,8 @@ typedef struct {
   int k_n[16];
   double k_bytes[16];    /* algorithmic bytes of each class (compulsory reads + writes) */
   double k_ops[16];      /* class 11: window-minimum lookups (gathered floats) */
+  long long bound_blocks;  /* (block, orientation) pairs of the sharp-point minimum */
+  long long bound_skipped; /* of those, skipped by the lower bound (exact) */
 } imf_stats;
 
 /* Bytes of device workspace the request needs (admission control). */

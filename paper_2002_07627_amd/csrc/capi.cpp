@@ -175,6 +175,9 @@ struct imf_ctx {
   size_t inflight_bytes = 0;
   int max_inflight = 4;
   int n_running = 0;
+  int mf_shape = 2;  // wave block shape of the sharp-point minimum (imf_block_dims)
+  int n_cu = 256;     // compute units of the device
+  int mf_wg_per_cu = 4;  // resident workgroups per CU of the sharp-point minimum (list pass)
 };
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -241,6 +244,10 @@ extern "C" imf_status imf_create(int device, size_t hbm_budget_bytes, imf_ctx** 
   imf_ctx* c = new imf_ctx();
   c->device = device;
   c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)fr);
+  if (const char* e = std::getenv("IMF_MINFILTER_SHAPE")) c->mf_shape = std::atoi(e) & 3;
+  c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  if (const char* e = std::getenv("IMF_MINFILTER_WG_PER_CU"))
+    c->mf_wg_per_cu = std::max(1, std::min(16, std::atoi(e)));
   if (hipStreamCreateWithFlags(&c->internal, hipStreamNonBlocking) != hipSuccess) {
     delete c;
     return fail(IMF_EDEVICE, "stream creation failed");
@@ -517,6 +524,8 @@ static imf_status ensure_rasters(imf_ctx* c, const imf_request* r, const std::ve
 // ---------------------------------------------------------------------------
 // planning
 // ---------------------------------------------------------------------------
+static const int kFpCap = 16384;  // footprint cells per orientation
+
 struct Plan {
   int nd, n[3];
   long long N;
@@ -534,7 +543,9 @@ struct Plan {
   long long max_vol;
   int max_t[3];
   int nlvl;
-  bool theta_known, two_phase, masks, sweep, cache;
+  bool theta_known, two_phase, masks, sweep, cache, bnb;
+  int shape;
+  long long cell_stride, nblocks, cell_waves, nwords_blk;
   double theta;
   double band;
   // workspace layout (bytes)
@@ -667,6 +678,29 @@ static imf_status make_plan(imf_ctx* c, const imf_request* r, const imf_outputs*
     const double lg = std::log2((double)p.P[0] * p.P[1] * p.P[2]);
     p.band = 2.0 * u * lg * std::sqrt((double)p.N * (double)maxT);
   }
+  // branch and bound for the sharp-point minimum (not in the plain comparator)
+  p.bnb = !plain && !(r->flags & IMF_FLAG_NO_BOUND);
+  p.shape = p.nd == 2 ? 0 : c->mf_shape;
+  {
+    int wx, wy, wz;
+    imf_block_dims(p.shape, wx, wy, wz);
+    const long long nbx = (r->nx + wx - 1) / wx, nby = (r->ny + wy - 1) / wy,
+                    nbz = (r->nz + wz - 1) / wz;
+    p.nblocks = nbx * nby * nbz;
+    p.nwords_blk = (imf_block_logical(p.shape, r->nx, r->ny, r->nz) + 63) / 64;
+    // work lists hold packed block coordinates
+    if (nbx >= 1024 || nby >= 2048 || nbz >= 2048) p.bnb = false;
+    p.cell_stride = 1;
+    p.cell_waves = 1;
+    for (int q = 0; q < p.nO; q++) {
+      const imf_orient_desc& d = p.desc[q];
+      const long long cdx = (d.box_dim[0] + wx - 1) / wx + 1;
+      const long long cdy = (d.box_dim[1] + wy - 1) / wy + 1;
+      const long long cdz = (d.box_dim[2] + wz - 1) / wz + 1;
+      p.cell_stride = std::max(p.cell_stride, cdx * cdy * cdz);
+      p.cell_waves = std::max(p.cell_waves, (cdx * wx + 63) / 64 * cdy * ((cdz + 7) / 8));
+    }
+  }
   const int h = p.P[0] / 2 + 1;
   p.spec_elems = (long long)p.P[1] * h * p.P[2];
   // workspace
@@ -684,6 +718,15 @@ static imf_status make_plan(imf_ctx* c, const imf_request* r, const imf_outputs*
   add(sizeof(float) * p.B * p.max_vol);                // g
   add(sizeof(float) * p.B * std::max(p.nlvl, 1) * p.max_vol);  // levels
   if (p.two_phase) add(sizeof(float) * N * p.nO);      // gamma stack
+  if (p.bnb) {
+    add(sizeof(float) * p.B * p.cell_stride);           // cell minima
+    add(sizeof(int) * p.B * (long long)(kFpCap + 1));   // footprints
+    add(sizeof(float) * p.nblocks);                     // block maxima of f
+    add(sizeof(int) * p.B * p.nblocks);                 // work lists
+    add(sizeof(int) * p.B);                             // list lengths
+    add(sizeof(uint64_t) * p.B * p.nwords_blk);         // kept-block bits
+    add(sizeof(int) * p.B * p.nwords_blk);              // list offsets
+  }
   if (p.sweep) add(sizeof(uint64_t) * p.B * ((p.max_m[0] + 63) / 64) * (long long)p.max_m[1] * p.max_m[2]);
   if (p.method == IMF_METHOD_FFT) {
     add(sizeof(float2) * p.spec_elems);                                  // rho_hat
@@ -864,6 +907,13 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
   float* g = carve<float>(ar, p.B * p.max_vol);
   float* lvl = carve<float>(ar, (size_t)p.B * std::max(p.nlvl, 1) * p.max_vol);
   float* gstack = p.two_phase ? carve<float>(ar, (size_t)N * p.nO) : nullptr;
+  float* cellmin = p.bnb ? carve<float>(ar, p.B * p.cell_stride) : nullptr;
+  int* fpbuf = p.bnb ? carve<int>(ar, p.B * (long long)(kFpCap + 1)) : nullptr;
+  float* fblock = p.bnb ? carve<float>(ar, p.nblocks) : nullptr;
+  int* wlist = p.bnb ? carve<int>(ar, p.B * p.nblocks) : nullptr;
+  int* wcount = p.bnb ? carve<int>(ar, p.B) : nullptr;
+  unsigned long long* wmask = p.bnb ? carve<unsigned long long>(ar, p.B * p.nwords_blk) : nullptr;
+  int* woff = p.bnb ? carve<int>(ar, p.B * p.nwords_blk) : nullptr;
   const long long dc_stride = ((p.max_m[0] + 63) / 64) * (long long)p.max_m[1] * p.max_m[2];
   uint64_t* dc = p.sweep ? carve<uint64_t>(ar, p.B * dc_stride) : nullptr;
   float2 *rho_hat = nullptr, *fw1 = nullptr, *fw2 = nullptr, *tw1 = nullptr, *tw2 = nullptr,
@@ -942,6 +992,16 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
   HIPCHK(hipMemsetAsync(flag_cnt, 0, sizeof(int) * (nb + 1), s));
   HIPCHK(imf_launch_omega0(r->fixture, r->domain, om, N, s));
   HIPCHK(imf_launch_fill_f(f, N, INFINITY, s));
+  if (fblock) HIPCHK(imf_launch_fill_f(fblock, p.nblocks, INFINITY, s));
+  // the minimum pass writes the mask chunks of the blocks it computes: clear
+  // the rest (skipped blocks, and the bits past nx of each row)
+  if (p.masks && p.theta_known && !p.sweep)
+    HIPCHK(imf_launch_fill_u32((unsigned*)out->acc_masks,
+                               2LL * p.nO * r->nz * r->ny * ((r->nx + 63) / 64), 0u, s));
+  if (p.bnb) {
+    // skipped blocks leave gamma = +inf behind
+    if (gstack) HIPCHK(imf_launch_fill_f(gstack, (long long)N * p.nO, INFINITY, s));
+  }
   HIPCHK(imf_launch_prefix_x(r->design, r->design_is_density, r->fixture, r->nx, r->ny, r->nz, ps,
                              s));
   tm.mark(1);
@@ -1074,6 +1134,27 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
     ma.mask_q0 = q0;
     ma.gamma_stack = gstack;
     ma.gamma_q0 = q0;
+    ma.bnb = p.bnb;
+    ma.shape = p.shape;
+    ma.cellmin = cellmin;
+    ma.cell_stride = p.cell_stride;
+    ma.cell_waves = p.cell_waves;
+    ma.fp = fpbuf;
+    ma.fp_cap = kFpCap;
+    ma.fblock = fblock;
+    ma.list = wlist;
+    ma.list_stride = p.nblocks;
+    ma.count = wcount;
+    ma.wmask = wmask;
+    ma.woff = woff;
+    ma.wstride = p.nwords_blk;
+    ma.fmax_up = gstack ? misc + 4 : nullptr;
+    ma.theta_lambda = r->lambda;
+    ma.theta_known = p.theta_known;
+    ma.q0 = q0;
+    ma.n_cu = c->n_cu;
+    ma.wg_per_cu = c->mf_wg_per_cu;
+    ma.skipped = (unsigned long long*)(misc + 8);
     HIPCHK(imf_launch_minfilter(ma, s, 0));
     tm.mark(10);
     HIPCHK(imf_launch_minfilter(ma, s, 1));
@@ -1096,8 +1177,8 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
                                (out->secluded ? 1 : 0)) +
                   (p.two_phase ? (4.0 * N + N / 8.0) * p.nO : 0.0);
   pd.host = ar.host;
-  HIPCHK(hipMemcpyAsync(pd.host, misc, 2 * sizeof(unsigned int), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(pd.host + 2, flag_cnt, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(pd.host, misc, 16 * sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(pd.host + 16, flag_cnt, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
   if (out->debug_overlap) {
     const imf_orient_desc& d = p.desc[out->debug_orient];
     for (int a = 0; a < 3; a++) {
@@ -1118,7 +1199,7 @@ static imf_status compute_finish(Pending& pd, imf_stats* st) {
   const Plan& p = pd.p;
   long long total_flags = 0;
   for (int b = 0; b < pd.nb; b++) {
-    const int n = (int)pd.host[2 + b];
+    const int n = (int)pd.host[16 + b];
     if (n > pd.flag_cap) {
       pd.tm.release();
       return fail(IMF_EACCURACY, "guard band of batch %d flagged %d overlaps (capacity %d)", b, n,
@@ -1139,6 +1220,12 @@ static imf_status compute_finish(Pending& pd, imf_stats* st) {
     std::memcpy(&me, &pd.host[1], 4);
     st->max_frac_err = me;
     st->guard_flags = total_flags;
+    if (p.bnb) {
+      unsigned long long sk;
+      std::memcpy(&sk, &pd.host[8], 8);
+      st->bound_skipped = (long long)sk;
+      st->bound_blocks = p.nblocks * p.nO;
+    }
     st->guard_band = p.band;
     pd.tm.collect(st);
     if (pd.tm.fine)

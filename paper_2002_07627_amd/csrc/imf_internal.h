@@ -159,9 +159,37 @@ struct imf_min_args {
   const uint8_t* omega0;    // [nz][ny][nx]
   int masks_on; double theta; uint64_t* masks; int mask_q0;  // masks for orientations mask_q0 + q
   float* gamma_stack; int gamma_q0;   // optional
+  // branch and bound: the output is cut into blocks of the wave shape; for
+  // every orientation a lower bound of gamma over a block is the minimum of g
+  // over the coarse cells (same shape, aligned to the query box) that cover
+  // block - S.  Blocks whose bound is >= their maximum of f, and above the
+  // mask threshold bound, cannot change f or set a mask bit and are skipped.
+  int bnb;                  // 0: plain, 1: branch and bound
+  int shape;                // wave block: 0 = 64x1x1, 1 = 32x2x1, 2 = 16x2x2, 3 = 16x4x1
+  float* cellmin; long long cell_stride;   // per q: [cdz][cdy][cdx]
+  long long cell_waves;                    // waves of the cell-minimum pass (largest box)
+  int* fp; int fp_cap;                     // per q: [0] count, then cell-index offsets
+  float* fblock;            // max of f per block (+inf before the first orientation)
+  int* list; long long list_stride;  // per q: blocks left to compute, packed
+                                     // bx | by << 10 | bz << 21
+  int* count;               // per q: length of that list
+  unsigned long long* wmask; int* woff; long long wstride;  // per q and 64 logical blocks:
+                            // kept-block bits of the bound pass, exclusive list offsets
+  unsigned int* fmax_up;    // two-phase: max of f over all voxels at the start of the batch
+                            // (order-preserving bits; lambda times it bounds the threshold)
+  double theta_lambda;      // lambda of the threshold bound lambda * fmax_up
+  int theta_known;
+  int q0;                   // global index of the batch's first orientation
+  int n_cu, wg_per_cu;      // resident workgroups of the list pass: CUs x per CU
+  unsigned long long* skipped;  // statistics: skipped (block, orientation) pairs
 };
-// stage: -1 all, 0 sparse-table levels, 1 the minimum filter
+// stage: -1 all, 0 sparse-table levels (and cell minima / footprints with
+// branch and bound), 1 the minimum filter
 hipError_t imf_launch_minfilter(const imf_min_args& a, hipStream_t s, int stage = -1);
+// blocks of the output for a wave shape
+void imf_block_dims(int shape, int& wx, int& wy, int& wz);
+// logical block indices of the minimum pass (blocks and brick padding)
+long long imf_block_logical(int shape, int nx, int ny, int nz);
 
 // sweep route: A = Omega_0 and (D^c dilated by S) with D^c = {g <= theta}
 struct imf_sweep_args {
@@ -175,6 +203,7 @@ hipError_t imf_launch_sweep(const imf_sweep_args& a, hipStream_t s);
 
 // finalize
 hipError_t imf_launch_fill_f(float* f, long long n, float v, hipStream_t s);
+hipError_t imf_launch_fill_u32(unsigned int* p, long long n, unsigned int v, hipStream_t s);
 hipError_t imf_launch_omega0(const uint8_t* fixture, const uint8_t* domain, uint8_t* omega0,
                              long long n, hipStream_t s);
 hipError_t imf_launch_fmax(const float* f, const uint8_t* omega0, long long n,

@@ -249,69 +249,344 @@ __global__ void __launch_bounds__(IMF_WG) k_levels(const imf_orient_desc* __rest
 
 __device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }
 
-// Sharp-point minimum of ONE orientation (Eq. imf_2): one wave per 64
-// consecutive x of a row; f is updated in place (one orientation per launch,
-// so every voxel has a single writer).  The runs are turned into box-index
-// offsets in LDS once per workgroup, and the run loop is unrolled so that 16
-// independent gathers are in flight per wave.
-#define MF_LDS_RUNS 1024
-#define MF_BY 16
-#define MF_BZ 16
-// Wave -> output mapping.  The hardware hands workgroups to the 8 XCDs round
-// robin, so workgroup b runs on XCD b % 8.  Each XCD is given a contiguous range
-// of bricks (one 64-wide x chunk by MF_BY rows by MF_BZ planes, y fastest), so
-// the waves resident on one XCD cover a compact region and share its L2.
-__device__ __forceinline__ bool mf_map(int nx, int ny, int nz, int& w, int& y, int& z) {
-  const int words = (nx + 63) >> 6;
-  const int nby = (ny + MF_BY - 1) / MF_BY, nbz = (nz + MF_BZ - 1) / MF_BZ;
-  const long long nbricks = (long long)words * nby * nbz;
-  const int wg_per_brick = MF_BY * MF_BZ / (IMF_WG / 64);
-  const long long nwg = nbricks * wg_per_brick;
-  const long long per_xcd = (nwg + 7) / 8;
-  const long long b = blockIdx.x;
-  const long long lg = (b % 8) * per_xcd + b / 8;
-  if (lg >= nwg) return false;
-  const long long brick = lg / wg_per_brick;
-  const int wib = (int)(lg % wg_per_brick) * (IMF_WG / 64) + (threadIdx.x >> 6);
-  const int yb = (int)(brick % nby);
-  const long long r = brick / nby;
-  const int zb = (int)(r % nbz);
-  w = (int)(r / nbz);
-  y = yb * MF_BY + wib % MF_BY;
-  z = zb * MF_BZ + wib / MF_BY;
-  return y < ny && z < nz;
+void imf_block_dims(int shape, int& wx, int& wy, int& wz) {
+  switch (shape) {
+    case 1: wx = 32; wy = 2; wz = 1; break;
+    case 2: wx = 16; wy = 2; wz = 2; break;
+    case 3: wx = 16; wy = 4; wz = 1; break;
+    default: wx = 64; wy = 1; wz = 1; break;
+  }
 }
 
-__global__ void __launch_bounds__(IMF_WG) k_minfilter(imf_min_args a, int qi) {
-  __shared__ int4 rr[MF_LDS_RUNS];
+__device__ __forceinline__ float wave_min_f(float v) {
+  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// branch and bound, part 1: footprints and cell minima
+// ---------------------------------------------------------------------------
+// Footprint of one orientation: the offsets (in cells of the block shape) of
+// every cell that meets block - S, the same for every block because blocks and
+// cells are aligned (t - box_lo = W b + i + e with e = kmax - k >= 0, so the
+// cell is b + floor((i + e) / W), i in [0, W)).  One workgroup per orientation.
+#define FP_BITS 65536
+__global__ void __launch_bounds__(IMF_WG) k_footprint(const imf_orient_desc* __restrict__ desc,
+                                                      int nx, int ny, int nz, int WX, int WY,
+                                                      int WZ, int* __restrict__ fp, int fp_cap) {
+  __shared__ unsigned int bm[FP_BITS / 32];
+  __shared__ int cnt;
+  const int q = blockIdx.x;
+  const imf_orient_desc& d = desc[q];
+  int* out = fp + (long long)q * (fp_cap + 1);
+  const int n[3] = {nx, ny, nz};
+  const int W[3] = {WX, WY, WZ};
+  int kmax[3], fd[3], cd[3];
+  for (int a = 0; a < 3; a++) {
+    kmax[a] = -d.box_lo[a];
+    const int E = d.box_dim[a] - n[a] + 1;  // extent of S
+    fd[a] = (E - 1 + W[a] - 1) / W[a] + 1;
+    cd[a] = (d.box_dim[a] + W[a] - 1) / W[a] + 1;  // one spare cell: padded blocks
+  }
+  const long long nbits = (long long)fd[0] * fd[1] * fd[2];
+  if (nbits > FP_BITS) {  // no bound for this orientation: nothing is skipped
+    if (threadIdx.x == 0) out[0] = -1;
+    return;
+  }
+  for (int i = threadIdx.x; i < FP_BITS / 32; i += IMF_WG) bm[i] = 0;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  const int ax = d.s_axis;
+  for (int r = threadIdx.x; r < d.n_sruns; r += IMF_WG) {
+    const imf_run u = d.sruns[r];
+    for (int j = 0; j < u.len; j++) {
+      int k[3] = {u.x, u.y, u.z};
+      k[ax] += j;
+      int lo[3], hi[3];
+      for (int a = 0; a < 3; a++) {
+        const int e = kmax[a] - k[a];
+        lo[a] = e / W[a];
+        hi[a] = (e + W[a] - 1) / W[a];
+      }
+      for (int dz = lo[2]; dz <= hi[2]; dz++)
+        for (int dy = lo[1]; dy <= hi[1]; dy++)
+          for (int dx = lo[0]; dx <= hi[0]; dx++) {
+            const int b = (dz * fd[1] + dy) * fd[0] + dx;
+            atomicOr(&bm[b >> 5], 1u << (b & 31));
+          }
+    }
+  }
+  __syncthreads();
+  for (int wi = threadIdx.x; wi < (int)((nbits + 31) / 32); wi += IMF_WG) {
+    unsigned int m = bm[wi];
+    while (m) {
+      const int bit = __ffs(m) - 1;
+      m &= m - 1;
+      const int b = wi * 32 + bit;
+      const int dx = b % fd[0], dy = (b / fd[0]) % fd[1], dz = b / (fd[0] * fd[1]);
+      const int slot = atomicAdd(&cnt, 1);
+      if (slot < fp_cap) out[1 + slot] = (dz * cd[1] + dy) * cd[0] + dx;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) out[0] = cnt <= fp_cap ? cnt : -1;
+}
+
+// minimum of g over each cell of the block shape (cells aligned to the box).
+// One wave per (64-x segment, cell row cy, CM_CZ cell planes): lanes read
+// consecutive x, reduce in groups of WX lanes and combine the WY x WZ rows of a
+// cell.
+#define CM_CZ 8
+__global__ void __launch_bounds__(IMF_WG) k_cellmin(const imf_orient_desc* __restrict__ desc,
+                                                    const float* __restrict__ g,
+                                                    long long g_stride, int WX, int WY, int WZ,
+                                                    float* __restrict__ cellmin,
+                                                    long long cell_stride) {
+  const int q = blockIdx.y;
+  const imf_orient_desc& d = desc[q];
+  const int mx = d.box_dim[0], my = d.box_dim[1], mz = d.box_dim[2];
+  // one spare cell per axis (all +inf) for blocks that pad past the grid
+  const int cdx = (mx + WX - 1) / WX + 1, cdy = (my + WY - 1) / WY + 1;
+  const int cdz = (mz + WZ - 1) / WZ + 1;
+  const int lane = threadIdx.x & 63;
+  const int segs = (cdx * WX + 63) / 64;
+  const int czc = (cdz + CM_CZ - 1) / CM_CZ;
+  const long long wave = (long long)blockIdx.x * (IMF_WG / 64) + (threadIdx.x >> 6);
+  if (wave >= (long long)segs * cdy * czc) return;
+  const int sg = (int)(wave % segs);
+  const long long rc = wave / segs;
+  const int cy = (int)(rc % cdy), cz0 = (int)(rc / cdy) * CM_CZ;
+  const int x = sg * 64 + lane;
+  const int cx = x / WX;
+  const float* gq = g + q * g_stride;
+  float* out = cellmin + q * cell_stride;
+  const int y0 = cy * WY, y1 = min(y0 + WY, my);
+  for (int cz = cz0; cz < min(cz0 + CM_CZ, cdz); cz++) {
+    float m = INFINITY;
+    for (int z = cz * WZ; z < min(cz * WZ + WZ, mz); z++)
+      for (int y = y0; y < y1; y++)
+        if (x < mx) m = fminf(m, gq[((long long)z * my + y) * mx + x]);
+    for (int o = 1; o < WX; o <<= 1) m = fminf(m, __shfl_xor(m, o));
+    if ((lane % WX) == 0 && cx < cdx) out[((long long)cz * cdy + cy) * cdx + cx] = m;
+  }
+}
+
+__global__ void k_fill(float* f, long long n, float v) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    f[i] = v;
+}
+__global__ void k_fill_u32(unsigned int* p, long long n, unsigned int v) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+// ---------------------------------------------------------------------------
+// Sharp-point minimum of ONE orientation (Eq. imf_2).  The output is cut into
+// blocks of WX x WY x WZ voxels, one wave per block; f is updated in place (one
+// orientation per launch, so every voxel has a single writer).
+//
+// Logical block order: bricks of 64 x 16 x 16 voxels (x chunk slowest, then z,
+// y fastest), blocks inside a brick x, y, z.  Consecutive logical indices are
+// close in space, so the waves one XCD runs at a time read overlapping windows
+// of g and its levels from that XCD's L2.
+// ---------------------------------------------------------------------------
+#define MF_LDS_RUNS 1024
+
+struct mf_geom {
+  int WX, WY, WZ;
+  int nbx, nby, nbz;      // blocks per axis
+  int brx, bry, brz;      // blocks per brick and axis
+  int nry, nrz;           // bricks along y, z
+  long long nlog;         // logical indices (bricks x blocks per brick)
+  __host__ __device__ mf_geom(int wx, int wy, int wz, int nx, int ny, int nz)
+      : WX(wx), WY(wy), WZ(wz) {
+    nbx = (nx + wx - 1) / wx;
+    nby = (ny + wy - 1) / wy;
+    nbz = (nz + wz - 1) / wz;
+    brx = 64 / wx;
+    bry = 16 / wy < nby ? 16 / wy : nby;
+    brz = 16 / wz < nbz ? 16 / wz : nbz;
+    const int nrx = (nbx + brx - 1) / brx;
+    nry = (nby + bry - 1) / bry;
+    nrz = (nbz + brz - 1) / brz;
+    nlog = (long long)nrx * nry * nrz * brx * bry * brz;
+  }
+  // logical index -> block (false for the padding of partial bricks)
+  __device__ __forceinline__ bool block(long long lg, int& bx, int& by, int& bz) const {
+    const int br = brx * bry * brz;
+    const long long brick = lg / br;
+    const int wib = (int)(lg - brick * br);
+    const int ry = (int)(brick % nry);
+    const long long r = brick / nry;
+    const int rz = (int)(r % nrz);
+    const int rx = (int)(r / nrz);
+    bx = rx * brx + wib % brx;
+    by = ry * bry + (wib / brx) % bry;
+    bz = rz * brz + wib / (brx * bry);
+    return bx < nbx && by < nby && bz < nbz;
+  }
+};
+
+template <int WX>
+__device__ __forceinline__ void mf_store_chunk(uint64_t* row_words, int bx, uint64_t chunk) {
+  if (WX == 64) row_words[bx] = chunk;
+  else if (WX == 32) ((uint32_t*)row_words)[bx] = (uint32_t)chunk;
+  else ((uint16_t*)row_words)[bx] = (uint16_t)chunk;
+}
+
+// max over the block maxima of f (an upper bound of F_max: the threshold
+// lambda F_max of two-phase masks is at most lambda times this)
+__global__ void __launch_bounds__(IMF_WG) k_blockmax(const float* __restrict__ fb, long long n,
+                                                     unsigned int* __restrict__ out) {
+  __shared__ float red[IMF_WG / 64];
+  float m = -INFINITY;
+  for (long long i = (long long)blockIdx.x * IMF_WG + threadIdx.x; i < n;
+       i += (long long)gridDim.x * IMF_WG)
+    m = fmaxf(m, fb[i]);
+  m = wave_max_f(m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < IMF_WG / 64; i++) m = fmaxf(m, red[i]);
+    atomicMax(out, f2ord(m));
+  }
+}
+
+// Branch and bound, part 2: lower bound of gamma over every block of one
+// orientation (the minimum of the cell minima over the footprint), the skip
+// decision and the compacted list of the blocks left to compute.  One thread
+// per logical block; the footprint offsets are the same for every block and
+// are staged in LDS, so neighbouring lanes read neighbouring cells.  A block is
+// skipped when its bound is >= its maximum of f (f cannot decrease) and, when
+// masks are produced, above the bound on the mask threshold (no mask bit).
+#define BND_CHUNK 2048
+template <int WX, int WY, int WZ>
+__global__ void __launch_bounds__(IMF_WG) k_bound(imf_min_args a, int qi) {
+  __shared__ int fpl[BND_CHUNK];
+  const mf_geom G(WX, WY, WZ, a.nx, a.ny, a.nz);
   const imf_orient_desc& d = a.desc[qi];
+  const int* fpg = a.fp + (long long)qi * (a.fp_cap + 1);
+  const int nfp = fpg[0];
+  const long long lg = (long long)blockIdx.x * IMF_WG + threadIdx.x;
+  int bx = 0, by = 0, bz = 0;
+  const bool live = lg < G.nlog && G.block(lg, bx, by, bz);
+  const int cdx = (d.box_dim[0] + WX - 1) / WX + 1, cdy = (d.box_dim[1] + WY - 1) / WY + 1;
+  const long long cb = ((long long)bz * cdy + by) * cdx + bx;
+  const float* cm = a.cellmin + qi * a.cell_stride;
+  float lb = nfp < 0 ? -INFINITY : INFINITY;  // no footprint: no bound
+  for (int c0 = 0; c0 < nfp; c0 += BND_CHUNK) {
+    const int n = min(BND_CHUNK, nfp - c0);
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += IMF_WG) fpl[i] = fpg[1 + c0 + i];
+    __syncthreads();
+    if (live)
+      for (int i = 0; i < n; i++) lb = fminf(lb, cm[cb + fpl[i]]);
+  }
+  const long long blk = ((long long)bz * G.nby + by) * G.nbx + bx;
+  const float fb = live ? a.fblock[blk] : -INFINITY;
+  const bool need_mask = a.masks_on || a.gamma_stack;
+  double thu = a.theta;
+  if (need_mask && !a.theta_known) thu = a.theta_lambda * (double)ord2f(*a.fmax_up);
+  const bool sk = live && lb >= fb && (!need_mask || (double)lb > thu);
+  const unsigned long long mw = __ballot(live && !sk);
+  if ((threadIdx.x & 63) == 0 && lg < G.nlog) a.wmask[(long long)qi * a.wstride + (lg >> 6)] = mw;
+}
+
+// Branch and bound, part 3: order-preserving compaction of the blocks left to
+// compute.  One workgroup scans the per-wave counts of the bound pass
+// (exclusive offsets and the total); the scatter pass then writes each kept
+// block at its offset, so the list keeps the logical (spatially coherent)
+// order that the minimum pass relies on for L2 reuse.
+__global__ void __launch_bounds__(1024) k_scan_masks(imf_min_args a, int qi, int nw) {
+  __shared__ int wsum[16];
+  __shared__ int carry;
+  const unsigned long long* m = a.wmask + (long long)qi * a.wstride;
+  int* off = a.woff + (long long)qi * a.wstride;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int c0 = 0; c0 < nw; c0 += 4096) {
+    int v[4], t = 0;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const int i = c0 + threadIdx.x * 4 + j;
+      v[j] = i < nw ? __popcll(m[i]) : 0;
+      t += v[j];
+    }
+    int x = t;  // inclusive scan over the wave
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    if (wv == 0) {
+      int w = lane < 16 ? wsum[lane] : 0;
+      for (int o = 1; o < 16; o <<= 1) {
+        const int y = __shfl_up(w, o);
+        if (lane >= o) w += y;
+      }
+      if (lane < 16) wsum[lane] = w;
+    }
+    __syncthreads();
+    int ex = carry + (wv > 0 ? wsum[wv - 1] : 0) + x - t;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const int i = c0 + threadIdx.x * 4 + j;
+      if (i < nw) off[i] = ex;
+      ex += v[j];
+    }
+    __syncthreads();
+    if (threadIdx.x == 1023) carry = ex;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.count[qi] = carry;
+}
+
+template <int WX, int WY, int WZ>
+__global__ void __launch_bounds__(IMF_WG) k_scatter(imf_min_args a, int qi) {
+  const mf_geom G(WX, WY, WZ, a.nx, a.ny, a.nz);
+  const long long lg = (long long)blockIdx.x * IMF_WG + threadIdx.x;
+  if (lg >= G.nlog) return;
+  const unsigned long long m = a.wmask[(long long)qi * a.wstride + (lg >> 6)];
+  const int lane = threadIdx.x & 63;
+  if (!((m >> lane) & 1ull)) return;
+  int bx, by, bz;
+  G.block(lg, bx, by, bz);
+  const int o = a.woff[(long long)qi * a.wstride + (lg >> 6)] + __popcll(m & ((1ull << lane) - 1));
+  // packed block coordinates (bx < 1024, by, bz < 2048)
+  a.list[(long long)qi * a.list_stride + o] =
+      (int)((unsigned)bx | ((unsigned)by << 10) | ((unsigned)bz << 21));
+}
+
+// The minimum over the sharp points for one block (one wave): gathers of the
+// sparse-table levels at the run offsets staged in LDS, 16 independent
+// gathers in flight per wave; then the running minimum f, the gamma stack, the
+// block maximum of f (branch and bound) and the mask chunk.
+template <int WX, int WY, int WZ>
+__device__ __forceinline__ void mf_block(const imf_min_args& a, const imf_orient_desc& d,
+                                         const int4* rr, int qi, int bx, int by, int bz,
+                                         long long blk) {
   const int nr = d.n_sruns;
   const int ax = d.s_axis;
   const long long sx = 1, sy = d.box_dim[0], sz = (long long)d.box_dim[0] * d.box_dim[1];
   const long long sa = ax == 0 ? sx : (ax == 1 ? sy : sz);
-  for (int r = threadIdx.x; r < nr && r < MF_LDS_RUNS; r += IMF_WG) {
-    const imf_run u = d.sruns[r];
-    const int sl = ilog2(u.len);
-    rr[r] = make_int4((int)(-(u.x * sx + u.y * sy + u.z * sz) - (long long)(u.len - 1) * sa), sl,
-                      (int)((long long)(u.len - (1 << sl)) * sa), 0);
-  }
-  __syncthreads();
-  const int words = (a.nx + 63) >> 6;
   const int lane = threadIdx.x & 63;
-  int w, y, z;
-  if (!mf_map(a.nx, a.ny, a.nz, w, y, z)) return;
-  const int x = w * 64 + lane;
-  const bool valid = x < a.nx;
+  const int lx = lane % WX, ly = (lane / WX) % WY, lz = lane / (WX * WY);
+  const int x = bx * WX + lx, y = by * WY + ly, z = bz * WZ + lz;
+  const bool valid = x < a.nx && y < a.ny && z < a.nz;
   const long long vi = ((long long)z * a.ny + y) * a.nx + x;
   const float* g = a.g + qi * a.g_stride;
   const float* lv = a.lvl + qi * a.lvl_stride - a.g_stride;  // level s at lv + s * g_stride
-  float gam = INFINITY;
+  const int nl = nr < MF_LDS_RUNS ? nr : MF_LDS_RUNS;
   // translation t = x - k; box index of t for k = 0 (invalid lanes read a
   // clamped in-box position and are discarded)
-  const int xc = valid ? x : a.nx - 1;
-  const long long base = (long long)(xc - d.box_lo[0]) + (long long)(y - d.box_lo[1]) * sy +
-                         (long long)(z - d.box_lo[2]) * sz;
-  const int nl = nr < MF_LDS_RUNS ? nr : MF_LDS_RUNS;
+  const int xc = x < a.nx ? x : a.nx - 1, yc = y < a.ny ? y : a.ny - 1;
+  const int zc = z < a.nz ? z : a.nz - 1;
+  const long long base = (long long)(xc - d.box_lo[0]) + (long long)(yc - d.box_lo[1]) * sy +
+                         (long long)(zc - d.box_lo[2]) * sz;
+  float gam = INFINITY;
   int r = 0;
   for (; r + 8 <= nl; r += 8) {
     float v[16];
@@ -339,23 +614,135 @@ __global__ void __launch_bounds__(IMF_WG) k_minfilter(imf_min_args a, int qi) {
     const long long p = base - (u.x * sx + u.y * sy + u.z * sz) - (long long)(u.len - 1) * sa;
     gam = fminf(gam, fminf(L[p], L[p + (long long)(u.len - (1 << sl)) * sa]));
   }
+  float fnew = -INFINITY;
   if (valid) {
     const float fo = a.f[vi];
+    fnew = fminf(fo, gam);
     if (gam < fo) a.f[vi] = gam;
     if (a.gamma_stack)
       a.gamma_stack[(long long)(a.gamma_q0 + qi) * a.nx * a.ny * a.nz + vi] = gam;
   }
+  if (a.bnb) {
+    fnew = wave_max_f(fnew);
+    if (lane == 0) a.fblock[blk] = fnew;
+  }
   if (a.masks_on) {
     const bool om = valid && a.omega0[vi];
     const unsigned long long bits = __ballot(om && (double)gam <= a.theta);
-    if (lane == 0)
-      a.masks[((long long)(a.mask_q0 + qi) * a.nz + z) * a.ny * words + (long long)y * words + w] =
-          bits;
+    if (lx == 0 && y < a.ny && z < a.nz) {
+      const int words = (a.nx + 63) >> 6;
+      const int row = ly + WY * lz;
+      uint64_t* row_words = a.masks + ((long long)(a.mask_q0 + qi) * a.nz + z) * a.ny * words +
+                            (long long)y * words;
+      mf_store_chunk<WX>(row_words, bx,
+                         WX == 64 ? bits : (bits >> (row * WX)) & ((1ull << WX) - 1));
+    }
   }
+}
+
+// runs of S as box-index offsets: x = offset of the run's far end for k = 0,
+// y = sparse-table level, z = offset of the second (overlapping) window
+__device__ __forceinline__ void mf_stage_runs(const imf_orient_desc& d, int4* rr) {
+  const int nr = d.n_sruns;
+  const int ax = d.s_axis;
+  const long long sx = 1, sy = d.box_dim[0], sz = (long long)d.box_dim[0] * d.box_dim[1];
+  const long long sa = ax == 0 ? sx : (ax == 1 ? sy : sz);
+  for (int r = threadIdx.x; r < nr && r < MF_LDS_RUNS; r += IMF_WG) {
+    const imf_run u = d.sruns[r];
+    const int sl = ilog2(u.len);
+    rr[r] = make_int4((int)(-(u.x * sx + u.y * sy + u.z * sz) - (long long)(u.len - 1) * sa), sl,
+                      (int)((long long)(u.len - (1 << sl)) * sa), 0);
+  }
+}
+
+// All blocks (no bound): one wave per block, 4 blocks per workgroup, runs
+// staged in LDS once per workgroup.  The logical blocks are cut into 8
+// contiguous ranges of workgroups, one per XCD: the hardware deals workgroups
+// to the XCDs round robin (workgroup b runs on XCD b % 8), so workgroup b takes
+// the (b / 8)-th group of 4 of range b % 8 and the blocks in flight on one XCD
+// stay a compact window that shares its L2.
+template <int WX, int WY, int WZ>
+__global__ void __launch_bounds__(IMF_WG) k_minfilter(imf_min_args a, int qi) {
+  __shared__ int4 rr[MF_LDS_RUNS];
+  const mf_geom G(WX, WY, WZ, a.nx, a.ny, a.nz);
+  const long long nwg = (G.nlog + 3) / 4;
+  const long long per = (nwg + 7) / 8;
+  const long long lg = (long long)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (lg >= nwg) return;  // uniform over the workgroup
+  const imf_orient_desc& d = a.desc[qi];
+  mf_stage_runs(d, rr);
+  __syncthreads();
+  int bx, by, bz;
+  if (!G.block(lg * 4 + (threadIdx.x >> 6), bx, by, bz)) return;
+  mf_block<WX, WY, WZ>(a, d, rr, qi, bx, by, bz, ((long long)bz * G.nby + by) * G.nbx + bx);
+}
+
+// Blocks left by the bound (compacted list in logical order): a resident grid
+// whose waves walk the list with a static schedule.  XCD x (workgroups x,
+// x + 8, ...) takes the x-th eighth of the list; inside it, its workgroups
+// take consecutive groups of 4 entries, then advance by the XCD's total.
+template <int WX, int WY, int WZ>
+__global__ void __launch_bounds__(IMF_WG) k_minfilter_list(imf_min_args a, int qi) {
+  __shared__ int4 rr[MF_LDS_RUNS];
+  const mf_geom G(WX, WY, WZ, a.nx, a.ny, a.nz);
+  const long long M = a.count[qi];
+  if (blockIdx.x == 0 && threadIdx.x == 0 && a.skipped)
+    atomicAdd(a.skipped, (unsigned long long)((long long)G.nbx * G.nby * G.nbz - M));
+  const imf_orient_desc& d = a.desc[qi];
+  mf_stage_runs(d, rr);
+  __syncthreads();
+  const int* list = a.list + (long long)qi * a.list_stride;
+  const long long per = (M + 7) / 8;
+  const long long lo = (long long)(blockIdx.x & 7) * per;
+  const long long hi = lo + per < M ? lo + per : M;
+  const long long step = (long long)(gridDim.x >> 3) * 4;
+  for (long long e = lo + (long long)(blockIdx.x >> 3) * 4 + (threadIdx.x >> 6); e < hi;
+       e += step) {
+    const unsigned int pk = (unsigned int)list[e];
+    const int bx = (int)(pk & 1023u), by = (int)((pk >> 10) & 2047u), bz = (int)(pk >> 21);
+    mf_block<WX, WY, WZ>(a, d, rr, qi, bx, by, bz, ((long long)bz * G.nby + by) * G.nbx + bx);
+  }
+}
+
+template <int WX, int WY, int WZ>
+static hipError_t launch_mf(const imf_min_args& a, hipStream_t s) {
+  const mf_geom G(WX, WY, WZ, a.nx, a.ny, a.nz);
+  const long long nwg = (G.nlog + 3) / 4;
+  const long long grid = (nwg + 7) / 8 * 8;
+  // the list pass: resident capacity (LDS-bound: 10 workgroups per CU), a
+  // multiple of 8 workgroups
+  long long lgrid = std::min((long long)a.n_cu * a.wg_per_cu, nwg);
+  lgrid = std::max(8LL, (lgrid + 7) / 8 * 8);
+  hipError_t e;
+  for (int q = 0; q < a.nq; q++) {
+    if (a.bnb) {
+      const unsigned gb = (unsigned)((G.nlog + IMF_WG - 1) / IMF_WG);
+      hipLaunchKernelGGL((k_bound<WX, WY, WZ>), dim3(gb), dim3(IMF_WG), 0, s, a, q);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      hipLaunchKernelGGL(k_scan_masks, dim3(1), dim3(1024), 0, s, a, q, (int)((G.nlog + 63) / 64));
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      hipLaunchKernelGGL((k_scatter<WX, WY, WZ>), dim3(gb), dim3(IMF_WG), 0, s, a, q);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      hipLaunchKernelGGL((k_minfilter_list<WX, WY, WZ>), dim3((unsigned)lgrid), dim3(IMF_WG), 0, s,
+                         a, q);
+    } else {
+      hipLaunchKernelGGL((k_minfilter<WX, WY, WZ>), dim3((unsigned)grid), dim3(IMF_WG), 0, s, a, q);
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+long long imf_block_logical(int shape, int nx, int ny, int nz) {
+  int wx, wy, wz;
+  imf_block_dims(shape, wx, wy, wz);
+  return mf_geom(wx, wy, wz, nx, ny, nz).nlog;
 }
 
 hipError_t imf_launch_minfilter(const imf_min_args& a, hipStream_t s, int stage) {
   hipError_t e;
+  int wx, wy, wz;
+  imf_block_dims(a.shape, wx, wy, wz);
   if ((stage < 0 || stage == 0) && a.nlvl > 0) {
     // one launch for all orientations of the batch; the grid covers the
     // largest line count (rows for x runs, x groups otherwise)
@@ -365,20 +752,37 @@ hipError_t imf_launch_minfilter(const imf_min_args& a, hipStream_t s, int stage)
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm)) !=
           hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_levels, dim3((unsigned)a.max_lines, 1, a.nq), dim3(IMF_WG), sm, s, a.desc, a.g, a.g_stride, a.lvl, a.lvl_stride, a.nlvl);
+    hipLaunchKernelGGL(k_levels, dim3((unsigned)a.max_lines, 1, a.nq), dim3(IMF_WG), sm, s,
+                       a.desc, a.g, a.g_stride, a.lvl, a.lvl_stride, a.nlvl);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if ((stage < 0 || stage == 0) && a.bnb) {
+    hipLaunchKernelGGL(k_footprint, dim3(a.nq), dim3(IMF_WG), 0, s, a.desc, a.nx, a.ny, a.nz, wx,
+                       wy, wz, a.fp, a.fp_cap);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // waves: (64-x segment, cell row, CM_CZ cell planes) over the largest box
+    const long long waves = a.cell_waves;
+    hipLaunchKernelGGL(k_cellmin, dim3((unsigned)((waves + 3) / 4), a.nq), dim3(IMF_WG), 0, s,
+                       a.desc, a.g, a.g_stride, wx, wy, wz, a.cellmin, a.cell_stride);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (a.fmax_up) {  // two-phase masks: bound of the threshold for this batch
+      const long long nb = (long long)((a.nx + wx - 1) / wx) * ((a.ny + wy - 1) / wy) *
+                           ((a.nz + wz - 1) / wz);
+      hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, a.fmax_up, 1LL, 0u);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      const long long wg = std::min(256LL, (nb + IMF_WG - 1) / IMF_WG);
+      hipLaunchKernelGGL(k_blockmax, dim3((unsigned)wg), dim3(IMF_WG), 0, s, a.fblock, nb,
+                         a.fmax_up);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
   }
   if (stage == 0) return hipSuccess;
-  const int words = (a.nx + 63) >> 6;
-  const long long nbricks = (long long)words * ((a.ny + MF_BY - 1) / MF_BY) *
-                            ((a.nz + MF_BZ - 1) / MF_BZ);
-  const long long nwg = nbricks * (MF_BY * MF_BZ / (IMF_WG / 64));
-  const long long grid = (nwg + 7) / 8 * 8;
-  for (int q = 0; q < a.nq; q++) {
-    hipLaunchKernelGGL(k_minfilter, dim3((unsigned)grid), dim3(IMF_WG), 0, s, a, q);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+  switch (a.shape) {
+    case 1: return launch_mf<32, 2, 1>(a, s);
+    case 2: return launch_mf<16, 2, 2>(a, s);
+    case 3: return launch_mf<16, 4, 1>(a, s);
+    default: return launch_mf<64, 1, 1>(a, s);
   }
-  return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------
@@ -475,12 +879,16 @@ hipError_t imf_launch_sweep(const imf_sweep_args& a, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // finalize
 // ---------------------------------------------------------------------------
-__global__ void k_fill(float* f, long long n, float v) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) f[i] = v;
+static unsigned fill_grid(long long n) {
+  const long long b = (n + 255) / 256;
+  return (unsigned)(b < 65536 ? (b > 0 ? b : 1) : 65536);
 }
 hipError_t imf_launch_fill_f(float* f, long long n, float v, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, f, n, v);
+  hipLaunchKernelGGL(k_fill, dim3(fill_grid(n)), dim3(256), 0, s, f, n, v);
+  return hipGetLastError();
+}
+hipError_t imf_launch_fill_u32(unsigned int* p, long long n, unsigned int v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u32, dim3(fill_grid(n)), dim3(256), 0, s, p, n, v);
   return hipGetLastError();
 }
 

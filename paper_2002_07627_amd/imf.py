@@ -19,7 +19,7 @@ TOOL_FLAT, TOOL_BALL, TOOL_RECT2D = 0, 1, 2
 DIR_F64, DIR_LATTICE = 0, 1
 SHARP_ALL, SHARP_BOUNDARY, SHARP_TIP = 0, 1, 2
 METHOD_AUTO, METHOD_FFT, METHOD_DIRECT = 0, 1, 2
-FLAG_PLAIN, FLAG_MASK_SWEEP, FLAG_NO_CACHE, FLAG_PROFILE = 1, 2, 4, 8
+FLAG_PLAIN, FLAG_MASK_SWEEP, FLAG_NO_CACHE, FLAG_PROFILE, FLAG_NO_BOUND = 1, 2, 4, 8, 16
 KERNEL_CLASSES = ("raster", "setup", "fwd_design", "tool_x", "tool_y", "tool_z",
                   "inv_z_product", "inv_y", "inv_x_c2r", "recheck", "levels", "minfilter",
                   "sweep", "finalize", "copies", "unused")
@@ -62,7 +62,8 @@ class _Stats(C.Structure):
                 ("n_orient", C.c_int), ("method", C.c_int), ("batch", C.c_int),
                 ("cache_hits", C.c_int), ("cache_misses", C.c_int),
                 ("k_ms", C.c_double * 16), ("k_n", C.c_int * 16),
-                ("k_bytes", C.c_double * 16), ("k_ops", C.c_double * 16)]
+                ("k_bytes", C.c_double * 16), ("k_ops", C.c_double * 16),
+                ("bound_blocks", C.c_longlong), ("bound_skipped", C.c_longlong)]
 
 
 @dataclass
@@ -83,6 +84,8 @@ class Stats:
     kernel_launches: dict
     kernel_bytes: dict
     kernel_ops: dict
+    bound_blocks: int
+    bound_skipped: int
 
     @classmethod
     def _from(cls, s: _Stats):
@@ -92,7 +95,7 @@ class Stats:
         ko = {k: s.k_ops[i] for i, k in enumerate(KERNEL_CLASSES) if s.k_n[i]}
         return cls(s.F_max, s.guard_flags, s.max_frac_err, s.guard_band, list(s.t_ms),
                    s.model_bytes, tuple(s.P), s.n_orient, s.method, s.batch, s.cache_hits,
-                   s.cache_misses, kms, kn, kb, ko)
+                   s.cache_misses, kms, kn, kb, ko, s.bound_blocks, s.bound_skipped)
 
 
 _lib = None

@@ -277,3 +277,45 @@ def test_empty_design_all_accessible(ctx):
     assert st.F_max == 0 and (host(out["imf"]) == 0).all()
     m = oracle.unpack_masks(masks_u64(out["masks"]), 22)
     assert m.all()
+
+
+# ---------------------------------------------------------------------------
+# branch and bound in the sharp-point minimum: every block shape, every mask
+# threshold mode, with and without the bound, against the oracle
+# ---------------------------------------------------------------------------
+_BND_REF = {}
+
+
+def _bound_case():
+    d = random_boxes((40, 48, 90), 24, 21, lo=6, hi=22)
+    fx = W.fixture_plate(d.shape, 3)
+    tl = W.tool(W.TOOL_BALL, 2, 8, 4, 6)
+    dirs = W.fib_hemisphere(16)
+    return d, fx, tl, dirs
+
+
+@pytest.mark.parametrize("mode", ["zero", "abs", "two_phase"])
+@pytest.mark.parametrize("shape", [0, 1, 2, 3])
+def test_bound_every_block_shape(shape, mode, monkeypatch):
+    import paper_2002_07627_amd as imf
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    d, fx, tl, dirs = _bound_case()
+    kw = {"zero": dict(lam=0.0), "abs": dict(lam=0.02, mask_theta_abs=6.0),
+          "two_phase": dict(lam=0.02)}[mode]
+    if mode not in _BND_REF:
+        _BND_REF[mode] = oracle.imf(oracle.Request(d, fx, tools=tl, dirs=dirs, dir_kind=0, **kw))
+    ref = _BND_REF[mode]
+    monkeypatch.setenv("IMF_MINFILTER_SHAPE", str(shape))
+    c = imf.Context(0)
+    try:
+        a, sa = c.compute(dev(d), dev(fx), tools=tl, dirs=dirs, method=imf.METHOD_FFT, **kw)
+        b, sb = c.compute(dev(d), dev(fx), tools=tl, dirs=dirs, method=imf.METHOD_FFT, **kw,
+                          flags=imf.FLAG_NO_BOUND)
+    finally:
+        c.close()
+    check_binary(a, ref)
+    for k in ("imf", "imf_norm", "secluded", "masks"):
+        assert torch.equal(a[k], b[k]), k
+    assert sa.bound_blocks > 0 and sb.bound_blocks == 0
+    assert 0 < sa.bound_skipped < sa.bound_blocks
