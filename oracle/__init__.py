@@ -63,8 +63,8 @@ def lib():
         L.or_raster.restype = C.c_longlong
         L.or_raster.argtypes = [C.c_int, C.POINTER(_Tool), C.c_int, C.c_void_p, C.c_int,
                                 C.c_void_p, C.c_void_p, C.c_longlong]
-        for name in ("or_imf", "or_overlap_at", "or_gamma_at", "or_overlap_full",
-                     "or_orient_info"):
+        for name in ("or_imf", "or_overlap_at", "or_gamma_at", "or_gamma_at_all",
+                     "or_overlap_full", "or_orient_info"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -226,6 +226,16 @@ def gamma_at(req: Request, orient: int, x) -> np.ndarray:
     st = lib().or_gamma_at(C.byref(req._c), orient, _ptr(x), C.c_longlong(len(x)), _ptr(out))
     if st:
         raise RuntimeError("oracle or_gamma_at failed with status %d" % st)
+    return out
+
+
+def gamma_at_all(req: Request, x) -> np.ndarray:
+    """Exact gamma_R(x) for every orientation R: [n_orient, n] (fixed-point units)."""
+    x = np.ascontiguousarray(np.asarray(x, dtype=np.int32).reshape(-1, 3))
+    out = np.zeros((req.n_orient, len(x)), np.int64)
+    st = lib().or_gamma_at_all(C.byref(req._c), _ptr(x), C.c_longlong(len(x)), _ptr(out))
+    if st:
+        raise RuntimeError("oracle or_gamma_at_all failed with status %d" % st)
     return out
 
 

@@ -630,6 +630,37 @@ int or_gamma_at(const or_request *q, int orient, const int32_t *xs, long long n,
   return OR_OK;
 }
 
+/* gamma_R(x) for n voxels x and every orientation R of the request:
+ * out[R * n + j], fixed point units (the same sums as or_gamma_at, with the
+ * obstacle field built once) */
+int or_gamma_at_all(const or_request *q, const int32_t *xs, long long n, int64_t *out) {
+  fields F;
+  int st = fields_build(&F, q);
+  if (st) return st;
+  const int nO = count_orient(q);
+  for (int r = 0; r < nO; r++) {
+    oriented_tool o;
+    st = build_orient(q, r, &o);
+    if (st) {
+      fields_free(&F);
+      return st;
+    }
+    for (long long j = 0; j < n; j++) {
+      int64_t m = INT64_MAX;
+#pragma omp parallel for schedule(dynamic, 16) reduction(min : m)
+      for (long long i = 0; i < o.nS; i++) {
+        const int64_t v = overlap_at(&F, &o, xs[3 * j] - o.S[3 * i], xs[3 * j + 1] - o.S[3 * i + 1],
+                                     xs[3 * j + 2] - o.S[3 * i + 2]);
+        if (v < m) m = v;
+      }
+      out[(long long)r * n + j] = m;
+    }
+    otool_free(&o);
+  }
+  fields_free(&F);
+  return OR_OK;
+}
+
 /* Overlap of one orientation over the whole translation range where it can be
  * nonzero: t in [-o_max, n - 1 - o_min] per axis.  box receives lo[3], dims[3].
  * Call with out == NULL to get the box only. */

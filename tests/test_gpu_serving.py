@@ -1,0 +1,141 @@
+"""Serving loop, admission and autotuning through the C interface.
+
+The serving mix takes requests of different grid sizes, orientation counts,
+binary and density designs and both cutters (subsets of one master Fibonacci
+set, so tool spectra are shared); every result in the mix must equal the same
+request computed alone (bit-identical: the per-orientation arithmetic does not
+depend on what else runs), and the small binary ones the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _mix(n_req=8, seed=91):
+    descs = W.serving_stream(n_req, seed=seed, sizes=(32, 40, 48, 56, 64), master_dirs=40)
+    return [dict(W.serving_request(d, master_dirs=40), desc=d) for d in descs]
+
+
+@pytest.fixture(scope="module")
+def imf_mod():
+    import paper_2002_07627_amd as imf
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return imf
+
+
+def _kw(imf, r):
+    return dict(tools=r["tool"], dirs=r["dirs"], dir_kind=imf.DIR_F64, lam=r["lam"],
+                method=imf.METHOD_FFT)
+
+
+def test_mix_equals_alone(imf_mod):
+    imf = imf_mod
+    reqs = _mix()
+    ctx = imf.Context(0)
+    try:
+        alone = []
+        for r in reqs:
+            o, _ = ctx.compute(dev(r["design"]), dev(r["fixture"]), **_kw(imf, r))
+            alone.append({k: v.clone() for k, v in o.items()})
+        inputs = [(dev(r["design"]), dev(r["fixture"])) for r in reqs]
+        tickets = [ctx.submit(d, fx, **_kw(imf, r)) for (d, fx), r in zip(inputs, reqs)]
+        lat = []
+        for i, t in enumerate(tickets):
+            o, st = ctx.wait(t)
+            lat.append(st.t_ms[7])
+            for k in ("imf", "imf_norm", "secluded", "masks"):
+                assert torch.equal(o[k], alone[i][k]), (i, k)
+        assert all(x > 0 for x in lat)
+    finally:
+        ctx.close()
+    # the binary ones against the oracle
+    for r, a in zip(reqs, alone):
+        if r["desc"]["density"] or r["desc"]["n"] > 40:
+            continue
+        ref = oracle.imf(oracle.Request(r["design"], r["fixture"], tools=r["tool"],
+                                        dirs=r["dirs"], dir_kind=0))
+        f = a["imf"].cpu().numpy().astype(np.float64)
+        assert np.array_equal(f, ref["imf"].reshape(f.shape))
+        assert np.array_equal(a["masks"].cpu().numpy().view(np.uint64),
+                              ref["masks"].reshape(a["masks"].shape))
+
+
+def test_cancel_and_timeout(imf_mod):
+    imf = imf_mod
+    reqs = _mix(6, seed=92)
+    ctx = imf.Context(0)
+    try:
+        inputs = [(dev(r["design"]), dev(r["fixture"])) for r in reqs]
+        tickets = [ctx.submit(d, fx, **_kw(imf, r)) for (d, fx), r in zip(inputs, reqs)]
+        # the last request is cancelled unless it already started
+        cancelled = True
+        try:
+            ctx.cancel(tickets[-1])
+        except imf.IMFError as e:
+            assert e.status == 4  # IMF_EBUSY: already running
+            cancelled = False
+        # a zero timeout on the first request either finds it done or times out
+        try:
+            ctx.wait(tickets[0], timeout_ms=0)
+            done0 = True
+        except imf.IMFError as e:
+            assert e.status == 5  # IMF_ETIMEOUT
+            done0 = False
+        for t in tickets[:-1] if done0 else tickets[:-1]:
+            if t == tickets[0] and done0:
+                continue
+            ctx.wait(t)
+        if cancelled:
+            with pytest.raises(imf.IMFError) as ei:
+                ctx.wait(tickets[-1])
+            assert ei.value.status == 6  # IMF_ECANCELLED
+        else:
+            ctx.wait(tickets[-1])
+    finally:
+        ctx.close()
+
+
+def test_admission_by_footprint(imf_mod):
+    imf = imf_mod
+    r = _mix(1, seed=93)[0]
+    ctx = imf.Context(0)
+    try:
+        need = ctx.footprint(dev(r["design"]), dev(r["fixture"]), **_kw(imf, r))
+        assert need > r["design"].size * 4
+    finally:
+        ctx.close()
+    small = imf.Context(0, budget_bytes=need // 4)
+    try:
+        with pytest.raises(imf.IMFError) as ei:
+            small.compute(dev(r["design"]), dev(r["fixture"]), **_kw(imf, r))
+        assert ei.value.status == 2  # IMF_ENOMEM
+    finally:
+        small.close()
+
+
+def test_autotune_then_batch_is_used_and_results_unchanged(imf_mod):
+    imf = imf_mod
+    d = W.design_3d_boxes_cyls(48, seed=94)
+    fx = W.fixture_plate(d.shape, 3)
+    kw = dict(tools=W.tool(W.TOOL_FLAT, 2, 10, 4, 8), dirs=W.fib_hemisphere(24),
+              dir_kind=imf.DIR_F64, method=imf.METHOD_FFT)
+    ctx = imf.Context(0)
+    try:
+        best = ctx.autotune(dev(d), dev(fx), **kw)
+        assert 1 <= best <= 24
+        o, st = ctx.compute(dev(d), dev(fx), **kw)
+        assert st.batch == best
+        p, _ = ctx.compute(dev(d), dev(fx), **kw, flags=imf.FLAG_PLAIN)
+        for k in ("imf", "imf_norm", "secluded", "masks"):
+            assert torch.equal(o[k], p[k]), k
+    finally:
+        ctx.close()

@@ -192,6 +192,26 @@ def test_single_voxel_tool_gives_rho():
     assert np.array_equal(out["imf"], rho_o)
 
 
+def test_pointwise_gamma_matches_brute_force():
+    """gamma at single voxels (the sampled checks at full size) against the
+    literal brute force: its minimum over orientations is f, and gamma <= 0
+    is the accessible mask of each orientation (lambda = 0)."""
+    rng = np.random.default_rng(21)
+    d = (rng.random((7, 8, 9)) < 0.3).astype(np.uint8)
+    fx = fixture_plate(d.shape, 1)
+    tl = tool(TOOL_FLAT, 1, 3, 2, 2)
+    dirs = lattice26()[::3]
+    b = brute.imf(d.astype(np.int64), fx, tl, dirs)
+    req = oracle.Request(d, fx, tools=tl, dirs=dirs, dir_kind=1)
+    zz, yy, xx = np.meshgrid(np.arange(7), np.arange(8), np.arange(9), indexing="ij")
+    pts = np.stack([xx.ravel(), yy.ravel(), zz.ravel()], axis=1)
+    gam = oracle.gamma_at_all(req, pts)
+    assert np.array_equal(gam.min(0), b["imf"].ravel())
+    om = (fx == 0).ravel()
+    assert np.array_equal((gam <= 0) & om, b["masks"].reshape(len(dirs), -1))
+    assert np.array_equal(oracle.gamma_at(req, 3, pts[::5]), gam[3, ::5])
+
+
 # ---------------------------------------------------------------------------
 # full IMF against brute force
 # ---------------------------------------------------------------------------

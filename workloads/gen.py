@@ -304,3 +304,17 @@ def serving_stream(n_req: int = 64, seed: int = 7627004, rate: float = 1.0,
                     "tool": TOOL_C3 if ball else TOOL_C2, "dir_index": sub,
                     "seed": seed * 100 + i})
     return out
+
+
+def serving_request(desc: dict, master_dirs: int = 130) -> dict:
+    """Materialize one serving-mix descriptor: design (binary boxes/cylinders
+    scaled to the grid, or density), fixture plate, tool, its subset of the
+    master Fibonacci set, lambda (0 for binary, 0.01 for density)."""
+    n = desc["n"]
+    if desc["density"]:
+        d = design_density(n, seed=desc["seed"])
+    else:
+        d = design_3d_boxes_cyls(n, seed=desc["seed"])
+    return {"design": d, "fixture": fixture_plate(d.shape, 6), "tool": desc["tool"],
+            "dirs": fib_hemisphere(master_dirs)[desc["dir_index"]],
+            "lam": 0.01 if desc["density"] else 0.0}
