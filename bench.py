@@ -9,9 +9,11 @@ F_max, fbar, B, Gamma and the 130 accessible masks (threshold lambda F_max).
 Inputs are resident in HBM before the timed region.
 
 Prints one JSON line: value = voxel-orientations per second (256^3 * 130 per
-step / seconds per step), the roofline of the dominant kernel (algorithmic
-bytes / its event-timed duration), the plain per-orientation path on the same
-GPU, and the CPU oracle timed on a bounded sample.
+step / seconds per step), the roofline of the dominant kernel (its algorithmic
+work / its event-timed duration), the HBM roofline of the transform passes, the
+plain per-orientation path on the same GPU, a cold-cache request, the serving
+mix (p50 / p99 latency under Poisson arrivals) and the CPU oracle timed on a
+bounded sample.
 """
 import argparse
 import json
@@ -43,6 +45,76 @@ def measured_traffic(kernel):
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != e["sha256"]:
         return None
     return e["bytes_per_launch"]
+
+
+# on-chip vector memory rate: 16 lanes (4-byte dwords) per clock per CU,
+# 256 CUs at 2.4 GHz -> 9.83e12 lane loads/s = 39.3 TB/s of gathered data
+GATHER_PEAK_GBS = 256 * 16 * 4 * 2.4
+
+
+def roofline_of(cls, kms, kn, kb, ko):
+    """Roofline of one kernel class: the sharp-point minimum is bound by its
+    gathers (vector memory lane rate), every other class by HBM."""
+    avg_ms = kms[cls] / kn[cls]
+    if cls == "minfilter":
+        work = 4.0 * ko[cls] / kn[cls]          # gathered bytes per launch
+        bound, peak = "alu", GATHER_PEAK_GBS
+    else:
+        work = kb[cls] / kn[cls]                # algorithmic HBM bytes per launch
+        bound, peak = "hbm", HBM_PEAK_GBS
+    achieved = work / (avg_ms * 1e-3) / 1e9
+    return {"bound": bound, "achieved": round(achieved, 1), "peak": peak, "unit": "GB/s",
+            "frac": round(achieved / peak, 4), "traffic": measured_traffic(cls),
+            "kernel": cls, "avg_launch_ms": round(avg_ms, 4),
+            ("gathered_bytes_per_launch" if cls == "minfilter"
+             else "algorithmic_bytes_per_launch"): work}
+
+
+def serving_leg(imf, W, torch, n_req=64, load=0.7, seed=7627004):
+    """The serving mix: n_req requests (grids 64..256^3, binary or density,
+    flat or ball cutter, 6-130 orientations of one master Fibonacci set).
+    A back-to-back pass calibrates the saturation rate (and fills the spectrum
+    cache); the mix is then replayed with Poisson arrivals at `load` times that
+    rate, and the submit-to-completion latencies give p50 / p99."""
+    import numpy as np
+    descs = W.serving_stream(n_req, seed=seed)
+    cache = {}
+    reqs = []
+    for d in descs:
+        key = (d["n"], d["density"])
+        if key not in cache:
+            r = W.serving_request(d)
+            cache[key] = (torch.from_numpy(r["design"]).cuda(),
+                          torch.from_numpy(r["fixture"]).cuda(), r["lam"])
+        des, fx, lam = cache[key]
+        reqs.append((des, fx, dict(tools=d["tool"], dirs=W.fib_hemisphere(130)[d["dir_index"]],
+                                   dir_kind=imf.DIR_F64, lam=lam, method=imf.METHOD_FFT)))
+    ctx = imf.Context(0)
+    try:
+        vo = sum(int(r[0].numel()) * len(r[2]["dirs"]) for r in reqs)
+        t0 = time.perf_counter()
+        for des, fx, kw in reqs:
+            ctx.compute(des, fx, **kw)
+        torch.cuda.synchronize()
+        t_sat = time.perf_counter() - t0
+        rate = load * n_req / t_sat
+        arrive = np.array([d["t"] for d in descs]) * (1.0 / rate) / (descs[-1]["t"] / n_req)
+        tickets = []
+        t0 = time.perf_counter()
+        for (des, fx, kw), ta in zip(reqs, arrive):
+            dt = ta - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            tickets.append(ctx.submit(des, fx, **kw))
+        lat = [ctx.wait(t)[1].t_ms[7] for t in tickets]
+        t_all = time.perf_counter() - t0
+    finally:
+        ctx.close()
+    return {"requests": n_req, "load": load, "arrival_rate_per_s": round(rate, 2),
+            "p50_ms": round(float(np.percentile(lat, 50)), 2),
+            "p99_ms": round(float(np.percentile(lat, 99)), 2),
+            "throughput_vo_per_s": vo / t_all,
+            "saturation_vo_per_s": vo / t_sat}
 
 
 def cpu_baseline(w, target_s=15.0):
@@ -92,6 +164,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also time a plain 1 GiB device copy (stream-copy bandwidth; the "
@@ -137,10 +210,12 @@ def main():
         log("warmup %d: %.1f ms (cache hits %d, misses %d)" % (i, st.t_ms[7], st.cache_hits,
                                                                  st.cache_misses))
     torch.cuda.synchronize()
-    stats = []
+    stats, per_step = [], []
     t0 = time.perf_counter()
     for i in range(args.steps):
-        _, st = ctx.compute(design, fixture, **kw, flags=imf.FLAG_PROFILE)
+        t1 = time.perf_counter()
+        _, st = ctx.compute(design, fixture, **kw, flags=imf.FLAG_PROFILE)  # returns when done
+        per_step.append(time.perf_counter() - t1)
         stats.append(st)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
@@ -161,9 +236,6 @@ def main():
             kb[k] = kb.get(k, 0) + st.kernel_bytes[k]
             ko[k] = ko.get(k, 0) + st.kernel_ops[k]
     dom = max(kms, key=kms.get)
-    avg_ms = kms[dom] / kn[dom]
-    bytes_per_launch = kb[dom] / kn[dom]
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     kernels = {k: {"ms_per_step": kms[k] / args.steps, "launches_per_step": kn[k] / args.steps,
                    "GBps": (kb[k] / (kms[k] * 1e-3) / 1e9) if kms[k] > 0 else None}
                for k in sorted(kms, key=kms.get, reverse=True)}
@@ -171,21 +243,10 @@ def main():
         log("  %-14s %8.2f ms/step  %5.1f launches  %s GB/s" %
             (k, v["ms_per_step"], v["launches_per_step"],
              "%.0f" % v["GBps"] if v["GBps"] else "-"))
-    traffic = measured_traffic(dom)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": dom, "avg_launch_ms": round(avg_ms, 4),
-                "algorithmic_bytes_per_launch": bytes_per_launch}
-    # the sharp-point minimum is bound by its gathers: every lookup is one
-    # 4-byte lane load through the vector memory pipeline, whose address rate is
-    # 16 lanes per clock per CU (256 CUs, 2.4 GHz -> 9.83e12 lane loads/s)
-    gather = None
-    if ko.get("minfilter"):
-        lps = ko["minfilter"] / (kms["minfilter"] * 1e-3)
-        peak = 256 * 16 * 2.4e9
-        gather = {"bound": "vmem-gather", "kernel": "minfilter", "achieved": lps,
-                  "peak": peak, "unit": "lane-loads/s", "frac": round(lps / peak, 4),
-                  "lookups_per_step": ko["minfilter"] / args.steps}
+    roofline = roofline_of(dom, kms, kn, kb, ko)
+    # the transform passes are HBM-bound: their roofline beside the dominant one
+    fft = {k: roofline_of(k, kms, kn, kb, ko) for k in ("inv_z_product", "inv_y", "inv_x_c2r")
+           if k in kms}
 
     plain = None
     if not args.no_plain:
@@ -197,8 +258,24 @@ def main():
                  "speedup": (N * nR / (el / args.steps)) / (N * nR / tp)}
         log("plain path: %.1f ms" % (1000 * tp))
     ctx.close()
+    # cold tool-spectrum cache: the same request on a fresh context
+    ctx = imf.Context(0)
+    t1 = time.perf_counter()
+    _, sc = ctx.compute(design, fixture, **kw)
+    torch.cuda.synchronize()
+    cold_ms = 1000 * (time.perf_counter() - t1)
+    ctx.close()
+    log("cold-cache request: %.1f ms (%d spectra computed)" % (cold_ms, sc.cache_misses))
     del design, fixture
     torch.cuda.empty_cache()
+
+    serving = None
+    if not args.no_serving:
+        log("serving mix: 64 requests, Poisson arrivals at 0.7x saturation")
+        serving = serving_leg(imf, W, torch)
+        log("serving: p50 %.1f ms, p99 %.1f ms, %.3e voxel-orientations/s" % (
+            serving["p50_ms"], serving["p99_ms"], serving["throughput_vo_per_s"]))
+        torch.cuda.empty_cache()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -208,9 +285,11 @@ def main():
 
     last = stats[-1]
     line = {
-        "metric": "IMF voxel-orientations/s at 256^3x130 orientations",
+        "metric": "IMF voxel-orientations/s at 256^3\u00d7130 orient. vs plain; "
+                  "p50/p99 request latency",
         "value": value, "unit": "voxel-orientations/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "warmup": args.warmup, "ms_per_step": ms,
+        "ms_per_step_median": 1000 * float(np.median(per_step)), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "256^3 density (sigmoid of sigma-4 smoothed noise, mean 0.35, "
                                "2^-24 grid), fixture plate z<6, ball cutter r4 L60 + holder "
@@ -219,9 +298,11 @@ def main():
                    "grid": list(w.design.shape), "orientations": nR, "P": list(last.P),
                    "batch": last.batch, "spectra": "cached (warm)"},
         "roofline": roofline,
-        "roofline_gather": gather,
+        "roofline_transform_passes": fft,
         "cpu_baseline": cpu,
         "plain": plain,
+        "cold_cache_ms": cold_ms,
+        "serving": serving,
         "kernels": kernels,
         "guard": {"F_max": last.F_max, "max_frac_err": last.max_frac_err,
                   "flags": last.guard_flags},

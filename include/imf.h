@@ -133,11 +133,13 @@ typedef struct {
   /* with IMF_FLAG_PROFILE: device time and launches per kernel class: 0 raster,
    * 1 setup, 2 forward design transform, 3-5 tool spectrum x/y/z, 6 product +
    * inverse z, 7 inverse y, 8 inverse x + rounding, 9 recheck, 10 window-min
-   * levels, 11 sharp-point minimum, 12 sweep, 13 finalize, 14 copies */
+   * levels (and the bound's cell minima), 11 sharp-point minimum, 12 sweep,
+   * 13 finalize, 14 copies, 15 branch-and-bound pass */
   double k_ms[16];
   int k_n[16];
   double k_bytes[16];    /* algorithmic bytes of each class (compulsory reads + writes) */
-  double k_ops[16];      /* class 11: window-minimum lookups (gathered floats) */
+  double k_ops[16];      /* class 11: window-minimum lookups (gathered floats, blocks that
+                            were computed) */
   long long bound_blocks;  /* (block, orientation) pairs of the sharp-point minimum */
   long long bound_skipped; /* of those, skipped by the lower bound (exact) */
 } imf_stats;

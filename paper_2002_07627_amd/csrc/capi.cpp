@@ -724,6 +724,7 @@ static imf_status make_plan(imf_ctx* c, const imf_request* r, const imf_outputs*
     add(sizeof(float) * p.nblocks);                     // block maxima of f
     add(sizeof(int) * p.B * p.nblocks);                 // work lists
     add(sizeof(int) * p.B);                             // list lengths
+    add(sizeof(int) * p.nO);                            // kept blocks per orientation
     add(sizeof(uint64_t) * p.B * p.nwords_blk);         // kept-block bits
     add(sizeof(int) * p.B * p.nwords_blk);              // list offsets
   }
@@ -788,7 +789,7 @@ struct Timer {
   hipStream_t s;
   bool fine = false;
   void mark(int k) {
-    static const bool coarse_mark[16] = {1, 1, 1, 0, 0, 1, 0, 0, 1, 1, 0, 1, 1, 1, 1, 1};
+    static const bool coarse_mark[16] = {1, 1, 1, 0, 0, 1, 0, 0, 1, 1, 0, 1, 1, 1, 1, 0};
     if (!fine && !coarse_mark[k & 15]) return;
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return;
@@ -800,7 +801,7 @@ struct Timer {
     cls.push_back(k);
   }
   void collect(imf_stats* st) {
-    static const int coarse[16] = {0, 6, 1, 2, 2, 2, 3, 3, 3, 4, 5, 5, 5, 6, 6, 6};
+    static const int coarse[16] = {0, 6, 1, 2, 2, 2, 3, 3, 3, 4, 5, 5, 5, 6, 6, 5};
     for (size_t i = 1; i < ev.size(); i++) {
       float ms = 0;
       hipEventElapsedTime(&ms, ev[i - 1], ev[i]);
@@ -861,6 +862,10 @@ struct Pending {
   imf_outputs* out = nullptr;
   double kbytes[16] = {0};  // algorithmic bytes per kernel class
   double kops[16] = {0};    // gathered floats of the minimum filter
+  // per orientation: lookups and bytes of the minimum pass over all blocks,
+  // scaled by the kept fraction once the bound's list lengths are known
+  std::vector<double> mf_ops, mf_bytes;
+  int kept_at = -1;         // offset of the kept counts in host[], or -1
 };
 
 // Enqueue the whole request on stream s (no host synchronization after the
@@ -912,6 +917,7 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
   float* fblock = p.bnb ? carve<float>(ar, p.nblocks) : nullptr;
   int* wlist = p.bnb ? carve<int>(ar, p.B * p.nblocks) : nullptr;
   int* wcount = p.bnb ? carve<int>(ar, p.B) : nullptr;
+  int* kept = p.bnb ? carve<int>(ar, p.nO) : nullptr;
   unsigned long long* wmask = p.bnb ? carve<unsigned long long>(ar, p.B * p.nwords_blk) : nullptr;
   int* woff = p.bnb ? carve<int>(ar, p.B * p.nwords_blk) : nullptr;
   const long long dc_stride = ((p.max_m[0] + 63) / 64) * (long long)p.max_m[1] * p.max_m[2];
@@ -1039,14 +1045,21 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
         pd.kbytes[8] += 4.0 * M3 + 16.0 * d.n_truns;
       }
       pd.kbytes[10] += 4.0 * M3 * (1 + d.nlvl);
-      pd.kops[11] += 2.0 * (double)N * d.n_sruns;
-      pd.kbytes[11] += 4.0 * M3 + 16.0 * d.n_sruns +
-                       (p.masks && p.theta_known && !p.sweep ? N / 8.0 : 0.0) +
-                       (p.two_phase ? 4.0 * N : 0.0);
+      // lookups: 2 per run and output lane (padding lanes of partial blocks included)
+      const double lanes = 64.0 * p.nblocks;
+      const double ops = 2.0 * lanes * d.n_sruns;
+      // g box read once, runs, f read + write, masks (Omega_0 + bits) or the gamma stack
+      const double byt = 4.0 * M3 + 16.0 * d.n_sruns + 8.0 * N +
+                         (p.masks && p.theta_known && !p.sweep ? N + N / 8.0 : 0.0) +
+                         (p.two_phase ? 4.0 * N : 0.0);
+      if (p.bnb) pd.kbytes[15] += 12.0 * p.nblocks;  // block maxima, keep bits, list
+      pd.mf_ops.push_back(ops);
+      pd.mf_bytes.push_back(byt);
+      pd.kops[11] += ops;
+      pd.kbytes[11] += byt;
       if (p.sweep) pd.kbytes[12] += 4.0 * M3 + N / 8.0 + N;
     }
     if (p.method == IMF_METHOD_FFT) pd.kbytes[6] += S;  // rho_hat, once per batch
-    pd.kbytes[11] += 9.0 * N;                          // f read + write, Omega_0
     if (p.method == IMF_METHOD_FFT) {
       if (nmiss[b]) {
         imf_tool_fft_args ta{d_miss + (size_t)b * p.B, nmiss[b], p.P[0], p.P[1], p.P[2],
@@ -1145,6 +1158,7 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
     ma.list = wlist;
     ma.list_stride = p.nblocks;
     ma.count = wcount;
+    ma.kept = kept;
     ma.wmask = wmask;
     ma.woff = woff;
     ma.wstride = p.nwords_blk;
@@ -1157,8 +1171,14 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
     ma.skipped = (unsigned long long*)(misc + 8);
     HIPCHK(imf_launch_minfilter(ma, s, 0));
     tm.mark(10);
-    HIPCHK(imf_launch_minfilter(ma, s, 1));
-    tm.mark(11);
+    for (int q = 0; q < nq; q++) {
+      if (p.bnb) {
+        HIPCHK(imf_launch_minfilter(ma, s, 1, q));
+        tm.mark(15);
+      }
+      HIPCHK(imf_launch_minfilter(ma, s, 2, q));
+      tm.mark(11);
+    }
     if (p.sweep) {
       imf_sweep_args sa{d_sweep + q0, nq, g, p.max_vol, p.theta, r->nx, r->ny, r->nz, om, dc,
                         dc_stride, out->acc_masks, q0};
@@ -1179,6 +1199,11 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
   pd.host = ar.host;
   HIPCHK(hipMemcpyAsync(pd.host, misc, 16 * sizeof(unsigned int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(pd.host + 16, flag_cnt, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
+  if (kept && 16 + nb + p.nO <= (1 << 14)) {
+    pd.kept_at = 16 + nb;
+    HIPCHK(hipMemcpyAsync(pd.host + pd.kept_at, kept, sizeof(int) * p.nO, hipMemcpyDeviceToHost,
+                          s));
+  }
   if (out->debug_overlap) {
     const imf_orient_desc& d = p.desc[out->debug_orient];
     for (int a = 0; a < 3; a++) {
@@ -1228,11 +1253,20 @@ static imf_status compute_finish(Pending& pd, imf_stats* st) {
     }
     st->guard_band = p.band;
     pd.tm.collect(st);
-    if (pd.tm.fine)
+    if (pd.tm.fine) {
+      if (pd.kept_at >= 0 && p.nblocks > 0) {  // the minimum pass ran on the kept blocks only
+        pd.kops[11] = pd.kbytes[11] = 0;
+        for (size_t q = 0; q < pd.mf_ops.size(); q++) {
+          const double fr = (double)(int)pd.host[pd.kept_at + q] / (double)p.nblocks;
+          pd.kops[11] += fr * pd.mf_ops[q];
+          pd.kbytes[11] += fr * pd.mf_bytes[q];
+        }
+      }
       for (int k = 0; k < 16; k++) {
         st->k_bytes[k] = pd.kbytes[k];
         st->k_ops[k] = pd.kops[k];
       }
+    }
     st->t_ms[7] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
                                                             pd.t_start).count();
     st->model_bytes = model_bytes(p);

@@ -173,6 +173,7 @@ struct imf_min_args {
   int* list; long long list_stride;  // per q: blocks left to compute, packed
                                      // bx | by << 10 | bz << 21
   int* count;               // per q: length of that list
+  int* kept;                // statistics: list length per global orientation, or NULL
   unsigned long long* wmask; int* woff; long long wstride;  // per q and 64 logical blocks:
                             // kept-block bits of the bound pass, exclusive list offsets
   unsigned int* fmax_up;    // two-phase: max of f over all voxels at the start of the batch
@@ -183,9 +184,11 @@ struct imf_min_args {
   int n_cu, wg_per_cu;      // resident workgroups of the list pass: CUs x per CU
   unsigned long long* skipped;  // statistics: skipped (block, orientation) pairs
 };
-// stage: -1 all, 0 sparse-table levels (and cell minima / footprints with
-// branch and bound), 1 the minimum filter
-hipError_t imf_launch_minfilter(const imf_min_args& a, hipStream_t s, int stage = -1);
+// stage 0: sparse-table levels of the batch (and cell minima, footprints and
+// the threshold bound with branch and bound); stage 1: the bound pass of
+// orientation q (branch and bound only); stage 2: the minimum pass of
+// orientation q; -1: everything for every orientation of the batch
+hipError_t imf_launch_minfilter(const imf_min_args& a, hipStream_t s, int stage = -1, int q = 0);
 // blocks of the output for a wave shape
 void imf_block_dims(int shape, int& wx, int& wy, int& wz);
 // logical block indices of the minimum pass (blocks and brick padding)

@@ -541,7 +541,10 @@ __global__ void __launch_bounds__(1024) k_scan_masks(imf_min_args a, int qi, int
     if (threadIdx.x == 1023) carry = ex;
     __syncthreads();
   }
-  if (threadIdx.x == 0) a.count[qi] = carry;
+  if (threadIdx.x == 0) {
+    a.count[qi] = carry;
+    if (a.kept) a.kept[a.q0 + qi] = carry;
+  }
 }
 
 template <int WX, int WY, int WZ>
@@ -704,33 +707,32 @@ __global__ void __launch_bounds__(IMF_WG) k_minfilter_list(imf_min_args a, int q
   }
 }
 
+// part 1: bound, scan and scatter of orientation q; part 2: its minimum pass
 template <int WX, int WY, int WZ>
-static hipError_t launch_mf(const imf_min_args& a, hipStream_t s) {
+static hipError_t launch_mf(const imf_min_args& a, hipStream_t s, int part, int q) {
   const mf_geom G(WX, WY, WZ, a.nx, a.ny, a.nz);
-  const long long nwg = (G.nlog + 3) / 4;
-  const long long grid = (nwg + 7) / 8 * 8;
-  // the list pass: resident capacity (LDS-bound: 10 workgroups per CU), a
-  // multiple of 8 workgroups
-  long long lgrid = std::min((long long)a.n_cu * a.wg_per_cu, nwg);
-  lgrid = std::max(8LL, (lgrid + 7) / 8 * 8);
   hipError_t e;
-  for (int q = 0; q < a.nq; q++) {
-    if (a.bnb) {
-      const unsigned gb = (unsigned)((G.nlog + IMF_WG - 1) / IMF_WG);
-      hipLaunchKernelGGL((k_bound<WX, WY, WZ>), dim3(gb), dim3(IMF_WG), 0, s, a, q);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-      hipLaunchKernelGGL(k_scan_masks, dim3(1), dim3(1024), 0, s, a, q, (int)((G.nlog + 63) / 64));
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-      hipLaunchKernelGGL((k_scatter<WX, WY, WZ>), dim3(gb), dim3(IMF_WG), 0, s, a, q);
-      if ((e = hipGetLastError()) != hipSuccess) return e;
-      hipLaunchKernelGGL((k_minfilter_list<WX, WY, WZ>), dim3((unsigned)lgrid), dim3(IMF_WG), 0, s,
-                         a, q);
-    } else {
-      hipLaunchKernelGGL((k_minfilter<WX, WY, WZ>), dim3((unsigned)grid), dim3(IMF_WG), 0, s, a, q);
-    }
+  if (part == 1) {
+    const unsigned gb = (unsigned)((G.nlog + IMF_WG - 1) / IMF_WG);
+    hipLaunchKernelGGL((k_bound<WX, WY, WZ>), dim3(gb), dim3(IMF_WG), 0, s, a, q);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan_masks, dim3(1), dim3(1024), 0, s, a, q, (int)((G.nlog + 63) / 64));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_scatter<WX, WY, WZ>), dim3(gb), dim3(IMF_WG), 0, s, a, q);
+    return hipGetLastError();
   }
-  return hipSuccess;
+  const long long nwg = (G.nlog + 3) / 4;
+  if (a.bnb) {
+    // resident capacity (a multiple of 8 workgroups)
+    long long lgrid = std::min((long long)a.n_cu * a.wg_per_cu, nwg);
+    lgrid = std::max(8LL, (lgrid + 7) / 8 * 8);
+    hipLaunchKernelGGL((k_minfilter_list<WX, WY, WZ>), dim3((unsigned)lgrid), dim3(IMF_WG), 0, s,
+                       a, q);
+  } else {
+    const long long grid = (nwg + 7) / 8 * 8;
+    hipLaunchKernelGGL((k_minfilter<WX, WY, WZ>), dim3((unsigned)grid), dim3(IMF_WG), 0, s, a, q);
+  }
+  return hipGetLastError();
 }
 
 long long imf_block_logical(int shape, int nx, int ny, int nz) {
@@ -739,7 +741,7 @@ long long imf_block_logical(int shape, int nx, int ny, int nz) {
   return mf_geom(wx, wy, wz, nx, ny, nz).nlog;
 }
 
-hipError_t imf_launch_minfilter(const imf_min_args& a, hipStream_t s, int stage) {
+hipError_t imf_launch_minfilter(const imf_min_args& a, hipStream_t s, int stage, int q) {
   hipError_t e;
   int wx, wy, wz;
   imf_block_dims(a.shape, wx, wy, wz);
@@ -777,12 +779,19 @@ hipError_t imf_launch_minfilter(const imf_min_args& a, hipStream_t s, int stage)
     }
   }
   if (stage == 0) return hipSuccess;
-  switch (a.shape) {
-    case 1: return launch_mf<32, 2, 1>(a, s);
-    case 2: return launch_mf<16, 2, 2>(a, s);
-    case 3: return launch_mf<16, 4, 1>(a, s);
-    default: return launch_mf<64, 1, 1>(a, s);
-  }
+  for (int qi = (stage < 0 ? 0 : q); qi < (stage < 0 ? a.nq : q + 1); qi++)
+    for (int part = 1; part <= 2; part++) {
+      if (part == 1 && (!a.bnb || stage == 2)) continue;
+      if (part == 2 && stage == 1) continue;
+      switch (a.shape) {
+        case 1: e = launch_mf<32, 2, 1>(a, s, part, qi); break;
+        case 2: e = launch_mf<16, 2, 2>(a, s, part, qi); break;
+        case 3: e = launch_mf<16, 4, 1>(a, s, part, qi); break;
+        default: e = launch_mf<64, 1, 1>(a, s, part, qi); break;
+      }
+      if (e != hipSuccess) return e;
+    }
+  return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------
@@ -957,7 +966,9 @@ hipError_t imf_launch_finalize(const float* f, const uint8_t* omega0, const void
   return hipGetLastError();
 }
 
-// masks from stored gamma once theta = lambda F_max is known
+// masks from stored gamma once theta = lambda F_max is known.  One wave per
+// 64-voxel word of a row: Omega_0 is read once and the wave walks all
+// orientations (independent coalesced loads, one mask word each).
 __global__ void __launch_bounds__(IMF_WG) k_masks_gamma(const float* __restrict__ gs, int nq,
                                                         const uint8_t* __restrict__ om, int nx,
                                                         int ny, int nz,
@@ -967,26 +978,36 @@ __global__ void __launch_bounds__(IMF_WG) k_masks_gamma(const float* __restrict_
   const long long wave = (long long)blockIdx.x * (IMF_WG / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const long long per_q = (long long)words * ny * nz;
-  if (wave >= per_q * nq) return;
-  const int q = (int)(wave / per_q);
-  const long long r = wave % per_q;
-  const int w = (int)(r % words);
-  const long long yz = r / words;
+  if (wave >= per_q) return;
+  const int w = (int)(wave % words);
+  const long long yz = wave / words;
   const int x = w * 64 + lane;
   const double theta = lambda * (double)ord2f(*fmax_bits);
-  bool b = false;
-  if (x < nx) {
-    const long long vi = yz * nx + x;
-    b = om[vi] && (double)gs[(long long)q * nx * ny * nz + vi] <= theta;
+  const long long N = (long long)nx * ny * nz;
+  const long long vi = yz * nx + (x < nx ? x : nx - 1);
+  const bool in = x < nx && om[vi];
+  const float* g = gs + vi;
+  int q = 0;
+  for (; q + 4 <= nq; q += 4) {
+    float v[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) v[j] = g[(long long)(q + j) * N];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const unsigned long long bits = __ballot(in && (double)v[j] <= theta);
+      if (lane == 0) masks[(long long)(q + j) * per_q + wave] = bits;
+    }
   }
-  const unsigned long long bits = __ballot(b);
-  if (lane == 0) masks[(long long)q * per_q + yz * words + w] = bits;
+  for (; q < nq; q++) {
+    const unsigned long long bits = __ballot(in && (double)g[(long long)q * N] <= theta);
+    if (lane == 0) masks[(long long)q * per_q + wave] = bits;
+  }
 }
 hipError_t imf_launch_masks_from_gamma(const float* gamma_stack, int nq, const uint8_t* omega0,
                                        int nx, int ny, int nz, const unsigned int* fmax_bits,
                                        double lambda, uint64_t* masks, hipStream_t s) {
   const int words = (nx + 63) >> 6;
-  const long long waves = (long long)words * ny * nz * nq;
+  const long long waves = (long long)words * ny * nz;
   const int per = IMF_WG / 64;
   hipLaunchKernelGGL(k_masks_gamma, dim3((unsigned)((waves + per - 1) / per)), dim3(IMF_WG), 0, s,
                      gamma_stack, nq, omega0, nx, ny, nz, fmax_bits, lambda, masks);

@@ -22,7 +22,7 @@ METHOD_AUTO, METHOD_FFT, METHOD_DIRECT = 0, 1, 2
 FLAG_PLAIN, FLAG_MASK_SWEEP, FLAG_NO_CACHE, FLAG_PROFILE, FLAG_NO_BOUND = 1, 2, 4, 8, 16
 KERNEL_CLASSES = ("raster", "setup", "fwd_design", "tool_x", "tool_y", "tool_z",
                   "inv_z_product", "inv_y", "inv_x_c2r", "recheck", "levels", "minfilter",
-                  "sweep", "finalize", "copies", "unused")
+                  "sweep", "finalize", "copies", "bound")
 
 _STATUS = {0: "IMF_OK", 1: "IMF_EINVAL", 2: "IMF_ENOMEM", 3: "IMF_EDEVICE", 4: "IMF_EBUSY",
            5: "IMF_ETIMEOUT", 6: "IMF_ECANCELLED", 7: "IMF_EACCURACY", 8: "IMF_ENOTIMPL"}
