@@ -1127,6 +1127,9 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
     ma.nlvl = p.nlvl;
     ma.max_m = 1;
     ma.max_lines = 1;
+    ma.stream_waves = 0;
+    ma.x_rows = 0;
+    ma.lds_levels = 0;
     for (int q = q0; q < q0 + nq; q++) {
       const imf_orient_desc& d = p.desc[q];
       const int ax = d.s_axis;
@@ -1135,6 +1138,12 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
           ax == 0 ? ((long long)d.box_dim[1] * d.box_dim[2] + 3) / 4
                   : (long long)((d.box_dim[0] + 15) / 16) * (ax == 1 ? d.box_dim[2] : d.box_dim[1]);
       ma.max_lines = std::max(ma.max_lines, lines);
+      if (ax != 0)
+        ma.stream_waves = std::max(ma.stream_waves, (long long)((d.box_dim[0] + 63) / 64) *
+                                                        (ax == 1 ? d.box_dim[2] : d.box_dim[1]));
+      else
+        ma.x_rows = std::max(ma.x_rows, (long long)d.box_dim[1] * d.box_dim[2]);
+      if (d.nlvl > 6) ma.lds_levels = 1;  // beyond the register forms (LS_MAXL)
     }
     ma.nx = r->nx;
     ma.ny = r->ny;

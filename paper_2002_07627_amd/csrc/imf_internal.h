@@ -153,7 +153,10 @@ struct imf_min_args {
   const float* g; long long g_stride;
   float* lvl; long long lvl_stride; int nlvl;   // sparse-table levels per q
   int max_m;                // largest box extent along any run axis (LDS of the level pass)
-  long long max_lines;      // workgroups of the level pass
+  long long max_lines;      // workgroups of the level pass (LDS form: x lines)
+  long long stream_waves;   // waves of the streamed level pass (y and z lines)
+  long long x_rows;         // rows of the shuffle level pass (x lines)
+  int lds_levels;           // some orientation needs more levels than the register forms
   int nx, ny, nz;
   float* f;                 // running min [nz][ny][nx]
   const uint8_t* omega0;    // [nz][ny][nx]

@@ -175,6 +175,7 @@ hipError_t imf_launch_recheck(const imf_orient_desc* desc, const long long* ps, 
 // out.  A workgroup holds LT lines of length m = box extent along the axis;
 // for the x axis the lines are rows, otherwise LT consecutive x columns.
 #define LVL_LT 16
+#define LS_MAXL 6  // levels handled by the register forms
 __global__ void __launch_bounds__(IMF_WG) k_levels(const imf_orient_desc* __restrict__ desc,
                                                    const float* __restrict__ g,
                                                    long long g_stride, float* __restrict__ lvl,
@@ -186,6 +187,10 @@ __global__ void __launch_bounds__(IMF_WG) k_levels(const imf_orient_desc* __rest
   const int mx = d.box_dim[0], my = d.box_dim[1], mz = d.box_dim[2];
   const int m = d.box_dim[ax];
   const long long sa = ax == 0 ? 1 : (ax == 1 ? (long long)mx : (long long)mx * my);
+  {
+    const int nl_q = d.nlvl < nlvl ? d.nlvl : nlvl;
+    if (nl_q >= 1 && nl_q <= LS_MAXL) return;  // k_levels_stream / k_levels_x
+  }
   // lines: for ax == 0, rows (y, z); else groups of LVL_LT consecutive x at a
   // fixed coordinate of the third axis
   long long nlines;
@@ -244,6 +249,114 @@ __global__ void __launch_bounds__(IMF_WG) k_levels(const imf_orient_desc* __rest
     float* tmp = A;
     A = B;
     B = tmp;
+  }
+}
+
+// Sparse-table levels along y or z lines, streamed: one wave per 64
+// consecutive x of a line, walking the line from its end (coalesced 256-byte
+// loads and stores, no LDS).  Level s at position i is
+// min(L_{s-1}(i), L_{s-1}(i + 2^(s-1))), with +inf past the line's end (the
+// same values as k_levels), so each level needs the previous level's value
+// 2^(s-1) steps back: delay lines in registers, with the loop unrolled by the
+// longest delay so that every slot index is a compile-time constant.
+template <int NL>
+__device__ __forceinline__ void levels_stream_line(const float* __restrict__ src,
+                                                   float* __restrict__ dst, long long g_stride,
+                                                   int m, long long sa, long long base, bool ok) {
+  constexpr int U = 1 << (NL - 1);
+  float D[(1 << NL) - 1];  // level s - 1 delays at [2^(s-1) - 1, 2^s - 1)
+#pragma unroll
+  for (int k = 0; k < (1 << NL) - 1; k++) D[k] = INFINITY;
+  const int nb = (m + U - 1) / U;
+  for (int b = nb - 1; b >= 0; b--) {
+    float gv[U];
+#pragma unroll
+    for (int j = 0; j < U; j++) {
+      const int i = b * U + (U - 1 - j);
+      gv[j] = (ok && i < m) ? src[base + (long long)i * sa] : INFINITY;
+    }
+#pragma unroll
+    for (int j = 0; j < U; j++) {
+      const int i = b * U + (U - 1 - j);
+      float v = gv[j];
+#pragma unroll
+      for (int s = 1; s <= NL; s++) {
+        const int slot = ((1 << (s - 1)) - 1) + (j & ((1 << (s - 1)) - 1));
+        const float prev = D[slot];
+        D[slot] = v;
+        v = fminf(v, prev);
+        if (ok && i < m) dst[(long long)(s - 1) * g_stride + base + (long long)i * sa] = v;
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(IMF_WG) k_levels_stream(const imf_orient_desc* __restrict__ desc,
+                                                          const float* __restrict__ g,
+                                                          long long g_stride,
+                                                          float* __restrict__ lvl,
+                                                          long long lvl_stride, int nlvl) {
+  const int q = blockIdx.y;
+  const imf_orient_desc& d = desc[q];
+  const int ax = d.s_axis;
+  const int nl_q = d.nlvl < nlvl ? d.nlvl : nlvl;
+  if (ax == 0 || nl_q < 1 || nl_q > LS_MAXL) return;  // left to k_levels
+  const int mx = d.box_dim[0], my = d.box_dim[1], mz = d.box_dim[2];
+  const int nxw = (mx + 63) / 64;
+  const long long w = (long long)blockIdx.x * (IMF_WG / 64) + (threadIdx.x >> 6);
+  const long long o = w / nxw;
+  if (o >= (ax == 1 ? mz : my)) return;
+  const int x = (int)(w % nxw) * 64 + (threadIdx.x & 63);
+  const bool ok = x < mx;
+  const long long base = ax == 1 ? o * my * mx + x : o * mx + x;
+  const long long sa = ax == 1 ? (long long)mx : (long long)mx * my;
+  const int m = d.box_dim[ax];
+  const float* src = g + q * g_stride;
+  float* dst = lvl + q * lvl_stride;
+  switch (nl_q) {
+    case 1: levels_stream_line<1>(src, dst, g_stride, m, sa, base, ok); break;
+    case 2: levels_stream_line<2>(src, dst, g_stride, m, sa, base, ok); break;
+    case 3: levels_stream_line<3>(src, dst, g_stride, m, sa, base, ok); break;
+    case 4: levels_stream_line<4>(src, dst, g_stride, m, sa, base, ok); break;
+    case 5: levels_stream_line<5>(src, dst, g_stride, m, sa, base, ok); break;
+    default: levels_stream_line<6>(src, dst, g_stride, m, sa, base, ok); break;
+  }
+}
+
+// Levels along x lines (rows, contiguous): one wave per row, 64 positions per
+// step, two chunks in registers (a = positions c..c+63, b = the next 64).
+// Level s of a needs level s-1 at lane + 2^(s-1), from a or (past lane 63)
+// from b; b's level s-1 is needed only at lanes < 2^(s-1), which stay inside
+// b for s <= 6.  Coalesced 256-byte loads and stores, no LDS.
+__global__ void __launch_bounds__(IMF_WG) k_levels_x(const imf_orient_desc* __restrict__ desc,
+                                                     const float* __restrict__ g,
+                                                     long long g_stride, float* __restrict__ lvl,
+                                                     long long lvl_stride, int nlvl) {
+  const int q = blockIdx.y;
+  const imf_orient_desc& d = desc[q];
+  const int nl_q = d.nlvl < nlvl ? d.nlvl : nlvl;
+  if (d.s_axis != 0 || nl_q < 1 || nl_q > LS_MAXL) return;  // left to the other forms
+  const int mx = d.box_dim[0];
+  const long long rows = (long long)d.box_dim[1] * d.box_dim[2];
+  const long long row = (long long)blockIdx.x * (IMF_WG / 64) + (threadIdx.x >> 6);
+  if (row >= rows) return;
+  const int lane = threadIdx.x & 63;
+  const float* src = g + q * g_stride + row * mx;
+  float* dst = lvl + q * lvl_stride + row * mx;
+  float b = lane < mx ? src[lane] : INFINITY;
+  for (int c = 0; c < mx; c += 64) {
+    float a = b;
+    b = c + 64 + lane < mx ? src[c + 64 + lane] : INFINITY;
+    float bb = b;
+    for (int s = 1; s <= nl_q; s++) {
+      const int h = 1 << (s - 1);
+      const int src_lane = (lane + h) & 63;
+      const float xa = __shfl(a, src_lane);
+      const float xb = __shfl(bb, src_lane);
+      a = fminf(a, lane + h < 64 ? xa : xb);
+      bb = fminf(bb, lane + h < 64 ? xb : INFINITY);  // valid where it is used
+      if (c + lane < mx) dst[(long long)(s - 1) * g_stride + c + lane] = a;
+    }
   }
 }
 
@@ -748,15 +861,29 @@ hipError_t imf_launch_minfilter(const imf_min_args& a, hipStream_t s, int stage,
   if ((stage < 0 || stage == 0) && a.nlvl > 0) {
     // one launch for all orientations of the batch; the grid covers the
     // largest line count (rows for x runs, x groups otherwise)
-    const size_t sm = (size_t)2 * LVL_LT * a.max_m * sizeof(float);
-    if (sm > 64 * 1024)
-      if ((e = hipFuncSetAttribute((const void*)k_levels,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm)) !=
-          hipSuccess)
-        return e;
-    hipLaunchKernelGGL(k_levels, dim3((unsigned)a.max_lines, 1, a.nq), dim3(IMF_WG), sm, s,
-                       a.desc, a.g, a.g_stride, a.lvl, a.lvl_stride, a.nlvl);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (a.lds_levels) {  // orientations with more than LS_MAXL levels
+      const size_t sm = (size_t)2 * LVL_LT * a.max_m * sizeof(float);
+      if (sm > 64 * 1024)
+        if ((e = hipFuncSetAttribute((const void*)k_levels,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm)) !=
+            hipSuccess)
+          return e;
+      hipLaunchKernelGGL(k_levels, dim3((unsigned)a.max_lines, 1, a.nq), dim3(IMF_WG), sm, s,
+                         a.desc, a.g, a.g_stride, a.lvl, a.lvl_stride, a.nlvl);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (a.x_rows > 0) {
+      hipLaunchKernelGGL(k_levels_x,
+                         dim3((unsigned)((a.x_rows + IMF_WG / 64 - 1) / (IMF_WG / 64)), a.nq),
+                         dim3(IMF_WG), 0, s, a.desc, a.g, a.g_stride, a.lvl, a.lvl_stride, a.nlvl);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (a.stream_waves > 0) {
+      hipLaunchKernelGGL(k_levels_stream,
+                         dim3((unsigned)((a.stream_waves + IMF_WG / 64 - 1) / (IMF_WG / 64)), a.nq),
+                         dim3(IMF_WG), 0, s, a.desc, a.g, a.g_stride, a.lvl, a.lvl_stride, a.nlvl);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
   }
   if ((stage < 0 || stage == 0) && a.bnb) {
     hipLaunchKernelGGL(k_footprint, dim3(a.nq), dim3(IMF_WG), 0, s, a.desc, a.nx, a.ny, a.nz, wx,

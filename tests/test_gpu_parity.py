@@ -319,3 +319,17 @@ def test_bound_every_block_shape(shape, mode, monkeypatch):
         assert torch.equal(a[k], b[k]), k
     assert sa.bound_blocks > 0 and sb.bound_blocks == 0
     assert 0 < sa.bound_skipped < sa.bound_blocks
+
+
+def test_long_cutter_uses_more_than_six_levels(ctx):
+    """A cutter longer than 128 voxels: runs of S need sparse-table levels
+    beyond the register forms (the LDS level pass), on every axis."""
+    import paper_2002_07627_amd as imf
+    d = random_boxes((20, 22, 24), 8, 31, lo=3, hi=9)
+    fx = W.fixture_plate(d.shape, 2)
+    tl = W.tool(W.TOOL_FLAT, 1, 140, 2, 4)
+    dirs = np.array([[1, 0, 0], [0, 1, 0], [0, 0, 1], [0, 0, -1]], np.int32)
+    out, st = ctx.compute(dev(d), dev(fx), tools=tl, dirs=dirs, dir_kind=imf.DIR_LATTICE,
+                          method=imf.METHOD_FFT)
+    ref = oracle.imf(oracle.Request(d, fx, tools=tl, dirs=dirs, dir_kind=1))
+    check_binary(out, ref)
