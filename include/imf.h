@@ -85,6 +85,12 @@ enum { IMF_METHOD_AUTO = 0, IMF_METHOD_FFT = 1, IMF_METHOD_DIRECT = 2 };
 #define IMF_FLAG_NO_CACHE 4u     /* do not keep tool spectra */
 #define IMF_FLAG_PROFILE 8u      /* time every kernel class with events (k_ms, k_n) */
 #define IMF_FLAG_NO_BOUND 16u    /* no branch and bound in the sharp-point minimum */
+#define IMF_FLAG_NO_GRAPH 32u    /* launch kernel by kernel: no HIP-graph capture or replay.
+                                    Otherwise the second request with the same signature
+                                    (request fields, input / output pointers, orientations,
+                                    cache state) is captured into a graph, and later ones
+                                    replay it; requests that compute tool spectra, PROFILE and
+                                    PLAIN requests always launch kernel by kernel */
 
 typedef struct {
   int ndim, nx, ny, nz;
@@ -142,6 +148,8 @@ typedef struct {
                             were computed) */
   long long bound_blocks;  /* (block, orientation) pairs of the sharp-point minimum */
   long long bound_skipped; /* of those, skipped by the lower bound (exact) */
+  int graph;               /* 0 launched kernel by kernel, 1 captured into a graph and
+                              launched, 2 a replay of a captured graph */
 } imf_stats;
 
 /* Bytes of device workspace the request needs (admission control). */

@@ -18,6 +18,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <unordered_map>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -175,6 +176,19 @@ struct imf_ctx {
   size_t inflight_bytes = 0;
   int max_inflight = 4;
   int n_running = 0;
+  // captured requests: signature -> instantiated graph and the host-side
+  // statistics of its launch sequence (the context lock guards both maps)
+  struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    double kbytes[16], kops[16];
+    std::vector<double> mf_ops, mf_bytes;
+    int kept_at = -1;
+    uint64_t tick = 0;
+  };
+  std::unordered_map<std::string, GraphEntry> graphs;
+  std::unordered_map<std::string, int> graph_seen;
+  uint64_t graph_tick = 0;
+  hipStream_t capture = nullptr;  // private stream graphs are captured on
   int mf_shape = 2;  // wave block shape of the sharp-point minimum (imf_block_dims)
   int n_cu = 256;     // compute units of the device
   int mf_wg_per_cu = 4;  // resident workgroups per CU of the sharp-point minimum (list pass)
@@ -271,7 +285,10 @@ extern "C" imf_status imf_destroy(imf_ctx* c) {
   for (void* p : c->raster_pools) hipFree(p);
   for (auto& kv : c->twiddles) hipFree(kv.second);
   if (c->arena.base) hipFree(c->arena.base);
+  for (auto& kv : c->graphs)
+    if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
   if (c->internal) hipStreamDestroy(c->internal);
+  if (c->capture) hipStreamDestroy(c->capture);
   delete c;
   return IMF_OK;
 }
@@ -788,7 +805,9 @@ struct Timer {
   std::vector<int> cls;
   hipStream_t s;
   bool fine = false;
+  bool off = false;  // no event marks (graph capture and replay)
   void mark(int k) {
+    if (off) return;
     static const bool coarse_mark[16] = {1, 1, 1, 0, 0, 1, 0, 0, 1, 1, 0, 1, 1, 1, 1, 0};
     if (!fine && !coarse_mark[k & 15]) return;
     hipEvent_t e;
@@ -866,6 +885,7 @@ struct Pending {
   // scaled by the kept fraction once the bound's list lengths are known
   std::vector<double> mf_ops, mf_bytes;
   int kept_at = -1;         // offset of the kept counts in host[], or -1
+  int graph = 0;            // 0 kernel by kernel, 1 captured and launched, 2 replayed
 };
 
 // Enqueue the whole request on stream s (no host synchronization after the
@@ -993,9 +1013,43 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
     STCHK(get_twiddles(c, p.P[1], &twy));
     STCHK(get_twiddles(c, p.P[2], &twz));
   }
+  // Everything from here to the statistics copies is stream work only, so it
+  // can be captured into a graph: a repeated request with the same signature
+  // (request fields, pointers, descriptors, cache state, workspace) replays it.
+  const bool graphable = !(r->flags & (IMF_FLAG_NO_GRAPH | IMF_FLAG_PROFILE | IMF_FLAG_PLAIN)) &&
+                         pd.misses == 0;
+  std::string sig;
+  if (graphable) {
+    auto put = [&](const void* v, size_t n) { sig.append((const char*)v, n); };
+    const long long req_i[] = {r->ndim, r->nx, r->ny, r->nz, r->design_is_density, r->n_tools,
+                               r->dir_kind, r->sharp, r->method, r->batch, (long long)r->flags};
+    put(req_i, sizeof(req_i));
+    const double req_d[] = {r->lambda, r->tau, r->mask_theta_abs};
+    put(req_d, sizeof(req_d));
+    const void* ptrs[] = {r->design, r->fixture, r->domain, out->imf, out->imf_norm,
+                          out->secluded, out->acc_masks, out->debug_overlap};
+    put(ptrs, sizeof(ptrs));
+    put(&out->debug_orient, sizeof(int));
+    long long ndir = 0;
+    for (int i = 0; i < r->n_tools; i++) {
+      put(&r->tool_ids[i], sizeof(int));
+      put(&r->n_dirs[i], sizeof(int));
+      ndir += r->n_dirs[i];
+    }
+    put(r->dirs, (size_t)ndir * r->ndim * (r->dir_kind == IMF_DIR_LATTICE ? 4 : 8));
+    put(&p.B, sizeof(p.B));
+    put(p.P, sizeof(p.P));
+    put(&ar.base, sizeof(ar.base));
+    put(&ar.host, sizeof(ar.host));
+    const void* tws[3] = {twx, twy, twz};
+    put(tws, sizeof(tws));
+    put(hall.data(), sizeof(imf_orient_desc) * hall.size());
+    for (const auto& k : p.keys) sig += k + "|";
+  }
+  auto launch_all = [&](hipStream_t s) -> imf_status {
   // setup
-  HIPCHK(hipMemsetAsync(misc, 0, 256, s));
-  HIPCHK(hipMemsetAsync(flag_cnt, 0, sizeof(int) * (nb + 1), s));
+  HIPCHK(imf_launch_fill_u32(misc, 64, 0u, s));
+  HIPCHK(imf_launch_fill_u32((unsigned*)flag_cnt, nb + 1, 0u, s));
   HIPCHK(imf_launch_omega0(r->fixture, r->domain, om, N, s));
   HIPCHK(imf_launch_fill_f(f, N, INFINITY, s));
   if (fblock) HIPCHK(imf_launch_fill_f(fblock, p.nblocks, INFINITY, s));
@@ -1213,6 +1267,61 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
     HIPCHK(hipMemcpyAsync(pd.host + pd.kept_at, kept, sizeof(int) * p.nO, hipMemcpyDeviceToHost,
                           s));
   }
+  return IMF_OK;
+  };
+  if (!graphable) {
+    STCHK(launch_all(s));
+  } else if (auto it = c->graphs.find(sig); it != c->graphs.end()) {
+    tm.off = true;
+    HIPCHK(hipGraphLaunch(it->second.exec, s));
+    it->second.tick = ++c->graph_tick;
+    std::memcpy(pd.kbytes, it->second.kbytes, sizeof pd.kbytes);
+    std::memcpy(pd.kops, it->second.kops, sizeof pd.kops);
+    pd.mf_ops = it->second.mf_ops;
+    pd.mf_bytes = it->second.mf_bytes;
+    pd.kept_at = it->second.kept_at;
+    pd.host = ar.host;
+    pd.graph = 2;
+  } else if (++c->graph_seen[sig] < 2) {
+    if (c->graph_seen.size() > 1024) c->graph_seen.clear();
+    STCHK(launch_all(s));
+  } else {
+    // second sighting: capture on the private stream, then launch on s
+    if (!c->capture) HIPCHK(hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking));
+    tm.off = true;
+    HIPCHK(hipStreamBeginCapture(c->capture, hipStreamCaptureModeRelaxed));
+    const imf_status st = launch_all(c->capture);
+    hipGraph_t gr = nullptr;
+    const hipError_t e1 = hipStreamEndCapture(c->capture, &gr);
+    if (st != IMF_OK) {
+      if (gr) hipGraphDestroy(gr);
+      return st;
+    }
+    if (e1 != hipSuccess) return fail(IMF_EDEVICE, "graph capture: %s", hipGetErrorString(e1));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e2 = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+    hipGraphDestroy(gr);
+    if (e2 != hipSuccess) return fail(IMF_EDEVICE, "graph instantiate: %s", hipGetErrorString(e2));
+    if (c->graphs.size() >= 32) {  // least recently used out
+      auto lru = c->graphs.begin();
+      for (auto i = c->graphs.begin(); i != c->graphs.end(); ++i)
+        if (i->second.tick < lru->second.tick) lru = i;
+      HIPCHK(hipStreamSynchronize(s));
+      hipGraphExecDestroy(lru->second.exec);
+      c->graphs.erase(lru);
+    }
+    auto& ge = c->graphs[sig];
+    ge.exec = ex;
+    std::memcpy(ge.kbytes, pd.kbytes, sizeof pd.kbytes);
+    std::memcpy(ge.kops, pd.kops, sizeof pd.kops);
+    ge.mf_ops = pd.mf_ops;
+    ge.mf_bytes = pd.mf_bytes;
+    ge.kept_at = pd.kept_at;
+    ge.tick = ++c->graph_tick;
+    c->graph_seen.erase(sig);
+    HIPCHK(hipGraphLaunch(ex, s));
+    pd.graph = 1;
+  }
   if (out->debug_overlap) {
     const imf_orient_desc& d = p.desc[out->debug_orient];
     for (int a = 0; a < 3; a++) {
@@ -1285,6 +1394,7 @@ static imf_status compute_finish(Pending& pd, imf_stats* st) {
     st->batch = p.B;
     st->cache_hits = pd.hits;
     st->cache_misses = pd.misses;
+    st->graph = pd.graph;
   } else {
     pd.tm.release();
   }

@@ -20,6 +20,7 @@ DIR_F64, DIR_LATTICE = 0, 1
 SHARP_ALL, SHARP_BOUNDARY, SHARP_TIP = 0, 1, 2
 METHOD_AUTO, METHOD_FFT, METHOD_DIRECT = 0, 1, 2
 FLAG_PLAIN, FLAG_MASK_SWEEP, FLAG_NO_CACHE, FLAG_PROFILE, FLAG_NO_BOUND = 1, 2, 4, 8, 16
+FLAG_NO_GRAPH = 32
 KERNEL_CLASSES = ("raster", "setup", "fwd_design", "tool_x", "tool_y", "tool_z",
                   "inv_z_product", "inv_y", "inv_x_c2r", "recheck", "levels", "minfilter",
                   "sweep", "finalize", "copies", "bound")
@@ -63,7 +64,8 @@ class _Stats(C.Structure):
                 ("cache_hits", C.c_int), ("cache_misses", C.c_int),
                 ("k_ms", C.c_double * 16), ("k_n", C.c_int * 16),
                 ("k_bytes", C.c_double * 16), ("k_ops", C.c_double * 16),
-                ("bound_blocks", C.c_longlong), ("bound_skipped", C.c_longlong)]
+                ("bound_blocks", C.c_longlong), ("bound_skipped", C.c_longlong),
+                ("graph", C.c_int)]
 
 
 @dataclass
@@ -86,6 +88,7 @@ class Stats:
     kernel_ops: dict
     bound_blocks: int
     bound_skipped: int
+    graph: int  # 0 kernel by kernel, 1 captured into a HIP graph, 2 graph replay
 
     @classmethod
     def _from(cls, s: _Stats):
@@ -95,7 +98,7 @@ class Stats:
         ko = {k: s.k_ops[i] for i, k in enumerate(KERNEL_CLASSES) if s.k_n[i]}
         return cls(s.F_max, s.guard_flags, s.max_frac_err, s.guard_band, list(s.t_ms),
                    s.model_bytes, tuple(s.P), s.n_orient, s.method, s.batch, s.cache_hits,
-                   s.cache_misses, kms, kn, kb, ko, s.bound_blocks, s.bound_skipped)
+                   s.cache_misses, kms, kn, kb, ko, s.bound_blocks, s.bound_skipped, s.graph)
 
 
 _lib = None
@@ -215,15 +218,23 @@ class Context:
         keep = (ids, nd, dd, design, fixture, domain)
         return r, keep, (nz, ny, nx), int(nd.sum())
 
-    def _outputs(self, shape, n_orient, masks, debug_orient, device, debug_numel=0):
+    def _outputs(self, shape, n_orient, masks, debug_orient, device, debug_numel=0, out=None):
         import torch
         nz, ny, nx = shape
-        o = {"imf": torch.empty(shape, dtype=torch.float32, device=device),
-             "imf_norm": torch.empty(shape, dtype=torch.float32, device=device),
-             "secluded": torch.empty(shape, dtype=torch.uint8, device=device)}
+        want = {"imf": (shape, torch.float32), "imf_norm": (shape, torch.float32),
+                "secluded": (shape, torch.uint8)}
         if masks:
-            o["masks"] = torch.empty((n_orient, nz, ny, (nx + 63) // 64), dtype=torch.int64,
-                                     device=device)
+            want["masks"] = ((n_orient, nz, ny, (nx + 63) // 64), torch.int64)
+        o = {}
+        for k, (shp, dt) in want.items():
+            t = None if out is None else out.get(k)
+            if t is None:
+                t = torch.empty(shp, dtype=dt, device=device)
+            elif (tuple(t.shape) != tuple(shp) and t.numel() != int(np.prod(shp))) or \
+                    t.dtype != dt or not t.is_contiguous() or t.device != device:
+                raise ValueError("output %r must be a contiguous %s tensor of shape %s on %s"
+                                 % (k, dt, shp, device))
+            o[k] = t
         co = _Outputs()
         co.imf, co.imf_norm, co.secluded = _ptr(o["imf"]), _ptr(o["imf_norm"]), \
             _ptr(o["secluded"])
@@ -245,12 +256,16 @@ class Context:
 
     def compute(self, design, fixture=None, domain=None, *, tools, dirs, dir_kind=DIR_F64,
                 sharp=SHARP_ALL, lam=0.0, tau=0.5, mask_theta_abs=-1.0, method=METHOD_AUTO,
-                batch=0, flags=0, masks=True, debug_orient=-1, debug_numel=0, stream=None):
-        """Run one request; returns a dict of device tensors and a Stats."""
+                batch=0, flags=0, masks=True, debug_orient=-1, debug_numel=0, stream=None,
+                out=None):
+        """Run one request; returns a dict of device tensors and a Stats.  `out`
+        may hold preallocated outputs ("imf", "imf_norm", "secluded", "masks"),
+        which a loop reuses so that its repeated requests replay one HIP graph."""
         r, keep, shape, n_orient = self._request(design, fixture, domain, tools, dirs,
                                                  dir_kind, sharp, lam, tau, mask_theta_abs,
                                                  method, batch, flags)
-        o, co = self._outputs(shape, n_orient, masks, debug_orient, design.device, debug_numel)
+        o, co = self._outputs(shape, n_orient, masks, debug_orient, design.device, debug_numel,
+                              out)
         st = _Stats()
         _check(_L().imf_compute(self._ctx, C.byref(r), C.byref(co), C.byref(st),
                                 _stream_handle(stream)))

@@ -139,3 +139,39 @@ def test_autotune_then_batch_is_used_and_results_unchanged(imf_mod):
             assert torch.equal(o[k], p[k]), k
     finally:
         ctx.close()
+
+
+def test_graph_replays_equal_eager(imf_mod):
+    """The second identical request is captured into a HIP graph and later
+    ones replay it; every replay equals the kernel-by-kernel result, with
+    other (eager) requests and synchronizations on the context in between."""
+    imf = imf_mod
+    d = W.design_density(40, seed=95)
+    fx = W.fixture_plate(d.shape, 3)
+    kw = dict(tools=W.TOOL_C3, dirs=W.fib_hemisphere(12), dir_kind=imf.DIR_F64, lam=0.01,
+              method=imf.METHOD_FFT)
+    other = W.design_3d_boxes_cyls(32, seed=96)
+    okw = dict(tools=W.TOOL_C2, dirs=W.lattice26()[:9], dir_kind=imf.DIR_LATTICE,
+               method=imf.METHOD_FFT)
+    ctx = imf.Context(0)
+    try:
+        dd, dfx, do = dev(d), dev(fx), dev(other)
+        # persistent outputs: the signature includes the output pointers
+        ref, _ = ctx.compute(dd, dfx, **kw, flags=imf.FLAG_NO_GRAPH)
+        ref = {k: v.clone() for k, v in ref.items()}
+        modes = []
+        keep = {k: torch.empty_like(v) for k, v in ref.items()}
+        for i in range(5):
+            for v in keep.values():
+                v.fill_(7)
+            o, st = ctx.compute(dd, dfx, **kw, out=keep)
+            modes.append(st.graph)
+            for k in ("imf", "imf_norm", "secluded", "masks"):
+                assert torch.equal(o[k], ref[k]), (i, k)
+            ctx.compute(do, **okw, flags=imf.FLAG_NO_GRAPH)   # eager work in between
+            torch.cuda.synchronize()
+        # the first sighting launches kernel by kernel, the second is captured,
+        # the rest replay
+        assert modes == [0, 1, 2, 2, 2], modes
+    finally:
+        ctx.close()
