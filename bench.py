@@ -165,6 +165,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also time a plain 1 GiB device copy (stream-copy bandwidth; the "
@@ -205,6 +206,11 @@ def main():
     ctx = imf.Context(0)
     kw = dict(tools=w.tool, dirs=w.dirs, dir_kind=imf.DIR_F64, lam=w.lam, tau=w.tau,
               method=imf.METHOD_FFT, batch=args.batch)
+    tuned = None
+    if not args.no_autotune and args.batch == 0:
+        t1 = time.perf_counter()
+        tuned = ctx.autotune(design, fixture, **kw)
+        log("autotune: batch %d (%.1f s)" % (tuned, time.perf_counter() - t1))
     for i in range(args.warmup):
         _, st = ctx.compute(design, fixture, **kw)
         log("warmup %d: %.1f ms (cache hits %d, misses %d)" % (i, st.t_ms[7], st.cache_hits,
@@ -310,7 +316,8 @@ def main():
                                "r14 L60, 130 Fibonacci-hemisphere orientations, lambda 0.01, "
                                "masks at lambda*F_max",
                    "grid": list(w.design.shape), "orientations": nR, "P": list(last.P),
-                   "batch": last.batch, "spectra": "cached (warm)"},
+                   "batch": last.batch, "autotuned": tuned is not None,
+                   "spectra": "cached (warm)"},
         "roofline": roofline,
         "roofline_transform_passes": fft,
         "cpu_baseline": cpu,

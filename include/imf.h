@@ -170,8 +170,12 @@ imf_status imf_wait(imf_ctx* ctx, uint64_t ticket, int timeout_ms, imf_stats* st
 /* Cancel a request that has not started; returns IMF_EBUSY if it is running. */
 imf_status imf_cancel(imf_ctx* ctx, uint64_t ticket);
 
-/* Time candidate batch widths for a request shape and remember the fastest
- * (used by later requests with batch = 0). */
+/* Autotune a request shape (method, grid, transform sizes) on a real request:
+ * time candidate batch widths, then block shapes (64x1x1, 32x2x1, 16x2x2,
+ * 16x4x1) and resident workgroups per CU (4, 6, 8) of the sharp-point minimum,
+ * each kernel by kernel after a warm-up, and remember the fastest; later
+ * requests of that shape with batch = 0 use it.  Results do not depend on the
+ * choice.  *best_batch receives the batch width. */
 imf_status imf_autotune(imf_ctx* ctx, const imf_request* req, const imf_outputs* out,
                         int* best_batch);
 

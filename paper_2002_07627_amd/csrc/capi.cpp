@@ -161,7 +161,14 @@ struct imf_ctx {
   std::vector<void*> raster_pools;
   std::map<std::string, SpecEntry> spectra;
   std::map<int, float2*> twiddles;
-  std::map<std::string, int> tuned_batch;
+  // autotuned launch parameters per request shape (method, grid, transform sizes)
+  struct Tuned {
+    int batch = 8;     // orientations per batch
+    int shape = -1;    // block shape of the sharp-point minimum (-1: context default)
+    int wg = 0;        // resident workgroups per CU of its list pass (0: context default)
+  };
+  std::map<std::string, Tuned> tuned;
+  int force_shape = -1, force_wg = 0;  // set while the autotuner times a candidate
   uint64_t tick = 0;
   Arena arena;
   hipStream_t internal = nullptr;
@@ -563,6 +570,7 @@ struct Plan {
   bool theta_known, two_phase, masks, sweep, cache, bnb;
   int shape;
   long long cell_stride, nblocks, cell_waves, nwords_blk;
+  int tuned_batch = 8, tuned_shape = 2, wg_per_cu = 4;  // launch parameters in effect
   double theta;
   double band;
   // workspace layout (bytes)
@@ -586,6 +594,29 @@ static imf_status validate(const imf_request* r) {
   if (r->method < 0 || r->method > 2) return fail(IMF_EINVAL, "unknown method");
   if (r->batch < 0 || r->batch > 64) return fail(IMF_EINVAL, "batch must be in [0, 64]");
   return IMF_OK;
+}
+
+static std::string tune_key(const Plan& p) {
+  char key[96];
+  snprintf(key, sizeof key, "%d|%d,%d,%d|%d,%d,%d", p.method, p.n[0], p.n[1], p.n[2], p.P[0],
+           p.P[1], p.P[2]);
+  return key;
+}
+
+// launch parameters for a plan: the autotuned ones for its shape if any, else
+// the context defaults; a candidate being timed by the autotuner overrides both
+static void ctx_tuned_params(imf_ctx* c, Plan& p) {
+  p.tuned_batch = 8;
+  p.tuned_shape = c->mf_shape;
+  p.wg_per_cu = c->mf_wg_per_cu;
+  auto it = c->tuned.find(tune_key(p));
+  if (it != c->tuned.end()) {
+    p.tuned_batch = it->second.batch;
+    if (it->second.shape >= 0) p.tuned_shape = it->second.shape;
+    if (it->second.wg > 0) p.wg_per_cu = it->second.wg;
+  }
+  if (c->force_shape >= 0) p.tuned_shape = c->force_shape;
+  if (c->force_wg > 0) p.wg_per_cu = c->force_wg;
 }
 
 static imf_status make_plan(imf_ctx* c, const imf_request* r, const imf_outputs* out,
@@ -659,13 +690,8 @@ static imf_status make_plan(imf_ctx* c, const imf_request* r, const imf_outputs*
   // batch width
   const bool plain = (r->flags & IMF_FLAG_PLAIN) != 0;
   p.B = r->batch;
-  if (p.B == 0) {
-    char key[96];
-    snprintf(key, sizeof key, "%d|%d,%d,%d|%d,%d,%d", p.method, p.n[0], p.n[1], p.n[2], p.P[0],
-             p.P[1], p.P[2]);
-    auto it = c->tuned_batch.find(key);
-    p.B = it != c->tuned_batch.end() ? it->second : 8;
-  }
+  ctx_tuned_params(c, p);
+  if (p.B == 0) p.B = p.tuned_batch;
   if (plain) p.B = 1;
   p.B = std::max(1, std::min(p.B, p.nO));
   // thresholds
@@ -697,7 +723,7 @@ static imf_status make_plan(imf_ctx* c, const imf_request* r, const imf_outputs*
   }
   // branch and bound for the sharp-point minimum (not in the plain comparator)
   p.bnb = !plain && !(r->flags & IMF_FLAG_NO_BOUND);
-  p.shape = p.nd == 2 ? 0 : c->mf_shape;
+  p.shape = p.nd == 2 ? 0 : p.tuned_shape;
   {
     int wx, wy, wz;
     imf_block_dims(p.shape, wx, wy, wz);
@@ -1230,7 +1256,7 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
     ma.theta_known = p.theta_known;
     ma.q0 = q0;
     ma.n_cu = c->n_cu;
-    ma.wg_per_cu = c->mf_wg_per_cu;
+    ma.wg_per_cu = p.wg_per_cu;
     ma.skipped = (unsigned long long*)(misc + 8);
     HIPCHK(imf_launch_minfilter(ma, s, 0));
     tm.mark(10);
@@ -1544,33 +1570,62 @@ extern "C" imf_status imf_autotune(imf_ctx* c, const imf_request* r, const imf_o
                                    int* best_batch) {
   if (!c || !r || !out) return fail(IMF_EINVAL, "NULL argument");
   std::lock_guard<std::recursive_mutex> lk(c->mu);
-  double best = 1e300;
-  int pick = 8;
   Plan p0;
   std::vector<Orient> os;
   STCHK(enumerate(c, r, os));
   STCHK(ensure_rasters(c, r, os, c->internal));
   STCHK(make_plan(c, r, out, os, p0));
-  for (int B : {1, 2, 4, 8, 12, 16}) {
-    if (B > p0.nO && B != 1) break;
+  // time one candidate: a warm-up request (fills the spectrum cache), then the
+  // faster of two timed ones, kernel by kernel
+  auto time_one = [&](int B, int shape, int wg, double& ms) -> imf_status {
     imf_request rr = *r;
     rr.batch = B;
+    rr.flags |= IMF_FLAG_NO_GRAPH;
+    rr.flags &= ~(unsigned)IMF_FLAG_PROFILE;
+    c->force_shape = shape;
+    c->force_wg = wg;
     imf_stats st;
-    // warm (spectra cached), then timed
-    imf_status s1 = compute_impl(c, &rr, out, &st, c->internal, c->arena);
+    ms = 1e300;
+    imf_status s1 = IMF_OK;
+    for (int k = 0; k < 3 && s1 == IMF_OK; k++) {
+      s1 = compute_impl(c, &rr, out, &st, c->internal, c->arena);
+      if (k > 0 && s1 == IMF_OK) ms = std::min(ms, st.t_ms[7]);
+    }
+    c->force_shape = -1;
+    c->force_wg = 0;
+    return s1;
+  };
+  imf_ctx::Tuned best;
+  best.shape = p0.tuned_shape;
+  best.wg = p0.wg_per_cu;
+  double best_ms = 1e300;
+  // batch width with the current tile shapes
+  for (int B : {1, 2, 4, 8, 12, 16}) {
+    if (B > p0.nO && B != 1) break;
+    double ms;
+    const imf_status s1 = time_one(B, best.shape, best.wg, ms);
     if (s1 == IMF_ENOMEM) break;
     STCHK(s1);
-    STCHK(compute_impl(c, &rr, out, &st, c->internal, c->arena));
-    if (st.t_ms[7] < best) {
-      best = st.t_ms[7];
-      pick = B;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best.batch = B;
     }
   }
-  char key[96];
-  snprintf(key, sizeof key, "%d|%d,%d,%d|%d,%d,%d", p0.method, p0.n[0], p0.n[1], p0.n[2],
-           p0.P[0], p0.P[1], p0.P[2]);
-  c->tuned_batch[key] = pick;
-  if (best_batch) *best_batch = pick;
+  // block shape and resident grid of the sharp-point minimum (3D only)
+  if (p0.nd == 3)
+    for (int shape : {2, 0, 1, 3})
+      for (int wg : {4, 6, 8}) {
+        if (shape == best.shape && wg == best.wg) continue;
+        double ms;
+        STCHK(time_one(best.batch, shape, wg, ms));
+        if (ms < best_ms) {
+          best_ms = ms;
+          best.shape = shape;
+          best.wg = wg;
+        }
+      }
+  c->tuned[tune_key(p0)] = best;
+  if (best_batch) *best_batch = best.batch;
   return IMF_OK;
 }
 
