@@ -133,3 +133,56 @@ def test_c3_256_density_130_sampled_within_tolerance(ctx):
         gq = oracle.gamma_at(req, q, pts) / Q
         clear = np.abs(gq - theta) > 2 * max(1e-4 * theta, tolabs)
         assert np.array_equal(bits_at(masks, q, pts)[clear], (gq <= theta)[clear]), q
+
+
+def test_c5_384_density_512_loop_sampled():
+    """The 384^3 density TO-loop workload (512 orientations, flat cutter,
+    fixtures and clamps; the spectra do not all fit the cache): f at a voxel
+    against all 512 exact gammas, sampled mask bits, and a perturbed-design
+    iteration on the warm context equal to the same request on a fresh one."""
+    import paper_2002_07627_amd as imf
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    w = W.c5()
+    kw = dict(tools=w.tool, dirs=w.dirs, dir_kind=imf.DIR_F64, lam=w.lam, tau=w.tau,
+              method=imf.METHOD_FFT)
+    d1 = W.perturb_density(w.design, seed=7627006)
+    fx = dev(w.fixture)
+    ctx = imf.Context(0)
+    try:
+        out, st = ctx.compute(dev(w.design), fx, **kw)
+        assert st.n_orient == 512
+        F_max = st.F_max
+        f0 = out["imf"].cpu().numpy()
+        rng = np.random.default_rng(384)
+        om = w.fixture == 0
+        pts = sample_voxels(rng, om, 8)
+        m = out["masks"]
+        bits = {q: bits_at(m[q:q + 1].cpu().numpy(), 0, pts) for q in (3, 200, 511)}
+        del out, m
+        o1, s1 = ctx.compute(dev(d1), fx, **kw)
+        assert s1.cache_hits > 0 and s1.cache_misses > 0
+        warm = {k: o1[k].cpu() for k in ("imf", "imf_norm", "secluded")}
+        del o1
+    finally:
+        ctx.close()
+    torch.cuda.empty_cache()
+    fresh_ctx = imf.Context(0)
+    try:
+        o2, _ = fresh_ctx.compute(dev(d1), fx, **kw)
+        for k in warm:
+            assert torch.equal(o2[k].cpu(), warm[k]), k
+        del o2
+    finally:
+        fresh_ctx.close()
+    Q = float(1 << 24)
+    req = oracle.Request(w.design, w.fixture, tools=w.tool, dirs=w.dirs, dir_kind=0, lam=w.lam)
+    tolabs = 1e-4 * w.lam * F_max
+    x = pts[:1]
+    gam = oracle.gamma_at_all(req, x)[:, 0] / Q
+    assert abs(float(f0[x[0, 2], x[0, 1], x[0, 0]]) - gam.min()) <= max(1e-4 * gam.min(), tolabs)
+    theta = w.lam * F_max
+    for q, b in bits.items():
+        gq = oracle.gamma_at(req, q, pts) / Q
+        clear = np.abs(gq - theta) > 2 * max(1e-4 * theta, tolabs)
+        assert np.array_equal(b[clear], (gq <= theta)[clear]), q
