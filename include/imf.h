@@ -179,6 +179,31 @@ imf_status imf_cancel(imf_ctx* ctx, uint64_t ticket);
 imf_status imf_autotune(imf_ctx* ctx, const imf_request* req, const imf_outputs* out,
                         int* best_batch);
 
+/* ----------------------------------------- coupling to the TO loop (Sec. 3) -- */
+/* Heaviside projection of the design variables (Eq. Heaviside):
+ * rho = 1 - exp(-beta xi) + xi exp(-beta), in float64 with xi clamped to [0, 1],
+ * then rounded to the nearest multiple of 2^-24 (halves up), so that rho can be
+ * the density design of a request.  xi and rho: device arrays of n floats
+ * (may alias).  Stream-ordered on `stream`. */
+imf_status imf_heaviside(imf_ctx* ctx, long long n, const float* xi, double beta, float* rho,
+                         void* stream);
+/* Accessibility filter (Eq. accFilter) from a request's outputs:
+ * filter = fbar (imf_norm, the allowance-applied normalized IMF) where the
+ * design is solid (rho > tau), 1 on the secluded set (secluded != 0), 0 elsewhere.
+ * With sens_phi != NULL also the filtered sensitivity (Eq. filtered_sens):
+ * sens_out = (1 - w_acc) S_phi / max_{Omega_0} |S_phi| + w_acc filter (the
+ * normalization is 0 where that maximum is 0), float64 arithmetic.  Omega_0 is
+ * `domain` != 0 if given, else fixture == 0, else everything.  All arrays are
+ * device arrays of nx*ny*nz elements laid out as a request's grids; design is
+ * uint8 {0,1} or float32 (design_is_density).  0 <= w_acc <= 1.  The
+ * normalization uses one device word of the context: calls that overlap on
+ * different streams of one context must be ordered by the caller. */
+imf_status imf_access_filter(imf_ctx* ctx, int nx, int ny, int nz, const void* design,
+                             int design_is_density, const uint8_t* fixture,
+                             const uint8_t* domain, const float* imf_norm,
+                             const uint8_t* secluded, double tau, const float* sens_phi,
+                             double w_acc, float* filter_out, float* sens_out, void* stream);
+
 /* ------------------------------------------------- single steps (checks) -- */
 /* Raster of one oriented tool (the Rotate step): offsets (x, y, z) in z, y, x
  * order into host arrays (voxels of the tool and the sharp points); flags bit 0 =

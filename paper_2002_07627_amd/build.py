@@ -11,11 +11,12 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libimf.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["capi.cpp", "k_raster.hip", "k_fft.hip", "k_imf.hip"]
+SOURCES = ["capi.cpp", "k_raster.hip", "k_fft.hip", "k_imf.hip", "k_couple.hip"]
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
           "-Wno-unused-function", "-Wno-unused-value", "-Wno-unused-result", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-# the rasterization predicate is evaluated exactly in the order written
-EXTRA = {"k_raster.hip": ["-ffp-contract=off"]}
+# the rasterization predicate and the coupling arithmetic are evaluated exactly
+# in the order written
+EXTRA = {"k_raster.hip": ["-ffp-contract=off"], "k_couple.hip": ["-ffp-contract=off"]}
 
 
 def _compile(src: str) -> str:

@@ -196,6 +196,7 @@ struct imf_ctx {
   std::unordered_map<std::string, int> graph_seen;
   uint64_t graph_tick = 0;
   hipStream_t capture = nullptr;  // private stream graphs are captured on
+  unsigned int* couple_scratch = nullptr;  // device word for the coupling reductions
   int mf_shape = 2;  // wave block shape of the sharp-point minimum (imf_block_dims)
   int n_cu = 256;     // compute units of the device
   int mf_wg_per_cu = 4;  // resident workgroups per CU of the sharp-point minimum (list pass)
@@ -296,6 +297,7 @@ extern "C" imf_status imf_destroy(imf_ctx* c) {
     if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
   if (c->internal) hipStreamDestroy(c->internal);
   if (c->capture) hipStreamDestroy(c->capture);
+  if (c->couple_scratch) hipFree(c->couple_scratch);
   delete c;
   return IMF_OK;
 }
@@ -1566,6 +1568,49 @@ extern "C" imf_status imf_fft_r2c_3d(imf_ctx* c, int nx, int ny, int nz, int px,
 // ---------------------------------------------------------------------------
 // autotune: time batch widths on a real request and keep the fastest
 // ---------------------------------------------------------------------------
+extern "C" imf_status imf_heaviside(imf_ctx* c, long long n, const float* xi, double beta,
+                                    float* rho, void* stream) {
+  if (!c || (n > 0 && (!xi || !rho))) return fail(IMF_EINVAL, "NULL argument");
+  if (n < 0 || !std::isfinite(beta) || beta < 0) return fail(IMF_EINVAL, "n >= 0 and beta >= 0");
+  if (n == 0) return IMF_OK;
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  HIPCHK(hipSetDevice(c->device));
+  HIPCHK(imf_launch_heaviside(xi, n, beta, rho, (hipStream_t)stream));
+  return IMF_OK;
+}
+
+extern "C" imf_status imf_access_filter(imf_ctx* c, int nx, int ny, int nz, const void* design,
+                                        int design_is_density, const uint8_t* fixture,
+                                        const uint8_t* domain, const float* imf_norm,
+                                        const uint8_t* secluded, double tau,
+                                        const float* sens_phi, double w_acc, float* filter_out,
+                                        float* sens_out, void* stream) {
+  if (!c || !design || !imf_norm || !secluded || !filter_out)
+    return fail(IMF_EINVAL, "NULL argument");
+  if (nx <= 0 || ny <= 0 || nz <= 0) return fail(IMF_EINVAL, "grid sizes must be positive");
+  if (sens_phi && (!sens_out || !(w_acc >= 0 && w_acc <= 1)))
+    return fail(IMF_EINVAL, "sens_out is NULL or w_acc outside [0, 1]");
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  HIPCHK(hipSetDevice(c->device));
+  if (!c->couple_scratch) HIPCHK(hipMalloc(&c->couple_scratch, 256));
+  imf_couple_args a{};
+  a.n = (long long)nx * ny * nz;
+  a.design = design;
+  a.density = design_is_density;
+  a.fixture = fixture;
+  a.domain = domain;
+  a.imf_norm = imf_norm;
+  a.secluded = secluded;
+  a.tau = tau;
+  a.filt = filter_out;
+  a.sens = sens_phi;
+  a.w = w_acc;
+  a.sens_out = sens_out;
+  a.smax = c->couple_scratch;
+  HIPCHK(imf_launch_access_filter(a, (hipStream_t)stream));
+  return IMF_OK;
+}
+
 extern "C" imf_status imf_autotune(imf_ctx* c, const imf_request* r, const imf_outputs* out,
                                    int* best_batch) {
   if (!c || !r || !out) return fail(IMF_EINVAL, "NULL argument");

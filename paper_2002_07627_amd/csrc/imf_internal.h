@@ -221,3 +221,17 @@ hipError_t imf_launch_finalize(const float* f, const uint8_t* omega0, const void
 hipError_t imf_launch_masks_from_gamma(const float* gamma_stack, int nq, const uint8_t* omega0,
                                        int nx, int ny, int nz, const unsigned int* fmax_bits,
                                        double lambda, uint64_t* masks, hipStream_t s);
+
+// coupling to the TO loop (Sec. 3)
+hipError_t imf_launch_heaviside(const float* xi, long long n, double beta, float* rho,
+                                hipStream_t s);
+struct imf_couple_args {
+  long long n;
+  const void* design; int density;       // rho_Omega (uint8 {0,1} or float32)
+  const uint8_t* fixture; const uint8_t* domain;  // Omega_0 as in a request
+  const float* imf_norm; const uint8_t* secluded; double tau;
+  float* filt;                           // out: Sbar_IMF
+  const float* sens; double w; float* sens_out;   // optional: S_phi in, S out
+  unsigned int* smax;                    // device scratch: max |S_phi| over Omega_0
+};
+hipError_t imf_launch_access_filter(const imf_couple_args& a, hipStream_t s);

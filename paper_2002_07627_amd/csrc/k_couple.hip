@@ -1,0 +1,99 @@
+// Steps that couple the IMF to a density-based TO loop (Sec. 3): the
+// Heaviside projection of the design variables (Eq. Heaviside), the
+// accessibility filter (Eq. accFilter) and the filtered sensitivity
+// (Eq. filtered_sens).  Pointwise and HBM-bound; float64 arithmetic, compiled
+// without FP contraction so that every operation rounds as written.
+#include "imf_internal.h"
+
+#define Q24 16777216.0
+
+static unsigned grid_of(long long n) {
+  const long long b = (n + 255) / 256;
+  return (unsigned)(b < 65536 ? (b > 0 ? b : 1) : 65536);
+}
+
+// rho = 1 - exp(-beta xi) + xi exp(-beta), xi clamped to [0, 1], rounded to
+// the nearest multiple of 2^-24 (halves up) and clamped to [0, 1]
+__global__ void k_heaviside(const float* __restrict__ xi, long long n, double beta,
+                            float* __restrict__ rho) {
+  const double eb = exp(-beta);
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    double x = (double)xi[i];
+    x = x < 0.0 ? 0.0 : (x > 1.0 ? 1.0 : x);
+    const double r = (1.0 - exp(-beta * x)) + x * eb;
+    double q = floor(r * Q24 + 0.5) / Q24;
+    q = q < 0.0 ? 0.0 : (q > 1.0 ? 1.0 : q);
+    rho[i] = (float)q;
+  }
+}
+
+hipError_t imf_launch_heaviside(const float* xi, long long n, double beta, float* rho,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_heaviside, dim3(grid_of(n)), dim3(256), 0, s, xi, n, beta, rho);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_u32_couple(unsigned int* p) {
+  if (threadIdx.x == 0) *p = 0u;
+}
+
+__device__ __forceinline__ bool in_omega0(const uint8_t* fixture, const uint8_t* domain,
+                                          long long i) {
+  return domain ? domain[i] != 0 : (fixture ? fixture[i] == 0 : true);
+}
+
+// Sbar_IMF: fbar on Omega = [rho > tau], 1 on Gamma, 0 elsewhere; and the
+// largest |S_phi| over Omega_0 (non-negative floats order as their bits)
+__global__ void k_access_filter(const void* __restrict__ design, int density,
+                                const float* __restrict__ imf_norm,
+                                const uint8_t* __restrict__ secluded, double tau, long long n,
+                                float* __restrict__ filt, const float* __restrict__ sens,
+                                const uint8_t* __restrict__ fixture,
+                                const uint8_t* __restrict__ domain,
+                                unsigned int* __restrict__ smax) {
+  float m = 0.f;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double rho = density ? (double)((const float*)design)[i]
+                               : (double)((const uint8_t*)design)[i];
+    float v = secluded[i] ? 1.f : 0.f;
+    if (rho > tau) v = imf_norm[i];
+    filt[i] = v;
+    if (sens && in_omega0(fixture, domain, i)) m = fmaxf(m, fabsf(sens[i]));
+  }
+  if (sens) {
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) atomicMax(smax, __float_as_uint(m));
+  }
+}
+
+// S = (1 - w) S_phi / max|S_phi| + w Sbar_IMF
+__global__ void k_filtered_sens(const float* __restrict__ sens, const float* __restrict__ filt,
+                                long long n, double w, const unsigned int* __restrict__ smax,
+                                float* __restrict__ out) {
+  const double m = (double)__uint_as_float(*smax);
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double sb = m > 0.0 ? (double)sens[i] / m : 0.0;
+    out[i] = (float)((1.0 - w) * sb + w * (double)filt[i]);
+  }
+}
+
+hipError_t imf_launch_access_filter(const imf_couple_args& a, hipStream_t s) {
+  hipError_t e;
+  if (a.sens) {
+    hipLaunchKernelGGL(k_fill_u32_couple, dim3(1), dim3(64), 0, s, a.smax);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_access_filter, dim3(grid_of(a.n)), dim3(256), 0, s, a.design, a.density,
+                     a.imf_norm, a.secluded, a.tau, a.n, a.filt, a.sens, a.fixture, a.domain,
+                     a.smax);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (a.sens && a.sens_out) {
+    hipLaunchKernelGGL(k_filtered_sens, dim3(grid_of(a.n)), dim3(256), 0, s, a.sens, a.filt, a.n,
+                       a.w, a.smax, a.sens_out);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}

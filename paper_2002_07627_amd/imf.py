@@ -318,6 +318,37 @@ class Context:
         _check(_L().imf_autotune(self._ctx, C.byref(r), C.byref(co), C.byref(b)))
         return b.value
 
+    # -------------------------------------------------- coupling to the TO loop
+    def heaviside(self, xi, beta: float, out=None, stream=None):
+        """Heaviside projection of design variables (float32 device tensor),
+        rounded to the 2^-24 grid: usable as the density design of a request."""
+        import torch
+        if xi.dtype != torch.float32 or not xi.is_cuda or not xi.is_contiguous():
+            raise ValueError("xi must be a contiguous float32 device tensor")
+        rho = torch.empty_like(xi) if out is None else out
+        _check(_L().imf_heaviside(self._ctx, C.c_longlong(xi.numel()), _ptr(xi),
+                                  C.c_double(beta), _ptr(rho), _stream_handle(stream)))
+        return rho
+
+    def access_filter(self, design, imf_norm, secluded, fixture=None, domain=None, *, tau=0.5,
+                      sens=None, w=0.0, stream=None):
+        """Accessibility filter (and, with `sens`, the filtered sensitivity) from a
+        request's outputs; returns (filter, filtered sensitivity or None)."""
+        import torch
+        shape = design.shape if design.dim() == 3 else (1,) + tuple(design.shape)
+        nz, ny, nx = shape
+        for t in (design, imf_norm, secluded, fixture, domain, sens):
+            if t is not None and (not t.is_cuda or not t.is_contiguous()
+                                  or t.numel() != design.numel()):
+                raise ValueError("all fields must be contiguous device tensors of the design's size")
+        filt = torch.empty(design.shape, dtype=torch.float32, device=design.device)
+        so = torch.empty_like(filt) if sens is not None else None
+        _check(_L().imf_access_filter(
+            self._ctx, nx, ny, nz, _ptr(design), int(design.dtype == torch.float32),
+            _ptr(fixture), _ptr(domain), _ptr(imf_norm), _ptr(secluded), C.c_double(tau),
+            _ptr(sens), C.c_double(w), _ptr(filt), _ptr(so), _stream_handle(stream)))
+        return filt, so
+
     # -------------------------------------------------------------- single steps
     def raster(self, tool: dict, d, dir_kind=None, sharp=SHARP_ALL):
         """(offsets int32 [n, 3] as x, y, z; flags uint8 [n]) of one oriented tool."""

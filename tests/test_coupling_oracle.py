@@ -1,0 +1,62 @@
+"""Pins of the TO-coupling oracle (Sec. 3: Eqs. Heaviside, accFilter,
+filtered_sens) against closed forms, limits and hand-checked cases."""
+import math
+
+import numpy as np
+
+from oracle import coupling as cp
+
+
+def test_heaviside_end_points_and_grid():
+    for beta in (0.5, 2.0, 8.0, 30.0):
+        r = cp.heaviside([0.0, 1.0, -0.3, 1.7], beta)
+        assert r.tolist() == [0.0, 1.0, 0.0, 1.0]      # rho(0) = 0, rho(1) = 1, clamped
+    x = np.linspace(0, 1, 10001)
+    r = cp.heaviside(x, 8.0).astype(np.float64)
+    assert np.array_equal(r * 2 ** 24, np.round(r * 2 ** 24))   # on the 2^-24 grid
+    assert (np.diff(r) >= 0).all()                              # monotone for beta > 0
+
+
+def test_heaviside_limits():
+    x = np.linspace(0, 1, 1001)
+    # beta -> 0: 1 - e^{-b x} + x e^{-b} = x + O(b)  (identity projection)
+    r = cp.heaviside(x, 1e-9).astype(np.float64)
+    assert np.abs(r - x).max() <= 2 ** -24
+    # beta large: a step; with beta = 60 every x >= 0.3 has 1 - rho = e^{-60 x}
+    # (1 - x) < 2^-25 and rounds to 1, and x = 0.01 gives 1 - e^{-0.6} (+ ~0)
+    r = cp.heaviside(x[300:], 60.0).astype(np.float64)
+    assert (r == 1.0).all()
+    assert abs(float(cp.heaviside([0.01], 60.0)[0]) - (1 - math.exp(-0.6))) < 2 ** -24
+    # slope at 0 is beta + e^{-beta}
+    b = 2.0
+    h = 1e-3
+    slope = float(cp.heaviside([h], b)[0]) / h
+    assert abs(slope - (b + math.exp(-b))) < 2e-3 * b
+
+
+def test_access_filter_cases():
+    design = np.array([0.2, 0.7, 0.4, 0.9, 0.5], np.float32)
+    fbar = np.array([0.3, 0.6, 0.8, 0.0, 0.9], np.float32)
+    sec = np.array([0, 0, 1, 0, 1], np.uint8)
+    f = cp.access_filter(design, fbar, sec, tau=0.5)
+    # void not secluded -> 0; solid -> fbar; secluded void -> 1; solid with
+    # fbar 0 -> 0; rho == tau is void -> secluded -> 1
+    assert f.tolist() == [0.0, np.float32(0.6), 1.0, 0.0, 1.0]
+
+
+def test_filtered_sensitivity_is_a_convex_combination():
+    rng = np.random.default_rng(3)
+    s = rng.normal(size=1000).astype(np.float32)
+    filt = rng.random(1000).astype(np.float32)
+    om = rng.random(1000) < 0.8
+    m = np.abs(s[om]).max()
+    out = cp.filtered_sensitivity(s, filt, 0.0, om)
+    assert np.allclose(out, s / m, rtol=0, atol=1e-7)
+    assert np.abs(out[om]).max() == np.float32(1.0)
+    out = cp.filtered_sensitivity(s, filt, 1.0, om)
+    assert np.array_equal(out, filt)
+    w = 0.3
+    out = cp.filtered_sensitivity(s, filt, w, om).astype(np.float64)
+    assert np.allclose(out, (1 - w) * s / m + w * filt, atol=1e-7)
+    assert np.array_equal(cp.filtered_sensitivity(np.zeros(5), np.ones(5), 0.5,
+                                                  np.ones(5, bool)), np.full(5, 0.5, np.float32))
