@@ -204,6 +204,22 @@ imf_status imf_access_filter(imf_ctx* ctx, int nx, int ny, int nz, const void* d
                              const uint8_t* secluded, double tau, const float* sens_phi,
                              double w_acc, float* filter_out, float* sens_out, void* stream);
 
+/* Greedy machining plan (Sec. 4, post-processing): starting from the negative
+ * space N = Omega_0 and [rho <= tau] (rho the design, Omega_0 as in a request),
+ * repeatedly choose the orientation whose accessible mask covers the most of
+ * what remains (ties: the lowest orientation index), remove that part, and stop
+ * when no orientation removes anything or after max_steps steps.  acc_masks:
+ * device [n_orient][nz][ny][ceil(nx/64)] as written by imf_compute.  Host
+ * outputs: orient_out[max_steps] and removed_out[max_steps] (voxels removed by
+ * each step), *n_steps, and *remaining (voxels of N no orientation reaches,
+ * or left after max_steps).  Returns when done (the plan is read on the host
+ * step by step). */
+imf_status imf_plan_greedy(imf_ctx* ctx, int nx, int ny, int nz, int n_orient,
+                           const uint64_t* acc_masks, const void* design, int design_is_density,
+                           const uint8_t* fixture, const uint8_t* domain, double tau,
+                           int max_steps, int* orient_out, long long* removed_out, int* n_steps,
+                           long long* remaining, void* stream);
+
 /* ------------------------------------------------- single steps (checks) -- */
 /* Raster of one oriented tool (the Rotate step): offsets (x, y, z) in z, y, x
  * order into host arrays (voxels of the tool and the sharp points); flags bit 0 =

@@ -12,6 +12,8 @@ definitions:
   Sbar_phi the objective sensitivity divided by its maximum magnitude over
   Omega_0 (the paper says "normalized" without the norm; 0 when that maximum
   is 0).
+* Greedy machining plan (Sec. 4, post-processing): repeatedly the orientation
+  whose accessible set covers the most of the remaining negative space.
 
 Only the tests may import this module.
 """
@@ -56,3 +58,26 @@ def filtered_sensitivity(sens_phi, filt, w: float, omega0) -> np.ndarray:
     m = float(np.abs(s[om]).max()) if om.any() else 0.0
     sbar = s / m if m > 0 else np.zeros_like(s)
     return ((1.0 - w) * sbar + w * np.asarray(filt, np.float64)).astype(np.float32)
+
+
+def plan_greedy(masks_bool, design, tau: float = 0.5, omega0=None, max_steps=None):
+    """Greedy machining plan (Sec. 4): from the negative space
+    N = Omega_0 and [rho <= tau], repeatedly take the orientation whose
+    accessible set covers the most of what remains (lowest index on ties),
+    remove it, until nothing more is removable.  masks_bool: [n_orient, ...]
+    booleans of the grid's shape.  Returns ([(orientation, removed), ...],
+    remaining)."""
+    A = np.asarray(masks_bool, bool).reshape(len(masks_bool), -1)
+    rho = np.asarray(design, np.float64).reshape(-1)
+    om = np.ones_like(rho, bool) if omega0 is None else np.asarray(omega0, bool).reshape(-1)
+    R = om & (rho <= tau)
+    steps = []
+    limit = len(A) if max_steps is None else max_steps
+    while len(steps) < limit:
+        cover = [int(np.count_nonzero(A[q] & R)) for q in range(len(A))]
+        best = int(np.argmax(cover))  # first maximum
+        if cover[best] == 0:
+            break
+        steps.append((best, cover[best]))
+        R &= ~A[best]
+    return steps, int(np.count_nonzero(R))

@@ -1611,6 +1611,62 @@ extern "C" imf_status imf_access_filter(imf_ctx* c, int nx, int ny, int nz, cons
   return IMF_OK;
 }
 
+extern "C" imf_status imf_plan_greedy(imf_ctx* c, int nx, int ny, int nz, int n_orient,
+                                      const uint64_t* acc_masks, const void* design,
+                                      int design_is_density, const uint8_t* fixture,
+                                      const uint8_t* domain, double tau, int max_steps,
+                                      int* orient_out, long long* removed_out, int* n_steps,
+                                      long long* remaining, void* stream) {
+  if (!c || !acc_masks || !design || !n_steps || !remaining ||
+      (max_steps > 0 && (!orient_out || !removed_out)))
+    return fail(IMF_EINVAL, "NULL argument");
+  if (nx <= 0 || ny <= 0 || nz <= 0 || n_orient <= 0 || max_steps < 0)
+    return fail(IMF_EINVAL, "sizes must be positive");
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  HIPCHK(hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  const long long nw = (long long)nz * ny * ((nx + 63) / 64);
+  uint64_t* R = nullptr;
+  unsigned long long* counts = nullptr;
+  HIPCHK(hipMalloc(&R, sizeof(uint64_t) * nw));
+  if (hipMalloc(&counts, sizeof(unsigned long long) * (n_orient + 1)) != hipSuccess) {
+    hipFree(R);
+    return fail(IMF_ENOMEM, "plan scratch");
+  }
+  std::vector<unsigned long long> h(n_orient + 1);
+  imf_status st = IMF_OK;
+  auto run = [&]() -> imf_status {
+    HIPCHK(imf_launch_negative_bits(design, design_is_density, tau, fixture, domain, nx,
+                                    (long long)ny * nz, R, s));
+    int k = 0;
+    for (; k < max_steps; k++) {
+      HIPCHK(imf_launch_cover_count(acc_masks, n_orient, nw, R, counts, s));
+      HIPCHK(hipMemcpyAsync(h.data(), counts, sizeof(unsigned long long) * n_orient,
+                            hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      int best = 0;
+      for (int q = 1; q < n_orient; q++)
+        if (h[q] > h[best]) best = q;
+      if (h[best] == 0) break;
+      orient_out[k] = best;
+      removed_out[k] = (long long)h[best];
+      HIPCHK(imf_launch_cover_remove(acc_masks + (long long)best * nw, nw, R, s));
+    }
+    *n_steps = k;
+    // what is left: popcount of R (counted against an all-ones "mask" = R itself)
+    HIPCHK(imf_launch_cover_count(R, 1, nw, R, counts, s));
+    HIPCHK(hipMemcpyAsync(h.data(), counts, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    *remaining = (long long)h[0];
+    return IMF_OK;
+  };
+  st = run();
+  hipStreamSynchronize(s);
+  hipFree(R);
+  hipFree(counts);
+  return st;
+}
+
 extern "C" imf_status imf_autotune(imf_ctx* c, const imf_request* r, const imf_outputs* out,
                                    int* best_batch) {
   if (!c || !r || !out) return fail(IMF_EINVAL, "NULL argument");

@@ -235,3 +235,10 @@ struct imf_couple_args {
   unsigned int* smax;                    // device scratch: max |S_phi| over Omega_0
 };
 hipError_t imf_launch_access_filter(const imf_couple_args& a, hipStream_t s);
+// greedy machining plan (Sec. 4)
+hipError_t imf_launch_negative_bits(const void* design, int density, double tau,
+                                    const uint8_t* fixture, const uint8_t* domain, int nx,
+                                    long long rows, uint64_t* R, hipStream_t s);
+hipError_t imf_launch_cover_count(const uint64_t* masks, int nq, long long nw, const uint64_t* R,
+                                  unsigned long long* counts, hipStream_t s);
+hipError_t imf_launch_cover_remove(const uint64_t* A, long long nw, uint64_t* R, hipStream_t s);

@@ -97,3 +97,78 @@ hipError_t imf_launch_access_filter(const imf_couple_args& a, hipStream_t s) {
   }
   return hipSuccess;
 }
+
+// ---------------------------------------------------------------------------
+// Greedy machining plan (Sec. 4, post-processing): the negative space to
+// remove, N = Omega_0 and [rho <= tau], as a bitset laid out like the masks;
+// per step the popcount of (A_q and R) for every orientation q, then
+// R = R and not A_q for the chosen one.
+// ---------------------------------------------------------------------------
+__global__ void k_negative_bits(const void* __restrict__ design, int density, double tau,
+                                const uint8_t* __restrict__ fixture,
+                                const uint8_t* __restrict__ domain, int nx, long long rows,
+                                uint64_t* __restrict__ R) {
+  const int words = (nx + 63) >> 6;
+  const long long wave = (long long)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (wave >= rows * words) return;
+  const long long row = wave / words;
+  const int x = (int)(wave % words) * 64 + (threadIdx.x & 63);
+  bool b = false;
+  if (x < nx) {
+    const long long i = row * nx + x;
+    const double rho = density ? (double)((const float*)design)[i]
+                               : (double)((const uint8_t*)design)[i];
+    b = in_omega0(fixture, domain, i) && rho <= tau;
+  }
+  const unsigned long long m = __ballot(b);
+  if ((threadIdx.x & 63) == 0) R[wave] = m;
+}
+
+__global__ void k_cover_count(const uint64_t* __restrict__ masks, long long nw,
+                              const uint64_t* __restrict__ R,
+                              unsigned long long* __restrict__ counts) {
+  const int q = blockIdx.y;
+  const uint64_t* A = masks + (long long)q * nw;
+  unsigned long long c = 0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nw;
+       i += (long long)gridDim.x * blockDim.x)
+    c += __popcll(A[i] & R[i]);
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(counts + q, c);
+}
+
+__global__ void k_cover_remove(const uint64_t* __restrict__ A, long long nw,
+                               uint64_t* __restrict__ R) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nw;
+       i += (long long)gridDim.x * blockDim.x)
+    R[i] &= ~A[i];
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0ull;
+}
+
+hipError_t imf_launch_negative_bits(const void* design, int density, double tau,
+                                    const uint8_t* fixture, const uint8_t* domain, int nx,
+                                    long long rows, uint64_t* R, hipStream_t s) {
+  const long long waves = rows * ((nx + 63) / 64);
+  hipLaunchKernelGGL(k_negative_bits, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, design,
+                     density, tau, fixture, domain, nx, rows, R);
+  return hipGetLastError();
+}
+
+hipError_t imf_launch_cover_count(const uint64_t* masks, int nq, long long nw, const uint64_t* R,
+                                  unsigned long long* counts, hipStream_t s) {
+  hipError_t e;
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(256), 0, s, counts, nq);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const long long per = (nw + 255) / 256;
+  const unsigned gx = (unsigned)(per < 64 ? (per > 0 ? per : 1) : 64);
+  hipLaunchKernelGGL(k_cover_count, dim3(gx, nq), dim3(256), 0, s, masks, nw, R, counts);
+  return hipGetLastError();
+}
+
+hipError_t imf_launch_cover_remove(const uint64_t* A, long long nw, uint64_t* R, hipStream_t s) {
+  hipLaunchKernelGGL(k_cover_remove, dim3(grid_of(nw)), dim3(256), 0, s, A, nw, R);
+  return hipGetLastError();
+}

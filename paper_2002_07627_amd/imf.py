@@ -349,6 +349,28 @@ class Context:
             _ptr(sens), C.c_double(w), _ptr(filt), _ptr(so), _stream_handle(stream)))
         return filt, so
 
+    def plan_greedy(self, masks, design, fixture=None, domain=None, *, tau=0.5, max_steps=None,
+                    stream=None):
+        """Greedy machining plan from a request's accessible masks: returns
+        ([(orientation, voxels removed), ...], voxels left)."""
+        shape = design.shape if design.dim() == 3 else (1,) + tuple(design.shape)
+        nz, ny, nx = shape
+        nq = masks.shape[0]
+        if masks.numel() != nq * nz * ny * ((nx + 63) // 64) or not masks.is_contiguous():
+            raise ValueError("masks must be the [n_orient][nz][ny][ceil(nx/64)] words of a request")
+        ms = nq if max_steps is None else int(max_steps)
+        orient = np.zeros(max(ms, 1), np.int32)
+        removed = np.zeros(max(ms, 1), np.int64)
+        n = C.c_int()
+        left = C.c_longlong()
+        import torch
+        _check(_L().imf_plan_greedy(
+            self._ctx, nx, ny, nz, nq, _ptr(masks), _ptr(design),
+            int(design.dtype == torch.float32), _ptr(fixture), _ptr(domain), C.c_double(tau), ms,
+            orient.ctypes.data_as(C.c_void_p), removed.ctypes.data_as(C.c_void_p), C.byref(n),
+            C.byref(left), _stream_handle(stream)))
+        return [(int(orient[i]), int(removed[i])) for i in range(n.value)], left.value
+
     # -------------------------------------------------------------- single steps
     def raster(self, tool: dict, d, dir_kind=None, sharp=SHARP_ALL):
         """(offsets int32 [n, 3] as x, y, z; flags uint8 [n]) of one oriented tool."""

@@ -20,7 +20,7 @@ def test_header_declares_the_boundary():
     for n in ("imf_create", "imf_destroy", "imf_compute", "imf_submit", "imf_wait",
               "imf_cancel", "imf_query_footprint", "imf_tool_register", "imf_autotune",
               "imf_raster", "imf_fft_c2c", "imf_fft_r2c_3d", "imf_last_error", "imf_fft_size",
-              "imf_heaviside", "imf_access_filter"):
+              "imf_heaviside", "imf_access_filter", "imf_plan_greedy"):
         assert n in names
 
 

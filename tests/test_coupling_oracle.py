@@ -60,3 +60,35 @@ def test_filtered_sensitivity_is_a_convex_combination():
     assert np.allclose(out, (1 - w) * s / m + w * filt, atol=1e-7)
     assert np.array_equal(cp.filtered_sensitivity(np.zeros(5), np.ones(5), 0.5,
                                                   np.ones(5, bool)), np.full(5, 0.5, np.float32))
+
+
+def test_greedy_plan_hand_case():
+    # 1D negative space of 10 voxels (design 0), three orientations
+    design = np.zeros(10)
+    design[[0, 9]] = 1                       # solid at both ends: N = voxels 1..8
+    A = np.zeros((3, 10), bool)
+    A[0, 1:4] = True                          # covers 3
+    A[1, 3:9] = True                          # covers 6 (largest)
+    A[2, 1:3] = True                          # covers 2, then 2 after step 1
+    steps, left = cp.plan_greedy(A, design)
+    assert steps == [(1, 6), (0, 2)] and left == 0
+    # ties go to the lowest index; unreachable voxels remain
+    A2 = np.zeros((2, 10), bool)
+    A2[0, 1:3] = A2[1, 5:7] = True
+    steps, left = cp.plan_greedy(A2, design)
+    assert steps == [(0, 2), (1, 2)] and left == 4
+    assert cp.plan_greedy(A2, design, max_steps=1) == ([(0, 2)], 6)
+
+
+def test_greedy_plan_invariants():
+    rng = np.random.default_rng(11)
+    A = rng.random((9, 500)) < 0.2
+    design = (rng.random(500) < 0.3).astype(np.float32)
+    om = rng.random(500) < 0.9
+    steps, left = cp.plan_greedy(A, design, omega0=om)
+    N = om & (design <= 0.5)
+    # what is left is exactly the negative space no orientation reaches
+    assert left == int(np.count_nonzero(N & ~A.any(0)))
+    # the removed counts sum to the reachable part and never increase
+    assert sum(r for _, r in steps) == int(np.count_nonzero(N & A.any(0)))
+    assert all(steps[i][1] >= steps[i + 1][1] for i in range(len(steps) - 1))

@@ -110,3 +110,32 @@ def test_coupled_loop_step_by_step(ctx):
         sref = cp.filtered_sensitivity(sens, fref, w, fx == 0)
         assert np.array_equal(s.cpu().numpy(), sref)
         xi = np.clip(xi - 0.05 * s.cpu().numpy(), 0, 1).astype(np.float32)
+
+
+def test_greedy_plan_matches_oracle(ctx):
+    """Greedy machining plan on a 64^3 binary part with 26 lattice directions:
+    the GPU plan equals the oracle plan on the same masks (which are themselves
+    bit-exact against the oracle), and on a small case the oracle's own masks."""
+    import paper_2002_07627_amd as imf
+    d = W.design_3d_boxes_cyls(64, seed=51)
+    fx = W.fixture_plate(d.shape, 3)
+    tl = W.tool(W.TOOL_FLAT, 1.5, 12, 4, 12)
+    dirs = W.lattice26()
+    out, _ = ctx.compute(dev(d), dev(fx), tools=tl, dirs=dirs, dir_kind=imf.DIR_LATTICE,
+                         method=imf.METHOD_FFT)
+    steps, left = ctx.plan_greedy(out["masks"], dev(d), dev(fx))
+    m = oracle.unpack_masks(out["masks"].cpu().numpy().view(np.uint64), 64)
+    ref_steps, ref_left = cp.plan_greedy(m, d, omega0=fx == 0)
+    assert steps == ref_steps and left == ref_left
+    assert len(steps) >= 2
+    s1, l1 = ctx.plan_greedy(out["masks"], dev(d), dev(fx), max_steps=1)
+    assert s1 == steps[:1] and l1 == left + sum(r for _, r in steps[1:])
+    # small case through the oracle's masks
+    d2 = W.design_3d_boxes_cyls(24, seed=52)
+    fx2 = W.fixture_plate(d2.shape, 2)
+    tl2 = W.tool(W.TOOL_FLAT, 1, 5, 2, 4)
+    out2, _ = ctx.compute(dev(d2), dev(fx2), tools=tl2, dirs=dirs, dir_kind=imf.DIR_LATTICE,
+                          method=imf.METHOD_FFT)
+    ref = oracle.imf(oracle.Request(d2, fx2, tools=tl2, dirs=dirs, dir_kind=1))
+    s2, l2 = ctx.plan_greedy(out2["masks"], dev(d2), dev(fx2))
+    assert (s2, l2) == cp.plan_greedy(oracle.unpack_masks(ref["masks"], 24), d2, omega0=fx2 == 0)
