@@ -277,6 +277,39 @@ def main():
         plain = {"value": N * nR / tp, "ms_per_step": 1000 * tp,
                  "speedup": (N * nR / (el / args.steps)) / (N * nR / tp)}
         log("plain path: %.1f ms" % (1000 * tp))
+    # TO-coupling steps on the same grid (pointwise, HBM-bound) and the greedy
+    # machining plan from the request's masks
+    coupling = None
+    out_c, _ = ctx.compute(design, fixture, **kw)
+    xi = torch.rand(design.shape, device=dev, generator=torch.Generator(device=dev).manual_seed(1))
+    sens = -xi.pow(3)
+    ctx.heaviside(xi, 8.0)
+    ctx.access_filter(design, out_c["imf_norm"], out_c["secluded"], fixture, sens=sens, w=0.3)
+    torch.cuda.synchronize()
+    reps = 20
+    t1 = time.perf_counter()
+    for i in range(reps):
+        rho_c = ctx.heaviside(xi, 8.0)
+    torch.cuda.synchronize()
+    t_h = (time.perf_counter() - t1) / reps
+    t1 = time.perf_counter()
+    for i in range(reps):
+        ctx.access_filter(design, out_c["imf_norm"], out_c["secluded"], fixture, sens=sens, w=0.3)
+    torch.cuda.synchronize()
+    t_f = (time.perf_counter() - t1) / reps
+    t1 = time.perf_counter()
+    plan, left = ctx.plan_greedy(out_c["masks"], design, fixture)
+    t_p = time.perf_counter() - t1
+    # bytes: Heaviside reads xi, writes rho; the filter reads the design, fbar,
+    # Gamma, S_phi (twice: max, then combine), the filter, and writes both fields
+    bh, bf = 8.0 * N, N * (4 + 4 + 1 + 4 + 4 + 4 + 4 + 4 + 1)
+    coupling = {"heaviside_ms": 1000 * t_h, "heaviside_GBps": bh / t_h / 1e9,
+                "access_filter_ms": 1000 * t_f, "access_filter_GBps": bf / t_f / 1e9,
+                "plan_ms": 1000 * t_p, "plan_steps": len(plan), "plan_left": left}
+    log("coupling: heaviside %.3f ms (%.0f GB/s), filter + sensitivity %.3f ms (%.0f GB/s), "
+        "greedy plan %d steps in %.1f ms" % (1000 * t_h, bh / t_h / 1e9, 1000 * t_f,
+                                             bf / t_f / 1e9, len(plan), 1000 * t_p))
+    del out_c, xi, sens, rho_c
     ctx.close()
     # cold tool-spectrum cache: the same request on a fresh context
     ctx = imf.Context(0)
@@ -324,6 +357,7 @@ def main():
         "plain": plain,
         "cold_cache_ms": cold_ms,
         "graph_replay_ms_per_step": graph_ms,
+        "coupling": coupling,
         "serving": serving,
         "kernels": kernels,
         "guard": {"F_max": last.F_max, "max_frac_err": last.max_frac_err,

@@ -84,7 +84,8 @@ enum { IMF_METHOD_AUTO = 0, IMF_METHOD_FFT = 1, IMF_METHOD_DIRECT = 2 };
 #define IMF_FLAG_MASK_SWEEP 2u   /* masks by sweeping D^c with the cutter (bit rows) */
 #define IMF_FLAG_NO_CACHE 4u     /* do not keep tool spectra */
 #define IMF_FLAG_PROFILE 8u      /* time every kernel class with events (k_ms, k_n) */
-#define IMF_FLAG_NO_BOUND 16u    /* no branch and bound in the sharp-point minimum */
+#define IMF_FLAG_NO_BOUND 16u    /* no branch and bound in the sharp-point minimum (it is
+                                    used on grids of at least 10^6 voxels) */
 #define IMF_FLAG_NO_GRAPH 32u    /* launch kernel by kernel: no HIP-graph capture or replay.
                                     Otherwise the second request with the same signature
                                     (request fields, input / output pointers, orientations,

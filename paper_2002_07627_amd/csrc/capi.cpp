@@ -200,6 +200,9 @@ struct imf_ctx {
   int mf_shape = 2;  // wave block shape of the sharp-point minimum (imf_block_dims)
   int n_cu = 256;     // compute units of the device
   int mf_wg_per_cu = 4;  // resident workgroups per CU of the sharp-point minimum (list pass)
+  // grids below this many voxels skip the branch and bound: its three short
+  // launches per orientation cost more than the blocks they save
+  long long bound_min_voxels = 1000000;
 };
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -268,6 +271,7 @@ extern "C" imf_status imf_create(int device, size_t hbm_budget_bytes, imf_ctx** 
   c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)fr);
   if (const char* e = std::getenv("IMF_MINFILTER_SHAPE")) c->mf_shape = std::atoi(e) & 3;
   c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  if (const char* e = std::getenv("IMF_BOUND_MIN_VOXELS")) c->bound_min_voxels = std::atoll(e);
   if (const char* e = std::getenv("IMF_MINFILTER_WG_PER_CU"))
     c->mf_wg_per_cu = std::max(1, std::min(16, std::atoi(e)));
   if (hipStreamCreateWithFlags(&c->internal, hipStreamNonBlocking) != hipSuccess) {
@@ -724,7 +728,7 @@ static imf_status make_plan(imf_ctx* c, const imf_request* r, const imf_outputs*
     p.band = 2.0 * u * lg * std::sqrt((double)p.N * (double)maxT);
   }
   // branch and bound for the sharp-point minimum (not in the plain comparator)
-  p.bnb = !plain && !(r->flags & IMF_FLAG_NO_BOUND);
+  p.bnb = !plain && !(r->flags & IMF_FLAG_NO_BOUND) && p.N >= c->bound_min_voxels;
   p.shape = p.nd == 2 ? 0 : p.tuned_shape;
   {
     int wx, wy, wz;

@@ -62,9 +62,13 @@ __global__ void k_access_filter(const void* __restrict__ design, int density,
     filt[i] = v;
     if (sens && in_omega0(fixture, domain, i)) m = fmaxf(m, fabsf(sens[i]));
   }
-  if (sens) {
+  if (sens) {  // one atomic per workgroup (the grid is capped at 2048 workgroups)
+    __shared__ float red[4];
     for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-    if ((threadIdx.x & 63) == 0) atomicMax(smax, __float_as_uint(m));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0)
+      atomicMax(smax, __float_as_uint(fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]))));
   }
 }
 
@@ -86,7 +90,8 @@ hipError_t imf_launch_access_filter(const imf_couple_args& a, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_u32_couple, dim3(1), dim3(64), 0, s, a.smax);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_access_filter, dim3(grid_of(a.n)), dim3(256), 0, s, a.design, a.density,
+  const unsigned gf = grid_of(a.n) < 2048 ? grid_of(a.n) : 2048;
+  hipLaunchKernelGGL(k_access_filter, dim3(gf), dim3(256), 0, s, a.design, a.density,
                      a.imf_norm, a.secluded, a.tau, a.n, a.filt, a.sens, a.fixture, a.domain,
                      a.smax);
   if ((e = hipGetLastError()) != hipSuccess) return e;

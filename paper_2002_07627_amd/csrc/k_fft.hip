@@ -657,7 +657,11 @@ __global__ void __launch_bounds__(IMF_WG) k_inv_x_c2r(imf_inv_args a, imf_fft_le
   }
   if (a.binary) {
     for (int o = 32; o > 0; o >>= 1) local_err = fmaxf(local_err, __shfl_xor(local_err, o));
-    if ((threadIdx.x & 63) == 0) atomicMax(a.max_err_bits, __float_as_uint(local_err));
+    // a statistic only: most waves are below the running maximum, so read it
+    // first and leave the contended atomic to the few that raise it
+    if ((threadIdx.x & 63) == 0 &&
+        __float_as_uint(local_err) > __atomic_load_n(a.max_err_bits, __ATOMIC_RELAXED))
+      atomicMax(a.max_err_bits, __float_as_uint(local_err));
   }
 }
 
