@@ -33,7 +33,22 @@ def build(force: bool = True) -> str:
 
 class _Tool(C.Structure):
     _fields_ = [("kind", C.c_int), ("cutter_r", C.c_double), ("cutter_len", C.c_double),
-                ("holder_r", C.c_double), ("holder_len", C.c_double)]
+                ("holder_r", C.c_double), ("holder_len", C.c_double),
+                ("vox", C.c_void_p), ("vdim", C.c_int * 3), ("vorg", C.c_int * 3)]
+
+
+VOXEL = 3   # tool kind: voxel model (labels 0 empty, 1 holder, 2 cutter)
+
+
+def _tool_c(t):
+    """ctypes tool; voxel tools keep a contiguous uint8 copy of their labels."""
+    if t["kind"] == VOXEL:
+        lab = np.ascontiguousarray(t["labels"], dtype=np.uint8)
+        nz, ny, nx = lab.shape
+        ct = _Tool(VOXEL, 0.0, 0.0, 0.0, 0.0, _ptr(lab), (C.c_int * 3)(nx, ny, nz),
+                   (C.c_int * 3)(*[int(v) for v in t["origin"]]))
+        return ct, lab
+    return _Tool(t["kind"], t["cutter_r"], t["cutter_len"], t["holder_r"], t["holder_len"]), None
 
 
 class _Req(C.Structure):
@@ -99,8 +114,10 @@ class Request:
         self.n_dirs = np.array([len(d) for d in dirs], dtype=np.int32)
         self.dir_kind = int(dir_kind)
         dt = np.int32 if self.dir_kind == 1 else np.float64
+        if self.dir_kind == 2:  # rotation matrices, 9 values each
+            dirs = [d.reshape(-1, 9) for d in dirs]
         self.dirs = np.ascontiguousarray(np.concatenate(dirs, axis=0), dtype=dt)
-        assert self.dirs.shape[1] == self.ndim
+        assert self.dirs.shape[1] == (9 if self.dir_kind == 2 else self.ndim)
         self.sharp, self.lam, self.tau = int(sharp), float(lam), float(tau)
         self.mask_theta_abs = float(mask_theta_abs)
         self._c = self._make()
@@ -114,10 +131,9 @@ class Request:
         return self.design.shape
 
     def _make(self):
-        tl = (_Tool * len(self.tools))(*[
-            _Tool(t["kind"], t["cutter_r"], t["cutter_len"], t["holder_r"], t["holder_len"])
-            for t in self.tools])
-        self._keep = tl
+        made = [_tool_c(t) for t in self.tools]
+        tl = (_Tool * len(self.tools))(*[m[0] for m in made])
+        self._keep = (tl, [m[1] for m in made])
         r = _Req()
         r.ndim, r.nx, r.ny, r.nz = self.ndim, self.nx, self.ny, self.nz
         r.density = int(self.density)
@@ -139,11 +155,15 @@ def raster(tool_, d, dir_kind=None, ndim=None):
     """Raster of one oriented tool: (offsets int32 [n, 3] as x,y,z, is_cutter bool [n])."""
     d = np.asarray(d)
     if dir_kind is None:
-        dir_kind = 1 if d.dtype.kind in "iu" else 0
-    ndim = ndim or d.shape[-1]
-    dd = np.ascontiguousarray(d.reshape(1, ndim), dtype=np.int32 if dir_kind == 1 else np.float64)
-    t = _Tool(tool_["kind"], tool_["cutter_r"], tool_["cutter_len"], tool_["holder_r"],
-              tool_["holder_len"])
+        dir_kind = 2 if d.size == 9 else (1 if d.dtype.kind in "iu" else 0)
+    if dir_kind == 2:
+        ndim = 3
+        dd = np.ascontiguousarray(d.reshape(1, 9), dtype=np.float64)
+    else:
+        ndim = ndim or d.shape[-1]
+        dd = np.ascontiguousarray(d.reshape(1, ndim),
+                                  dtype=np.int32 if dir_kind == 1 else np.float64)
+    t, keep = _tool_c(tool_)
     L = lib()
     n = L.or_raster(ndim, C.byref(t), dir_kind, _ptr(dd), 0, None, None, 0)
     if n == -1:

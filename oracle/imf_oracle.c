@@ -41,8 +41,12 @@
 #define OR_ENOMEM 2
 
 typedef struct {
-  int kind; /* 0 flat end mill, 1 ball end mill, 2 2D rectangle */
+  int kind; /* 0 flat end mill, 1 ball end mill, 2 2D rectangle, 3 voxel model */
   double cutter_r, cutter_len, holder_r, holder_len;
+  /* voxel model (kind 3): labels [vdim z][y][x] in the tool frame, 0 empty,
+   * 1 holder, 2 cutter; vorg = the tip voxel (tool-frame origin) */
+  const uint8_t *vox;
+  int vdim[3], vorg[3];
 } or_tool;
 
 typedef struct {
@@ -54,7 +58,9 @@ typedef struct {
   int n_tools;
   const or_tool *tools;
   const int *n_dirs;
-  int dir_kind; /* 0: float64 unit vectors, 1: int32 lattice vectors */
+  int dir_kind; /* 0: float64 unit vectors, 1: int32 lattice vectors, 2: float64
+                   rotation matrices (9 per orientation, row-major, tool frame to grid;
+                   3D only; an axisymmetric tool uses the image of its +z axis) */
   const void *dirs;
   int sharp; /* 0 all cutter voxels, 1 boundary voxels, 2 tip voxel */
   double lambda, tau, mask_theta_abs;
@@ -82,6 +88,7 @@ typedef struct {
   int64_t v[3], vn; /* lattice vector and |v|^2 */
   or_tool t;
   int64_t r2, L2, rh2, LH2; /* doubled parameters (lattice mode) */
+  double R[9];              /* rotation (voxel tools), row-major */
 } raster_ctx;
 
 static int is_half_integer(double x) {
@@ -94,10 +101,34 @@ static int raster_setup(raster_ctx *c, int ndim, const or_tool *t, int dir_kind,
   memset(c, 0, sizeof(*c));
   c->ndim = ndim;
   c->t = *t;
-  if (t->kind < 0 || t->kind > 2) return OR_EINVAL;
+  if (t->kind < 0 || t->kind > 3) return OR_EINVAL;
   if (t->kind == 2 && ndim != 2) return OR_EINVAL;
-  if (!(t->cutter_r > 0 && t->cutter_len > 0 && t->holder_r >= 0 && t->holder_len >= 0))
+  if (t->kind == 3) {
+    if (ndim != 3 || dir_kind != 2 || !t->vox) return OR_EINVAL;
+    for (int a = 0; a < 3; a++)
+      if (t->vdim[a] < 1 || t->vorg[a] < 0 || t->vorg[a] >= t->vdim[a]) return OR_EINVAL;
+  } else if (!(t->cutter_r > 0 && t->cutter_len > 0 && t->holder_r >= 0 &&
+               t->holder_len >= 0)) {
     return OR_EINVAL;
+  }
+  if (dir_kind == 2) {
+    /* rotation: orthonormal with determinant +1; d = image of the tool's +z */
+    if (ndim != 3) return OR_EINVAL;
+    const double *R = (const double *)dirs + (size_t)index * 9;
+    for (int i = 0; i < 9; i++) c->R[i] = R[i];
+    for (int i = 0; i < 3; i++)
+      for (int j = 0; j < 3; j++) {
+        const double dot = R[3 * i] * R[3 * j] + R[3 * i + 1] * R[3 * j + 1] + R[3 * i + 2] * R[3 * j + 2];
+        if (fabs(dot - (i == j ? 1.0 : 0.0)) > 1e-9) return OR_EINVAL;
+      }
+    const double det = R[0] * (R[4] * R[8] - R[5] * R[7]) - R[1] * (R[3] * R[8] - R[5] * R[6]) +
+                       R[2] * (R[3] * R[7] - R[4] * R[6]);
+    if (det < 0) return OR_EINVAL;
+    c->d[0] = R[2];
+    c->d[1] = R[5];
+    c->d[2] = R[8];
+    return OR_OK;
+  }
   if (dir_kind == 1) {
     const int32_t *iv = (const int32_t *)dirs + (size_t)index * ndim;
     c->lattice = 1;
@@ -128,6 +159,23 @@ static int raster_setup(raster_ctx *c, int ndim, const or_tool *t, int dir_kind,
 /* membership of integer offset o: returns bit0 = in tool T, bit1 = in cutter K */
 static int raster_member(const raster_ctx *c, int64_t ox, int64_t oy, int64_t oz) {
   int cut = 0, hold = 0;
+  if (c->t.kind == 3) {
+    /* re-sampling: the tool-frame point R^T o, rounded to the nearest voxel
+     * (halves to even), evaluated in this order */
+    const double x = (double)ox, y = (double)oy, z = (double)oz;
+    const double *R = c->R;
+    int64_t idx[3];
+    for (int a = 0; a < 3; a++) {
+      const double u = (R[a] * x + R[3 + a] * y) + R[6 + a] * z;
+      idx[a] = (int64_t)rint(u) + c->t.vorg[a];
+      if (idx[a] < 0 || idx[a] >= c->t.vdim[a]) return 0;
+    }
+    const uint8_t lab =
+        c->t.vox[(idx[2] * c->t.vdim[1] + idx[1]) * c->t.vdim[0] + idx[0]];
+    cut = lab == 2;
+    hold = lab == 1;
+    return (cut || hold) | (cut << 1);
+  }
   if (c->lattice) {
     int64_t dot, o2;
     if (c->ndim == 3) {
@@ -187,6 +235,25 @@ static int raster_member(const raster_ctx *c, int64_t ox, int64_t oy, int64_t oz
 }
 
 static void raster_bbox(const raster_ctx *c, int lo[3], int hi[3]) {
+  if (c->t.kind == 3) {
+    /* image of the label box (widened by half a voxel) under R, plus one */
+    for (int a = 0; a < 3; a++) {
+      double mn = 1e300, mx = -1e300;
+      for (int k = 0; k < 8; k++) {
+        double p = 0;
+        for (int b = 0; b < 3; b++) {
+          const double e = (k >> b) & 1 ? (double)(c->t.vdim[b] - 1 - c->t.vorg[b]) + 0.5
+                                        : -(double)c->t.vorg[b] - 0.5;
+          p += c->R[3 * a + b] * e;
+        }
+        if (p < mn) mn = p;
+        if (p > mx) mx = p;
+      }
+      lo[a] = (int)floor(mn) - 1;
+      hi[a] = (int)ceil(mx) + 1;
+    }
+    return;
+  }
   double len = c->t.cutter_len + c->t.holder_len;
   if (2 * c->t.cutter_r > len) len = 2 * c->t.cutter_r;
   const double rmax = c->t.cutter_r > c->t.holder_r ? c->t.cutter_r : c->t.holder_r;

@@ -446,3 +446,78 @@ def test_fixture_blocks_tools_from_below():
     assert not m[0, 3:6].any() and m[0, 6:].all()
     assert m[1, 3:].all()               # from above everything off the plate
     assert not m[:, :3].any()           # fixture voxels are outside Omega_0
+
+
+# ---------------------------------------------------------------------------
+# voxel-model tools: inverse nearest-neighbour re-sampling under a rotation
+# ---------------------------------------------------------------------------
+
+def _label_offsets(t):
+    lab = t["labels"]
+    z, y, x = np.nonzero(lab)
+    o = t["origin"]
+    return {(int(a) - o[0], int(b) - o[1], int(c) - o[2]): int(lab[c, b, a])
+            for a, b, c in zip(x, y, z)}
+
+
+def test_voxel_tool_identity_and_cube_rotations_are_exact():
+    from workloads import asymmetric_tool, cube_rotations
+    t = asymmetric_tool()
+    ref = _label_offsets(t)
+    for R in [np.eye(3)] + list(cube_rotations()):
+        offs, cut = oracle.raster(t, R)
+        got = {tuple(p): 2 if c else 1 for p, c in zip(offs.tolist(), cut)}
+        # R maps the tool-frame offset p to the grid offset R p exactly
+        want = {tuple(int(v) for v in np.rint(R @ np.array(p, float))): lab
+                for p, lab in ref.items()}
+        assert got == want
+
+
+def test_voxelized_tool_rotated_onto_axes_equals_the_analytic_raster():
+    from workloads import voxel_tool, rotation_to
+    tl = tool(TOOL_FLAT, 1.5, 6, 3, 5)
+    offs, cut = oracle.raster(tl, np.array([0, 0, 1], np.int32))
+    lo = offs.min(0)
+    dims = offs.max(0) - lo + 1
+    lab = np.zeros(dims[::-1], np.uint8)
+    lab[offs[:, 2] - lo[2], offs[:, 1] - lo[1], offs[:, 0] - lo[0]] = np.where(cut, 2, 1)
+    vt = voxel_tool(lab, -lo)
+    for d in ([1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]):
+        R = np.rint(rotation_to(np.array(d, float)))
+        a_offs, a_cut = oracle.raster(tl, np.array(d, np.int32))
+        v_offs, v_cut = oracle.raster(vt, R)
+        assert {tuple(p): c for p, c in zip(a_offs.tolist(), a_cut)} == \
+               {tuple(p): c for p, c in zip(v_offs.tolist(), v_cut)}, d
+
+
+def test_voxel_tool_imf_equals_analytic_on_axis_directions():
+    """End to end: the voxelized flat tool under the 6 axis rotations gives the
+    same IMF and masks as the analytic tool along the 6 lattice axes."""
+    from workloads import voxel_tool, rotation_to
+    rng = np.random.default_rng(77)
+    d = (rng.random((10, 11, 12)) < 0.3).astype(np.uint8)
+    fx = fixture_plate(d.shape, 1)
+    tl = tool(TOOL_FLAT, 1, 3, 2, 2)
+    offs, cut = oracle.raster(tl, np.array([0, 0, 1], np.int32))
+    lo = offs.min(0)
+    lab = np.zeros((offs.max(0) - lo + 1)[::-1], np.uint8)
+    lab[offs[:, 2] - lo[2], offs[:, 1] - lo[1], offs[:, 0] - lo[0]] = np.where(cut, 2, 1)
+    vt = voxel_tool(lab, -lo)
+    axes = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]], np.int32)
+    rots = np.stack([np.rint(rotation_to(a.astype(float))) for a in axes])
+    a = oracle.imf(oracle.Request(d, fx, tools=tl, dirs=axes, dir_kind=1))
+    v = oracle.imf(oracle.Request(d, fx, tools=vt, dirs=rots, dir_kind=2))
+    for k in ("imf", "imf_norm", "secluded", "masks", "masks_dil"):
+        assert np.array_equal(a[k], v[k]), k
+
+
+def test_voxel_tool_random_rotations_keep_the_volume():
+    from workloads import asymmetric_tool, random_rotations
+    t = asymmetric_tool()
+    n = int(np.count_nonzero(t["labels"]))
+    for R in random_rotations(12, 5):
+        offs, cut = oracle.raster(t, R)
+        assert abs(len(offs) - n) <= 0.2 * n
+        assert cut.any() and (~cut).any()
+    with pytest.raises(ValueError):
+        oracle.raster(t, np.diag([1.0, 1.0, -1.0]))        # a reflection, not a rotation

@@ -318,3 +318,80 @@ def serving_request(desc: dict, master_dirs: int = 130) -> dict:
     return {"design": d, "fixture": fixture_plate(d.shape, 6), "tool": desc["tool"],
             "dirs": fib_hemisphere(master_dirs)[desc["dir_index"]],
             "lam": 0.01 if desc["density"] else 0.0}
+
+
+# ---------------------------------------------------------------------------
+# voxel-model tools and rotations
+# ---------------------------------------------------------------------------
+TOOL_VOXEL = 3
+
+
+def voxel_tool(labels, origin) -> dict:
+    """A voxel-model tool: labels [z][y][x] (0 empty, 1 holder, 2 cutter) in the
+    tool frame; origin = (x, y, z) index of the tip voxel."""
+    lab = np.ascontiguousarray(labels, dtype=np.uint8)
+    assert lab.ndim == 3 and set(np.unique(lab)) <= {0, 1, 2}
+    return {"kind": TOOL_VOXEL, "labels": lab, "origin": tuple(int(v) for v in origin)}
+
+
+def asymmetric_tool(r: int = 2, length: int = 14, holder_half: int = 5,
+                    holder_len: int = 10) -> dict:
+    """A non-axisymmetric voxel tool: cylindrical cutter of radius r along +z
+    over [0, length) with a side tooth (x in [r, r + 2], |y| <= 1, z < 3), and a
+    square holder (|x|, |y| <= holder_half) over [length, length + holder_len)."""
+    h = holder_half
+    x = np.arange(-h, h + 1)
+    zs = np.arange(0, length + holder_len)
+    Z, Y, X = np.meshgrid(zs, x, x, indexing="ij")
+    lab = np.zeros(Z.shape, np.uint8)
+    cutter = ((X ** 2 + Y ** 2 <= r * r) & (Z < length)) | \
+             ((X >= r) & (X <= r + 2) & (np.abs(Y) <= 1) & (Z < 3))
+    holder = (Z >= length)
+    lab[holder] = 1
+    lab[cutter] = 2
+    return voxel_tool(lab, (h, h, 0))
+
+
+def quat_to_matrix(q) -> np.ndarray:
+    """Rotation matrix (row-major, tool frame to grid) of a quaternion (w, x, y, z)."""
+    w, x, y, z = np.asarray(q, np.float64) / np.linalg.norm(q)
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def random_rotations(n: int, seed: int) -> np.ndarray:
+    """n uniformly distributed rotations (Shoemake's method), [n, 3, 3]."""
+    r = _rng(seed)
+    u1, u2, u3 = r.random(n), r.random(n), r.random(n)
+    q = np.stack([np.sqrt(1 - u1) * np.sin(2 * np.pi * u2), np.sqrt(1 - u1) * np.cos(2 * np.pi * u2),
+                  np.sqrt(u1) * np.sin(2 * np.pi * u3), np.sqrt(u1) * np.cos(2 * np.pi * u3)], 1)
+    return np.stack([quat_to_matrix(v) for v in q])
+
+
+def cube_rotations() -> np.ndarray:
+    """The 24 proper rotations of the cube (signed permutation matrices, det +1)."""
+    import itertools
+    out = []
+    for perm in itertools.permutations(range(3)):
+        for signs in itertools.product((1, -1), repeat=3):
+            m = np.zeros((3, 3))
+            for i, j in enumerate(perm):
+                m[i, j] = signs[i]
+            if np.linalg.det(m) > 0:
+                out.append(m)
+    return np.array(out)
+
+
+def rotation_to(d, roll: float = 0.0) -> np.ndarray:
+    """A rotation taking the tool's +z axis to the unit vector d, then rolled
+    by `roll` radians about d."""
+    d = np.asarray(d, np.float64)
+    d = d / np.linalg.norm(d)
+    a = np.array([1.0, 0, 0]) if abs(d[0]) < 0.9 else np.array([0, 1.0, 0])
+    e1 = np.cross(a, d)
+    e1 /= np.linalg.norm(e1)
+    e2 = np.cross(d, e1)
+    c, s = np.cos(roll), np.sin(roll)
+    u, v = c * e1 + s * e2, -s * e1 + c * e2
+    return np.stack([u, v, d], axis=1)   # columns: images of x, y, z
