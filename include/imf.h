@@ -65,16 +65,25 @@ imf_status imf_destroy(imf_ctx* ctx);
 const char* imf_last_error(void);
 
 /* ---------------------------------------------------------------- tools -- */
-enum { IMF_TOOL_FLAT = 0, IMF_TOOL_BALL = 1, IMF_TOOL_RECT2D = 2 };
+enum { IMF_TOOL_FLAT = 0, IMF_TOOL_BALL = 1, IMF_TOOL_RECT2D = 2, IMF_TOOL_VOXEL = 3 };
 typedef struct {
   int kind;                /* IMF_TOOL_*; RECT2D is 2D only (radii are half-widths) */
   double cutter_r, cutter_len, holder_r, holder_len; /* voxels */
 } imf_tool;
 /* Register a tool (Sec. 2.1: T = H u K).  Returns an id for requests. */
 imf_status imf_tool_register(imf_ctx* ctx, const imf_tool* tool, int* tool_id);
+/* Register a voxel-model tool (the voxel tool that Algorithm 1's Rotate step
+ * re-samples): labels host [nz][ny][nx] in the tool frame, 0 empty, 1 holder,
+ * 2 cutter (the cutter voxels are the sharp points); origin (x, y, z) = the tip
+ * voxel.  Used with IMF_DIR_ROTATION directions (3D): a grid offset o takes the
+ * label at rint(R^T o) + origin, R^T o evaluated in float64 as
+ * (R[0][a] o_x + R[1][a] o_y) + R[2][a] o_z, rint rounding halves to even.
+ * The labels are copied to the device; the tool lives until imf_destroy. */
+imf_status imf_tool_register_voxel(imf_ctx* ctx, int nx, int ny, int nz, const uint8_t* labels,
+                                   const int origin[3], int* tool_id);
 
 /* -------------------------------------------------------------- request -- */
-enum { IMF_DIR_F64 = 0, IMF_DIR_LATTICE = 1 };
+enum { IMF_DIR_F64 = 0, IMF_DIR_LATTICE = 1, IMF_DIR_ROTATION = 2 };
 /* sharp points: all cutter voxels (Algorithm 1: Support([1_K])), the cutter's
  * boundary voxels, or the tip voxel only (sparser sampling, Sec. 2.1.5) */
 enum { IMF_SHARP_ALL = 0, IMF_SHARP_BOUNDARY = 1, IMF_SHARP_TIP = 2 };
@@ -104,8 +113,11 @@ typedef struct {
   const int* n_dirs;           /* host [n_tools], each >= 1 */
   int dir_kind;                /* IMF_DIR_F64: float64 unit vectors; IMF_DIR_LATTICE: int32
                                   vectors, exact integer rasterization (sizes must be
-                                  multiples of 1/2) */
-  const void* dirs;            /* host [sum n_dirs][ndim] (x, y[, z]) */
+                                  multiples of 1/2); IMF_DIR_ROTATION: float64 rotation
+                                  matrices, row-major, tool frame to grid, orthonormal to
+                                  1e-9 with determinant +1 (3D; needed by voxel tools;
+                                  an axisymmetric tool takes the image of its +z axis) */
+  const void* dirs;            /* host [sum n_dirs][ndim] (x, y[, z]), or [sum n_dirs][9] */
   int sharp;                   /* IMF_SHARP_* */
   double lambda;               /* allowance: B = Omega_0 and f > lambda F_max */
   double tau;                  /* Omega = [rho > tau] for the secluded set (0.5) */
@@ -228,6 +240,10 @@ imf_status imf_plan_greedy(imf_ctx* ctx, int nx, int ny, int nz, int n_orient,
 imf_status imf_raster(imf_ctx* ctx, int ndim, const imf_tool* tool, int dir_kind,
                       const void* dir, int sharp, int32_t* offsets, uint8_t* flags,
                       long long cap, long long* count);
+/* The same for a registered tool (any kind, voxel tools included). */
+imf_status imf_raster_tool(imf_ctx* ctx, int tool_id, int ndim, int dir_kind, const void* dir,
+                           int sharp, int32_t* offsets, uint8_t* flags, long long cap,
+                           long long* count);
 /* Complex FFT of `batch` columns of length n laid out [n][batch] (interleaved
  * float re, im), device pointers, unnormalized, sign -1 (inverse: +1). */
 imf_status imf_fft_c2c(imf_ctx* ctx, int n, int batch, const float* in, float* out,

@@ -157,6 +157,11 @@ struct imf_ctx {
   size_t spec_bytes = 0, arena_bytes = 0, raster_bytes = 0;
   std::recursive_mutex mu;
   std::vector<imf_tool> tools;
+  struct VoxTool {
+    uint8_t* dev = nullptr;  // labels on the device (voxel-model tools only)
+    int dim[3] = {0, 0, 0}, org[3] = {0, 0, 0};
+  };
+  std::vector<VoxTool> vtools;  // parallel to tools
   std::map<std::string, OrientEntry> rasters;
   std::vector<void*> raster_pools;
   std::map<std::string, SpecEntry> spectra;
@@ -302,6 +307,8 @@ extern "C" imf_status imf_destroy(imf_ctx* c) {
   if (c->internal) hipStreamDestroy(c->internal);
   if (c->capture) hipStreamDestroy(c->capture);
   if (c->couple_scratch) hipFree(c->couple_scratch);
+  for (auto& v : c->vtools)
+    if (v.dev) hipFree(v.dev);
   delete c;
   return IMF_OK;
 }
@@ -316,6 +323,43 @@ extern "C" imf_status imf_tool_register(imf_ctx* c, const imf_tool* t, int* id) 
     return fail(IMF_EINVAL, "tool larger than 400 voxels");
   std::lock_guard<std::recursive_mutex> lk(c->mu);
   c->tools.push_back(*t);
+  c->vtools.emplace_back();
+  *id = (int)c->tools.size() - 1;
+  return IMF_OK;
+}
+
+extern "C" imf_status imf_tool_register_voxel(imf_ctx* c, int nx, int ny, int nz,
+                                              const uint8_t* labels, const int origin[3],
+                                              int* id) {
+  if (!c || !labels || !origin || !id) return fail(IMF_EINVAL, "NULL argument");
+  if (nx < 1 || ny < 1 || nz < 1 || nx > 1024 || ny > 1024 || nz > 1024)
+    return fail(IMF_EINVAL, "voxel tool of %d x %d x %d voxels", nx, ny, nz);
+  const int dims[3] = {nx, ny, nz};
+  for (int a = 0; a < 3; a++)
+    if (origin[a] < 0 || origin[a] >= dims[a]) return fail(IMF_EINVAL, "tip outside the labels");
+  const size_t n = (size_t)nx * ny * nz;
+  bool any_cut = false;
+  for (size_t i = 0; i < n; i++) {
+    if (labels[i] > 2) return fail(IMF_EINVAL, "labels must be 0, 1 or 2");
+    any_cut = any_cut || labels[i] == 2;
+  }
+  if (!any_cut) return fail(IMF_EINVAL, "a voxel tool needs cutter voxels");
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  HIPCHK(hipSetDevice(c->device));
+  imf_ctx::VoxTool v;
+  HIPCHK(hipMalloc(&v.dev, n));
+  if (hipMemcpy(v.dev, labels, n, hipMemcpyHostToDevice) != hipSuccess) {
+    hipFree(v.dev);
+    return fail(IMF_EDEVICE, "voxel tool upload");
+  }
+  for (int a = 0; a < 3; a++) {
+    v.dim[a] = dims[a];
+    v.org[a] = origin[a];
+  }
+  imf_tool t{};
+  t.kind = IMF_TOOL_VOXEL;
+  c->tools.push_back(t);
+  c->vtools.push_back(v);
   *id = (int)c->tools.size() - 1;
   return IMF_OK;
 }
@@ -327,6 +371,7 @@ struct Orient {
   int tool;
   double d[3];
   long long v[3];
+  double R[9];  // rotation (IMF_DIR_ROTATION)
   std::string key;
 };
 
@@ -342,6 +387,10 @@ static imf_status enumerate(imf_ctx* c, const imf_request* r, std::vector<Orient
     const imf_tool& t = c->tools[tid];
     if (t.kind == IMF_TOOL_RECT2D && nd != 2)
       return fail(IMF_EINVAL, "RECT2D tools are 2D only");
+    if (t.kind == IMF_TOOL_VOXEL && r->dir_kind != IMF_DIR_ROTATION)
+      return fail(IMF_EINVAL, "voxel tools need rotation matrices (IMF_DIR_ROTATION)");
+    if (r->dir_kind == IMF_DIR_ROTATION && nd != 3)
+      return fail(IMF_EINVAL, "rotation matrices are for 3D requests");
     if (r->dir_kind == IMF_DIR_LATTICE &&
         !(is_half_int(t.cutter_r) && is_half_int(t.cutter_len) && is_half_int(t.holder_r) &&
           is_half_int(t.holder_len)))
@@ -369,13 +418,32 @@ static imf_status enumerate(imf_ctx* c, const imf_request* r, std::vector<Orient
         }
         if (!(std::fabs(std::sqrt(n2) - 1.0) <= 1e-12))
           return fail(IMF_EINVAL, "direction %zu is not a unit vector", k);
+      } else if (r->dir_kind == IMF_DIR_ROTATION) {
+        const double* R = (const double*)r->dirs + k * 9;
+        for (int i = 0; i < 9; i++) o.R[i] = R[i];
+        for (int i = 0; i < 3; i++)
+          for (int j = 0; j < 3; j++) {
+            const double dot = R[3 * i] * R[3 * j] + R[3 * i + 1] * R[3 * j + 1] +
+                               R[3 * i + 2] * R[3 * j + 2];
+            if (!(std::fabs(dot - (i == j ? 1.0 : 0.0)) <= 1e-9))
+              return fail(IMF_EINVAL, "rotation %zu is not orthonormal", k);
+          }
+        const double det = R[0] * (R[4] * R[8] - R[5] * R[7]) -
+                           R[1] * (R[3] * R[8] - R[5] * R[6]) + R[2] * (R[3] * R[7] - R[4] * R[6]);
+        if (!(det > 0)) return fail(IMF_EINVAL, "rotation %zu has determinant -1", k);
+        o.d[0] = R[2];  // image of the tool's +z axis
+        o.d[1] = R[5];
+        o.d[2] = R[8];
       } else {
         return fail(IMF_EINVAL, "unknown dir_kind %d", r->dir_kind);
       }
-      char buf[160];
+      char buf[400];
       if (r->dir_kind == IMF_DIR_LATTICE)
         snprintf(buf, sizeof buf, "%d|%d|L|%d|%lld,%lld,%lld", tid, nd, r->sharp, o.v[0], o.v[1],
                  o.v[2]);
+      else if (r->dir_kind == IMF_DIR_ROTATION && t.kind == IMF_TOOL_VOXEL)
+        snprintf(buf, sizeof buf, "%d|%d|R|%d|%a,%a,%a,%a,%a,%a,%a,%a,%a", tid, nd, r->sharp,
+                 o.R[0], o.R[1], o.R[2], o.R[3], o.R[4], o.R[5], o.R[6], o.R[7], o.R[8]);
       else
         snprintf(buf, sizeof buf, "%d|%d|F|%d|%a,%a,%a", tid, nd, r->sharp, o.d[0], o.d[1], o.d[2]);
       o.key = buf;
@@ -385,13 +453,44 @@ static imf_status enumerate(imf_ctx* c, const imf_request* r, std::vector<Orient
   return IMF_OK;
 }
 
-static void raster_desc_for(const imf_tool& t, const Orient& o, int nd, int lattice, int sharp,
-                            imf_raster_desc& d) {
+static void raster_desc_for(const imf_ctx* c, int tid, const Orient& o, int nd, int lattice,
+                            int sharp, imf_raster_desc& d) {
+  const imf_tool& t = c->tools[tid];
   std::memset(&d, 0, sizeof d);
   d.kind = t.kind;
   d.ndim = nd;
   d.lattice = lattice;
   d.sharp = sharp;
+  if (t.kind == IMF_TOOL_VOXEL) {
+    // image of the label box (widened by half a voxel) under R, plus one
+    const imf_ctx::VoxTool& v = c->vtools[tid];
+    d.vox = v.dev;
+    for (int a = 0; a < 3; a++) {
+      d.vdim[a] = v.dim[a];
+      d.vorg[a] = v.org[a];
+      d.d[a] = o.d[a];
+    }
+    for (int i = 0; i < 9; i++) d.R[i] = o.R[i];
+    int best = 0;
+    for (int a = 0; a < 3; a++) {
+      double mn = 1e300, mx = -1e300;
+      for (int k = 0; k < 8; k++) {
+        double p = 0;
+        for (int b = 0; b < 3; b++) {
+          const double e = (k >> b) & 1 ? (double)(v.dim[b] - 1 - v.org[b]) + 0.5
+                                        : -(double)v.org[b] - 0.5;
+          p += o.R[3 * a + b] * e;
+        }
+        mn = std::min(mn, p);
+        mx = std::max(mx, p);
+      }
+      d.lo[a] = (int)std::floor(mn) - 1;
+      d.dim[a] = (int)std::ceil(mx) + 1 - d.lo[a] + 1;
+      if (std::fabs(d.d[a]) > std::fabs(d.d[best])) best = a;
+    }
+    d.s_axis = best;
+    return;
+  }
   d.r = t.cutter_r;
   d.L = t.cutter_len;
   d.rh = t.holder_r;
@@ -446,7 +545,7 @@ static imf_status ensure_rasters(imf_ctx* c, const imf_request* r, const std::ve
   long long flags_total = 0, rows_total = 0;
   int max_vol = 0, max_rows = 0;
   for (int i = 0; i < n; i++) {
-    raster_desc_for(c->tools[miss[i]->tool], *miss[i], r->ndim, r->dir_kind == IMF_DIR_LATTICE,
+    raster_desc_for(c, miss[i]->tool, *miss[i], r->ndim, r->dir_kind == IMF_DIR_LATTICE,
                     r->sharp, hd[i]);
     const long long vol = (long long)hd[i].dim[0] * hd[i].dim[1] * hd[i].dim[2];
     if (vol > (1LL << 30)) return fail(IMF_EINVAL, "tool raster box too large");
@@ -1459,11 +1558,21 @@ extern "C" imf_status imf_raster(imf_ctx* c, int ndim, const imf_tool* tool, int
                                  const void* dir, int sharp, int32_t* offsets, uint8_t* flags_out,
                                  long long cap, long long* count) {
   if (!c || !tool || !dir || !count) return fail(IMF_EINVAL, "NULL argument");
+  if (tool->kind == IMF_TOOL_VOXEL)
+    return fail(IMF_EINVAL, "voxel tools are registered first (imf_raster_tool)");
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  int tid;
+  STCHK(imf_tool_register(c, tool, &tid));
+  return imf_raster_tool(c, tid, ndim, dir_kind, dir, sharp, offsets, flags_out, cap, count);
+}
+
+extern "C" imf_status imf_raster_tool(imf_ctx* c, int tid, int ndim, int dir_kind,
+                                      const void* dir, int sharp, int32_t* offsets,
+                                      uint8_t* flags_out, long long cap, long long* count) {
+  if (!c || !dir || !count) return fail(IMF_EINVAL, "NULL argument");
   if (ndim != 2 && ndim != 3) return fail(IMF_EINVAL, "ndim must be 2 or 3");
   std::lock_guard<std::recursive_mutex> lk(c->mu);
   HIPCHK(hipSetDevice(c->device));
-  int tid;
-  STCHK(imf_tool_register(c, tool, &tid));
   imf_request r{};
   r.ndim = ndim;
   r.n_tools = 1;
@@ -1476,7 +1585,7 @@ extern "C" imf_status imf_raster(imf_ctx* c, int ndim, const imf_tool* tool, int
   std::vector<Orient> os;
   STCHK(enumerate(c, &r, os));
   imf_raster_desc hd;
-  raster_desc_for(*tool, os[0], ndim, dir_kind == IMF_DIR_LATTICE, sharp, hd);
+  raster_desc_for(c, tid, os[0], ndim, dir_kind == IMF_DIR_LATTICE, sharp, hd);
   const long long vol = (long long)hd.dim[0] * hd.dim[1] * hd.dim[2];
   hd.flags_off = 0;
   hd.rows_off = 0;

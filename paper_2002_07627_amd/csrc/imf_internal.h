@@ -15,7 +15,7 @@ struct imf_run {
 
 // Geometry of one oriented tool, as the raster kernels need it.
 struct imf_raster_desc {
-  int kind;            // 0 flat, 1 ball, 2 2D rectangle
+  int kind;            // 0 flat, 1 ball, 2 2D rectangle, 3 voxel model
   int ndim;
   int lattice;         // 1: exact integer predicate on v, 0: float64 on d
   int sharp;           // 0 all cutter voxels, 1 boundary voxels, 2 tip voxel
@@ -26,6 +26,9 @@ struct imf_raster_desc {
   long long r2, L2, rh2, LH2;  // doubled sizes (lattice mode)
   int lo[3], dim[3];   // bounding box of the raster in offsets
   int s_axis;          // axis along which the sharp-point runs are formed
+  const uint8_t* vox;  // voxel model: device labels [vdim z][y][x], tip at vorg
+  int vdim[3], vorg[3];
+  double R[9];         // voxel model: rotation, row-major (tool frame to grid)
   long long flags_off; // byte offset of this orientation's flag volume
   long long rows_off;  // offset (in rows) of this orientation's row slots
 };

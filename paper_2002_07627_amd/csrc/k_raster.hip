@@ -1,4 +1,6 @@
 // Rasterization of oriented tools (the Rotate step of Algorithm 1, Sec. 2.1.5).
+// Voxel-model tools are re-sampled: a grid offset o takes the label of the
+// tool-frame voxel nearest to R^T o.
 //
 // The paper rotates and re-samples a voxel tool; here the axisymmetric tool
 // (cutter K of radius r over axial [0, L), holder H of radius rh over axial
@@ -20,6 +22,22 @@
 __device__ __forceinline__ int raster_member(const imf_raster_desc& c, long long ox, long long oy,
                                              long long oz) {
   int cut = 0, hold = 0;
+  if (c.kind == 3) {
+    // voxel model: inverse nearest-neighbour re-sampling, the tool-frame point
+    // R^T o rounded (halves to even) to a label voxel
+    const double x = (double)ox, y = (double)oy, z = (double)oz;
+    long long idx[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+      const double u = (c.R[a] * x + c.R[3 + a] * y) + c.R[6 + a] * z;
+      idx[a] = (long long)rint(u) + c.vorg[a];
+      if (idx[a] < 0 || idx[a] >= c.vdim[a]) return 0;
+    }
+    const uint8_t lab = c.vox[(idx[2] * c.vdim[1] + idx[1]) * c.vdim[0] + idx[0]];
+    cut = lab == 2;
+    hold = lab == 1;
+    return (cut || hold) | (cut << 1);
+  }
   if (c.lattice) {
     long long dot, o2;
     if (c.ndim == 3) {

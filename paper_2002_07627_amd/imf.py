@@ -15,8 +15,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libimf.so")
 
-TOOL_FLAT, TOOL_BALL, TOOL_RECT2D = 0, 1, 2
-DIR_F64, DIR_LATTICE = 0, 1
+TOOL_FLAT, TOOL_BALL, TOOL_RECT2D, TOOL_VOXEL = 0, 1, 2, 3
+DIR_F64, DIR_LATTICE, DIR_ROTATION = 0, 1, 2
 SHARP_ALL, SHARP_BOUNDARY, SHARP_TIP = 0, 1, 2
 METHOD_AUTO, METHOD_FFT, METHOD_DIRECT = 0, 1, 2
 FLAG_PLAIN, FLAG_MASK_SWEEP, FLAG_NO_CACHE, FLAG_PROFILE, FLAG_NO_BOUND = 1, 2, 4, 8, 16
@@ -166,6 +166,18 @@ class Context:
             pass
 
     def tool(self, t: dict) -> int:
+        if t["kind"] == TOOL_VOXEL:
+            lab = np.ascontiguousarray(t["labels"], dtype=np.uint8)
+            key = ("voxel", lab.shape, lab.tobytes(), tuple(t["origin"]))
+            if key not in self._tools:
+                tid = C.c_int()
+                nz, ny, nx = lab.shape
+                org = (C.c_int * 3)(*[int(v) for v in t["origin"]])
+                _check(_L().imf_tool_register_voxel(self._ctx, nx, ny, nz,
+                                                    lab.ctypes.data_as(C.c_void_p), org,
+                                                    C.byref(tid)))
+                self._tools[key] = tid.value
+            return self._tools[key]
         key = (t["kind"], t["cutter_r"], t["cutter_len"], t["holder_r"], t["holder_len"])
         if key not in self._tools:
             tid = C.c_int()
@@ -201,8 +213,11 @@ class Context:
         dirs = [np.asarray(d) for d in dirs]
         nd = np.array([len(d) for d in dirs], dtype=np.int32)
         dt = np.int32 if dir_kind == DIR_LATTICE else np.float64
+        if dir_kind == DIR_ROTATION:
+            dirs = [d.reshape(-1, 9) for d in dirs]
+            nd = np.array([len(d) for d in dirs], dtype=np.int32)
         dd = np.ascontiguousarray(np.concatenate(dirs, axis=0), dtype=dt)
-        if dd.shape[1] != ndim:
+        if dd.shape[1] != (9 if dir_kind == DIR_ROTATION else ndim):
             raise ValueError("directions must have %d components" % ndim)
         r = _Request()
         r.ndim, r.nx, r.ny, r.nz = ndim, nx, ny, nz
@@ -376,23 +391,28 @@ class Context:
         """(offsets int32 [n, 3] as x, y, z; flags uint8 [n]) of one oriented tool."""
         d = np.asarray(d)
         if dir_kind is None:
-            dir_kind = DIR_LATTICE if d.dtype.kind in "iu" else DIR_F64
-        ndim = d.shape[-1]
-        dd = np.ascontiguousarray(d.reshape(1, ndim),
-                                  dtype=np.int32 if dir_kind == DIR_LATTICE else np.float64)
-        ct = _Tool(tool["kind"], tool["cutter_r"], tool["cutter_len"], tool["holder_r"],
-                   tool["holder_len"])
+            dir_kind = DIR_ROTATION if d.size == 9 else (
+                DIR_LATTICE if d.dtype.kind in "iu" else DIR_F64)
+        if dir_kind == DIR_ROTATION:
+            ndim = 3
+            dd = np.ascontiguousarray(d.reshape(1, 9), dtype=np.float64)
+        else:
+            ndim = d.shape[-1]
+            dd = np.ascontiguousarray(d.reshape(1, ndim),
+                                      dtype=np.int32 if dir_kind == DIR_LATTICE else np.float64)
+        tid = self.tool(tool)
         n = C.c_longlong()
-        st = _L().imf_raster(self._ctx, ndim, C.byref(ct), dir_kind,
-                             dd.ctypes.data_as(C.c_void_p), sharp, None, None, 0, C.byref(n))
+        st = _L().imf_raster_tool(self._ctx, tid, ndim, dir_kind, dd.ctypes.data_as(C.c_void_p),
+                                  sharp, None, None, C.c_longlong(0), C.byref(n))
         if st not in (0, 1) or n.value <= 0:
             _check(st)
         offs = np.zeros((n.value, 3), np.int32)
         fl = np.zeros(n.value, np.uint8)
-        _check(_L().imf_raster(self._ctx, ndim, C.byref(ct), dir_kind,
-                               dd.ctypes.data_as(C.c_void_p), sharp,
-                               offs.ctypes.data_as(C.c_void_p), fl.ctypes.data_as(C.c_void_p),
-                               n.value, C.byref(n)))
+        _check(_L().imf_raster_tool(self._ctx, tid, ndim, dir_kind,
+                                    dd.ctypes.data_as(C.c_void_p), sharp,
+                                    offs.ctypes.data_as(C.c_void_p),
+                                    fl.ctypes.data_as(C.c_void_p), C.c_longlong(n.value),
+                                    C.byref(n)))
         return offs, fl
 
     def fft_c2c(self, x, inverse=False, stream=None):

@@ -334,3 +334,54 @@ def test_long_cutter_uses_more_than_six_levels(ctx):
                           method=imf.METHOD_FFT)
     ref = oracle.imf(oracle.Request(d, fx, tools=tl, dirs=dirs, dir_kind=1))
     check_binary(out, ref)
+
+
+# ---------------------------------------------------------------------------
+# voxel-model tools under rotation matrices
+# ---------------------------------------------------------------------------
+
+def test_voxel_tool_raster_bit_exact(ctx):
+    import paper_2002_07627_amd as imf
+    t = W.asymmetric_tool()
+    rots = np.concatenate([W.random_rotations(24, 61), W.cube_rotations()[:6],
+                           np.stack([W.rotation_to([1, 1, 1], r) for r in (0.0, 0.7, 2.1)])])
+    for R in rots:
+        go, gf = ctx.raster(t, R, imf.DIR_ROTATION)
+        oo, oc = oracle.raster(t, R, 2)
+        a = {tuple(p): int(f) & 3 for p, f in zip(go.tolist(), gf)}
+        b = {tuple(p): 1 | (2 if c else 0) for p, c in zip(oo.tolist(), oc)}
+        assert a == b
+
+
+@pytest.mark.parametrize("sharp", [0, 1])
+def test_voxel_tool_imf_bit_exact(ctx, sharp):
+    """Non-axisymmetric voxel tool at random rotations and at one axis with three
+    rolls (roll matters for it), together with an axisymmetric tool given by
+    rotations, against the oracle."""
+    import paper_2002_07627_amd as imf
+    d = random_boxes((26, 28, 30), 11, 62)
+    fx = W.fixture_plate(d.shape, 2)
+    vt = W.asymmetric_tool(r=1, length=6, holder_half=3, holder_len=4)
+    ft = W.tool(W.TOOL_FLAT, 1, 5, 2, 3)
+    rv = np.concatenate([W.random_rotations(7, 63),
+                         np.stack([W.rotation_to([0, 1, 2], r) for r in (0.0, 1.0, 2.5)])])
+    rf = W.random_rotations(4, 64)
+    out, st = ctx.compute(dev(d), dev(fx), tools=[vt, ft], dirs=[rv, rf],
+                          dir_kind=imf.DIR_ROTATION, sharp=sharp, method=imf.METHOD_FFT)
+    ref = oracle.imf(oracle.Request(d, fx, tools=[vt, ft], dirs=[rv, rf], dir_kind=2,
+                                    sharp=sharp))
+    check_binary(out, ref)
+    assert st.n_orient == 14
+    # the three rolls about one axis give three different accessible sets
+    m = masks_u64(out["masks"])
+    assert len({m[7 + i].tobytes() for i in range(3)}) > 1
+
+
+def test_voxel_tool_rejects_bad_rotations(ctx):
+    import paper_2002_07627_amd as imf
+    d = dev(np.zeros((8, 8, 8), np.uint8))
+    vt = W.asymmetric_tool()
+    with pytest.raises(imf.IMFError):
+        ctx.compute(d, tools=vt, dirs=np.diag([1.0, 1.0, -1.0])[None], dir_kind=imf.DIR_ROTATION)
+    with pytest.raises(imf.IMFError):
+        ctx.compute(d, tools=vt, dirs=np.array([[0.0, 0.0, 1.0]]), dir_kind=imf.DIR_F64)
