@@ -57,7 +57,8 @@ class _Req(C.Structure):
                 ("domain", C.c_void_p), ("n_tools", C.c_int), ("tools", C.POINTER(_Tool)),
                 ("n_dirs", C.POINTER(C.c_int)), ("dir_kind", C.c_int), ("dirs", C.c_void_p),
                 ("sharp", C.c_int), ("lam", C.c_double), ("tau", C.c_double),
-                ("mask_theta_abs", C.c_double)]
+                ("mask_theta_abs", C.c_double), ("fixture_sets", C.c_void_p),
+                ("n_fixture_sets", C.c_int), ("fixture_of", C.c_void_p)]
 
 
 class _Out(C.Structure):
@@ -94,7 +95,8 @@ class Request:
     of :mod:`workloads`: ``[z][y][x]`` arrays, direction = tip toward holder."""
 
     def __init__(self, design, fixture=None, domain=None, tools=(), dirs=(), dir_kind=0,
-                 density=None, sharp=0, lam=0.0, tau=0.5, mask_theta_abs=-1.0):
+                 density=None, sharp=0, lam=0.0, tau=0.5, mask_theta_abs=-1.0,
+                 fixture_sets=None, fixture_of=None):
         design = np.ascontiguousarray(design)
         self.ndim = design.ndim
         if self.ndim == 2:
@@ -120,6 +122,11 @@ class Request:
         assert self.dirs.shape[1] == (9 if self.dir_kind == 2 else self.ndim)
         self.sharp, self.lam, self.tau = int(sharp), float(lam), float(tau)
         self.mask_theta_abs = float(mask_theta_abs)
+        # fixtures per setup: orientation R sees fixture | fixture_sets[fixture_of[R]]
+        self.fixture_sets = None if fixture_sets is None else np.ascontiguousarray(
+            np.asarray(fixture_sets).reshape((-1,) + self.design.shape), dtype=np.uint8)
+        self.fixture_of = None if fixture_of is None else np.ascontiguousarray(
+            fixture_of, dtype=np.int32)
         self._c = self._make()
 
     @property
@@ -144,6 +151,10 @@ class Request:
         r.dir_kind, r.dirs = self.dir_kind, _ptr(self.dirs)
         r.sharp, r.lam, r.tau, r.mask_theta_abs = self.sharp, self.lam, self.tau, \
             self.mask_theta_abs
+        if self.fixture_sets is not None:
+            r.fixture_sets = _ptr(self.fixture_sets)
+            r.n_fixture_sets = len(self.fixture_sets)
+            r.fixture_of = _ptr(self.fixture_of)
         return r
 
     @property

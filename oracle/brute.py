@@ -85,10 +85,13 @@ def _shift_sum(field, offsets, lo, dims):
     return out
 
 
-def imf(design, fixture, tool, dirs, lam=0.0, tau=0.5, scale=1):
+def imf(design, fixture, tool, dirs, lam=0.0, tau=0.5, scale=1, fixture_sets=None,
+        fixture_of=None):
     """Brute-force f, F_max, fbar, Gamma and accessible masks (bool [nR, ...]).
 
-    ``design`` holds integers in fixed point (``scale`` = 1 for binary)."""
+    ``design`` holds integers in fixed point (``scale`` = 1 for binary).  With
+    ``fixture_sets``, orientation i sees the fixture ``fixture | fixture_sets[
+    fixture_of[i]]`` and the design domain excludes every fixture voxel."""
     design = np.asarray(design, dtype=np.int64)
     ndim = design.ndim
     d3 = design.reshape((1,) * (3 - ndim) + design.shape)
@@ -96,16 +99,22 @@ def imf(design, fixture, tool, dirs, lam=0.0, tau=0.5, scale=1):
         np.asarray(fixture).reshape(d3.shape).astype(np.int64)
     rhoO = np.where(fix > 0, scale, d3)
     omega0 = fix == 0
+    rhoO_of = [rhoO] * len(dirs)
+    if fixture_sets is not None:
+        sets = [np.asarray(f).reshape(d3.shape) != 0 for f in fixture_sets]
+        rhoO_of = [np.where(sets[fixture_of[i]], scale, rhoO) for i in range(len(dirs))]
+        for f in sets:
+            omega0 = omega0 & ~f
     nz, ny, nx = d3.shape
     f = np.full(d3.shape, np.iinfo(np.int64).max, dtype=np.int64)
     gammas, frees = [], []
-    for v in dirs:
+    for i, v in enumerate(dirs):
         T, K = raster(tool, v)
         # gamma_R(x) = min over k of the overlap of the tool placed with k on x
         gam = np.full(d3.shape, np.iinfo(np.int64).max, dtype=np.int64)
         for k in K:
             placed = [(o[0] - k[0], o[1] - k[1], o[2] - k[2]) for o in T]
-            ov = _shift_sum(rhoO, placed, (0, 0, 0), (nx, ny, nz))
+            ov = _shift_sum(rhoO_of[i], placed, (0, 0, 0), (nx, ny, nz))
             gam = np.minimum(gam, ov)
         gammas.append(gam)
         f = np.minimum(f, gam)
@@ -118,12 +127,12 @@ def imf(design, fixture, tool, dirs, lam=0.0, tau=0.5, scale=1):
     gamma_set = B & ~solid
     # accessibility by sweeping free translations (threshold theta = lambda F_max)
     masks = []
-    for (T, K) in frees:
+    for i, (T, K) in enumerate(frees):
         Tarr = np.array(T)
         lo = tuple(int(-Tarr[:, a].max()) for a in range(3))
         dims = tuple(int((nx, ny, nz)[a] + Tarr[:, a].max() - Tarr[:, a].min())
                      for a in range(3))
-        g = _shift_sum(rhoO, T, lo, dims)
+        g = _shift_sum(rhoO_of[i], T, lo, dims)
         free = g.astype(np.float64) <= thB
         acc = np.zeros(d3.shape, dtype=bool)
         fz, fy, fx = np.nonzero(free)

@@ -64,6 +64,13 @@ typedef struct {
   const void *dirs;
   int sharp; /* 0 all cutter voxels, 1 boundary voxels, 2 tip voxel */
   double lambda, tau, mask_theta_abs;
+  /* fixtures that change with the setup (Sec. 2.1.5: the fixture, hence O,
+   * may differ per re-clamping, known beforehand): orientation R sees
+   * F_R = fixture u fixture_sets[fixture_of[R]]; Omega_0 (without a domain)
+   * excludes every fixture voxel of every setup */
+  const uint8_t *fixture_sets; /* [n_fixture_sets][N], or NULL */
+  int n_fixture_sets;
+  const int *fixture_of;       /* [n_orient] */
 } or_request;
 
 typedef struct {
@@ -384,16 +391,32 @@ typedef struct {
   int nx, ny, nz;
   long long N;
   int64_t scale; /* 1 for binary, 2^24 for density */
-  int64_t *rhoO; /* obstacle field in fixed point */
+  int64_t *rhoO; /* obstacle field of the current orientation, fixed point */
   int64_t *rhoD; /* design field in fixed point */
   uint8_t *omega0;
+  int64_t *rhoO_base; /* with the common fixture only */
+  int64_t **rhoO_sets; /* per fixture set, or NULL */
+  int nsets;
 } fields;
 
 static void fields_free(fields *F) {
-  free(F->rhoO);
+  free(F->rhoO_base);
+  for (int s = 0; s < F->nsets; s++) free(F->rhoO_sets[s]);
+  free(F->rhoO_sets);
   free(F->rhoD);
   free(F->omega0);
   memset(F, 0, sizeof(*F));
+}
+
+/* the obstacle field rho_O seen by orientation `orient` */
+static void fields_select(fields *F, const or_request *q, int orient) {
+  F->rhoO = F->nsets ? F->rhoO_sets[q->fixture_of[orient]] : F->rhoO_base;
+}
+
+static int count_orient_req(const or_request *q) {
+  int n = 0;
+  for (int i = 0; i < q->n_tools; i++) n += q->n_dirs[i];
+  return n;
 }
 
 static int fields_build(fields *F, const or_request *q) {
@@ -406,10 +429,11 @@ static int fields_build(fields *F, const or_request *q) {
   F->nz = q->nz;
   F->N = (long long)q->nx * q->ny * q->nz;
   F->scale = q->density ? ((int64_t)1 << 24) : 1;
-  F->rhoO = (int64_t *)malloc(sizeof(int64_t) * (size_t)F->N);
+  F->rhoO_base = (int64_t *)malloc(sizeof(int64_t) * (size_t)F->N);
+  F->rhoO = F->rhoO_base;
   F->rhoD = (int64_t *)malloc(sizeof(int64_t) * (size_t)F->N);
   F->omega0 = (uint8_t *)malloc((size_t)F->N);
-  if (!F->rhoO || !F->rhoD || !F->omega0) {
+  if (!F->rhoO_base || !F->rhoD || !F->omega0) {
     fields_free(F);
     return OR_ENOMEM;
   }
@@ -433,8 +457,38 @@ static int fields_build(fields *F, const or_request *q) {
     }
     F->rhoD[i] = v;
     const int fix = q->fixture ? (q->fixture[i] != 0) : 0;
-    F->rhoO[i] = fix ? F->scale : v; /* max(rho_Omega, 1_F) */
+    F->rhoO_base[i] = fix ? F->scale : v; /* max(rho_Omega, 1_F) */
     F->omega0[i] = q->domain ? (q->domain[i] != 0) : (uint8_t)!fix;
+  }
+  if (q->n_fixture_sets > 0) {
+    if (!q->fixture_sets || !q->fixture_of) {
+      fields_free(F);
+      return OR_EINVAL;
+    }
+    F->nsets = q->n_fixture_sets;
+    F->rhoO_sets = (int64_t **)calloc((size_t)F->nsets, sizeof(int64_t *));
+    if (!F->rhoO_sets) {
+      fields_free(F);
+      return OR_ENOMEM;
+    }
+    for (int s = 0; s < F->nsets; s++) {
+      F->rhoO_sets[s] = (int64_t *)malloc(sizeof(int64_t) * (size_t)F->N);
+      if (!F->rhoO_sets[s]) {
+        fields_free(F);
+        return OR_ENOMEM;
+      }
+      const uint8_t *fs = q->fixture_sets + (size_t)s * F->N;
+      for (long long i = 0; i < F->N; i++) {
+        F->rhoO_sets[s][i] = fs[i] ? F->scale : F->rhoO_base[i];
+        if (fs[i] && !q->domain) F->omega0[i] = 0;
+      }
+    }
+    const int nO = count_orient_req(q);
+    for (int r = 0; r < nO; r++)
+      if (q->fixture_of[r] < 0 || q->fixture_of[r] >= F->nsets) {
+        fields_free(F);
+        return OR_EINVAL;
+      }
   }
   return OR_OK;
 }
@@ -504,6 +558,7 @@ int or_imf(const or_request *q, const or_outputs *out) {
 
   for (int r = 0; r < nO && st == OR_OK; r++) {
     oriented_tool o;
+    fields_select(&F, q, r);
     st = build_orient(q, r, &o);
     if (st) break;
     /* query box of translations: t = x - k, x in grid, k in S_R */
@@ -602,6 +657,7 @@ int or_imf(const or_request *q, const or_outputs *out) {
     memset(out->masks_dil, 0, sizeof(uint64_t) * (size_t)nO * nz * ny * words);
     for (int r = 0; r < nO && st == OR_OK; r++) {
       oriented_tool o;
+      fields_select(&F, q, r);
       st = build_orient(q, r, &o);
       if (st) break;
       long long lo[3], dim[3];
@@ -658,6 +714,7 @@ int or_overlap_at(const or_request *q, int orient, const int32_t *t, long long n
   int st = fields_build(&F, q);
   if (st) return st;
   oriented_tool o;
+  fields_select(&F, q, orient);
   st = build_orient(q, orient, &o);
   if (st) {
     fields_free(&F);
@@ -677,6 +734,7 @@ int or_gamma_at(const or_request *q, int orient, const int32_t *xs, long long n,
   int st = fields_build(&F, q);
   if (st) return st;
   oriented_tool o;
+  fields_select(&F, q, orient);
   st = build_orient(q, orient, &o);
   if (st) {
     fields_free(&F);
@@ -707,6 +765,7 @@ int or_gamma_at_all(const or_request *q, const int32_t *xs, long long n, int64_t
   const int nO = count_orient(q);
   for (int r = 0; r < nO; r++) {
     oriented_tool o;
+    fields_select(&F, q, r);
     st = build_orient(q, r, &o);
     if (st) {
       fields_free(&F);
@@ -736,6 +795,7 @@ int or_overlap_full(const or_request *q, int orient, int64_t *out, int *box) {
   int st = fields_build(&F, q);
   if (st) return st;
   oriented_tool o;
+  fields_select(&F, q, orient);
   st = build_orient(q, orient, &o);
   if (st) {
     fields_free(&F);

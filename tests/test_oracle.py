@@ -521,3 +521,45 @@ def test_voxel_tool_random_rotations_keep_the_volume():
         assert cut.any() and (~cut).any()
     with pytest.raises(ValueError):
         oracle.raster(t, np.diag([1.0, 1.0, -1.0]))        # a reflection, not a rotation
+
+
+# ---------------------------------------------------------------------------
+# fixtures that change with the setup
+# ---------------------------------------------------------------------------
+
+def test_fixture_sets_equal_brute_force():
+    rng = np.random.default_rng(91)
+    d = (rng.random((7, 8, 9)) < 0.3).astype(np.uint8)
+    fx = fixture_plate(d.shape, 1)
+    sets = np.zeros((2,) + d.shape, np.uint8)
+    sets[0][:, :, :2] = 1          # a clamp on the low-x side
+    sets[1][:, :2, :] = 1          # a clamp on the low-y side
+    tl = tool(TOOL_FLAT, 1, 3, 2, 2)
+    dirs = lattice26()[::4]
+    fof = np.array([0, 0, 1, 1, 0, 1, 1][:len(dirs)], np.int32)
+    b = brute.imf(d.astype(np.int64), fx, tl, dirs, fixture_sets=sets, fixture_of=fof)
+    o = oracle.imf(oracle.Request(d, fx, tools=tl, dirs=dirs, dir_kind=1, fixture_sets=sets,
+                                  fixture_of=fof))
+    assert np.array_equal(o["imf"], b["imf"].astype(np.float64))
+    assert np.array_equal(o["secluded"].astype(bool), b["secluded"])
+    m = oracle.unpack_masks(o["masks"], 9).reshape(b["masks"].shape)
+    assert np.array_equal(m, b["masks"])
+    assert np.array_equal(oracle.unpack_masks(o["masks_dil"], 9).reshape(b["masks"].shape),
+                          b["masks"])
+    # the design domain excludes every setup's fixture
+    assert not o["imf_norm"][sets.any(0) != 0].any()
+
+
+def test_identical_fixture_sets_reduce_to_one_fixture():
+    rng = np.random.default_rng(92)
+    d = (rng.random((8, 9, 10)) < 0.3).astype(np.uint8)
+    fx = fixture_plate(d.shape, 2)
+    tl = tool(TOOL_FLAT, 1, 3, 2, 2)
+    dirs = lattice26()[::3]
+    a = oracle.imf(oracle.Request(d, fx, tools=tl, dirs=dirs, dir_kind=1))
+    sets = np.stack([fx, fx, fx])
+    fof = np.arange(len(dirs)) % 3
+    b = oracle.imf(oracle.Request(d, None, tools=tl, dirs=dirs, dir_kind=1, fixture_sets=sets,
+                                  fixture_of=fof))
+    for k in ("imf", "imf_norm", "secluded", "masks"):
+        assert np.array_equal(a[k], b[k]), k
