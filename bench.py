@@ -310,6 +310,26 @@ def main():
         "greedy plan %d steps in %.1f ms" % (1000 * t_h, bh / t_h / 1e9, 1000 * t_f,
                                              bf / t_f / 1e9, len(plan), 1000 * t_p))
     del out_c, xi, sens, rho_c
+    # fixtures that change with the setup: four vise setups, the orientations
+    # grouped by azimuth sector (one extra design transform and prefix sum per
+    # setup, batches split at setup changes)
+    n_sets = 4
+    fof = W.setup_of_dirs(w.dirs, n_sets)
+    order = np.argsort(fof, kind="stable")
+    sets = torch.from_numpy(W.setup_clamps(w.design.shape, n_sets)).to(dev)
+    skw = dict(kw, dirs=w.dirs[order])
+    ctx.compute(design, fixture, **skw, fixture_sets=sets, fixture_of=fof[order])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for i in range(args.steps):
+        _, ss = ctx.compute(design, fixture, **skw, fixture_sets=sets, fixture_of=fof[order],
+                            flags=imf.FLAG_NO_GRAPH)
+    torch.cuda.synchronize()
+    set_ms = 1000 * (time.perf_counter() - t1) / args.steps
+    setups = {"n_sets": n_sets, "ms_per_step": set_ms, "value": N * nR / (set_ms * 1e-3),
+              "vs_one_fixture": ms / set_ms}
+    log("%d setups with their own fixtures: %.2f ms/step" % (n_sets, set_ms))
+    del sets
     ctx.close()
     # cold tool-spectrum cache: the same request on a fresh context
     ctx = imf.Context(0)
@@ -358,6 +378,7 @@ def main():
         "cold_cache_ms": cold_ms,
         "graph_replay_ms_per_step": graph_ms,
         "coupling": coupling,
+        "setups": setups,
         "serving": serving,
         "kernels": kernels,
         "guard": {"F_max": last.F_max, "max_frac_err": last.max_frac_err,

@@ -126,6 +126,17 @@ typedef struct {
   int method;                  /* IMF_METHOD_* */
   int batch;                   /* orientations per batch, 0: automatic */
   unsigned flags;              /* IMF_FLAG_* */
+  /* Fixtures that change with the setup (Sec. 2.1.5: the fixture, hence the
+     obstacle O, may differ per re-clamping when the setups are known beforehand).
+     Orientation q (in the order of dirs) sees the fixture
+     fixture | fixture_sets[fixture_of[q]]; without a domain, Omega_0 excludes the
+     voxels of every set.  0 sets: one fixture for all orientations (both pointers
+     ignored).  Orientations of one set need not be contiguous, but each change of
+     set along dirs starts a new batch, so grouping them is faster.  Caller-owned;
+     fixture_of is read during the call only (imf_submit copies it). */
+  int n_fixture_sets;           /* 0 .. 256 */
+  const uint8_t* fixture_sets;  /* device [n_fixture_sets][nz][ny][nx], nonzero = fixture */
+  const int* fixture_of;        /* host [sum n_dirs], each in [0, n_fixture_sets) */
 } imf_request;
 
 typedef struct {

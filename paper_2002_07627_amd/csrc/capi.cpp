@@ -676,6 +676,10 @@ struct Plan {
   int shape;
   long long cell_stride, nblocks, cell_waves, nwords_blk;
   int tuned_batch = 8, tuned_shape = 2, wg_per_cu = 4;  // launch parameters in effect
+  // batches: orientations [bstart[b], bstart[b+1]), all seeing fixture set bset[b]
+  // (0 without fixture sets); at most B wide, split wherever the set changes
+  std::vector<int> bstart, bset;
+  int nsets = 0;  // fixture sets (0: the common fixture only)
   double theta;
   double band;
   // workspace layout (bytes)
@@ -698,6 +702,18 @@ static imf_status validate(const imf_request* r) {
   if (!std::isfinite(r->tau)) return fail(IMF_EINVAL, "tau is not finite");
   if (r->method < 0 || r->method > 2) return fail(IMF_EINVAL, "unknown method");
   if (r->batch < 0 || r->batch > 64) return fail(IMF_EINVAL, "batch must be in [0, 64]");
+  if (r->n_fixture_sets < 0 || r->n_fixture_sets > 256)
+    return fail(IMF_EINVAL, "n_fixture_sets must be in [0, 256]");
+  if (r->n_fixture_sets > 0) {
+    if (!r->fixture_sets || !r->fixture_of)
+      return fail(IMF_EINVAL, "fixture sets need fixture_sets and fixture_of");
+    long long nO = 0;
+    for (int i = 0; i < r->n_tools; i++) nO += std::max(r->n_dirs[i], 0);
+    for (long long q = 0; q < nO; q++)
+      if (r->fixture_of[q] < 0 || r->fixture_of[q] >= r->n_fixture_sets)
+        return fail(IMF_EINVAL, "fixture_of[%lld] = %d is not a fixture set", q,
+                    r->fixture_of[q]);
+  }
   return IMF_OK;
 }
 
@@ -799,6 +815,17 @@ static imf_status make_plan(imf_ctx* c, const imf_request* r, const imf_outputs*
   if (p.B == 0) p.B = p.tuned_batch;
   if (plain) p.B = 1;
   p.B = std::max(1, std::min(p.B, p.nO));
+  p.nsets = r->n_fixture_sets;
+  p.bstart.assign(1, 0);
+  p.bset.clear();
+  for (int q = 0; q < p.nO;) {
+    const int set = p.nsets ? r->fixture_of[q] : 0;
+    int e = q + 1;
+    while (e < p.nO && e - q < p.B && (!p.nsets || r->fixture_of[e] == set)) e++;
+    p.bset.push_back(set);
+    p.bstart.push_back(e);
+    q = e;
+  }
   // thresholds
   p.masks = out && out->acc_masks;
   p.sweep = p.masks && (r->flags & IMF_FLAG_MASK_SWEEP);
@@ -857,9 +884,11 @@ static imf_status make_plan(imf_ctx* c, const imf_request* r, const imf_outputs*
   const long long N = p.N;
   add(sizeof(float) * N);                              // f
   add(N);                                              // omega0
-  add(sizeof(long long) * (r->nx + 1) * (long long)r->ny * r->nz);  // prefix sums
+  const int nps = std::max(p.nsets, 1);
+  add(sizeof(long long) * (r->nx + 1) * (long long)r->ny * r->nz * nps);  // prefix sums
+  if (p.nsets) add((size_t)N * (p.nsets + 1));       // fixture of each setup, union
   add(256);                                            // fmax + max_err
-  const int nb = (p.nO + p.B - 1) / p.B;
+  const int nb = (int)p.bset.size();
   add(sizeof(int) * (nb + 1));                         // per-batch flag counters
   add(sizeof(int2) * (size_t)(1 << 20));               // flag list
   add(sizeof(imf_orient_desc) * p.nO * 2);             // descriptors (+ sweep)
@@ -878,7 +907,7 @@ static imf_status make_plan(imf_ctx* c, const imf_request* r, const imf_outputs*
   }
   if (p.sweep) add(sizeof(uint64_t) * p.B * ((p.max_m[0] + 63) / 64) * (long long)p.max_m[1] * p.max_m[2]);
   if (p.method == IMF_METHOD_FFT) {
-    add(sizeof(float2) * p.spec_elems);                                  // rho_hat
+    add(sizeof(float2) * p.spec_elems * nps);                            // rho_hat per set
     add(sizeof(float2) * (long long)r->nz * r->ny * h);                  // fwd work1
     add(sizeof(float2) * (long long)r->nz * p.P[1] * h);                 // fwd work2
     add(sizeof(float2) * p.B * (long long)p.max_t[2] * p.max_t[1] * h);  // tool work1
@@ -1044,13 +1073,16 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
   STCHK(arena_reserve(c, ar, p.ws_bytes));
   const long long N = p.N;
   const int h = p.P[0] / 2 + 1;
-  const int nb = (p.nO + p.B - 1) / p.B;
+  const int nb = (int)p.bset.size();
   pd.nb = nb;
   if (nb + 2 > (1 << 14)) return fail(IMF_EINVAL, "too many batches");
+  const int nps = std::max(p.nsets, 1);
   // carve the workspace (same order as make_plan)
   float* f = carve<float>(ar, N);
   uint8_t* om = carve<uint8_t>(ar, N);
-  long long* ps = carve<long long>(ar, (r->nx + 1) * (long long)r->ny * r->nz);
+  const long long ps_stride = (r->nx + 1) * (long long)r->ny * r->nz;
+  long long* ps = carve<long long>(ar, ps_stride * nps);
+  uint8_t* setfix = p.nsets ? carve<uint8_t>(ar, N * (p.nsets + 1)) : nullptr;
   unsigned int* misc = carve<unsigned int>(ar, 64);
   unsigned int* fmax_bits = misc;
   unsigned int* maxerr_bits = misc + 1;
@@ -1080,7 +1112,7 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
   const long long w1_stride = (long long)p.max_m[2] * p.P[1] * h;
   const long long w2_stride = (long long)p.max_m[2] * p.max_m[1] * h;
   if (p.method == IMF_METHOD_FFT) {
-    rho_hat = carve<float2>(ar, p.spec_elems);
+    rho_hat = carve<float2>(ar, p.spec_elems * nps);
     fw1 = carve<float2>(ar, (long long)r->nz * r->ny * h);
     fw2 = carve<float2>(ar, (long long)r->nz * p.P[1] * h);
     tw1 = carve<float2>(ar, p.B * tw1_stride);
@@ -1130,7 +1162,7 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
   if (d_miss) {
     hmiss.resize((size_t)nb * p.B);
     for (int b = 0; b < nb; b++)
-      for (int q = b * p.B; q < std::min(p.nO, (b + 1) * p.B); q++)
+      for (int q = p.bstart[b]; q < p.bstart[b + 1]; q++)
         if (need_fft[q]) hmiss[(size_t)b * p.B + nmiss[b]++] = p.desc[q];
   }
   HIPCHK(hipMemcpy(d_desc, hall.data(), sizeof(imf_orient_desc) * hall.size(),
@@ -1168,6 +1200,11 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
       ndir += r->n_dirs[i];
     }
     put(r->dirs, (size_t)ndir * r->ndim * (r->dir_kind == IMF_DIR_LATTICE ? 4 : 8));
+    put(&r->n_fixture_sets, sizeof(int));
+    if (r->n_fixture_sets) {
+      put(&r->fixture_sets, sizeof(void*));
+      put(r->fixture_of, sizeof(int) * (size_t)ndir);
+    }
     put(&p.B, sizeof(p.B));
     put(p.P, sizeof(p.P));
     put(&ar.base, sizeof(ar.base));
@@ -1181,7 +1218,17 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
   // setup
   HIPCHK(imf_launch_fill_u32(misc, 64, 0u, s));
   HIPCHK(imf_launch_fill_u32((unsigned*)flag_cnt, nb + 1, 0u, s));
-  HIPCHK(imf_launch_omega0(r->fixture, r->domain, om, N, s));
+  // fixture of each setup (the common fixture with that setup's set) and their union
+  const uint8_t* fix_all = r->fixture;
+  if (p.nsets) {
+    for (int k = 0; k < p.nsets; k++)
+      HIPCHK(imf_launch_or_u8(r->fixture, r->fixture_sets + (size_t)N * k, setfix + N * k, N, s));
+    uint8_t* uni = setfix + N * p.nsets;
+    HIPCHK(imf_launch_or_u8(nullptr, setfix, uni, N, s));
+    for (int k = 1; k < p.nsets; k++) HIPCHK(imf_launch_or_u8(uni, setfix + N * k, uni, N, s));
+    fix_all = uni;
+  }
+  HIPCHK(imf_launch_omega0(fix_all, r->domain, om, N, s));
   HIPCHK(imf_launch_fill_f(f, N, INFINITY, s));
   if (fblock) HIPCHK(imf_launch_fill_f(fblock, p.nblocks, INFINITY, s));
   // the minimum pass writes the mask chunks of the blocks it computes: clear
@@ -1193,22 +1240,35 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
     // skipped blocks leave gamma = +inf behind
     if (gstack) HIPCHK(imf_launch_fill_f(gstack, (long long)N * p.nO, INFINITY, s));
   }
-  HIPCHK(imf_launch_prefix_x(r->design, r->design_is_density, r->fixture, r->nx, r->ny, r->nz, ps,
-                             s));
+  for (int k = 0; k < nps; k++)
+    HIPCHK(imf_launch_prefix_x(r->design, r->design_is_density,
+                               p.nsets ? setfix + N * k : r->fixture, r->nx, r->ny, r->nz,
+                               ps + ps_stride * k, s));
   tm.mark(1);
   const double esz = r->design_is_density ? 4.0 : 1.0;
   const double S = 8.0 * (double)p.spec_elems;
-  pd.kbytes[1] = (double)N * (esz + 2 + 4) + 8.0 * (r->nx + 1) * (double)r->ny * r->nz;
+  const bool has_fix = r->fixture || p.nsets;
+  // Omega_0 (fixture read, mask write), f fill, per set the prefix sums
+  // (design and fixture read, sums written), per set the fixture and union masks
+  pd.kbytes[1] = (double)N * ((has_fix ? 1 : 0) + 1 + 4) +
+                 nps * ((double)N * (esz + (has_fix ? 1 : 0)) + 8.0 * ps_stride) +
+                 6.0 * N * p.nsets;
   if (p.method == IMF_METHOD_FFT) {
-    pd.kbytes[2] = (double)N * (esz + (r->fixture ? 1 : 0)) + S;
-    imf_fwd_design_args fa{r->design, r->design_is_density, r->fixture, r->nx, r->ny, r->nz,
-                           p.P[0], p.P[1], p.P[2], fw1, fw2, rho_hat};
-    HIPCHK(imf_launch_fwd_design(fa, p.fl[0], p.fl[1], p.fl[2], twx, twy, twz, s));
+    pd.kbytes[2] = nps * ((double)N * (esz + (has_fix ? 1 : 0)) + S);
+    for (int k = 0; k < nps; k++) {
+      imf_fwd_design_args fa{r->design, r->design_is_density,
+                             p.nsets ? setfix + N * k : r->fixture, r->nx, r->ny, r->nz,
+                             p.P[0], p.P[1], p.P[2], fw1, fw2, rho_hat + p.spec_elems * k};
+      HIPCHK(imf_launch_fwd_design(fa, p.fl[0], p.fl[1], p.fl[2], twx, twy, twz, s));
+    }
     tm.mark(2);
   }
   for (int b = 0; b < nb; b++) {
-    const int q0 = b * p.B;
-    const int nq = std::min(p.B, p.nO - q0);
+    const int q0 = p.bstart[b];
+    const int nq = p.bstart[b + 1] - q0;
+    // the obstacle of this batch's setup: its spectrum and prefix sums
+    const long long* ps_b = ps + ps_stride * p.bset[b];
+    const float2* rho_hat_b = rho_hat ? rho_hat + p.spec_elems * p.bset[b] : nullptr;
     const imf_orient_desc* bd = d_desc + q0;
     // algorithmic bytes of this batch, per kernel class
     for (int q = q0; q < q0 + nq; q++) {
@@ -1259,7 +1319,7 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
       imf_inv_args ia{};
       ia.desc = bd;
       ia.nq = nq;
-      ia.rho_hat = rho_hat;
+      ia.rho_hat = rho_hat_b;
       ia.px = p.P[0];
       ia.py = p.P[1];
       ia.pz = p.P[2];
@@ -1286,12 +1346,12 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
         tm.mark(6 + stage);
       }
       if (ia.binary || ia.theta_known) {
-        HIPCHK(imf_launch_recheck(bd, ps, r->nx, r->ny, r->nz, r->design_is_density, flag_cnt + b,
+        HIPCHK(imf_launch_recheck(bd, ps_b, r->nx, r->ny, r->nz, r->design_is_density, flag_cnt + b,
                                   flags, flag_cap, ia.theta_known, p.theta, g, p.max_vol, s));
         tm.mark(9);
       }
     } else {
-      HIPCHK(imf_launch_direct(bd, nq, ps, r->nx, r->ny, r->nz, r->design_is_density, g,
+      HIPCHK(imf_launch_direct(bd, nq, ps_b, r->nx, r->ny, r->nz, r->design_is_density, g,
                                p.max_vol, (int)p.max_vol, s));
       tm.mark(8);
     }
@@ -1852,7 +1912,7 @@ struct Request {
   uint64_t ticket;
   imf_request req;
   imf_outputs out;
-  std::vector<int> tool_ids, n_dirs;
+  std::vector<int> tool_ids, n_dirs, fixture_of;
   std::vector<char> dirs;
   size_t footprint = 0;
   int state = 0;  // 0 queued, 1 running, 2 done, 3 cancelled
@@ -1949,6 +2009,10 @@ extern "C" imf_status imf_submit(imf_ctx* c, const imf_request* r, const imf_out
   rq->req.tool_ids = rq->tool_ids.data();
   rq->req.n_dirs = rq->n_dirs.data();
   rq->req.dirs = rq->dirs.data();
+  if (r->n_fixture_sets > 0) {
+    rq->fixture_of.assign(r->fixture_of, r->fixture_of + nd);
+    rq->req.fixture_of = rq->fixture_of.data();
+  }
   STCHK(imf_query_footprint(c, &rq->req, &rq->footprint));
   rq->t_submit = std::chrono::steady_clock::now();
   {

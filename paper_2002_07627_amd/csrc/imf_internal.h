@@ -215,6 +215,8 @@ hipError_t imf_launch_fill_f(float* f, long long n, float v, hipStream_t s);
 hipError_t imf_launch_fill_u32(unsigned int* p, long long n, unsigned int v, hipStream_t s);
 hipError_t imf_launch_omega0(const uint8_t* fixture, const uint8_t* domain, uint8_t* omega0,
                              long long n, hipStream_t s);
+hipError_t imf_launch_or_u8(const uint8_t* a, const uint8_t* b, uint8_t* out, long long n,
+                            hipStream_t s);
 hipError_t imf_launch_fmax(const float* f, const uint8_t* omega0, long long n,
                            unsigned int* fmax_bits, hipStream_t s);
 hipError_t imf_launch_finalize(const float* f, const uint8_t* omega0, const void* design,

@@ -1040,6 +1040,22 @@ hipError_t imf_launch_omega0(const uint8_t* fixture, const uint8_t* domain, uint
   return hipGetLastError();
 }
 
+// out = (a != 0) | (b != 0), a may be NULL: the fixture of one setup (the
+// common fixture with that setup's set), or the union over every setup
+__global__ void k_or_u8(const uint8_t* __restrict__ a, const uint8_t* __restrict__ b,
+                        uint8_t* __restrict__ out, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    out[i] = (uint8_t)(((a ? a[i] : 0) | b[i]) != 0);
+}
+hipError_t imf_launch_or_u8(const uint8_t* a, const uint8_t* b, uint8_t* out, long long n,
+                            hipStream_t s) {
+  long long blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_or_u8, dim3((unsigned)blocks), dim3(256), 0, s, a, b, out, n);
+  return hipGetLastError();
+}
+
 // F_max = max of f over Omega_0 (0 if Omega_0 is empty); stored order-mapped
 __global__ void __launch_bounds__(IMF_WG) k_fmax(const float* __restrict__ f,
                                                  const uint8_t* __restrict__ om, long long n,

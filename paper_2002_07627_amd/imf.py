@@ -47,7 +47,8 @@ class _Request(C.Structure):
                 ("n_dirs", C.c_void_p), ("dir_kind", C.c_int), ("dirs", C.c_void_p),
                 ("sharp", C.c_int), ("lam", C.c_double), ("tau", C.c_double),
                 ("mask_theta_abs", C.c_double), ("method", C.c_int), ("batch", C.c_int),
-                ("flags", C.c_uint)]
+                ("flags", C.c_uint), ("n_fixture_sets", C.c_int),
+                ("fixture_sets", C.c_void_p), ("fixture_of", C.c_void_p)]
 
 
 class _Outputs(C.Structure):
@@ -188,7 +189,7 @@ class Context:
 
     # ------------------------------------------------------------------ request
     def _request(self, design, fixture, domain, tools, dirs, dir_kind, sharp, lam, tau,
-                 mask_theta_abs, method, batch, flags):
+                 mask_theta_abs, method, batch, flags, fixture_sets=None, fixture_of=None):
         import torch
         if not design.is_cuda:
             raise ValueError("design must be a device tensor")
@@ -230,7 +231,22 @@ class Context:
         r.dirs = dd.ctypes.data_as(C.c_void_p)
         r.sharp, r.lam, r.tau, r.mask_theta_abs = sharp, lam, tau, mask_theta_abs
         r.method, r.batch, r.flags = method, batch, flags
-        keep = (ids, nd, dd, design, fixture, domain)
+        fof = None
+        if fixture_sets is not None:
+            # one fixture per setup: [n_sets, *design.shape] uint8 on the device,
+            # fixture_of[q] names the set of orientation q
+            if fixture_sets.dtype != torch.uint8 or not fixture_sets.is_cuda or \
+                    not fixture_sets.is_contiguous() or \
+                    fixture_sets.numel() % max(design.numel(), 1) or fixture_sets.numel() == 0:
+                raise ValueError("fixture_sets must be a contiguous uint8 device tensor of "
+                                 "shape [n_sets, *design.shape]")
+            fof = np.ascontiguousarray(fixture_of, dtype=np.int32).reshape(-1)
+            if len(fof) != int(nd.sum()):
+                raise ValueError("fixture_of needs one set index per orientation")
+            r.n_fixture_sets = fixture_sets.numel() // design.numel()
+            r.fixture_sets = _ptr(fixture_sets)
+            r.fixture_of = fof.ctypes.data_as(C.c_void_p)
+        keep = (ids, nd, dd, design, fixture, domain, fixture_sets, fof)
         return r, keep, (nz, ny, nx), int(nd.sum())
 
     def _outputs(self, shape, n_orient, masks, debug_orient, device, debug_numel=0, out=None):
@@ -262,9 +278,10 @@ class Context:
 
     def footprint(self, design, fixture=None, domain=None, *, tools, dirs, dir_kind=DIR_F64,
                   sharp=SHARP_ALL, lam=0.0, tau=0.5, mask_theta_abs=-1.0, method=METHOD_AUTO,
-                  batch=0, flags=0) -> int:
+                  batch=0, flags=0, fixture_sets=None, fixture_of=None) -> int:
         r, keep, _, _ = self._request(design, fixture, domain, tools, dirs, dir_kind, sharp, lam,
-                                      tau, mask_theta_abs, method, batch, flags)
+                                      tau, mask_theta_abs, method, batch, flags, fixture_sets,
+                                      fixture_of)
         b = C.c_size_t()
         _check(_L().imf_query_footprint(self._ctx, C.byref(r), C.byref(b)))
         return b.value
@@ -272,13 +289,15 @@ class Context:
     def compute(self, design, fixture=None, domain=None, *, tools, dirs, dir_kind=DIR_F64,
                 sharp=SHARP_ALL, lam=0.0, tau=0.5, mask_theta_abs=-1.0, method=METHOD_AUTO,
                 batch=0, flags=0, masks=True, debug_orient=-1, debug_numel=0, stream=None,
-                out=None):
+                out=None, fixture_sets=None, fixture_of=None):
         """Run one request; returns a dict of device tensors and a Stats.  `out`
         may hold preallocated outputs ("imf", "imf_norm", "secluded", "masks"),
-        which a loop reuses so that its repeated requests replay one HIP graph."""
+        which a loop reuses so that its repeated requests replay one HIP graph.
+        `fixture_sets` ([n_sets, *shape] uint8, device) with `fixture_of` (one set
+        index per orientation) give each setup its own extra fixture."""
         r, keep, shape, n_orient = self._request(design, fixture, domain, tools, dirs,
                                                  dir_kind, sharp, lam, tau, mask_theta_abs,
-                                                 method, batch, flags)
+                                                 method, batch, flags, fixture_sets, fixture_of)
         o, co = self._outputs(shape, n_orient, masks, debug_orient, design.device, debug_numel,
                               out)
         st = _Stats()
@@ -293,11 +312,11 @@ class Context:
 
     def submit(self, design, fixture=None, domain=None, *, tools, dirs, dir_kind=DIR_F64,
                sharp=SHARP_ALL, lam=0.0, tau=0.5, mask_theta_abs=-1.0, method=METHOD_AUTO,
-               batch=0, flags=0, masks=True):
+               batch=0, flags=0, masks=True, fixture_sets=None, fixture_of=None):
         """Enqueue a request in the serving loop; returns a ticket."""
         r, keep, shape, n_orient = self._request(design, fixture, domain, tools, dirs,
                                                  dir_kind, sharp, lam, tau, mask_theta_abs,
-                                                 method, batch, flags)
+                                                 method, batch, flags, fixture_sets, fixture_of)
         o, co = self._outputs(shape, n_orient, masks, -1, design.device)
         t = C.c_uint64()
         _check(_L().imf_submit(self._ctx, C.byref(r), C.byref(co), C.byref(t)))
@@ -327,7 +346,7 @@ class Context:
             design, fixture, domain, tools, dirs, kw.get("dir_kind", DIR_F64),
             kw.get("sharp", SHARP_ALL), kw.get("lam", 0.0), kw.get("tau", 0.5),
             kw.get("mask_theta_abs", -1.0), kw.get("method", METHOD_AUTO), 0,
-            kw.get("flags", 0))
+            kw.get("flags", 0), kw.get("fixture_sets"), kw.get("fixture_of"))
         o, co = self._outputs(shape, n_orient, masks, -1, design.device)
         b = C.c_int()
         _check(_L().imf_autotune(self._ctx, C.byref(r), C.byref(co), C.byref(b)))

@@ -395,3 +395,35 @@ def rotation_to(d, roll: float = 0.0) -> np.ndarray:
     c, s = np.cos(roll), np.sin(roll)
     u, v = c * e1 + s * e2, -s * e1 + c * e2
     return np.stack([u, v, d], axis=1)   # columns: images of x, y, z
+
+
+def setup_clamps(shape, n_sets: int, seed: int = 7627007, depth: int = 3,
+                 height: int = 10) -> np.ndarray:
+    """One extra fixture per machining setup: a pair of vise jaws gripping the
+    part from opposite sides along x or y (alternating), at a seeded position
+    along the other axis, above the plate.  Returns uint8 [n_sets, *shape]."""
+    rng = _rng(seed)
+    nz, ny, nx = shape
+    out = np.zeros((n_sets,) + tuple(shape), np.uint8)
+    for s in range(n_sets):
+        z0 = int(rng.integers(0, max(nz // 4, 1)))
+        z1 = min(nz, z0 + height)
+        if s % 2 == 0:
+            a = int(rng.integers(0, max(ny - ny // 3, 1)))
+            b = min(ny, a + max(ny // 3, 1))
+            out[s, z0:z1, a:b, :depth] = 1
+            out[s, z0:z1, a:b, nx - depth:] = 1
+        else:
+            a = int(rng.integers(0, max(nx - nx // 3, 1)))
+            b = min(nx, a + max(nx // 3, 1))
+            out[s, z0:z1, :depth, a:b] = 1
+            out[s, z0:z1, ny - depth:, a:b] = 1
+    return out
+
+
+def setup_of_dirs(dirs, n_sets: int) -> np.ndarray:
+    """The setup of each orientation: sectors of the azimuth of its direction
+    (x, y components), n_sets sectors of equal angle."""
+    d = np.asarray(dirs, np.float64).reshape(len(dirs), -1)
+    phi = np.arctan2(d[:, 1], d[:, 0]) % (2 * np.pi)
+    return np.minimum((phi / (2 * np.pi) * n_sets).astype(np.int32), n_sets - 1)
