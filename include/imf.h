@@ -174,6 +174,8 @@ typedef struct {
   long long bound_skipped; /* of those, skipped by the lower bound (exact) */
   int graph;               /* 0 launched kernel by kernel, 1 captured into a graph and
                               launched, 2 a replay of a captured graph */
+  int lattice_runs;        /* orientations whose sharp points are split into runs along a
+                              lattice vector other than a coordinate axis */
 } imf_stats;
 
 /* Bytes of device workspace the request needs (admission control). */

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <numeric>
 #include <cstdarg>
 #include <atomic>
 #include <chrono>
@@ -130,7 +131,9 @@ extern "C" int imf_fft_size(int n) {
 // ---------------------------------------------------------------------------
 struct OrientEntry {
   int ext[IMF_EXT_INTS];
-  int s_axis;
+  int s_axis;       // 0..2: sharp-point runs along that axis; 3: along sv
+  int sv[3];        // lattice vector of the sharp-point runs
+  int maxlen;       // longest sharp-point run
   const imf_run* truns;
   const imf_run* sruns;
   const imf_run* sxruns;
@@ -208,6 +211,8 @@ struct imf_ctx {
   // grids below this many voxels skip the branch and bound: its three short
   // launches per orientation cost more than the blocks they save
   long long bound_min_voxels = 1000000;
+  // sharp-point runs along lattice vectors where they are fewer (3D)
+  bool lattice_runs = true;
 };
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -277,6 +282,7 @@ extern "C" imf_status imf_create(int device, size_t hbm_budget_bytes, imf_ctx** 
   if (const char* e = std::getenv("IMF_MINFILTER_SHAPE")) c->mf_shape = std::atoi(e) & 3;
   c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
   if (const char* e = std::getenv("IMF_BOUND_MIN_VOXELS")) c->bound_min_voxels = std::atoll(e);
+  if (const char* e = std::getenv("IMF_AXIS_RUNS")) c->lattice_runs = std::atoi(e) == 0;
   if (const char* e = std::getenv("IMF_MINFILTER_WG_PER_CU"))
     c->mf_wg_per_cu = std::max(1, std::min(16, std::atoi(e)));
   if (hipStreamCreateWithFlags(&c->internal, hipStreamNonBlocking) != hipSuccess) {
@@ -524,6 +530,85 @@ static void raster_desc_for(const imf_ctx* c, int tid, const Orient& o, int nd, 
   d.s_axis = best;
 }
 
+// Sharp-point runs along a lattice vector.  The minimum over S costs two
+// lookups per run, and S splits into fewer runs along a short lattice vector
+// near the tool axis than along a coordinate axis (a line meets a convex set
+// in one run).  Among the primitive vectors with components in [-2, 2] (one of
+// each +-v pair, the coordinate axes included), take the one with the fewest
+// runs; keep the axis runs `ar` (along `ax`) unless another vector saves at
+// least 5% of them with no run longer than 127 points (six levels).  Exact: the
+// runs cover S whatever the vector.  Returns false to keep the axis runs.
+static bool lattice_runs(const imf_run* ar, int n, int ax, const int* ext, int sv[3],
+                         int* maxlen, std::vector<imf_run>& out) {
+  int lo[3], dim[3];
+  for (int a = 0; a < 3; a++) {
+    lo[a] = ext[6 + a] - 2;
+    dim[a] = ext[9 + a] - ext[6 + a] + 5;
+  }
+  const long long vol = (long long)dim[0] * dim[1] * dim[2];
+  if (n <= 0 || vol > (1LL << 26)) return false;
+  std::vector<uint8_t> B((size_t)vol, 0);
+  auto at = [&](int x, int y, int z) {
+    return ((long long)(z - lo[2]) * dim[1] + (y - lo[1])) * dim[0] + (x - lo[0]);
+  };
+  std::vector<int> pts;
+  for (int r = 0; r < n; r++)
+    for (int j = 0; j < ar[r].len; j++) {
+      int k[3] = {ar[r].x, ar[r].y, ar[r].z};
+      k[ax] += j;
+      B[(size_t)at(k[0], k[1], k[2])] = 1;
+      pts.push_back(k[0]);
+      pts.push_back(k[1]);
+      pts.push_back(k[2]);
+    }
+  const size_t np = pts.size() / 3;
+  int best = n, bv[3] = {0, 0, 0};
+  for (int vz = -2; vz <= 2; vz++)
+    for (int vy = -2; vy <= 2; vy++)
+      for (int vx = -2; vx <= 2; vx++) {
+        const int v[3] = {vx, vy, vz};
+        const int f = vx ? vx : (vy ? vy : vz);
+        if (f <= 0) continue;  // zero, or the negative of a listed vector
+        int gd = 0;
+        for (int a = 0; a < 3; a++) gd = std::gcd(gd, std::abs(v[a]));
+        if (gd != 1) continue;
+        if (std::abs(v[0]) + std::abs(v[1]) + std::abs(v[2]) == 1 && v[ax] != 0) continue;
+        int cnt = 0;
+        for (size_t i = 0; i < np && cnt < best; i++)
+          cnt += !B[(size_t)at(pts[3 * i] - vx, pts[3 * i + 1] - vy, pts[3 * i + 2] - vz)];
+        if (cnt < best && (double)cnt < 0.95 * n) {
+          best = cnt;
+          bv[0] = vx;
+          bv[1] = vy;
+          bv[2] = vz;
+        }
+      }
+  if (!bv[0] && !bv[1] && !bv[2]) return false;
+  auto in = [&](int x, int y, int z) {
+    return x >= lo[0] && x < lo[0] + dim[0] && y >= lo[1] && y < lo[1] + dim[1] &&
+           z >= lo[2] && z < lo[2] + dim[2] && B[(size_t)at(x, y, z)];
+  };
+  out.clear();
+  int ml = 0;
+  for (size_t i = 0; i < np; i++) {
+    const int x = pts[3 * i], y = pts[3 * i + 1], z = pts[3 * i + 2];
+    if (in(x - bv[0], y - bv[1], z - bv[2])) continue;
+    int len = 1;
+    while (in(x + len * bv[0], y + len * bv[1], z + len * bv[2])) len++;
+    if (len > 127) return false;
+    ml = std::max(ml, len);
+    out.push_back(imf_run{x, y, z, len});
+  }
+  // runs in (z, y, x) order of their first point: neighbouring runs read
+  // neighbouring cache lines in the minimum pass
+  std::sort(out.begin(), out.end(), [](const imf_run& p, const imf_run& q) {
+    return p.z != q.z ? p.z < q.z : (p.y != q.y ? p.y < q.y : p.x < q.x);
+  });
+  for (int a = 0; a < 3; a++) sv[a] = bv[a];
+  *maxlen = ml;
+  return true;
+}
+
 static int rows_of(const imf_raster_desc& d) {
   const int u = (d.s_axis + 1) % 3, w = (d.s_axis + 2) % 3;
   return std::max(d.dim[1] * d.dim[2], d.dim[u] * d.dim[w]);
@@ -636,16 +721,54 @@ static imf_status ensure_rasters(imf_ctx* c, const imf_request* r, const std::ve
   RCHK(hipMemcpyAsync(base, hb.data(), sizeof(long long) * hb.size(), hipMemcpyHostToDevice, s));
   RCHK(imf_launch_compact(dd, n, max_rows, slots, cnt, base, pool, s));
   RCHK(hipStreamSynchronize(s));
-#undef RCHK
+  // sharp-point runs along lattice vectors (3D): chosen on the host from the
+  // axis runs, uploaded as one more pool
+  std::vector<OrientEntry> ents(n);
   for (int i = 0; i < n; i++) {
-    OrientEntry e;
+    OrientEntry& e = ents[i];
     std::memcpy(e.ext, &hext[(size_t)i * IMF_EXT_INTS], sizeof e.ext);
     e.s_axis = hd[i].s_axis;
+    for (int a = 0; a < 3; a++) e.sv[a] = a == e.s_axis;
+    e.maxlen = e.ext[9 + e.s_axis] - e.ext[6 + e.s_axis] + 1;
     e.truns = pool + hb[(size_t)i * 3 + 0];
     e.sruns = pool + hb[(size_t)i * 3 + 1];
     e.sxruns = pool + hb[(size_t)i * 3 + 2];
-    c->rasters[miss[i]->key] = e;
   }
+  if (r->ndim == 3 && c->lattice_runs) {
+    std::vector<imf_run> hpool((size_t)std::max(total, 1LL));
+    RCHK(hipMemcpy(hpool.data(), pool, sizeof(imf_run) * hpool.size(), hipMemcpyDeviceToHost));
+    std::vector<imf_run> vall, one;
+    std::vector<long long> voff(n, -1);
+    for (int i = 0; i < n; i++) {
+      OrientEntry& e = ents[i];
+      int sv[3], ml = 0;
+      if (!lattice_runs(hpool.data() + hb[(size_t)i * 3 + 1], e.ext[16], e.s_axis, e.ext, sv, &ml,
+                        one))
+        continue;
+      voff[i] = (long long)vall.size();
+      vall.insert(vall.end(), one.begin(), one.end());
+      e.s_axis = std::abs(sv[0]) + std::abs(sv[1]) + std::abs(sv[2]) == 1
+                     ? (sv[0] ? 0 : (sv[1] ? 1 : 2))
+                     : 3;
+      for (int a = 0; a < 3; a++) e.sv[a] = e.s_axis < 3 ? (a == e.s_axis) : sv[a];
+      e.ext[16] = (int)one.size();
+      e.maxlen = ml;
+    }
+    if (!vall.empty()) {
+      imf_run* vpool = nullptr;
+      if (hipMalloc(&vpool, sizeof(imf_run) * vall.size()) != hipSuccess) {
+        cleanup();
+        return fail(IMF_ENOMEM, "raster run pool");
+      }
+      c->raster_pools.push_back(vpool);
+      c->raster_bytes += sizeof(imf_run) * vall.size();
+      RCHK(hipMemcpy(vpool, vall.data(), sizeof(imf_run) * vall.size(), hipMemcpyHostToDevice));
+      for (int i = 0; i < n; i++)
+        if (voff[i] >= 0) ents[i].sruns = vpool + voff[i];
+    }
+  }
+#undef RCHK
+  for (int i = 0; i < n; i++) c->rasters[miss[i]->key] = ents[i];
   cleanup();
   return IMF_OK;
 }
@@ -779,12 +902,13 @@ static imf_status make_plan(imf_ctx* c, const imf_request* r, const imf_outputs*
     }
     p.max_vol = std::max(p.max_vol, vol);
     d.s_axis = e.s_axis;
+    for (int a = 0; a < 3; a++) d.sv[a] = e.sv[a];
     d.n_sruns = e.ext[16];
     d.n_truns = e.ext[15];
     d.sruns = e.sruns;
     d.truns = e.truns;
     d.spec = nullptr;
-    const int sdim = e.ext[9 + e.s_axis] - e.ext[6 + e.s_axis] + 1;
+    const int sdim = e.maxlen;  // longest run of S
     max_sdim = std::max(max_sdim, sdim);
     d.nlvl = 0;
     while ((2 << d.nlvl) <= sdim) d.nlvl++;
@@ -1373,11 +1497,16 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
     ma.max_m = 1;
     ma.max_lines = 1;
     ma.stream_waves = 0;
+    ma.vstream_waves = 0;
     ma.x_rows = 0;
     ma.lds_levels = 0;
     for (int q = q0; q < q0 + nq; q++) {
       const imf_orient_desc& d = p.desc[q];
       const int ax = d.s_axis;
+      if (ax == 3) {  // runs along a lattice vector (at most six levels)
+        ma.vstream_waves = std::max(ma.vstream_waves, imf_vlines_of(d.sv, d.box_dim).waves);
+        continue;
+      }
       ma.max_m = std::max(ma.max_m, d.box_dim[ax]);
       const long long lines =
           ax == 0 ? ((long long)d.box_dim[1] * d.box_dim[2] + 3) / 4
@@ -1586,6 +1715,7 @@ static imf_status compute_finish(Pending& pd, imf_stats* st) {
     st->cache_hits = pd.hits;
     st->cache_misses = pd.misses;
     st->graph = pd.graph;
+    for (int q = 0; q < p.nO; q++) st->lattice_runs += p.desc[q].s_axis == 3;
   } else {
     pd.tm.release();
   }

@@ -7,8 +7,9 @@
 #define IMF_MAX_RUNS_PER_ROW 4
 #define IMF_WG 256
 
-// A run of voxels of an oriented tool raster: offsets start + j * e_axis,
-// 0 <= j < len.  Offsets are relative to the cutter tip (the origin).
+// A run of voxels of an oriented tool raster: offsets start + j * e (e a
+// coordinate axis, or for the sharp-point runs the lattice vector sv of the
+// orientation), 0 <= j < len.  Offsets are relative to the cutter tip.
 struct imf_run {
   int x, y, z, len;
 };
@@ -39,16 +40,50 @@ struct imf_raster_desc {
 // along s_axis, [17] number of x-runs of S.
 #define IMF_EXT_INTS 20
 
+// Integer floor and ceiling of p / q for q > 0.
+__host__ __device__ inline int imf_floor_div(int p, int q) {
+  return p >= 0 ? p / q : -((-p + q - 1) / q);
+}
+__host__ __device__ inline int imf_ceil_div(int p, int q) { return -imf_floor_div(-p, q); }
+
+// Lattice lines of a query box along v (v[1] or v[2] nonzero), as the
+// streamed level pass walks them.  Seed axis a is z if v[2] != 0, else y;
+// every lattice line meets the window of |v[a]| planes at the entry side of
+// axis a (a in [0, |v[a]|) if v[a] > 0, else the last |v[a]| planes) in
+// exactly one point, its seed (x, b, a), and from there steps s = 0, 1, ...
+// of +v.  Seeds of lines that can meet the box: b in [lob, lob + nb0), x in
+// chunks of 64 from lox.  Waves: (x chunk, b, residue of a).
+struct imf_vlines {
+  int a, b, ua, S;  // seed axis, the other of y / z, |v[a]|, steps covering axis a
+  int lob, nb0, lox, nxc;
+  long long waves;
+};
+__host__ __device__ inline imf_vlines imf_vlines_of(const int v[3], const int dim[3]) {
+  imf_vlines L;
+  L.a = v[2] != 0 ? 2 : 1;
+  L.b = L.a == 2 ? 1 : 2;
+  L.ua = v[L.a] < 0 ? -v[L.a] : v[L.a];
+  L.S = imf_ceil_div(dim[L.a], L.ua);
+  const int vb = v[L.b], vx = v[0];
+  L.lob = vb > 0 ? -vb * (L.S - 1) : 0;
+  L.nb0 = dim[L.b] + (vb < 0 ? -vb : vb) * (L.S - 1);
+  L.lox = vx > 0 ? -vx * (L.S - 1) : 0;
+  L.nxc = imf_ceil_div(dim[0] + (vx < 0 ? -vx : vx) * (L.S - 1), 64);
+  L.waves = (long long)L.nxc * L.nb0 * L.ua;
+  return L;
+}
+
 // Per-orientation data used by the correlation, min filter and masks.
 struct imf_orient_desc {
   int box_lo[3];       // first translation of the query box (t = x - k)
   int box_dim[3];      // query box size M per axis
-  int s_axis;          // axis of the sharp-point runs
+  int s_axis;          // axis of the sharp-point runs (0, 1, 2), or 3: along sv
+  int sv[3];           // lattice vector of the sharp-point runs (e_axis for an axis)
   int n_sruns;         // number of sharp-point runs
   int n_truns;         // number of tool x-runs
   int tlo[3], tdim[3]; // bounding box of the tool raster (offsets)
   int nlvl;            // sparse-table levels this orientation's runs need
-  const imf_run* sruns;  // sharp-point runs along s_axis (x-runs for the sweep route)
+  const imf_run* sruns;  // sharp-point runs along sv (x-runs for the sweep route)
   const imf_run* truns;  // x-runs of the tool T, row order (z, y)
   float2* spec;          // this orientation's tool spectrum [py][px/2+1][pz]
 };
@@ -158,6 +193,7 @@ struct imf_min_args {
   int max_m;                // largest box extent along any run axis (LDS of the level pass)
   long long max_lines;      // workgroups of the level pass (LDS form: x lines)
   long long stream_waves;   // waves of the streamed level pass (y and z lines)
+  long long vstream_waves;  // waves of the level pass along lattice vectors
   long long x_rows;         // rows of the shuffle level pass (x lines)
   int lds_levels;           // some orientation needs more levels than the register forms
   int nx, ny, nz;

@@ -184,6 +184,7 @@ __global__ void __launch_bounds__(IMF_WG) k_levels(const imf_orient_desc* __rest
   const int q = blockIdx.z;
   const imf_orient_desc& d = desc[q];
   const int ax = d.s_axis;
+  if (ax > 2) return;  // runs along a lattice vector: k_levels_vstream
   const int mx = d.box_dim[0], my = d.box_dim[1], mz = d.box_dim[2];
   const int m = d.box_dim[ax];
   const long long sa = ax == 0 ? 1 : (ax == 1 ? (long long)mx : (long long)mx * my);
@@ -300,7 +301,7 @@ __global__ void __launch_bounds__(IMF_WG) k_levels_stream(const imf_orient_desc*
   const imf_orient_desc& d = desc[q];
   const int ax = d.s_axis;
   const int nl_q = d.nlvl < nlvl ? d.nlvl : nlvl;
-  if (ax == 0 || nl_q < 1 || nl_q > LS_MAXL) return;  // left to k_levels
+  if (ax == 0 || ax > 2 || nl_q < 1 || nl_q > LS_MAXL) return;  // left to the other forms
   const int mx = d.box_dim[0], my = d.box_dim[1], mz = d.box_dim[2];
   const int nxw = (mx + 63) / 64;
   const long long w = (long long)blockIdx.x * (IMF_WG / 64) + (threadIdx.x >> 6);
@@ -360,6 +361,115 @@ __global__ void __launch_bounds__(IMF_WG) k_levels_x(const imf_orient_desc* __re
   }
 }
 
+// Levels along the lines of a lattice vector v (runs of S along v, Sec. 2.1.3
+// computes the minimum over S, any exact cover of S by runs gives it): level
+// s at t is min_{j < 2^s} g(t + j v), +inf outside the box.  One wave per 64
+// seeds of consecutive x (imf_vlines), each lane walking its line from the far
+// end with the register delay lines of levels_stream_line; steps past a
+// lane's part of the box load +inf and store nothing.  Loads and stores at
+// one step are 64 consecutive x: coalesced.
+__device__ __forceinline__ void vline_range(int c0, int dv, int m, int S, int& lo, int& hi) {
+  // steps s in [0, S) with 0 <= c0 + s dv < m
+  if (dv == 0) {
+    lo = 0;
+    hi = (c0 >= 0 && c0 < m) ? S : 0;
+  } else if (dv > 0) {
+    lo = max(0, imf_ceil_div(-c0, dv));
+    hi = min(S, imf_floor_div(m - 1 - c0, dv) + 1);
+  } else {
+    lo = max(0, imf_floor_div(c0 - m, -dv) + 1);
+    hi = min(S, imf_floor_div(c0, -dv) + 1);
+  }
+}
+
+template <int NL>
+__device__ __forceinline__ void levels_vstream_line(const float* __restrict__ src,
+                                                    float* __restrict__ dst, long long g_stride,
+                                                    long long idx0, long long step, int wlo,
+                                                    int whi, int llo, int lhi) {
+  constexpr int U = 1 << (NL - 1);
+  float D[(1 << NL) - 1];
+#pragma unroll
+  for (int k = 0; k < (1 << NL) - 1; k++) D[k] = INFINITY;
+  const int nb = (whi - wlo + U - 1) / U;
+  for (int b = nb - 1; b >= 0; b--) {
+    float gv[U];
+#pragma unroll
+    for (int j = 0; j < U; j++) {
+      const int i = wlo + b * U + (U - 1 - j);
+      gv[j] = (i >= llo && i < lhi) ? src[idx0 + (long long)i * step] : INFINITY;
+    }
+#pragma unroll
+    for (int j = 0; j < U; j++) {
+      const int i = wlo + b * U + (U - 1 - j);
+      const bool ok = i >= llo && i < lhi;
+      float v = gv[j];
+#pragma unroll
+      for (int s = 1; s <= NL; s++) {
+        const int slot = ((1 << (s - 1)) - 1) + (j & ((1 << (s - 1)) - 1));
+        const float prev = D[slot];
+        D[slot] = v;
+        v = fminf(v, prev);
+        if (ok) dst[(long long)(s - 1) * g_stride + idx0 + (long long)i * step] = v;
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(IMF_WG) k_levels_vstream(const imf_orient_desc* __restrict__ desc,
+                                                           const float* __restrict__ g,
+                                                           long long g_stride,
+                                                           float* __restrict__ lvl,
+                                                           long long lvl_stride, int nlvl) {
+  const int q = blockIdx.y;
+  const imf_orient_desc& d = desc[q];
+  const int nl_q = d.nlvl < nlvl ? d.nlvl : nlvl;
+  if (d.s_axis != 3 || nl_q < 1 || nl_q > LS_MAXL) return;
+  const int v[3] = {d.sv[0], d.sv[1], d.sv[2]};
+  const int dim[3] = {d.box_dim[0], d.box_dim[1], d.box_dim[2]};
+  const imf_vlines L = imf_vlines_of(v, dim);
+  const long long w = (long long)blockIdx.x * (IMF_WG / 64) + (threadIdx.x >> 6);
+  if (w >= L.waves) return;  // whole waves
+  const int lane = threadIdx.x & 63;
+  const int xc = (int)(w % L.nxc);
+  const long long rest = w / L.nxc;
+  const int b0 = L.lob + (int)(rest % L.nb0);
+  const int r = (int)(rest / L.nb0);
+  const int a0 = v[L.a] > 0 ? r : dim[L.a] - 1 - r;
+  const int xs = L.lox + xc * 64 + lane;
+  int lo, hi, l2, h2;
+  vline_range(xs, v[0], dim[0], L.S, lo, hi);
+  vline_range(a0, v[L.a], dim[L.a], L.S, l2, h2);
+  lo = max(lo, l2);
+  hi = min(hi, h2);
+  vline_range(b0, v[L.b], dim[L.b], L.S, l2, h2);
+  lo = max(lo, l2);
+  hi = min(hi, h2);
+  // the wave's steps: the union of its lanes' (contiguous) ranges
+  int wlo = lo < hi ? lo : 0x7fffffff, whi = lo < hi ? hi : -1;
+  for (int o = 32; o > 0; o >>= 1) {
+    wlo = min(wlo, __shfl_xor(wlo, o));
+    whi = max(whi, __shfl_xor(whi, o));
+  }
+  if (wlo >= whi) return;  // uniform over the wave
+  int c[3];
+  c[0] = xs;
+  c[L.a] = a0;
+  c[L.b] = b0;
+  const long long idx0 = c[0] + (long long)dim[0] * (c[1] + (long long)dim[1] * c[2]);
+  const long long step = v[0] + (long long)dim[0] * (v[1] + (long long)dim[1] * v[2]);
+  const float* src = g + q * g_stride;
+  float* dst = lvl + q * lvl_stride;
+  switch (nl_q) {
+    case 1: levels_vstream_line<1>(src, dst, g_stride, idx0, step, wlo, whi, lo, hi); break;
+    case 2: levels_vstream_line<2>(src, dst, g_stride, idx0, step, wlo, whi, lo, hi); break;
+    case 3: levels_vstream_line<3>(src, dst, g_stride, idx0, step, wlo, whi, lo, hi); break;
+    case 4: levels_vstream_line<4>(src, dst, g_stride, idx0, step, wlo, whi, lo, hi); break;
+    case 5: levels_vstream_line<5>(src, dst, g_stride, idx0, step, wlo, whi, lo, hi); break;
+    default: levels_vstream_line<6>(src, dst, g_stride, idx0, step, wlo, whi, lo, hi); break;
+  }
+}
+
 __device__ __forceinline__ int ilog2(int v) { return 31 - __clz(v); }
 
 void imf_block_dims(int shape, int& wx, int& wy, int& wz) {
@@ -409,12 +519,10 @@ __global__ void __launch_bounds__(IMF_WG) k_footprint(const imf_orient_desc* __r
   for (int i = threadIdx.x; i < FP_BITS / 32; i += IMF_WG) bm[i] = 0;
   if (threadIdx.x == 0) cnt = 0;
   __syncthreads();
-  const int ax = d.s_axis;
   for (int r = threadIdx.x; r < d.n_sruns; r += IMF_WG) {
     const imf_run u = d.sruns[r];
     for (int j = 0; j < u.len; j++) {
-      int k[3] = {u.x, u.y, u.z};
-      k[ax] += j;
+      const int k[3] = {u.x + j * d.sv[0], u.y + j * d.sv[1], u.z + j * d.sv[2]};
       int lo[3], hi[3];
       for (int a = 0; a < 3; a++) {
         const int e = kmax[a] - k[a];
@@ -685,9 +793,8 @@ __device__ __forceinline__ void mf_block(const imf_min_args& a, const imf_orient
                                          const int4* rr, int qi, int bx, int by, int bz,
                                          long long blk) {
   const int nr = d.n_sruns;
-  const int ax = d.s_axis;
   const long long sx = 1, sy = d.box_dim[0], sz = (long long)d.box_dim[0] * d.box_dim[1];
-  const long long sa = ax == 0 ? sx : (ax == 1 ? sy : sz);
+  const long long sa = d.sv[0] * sx + d.sv[1] * sy + d.sv[2] * sz;  // box offset of sv
   const int lane = threadIdx.x & 63;
   const int lx = lane % WX, ly = (lane / WX) % WY, lz = lane / (WX * WY);
   const int x = bx * WX + lx, y = by * WY + ly, z = bz * WZ + lz;
@@ -760,9 +867,8 @@ __device__ __forceinline__ void mf_block(const imf_min_args& a, const imf_orient
 // y = sparse-table level, z = offset of the second (overlapping) window
 __device__ __forceinline__ void mf_stage_runs(const imf_orient_desc& d, int4* rr) {
   const int nr = d.n_sruns;
-  const int ax = d.s_axis;
   const long long sx = 1, sy = d.box_dim[0], sz = (long long)d.box_dim[0] * d.box_dim[1];
-  const long long sa = ax == 0 ? sx : (ax == 1 ? sy : sz);
+  const long long sa = d.sv[0] * sx + d.sv[1] * sy + d.sv[2] * sz;  // box offset of sv
   for (int r = threadIdx.x; r < nr && r < MF_LDS_RUNS; r += IMF_WG) {
     const imf_run u = d.sruns[r];
     const int sl = ilog2(u.len);
@@ -875,6 +981,13 @@ hipError_t imf_launch_minfilter(const imf_min_args& a, hipStream_t s, int stage,
     if (a.x_rows > 0) {
       hipLaunchKernelGGL(k_levels_x,
                          dim3((unsigned)((a.x_rows + IMF_WG / 64 - 1) / (IMF_WG / 64)), a.nq),
+                         dim3(IMF_WG), 0, s, a.desc, a.g, a.g_stride, a.lvl, a.lvl_stride, a.nlvl);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (a.vstream_waves > 0) {
+      hipLaunchKernelGGL(k_levels_vstream,
+                         dim3((unsigned)((a.vstream_waves + IMF_WG / 64 - 1) / (IMF_WG / 64)),
+                              a.nq),
                          dim3(IMF_WG), 0, s, a.desc, a.g, a.g_stride, a.lvl, a.lvl_stride, a.nlvl);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }

@@ -385,3 +385,54 @@ def test_voxel_tool_rejects_bad_rotations(ctx):
         ctx.compute(d, tools=vt, dirs=np.diag([1.0, 1.0, -1.0])[None], dir_kind=imf.DIR_ROTATION)
     with pytest.raises(imf.IMFError):
         ctx.compute(d, tools=vt, dirs=np.array([[0.0, 0.0, 1.0]]), dir_kind=imf.DIR_F64)
+
+
+# ---------------------------------------------------------------------------
+# sharp-point runs along lattice vectors against runs along a coordinate axis
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mode", ["binary_lattice", "density_two_phase"])
+def test_lattice_vector_runs_equal_axis_runs(mode, monkeypatch):
+    """The minimum over S is the same whichever exact cover of S by runs is
+    used: results with runs along lattice vectors (chosen per orientation)
+    equal those with runs along a coordinate axis, bit for bit, with the
+    bound on, and equal the oracle."""
+    import paper_2002_07627_amd as imf
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    if mode == "binary_lattice":
+        d = random_boxes((36, 40, 44), 16, 51, lo=4, hi=14)
+        fx = W.fixture_plate(d.shape, 3)
+        tl = W.tool(W.TOOL_BALL, 2, 9, 4, 6)
+        dirs = W.lattice26()
+        kw = dict(tools=tl, dirs=dirs, dir_kind=imf.DIR_LATTICE, method=imf.METHOD_FFT)
+        req = oracle.Request(d, fx, tools=tl, dirs=dirs, dir_kind=1)
+    else:
+        d = W.design_density(44, seed=52)
+        fx = W.fixture_plate(d.shape, 3)
+        tl = W.tool(W.TOOL_BALL, 2, 10, 4, 6)
+        dirs = W.fib_hemisphere(24)
+        kw = dict(tools=tl, dirs=dirs, lam=0.02, method=imf.METHOD_FFT)
+        req = oracle.Request(d, fx, tools=tl, dirs=dirs, dir_kind=0, lam=0.02)
+    monkeypatch.setenv("IMF_BOUND_MIN_VOXELS", "0")
+    outs = {}
+    for axis_only in ("0", "1"):
+        monkeypatch.setenv("IMF_AXIS_RUNS", axis_only)
+        c = imf.Context(0)
+        try:
+            o, st = c.compute(dev(d), dev(fx), **kw)
+            outs[axis_only] = ({k: v.clone() for k, v in o.items()}, st)
+        finally:
+            c.close()
+    (a, sa), (b, sb) = outs["0"], outs["1"]
+    assert sa.lattice_runs > 0 and sb.lattice_runs == 0
+    assert sa.bound_blocks > 0
+    for k in ("imf", "imf_norm", "secluded", "masks"):
+        assert torch.equal(a[k], b[k]), k
+    ref = oracle.imf(req)
+    if mode == "binary_lattice":
+        check_binary(a, ref)
+    else:
+        f = host(a["imf"]).astype(np.float64)
+        tol = 1e-4 * np.maximum(np.abs(ref["imf"]), 0.02 * ref["F_max"])
+        assert (np.abs(f - ref["imf"]) <= tol).all()
