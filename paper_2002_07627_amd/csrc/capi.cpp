@@ -213,6 +213,8 @@ struct imf_ctx {
   long long bound_min_voxels = 1000000;
   // sharp-point runs along lattice vectors where they are fewer (3D)
   bool lattice_runs = true;
+  // process orientations in farthest-point order of their tool axes
+  bool spread_order = true;
 };
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -283,6 +285,7 @@ extern "C" imf_status imf_create(int device, size_t hbm_budget_bytes, imf_ctx** 
   c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
   if (const char* e = std::getenv("IMF_BOUND_MIN_VOXELS")) c->bound_min_voxels = std::atoll(e);
   if (const char* e = std::getenv("IMF_AXIS_RUNS")) c->lattice_runs = std::atoi(e) == 0;
+  if (const char* e = std::getenv("IMF_GIVEN_ORDER")) c->spread_order = std::atoi(e) == 0;
   if (const char* e = std::getenv("IMF_MINFILTER_WG_PER_CU"))
     c->mf_wg_per_cu = std::max(1, std::min(16, std::atoi(e)));
   if (hipStreamCreateWithFlags(&c->internal, hipStreamNonBlocking) != hipSuccess) {
@@ -374,6 +377,7 @@ extern "C" imf_status imf_tool_register_voxel(imf_ctx* c, int nx, int ny, int nz
 // orientations of a request
 // ---------------------------------------------------------------------------
 struct Orient {
+  int index;  // position in the request (outputs are indexed by it)
   int tool;
   double d[3];
   long long v[3];
@@ -453,8 +457,41 @@ static imf_status enumerate(imf_ctx* c, const imf_request* r, std::vector<Orient
       else
         snprintf(buf, sizeof buf, "%d|%d|F|%d|%a,%a,%a", tid, nd, r->sharp, o.d[0], o.d[1], o.d[2]);
       o.key = buf;
+      o.index = (int)out.size();
       out.push_back(o);
     }
+  }
+  if (c->spread_order && out.size() > 2) {
+    // processing order: farthest point first over the tool axes (from the
+    // request's first orientation), each fixture set's orientations kept
+    // together.  f is a minimum, so the order changes no result; spreading the
+    // directions early lowers f sooner, and the bound then skips more blocks.
+    const size_t n = out.size();
+    std::vector<int> ord;
+    std::vector<char> taken(n, 0);
+    std::vector<double> far(n, 1e300);
+    ord.push_back(0);
+    taken[0] = 1;
+    while (ord.size() < n) {
+      const Orient& l = out[ord.back()];
+      size_t best = n;
+      for (size_t i = 0; i < n; i++) {
+        if (taken[i]) continue;
+        const double dot = l.d[0] * out[i].d[0] + l.d[1] * out[i].d[1] + l.d[2] * out[i].d[2];
+        far[i] = std::min(far[i], 1.0 - dot);
+        if (best == n || far[i] > far[best]) best = i;
+      }
+      taken[best] = 1;
+      ord.push_back((int)best);
+    }
+    if (r->n_fixture_sets > 0)
+      std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+        return r->fixture_of[a] < r->fixture_of[b];
+      });
+    std::vector<Orient> sorted;
+    sorted.reserve(n);
+    for (int i : ord) sorted.push_back(out[i]);
+    out.swap(sorted);
   }
   return IMF_OK;
 }
@@ -803,6 +840,7 @@ struct Plan {
   // (0 without fixture sets); at most B wide, split wherever the set changes
   std::vector<int> bstart, bset;
   int nsets = 0;  // fixture sets (0: the common fixture only)
+  int debug_pos = -1;  // processing position of the orientation whose overlaps are copied
   double theta;
   double band;
   // workspace layout (bytes)
@@ -908,6 +946,8 @@ static imf_status make_plan(imf_ctx* c, const imf_request* r, const imf_outputs*
     d.sruns = e.sruns;
     d.truns = e.truns;
     d.spec = nullptr;
+    d.out_q = os[q].index;
+    if (out && out->debug_overlap && os[q].index == out->debug_orient) p.debug_pos = q;
     const int sdim = e.maxlen;  // longest run of S
     max_sdim = std::max(max_sdim, sdim);
     d.nlvl = 0;
@@ -943,9 +983,9 @@ static imf_status make_plan(imf_ctx* c, const imf_request* r, const imf_outputs*
   p.bstart.assign(1, 0);
   p.bset.clear();
   for (int q = 0; q < p.nO;) {
-    const int set = p.nsets ? r->fixture_of[q] : 0;
+    const int set = p.nsets ? r->fixture_of[os[q].index] : 0;
     int e = q + 1;
-    while (e < p.nO && e - q < p.B && (!p.nsets || r->fixture_of[e] == set)) e++;
+    while (e < p.nO && e - q < p.B && (!p.nsets || r->fixture_of[os[e].index] == set)) e++;
     p.bset.push_back(set);
     p.bstart.push_back(e);
     q = e;
@@ -1479,10 +1519,10 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
                                p.max_vol, (int)p.max_vol, s));
       tm.mark(8);
     }
-    if (out->debug_overlap && out->debug_orient >= q0 && out->debug_orient < q0 + nq) {
-      const imf_orient_desc& d = p.desc[out->debug_orient];
+    if (out->debug_overlap && p.debug_pos >= q0 && p.debug_pos < q0 + nq) {
+      const imf_orient_desc& d = p.desc[p.debug_pos];
       const long long vol = (long long)d.box_dim[0] * d.box_dim[1] * d.box_dim[2];
-      HIPCHK(hipMemcpyAsync(out->debug_overlap, g + (long long)(out->debug_orient - q0) * p.max_vol,
+      HIPCHK(hipMemcpyAsync(out->debug_overlap, g + (long long)(p.debug_pos - q0) * p.max_vol,
                             sizeof(float) * vol, hipMemcpyDeviceToDevice, s));
       tm.mark(14);
     }
@@ -1643,7 +1683,7 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
     pd.graph = 1;
   }
   if (out->debug_overlap) {
-    const imf_orient_desc& d = p.desc[out->debug_orient];
+    const imf_orient_desc& d = p.desc[p.debug_pos];
     for (int a = 0; a < 3; a++) {
       pd.out->debug_box[a] = d.box_lo[a];
       pd.out->debug_box[3 + a] = d.box_dim[a];

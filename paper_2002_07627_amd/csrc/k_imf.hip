@@ -843,7 +843,7 @@ __device__ __forceinline__ void mf_block(const imf_min_args& a, const imf_orient
     fnew = fminf(fo, gam);
     if (gam < fo) a.f[vi] = gam;
     if (a.gamma_stack)
-      a.gamma_stack[(long long)(a.gamma_q0 + qi) * a.nx * a.ny * a.nz + vi] = gam;
+      a.gamma_stack[(long long)d.out_q * a.nx * a.ny * a.nz + vi] = gam;
   }
   if (a.bnb) {
     fnew = wave_max_f(fnew);
@@ -855,7 +855,7 @@ __device__ __forceinline__ void mf_block(const imf_min_args& a, const imf_orient
     if (lx == 0 && y < a.ny && z < a.nz) {
       const int words = (a.nx + 63) >> 6;
       const int row = ly + WY * lz;
-      uint64_t* row_words = a.masks + ((long long)(a.mask_q0 + qi) * a.nz + z) * a.ny * words +
+      uint64_t* row_words = a.masks + ((long long)d.out_q * a.nz + z) * a.ny * words +
                             (long long)y * words;
       mf_store_chunk<WX>(row_words, bx,
                          WX == 64 ? bits : (bits >> (row * WX)) & ((1ull << WX) - 1));
@@ -1104,7 +1104,7 @@ __global__ void __launch_bounds__(IMF_WG) k_sweep(imf_sweep_args a) {
     const int x = w * 64 + b;
     if (x < a.nx && a.omega0[vrow + x]) om |= 1ull << b;
   }
-  a.masks[((long long)(a.mask_q0 + q) * a.nz + z) * a.ny * words + (long long)y * words + w] =
+  a.masks[((long long)d.out_q * a.nz + z) * a.ny * words + (long long)y * words + w] =
       acc & om;
 }
 

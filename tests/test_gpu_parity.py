@@ -436,3 +436,44 @@ def test_lattice_vector_runs_equal_axis_runs(mode, monkeypatch):
         f = host(a["imf"]).astype(np.float64)
         tol = 1e-4 * np.maximum(np.abs(ref["imf"]), 0.02 * ref["F_max"])
         assert (np.abs(f - ref["imf"]) <= tol).all()
+
+
+def test_processing_order_changes_no_result(monkeypatch):
+    """Orientations are processed in farthest-point order of their tool axes;
+    every output (f, fbar, Gamma, per-orientation masks in the caller's order,
+    the overlaps of a chosen orientation) equals processing them in the given
+    order, bit for bit: two tools, two-phase masks, the bound on."""
+    import paper_2002_07627_amd as imf
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    d = W.design_density(40, seed=53)
+    fx = W.fixture_plate(d.shape, 3)
+    t1, t2 = W.tool(W.TOOL_BALL, 2, 9, 4, 6), W.tool(W.TOOL_FLAT, 1.5, 7, 3, 5)
+    d1, d2 = W.fib_hemisphere(14), W.fib_hemisphere(9)
+    req = oracle.Request(d, fx, tools=[t1, t2], dirs=[d1, d2], dir_kind=0, lam=0.02)
+    q = 17
+    info = oracle.orient_info(req, q)
+    box = [n + info["kmax"][a] - info["kmin"][a] for a, n in enumerate((40, 40, 40))]
+    monkeypatch.setenv("IMF_BOUND_MIN_VOXELS", "0")
+    outs = {}
+    for given in ("0", "1"):
+        monkeypatch.setenv("IMF_GIVEN_ORDER", given)
+        c = imf.Context(0)
+        try:
+            o, st = c.compute(dev(d), dev(fx), tools=[t1, t2], dirs=[d1, d2], lam=0.02,
+                              method=imf.METHOD_FFT, batch=3, debug_orient=q,
+                              debug_numel=int(np.prod(box)))
+            outs[given] = {k: (v.clone() if hasattr(v, "clone") else v) for k, v in o.items()}
+            outs[given]["band"] = st.guard_band
+        finally:
+            c.close()
+    a, b = outs["0"], outs["1"]
+    for k in ("imf", "imf_norm", "secluded", "masks", "debug"):
+        assert torch.equal(a[k], b[k]), k
+    assert a["debug_box"] == b["debug_box"]
+    assert tuple(a["debug_box"][:3]) == tuple(-np.asarray(info["kmax"]))
+    ref = oracle.imf(req, debug_orient=q)
+    g = host(a["debug"]).reshape(box[2], box[1], box[0]).astype(np.float64)
+    E = a["band"] / 2          # the float32 transform error model of the guard band
+    r = ref["g_debug"] / float(1 << 24)
+    assert (np.abs(g - r) <= np.maximum(1e-4 * np.abs(r), E)).all()
