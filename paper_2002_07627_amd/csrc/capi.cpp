@@ -134,6 +134,7 @@ struct OrientEntry {
   int s_axis;       // 0..2: sharp-point runs along that axis; 3: along sv
   int sv[3];        // lattice vector of the sharp-point runs
   int maxlen;       // longest sharp-point run
+  int n_pow2;       // the first n_pow2 sharp-point runs have power-of-two lengths
   const imf_run* truns;
   const imf_run* sruns;
   const imf_run* sxruns;
@@ -636,11 +637,6 @@ static bool lattice_runs(const imf_run* ar, int n, int ax, const int* ext, int s
     ml = std::max(ml, len);
     out.push_back(imf_run{x, y, z, len});
   }
-  // runs in (z, y, x) order of their first point: neighbouring runs read
-  // neighbouring cache lines in the minimum pass
-  std::sort(out.begin(), out.end(), [](const imf_run& p, const imf_run& q) {
-    return p.z != q.z ? p.z < q.z : (p.y != q.y ? p.y < q.y : p.x < q.x);
-  });
   for (int a = 0; a < 3; a++) sv[a] = bv[a];
   *maxlen = ml;
   return true;
@@ -771,25 +767,37 @@ static imf_status ensure_rasters(imf_ctx* c, const imf_request* r, const std::ve
     e.sruns = pool + hb[(size_t)i * 3 + 1];
     e.sxruns = pool + hb[(size_t)i * 3 + 2];
   }
-  if (r->ndim == 3 && c->lattice_runs) {
+  {
     std::vector<imf_run> hpool((size_t)std::max(total, 1LL));
     RCHK(hipMemcpy(hpool.data(), pool, sizeof(imf_run) * hpool.size(), hipMemcpyDeviceToHost));
     std::vector<imf_run> vall, one;
     std::vector<long long> voff(n, -1);
     for (int i = 0; i < n; i++) {
       OrientEntry& e = ents[i];
+      const imf_run* ar = hpool.data() + hb[(size_t)i * 3 + 1];
       int sv[3], ml = 0;
-      if (!lattice_runs(hpool.data() + hb[(size_t)i * 3 + 1], e.ext[16], e.s_axis, e.ext, sv, &ml,
-                        one))
-        continue;
+      if (r->ndim == 3 && c->lattice_runs &&
+          lattice_runs(ar, e.ext[16], e.s_axis, e.ext, sv, &ml, one)) {
+        e.s_axis = std::abs(sv[0]) + std::abs(sv[1]) + std::abs(sv[2]) == 1
+                       ? (sv[0] ? 0 : (sv[1] ? 1 : 2))
+                       : 3;
+        for (int a = 0; a < 3; a++) e.sv[a] = e.s_axis < 3 ? (a == e.s_axis) : sv[a];
+        e.ext[16] = (int)one.size();
+        e.maxlen = ml;
+      } else {
+        one.assign(ar, ar + e.ext[16]);
+      }
+      // runs of power-of-two length first (their two windows coincide: one
+      // lookup), each part in (z, y, x) order of the first point so that
+      // neighbouring runs read neighbouring cache lines
+      auto pow2 = [](const imf_run& u) { return (u.len & (u.len - 1)) == 0; };
+      std::sort(one.begin(), one.end(), [&](const imf_run& p, const imf_run& q) {
+        if (pow2(p) != pow2(q)) return pow2(p);
+        return p.z != q.z ? p.z < q.z : (p.y != q.y ? p.y < q.y : p.x < q.x);
+      });
+      e.n_pow2 = (int)std::count_if(one.begin(), one.end(), pow2);
       voff[i] = (long long)vall.size();
       vall.insert(vall.end(), one.begin(), one.end());
-      e.s_axis = std::abs(sv[0]) + std::abs(sv[1]) + std::abs(sv[2]) == 1
-                     ? (sv[0] ? 0 : (sv[1] ? 1 : 2))
-                     : 3;
-      for (int a = 0; a < 3; a++) e.sv[a] = e.s_axis < 3 ? (a == e.s_axis) : sv[a];
-      e.ext[16] = (int)one.size();
-      e.maxlen = ml;
     }
     if (!vall.empty()) {
       imf_run* vpool = nullptr;
@@ -942,6 +950,7 @@ static imf_status make_plan(imf_ctx* c, const imf_request* r, const imf_outputs*
     d.s_axis = e.s_axis;
     for (int a = 0; a < 3; a++) d.sv[a] = e.sv[a];
     d.n_sruns = e.ext[16];
+    d.n_sruns1 = e.n_pow2;
     d.n_truns = e.ext[15];
     d.sruns = e.sruns;
     d.truns = e.truns;
@@ -1317,6 +1326,7 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
   for (int q = 0; q < p.nO; q++) {
     p.sweep_desc[q].sruns = p.ent[q]->sxruns;
     p.sweep_desc[q].n_sruns = p.ent[q]->ext[17];
+    p.sweep_desc[q].n_sruns1 = 0;
   }
   // descriptors: all of them, and per batch the orientations whose spectra are computed
   std::vector<imf_orient_desc> hall(p.desc);
@@ -1456,7 +1466,7 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
       pd.kbytes[10] += 4.0 * M3 * (1 + d.nlvl);
       // lookups: 2 per run and output lane (padding lanes of partial blocks included)
       const double lanes = 64.0 * p.nblocks;
-      const double ops = 2.0 * lanes * d.n_sruns;
+      const double ops = lanes * (2.0 * d.n_sruns - d.n_sruns1);
       // g box read once, runs, f read + write, masks (Omega_0 + bits) or the gamma stack
       const double byt = 4.0 * M3 + 16.0 * d.n_sruns + 8.0 * N +
                          (p.masks && p.theta_known && !p.sweep ? N + N / 8.0 : 0.0) +

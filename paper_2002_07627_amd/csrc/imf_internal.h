@@ -80,6 +80,7 @@ struct imf_orient_desc {
   int s_axis;          // axis of the sharp-point runs (0, 1, 2), or 3: along sv
   int sv[3];           // lattice vector of the sharp-point runs (e_axis for an axis)
   int n_sruns;         // number of sharp-point runs
+  int n_sruns1;        // the first n_sruns1 have power-of-two lengths (one lookup each)
   int n_truns;         // number of tool x-runs
   int tlo[3], tdim[3]; // bounding box of the tool raster (offsets)
   int nlvl;            // sparse-table levels this orientation's runs need

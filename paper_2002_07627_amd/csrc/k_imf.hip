@@ -613,6 +613,11 @@ __global__ void k_fill_u32(unsigned int* p, long long n, unsigned int v) {
 // of g and its levels from that XCD's L2.
 // ---------------------------------------------------------------------------
 #define MF_LDS_RUNS 1024
+struct mf_run {
+  long long off;  // element offset from g (level and far end folded in)
+  int dz;         // offset of the second window
+  int pad;
+};
 
 struct mf_geom {
   int WX, WY, WZ;
@@ -790,7 +795,7 @@ __global__ void __launch_bounds__(IMF_WG) k_scatter(imf_min_args a, int qi) {
 // block maximum of f (branch and bound) and the mask chunk.
 template <int WX, int WY, int WZ>
 __device__ __forceinline__ void mf_block(const imf_min_args& a, const imf_orient_desc& d,
-                                         const int4* rr, int qi, int bx, int by, int bz,
+                                         const mf_run* rr, int qi, int bx, int by, int bz,
                                          long long blk) {
   const int nr = d.n_sruns;
   const long long sx = 1, sy = d.box_dim[0], sz = (long long)d.box_dim[0] * d.box_dim[1];
@@ -811,24 +816,33 @@ __device__ __forceinline__ void mf_block(const imf_min_args& a, const imf_orient
                          (long long)(zc - d.box_lo[2]) * sz;
   float gam = INFINITY;
   int r = 0;
+  const float* gq = a.g + qi * a.g_stride;  // run offsets are relative to g (levels included)
+  // runs of power-of-two length come first: one window each
+  const int n1 = d.n_sruns1 < nl ? d.n_sruns1 : nl;
+  for (; r + 16 <= n1; r += 16) {
+    float v[16];
+#pragma unroll
+    for (int j = 0; j < 16; j++) v[j] = gq[base + rr[r + j].off];
+#pragma unroll
+    for (int j = 0; j < 16; j++) gam = fminf(gam, v[j]);
+  }
+  for (; r < n1; r++) gam = fminf(gam, gq[base + rr[r].off]);
   for (; r + 8 <= nl; r += 8) {
     float v[16];
 #pragma unroll
     for (int j = 0; j < 8; j++) {
-      const int4 u = rr[r + j];
-      const float* L = u.y == 0 ? g : lv + (long long)u.y * a.g_stride;
-      const long long p = base + u.x;
-      v[2 * j] = L[p];
-      v[2 * j + 1] = L[p + u.z];
+      const mf_run u = rr[r + j];
+      const long long p = base + u.off;
+      v[2 * j] = gq[p];
+      v[2 * j + 1] = gq[p + u.dz];
     }
 #pragma unroll
     for (int j = 0; j < 8; j++) gam = fminf(gam, fminf(v[2 * j], v[2 * j + 1]));
   }
   for (; r < nl; r++) {
-    const int4 u = rr[r];
-    const float* L = u.y == 0 ? g : lv + (long long)u.y * a.g_stride;
-    const long long p = base + u.x;
-    gam = fminf(gam, fminf(L[p], L[p + u.z]));
+    const mf_run u = rr[r];
+    const long long p = base + u.off;
+    gam = fminf(gam, fminf(gq[p], gq[p + u.dz]));
   }
   for (r = MF_LDS_RUNS; r < nr; r++) {  // beyond the LDS capacity: read the runs directly
     const imf_run u = d.sruns[r];
@@ -863,17 +877,25 @@ __device__ __forceinline__ void mf_block(const imf_min_args& a, const imf_orient
   }
 }
 
-// runs of S as box-index offsets: x = offset of the run's far end for k = 0,
-// y = sparse-table level, z = offset of the second (overlapping) window
-__device__ __forceinline__ void mf_stage_runs(const imf_orient_desc& d, int4* rr) {
+// runs of S as element offsets from g of this orientation, for k = 0: off =
+// the run's far end in its sparse-table level (the level arrays live in the
+// same workspace as g), dz = offset of the second (overlapping) window
+__device__ __forceinline__ void mf_stage_runs(const imf_min_args& a, const imf_orient_desc& d,
+                                              int qi, mf_run* rr) {
   const int nr = d.n_sruns;
   const long long sx = 1, sy = d.box_dim[0], sz = (long long)d.box_dim[0] * d.box_dim[1];
   const long long sa = d.sv[0] * sx + d.sv[1] * sy + d.sv[2] * sz;  // box offset of sv
+  // level s >= 1 of orientation qi, relative to its g
+  const long long l1 = (long long)(a.lvl - a.g) + qi * (a.lvl_stride - a.g_stride);
   for (int r = threadIdx.x; r < nr && r < MF_LDS_RUNS; r += IMF_WG) {
     const imf_run u = d.sruns[r];
     const int sl = ilog2(u.len);
-    rr[r] = make_int4((int)(-(u.x * sx + u.y * sy + u.z * sz) - (long long)(u.len - 1) * sa), sl,
-                      (int)((long long)(u.len - (1 << sl)) * sa), 0);
+    mf_run m;
+    m.off = (sl == 0 ? 0 : l1 + (long long)(sl - 1) * a.g_stride) -
+            (u.x * sx + u.y * sy + u.z * sz) - (long long)(u.len - 1) * sa;
+    m.dz = (int)((long long)(u.len - (1 << sl)) * sa);
+    m.pad = 0;
+    rr[r] = m;
   }
 }
 
@@ -885,14 +907,14 @@ __device__ __forceinline__ void mf_stage_runs(const imf_orient_desc& d, int4* rr
 // stay a compact window that shares its L2.
 template <int WX, int WY, int WZ>
 __global__ void __launch_bounds__(IMF_WG) k_minfilter(imf_min_args a, int qi) {
-  __shared__ int4 rr[MF_LDS_RUNS];
+  __shared__ mf_run rr[MF_LDS_RUNS];
   const mf_geom G(WX, WY, WZ, a.nx, a.ny, a.nz);
   const long long nwg = (G.nlog + 3) / 4;
   const long long per = (nwg + 7) / 8;
   const long long lg = (long long)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (lg >= nwg) return;  // uniform over the workgroup
   const imf_orient_desc& d = a.desc[qi];
-  mf_stage_runs(d, rr);
+  mf_stage_runs(a, d, qi, rr);
   __syncthreads();
   int bx, by, bz;
   if (!G.block(lg * 4 + (threadIdx.x >> 6), bx, by, bz)) return;
@@ -905,13 +927,13 @@ __global__ void __launch_bounds__(IMF_WG) k_minfilter(imf_min_args a, int qi) {
 // take consecutive groups of 4 entries, then advance by the XCD's total.
 template <int WX, int WY, int WZ>
 __global__ void __launch_bounds__(IMF_WG) k_minfilter_list(imf_min_args a, int qi) {
-  __shared__ int4 rr[MF_LDS_RUNS];
+  __shared__ mf_run rr[MF_LDS_RUNS];
   const mf_geom G(WX, WY, WZ, a.nx, a.ny, a.nz);
   const long long M = a.count[qi];
   if (blockIdx.x == 0 && threadIdx.x == 0 && a.skipped)
     atomicAdd(a.skipped, (unsigned long long)((long long)G.nbx * G.nby * G.nbz - M));
   const imf_orient_desc& d = a.desc[qi];
-  mf_stage_runs(d, rr);
+  mf_stage_runs(a, d, qi, rr);
   __syncthreads();
   const int* list = a.list + (long long)qi * a.list_stride;
   const long long per = (M + 7) / 8;
