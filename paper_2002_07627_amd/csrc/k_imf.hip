@@ -614,9 +614,8 @@ __global__ void k_fill_u32(unsigned int* p, long long n, unsigned int v) {
 // ---------------------------------------------------------------------------
 #define MF_LDS_RUNS 1024
 struct mf_run {
-  long long off;  // element offset from g (level and far end folded in)
-  int dz;         // offset of the second window
-  int pad;
+  long long off;   // element offset from g of the first window (level and far end folded in)
+  long long off2;  // the second (overlapping) window
 };
 
 struct mf_geom {
@@ -832,17 +831,15 @@ __device__ __forceinline__ void mf_block(const imf_min_args& a, const imf_orient
 #pragma unroll
     for (int j = 0; j < 8; j++) {
       const mf_run u = rr[r + j];
-      const long long p = base + u.off;
-      v[2 * j] = gq[p];
-      v[2 * j + 1] = gq[p + u.dz];
+      v[2 * j] = gq[base + u.off];
+      v[2 * j + 1] = gq[base + u.off2];
     }
 #pragma unroll
     for (int j = 0; j < 8; j++) gam = fminf(gam, fminf(v[2 * j], v[2 * j + 1]));
   }
   for (; r < nl; r++) {
     const mf_run u = rr[r];
-    const long long p = base + u.off;
-    gam = fminf(gam, fminf(gq[p], gq[p + u.dz]));
+    gam = fminf(gam, fminf(gq[base + u.off], gq[base + u.off2]));
   }
   for (r = MF_LDS_RUNS; r < nr; r++) {  // beyond the LDS capacity: read the runs directly
     const imf_run u = d.sruns[r];
@@ -879,7 +876,7 @@ __device__ __forceinline__ void mf_block(const imf_min_args& a, const imf_orient
 
 // runs of S as element offsets from g of this orientation, for k = 0: off =
 // the run's far end in its sparse-table level (the level arrays live in the
-// same workspace as g), dz = offset of the second (overlapping) window
+// same workspace as g), off2 = the second (overlapping) window
 __device__ __forceinline__ void mf_stage_runs(const imf_min_args& a, const imf_orient_desc& d,
                                               int qi, mf_run* rr) {
   const int nr = d.n_sruns;
@@ -893,8 +890,7 @@ __device__ __forceinline__ void mf_stage_runs(const imf_min_args& a, const imf_o
     mf_run m;
     m.off = (sl == 0 ? 0 : l1 + (long long)(sl - 1) * a.g_stride) -
             (u.x * sx + u.y * sy + u.z * sz) - (long long)(u.len - 1) * sa;
-    m.dz = (int)((long long)(u.len - (1 << sl)) * sa);
-    m.pad = 0;
+    m.off2 = m.off + (long long)(u.len - (1 << sl)) * sa;
     rr[r] = m;
   }
 }
