@@ -227,7 +227,10 @@ def main():
     el = time.perf_counter() - t0
     ms = 1000 * el / args.steps
     value = N * nR / (el / args.steps)
-    log("timed: %.2f ms/step, %.3e voxel-orientations/s" % (ms, value))
+    log("timed: %.2f ms/step, %.3e voxel-orientations/s (block shape %d, %d workgroups/CU, "
+        "%d orientations with lattice-vector runs)" % (ms, value, stats[-1].mf_shape,
+                                                      stats[-1].mf_wg_per_cu,
+                                                      stats[-1].lattice_runs))
     if stats[-1].bound_blocks:
         log("bound: %d of %d (block, orientation) pairs skipped (%.1f%%)" % (
             stats[-1].bound_skipped, stats[-1].bound_blocks,
@@ -370,6 +373,8 @@ def main():
                                "masks at lambda*F_max",
                    "grid": list(w.design.shape), "orientations": nR, "P": list(last.P),
                    "batch": last.batch, "autotuned": tuned is not None,
+                   "minfilter_block_shape": last.mf_shape, "minfilter_wg_per_cu": last.mf_wg_per_cu,
+                   "lattice_run_orientations": last.lattice_runs,
                    "spectra": "cached (warm)"},
         "roofline": roofline,
         "roofline_transform_passes": fft,

@@ -216,6 +216,9 @@ struct imf_ctx {
   bool lattice_runs = true;
   // process orientations in farthest-point order of their tool axes
   bool spread_order = true;
+  // list pass: the 4 waves of a workgroup (4 consecutive kept blocks, mostly
+  // x neighbours) gather the same runs in step, so they share L1 lines
+  int mf_sync = 1;
 };
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -287,6 +290,7 @@ extern "C" imf_status imf_create(int device, size_t hbm_budget_bytes, imf_ctx** 
   if (const char* e = std::getenv("IMF_BOUND_MIN_VOXELS")) c->bound_min_voxels = std::atoll(e);
   if (const char* e = std::getenv("IMF_AXIS_RUNS")) c->lattice_runs = std::atoi(e) == 0;
   if (const char* e = std::getenv("IMF_GIVEN_ORDER")) c->spread_order = std::atoi(e) == 0;
+  if (const char* e = std::getenv("IMF_MINFILTER_SYNC")) c->mf_sync = std::atoi(e);
   if (const char* e = std::getenv("IMF_MINFILTER_WG_PER_CU"))
     c->mf_wg_per_cu = std::max(1, std::min(16, std::atoi(e)));
   if (hipStreamCreateWithFlags(&c->internal, hipStreamNonBlocking) != hipSuccess) {
@@ -1602,6 +1606,7 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
     ma.n_cu = c->n_cu;
     ma.wg_per_cu = p.wg_per_cu;
     ma.skipped = (unsigned long long*)(misc + 8);
+    ma.sync_waves = c->mf_sync;
     HIPCHK(imf_launch_minfilter(ma, s, 0));
     tm.mark(10);
     for (int q = 0; q < nq; q++) {
@@ -1766,6 +1771,8 @@ static imf_status compute_finish(Pending& pd, imf_stats* st) {
     st->cache_misses = pd.misses;
     st->graph = pd.graph;
     for (int q = 0; q < p.nO; q++) st->lattice_runs += p.desc[q].s_axis == 3;
+    st->mf_shape = p.shape;
+    st->mf_wg_per_cu = p.wg_per_cu;
   } else {
     pd.tm.release();
   }

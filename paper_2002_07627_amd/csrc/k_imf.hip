@@ -792,10 +792,10 @@ __global__ void __launch_bounds__(IMF_WG) k_scatter(imf_min_args a, int qi) {
 // sparse-table levels at the run offsets staged in LDS, 16 independent
 // gathers in flight per wave; then the running minimum f, the gamma stack, the
 // block maximum of f (branch and bound) and the mask chunk.
-template <int WX, int WY, int WZ>
+template <int WX, int WY, int WZ, bool SYNC = false>
 __device__ __forceinline__ void mf_block(const imf_min_args& a, const imf_orient_desc& d,
                                          const mf_run* rr, int qi, int bx, int by, int bz,
-                                         long long blk) {
+                                         long long blk, bool act = true) {
   const int nr = d.n_sruns;
   const long long sx = 1, sy = d.box_dim[0], sz = (long long)d.box_dim[0] * d.box_dim[1];
   const long long sa = d.sv[0] * sx + d.sv[1] * sy + d.sv[2] * sz;  // box offset of sv
@@ -819,24 +819,34 @@ __device__ __forceinline__ void mf_block(const imf_min_args& a, const imf_orient
   // runs of power-of-two length come first: one window each
   const int n1 = d.n_sruns1 < nl ? d.n_sruns1 : nl;
   for (; r + 16 <= n1; r += 16) {
-    float v[16];
+    if (act) {
+      float v[16];
 #pragma unroll
-    for (int j = 0; j < 16; j++) v[j] = gq[base + rr[r + j].off];
+      for (int j = 0; j < 16; j++) v[j] = gq[base + rr[r + j].off];
 #pragma unroll
-    for (int j = 0; j < 16; j++) gam = fminf(gam, v[j]);
-  }
-  for (; r < n1; r++) gam = fminf(gam, gq[base + rr[r].off]);
-  for (; r + 8 <= nl; r += 8) {
-    float v[16];
-#pragma unroll
-    for (int j = 0; j < 8; j++) {
-      const mf_run u = rr[r + j];
-      v[2 * j] = gq[base + u.off];
-      v[2 * j + 1] = gq[base + u.off2];
+      for (int j = 0; j < 16; j++) gam = fminf(gam, v[j]);
     }
-#pragma unroll
-    for (int j = 0; j < 8; j++) gam = fminf(gam, fminf(v[2 * j], v[2 * j + 1]));
+    if (SYNC) __syncthreads();  // the workgroup's waves gather the same runs together
   }
+  if (act)
+    for (; r < n1; r++) gam = fminf(gam, gq[base + rr[r].off]);
+  else
+    r = n1;
+  for (; r + 8 <= nl; r += 8) {
+    if (act) {
+      float v[16];
+#pragma unroll
+      for (int j = 0; j < 8; j++) {
+        const mf_run u = rr[r + j];
+        v[2 * j] = gq[base + u.off];
+        v[2 * j + 1] = gq[base + u.off2];
+      }
+#pragma unroll
+      for (int j = 0; j < 8; j++) gam = fminf(gam, fminf(v[2 * j], v[2 * j + 1]));
+    }
+    if (SYNC) __syncthreads();
+  }
+  if (!act) return;
   for (; r < nl; r++) {
     const mf_run u = rr[r];
     gam = fminf(gam, fminf(gq[base + u.off], gq[base + u.off2]));
@@ -921,7 +931,7 @@ __global__ void __launch_bounds__(IMF_WG) k_minfilter(imf_min_args a, int qi) {
 // whose waves walk the list with a static schedule.  XCD x (workgroups x,
 // x + 8, ...) takes the x-th eighth of the list; inside it, its workgroups
 // take consecutive groups of 4 entries, then advance by the XCD's total.
-template <int WX, int WY, int WZ>
+template <int WX, int WY, int WZ, bool SYNC>
 __global__ void __launch_bounds__(IMF_WG) k_minfilter_list(imf_min_args a, int qi) {
   __shared__ mf_run rr[MF_LDS_RUNS];
   const mf_geom G(WX, WY, WZ, a.nx, a.ny, a.nz);
@@ -936,6 +946,18 @@ __global__ void __launch_bounds__(IMF_WG) k_minfilter_list(imf_min_args a, int q
   const long long lo = (long long)(blockIdx.x & 7) * per;
   const long long hi = lo + per < M ? lo + per : M;
   const long long step = (long long)(gridDim.x >> 3) * 4;
+  if (SYNC) {
+    // groups of 4 consecutive entries, one per wave, walked in step
+    for (long long e0 = lo + (long long)(blockIdx.x >> 3) * 4; e0 < hi; e0 += step) {
+      const long long e = e0 + (threadIdx.x >> 6);
+      const bool act = e < hi;
+      const unsigned int pk = act ? (unsigned int)list[e] : 0u;
+      const int bx = (int)(pk & 1023u), by = (int)((pk >> 10) & 2047u), bz = (int)(pk >> 21);
+      mf_block<WX, WY, WZ, true>(a, d, rr, qi, bx, by, bz,
+                                 ((long long)bz * G.nby + by) * G.nbx + bx, act);
+    }
+    return;
+  }
   for (long long e = lo + (long long)(blockIdx.x >> 3) * 4 + (threadIdx.x >> 6); e < hi;
        e += step) {
     const unsigned int pk = (unsigned int)list[e];
@@ -963,7 +985,11 @@ static hipError_t launch_mf(const imf_min_args& a, hipStream_t s, int part, int 
     // resident capacity (a multiple of 8 workgroups)
     long long lgrid = std::min((long long)a.n_cu * a.wg_per_cu, nwg);
     lgrid = std::max(8LL, (lgrid + 7) / 8 * 8);
-    hipLaunchKernelGGL((k_minfilter_list<WX, WY, WZ>), dim3((unsigned)lgrid), dim3(IMF_WG), 0, s,
+    if (a.sync_waves)
+      hipLaunchKernelGGL((k_minfilter_list<WX, WY, WZ, true>), dim3((unsigned)lgrid), dim3(IMF_WG), 0, s,
+                       a, q);
+    else
+      hipLaunchKernelGGL((k_minfilter_list<WX, WY, WZ, false>), dim3((unsigned)lgrid), dim3(IMF_WG), 0, s,
                        a, q);
   } else {
     const long long grid = (nwg + 7) / 8 * 8;

@@ -66,7 +66,8 @@ class _Stats(C.Structure):
                 ("k_ms", C.c_double * 16), ("k_n", C.c_int * 16),
                 ("k_bytes", C.c_double * 16), ("k_ops", C.c_double * 16),
                 ("bound_blocks", C.c_longlong), ("bound_skipped", C.c_longlong),
-                ("graph", C.c_int), ("lattice_runs", C.c_int)]
+                ("graph", C.c_int), ("lattice_runs", C.c_int), ("mf_shape", C.c_int),
+                ("mf_wg_per_cu", C.c_int)]
 
 
 @dataclass
@@ -91,6 +92,8 @@ class Stats:
     bound_skipped: int
     graph: int  # 0 kernel by kernel, 1 captured into a HIP graph, 2 graph replay
     lattice_runs: int  # orientations with sharp-point runs along a lattice vector
+    mf_shape: int      # block shape of the sharp-point minimum (imf.h)
+    mf_wg_per_cu: int  # resident workgroups per CU of its list pass
 
     @classmethod
     def _from(cls, s: _Stats):
@@ -101,7 +104,7 @@ class Stats:
         return cls(s.F_max, s.guard_flags, s.max_frac_err, s.guard_band, list(s.t_ms),
                    s.model_bytes, tuple(s.P), s.n_orient, s.method, s.batch, s.cache_hits,
                    s.cache_misses, kms, kn, kb, ko, s.bound_blocks, s.bound_skipped, s.graph,
-                   s.lattice_runs)
+                   s.lattice_runs, s.mf_shape, s.mf_wg_per_cu)
 
 
 _lib = None
