@@ -216,9 +216,10 @@ struct imf_ctx {
   bool lattice_runs = true;
   // process orientations in farthest-point order of their tool axes
   bool spread_order = true;
-  // list pass: the 4 waves of a workgroup (4 consecutive kept blocks, mostly
-  // x neighbours) gather the same runs in step, so they share L1 lines
-  int mf_sync = 1;
+  // list pass: the waves of a workgroup (consecutive kept blocks, mostly x
+  // neighbours) gather the same runs in step, so they share L1 lines:
+  // 0 off, 1 four waves, 2 eight waves per workgroup
+  int mf_sync = 2;
 };
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }

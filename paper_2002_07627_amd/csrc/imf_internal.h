@@ -227,7 +227,7 @@ struct imf_min_args {
   int q0;                   // global index of the batch's first orientation
   int n_cu, wg_per_cu;      // resident workgroups of the list pass: CUs x per CU
   unsigned long long* skipped;  // statistics: skipped (block, orientation) pairs
-  int sync_waves;               // list pass: a workgroup's waves walk the runs in step
+  int sync_waves;               // list pass: 0, or 1 / 2 for 4 / 8 waves per workgroup in step
 };
 // stage 0: sparse-table levels of the batch (and cell minima, footprints and
 // the threshold bound with branch and bound); stage 1: the bound pass of

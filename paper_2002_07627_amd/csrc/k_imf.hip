@@ -607,7 +607,7 @@ __global__ void k_fill_u32(unsigned int* p, long long n, unsigned int v) {
 // blocks of WX x WY x WZ voxels, one wave per block; f is updated in place (one
 // orientation per launch, so every voxel has a single writer).
 //
-// Logical block order: bricks of 64 x 16 x 16 voxels (x chunk slowest, then z,
+// Logical block order: bricks of 128 x 16 x 16 voxels (x chunk slowest, then z,
 // y fastest), blocks inside a brick x, y, z.  Consecutive logical indices are
 // close in space, so the waves one XCD runs at a time read overlapping windows
 // of g and its levels from that XCD's L2.
@@ -629,7 +629,7 @@ struct mf_geom {
     nbx = (nx + wx - 1) / wx;
     nby = (ny + wy - 1) / wy;
     nbz = (nz + wz - 1) / wz;
-    brx = 64 / wx;
+    brx = 128 / wx;
     bry = 16 / wy < nby ? 16 / wy : nby;
     brz = 16 / wz < nbz ? 16 / wz : nbz;
     const int nrx = (nbx + brx - 1) / brx;
@@ -894,7 +894,7 @@ __device__ __forceinline__ void mf_stage_runs(const imf_min_args& a, const imf_o
   const long long sa = d.sv[0] * sx + d.sv[1] * sy + d.sv[2] * sz;  // box offset of sv
   // level s >= 1 of orientation qi, relative to its g
   const long long l1 = (long long)(a.lvl - a.g) + qi * (a.lvl_stride - a.g_stride);
-  for (int r = threadIdx.x; r < nr && r < MF_LDS_RUNS; r += IMF_WG) {
+  for (int r = threadIdx.x; r < nr && r < MF_LDS_RUNS; r += blockDim.x) {
     const imf_run u = d.sruns[r];
     const int sl = ilog2(u.len);
     mf_run m;
@@ -930,9 +930,12 @@ __global__ void __launch_bounds__(IMF_WG) k_minfilter(imf_min_args a, int qi) {
 // Blocks left by the bound (compacted list in logical order): a resident grid
 // whose waves walk the list with a static schedule.  XCD x (workgroups x,
 // x + 8, ...) takes the x-th eighth of the list; inside it, its workgroups
-// take consecutive groups of 4 entries, then advance by the XCD's total.
-template <int WX, int WY, int WZ, bool SYNC>
-__global__ void __launch_bounds__(IMF_WG) k_minfilter_list(imf_min_args a, int qi) {
+// take consecutive groups of NW entries, then advance by the XCD's total.
+// With SYNC the NW waves of a workgroup walk the runs in step (a barrier per
+// 8 runs): consecutive kept blocks are mostly x neighbours in one brick row,
+// so their gathers of one run hit the same cache lines while they are in L1.
+template <int WX, int WY, int WZ, bool SYNC, int NW>
+__global__ void __launch_bounds__(64 * NW) k_minfilter_list(imf_min_args a, int qi) {
   __shared__ mf_run rr[MF_LDS_RUNS];
   const mf_geom G(WX, WY, WZ, a.nx, a.ny, a.nz);
   const long long M = a.count[qi];
@@ -945,10 +948,10 @@ __global__ void __launch_bounds__(IMF_WG) k_minfilter_list(imf_min_args a, int q
   const long long per = (M + 7) / 8;
   const long long lo = (long long)(blockIdx.x & 7) * per;
   const long long hi = lo + per < M ? lo + per : M;
-  const long long step = (long long)(gridDim.x >> 3) * 4;
+  const long long step = (long long)(gridDim.x >> 3) * NW;
   if (SYNC) {
-    // groups of 4 consecutive entries, one per wave, walked in step
-    for (long long e0 = lo + (long long)(blockIdx.x >> 3) * 4; e0 < hi; e0 += step) {
+    // groups of NW consecutive entries, one per wave, walked in step
+    for (long long e0 = lo + (long long)(blockIdx.x >> 3) * NW; e0 < hi; e0 += step) {
       const long long e = e0 + (threadIdx.x >> 6);
       const bool act = e < hi;
       const unsigned int pk = act ? (unsigned int)list[e] : 0u;
@@ -958,7 +961,7 @@ __global__ void __launch_bounds__(IMF_WG) k_minfilter_list(imf_min_args a, int q
     }
     return;
   }
-  for (long long e = lo + (long long)(blockIdx.x >> 3) * 4 + (threadIdx.x >> 6); e < hi;
+  for (long long e = lo + (long long)(blockIdx.x >> 3) * NW + (threadIdx.x >> 6); e < hi;
        e += step) {
     const unsigned int pk = (unsigned int)list[e];
     const int bx = (int)(pk & 1023u), by = (int)((pk >> 10) & 2047u), bz = (int)(pk >> 21);
@@ -985,12 +988,17 @@ static hipError_t launch_mf(const imf_min_args& a, hipStream_t s, int part, int 
     // resident capacity (a multiple of 8 workgroups)
     long long lgrid = std::min((long long)a.n_cu * a.wg_per_cu, nwg);
     lgrid = std::max(8LL, (lgrid + 7) / 8 * 8);
-    if (a.sync_waves)
-      hipLaunchKernelGGL((k_minfilter_list<WX, WY, WZ, true>), dim3((unsigned)lgrid), dim3(IMF_WG), 0, s,
-                       a, q);
-    else
-      hipLaunchKernelGGL((k_minfilter_list<WX, WY, WZ, false>), dim3((unsigned)lgrid), dim3(IMF_WG), 0, s,
-                       a, q);
+    if (a.sync_waves == 2) {  // eight waves per workgroup (half as many workgroups)
+      lgrid = std::max(8LL, ((long long)a.n_cu * std::max(1, a.wg_per_cu / 2) + 7) / 8 * 8);
+      hipLaunchKernelGGL((k_minfilter_list<WX, WY, WZ, true, 8>), dim3((unsigned)lgrid), dim3(512),
+                         0, s, a, q);
+    } else if (a.sync_waves) {
+      hipLaunchKernelGGL((k_minfilter_list<WX, WY, WZ, true, 4>), dim3((unsigned)lgrid),
+                         dim3(IMF_WG), 0, s, a, q);
+    } else {
+      hipLaunchKernelGGL((k_minfilter_list<WX, WY, WZ, false, 4>), dim3((unsigned)lgrid),
+                         dim3(IMF_WG), 0, s, a, q);
+    }
   } else {
     const long long grid = (nwg + 7) / 8 * 8;
     hipLaunchKernelGGL((k_minfilter<WX, WY, WZ>), dim3((unsigned)grid), dim3(IMF_WG), 0, s, a, q);

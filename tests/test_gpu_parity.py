@@ -477,3 +477,27 @@ def test_processing_order_changes_no_result(monkeypatch):
     E = a["band"] / 2          # the float32 transform error model of the guard band
     r = ref["g_debug"] / float(1 << 24)
     assert (np.abs(g - r) <= np.maximum(1e-4 * np.abs(r), E)).all()
+
+
+def test_minimum_pass_wave_modes_equal(monkeypatch):
+    """The list pass of the minimum with independent waves, four waves in step
+    and eight waves in step gives identical outputs (two-phase masks, bound on)."""
+    import paper_2002_07627_amd as imf
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    d, fx, tl, dirs = _bound_case()
+    monkeypatch.setenv("IMF_BOUND_MIN_VOXELS", "0")
+    outs = []
+    for mode in ("0", "1", "2"):
+        monkeypatch.setenv("IMF_MINFILTER_SYNC", mode)
+        c = imf.Context(0)
+        try:
+            o, st = c.compute(dev(d), dev(fx), tools=tl, dirs=dirs, lam=0.02,
+                              method=imf.METHOD_FFT)
+            outs.append({k: v.clone() for k, v in o.items()})
+            assert st.bound_blocks > 0
+        finally:
+            c.close()
+    for o in outs[1:]:
+        for k in ("imf", "imf_norm", "secluded", "masks"):
+            assert torch.equal(o[k], outs[0][k]), k
