@@ -1082,6 +1082,7 @@ static imf_status make_plan(imf_ctx* c, const imf_request* r, const imf_outputs*
     add(sizeof(int) * p.nO);                            // kept blocks per orientation
     add(sizeof(uint64_t) * p.B * p.nwords_blk);         // kept-block bits
     add(sizeof(int) * p.B * p.nwords_blk);              // list offsets
+    if (p.two_phase) add(sizeof(uint64_t) * p.nO * p.nwords_blk);  // kept-block bits per orientation
   }
   if (p.sweep) add(sizeof(uint64_t) * p.B * ((p.max_m[0] + 63) / 64) * (long long)p.max_m[1] * p.max_m[2]);
   if (p.method == IMF_METHOD_FFT) {
@@ -1281,6 +1282,8 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
   int* kept = p.bnb ? carve<int>(ar, p.nO) : nullptr;
   unsigned long long* wmask = p.bnb ? carve<unsigned long long>(ar, p.B * p.nwords_blk) : nullptr;
   int* woff = p.bnb ? carve<int>(ar, p.B * p.nwords_blk) : nullptr;
+  unsigned long long* keepbits =
+      p.bnb && p.two_phase ? carve<unsigned long long>(ar, (size_t)p.nO * p.nwords_blk) : nullptr;
   const long long dc_stride = ((p.max_m[0] + 63) / 64) * (long long)p.max_m[1] * p.max_m[2];
   uint64_t* dc = p.sweep ? carve<uint64_t>(ar, p.B * dc_stride) : nullptr;
   float2 *rho_hat = nullptr, *fw1 = nullptr, *fw2 = nullptr, *tw1 = nullptr, *tw2 = nullptr,
@@ -1415,10 +1418,7 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
   if (p.masks && p.theta_known && !p.sweep)
     HIPCHK(imf_launch_fill_u32((unsigned*)out->acc_masks,
                                2LL * p.nO * r->nz * r->ny * ((r->nx + 63) / 64), 0u, s));
-  if (p.bnb) {
-    // skipped blocks leave gamma = +inf behind
-    if (gstack) HIPCHK(imf_launch_fill_f(gstack, (long long)N * p.nO, INFINITY, s));
-  }
+  // blocks the bound skips write no gamma: the mask pass reads their keep bits
   for (int k = 0; k < nps; k++)
     HIPCHK(imf_launch_prefix_x(r->design, r->design_is_density,
                                p.nsets ? setfix + N * k : r->fixture, r->nx, r->ny, r->nz,
@@ -1608,6 +1608,7 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
     ma.wg_per_cu = p.wg_per_cu;
     ma.skipped = (unsigned long long*)(misc + 8);
     ma.sync_waves = c->mf_sync;
+    ma.keepbits = keepbits;
     HIPCHK(imf_launch_minfilter(ma, s, 0));
     tm.mark(10);
     for (int q = 0; q < nq; q++) {
@@ -1630,7 +1631,8 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
                              r->tau, out->imf, out->imf_norm, out->secluded, s));
   if (p.two_phase)
     HIPCHK(imf_launch_masks_from_gamma(gstack, p.nO, om, r->nx, r->ny, r->nz, fmax_bits,
-                                       r->lambda, out->acc_masks, s));
+                                       r->lambda, out->acc_masks, keepbits, p.shape,
+                                       p.nwords_blk, s));
   tm.mark(13);
   pd.kbytes[13] = (double)N * (4 + 1 + esz + (out->imf ? 4 : 0) + (out->imf_norm ? 4 : 0) +
                                (out->secluded ? 1 : 0)) +

@@ -227,6 +227,7 @@ struct imf_min_args {
   int q0;                   // global index of the batch's first orientation
   int n_cu, wg_per_cu;      // resident workgroups of the list pass: CUs x per CU
   unsigned long long* skipped;  // statistics: skipped (block, orientation) pairs
+  unsigned long long* keepbits;  // per orientation (request order): kept-block bits, or NULL
   int sync_waves;               // list pass: 0, or 1 / 2 for 4 / 8 waves per workgroup in step
 };
 // stage 0: sparse-table levels of the batch (and cell minima, footprints and
@@ -264,7 +265,9 @@ hipError_t imf_launch_finalize(const float* f, const uint8_t* omega0, const void
                                uint8_t* secluded, hipStream_t s);
 hipError_t imf_launch_masks_from_gamma(const float* gamma_stack, int nq, const uint8_t* omega0,
                                        int nx, int ny, int nz, const unsigned int* fmax_bits,
-                                       double lambda, uint64_t* masks, hipStream_t s);
+                                       double lambda, uint64_t* masks,
+                                       const unsigned long long* keep, int shape,
+                                       long long kstride, hipStream_t s);
 
 // coupling to the TO loop (Sec. 3)
 hipError_t imf_launch_heaviside(const float* xi, long long n, double beta, float* rho,

@@ -637,6 +637,12 @@ struct mf_geom {
     nrz = (nbz + brz - 1) / brz;
     nlog = (long long)nrx * nry * nrz * brx * bry * brz;
   }
+  // block -> logical index (the inverse of block())
+  __device__ __forceinline__ long long logical(int bx, int by, int bz) const {
+    const long long brick = ((long long)(bx / brx) * nrz + bz / brz) * nry + by / bry;
+    const int wib = ((bz % brz) * bry + by % bry) * brx + bx % brx;
+    return brick * (brx * bry * brz) + wib;
+  }
   // logical index -> block (false for the padding of partial bricks)
   __device__ __forceinline__ bool block(long long lg, int& bx, int& by, int& bz) const {
     const int br = brx * bry * brz;
@@ -715,7 +721,10 @@ __global__ void __launch_bounds__(IMF_WG) k_bound(imf_min_args a, int qi) {
   if (need_mask && !a.theta_known) thu = a.theta_lambda * (double)ord2f(*a.fmax_up);
   const bool sk = live && lb >= fb && (!need_mask || (double)lb > thu);
   const unsigned long long mw = __ballot(live && !sk);
-  if ((threadIdx.x & 63) == 0 && lg < G.nlog) a.wmask[(long long)qi * a.wstride + (lg >> 6)] = mw;
+  if ((threadIdx.x & 63) == 0 && lg < G.nlog) {
+    a.wmask[(long long)qi * a.wstride + (lg >> 6)] = mw;
+    if (a.keepbits) a.keepbits[(long long)d.out_q * a.wstride + (lg >> 6)] = mw;
+  }
 }
 
 // Branch and bound, part 3: order-preserving compaction of the blocks left to
@@ -1281,7 +1290,9 @@ __global__ void __launch_bounds__(IMF_WG) k_masks_gamma(const float* __restrict_
                                                         const uint8_t* __restrict__ om, int nx,
                                                         int ny, int nz,
                                                         const unsigned int* __restrict__ fmax_bits,
-                                                        double lambda, uint64_t* __restrict__ masks) {
+                                                        double lambda, uint64_t* __restrict__ masks,
+                                                        const unsigned long long* __restrict__ keep,
+                                                        int WX, int WY, int WZ, long long kstride) {
   const int words = (nx + 63) >> 6;
   const long long wave = (long long)blockIdx.x * (IMF_WG / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -1295,11 +1306,29 @@ __global__ void __launch_bounds__(IMF_WG) k_masks_gamma(const float* __restrict_
   const long long vi = yz * nx + (x < nx ? x : nx - 1);
   const bool in = x < nx && om[vi];
   const float* g = gs + vi;
+  // Blocks the bound skipped hold no gamma (their mask bits are 0).  The
+  // blocks of one 64-voxel word are consecutive in the logical order (bricks
+  // are 128 voxels wide, blocks x fastest), so one keep word per orientation,
+  // the same for the whole wave, holds their bits from (lg0 & 63) on.
+  long long kw = 0;
+  int kb0 = 0;
+  if (keep) {
+    const mf_geom G(WX, WY, WZ, nx, ny, nz);
+    const int y = (int)(yz % ny), z = (int)(yz / ny);
+    const long long lg0 = G.logical((w * 64) / WX, y / WY, z / WZ);
+    kw = lg0 >> 6;
+    kb0 = (int)(lg0 & 63);
+  }
+  const int kbit = kb0 + (WX < 64 ? lane / WX : 0);
+  auto word_of = [&](int q) { return keep ? keep[(long long)q * kstride + kw] : ~0ull; };
   int q = 0;
   for (; q + 4 <= nq; q += 4) {
+    unsigned long long wd[4];
     float v[4];
 #pragma unroll
-    for (int j = 0; j < 4; j++) v[j] = g[(long long)(q + j) * N];
+    for (int j = 0; j < 4; j++) wd[j] = word_of(q + j);
+#pragma unroll
+    for (int j = 0; j < 4; j++) v[j] = (wd[j] >> kbit) & 1 ? g[(long long)(q + j) * N] : INFINITY;
 #pragma unroll
     for (int j = 0; j < 4; j++) {
       const unsigned long long bits = __ballot(in && (double)v[j] <= theta);
@@ -1307,17 +1336,23 @@ __global__ void __launch_bounds__(IMF_WG) k_masks_gamma(const float* __restrict_
     }
   }
   for (; q < nq; q++) {
-    const unsigned long long bits = __ballot(in && (double)g[(long long)q * N] <= theta);
+    const float v = (word_of(q) >> kbit) & 1 ? g[(long long)q * N] : INFINITY;
+    const unsigned long long bits = __ballot(in && (double)v <= theta);
     if (lane == 0) masks[(long long)q * per_q + wave] = bits;
   }
 }
 hipError_t imf_launch_masks_from_gamma(const float* gamma_stack, int nq, const uint8_t* omega0,
                                        int nx, int ny, int nz, const unsigned int* fmax_bits,
-                                       double lambda, uint64_t* masks, hipStream_t s) {
+                                       double lambda, uint64_t* masks,
+                                       const unsigned long long* keep, int shape,
+                                       long long kstride, hipStream_t s) {
   const int words = (nx + 63) >> 6;
   const long long waves = (long long)words * ny * nz;
   const int per = IMF_WG / 64;
+  int wx, wy, wz;
+  imf_block_dims(shape, wx, wy, wz);
   hipLaunchKernelGGL(k_masks_gamma, dim3((unsigned)((waves + per - 1) / per)), dim3(IMF_WG), 0, s,
-                     gamma_stack, nq, omega0, nx, ny, nz, fmax_bits, lambda, masks);
+                     gamma_stack, nq, omega0, nx, ny, nz, fmax_bits, lambda, masks, keep, wx, wy,
+                     wz, kstride);
   return hipGetLastError();
 }
