@@ -1582,9 +1582,7 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
     ma.masks_on = p.masks && p.theta_known && !p.sweep;
     ma.theta = p.theta;
     ma.masks = out->acc_masks;
-    ma.mask_q0 = q0;
     ma.gamma_stack = gstack;
-    ma.gamma_q0 = q0;
     ma.bnb = p.bnb;
     ma.shape = p.shape;
     ma.cellmin = cellmin;
@@ -1621,7 +1619,7 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
     }
     if (p.sweep) {
       imf_sweep_args sa{d_sweep + q0, nq, g, p.max_vol, p.theta, r->nx, r->ny, r->nz, om, dc,
-                        dc_stride, out->acc_masks, q0};
+                        dc_stride, out->acc_masks};
       HIPCHK(imf_launch_sweep(sa, s));
       tm.mark(12);
     }

@@ -201,8 +201,8 @@ struct imf_min_args {
   int nx, ny, nz;
   float* f;                 // running min [nz][ny][nx]
   const uint8_t* omega0;    // [nz][ny][nx]
-  int masks_on; double theta; uint64_t* masks; int mask_q0;  // masks for orientations mask_q0 + q
-  float* gamma_stack; int gamma_q0;   // optional
+  int masks_on; double theta; uint64_t* masks;  // masks, indexed by each descriptor's out_q
+  float* gamma_stack;                  // optional, indexed by out_q
   // branch and bound: the output is cut into blocks of the wave shape; for
   // every orientation a lower bound of gamma over a block is the minimum of g
   // over the coarse cells (same shape, aligned to the query box) that cover
@@ -246,7 +246,7 @@ struct imf_sweep_args {
   const float* g; long long g_stride; double theta;
   int nx, ny, nz; const uint8_t* omega0;
   uint64_t* dc; long long dc_stride;   // scratch bitset per q over the box
-  uint64_t* masks; int mask_q0;
+  uint64_t* masks;                     // indexed by each descriptor's out_q
 };
 hipError_t imf_launch_sweep(const imf_sweep_args& a, hipStream_t s);
 
