@@ -581,14 +581,24 @@ __global__ void __launch_bounds__(IMF_WG) k_cellmin(const imf_orient_desc* __res
   const int cx = x / WX;
   const float* gq = g + q * g_stride;
   float* out = cellmin + q * cell_stride;
-  const int y0 = cy * WY, y1 = min(y0 + WY, my);
-  for (int cz = cz0; cz < min(cz0 + CM_CZ, cdz); cz++) {
-    float m = INFINITY;
-    for (int z = cz * WZ; z < min(cz * WZ + WZ, mz); z++)
-      for (int y = y0; y < y1; y++)
-        if (x < mx) m = fminf(m, gq[((long long)z * my + y) * mx + x]);
+  const int y0 = cy * WY;
+  // all rows of the CM_CZ cell planes first (up to 4 rows per cell: WY * WZ
+  // <= 4 for every block shape), so the loads are in flight together
+  float v[CM_CZ][4];
+#pragma unroll
+  for (int c = 0; c < CM_CZ; c++)
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+      const int cz = cz0 + c, z = cz * WZ + r / WY, y = y0 + r % WY;
+      const bool ok = r < WY * WZ && cz < cdz && z < mz && y < my && x < mx;
+      v[c][r] = ok ? gq[((long long)z * my + y) * mx + x] : INFINITY;
+    }
+#pragma unroll
+  for (int c = 0; c < CM_CZ; c++) {
+    const int cz = cz0 + c;
+    float m = fminf(fminf(v[c][0], v[c][1]), fminf(v[c][2], v[c][3]));
     for (int o = 1; o < WX; o <<= 1) m = fminf(m, __shfl_xor(m, o));
-    if ((lane % WX) == 0 && cx < cdx) out[((long long)cz * cdy + cy) * cdx + cx] = m;
+    if ((lane % WX) == 0 && cx < cdx && cz < cdz) out[((long long)cz * cdy + cy) * cdx + cx] = m;
   }
 }
 
