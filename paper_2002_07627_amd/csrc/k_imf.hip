@@ -1330,25 +1330,33 @@ __global__ void __launch_bounds__(IMF_WG) k_masks_gamma(const float* __restrict_
     kb0 = (int)(lg0 & 63);
   }
   const int kbit = kb0 + (WX < 64 ? lane / WX : 0);
-  auto word_of = [&](int q) { return keep ? keep[(long long)q * kstride + kw] : ~0ull; };
-  int q = 0;
-  for (; q + 4 <= nq; q += 4) {
-    unsigned long long wd[4];
-    float v[4];
+  // keep words of 64 orientations at a time, one per lane, then broadcast
+  for (int qc = 0; qc < nq; qc += 64) {
+    const int nc = nq - qc < 64 ? nq - qc : 64;
+    const unsigned long long mine_w =
+        keep && lane < nc ? keep[(long long)(qc + lane) * kstride + kw] : ~0ull;
+    const unsigned int lo32 = (unsigned int)mine_w, hi32 = (unsigned int)(mine_w >> 32);
+    auto word_of = [&](int j) {
+      return ((unsigned long long)__builtin_amdgcn_readlane(hi32, j) << 32) |
+             (unsigned int)__builtin_amdgcn_readlane(lo32, j);
+    };
+    int j = 0;
+    for (; j + 4 <= nc; j += 4) {
+      float v[4];
 #pragma unroll
-    for (int j = 0; j < 4; j++) wd[j] = word_of(q + j);
+      for (int i = 0; i < 4; i++)
+        v[i] = (word_of(j + i) >> kbit) & 1 ? g[(long long)(qc + j + i) * N] : INFINITY;
 #pragma unroll
-    for (int j = 0; j < 4; j++) v[j] = (wd[j] >> kbit) & 1 ? g[(long long)(q + j) * N] : INFINITY;
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-      const unsigned long long bits = __ballot(in && (double)v[j] <= theta);
-      if (lane == 0) masks[(long long)(q + j) * per_q + wave] = bits;
+      for (int i = 0; i < 4; i++) {
+        const unsigned long long bits = __ballot(in && (double)v[i] <= theta);
+        if (lane == 0) masks[(long long)(qc + j + i) * per_q + wave] = bits;
+      }
     }
-  }
-  for (; q < nq; q++) {
-    const float v = (word_of(q) >> kbit) & 1 ? g[(long long)q * N] : INFINITY;
-    const unsigned long long bits = __ballot(in && (double)v <= theta);
-    if (lane == 0) masks[(long long)q * per_q + wave] = bits;
+    for (; j < nc; j++) {
+      const float v = (word_of(j) >> kbit) & 1 ? g[(long long)(qc + j) * N] : INFINITY;
+      const unsigned long long bits = __ballot(in && (double)v <= theta);
+      if (lane == 0) masks[(long long)(qc + j) * per_q + wave] = bits;
+    }
   }
 }
 hipError_t imf_launch_masks_from_gamma(const float* gamma_stack, int nq, const uint8_t* omega0,
