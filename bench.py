@@ -44,7 +44,7 @@ def measured_traffic(kernel):
     src = os.path.join(ROOT, e["source"])
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != e["sha256"]:
         return None
-    return e["bytes_per_launch"]
+    return e["bytes_per_launch"] or None
 
 
 # on-chip vector memory rate: 16 lanes (4-byte dwords) per clock per CU,
