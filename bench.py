@@ -168,8 +168,10 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--batch", type=int, default=0)
     ap.add_argument("--copy-probe", action="store_true",
-                    help="also time a plain 1 GiB device copy (stream-copy bandwidth; the "
-                         "reference kernel for the FETCH_SIZE / WRITE_SIZE counter scale)")
+                    help="time a plain 1 GiB device copy (stream-copy bandwidth; the reference "
+                         "kernel for the FETCH_SIZE / WRITE_SIZE counter scale); on by default "
+                         "unless --no-copy-probe")
+    ap.add_argument("--no-copy-probe", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the IMF path here runs on a single MI355X "
@@ -184,7 +186,7 @@ def main():
     import workloads as W
 
     copy_gbs = None
-    if args.copy_probe:
+    if args.copy_probe or not args.no_copy_probe:
         x = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0").fill_(1.0)
         y = torch.empty_like(x)
         y.copy_(x)
@@ -253,6 +255,18 @@ def main():
             (k, v["ms_per_step"], v["launches_per_step"],
              "%.0f" % v["GBps"] if v["GBps"] else "-"))
     roofline = roofline_of(dom, kms, kn, kb, ko)
+    # measured HBM traffic of the whole request: per-launch FETCH + WRITE bytes
+    # of the committed counter runs times this run's launches, for the kernel
+    # classes those runs cover (null when any of them changed since)
+    hbm_req = None
+    tr = {k: measured_traffic(k) for k in ("minfilter", "bound", "inv_z_product", "inv_y",
+                                           "inv_x_c2r", "levels")}
+    if all(v is not None for v in tr.values()) and all(k in kn for k in tr):
+        b_req = sum(tr[k] * kn[k] / args.steps for k in tr)
+        covered_ms = sum(kms[k] / args.steps for k in tr)
+        hbm_req = {"bytes_per_request": b_req, "GBps_over_request": b_req / (ms * 1e-3) / 1e9,
+                   "frac_of_peak": b_req / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                   "classes": sorted(tr), "share_of_request_time": covered_ms / ms}
     # the transform passes are HBM-bound: their roofline beside the dominant one
     fft = {k: roofline_of(k, kms, kn, kb, ko) for k in ("inv_z_product", "inv_y", "inv_x_c2r")
            if k in kms}
@@ -391,6 +405,7 @@ def main():
         "bound": {"blocks": last.bound_blocks, "skipped": last.bound_skipped,
                   "frac": (last.bound_skipped / last.bound_blocks) if last.bound_blocks else None},
         "stream_copy_GBps": copy_gbs,
+        "request_hbm_traffic": hbm_req,
         "model_bytes_per_step": last.model_bytes,
         "model_GBps": last.model_bytes / (ms * 1e-3) / 1e9,
     }
