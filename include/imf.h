@@ -207,6 +207,14 @@ imf_status imf_cancel(imf_ctx* ctx, uint64_t ticket);
  * choice.  *best_batch receives the batch width. */
 imf_status imf_autotune(imf_ctx* ctx, const imf_request* req, const imf_outputs* out,
                         int* best_batch);
+/* The context's autotuned table as a text file (host file IO only): save
+ * writes every tuned request shape; load merges a saved table into the
+ * context (an entry replaces the one for the same shape), so a new process
+ * skips the tuning.  A malformed file is rejected whole with IMF_EINVAL and
+ * leaves the context unchanged.  *n_loaded (may be NULL) receives the number
+ * of entries read. */
+imf_status imf_autotune_save(imf_ctx* ctx, const char* path);
+imf_status imf_autotune_load(imf_ctx* ctx, const char* path, int* n_loaded);
 
 /* ----------------------------------------- coupling to the TO loop (Sec. 3) -- */
 /* Heaviside projection of the design variables (Eq. Heaviside):

@@ -2091,6 +2091,61 @@ extern "C" imf_status imf_autotune(imf_ctx* c, const imf_request* r, const imf_o
   return IMF_OK;
 }
 
+// The autotuned table as text: a header line, then one line per request shape
+// "<method>|<nx>,<ny>,<nz>|<px>,<py>,<pz> <batch> <shape> <wg>".
+extern "C" imf_status imf_autotune_save(imf_ctx* c, const char* path) {
+  if (!c || !path) return fail(IMF_EINVAL, "NULL argument");
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  FILE* f = std::fopen(path, "w");
+  if (!f) return fail(IMF_EINVAL, "cannot write %s", path);
+  bool ok = std::fprintf(f, "imf-autotune 1\n") > 0;
+  for (const auto& kv : c->tuned)
+    ok = ok && std::fprintf(f, "%s %d %d %d\n", kv.first.c_str(), kv.second.batch,
+                            kv.second.shape, kv.second.wg) > 0;
+  ok = (std::fclose(f) == 0) && ok;
+  return ok ? IMF_OK : fail(IMF_EINVAL, "writing %s failed", path);
+}
+
+extern "C" imf_status imf_autotune_load(imf_ctx* c, const char* path, int* n_loaded) {
+  if (!c || !path) return fail(IMF_EINVAL, "NULL argument");
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(IMF_EINVAL, "cannot read %s", path);
+  std::map<std::string, imf_ctx::Tuned> got;
+  char line[256];
+  int ln = 0;
+  imf_status st = IMF_OK;
+  while (st == IMF_OK && std::fgets(line, sizeof line, f)) {
+    ln++;
+    if (ln == 1) {
+      if (std::strncmp(line, "imf-autotune 1", 14) != 0)
+        st = fail(IMF_EINVAL, "%s: not an autotune table", path);
+      continue;
+    }
+    char key[128];
+    int m, n[3], P[3], batch, shape, wg, used = 0;
+    if (std::sscanf(line, "%127s %d %d %d %n", key, &batch, &shape, &wg, &used) != 4 ||
+        line[used] != '\0' ||
+        std::sscanf(key, "%d|%d,%d,%d|%d,%d,%d", &m, &n[0], &n[1], &n[2], &P[0], &P[1], &P[2]) !=
+            7 ||
+        batch < 1 || batch > 64 || shape < -1 || shape > 3 || wg < 0 || wg > 16) {
+      st = fail(IMF_EINVAL, "%s:%d: malformed autotune entry", path, ln);
+      break;
+    }
+    imf_ctx::Tuned t;
+    t.batch = batch;
+    t.shape = shape;
+    t.wg = wg;
+    got[key] = t;
+  }
+  std::fclose(f);
+  if (st == IMF_OK && ln == 0) st = fail(IMF_EINVAL, "%s: empty", path);
+  if (st != IMF_OK) return st;
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  for (const auto& kv : got) c->tuned[kv.first] = kv.second;
+  if (n_loaded) *n_loaded = (int)got.size();
+  return IMF_OK;
+}
+
 // ---------------------------------------------------------------------------
 // serving: a queue of requests, admitted by workspace footprint, each run on
 // a worker with its own stream and workspace (continuous batching: a request

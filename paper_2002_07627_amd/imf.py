@@ -125,6 +125,7 @@ def _L():
         L.imf_fft_size.restype = C.c_int
         for name in ("imf_create", "imf_destroy", "imf_tool_register", "imf_query_footprint",
                      "imf_compute", "imf_submit", "imf_wait", "imf_cancel", "imf_autotune",
+                     "imf_autotune_save", "imf_autotune_load",
                      "imf_raster", "imf_fft_c2c", "imf_fft_r2c_3d"):
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -356,6 +357,16 @@ class Context:
         b = C.c_int()
         _check(_L().imf_autotune(self._ctx, C.byref(r), C.byref(co), C.byref(b)))
         return b.value
+
+    def autotune_save(self, path: str):
+        """Write the context's autotuned table to a text file."""
+        _check(_L().imf_autotune_save(self._ctx, os.fsencode(path)))
+
+    def autotune_load(self, path: str) -> int:
+        """Merge a saved autotune table; returns the number of entries."""
+        n = C.c_int()
+        _check(_L().imf_autotune_load(self._ctx, os.fsencode(path), C.byref(n)))
+        return n.value
 
     # -------------------------------------------------- coupling to the TO loop
     def heaviside(self, xi, beta: float, out=None, stream=None):

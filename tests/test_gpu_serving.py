@@ -141,6 +141,41 @@ def test_autotune_then_batch_is_used_and_results_unchanged(imf_mod):
         ctx.close()
 
 
+def test_autotune_table_saved_and_loaded(imf_mod, tmp_path):
+    """A tuned table written by one context and read by a fresh one: the
+    fresh context uses the tuned batch and block parameters without tuning,
+    with the same results; a malformed table is rejected and changes nothing."""
+    imf = imf_mod
+    d = W.design_3d_boxes_cyls(48, seed=97)
+    fx = W.fixture_plate(d.shape, 3)
+    kw = dict(tools=W.tool(W.TOOL_FLAT, 2, 10, 4, 8), dirs=W.fib_hemisphere(20),
+              dir_kind=imf.DIR_F64, method=imf.METHOD_FFT)
+    path = str(tmp_path / "tuned.txt")
+    ctx = imf.Context(0)
+    try:
+        best = ctx.autotune(dev(d), dev(fx), **kw)
+        o1, s1 = ctx.compute(dev(d), dev(fx), **kw)
+        o1 = {k: v.clone() for k, v in o1.items()}
+        ctx.autotune_save(path)
+    finally:
+        ctx.close()
+    bad = str(tmp_path / "bad.txt")
+    with open(bad, "w") as f:
+        f.write("imf-autotune 1\n1|48,48,48|96,96,96 0 2 6\n")   # batch 0 is invalid
+    ctx = imf.Context(0)
+    try:
+        with pytest.raises(imf.IMFError):
+            ctx.autotune_load(bad)
+        assert ctx.autotune_load(path) >= 1
+        o2, s2 = ctx.compute(dev(d), dev(fx), **kw)
+        assert s2.batch == best == s1.batch
+        assert (s2.mf_shape, s2.mf_wg_per_cu) == (s1.mf_shape, s1.mf_wg_per_cu)
+        for k in ("imf", "imf_norm", "secluded", "masks"):
+            assert torch.equal(o2[k], o1[k]), k
+    finally:
+        ctx.close()
+
+
 def test_graph_replays_equal_eager(imf_mod):
     """The second identical request is captured into a HIP graph and later
     ones replay it; every replay equals the kernel-by-kernel result, with
