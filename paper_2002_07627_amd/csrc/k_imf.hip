@@ -623,6 +623,12 @@ __global__ void k_fill_u32(unsigned int* p, long long n, unsigned int v) {
 // of g and its levels from that XCD's L2.
 // ---------------------------------------------------------------------------
 #define MF_LDS_RUNS 1024
+#ifndef MF_GRP
+// runs per group of the gather loop (a barrier per group when the waves go in
+// step): eight 16 x 2 x 2 blocks gathering 4 runs touch ~160 lines, within the
+// 256 lines of the L1, so the later waves of a group still find them there
+#define MF_GRP 4
+#endif
 struct mf_run {
   long long off;   // element offset from g of the first window (level and far end folded in)
   long long off2;  // the second (overlapping) window
@@ -837,13 +843,13 @@ __device__ __forceinline__ void mf_block(const imf_min_args& a, const imf_orient
   const float* gq = a.g + qi * a.g_stride;  // run offsets are relative to g (levels included)
   // runs of power-of-two length come first: one window each
   const int n1 = d.n_sruns1 < nl ? d.n_sruns1 : nl;
-  for (; r + 16 <= n1; r += 16) {
+  for (; r + 2 * MF_GRP <= n1; r += 2 * MF_GRP) {
     if (act) {
-      float v[16];
+      float v[2 * MF_GRP];
 #pragma unroll
-      for (int j = 0; j < 16; j++) v[j] = gq[base + rr[r + j].off];
+      for (int j = 0; j < 2 * MF_GRP; j++) v[j] = gq[base + rr[r + j].off];
 #pragma unroll
-      for (int j = 0; j < 16; j++) gam = fminf(gam, v[j]);
+      for (int j = 0; j < 2 * MF_GRP; j++) gam = fminf(gam, v[j]);
     }
     if (SYNC) __syncthreads();  // the workgroup's waves gather the same runs together
   }
@@ -851,17 +857,17 @@ __device__ __forceinline__ void mf_block(const imf_min_args& a, const imf_orient
     for (; r < n1; r++) gam = fminf(gam, gq[base + rr[r].off]);
   else
     r = n1;
-  for (; r + 8 <= nl; r += 8) {
+  for (; r + MF_GRP <= nl; r += MF_GRP) {
     if (act) {
-      float v[16];
+      float v[2 * MF_GRP];
 #pragma unroll
-      for (int j = 0; j < 8; j++) {
+      for (int j = 0; j < MF_GRP; j++) {
         const mf_run u = rr[r + j];
         v[2 * j] = gq[base + u.off];
         v[2 * j + 1] = gq[base + u.off2];
       }
 #pragma unroll
-      for (int j = 0; j < 8; j++) gam = fminf(gam, fminf(v[2 * j], v[2 * j + 1]));
+      for (int j = 0; j < MF_GRP; j++) gam = fminf(gam, fminf(v[2 * j], v[2 * j + 1]));
     }
     if (SYNC) __syncthreads();
   }
