@@ -1274,7 +1274,12 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
   float* g = carve<float>(ar, p.B * p.max_vol);
   float* lvl = carve<float>(ar, (size_t)p.B * std::max(p.nlvl, 1) * p.max_vol);
   float* gstack = p.two_phase ? carve<float>(ar, (size_t)N * p.nO) : nullptr;
-  float* cellmin = p.bnb ? carve<float>(ar, p.B * p.cell_stride) : nullptr;
+  unsigned int* cellmin = p.bnb ? carve<unsigned int>(ar, p.B * p.cell_stride) : nullptr;
+  // the bound's cell minima come from the inverse x pass (and the recheck)
+  // on the transform path, from a pass over g on the direct path
+  const bool cm_fused = p.bnb && p.method == IMF_METHOD_FFT;
+  int cwx = 1, cwy = 1, cwz = 1;
+  imf_block_dims(p.shape, cwx, cwy, cwz);
   int* fpbuf = p.bnb ? carve<int>(ar, p.B * (long long)(kFpCap + 1)) : nullptr;
   float* fblock = p.bnb ? carve<float>(ar, p.nblocks) : nullptr;
   int* wlist = p.bnb ? carve<int>(ar, p.B * p.nblocks) : nullptr;
@@ -1520,13 +1525,19 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
       ia.flag_cnt = flag_cnt + b;
       ia.flag_cap = flag_cap;
       ia.flags = flags;
+      ia.cellmin = cm_fused ? cellmin : nullptr;
+      ia.cell_stride = p.cell_stride;
+      ia.cwx = cwx;
+      ia.cwy = cwy;
+      ia.cwz = cwz;
       for (int stage = 0; stage < 3; stage++) {
         HIPCHK(imf_launch_inverse(ia, p.fl[0], p.fl[1], p.fl[2], twx, twy, twz, s, stage));
         tm.mark(6 + stage);
       }
       if (ia.binary || ia.theta_known) {
         HIPCHK(imf_launch_recheck(bd, ps_b, r->nx, r->ny, r->nz, r->design_is_density, flag_cnt + b,
-                                  flags, flag_cap, ia.theta_known, p.theta, g, p.max_vol, s));
+                                  flags, flag_cap, ia.theta_known, p.theta, g, p.max_vol,
+                                  ia.cellmin, p.cell_stride, cwx, cwy, cwz, s));
         tm.mark(9);
       }
     } else {
@@ -1586,6 +1597,7 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
     ma.bnb = p.bnb;
     ma.shape = p.shape;
     ma.cellmin = cellmin;
+    ma.cellmin_fused = cm_fused;
     ma.cell_stride = p.cell_stride;
     ma.cell_waves = p.cell_waves;
     ma.fp = fpbuf;

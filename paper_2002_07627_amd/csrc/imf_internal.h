@@ -40,6 +40,17 @@ struct imf_raster_desc {
 // along s_axis, [17] number of x-runs of S.
 #define IMF_EXT_INTS 20
 
+// Order-preserving map of float to unsigned int (atomic min / max of floats,
+// and cell minima that several workgroups lower).
+__device__ __forceinline__ unsigned int f2ord(float f) {
+  const unsigned int b = __float_as_uint(f);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float ord2f(unsigned int u) {
+  return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+#define IMF_ORD_INF 0xFF800000u  // f2ord(+infinity)
+
 // Integer floor and ceiling of p / q for q > 0.
 __host__ __device__ inline int imf_floor_div(int p, int q) {
   return p >= 0 ? p / q : -((-p + q - 1) / q);
@@ -170,6 +181,9 @@ struct imf_inv_args {
   double theta, band;
   unsigned int* max_err_bits;        // atomic max of |g - rint g| (binary)
   int* flag_cnt; int flag_cap; int2* flags;   // (q, linear box index)
+  // optional: minima of g over the bound's cells (cwx x cwy x cwz, aligned to
+  // the box), per q [cdz][cdy][cdx] as f2ord values, lowered by atomic min
+  unsigned int* cellmin; long long cell_stride; int cwx, cwy, cwz;
 };
 // stage: -1 all, 0 product + z pass, 1 y pass, 2 x pass (complex-to-real) + epilogue
 hipError_t imf_launch_inverse(const imf_inv_args& a, const imf_fft_len& fx,
@@ -185,7 +199,8 @@ hipError_t imf_launch_direct(const imf_orient_desc* desc, int nq, const long lon
 hipError_t imf_launch_recheck(const imf_orient_desc* desc, const long long* ps, int nx, int ny, int nz, int density,
                               const int* flag_cnt, const int2* flags, int flag_cap,
                               int theta_known, double theta, float* g, long long g_stride,
-                              hipStream_t s);
+                              unsigned int* cellmin, long long cell_stride, int cwx, int cwy,
+                              int cwz, hipStream_t s);
 
 // sharp-point min filter with running minimum, masks, optional gamma stack
 struct imf_min_args {
@@ -210,7 +225,8 @@ struct imf_min_args {
   // mask threshold bound, cannot change f or set a mask bit and are skipped.
   int bnb;                  // 0: plain, 1: branch and bound
   int shape;                // wave block: 0 = 64x1x1, 1 = 32x2x1, 2 = 16x2x2, 3 = 16x4x1
-  float* cellmin; long long cell_stride;   // per q: [cdz][cdy][cdx]
+  unsigned int* cellmin; long long cell_stride;   // per q: [cdz][cdy][cdx], f2ord values
+  int cellmin_fused;                    // 1: the inverse x pass and the recheck wrote them
   long long cell_waves;                    // waves of the cell-minimum pass (largest box)
   int* fp; int fp_cap;                     // per q: [0] count, then cell-index offsets
   float* fblock;            // max of f per block (+inf before the first orientation)

@@ -538,6 +538,12 @@ __global__ void __launch_bounds__(IMF_WG) k_inv_z_product(imf_inv_args a, imf_ff
   extern __shared__ float2 smem[];
   const int n = L.n;
   const int h = a.px / 2 + 1;
+  if (a.cellmin) {  // the x pass lowers these cell minima by atomic min
+    const long long nc = (long long)a.nq * a.cell_stride;
+    for (long long i = (long long)blockIdx.x * IMF_WG + threadIdx.x; i < nc;
+         i += (long long)gridDim.x * IMF_WG)
+      a.cellmin[i] = IMF_ORD_INF;
+  }
   int bx, ky, bz;
   if (!xcd_blocks(GX, GY, 1, bx, ky, bz)) return;
   const int c0 = bx * CT;
@@ -654,6 +660,32 @@ __global__ void __launch_bounds__(IMF_WG) k_inv_x_c2r(imf_inv_args a, imf_fft_le
       }
     }
     dst[li] = v;
+  }
+  if (a.cellmin) {
+    // minima of this tile's rows over the bound's cells, from the transformed
+    // tile still in LDS (the values just written: rounded when binary), one
+    // atomic min per (row, cell); the recheck lowers a cell again when it
+    // corrects a value
+    const int cwx = a.cwx, cwy = a.cwy, cwz = a.cwz;
+    const int ncx = (mx + cwx - 1) / cwx;
+    const int cdx = ncx + 1, cdy = (my + cwy - 1) / cwy + 1;
+    unsigned int* cm = a.cellmin + q * a.cell_stride;
+    for (int i = threadIdx.x; i < 2 * CT * ncx; i += IMF_WG) {
+      const int rr = i / ncx, cx = i - rr * ncx;
+      const long long row = row0 + rr;
+      if (row >= rows) continue;
+      float m = INFINITY;
+      const int x1 = min(cx * cwx + cwx, mx);
+      for (int x = cx * cwx; x < x1; x++) {
+        int pos = x + sh;
+        if (pos >= n) pos -= n;
+        const float2 z = X[LIDX(pos, rr >> 1)];
+        const float v = (rr & 1) ? z.y : z.x;
+        m = fminf(m, a.binary ? rintf(v) : v);
+      }
+      const long long zz = row / my, yy = row - zz * my;
+      atomicMin(&cm[((zz / cwz) * cdy + yy / cwy) * cdx + cx], f2ord(m));
+    }
   }
   if (a.binary) {
     for (int o = 32; o > 0; o >>= 1) local_err = fmaxf(local_err, __shfl_xor(local_err, o));

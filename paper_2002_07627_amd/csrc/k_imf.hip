@@ -10,14 +10,6 @@ __device__ __forceinline__ float wave_max_f(float v) {
   return v;
 }
 
-// order-preserving map of float to unsigned int (for atomic max)
-__device__ __forceinline__ unsigned int f2ord(float f) {
-  const unsigned int b = __float_as_uint(f);
-  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
-}
-__device__ __forceinline__ float ord2f(unsigned int u) {
-  return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
-}
 
 // ---------------------------------------------------------------------------
 // prefix sums of rho_O = max(design, fixture) along x, fixed point:
@@ -123,7 +115,10 @@ __global__ void __launch_bounds__(IMF_WG) k_recheck(const imf_orient_desc* __res
                                                     const int* __restrict__ flag_cnt,
                                                     const int2* __restrict__ flags, int flag_cap,
                                                     int theta_known, double theta,
-                                                    float* __restrict__ g, long long g_stride) {
+                                                    float* __restrict__ g, long long g_stride,
+                                                    unsigned int* __restrict__ cellmin,
+                                                    long long cell_stride, int cwx, int cwy,
+                                                    int cwz) {
   const int n = min(*flag_cnt, flag_cap);
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
     const int2 f = flags[k];
@@ -150,17 +145,25 @@ __global__ void __launch_bounds__(IMF_WG) k_recheck(const imf_orient_desc* __res
       }
     }
     g[(long long)f.x * g_stride + i] = v;
+    if (cellmin) {  // the corrected value may lie below its cell's minimum
+      const int cdx = (d.box_dim[0] + cwx - 1) / cwx + 1;
+      const int cdy = (d.box_dim[1] + cwy - 1) / cwy + 1;
+      atomicMin(&cellmin[(long long)f.x * cell_stride +
+                         ((long long)(bz / cwz) * cdy + by / cwy) * cdx + bx / cwx],
+                f2ord(v));
+    }
   }
 }
 
 hipError_t imf_launch_recheck(const imf_orient_desc* desc, const long long* ps, int nx, int ny, int nz, int density,
                               const int* flag_cnt, const int2* flags, int flag_cap,
                               int theta_known, double theta, float* g, long long g_stride,
-                              hipStream_t s) {
+                              unsigned int* cellmin, long long cell_stride, int cwx, int cwy,
+                              int cwz, hipStream_t s) {
   const int blocks = flag_cap < 256 * 1024 ? (flag_cap + IMF_WG - 1) / IMF_WG : 1024;
   hipLaunchKernelGGL(k_recheck, dim3(blocks > 0 ? blocks : 1), dim3(IMF_WG), 0, s, desc, ps,
                      nx, ny, nz, density, flag_cnt, flags, flag_cap, theta_known, theta, g,
-                     g_stride);
+                     g_stride, cellmin, cell_stride, cwx, cwy, cwz);
   return hipGetLastError();
 }
 
@@ -561,7 +564,7 @@ __global__ void __launch_bounds__(IMF_WG) k_footprint(const imf_orient_desc* __r
 __global__ void __launch_bounds__(IMF_WG) k_cellmin(const imf_orient_desc* __restrict__ desc,
                                                     const float* __restrict__ g,
                                                     long long g_stride, int WX, int WY, int WZ,
-                                                    float* __restrict__ cellmin,
+                                                    unsigned int* __restrict__ cellmin,
                                                     long long cell_stride) {
   const int q = blockIdx.y;
   const imf_orient_desc& d = desc[q];
@@ -580,7 +583,7 @@ __global__ void __launch_bounds__(IMF_WG) k_cellmin(const imf_orient_desc* __res
   const int x = sg * 64 + lane;
   const int cx = x / WX;
   const float* gq = g + q * g_stride;
-  float* out = cellmin + q * cell_stride;
+  unsigned int* out = cellmin + q * cell_stride;
   const int y0 = cy * WY;
   // all rows of the CM_CZ cell planes first (up to 4 rows per cell: WY * WZ
   // <= 4 for every block shape), so the loads are in flight together
@@ -598,7 +601,8 @@ __global__ void __launch_bounds__(IMF_WG) k_cellmin(const imf_orient_desc* __res
     const int cz = cz0 + c;
     float m = fminf(fminf(v[c][0], v[c][1]), fminf(v[c][2], v[c][3]));
     for (int o = 1; o < WX; o <<= 1) m = fminf(m, __shfl_xor(m, o));
-    if ((lane % WX) == 0 && cx < cdx && cz < cdz) out[((long long)cz * cdy + cy) * cdx + cx] = m;
+    if ((lane % WX) == 0 && cx < cdx && cz < cdz)
+      out[((long long)cz * cdy + cy) * cdx + cx] = f2ord(m);
   }
 }
 
@@ -720,16 +724,18 @@ __global__ void __launch_bounds__(IMF_WG) k_bound(imf_min_args a, int qi) {
   const bool live = lg < G.nlog && G.block(lg, bx, by, bz);
   const int cdx = (d.box_dim[0] + WX - 1) / WX + 1, cdy = (d.box_dim[1] + WY - 1) / WY + 1;
   const long long cb = ((long long)bz * cdy + by) * cdx + bx;
-  const float* cm = a.cellmin + qi * a.cell_stride;
-  float lb = nfp < 0 ? -INFINITY : INFINITY;  // no footprint: no bound
+  const unsigned int* cm = a.cellmin + qi * a.cell_stride;
+  // minimum in the order-preserving integer map of the cell minima
+  unsigned int lbo = nfp < 0 ? 0u : IMF_ORD_INF;  // no footprint: no bound
   for (int c0 = 0; c0 < nfp; c0 += BND_CHUNK) {
     const int n = min(BND_CHUNK, nfp - c0);
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += IMF_WG) fpl[i] = fpg[1 + c0 + i];
     __syncthreads();
     if (live)
-      for (int i = 0; i < n; i++) lb = fminf(lb, cm[cb + fpl[i]]);
+      for (int i = 0; i < n; i++) lbo = min(lbo, cm[cb + fpl[i]]);
   }
+  const float lb = nfp < 0 ? -INFINITY : ord2f(lbo);
   const long long blk = ((long long)bz * G.nby + by) * G.nbx + bx;
   const float fb = live ? a.fblock[blk] : -INFINITY;
   const bool need_mask = a.masks_on || a.gamma_stack;
@@ -1081,9 +1087,11 @@ hipError_t imf_launch_minfilter(const imf_min_args& a, hipStream_t s, int stage,
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // waves: (64-x segment, cell row, CM_CZ cell planes) over the largest box
     const long long waves = a.cell_waves;
-    hipLaunchKernelGGL(k_cellmin, dim3((unsigned)((waves + 3) / 4), a.nq), dim3(IMF_WG), 0, s,
-                       a.desc, a.g, a.g_stride, wx, wy, wz, a.cellmin, a.cell_stride);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (!a.cellmin_fused) {
+      hipLaunchKernelGGL(k_cellmin, dim3((unsigned)((waves + 3) / 4), a.nq), dim3(IMF_WG), 0, s,
+                         a.desc, a.g, a.g_stride, wx, wy, wz, a.cellmin, a.cell_stride);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     if (a.fmax_up) {  // two-phase masks: bound of the threshold for this batch
       const long long nb = (long long)((a.nx + wx - 1) / wx) * ((a.ny + wy - 1) / wy) *
                            ((a.nz + wz - 1) / wz);
