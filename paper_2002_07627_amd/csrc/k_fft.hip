@@ -135,10 +135,10 @@ __device__ __forceinline__ void dft<7>(float2* v, bool inv) { dft_generic<7>(v, 
 
 // one self-sorting (Stockham) stage, in place: every thread keeps its
 // butterflies in registers across the barrier
-template <int R, int CT, int MAXE>
+template <int R, int CT, int MAXE, int NTH = IMF_WG>
 __device__ __forceinline__ void fft_stage(float2* X, const float2* tw, const imf_fft_len& L,
                                           int s, bool inv) {
-  constexpr int JR = IMF_WG / CT;
+  constexpr int JR = NTH / CT;
   constexpr int IT = (MAXE + R - 1) / R;
   float2 reg[IT * R];
   const int n = L.n;
@@ -209,9 +209,9 @@ constexpr int ct_ns(int n, int idx) {
 }
 
 // one stage with every size known at compile time
-template <int R, int N, int NS, int CT>
+template <int R, int N, int NS, int CT, int NTH = IMF_WG>
 __device__ __forceinline__ void fft_stage_ct(float2* X, const float2* tw, bool inv) {
-  constexpr int JR = IMF_WG / CT;
+  constexpr int JR = NTH / CT;
   constexpr int NB = N / R;
   constexpr int IT = (NB + JR - 1) / JR;
   constexpr int STEP = N / (NS * R);
@@ -253,29 +253,29 @@ __device__ __forceinline__ void fft_stage_ct(float2* X, const float2* tw, bool i
   __syncthreads();
 }
 
-template <int N, int CT, int S>
+template <int N, int CT, int S, int NTH = IMF_WG>
 __device__ __forceinline__ void fft_stages_ct(float2* X, const float2* tw, bool inv) {
   if constexpr (S < ct_nstages(N)) {
-    fft_stage_ct<ct_radix(N, S), N, ct_ns(N, S), CT>(X, tw, inv);
-    fft_stages_ct<N, CT, S + 1>(X, tw, inv);
+    fft_stage_ct<ct_radix(N, S), N, ct_ns(N, S), CT, NTH>(X, tw, inv);
+    fft_stages_ct<N, CT, S + 1, NTH>(X, tw, inv);
   }
 }
 
 // Transform all CT columns of the tile: NT > 0 is a compile-time length,
 // NT == 0 the run-time plan L.
-template <int CT, int MAXE, int NT>
+template <int CT, int MAXE, int NT, int NTH = IMF_WG>
 __device__ void fft_tile(float2* X, const float2* tw, const imf_fft_len& L, bool inv) {
   if constexpr (NT > 0) {
-    fft_stages_ct<NT, CT, 0>(X, tw, inv);
+    fft_stages_ct<NT, CT, 0, NTH>(X, tw, inv);
   } else {
     for (int s = 0; s < L.nstages; s++) {
       switch (L.radix[s]) {
-        case 8: fft_stage<8, CT, MAXE>(X, tw, L, s, inv); break;
-        case 4: fft_stage<4, CT, MAXE>(X, tw, L, s, inv); break;
-        case 2: fft_stage<2, CT, MAXE>(X, tw, L, s, inv); break;
-        case 3: fft_stage<3, CT, MAXE>(X, tw, L, s, inv); break;
-        case 5: fft_stage<5, CT, MAXE>(X, tw, L, s, inv); break;
-        case 7: fft_stage<7, CT, MAXE>(X, tw, L, s, inv); break;
+        case 8: fft_stage<8, CT, MAXE, NTH>(X, tw, L, s, inv); break;
+        case 4: fft_stage<4, CT, MAXE, NTH>(X, tw, L, s, inv); break;
+        case 2: fft_stage<2, CT, MAXE, NTH>(X, tw, L, s, inv); break;
+        case 3: fft_stage<3, CT, MAXE, NTH>(X, tw, L, s, inv); break;
+        case 5: fft_stage<5, CT, MAXE, NTH>(X, tw, L, s, inv); break;
+        case 7: fft_stage<7, CT, MAXE, NTH>(X, tw, L, s, inv); break;
         default: break;
       }
     }
@@ -394,8 +394,8 @@ struct strided_io {
 // pass kinds for the per-orientation geometry
 enum { PASS_DESIGN_Y = 0, PASS_TOOL_Y = 1, PASS_INV_Y = 2 };
 
-template <int CT, int MAXE, int NT, int KIND>
-__global__ void __launch_bounds__(IMF_WG) k_pass_strided(strided_io io, imf_fft_len L,
+template <int CT, int MAXE, int NT, int KIND, int NTH = IMF_WG>
+__global__ void __launch_bounds__(NTH) k_pass_strided(strided_io io, imf_fft_len L,
                                                          const float2* __restrict__ twg,
                                                          const imf_orient_desc* __restrict__ desc,
                                                          int planes_fixed, int n_in_fixed,
@@ -421,7 +421,7 @@ __global__ void __launch_bounds__(IMF_WG) k_pass_strided(strided_io io, imf_fft_
   load_twiddles(tw, twg, n);
   const int c0 = bx * CT;
   const float2* in = io.in + q * io.in_q + plane * io.in_plane + c0;
-  for (int i = threadIdx.x; i < CT * n; i += IMF_WG) {
+  for (int i = threadIdx.x; i < CT * n; i += NTH) {
     const int j = i / CT, c = i - j * CT;
     float2 v = make_float2(0.f, 0.f);
     if (j < n_in && c0 + c < io.ncols) v = in[j * io.in_j + c];
@@ -430,9 +430,9 @@ __global__ void __launch_bounds__(IMF_WG) k_pass_strided(strided_io io, imf_fft_
     X[LIDX(pos, c)] = v;
   }
   __syncthreads();
-  fft_tile<CT, MAXE, NT>(X, tw, L, inv != 0);
+  fft_tile<CT, MAXE, NT, NTH>(X, tw, L, inv != 0);
   float2* out = io.out + q * io.out_q + plane * io.out_plane + c0;
-  for (int i = threadIdx.x; i < CT * n_out; i += IMF_WG) {
+  for (int i = threadIdx.x; i < CT * n_out; i += NTH) {
     const int j = i / CT, c = i - j * CT;
     if (c0 + c >= io.ncols) continue;
     int pos = j + sh_out;
@@ -531,8 +531,8 @@ __global__ void __launch_bounds__(IMF_WG) k_tool_x(const imf_orient_desc* __rest
 //     The rho_hat tile is kept in registers and reused for every orientation
 //     of the batch.
 // ---------------------------------------------------------------------------
-template <int CT, int MAXE, int NT>
-__global__ void __launch_bounds__(IMF_WG) k_inv_z_product(imf_inv_args a, imf_fft_len L,
+template <int CT, int MAXE, int NT, int NTH = IMF_WG>
+__global__ void __launch_bounds__(NTH) k_inv_z_product(imf_inv_args a, imf_fft_len L,
                                                           const float2* __restrict__ twg, int GX,
                                                           int GY) {
   extern __shared__ float2 smem[];
@@ -540,8 +540,8 @@ __global__ void __launch_bounds__(IMF_WG) k_inv_z_product(imf_inv_args a, imf_ff
   const int h = a.px / 2 + 1;
   if (a.cellmin) {  // the x pass lowers these cell minima by atomic min
     const long long nc = (long long)a.nq * a.cell_stride;
-    for (long long i = (long long)blockIdx.x * IMF_WG + threadIdx.x; i < nc;
-         i += (long long)gridDim.x * IMF_WG)
+    for (long long i = (long long)blockIdx.x * NTH + threadIdx.x; i < nc;
+         i += (long long)gridDim.x * NTH)
       a.cellmin[i] = IMF_ORD_INF;
   }
   int bx, ky, bz;
@@ -553,11 +553,11 @@ __global__ void __launch_bounds__(IMF_WG) k_inv_z_product(imf_inv_args a, imf_ff
   load_twiddles(tw, twg, n);
   const float scale = 1.0f / ((float)a.px * (float)a.py * (float)a.pz);
   const float2* rsrc = a.rho_hat + ((long long)ky * h + c0) * n;
-  constexpr int RE = NT > 0 ? (CT * NT + IMF_WG - 1) / IMF_WG : MAXE;
+  constexpr int RE = NT > 0 ? (CT * NT + NTH - 1) / NTH : MAXE;
   float2 rho[RE];
 #pragma unroll
   for (int e = 0; e < RE; e++) {
-    const int i = threadIdx.x + e * IMF_WG;
+    const int i = threadIdx.x + e * NTH;
     rho[e] = i < ncol * n ? rsrc[i] : make_float2(0.f, 0.f);
   }
   for (int q = 0; q < a.nq; q++) {
@@ -566,7 +566,7 @@ __global__ void __launch_bounds__(IMF_WG) k_inv_z_product(imf_inv_args a, imf_ff
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < RE; e++) {
-      const int i = threadIdx.x + e * IMF_WG;
+      const int i = threadIdx.x + e * NTH;
       if (i < CT * n) {
         const int c = i / n, k = i - c * n;
         float2 v = make_float2(0.f, 0.f);
@@ -580,12 +580,12 @@ __global__ void __launch_bounds__(IMF_WG) k_inv_z_product(imf_inv_args a, imf_ff
       }
     }
     __syncthreads();
-    fft_tile<CT, MAXE, NT>(X, tw, L, true);
+    fft_tile<CT, MAXE, NT, NTH>(X, tw, L, true);
     const int mz = d.box_dim[2];
     const int sh = pmod(d.box_lo[2], n);
     float2* dst = a.w1 + q * a.w1_stride + (long long)ky * h + c0;
     const long long zs = (long long)a.py * h;
-    for (int i = threadIdx.x; i < CT * mz; i += IMF_WG) {
+    for (int i = threadIdx.x; i < CT * mz; i += NTH) {
       const int z = i / CT, c = i - z * CT;
       if (c >= ncol) continue;
       int pos = z + sh;
@@ -599,8 +599,8 @@ __global__ void __launch_bounds__(IMF_WG) k_inv_z_product(imf_inv_args a, imf_ff
 // (6) inverse x pass (complex-to-real, two rows per complex column) with the
 //     rounding / guard-band epilogue.  Writes g over the query box.
 // ---------------------------------------------------------------------------
-template <int CT, int MAXE, int NT>
-__global__ void __launch_bounds__(IMF_WG) k_inv_x_c2r(imf_inv_args a, imf_fft_len L,
+template <int CT, int MAXE, int NT, int NTH = IMF_WG>
+__global__ void __launch_bounds__(NTH) k_inv_x_c2r(imf_inv_args a, imf_fft_len L,
                                                       const float2* __restrict__ twg) {
   extern __shared__ float2 smem[];
   const int n = L.n, h = n / 2 + 1;
@@ -614,7 +614,7 @@ __global__ void __launch_bounds__(IMF_WG) k_inv_x_c2r(imf_inv_args a, imf_fft_le
   float2* tw = smem + (CT + 1) * n;
   load_twiddles(tw, twg, n);
   const float2* src = a.w2 + q * a.w2_stride;
-  for (int i = threadIdx.x; i < CT * h; i += IMF_WG) {
+  for (int i = threadIdx.x; i < CT * h; i += NTH) {
     const int c = i / h, k = i - c * h;
     const long long ra = row0 + 2 * c, rb = ra + 1;
     float2 A = make_float2(0.f, 0.f), B = make_float2(0.f, 0.f);
@@ -631,11 +631,11 @@ __global__ void __launch_bounds__(IMF_WG) k_inv_x_c2r(imf_inv_args a, imf_fft_le
     if (k > 0 && k < n - k) X[LIDX(n - k, c)] = make_float2(A.x + B.y, B.x - A.y);
   }
   __syncthreads();
-  fft_tile<CT, MAXE, NT>(X, tw, L, true);
+  fft_tile<CT, MAXE, NT, NTH>(X, tw, L, true);
   const int sh = pmod(d.box_lo[0], n);
   float* dst = a.g + q * a.g_stride;
   float local_err = 0.f;
-  for (int i = threadIdx.x; i < 2 * CT * mx; i += IMF_WG) {
+  for (int i = threadIdx.x; i < 2 * CT * mx; i += NTH) {
     const int rr = i / mx, x = i - rr * mx;
     const long long row = row0 + rr;
     if (row >= rows) continue;
@@ -670,7 +670,7 @@ __global__ void __launch_bounds__(IMF_WG) k_inv_x_c2r(imf_inv_args a, imf_fft_le
     const int ncx = (mx + cwx - 1) / cwx;
     const int cdx = ncx + 1, cdy = (my + cwy - 1) / cwy + 1;
     unsigned int* cm = a.cellmin + q * a.cell_stride;
-    for (int i = threadIdx.x; i < 2 * CT * ncx; i += IMF_WG) {
+    for (int i = threadIdx.x; i < 2 * CT * ncx; i += NTH) {
       const int rr = i / ncx, cx = i - rr * ncx;
       const long long row = row0 + rr;
       if (row >= rows) continue;
@@ -741,6 +741,13 @@ __global__ void __launch_bounds__(IMF_WG) k_inv_x_c2r(imf_inv_args a, imf_fft_le
         }                                                  \
     }                                                      \
   } while (0)
+
+// threads per workgroup of the inverse passes (the per-request hot transforms):
+// twice the default, so each thread keeps half the butterflies in registers
+// and a CU holds more waves to hide HBM latency
+#ifndef IMF_INV_NTH
+#define IMF_INV_NTH 512
+#endif
 
 static size_t smem_bytes(int n, int ct) { return (size_t)((ct + 1) * n + n) * sizeof(float2); }
 
@@ -832,30 +839,31 @@ hipError_t imf_launch_inverse(const imf_inv_args& a, const imf_fft_len& fx,
   hipError_t e = hipSuccess;
   if (stage < 0 || stage == 0) DISPATCH(fz.n, {
     const size_t sm = smem_bytes(fz.n, CT);
-    auto k = k_inv_z_product<CT, MAXE, NT>;
+    auto k = k_inv_z_product<CT, MAXE, NT, IMF_INV_NTH>;
     if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
     const int GX = (h + CT - 1) / CT;
-    hipLaunchKernelGGL(k, dim3(xcd_grid(GX, a.py, 1)), dim3(IMF_WG), sm, s, a, fz, twz, GX, a.py);
+    hipLaunchKernelGGL(k, dim3(xcd_grid(GX, a.py, 1)), dim3(IMF_INV_NTH), sm, s, a, fz, twz, GX,
+                       a.py);
   });
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (stage < 0 || stage == 1) DISPATCH(fy.n, {
     strided_io io{a.w1, a.w1_stride, (long long)a.py * h, h,
                   a.w2, a.w2_stride, (long long)a.max_my * h, h, h};
     const size_t sm = smem_bytes(fy.n, CT);
-    auto k = k_pass_strided<CT, MAXE, NT, PASS_INV_Y>;
+    auto k = k_pass_strided<CT, MAXE, NT, PASS_INV_Y, IMF_INV_NTH>;
     if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
     const int GX = (h + CT - 1) / CT;
-    hipLaunchKernelGGL(k, dim3(xcd_grid(GX, a.max_mz, a.nq)), dim3(IMF_WG), sm, s, io, fy, twy,
+    hipLaunchKernelGGL(k, dim3(xcd_grid(GX, a.max_mz, a.nq)), dim3(IMF_INV_NTH), sm, s, io, fy, twy,
                        a.desc, 0, a.py, 0, 1, GX, a.max_mz, a.nq);
   });
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (stage < 0 || stage == 2) DISPATCH(fx.n, {
     const size_t sm = smem_bytes(fx.n, CT);
-    auto k = k_inv_x_c2r<CT, MAXE, NT>;
+    auto k = k_inv_x_c2r<CT, MAXE, NT, IMF_INV_NTH>;
     if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
     const long long rows = (long long)a.max_my * a.max_mz;
     hipLaunchKernelGGL(k, dim3((unsigned)((rows + 2 * CT - 1) / (2 * CT)), 1, a.nq),
-                       dim3(IMF_WG), sm, s, a, fx, twx);
+                       dim3(IMF_INV_NTH), sm, s, a, fx, twx);
   });
   return hipGetLastError();
 }
