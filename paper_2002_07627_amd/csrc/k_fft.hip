@@ -445,8 +445,8 @@ __global__ void __launch_bounds__(NTH) k_pass_strided(strided_io io, imf_fft_len
 // (3) forward z pass: strided input (plane stride), contiguous output columns
 //     out[ky][kx][kz].  The tile is CT consecutive kx at one ky.
 // ---------------------------------------------------------------------------
-template <int CT, int MAXE, int NT, int TOOL>
-__global__ void __launch_bounds__(IMF_WG) k_pass_z_fwd(const float2* __restrict__ in,
+template <int CT, int MAXE, int NT, int TOOL, int NTH = IMF_WG>
+__global__ void __launch_bounds__(NTH) k_pass_z_fwd(const float2* __restrict__ in,
                                                        long long in_q, long long in_j,
                                                        float2* __restrict__ out, int h,
                                                        int n_in_fixed, imf_fft_len L,
@@ -471,7 +471,7 @@ __global__ void __launch_bounds__(IMF_WG) k_pass_z_fwd(const float2* __restrict_
   const int c0 = bx * CT;
   // element (j, ky, kx) of the input at j * in_j + ky * h + kx
   const float2* src = in + q * in_q + (long long)ky * h + c0;
-  for (int i = threadIdx.x; i < CT * n; i += IMF_WG) {
+  for (int i = threadIdx.x; i < CT * n; i += NTH) {
     const int j = i / CT, c = i - j * CT;
     float2 v = make_float2(0.f, 0.f);
     if (j < n_in && c0 + c < h) v = src[j * in_j + c];
@@ -480,10 +480,10 @@ __global__ void __launch_bounds__(IMF_WG) k_pass_z_fwd(const float2* __restrict_
     X[LIDX(pos, c)] = v;
   }
   __syncthreads();
-  fft_tile<CT, MAXE, NT>(X, tw, L, false);
+  fft_tile<CT, MAXE, NT, NTH>(X, tw, L, false);
   float2* dst = obase + ((long long)ky * h + c0) * n;
   const int ncol = min(CT, h - c0);
-  for (int i = threadIdx.x; i < ncol * n; i += IMF_WG) {
+  for (int i = threadIdx.x; i < ncol * n; i += NTH) {
     const int c = i / n, k = i - c * n;
     dst[(long long)c * n + k] = X[LIDX(k, c)];
   }
@@ -742,9 +742,9 @@ __global__ void __launch_bounds__(NTH) k_inv_x_c2r(imf_inv_args a, imf_fft_len L
     }                                                      \
   } while (0)
 
-// threads per workgroup of the inverse passes (the per-request hot transforms):
-// twice the default, so each thread keeps half the butterflies in registers
-// and a CU holds more waves to hide HBM latency
+// threads per workgroup of the per-orientation passes (tool spectra and the
+// inverse transform): twice the default, so each thread keeps half the
+// butterflies in registers and a CU holds more waves to hide HBM latency
 #ifndef IMF_INV_NTH
 #define IMF_INV_NTH 512
 #endif
@@ -813,19 +813,19 @@ hipError_t imf_launch_tool_fft(const imf_tool_fft_args& a, const imf_fft_len& fy
     strided_io io{a.work1, a.w1_stride, (long long)a.max_ty * h, h,
                   a.work2, a.w2_stride, (long long)a.py * h, h, h};
     const size_t sm = smem_bytes(fy.n, CT);
-    auto k = k_pass_strided<CT, MAXE, NT, PASS_TOOL_Y>;
+    auto k = k_pass_strided<CT, MAXE, NT, PASS_TOOL_Y, IMF_INV_NTH>;
     if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
     const int GX = (h + CT - 1) / CT;
-    hipLaunchKernelGGL(k, dim3(xcd_grid(GX, a.max_tz, a.nq)), dim3(IMF_WG), sm, s, io, fy, twy,
+    hipLaunchKernelGGL(k, dim3(xcd_grid(GX, a.max_tz, a.nq)), dim3(IMF_INV_NTH), sm, s, io, fy, twy,
                        a.desc, 0, 0, a.py, 0, GX, a.max_tz, a.nq);
   });
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (stage < 0 || stage == 2) DISPATCH(fz.n, {
     const size_t sm = smem_bytes(fz.n, CT);
-    auto k = k_pass_z_fwd<CT, MAXE, NT, 1>;
+    auto k = k_pass_z_fwd<CT, MAXE, NT, 1, IMF_INV_NTH>;
     if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
     const int GX = (h + CT - 1) / CT;
-    hipLaunchKernelGGL(k, dim3(xcd_grid(GX, a.py, a.nq)), dim3(IMF_WG), sm, s, a.work2,
+    hipLaunchKernelGGL(k, dim3(xcd_grid(GX, a.py, a.nq)), dim3(IMF_INV_NTH), sm, s, a.work2,
                        a.w2_stride, (long long)a.py * h, (float2*)nullptr, h, 0, fz, twz, a.desc,
                        0LL, GX, a.py, a.nq);
   });
