@@ -135,6 +135,7 @@ struct OrientEntry {
   int sv[3];        // lattice vector of the sharp-point runs
   int maxlen;       // longest sharp-point run
   int n_pow2;       // the first n_pow2 sharp-point runs have power-of-two lengths
+  unsigned lvl_used;  // bit s-1: some sharp-point run reads sparse-table level s
   const imf_run* truns;
   const imf_run* sruns;
   const imf_run* sxruns;
@@ -801,6 +802,11 @@ static imf_status ensure_rasters(imf_ctx* c, const imf_request* r, const std::ve
         return p.z != q.z ? p.z < q.z : (p.y != q.y ? p.y < q.y : p.x < q.x);
       });
       e.n_pow2 = (int)std::count_if(one.begin(), one.end(), pow2);
+      // a run of length l reads level floor(log2 l) only; the level passes
+      // skip the stores of levels no run reads
+      e.lvl_used = 0;
+      for (const imf_run& u : one)
+        if (u.len >= 2) e.lvl_used |= 1u << (30 - __builtin_clz((unsigned)u.len));
       voff[i] = (long long)vall.size();
       vall.insert(vall.end(), one.begin(), one.end());
     }
@@ -956,6 +962,7 @@ static imf_status make_plan(imf_ctx* c, const imf_request* r, const imf_outputs*
     for (int a = 0; a < 3; a++) d.sv[a] = e.sv[a];
     d.n_sruns = e.ext[16];
     d.n_sruns1 = e.n_pow2;
+    d.lvl_used = e.lvl_used;
     d.n_truns = e.ext[15];
     d.sruns = e.sruns;
     d.truns = e.truns;

@@ -95,6 +95,7 @@ struct imf_orient_desc {
   int n_truns;         // number of tool x-runs
   int tlo[3], tdim[3]; // bounding box of the tool raster (offsets)
   int nlvl;            // sparse-table levels this orientation's runs need
+  unsigned lvl_used;   // bit s-1 set: some run reads level s (others are not stored)
   int out_q;           // index of the orientation in the request (masks, gamma stack)
   const imf_run* sruns;  // sharp-point runs along sv (x-runs for the sweep route)
   const imf_run* truns;  // x-runs of the tool T, row order (z, y)

@@ -171,7 +171,9 @@ hipError_t imf_launch_recheck(const imf_orient_desc* desc, const long long* ps, 
 // sharp-point minimum (Eq. imf_2): gamma(x) = min over runs of S of the window
 // minimum of g along the run axis.  Level s of the sparse table holds
 // min g[p, p + 2^s) along the axis; a run of length l reads two level-s
-// windows, s = floor(log2 l).
+// windows, s = floor(log2 l).  Levels between 1 and the highest are formed
+// for the recurrence but stored only where some run of the orientation reads
+// them (lvl_used of the descriptor).
 // ---------------------------------------------------------------------------
 // All sparse-table levels of one orientation in one pass: lines along the run
 // axis are staged in LDS (ping-pong), each level is formed there and written
@@ -247,7 +249,7 @@ __global__ void __launch_bounds__(IMF_WG) k_levels(const imf_orient_desc* __rest
       B[l * m + i] = v;
       bool ok;
       const long long gi = index_of(l, i, ok);
-      if (ok) dst[gi] = v;
+      if (ok && ((d.lvl_used >> (s - 1)) & 1u)) dst[gi] = v;
     }
     __syncthreads();
     float* tmp = A;
@@ -266,7 +268,8 @@ __global__ void __launch_bounds__(IMF_WG) k_levels(const imf_orient_desc* __rest
 template <int NL>
 __device__ __forceinline__ void levels_stream_line(const float* __restrict__ src,
                                                    float* __restrict__ dst, long long g_stride,
-                                                   int m, long long sa, long long base, bool ok) {
+                                                   int m, long long sa, long long base, bool ok,
+                                                   unsigned used) {
   constexpr int U = 1 << (NL - 1);
   float D[(1 << NL) - 1];  // level s - 1 delays at [2^(s-1) - 1, 2^s - 1)
 #pragma unroll
@@ -289,7 +292,8 @@ __device__ __forceinline__ void levels_stream_line(const float* __restrict__ src
         const float prev = D[slot];
         D[slot] = v;
         v = fminf(v, prev);
-        if (ok && i < m) dst[(long long)(s - 1) * g_stride + base + (long long)i * sa] = v;
+        if (((used >> (s - 1)) & 1u) && ok && i < m)
+          dst[(long long)(s - 1) * g_stride + base + (long long)i * sa] = v;
       }
     }
   }
@@ -317,13 +321,14 @@ __global__ void __launch_bounds__(IMF_WG) k_levels_stream(const imf_orient_desc*
   const int m = d.box_dim[ax];
   const float* src = g + q * g_stride;
   float* dst = lvl + q * lvl_stride;
+  const unsigned used = d.lvl_used;
   switch (nl_q) {
-    case 1: levels_stream_line<1>(src, dst, g_stride, m, sa, base, ok); break;
-    case 2: levels_stream_line<2>(src, dst, g_stride, m, sa, base, ok); break;
-    case 3: levels_stream_line<3>(src, dst, g_stride, m, sa, base, ok); break;
-    case 4: levels_stream_line<4>(src, dst, g_stride, m, sa, base, ok); break;
-    case 5: levels_stream_line<5>(src, dst, g_stride, m, sa, base, ok); break;
-    default: levels_stream_line<6>(src, dst, g_stride, m, sa, base, ok); break;
+    case 1: levels_stream_line<1>(src, dst, g_stride, m, sa, base, ok, used); break;
+    case 2: levels_stream_line<2>(src, dst, g_stride, m, sa, base, ok, used); break;
+    case 3: levels_stream_line<3>(src, dst, g_stride, m, sa, base, ok, used); break;
+    case 4: levels_stream_line<4>(src, dst, g_stride, m, sa, base, ok, used); break;
+    case 5: levels_stream_line<5>(src, dst, g_stride, m, sa, base, ok, used); break;
+    default: levels_stream_line<6>(src, dst, g_stride, m, sa, base, ok, used); break;
   }
 }
 
@@ -359,7 +364,8 @@ __global__ void __launch_bounds__(IMF_WG) k_levels_x(const imf_orient_desc* __re
       const float xb = __shfl(bb, src_lane);
       a = fminf(a, lane + h < 64 ? xa : xb);
       bb = fminf(bb, lane + h < 64 ? xb : INFINITY);  // valid where it is used
-      if (c + lane < mx) dst[(long long)(s - 1) * g_stride + c + lane] = a;
+      if (((d.lvl_used >> (s - 1)) & 1u) && c + lane < mx)
+        dst[(long long)(s - 1) * g_stride + c + lane] = a;
     }
   }
 }
@@ -389,7 +395,7 @@ template <int NL>
 __device__ __forceinline__ void levels_vstream_line(const float* __restrict__ src,
                                                     float* __restrict__ dst, long long g_stride,
                                                     long long idx0, long long step, int wlo,
-                                                    int whi, int llo, int lhi) {
+                                                    int whi, int llo, int lhi, unsigned used) {
   constexpr int U = 1 << (NL - 1);
   float D[(1 << NL) - 1];
 #pragma unroll
@@ -413,7 +419,8 @@ __device__ __forceinline__ void levels_vstream_line(const float* __restrict__ sr
         const float prev = D[slot];
         D[slot] = v;
         v = fminf(v, prev);
-        if (ok) dst[(long long)(s - 1) * g_stride + idx0 + (long long)i * step] = v;
+        if (((used >> (s - 1)) & 1u) && ok)
+          dst[(long long)(s - 1) * g_stride + idx0 + (long long)i * step] = v;
       }
     }
   }
@@ -463,13 +470,14 @@ __global__ void __launch_bounds__(IMF_WG) k_levels_vstream(const imf_orient_desc
   const long long step = v[0] + (long long)dim[0] * (v[1] + (long long)dim[1] * v[2]);
   const float* src = g + q * g_stride;
   float* dst = lvl + q * lvl_stride;
+  const unsigned used = d.lvl_used;
   switch (nl_q) {
-    case 1: levels_vstream_line<1>(src, dst, g_stride, idx0, step, wlo, whi, lo, hi); break;
-    case 2: levels_vstream_line<2>(src, dst, g_stride, idx0, step, wlo, whi, lo, hi); break;
-    case 3: levels_vstream_line<3>(src, dst, g_stride, idx0, step, wlo, whi, lo, hi); break;
-    case 4: levels_vstream_line<4>(src, dst, g_stride, idx0, step, wlo, whi, lo, hi); break;
-    case 5: levels_vstream_line<5>(src, dst, g_stride, idx0, step, wlo, whi, lo, hi); break;
-    default: levels_vstream_line<6>(src, dst, g_stride, idx0, step, wlo, whi, lo, hi); break;
+    case 1: levels_vstream_line<1>(src, dst, g_stride, idx0, step, wlo, whi, lo, hi, used); break;
+    case 2: levels_vstream_line<2>(src, dst, g_stride, idx0, step, wlo, whi, lo, hi, used); break;
+    case 3: levels_vstream_line<3>(src, dst, g_stride, idx0, step, wlo, whi, lo, hi, used); break;
+    case 4: levels_vstream_line<4>(src, dst, g_stride, idx0, step, wlo, whi, lo, hi, used); break;
+    case 5: levels_vstream_line<5>(src, dst, g_stride, idx0, step, wlo, whi, lo, hi, used); break;
+    default: levels_vstream_line<6>(src, dst, g_stride, idx0, step, wlo, whi, lo, hi, used); break;
   }
 }
 
