@@ -1,0 +1,87 @@
+"""GPU parity on degenerate grids: one- and two-voxel-thick slabs, a single
+voxel, and a row that crosses a 64-voxel mask word, through both correlation
+routes, against the CPU oracle (binary: bit-exact; density: the per-voxel
+tolerance of the parity suite)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(1, 9, 70), (3, 1, 5), (2, 2, 2), (1, 1, 1), (6, 1, 1)]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2002_07627_amd as imf
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = imf.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def thin_design(shape, seed):
+    rng = np.random.default_rng(seed)
+    return (rng.random(shape) < 0.3).astype(np.uint8)
+
+
+@pytest.mark.parametrize("method", ["fft", "direct"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_thin_grids_binary_bit_exact(ctx, shape, method):
+    import paper_2002_07627_amd as imf
+    d = thin_design(shape, 7627100 + sum(shape))
+    fx = np.zeros(shape, np.uint8)
+    fx[0, 0, 0] = 1  # one fixture voxel (outside the design domain)
+    tl = W.tool(W.TOOL_BALL, 1.5, 5, 2.5, 4)
+    dirs = W.lattice26()
+    m = imf.METHOD_FFT if method == "fft" else imf.METHOD_DIRECT
+    print("thin binary", shape, method, flush=True)
+    out, _ = ctx.compute(dev(d), dev(fx), tools=tl, dirs=dirs, dir_kind=imf.DIR_LATTICE,
+                         method=m)
+    ref = oracle.imf(oracle.Request(d, fx, tools=tl, dirs=dirs, dir_kind=1))
+    f = host(out["imf"]).astype(np.float64)
+    assert np.array_equal(f, ref["imf"].reshape(f.shape))
+    assert np.array_equal(host(out["imf_norm"]), ref["imf_norm"].reshape(f.shape))
+    assert np.array_equal(host(out["secluded"]), ref["secluded"].reshape(f.shape))
+    mk = host(out["masks"]).view(np.uint64)
+    assert np.array_equal(mk, ref["masks"].reshape(mk.shape))
+
+
+@pytest.mark.parametrize("shape", [(1, 9, 70), (3, 1, 5)])
+def test_thin_grids_density_with_bound(shape, monkeypatch):
+    """The branch-and-bound pass on (its size threshold lifted) over slabs
+    thinner than one block."""
+    import paper_2002_07627_amd as imf
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rng = np.random.default_rng(7627200 + sum(shape))
+    d = W.quantize_q24(rng.random(shape).astype(np.float32))
+    tl = W.tool(W.TOOL_BALL, 1.5, 5, 2.5, 4)
+    dirs = W.fib_hemisphere(12)
+    lam = 0.05
+    print("thin density", shape, flush=True)
+    monkeypatch.setenv("IMF_BOUND_MIN_VOXELS", "0")
+    c = imf.Context(0)
+    try:
+        out, st = c.compute(dev(d), tools=tl, dirs=dirs, dir_kind=imf.DIR_F64, lam=lam,
+                            method=imf.METHOD_FFT)
+    finally:
+        c.close()
+    assert st.bound_blocks > 0
+    ref = oracle.imf(oracle.Request(d, None, tools=tl, dirs=dirs, dir_kind=0, lam=lam))
+    f = host(out["imf"]).astype(np.float64)
+    fr = ref["imf"].reshape(f.shape)
+    tol = 1e-4 * np.maximum(np.abs(fr), lam * ref["F_max"])
+    assert np.all(np.abs(f - fr) <= tol)
