@@ -793,12 +793,37 @@ static imf_status ensure_rasters(imf_ctx* c, const imf_request* r, const std::ve
       } else {
         one.assign(ar, ar + e.ext[16]);
       }
-      // runs of power-of-two length first (their two windows coincide: one
-      // lookup), each part in (z, y, x) order of the first point so that
-      // neighbouring runs read neighbouring cache lines
+      // A run of length l is read as two windows of the sparse-table level
+      // s = floor(log2 l) (one when l = 2^s).  Each window is itself a run of
+      // S (min is idempotent, so the overlap is harmless): splitting every
+      // run into its windows leaves runs of power-of-two length only, one
+      // lookup each, which are then ordered by level and by first point
+      // (z, y, x), so that consecutive lookups of the gather loop read the
+      // same level array at neighbouring lines.  Kept whole if the windows
+      // would not fit the minimum pass's LDS staging.
       auto pow2 = [](const imf_run& u) { return (u.len & (u.len - 1)) == 0; };
+      auto level = [](const imf_run& u) { return 31 - __builtin_clz((unsigned)u.len); };
+      {
+        size_t nwin = 0;
+        for (const imf_run& u : one) nwin += pow2(u) ? 1 : 2;
+        if (nwin <= (size_t)IMF_MF_LDS_RUNS && nwin > one.size()) {
+          std::vector<imf_run> win;
+          win.reserve(nwin);
+          for (const imf_run& u : one) {
+            const int w = 1 << level(u);
+            win.push_back(imf_run{u.x, u.y, u.z, w});
+            if (w != u.len) {
+              const int sh = u.len - w;
+              win.push_back(imf_run{u.x + sh * e.sv[0], u.y + sh * e.sv[1], u.z + sh * e.sv[2], w});
+            }
+          }
+          one.swap(win);
+          e.ext[16] = (int)one.size();
+        }
+      }
       std::sort(one.begin(), one.end(), [&](const imf_run& p, const imf_run& q) {
         if (pow2(p) != pow2(q)) return pow2(p);
+        if (level(p) != level(q)) return level(p) < level(q);
         return p.z != q.z ? p.z < q.z : (p.y != q.y ? p.y < q.y : p.x < q.x);
       });
       e.n_pow2 = (int)std::count_if(one.begin(), one.end(), pow2);

@@ -6,6 +6,9 @@
 
 #define IMF_MAX_RUNS_PER_ROW 4
 #define IMF_WG 256
+// sharp-point runs the minimum pass stages in LDS per workgroup (the rest are
+// read from memory one by one)
+#define IMF_MF_LDS_RUNS 1024
 
 // A run of voxels of an oriented tool raster: offsets start + j * e (e a
 // coordinate axis, or for the sharp-point runs the lattice vector sv of the

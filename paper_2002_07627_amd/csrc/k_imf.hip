@@ -634,7 +634,7 @@ __global__ void k_fill_u32(unsigned int* p, long long n, unsigned int v) {
 // close in space, so the waves one XCD runs at a time read overlapping windows
 // of g and its levels from that XCD's L2.
 // ---------------------------------------------------------------------------
-#define MF_LDS_RUNS 1024
+#define MF_LDS_RUNS IMF_MF_LDS_RUNS
 #ifndef MF_GRP
 // runs per group of the gather loop (a barrier per group when the waves go in
 // step): eight 16 x 2 x 2 blocks gathering 4 runs touch ~160 lines, within the
