@@ -209,7 +209,7 @@ struct imf_ctx {
   unsigned int* couple_scratch = nullptr;  // device word for the coupling reductions
   int mf_shape = 2;  // wave block shape of the sharp-point minimum (imf_block_dims)
   int n_cu = 256;     // compute units of the device
-  int mf_wg_per_cu = 6;  // resident workgroups per CU of the sharp-point minimum (list pass)
+  int mf_wg_per_cu = 8;  // resident workgroups per CU of the sharp-point minimum (list pass)
   // grids below this many voxels skip the branch and bound: its three short
   // launches per orientation cost more than the blocks they save
   long long bound_min_voxels = 1000000;
@@ -879,7 +879,7 @@ struct Plan {
   bool theta_known, two_phase, masks, sweep, cache, bnb;
   int shape;
   long long cell_stride, nblocks, cell_waves, nwords_blk;
-  int tuned_batch = 8, tuned_shape = 2, wg_per_cu = 6;  // launch parameters in effect
+  int tuned_batch = 8, tuned_shape = 2, wg_per_cu = 8;  // launch parameters in effect
   // batches: orientations [bstart[b], bstart[b+1]), all seeing fixture set bset[b]
   // (0 without fixture sets); at most B wide, split wherever the set changes
   std::vector<int> bstart, bset;
