@@ -31,15 +31,34 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# kernel instances this run launched, per class whose instance depends on the
+# launch configuration (set once the block shape in effect is known)
+RUN_KERNELS = {}
+
+
+def minfilter_kernels(shape):
+    """Template instances of the sharp-point minimum's list pass and its bound
+    for a block shape, with the default eight waves in step (None otherwise)."""
+    if os.environ.get("IMF_MINFILTER_SYNC", "2") != "2":
+        return {"minfilter": None, "bound": None}
+    wx, wy, wz = {1: (32, 2, 1), 2: (16, 2, 2), 3: (16, 4, 1)}.get(shape, (64, 1, 1))
+    return {"minfilter": ["void k_minfilter_list<%d, %d, %d, true, 8>" % (wx, wy, wz)],
+            "bound": ["void k_bound<%d, %d, %d>" % (wx, wy, wz), "k_scan_masks",
+                      "void k_scatter<%d, %d, %d>" % (wx, wy, wz)]}
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed FETCH_SIZE / WRITE_SIZE
-    summary, or None when the kernel's source changed since it was measured."""
+    summary, or None when the kernel's source changed since it was measured or
+    the summary covers another instance than the one this run launched."""
     import hashlib
     f = os.path.join(ROOT, "profiles", "traffic_c3_256x130.json")
     if not os.path.exists(f):
         return None
     e = json.load(open(f)).get(kernel)
     if not e:
+        return None
+    if kernel in RUN_KERNELS and RUN_KERNELS[kernel] != e.get("kernels"):
         return None
     src = os.path.join(ROOT, e["source"])
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != e["sha256"]:
@@ -254,6 +273,7 @@ def main():
         log("  %-14s %8.2f ms/step  %5.1f launches  %s GB/s" %
             (k, v["ms_per_step"], v["launches_per_step"],
              "%.0f" % v["GBps"] if v["GBps"] else "-"))
+    RUN_KERNELS.update(minfilter_kernels(stats[-1].mf_shape))
     roofline = roofline_of(dom, kms, kn, kb, ko)
     # measured HBM traffic of the whole request: per-launch FETCH + WRITE bytes
     # of the committed counter runs times this run's launches, for the kernel
