@@ -85,3 +85,24 @@ def test_thin_grids_density_with_bound(shape, monkeypatch):
     fr = ref["imf"].reshape(f.shape)
     tol = 1e-4 * np.maximum(np.abs(fr), lam * ref["F_max"])
     assert np.all(np.abs(f - fr) <= tol)
+
+
+@pytest.mark.parametrize("radius", [13, 19])
+def test_wide_cutter_run_lists_beyond_the_staging(ctx, radius):
+    """A ball cutter so wide that its sharp-point windows (radius 13: about
+    1000 runs' windows) or even its runs (radius 19: about 1130) outnumber the
+    1024 entries the minimum pass stages in LDS: the run lists stay whole and
+    the surplus runs are read from memory one by one."""
+    import paper_2002_07627_amd as imf
+    rng = np.random.default_rng(7627300 + radius)
+    d = (rng.random((8, 12, 18)) < 0.25).astype(np.uint8)
+    tl = W.tool(W.TOOL_BALL, radius, radius, 2, 2)  # the ball alone cuts
+    dirs = np.array([[0, 0, 1], [1, 0, 0], [0, -1, 0]], np.int32)
+    print("wide cutter r", radius, flush=True)
+    out, _ = ctx.compute(dev(d), tools=tl, dirs=dirs, dir_kind=imf.DIR_LATTICE,
+                         method=imf.METHOD_FFT)
+    ref = oracle.imf(oracle.Request(d, None, tools=tl, dirs=dirs, dir_kind=1))
+    f = host(out["imf"]).astype(np.float64)
+    assert np.array_equal(f, ref["imf"].reshape(f.shape))
+    mk = host(out["masks"]).view(np.uint64)
+    assert np.array_equal(mk, ref["masks"].reshape(mk.shape))
