@@ -637,8 +637,10 @@ __global__ void k_fill_u32(unsigned int* p, long long n, unsigned int v) {
 #define MF_LDS_RUNS IMF_MF_LDS_RUNS
 #ifndef MF_GRP
 // runs per group of the gather loop (a barrier per group when the waves go in
-// step): eight 16 x 2 x 2 blocks gathering 4 runs touch ~160 lines, within the
-// 256 lines of the L1, so the later waves of a group still find them there
+// step), i.e. 8 gathers: two windows per run, or 2 * MF_GRP runs of
+// power-of-two length (the host splits runs into such windows).  Eight
+// 16 x 2 x 2 blocks making 8 gathers touch ~160 lines, within the 256 lines of
+// the L1, so the later waves of a group still find them there
 #define MF_GRP 4
 #endif
 struct mf_run {
