@@ -41,7 +41,7 @@ def minfilter_kernels(shape):
     for a block shape, with the default eight waves in step (None otherwise)."""
     if os.environ.get("IMF_MINFILTER_SYNC", "2") != "2":
         return {"minfilter": None, "bound": None}
-    wx, wy, wz = {1: (32, 2, 1), 2: (16, 2, 2), 3: (16, 4, 1)}.get(shape, (64, 1, 1))
+    wx, wy, wz = {1: (32, 2, 1), 2: (16, 2, 2), 3: (16, 4, 1), 4: (8, 4, 2)}.get(shape, (64, 1, 1))
     return {"minfilter": ["void k_minfilter_list<%d, %d, %d, true, 8>" % (wx, wy, wz)],
             "bound": ["void k_bound<%d, %d, %d>" % (wx, wy, wz), "k_scan_masks",
                       "void k_scatter<%d, %d, %d>" % (wx, wy, wz)]}

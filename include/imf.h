@@ -201,8 +201,9 @@ imf_status imf_cancel(imf_ctx* ctx, uint64_t ticket);
 
 /* Autotune a request shape (method, grid, transform sizes) on a real request:
  * time candidate batch widths, then block shapes (64x1x1, 32x2x1, 16x2x2,
- * 16x4x1) and resident workgroups per CU (4, 6, 8) of the sharp-point minimum,
- * each kernel by kernel after a warm-up, and remember the fastest; later
+ * 16x4x1, 8x4x2) and resident workgroups per CU (4, 6, 8) of the sharp-point
+ * minimum, each kernel by kernel after a warm-up, and remember the fastest
+ * (another shape replaces the default only when 2% faster); later
  * requests of that shape with batch = 0 use it.  Results do not depend on the
  * choice.  *best_batch receives the batch width. */
 imf_status imf_autotune(imf_ctx* ctx, const imf_request* req, const imf_outputs* out,

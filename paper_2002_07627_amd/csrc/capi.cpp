@@ -287,7 +287,8 @@ extern "C" imf_status imf_create(int device, size_t hbm_budget_bytes, imf_ctx** 
   imf_ctx* c = new imf_ctx();
   c->device = device;
   c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)fr);
-  if (const char* e = std::getenv("IMF_MINFILTER_SHAPE")) c->mf_shape = std::atoi(e) & 3;
+  if (const char* e = std::getenv("IMF_MINFILTER_SHAPE"))
+    c->mf_shape = std::max(0, std::min(4, std::atoi(e)));
   c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
   if (const char* e = std::getenv("IMF_BOUND_MIN_VOXELS")) c->bound_min_voxels = std::atoll(e);
   if (const char* e = std::getenv("IMF_AXIS_RUNS")) c->lattice_runs = std::atoi(e) == 0;
@@ -2173,7 +2174,7 @@ extern "C" imf_status imf_autotune(imf_ctx* c, const imf_request* r, const imf_o
   // alternative must win by 2% (timings of near-equal settings flip with
   // noise, and a stable choice keeps profiles of one setting comparable)
   if (p0.nd == 3)
-    for (int shape : {2, 0, 1, 3})
+    for (int shape : {2, 4, 0, 1, 3})
       for (int wg : {4, 6, 8}) {
         if (shape == best.shape && wg == best.wg) continue;
         double ms;
@@ -2225,7 +2226,7 @@ extern "C" imf_status imf_autotune_load(imf_ctx* c, const char* path, int* n_loa
         line[used] != '\0' ||
         std::sscanf(key, "%d|%d,%d,%d|%d,%d,%d", &m, &n[0], &n[1], &n[2], &P[0], &P[1], &P[2]) !=
             7 ||
-        batch < 1 || batch > 64 || shape < -1 || shape > 3 || wg < 0 || wg > 16) {
+        batch < 1 || batch > 64 || shape < -1 || shape > 4 || wg < 0 || wg > 16) {
       st = fail(IMF_EINVAL, "%s:%d: malformed autotune entry", path, ln);
       break;
     }

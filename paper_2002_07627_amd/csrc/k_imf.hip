@@ -488,6 +488,7 @@ void imf_block_dims(int shape, int& wx, int& wy, int& wz) {
     case 1: wx = 32; wy = 2; wz = 1; break;
     case 2: wx = 16; wy = 2; wz = 2; break;
     case 3: wx = 16; wy = 4; wz = 1; break;
+    case 4: wx = 8; wy = 4; wz = 2; break;
     default: wx = 64; wy = 1; wz = 1; break;
   }
 }
@@ -593,21 +594,31 @@ __global__ void __launch_bounds__(IMF_WG) k_cellmin(const imf_orient_desc* __res
   const float* gq = g + q * g_stride;
   unsigned int* out = cellmin + q * cell_stride;
   const int y0 = cy * WY;
-  // all rows of the CM_CZ cell planes first (up to 4 rows per cell: WY * WZ
-  // <= 4 for every block shape), so the loads are in flight together
-  float v[CM_CZ][4];
+  // the rows of a cell (WY * WZ <= 8 for every block shape) four at a time,
+  // those of the CM_CZ cell planes together, so the loads are in flight
+  // together
+  float mm[CM_CZ];
 #pragma unroll
-  for (int c = 0; c < CM_CZ; c++)
+  for (int c = 0; c < CM_CZ; c++) mm[c] = INFINITY;
+  for (int r0 = 0; r0 < WY * WZ; r0 += 4) {
+    float v[CM_CZ][4];
 #pragma unroll
-    for (int r = 0; r < 4; r++) {
-      const int cz = cz0 + c, z = cz * WZ + r / WY, y = y0 + r % WY;
-      const bool ok = r < WY * WZ && cz < cdz && z < mz && y < my && x < mx;
-      v[c][r] = ok ? gq[((long long)z * my + y) * mx + x] : INFINITY;
-    }
+    for (int c = 0; c < CM_CZ; c++)
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        const int rr = r0 + r;
+        const int cz = cz0 + c, z = cz * WZ + rr / WY, y = y0 + rr % WY;
+        const bool ok = rr < WY * WZ && cz < cdz && z < mz && y < my && x < mx;
+        v[c][r] = ok ? gq[((long long)z * my + y) * mx + x] : INFINITY;
+      }
+#pragma unroll
+    for (int c = 0; c < CM_CZ; c++)
+      mm[c] = fminf(mm[c], fminf(fminf(v[c][0], v[c][1]), fminf(v[c][2], v[c][3])));
+  }
 #pragma unroll
   for (int c = 0; c < CM_CZ; c++) {
     const int cz = cz0 + c;
-    float m = fminf(fminf(v[c][0], v[c][1]), fminf(v[c][2], v[c][3]));
+    float m = mm[c];
     for (int o = 1; o < WX; o <<= 1) m = fminf(m, __shfl_xor(m, o));
     if ((lane % WX) == 0 && cx < cdx && cz < cdz)
       out[((long long)cz * cdy + cy) * cdx + cx] = f2ord(m);
@@ -693,7 +704,8 @@ template <int WX>
 __device__ __forceinline__ void mf_store_chunk(uint64_t* row_words, int bx, uint64_t chunk) {
   if (WX == 64) row_words[bx] = chunk;
   else if (WX == 32) ((uint32_t*)row_words)[bx] = (uint32_t)chunk;
-  else ((uint16_t*)row_words)[bx] = (uint16_t)chunk;
+  else if (WX == 16) ((uint16_t*)row_words)[bx] = (uint16_t)chunk;
+  else ((uint8_t*)row_words)[bx] = (uint8_t)chunk;
 }
 
 // max over the block maxima of f (an upper bound of F_max: the threshold
@@ -1122,6 +1134,7 @@ hipError_t imf_launch_minfilter(const imf_min_args& a, hipStream_t s, int stage,
         case 1: e = launch_mf<32, 2, 1>(a, s, part, qi); break;
         case 2: e = launch_mf<16, 2, 2>(a, s, part, qi); break;
         case 3: e = launch_mf<16, 4, 1>(a, s, part, qi); break;
+        case 4: e = launch_mf<8, 4, 2>(a, s, part, qi); break;
         default: e = launch_mf<64, 1, 1>(a, s, part, qi); break;
       }
       if (e != hipSuccess) return e;

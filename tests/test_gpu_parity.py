@@ -295,7 +295,7 @@ def _bound_case():
 
 
 @pytest.mark.parametrize("mode", ["zero", "abs", "two_phase"])
-@pytest.mark.parametrize("shape", [0, 1, 2, 3])
+@pytest.mark.parametrize("shape", [0, 1, 2, 3, 4])
 def test_bound_every_block_shape(shape, mode, monkeypatch):
     import paper_2002_07627_amd as imf
     if not torch.cuda.is_available():
@@ -320,6 +320,27 @@ def test_bound_every_block_shape(shape, mode, monkeypatch):
         assert torch.equal(a[k], b[k]), k
     assert sa.bound_blocks > 0 and sb.bound_blocks == 0
     assert 0 < sa.bound_skipped < sa.bound_blocks
+
+
+@pytest.mark.parametrize("shape", [2, 4])
+def test_bound_direct_route_cell_minima(shape, monkeypatch):
+    """The direct correlation route computes the bound's cell minima in a pass
+    of its own (cells of up to 8 rows for the 8 x 4 x 2 blocks)."""
+    import paper_2002_07627_amd as imf
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    d, fx, tl, dirs = _bound_case()
+    if "zero" not in _BND_REF:
+        _BND_REF["zero"] = oracle.imf(oracle.Request(d, fx, tools=tl, dirs=dirs, dir_kind=0))
+    monkeypatch.setenv("IMF_MINFILTER_SHAPE", str(shape))
+    monkeypatch.setenv("IMF_BOUND_MIN_VOXELS", "0")
+    c = imf.Context(0)
+    try:
+        a, sa = c.compute(dev(d), dev(fx), tools=tl, dirs=dirs, method=imf.METHOD_DIRECT)
+    finally:
+        c.close()
+    check_binary(a, _BND_REF["zero"])
+    assert sa.mf_shape == shape and 0 < sa.bound_skipped < sa.bound_blocks
 
 
 def test_long_cutter_uses_more_than_six_levels(ctx):
