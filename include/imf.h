@@ -177,7 +177,7 @@ typedef struct {
   int lattice_runs;        /* orientations whose sharp points are split into runs along a
                               lattice vector other than a coordinate axis */
   int mf_shape;            /* block shape of the sharp-point minimum (0: 64x1x1, 1: 32x2x1,
-                              2: 16x2x2, 3: 16x4x1 voxels per wave) */
+                              2: 16x2x2, 3: 16x4x1, 4: 8x4x2 voxels per wave) */
   int mf_wg_per_cu;        /* resident workgroups per CU of its list pass */
 } imf_stats;
 
