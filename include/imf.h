@@ -181,15 +181,23 @@ typedef struct {
   int mf_wg_per_cu;        /* resident workgroups per CU of its list pass */
 } imf_stats;
 
-/* Bytes of device workspace the request needs (admission control). */
+/* Bytes of device workspace the request needs (admission control).  The
+ * workspace holds the fields of one batch of orientations, sized so that the
+ * batch fits the memory budget (App. B: the convolution fields of many
+ * orientations are processed in batches under a memory limit). */
 imf_status imf_query_footprint(imf_ctx* ctx, const imf_request* req, size_t* bytes);
-/* Compute the IMF, masks and secluded set of one request, stream-ordered on
- * `stream` (a hipStream_t, NULL = default); returns after completion. */
+/* Compute the IMF, masks and secluded set of one request (Algorithm 1 of
+ * Sec. 2.1.5: rotate, convolve, sharp-point minimum, minimum over orientations
+ * and tools, normalization and allowance; masks by Eqs. sweep / A),
+ * stream-ordered on `stream` (a hipStream_t, NULL = default); returns after
+ * completion. */
 imf_status imf_compute(imf_ctx* ctx, const imf_request* req, const imf_outputs* out,
                        imf_stats* stats, void* stream);
 
 /* -------------------------------------------------------------- serving -- */
-/* Enqueue a request; the library admits it when its footprint fits the budget
+/* The serving calls have no counterpart in the paper: they run imf_compute's
+ * work for requests of several callers (e.g. concurrent TO runs).
+ * Enqueue a request; the library admits it when its footprint fits the budget
  * and runs it on its own stream, overlapping with other admitted requests.
  * Host arrays of `req` are copied; device buffers must stay valid until wait. */
 imf_status imf_submit(imf_ctx* ctx, const imf_request* req, const imf_outputs* out,
@@ -217,7 +225,7 @@ imf_status imf_autotune(imf_ctx* ctx, const imf_request* req, const imf_outputs*
 imf_status imf_autotune_save(imf_ctx* ctx, const char* path);
 imf_status imf_autotune_load(imf_ctx* ctx, const char* path, int* n_loaded);
 
-/* ----------------------------------------- coupling to the TO loop (Sec. 3) -- */
+/* ----------------------------------------- coupling to the TO loop (Sec. 2.2) -- */
 /* Heaviside projection of the design variables (Eq. Heaviside):
  * rho = 1 - exp(-beta xi) + xi exp(-beta), in float64 with xi clamped to [0, 1],
  * then rounded to the nearest multiple of 2^-24 (halves up), so that rho can be
@@ -242,7 +250,7 @@ imf_status imf_access_filter(imf_ctx* ctx, int nx, int ny, int nz, const void* d
                              const uint8_t* secluded, double tau, const float* sens_phi,
                              double w_acc, float* filter_out, float* sens_out, void* stream);
 
-/* Greedy machining plan (Sec. 4, post-processing): starting from the negative
+/* Greedy machining plan (Sec. 3.4.1, post-processing): starting from the negative
  * space N = Omega_0 and [rho <= tau] (rho the design, Omega_0 as in a request),
  * repeatedly choose the orientation whose accessible mask covers the most of
  * what remains (ties: the lowest orientation index), remove that part, and stop

@@ -148,3 +148,76 @@ def imf(design, fixture, tool, dirs, lam=0.0, tau=0.5, scale=1, fixture_sets=Non
             "secluded": gamma_set.reshape(shp),
             "masks": np.stack([m.reshape(shp) for m in masks]),
             "gammas": np.stack([g.reshape(shp) for g in gammas])}
+
+
+def raster_exact_box(tool, v, lo, hi):
+    """Membership of every integer offset of the box [lo, hi] (inclusive, x, y, z)
+    for a lattice direction v, in exact integer arithmetic (numpy int64), with
+    the points where some boundary test of the predicate holds with equality.
+
+    Same definition as ``_in_tool``: a = o.v/|v|, q^2 = |o|^2 - a^2, every
+    comparison multiplied through by |v|^2 and by 4 so that half-integer sizes
+    stay integral.  Returns (T, K, tie) boolean arrays indexed [z][y][x]."""
+    v = [int(c) for c in v] + [0] * (3 - len(v))
+    zs, ys, xs = (np.arange(lo[a], hi[a] + 1, dtype=np.int64) for a in (2, 1, 0))
+    z, y, x = np.meshgrid(zs, ys, xs, indexing="ij")
+    dot = x * v[0] + y * v[1] + z * v[2]
+    n = v[0] * v[0] + v[1] * v[1] + v[2] * v[2]
+    o2 = x * x + y * y + z * z
+    r2, L2 = int(round(2 * tool["cutter_r"])), int(round(2 * tool["cutter_len"]))
+    rh2 = int(round(2 * tool["holder_r"]))
+    LH2 = int(round(2 * (tool["cutter_len"] + tool["holder_len"])))
+    assert abs(r2 - 2 * tool["cutter_r"]) < 1e-12 and abs(L2 - 2 * tool["cutter_len"]) < 1e-12
+    perp = 4 * (o2 * n - dot * dot)          # 4 q^2 |v|^2
+    ax = 4 * dot * dot                       # 4 a^2 |v|^2 (a >= 0 where dot >= 0)
+    pos = dot >= 0
+
+    def a_ge(c2):                            # a >= c for c = c2 / 2 >= 0
+        return pos & (ax >= c2 * c2 * n)
+
+    def a_lt(c2):                            # a < c for c = c2 / 2 > 0
+        return ~pos | (ax < c2 * c2 * n)
+
+    in_r = perp <= r2 * r2 * n
+    if tool["kind"] == 1:
+        ball = pos & (o2 * o2 * n <= r2 * r2 * dot * dot)
+        cut = ball | (a_ge(r2) & a_lt(L2) & in_r)
+    else:
+        cut = pos & a_lt(L2) & in_r
+    hold = a_ge(L2) & a_lt(LH2) & (perp <= rh2 * rh2 * n)
+    tie = (perp == r2 * r2 * n) | (perp == rh2 * rh2 * n) | (dot == 0)
+    for c2 in (L2, LH2) + ((r2,) if tool["kind"] == 1 else ()):
+        tie |= pos & (ax == c2 * c2 * n)
+    if tool["kind"] == 1:
+        tie |= pos & (o2 * o2 * n == r2 * r2 * dot * dot)
+    return cut | hold, cut, tie
+
+
+def raster_margin_box(tool, d, lo, hi, eps=1e-9):
+    """Membership of every integer offset of the box [lo, hi] (inclusive) for a
+    float64 unit direction d, evaluated in extended precision (numpy
+    longdouble) from the definitions a = o.d, q^2 = |o - a d|^2 and, for the
+    ball end, |o - r d|^2 <= r^2; plus the points where some boundary test is
+    within eps of equality (there the float64 raster may go either way).
+    Returns (T, K, near) boolean arrays indexed [z][y][x]."""
+    ld = np.longdouble
+    d = [ld(float(c)) for c in d] + [ld(0)] * (3 - len(d))
+    zs, ys, xs = (np.arange(lo[a], hi[a] + 1).astype(ld) for a in (2, 1, 0))
+    z, y, x = np.meshgrid(zs, ys, xs, indexing="ij")
+    a = x * d[0] + y * d[1] + z * d[2]
+    q2 = (x - a * d[0]) ** 2 + (y - a * d[1]) ** 2 + (z - a * d[2]) ** 2
+    r, L = ld(tool["cutter_r"]), ld(tool["cutter_len"])
+    rh, LH = ld(tool["holder_r"]), ld(tool["cutter_len"]) + ld(tool["holder_len"])
+    margins = [r * r - q2, rh * rh - q2, a, L - a, LH - a]
+    in_cyl = (a < L) & (q2 <= r * r)
+    if tool["kind"] == 1:
+        b2 = (x - r * d[0]) ** 2 + (y - r * d[1]) ** 2 + (z - r * d[2]) ** 2
+        margins += [r * r - b2, a - r]
+        cut = (b2 <= r * r) | ((a >= r) & in_cyl)
+    else:
+        cut = (a >= 0) & in_cyl
+    hold = (a >= L) & (a < LH) & (q2 <= rh * rh)
+    near = np.zeros(a.shape, bool)
+    for m in margins:
+        near |= np.abs(m) <= eps
+    return cut | hold, cut, near

@@ -1,5 +1,5 @@
 """TEST INFRASTRUCTURE ONLY: plain float64 oracle of the steps that couple the
-IMF to a density-based TO loop (Sec. 3 of the paper), written from their
+IMF to a density-based TO loop (Sec. 2.2 of the paper), written from their
 definitions:
 
 * Heaviside projection (Eq. Heaviside): rho = 1 - exp(-beta xi) + xi exp(-beta).
@@ -12,7 +12,7 @@ definitions:
   Sbar_phi the objective sensitivity divided by its maximum magnitude over
   Omega_0 (the paper says "normalized" without the norm; 0 when that maximum
   is 0).
-* Greedy machining plan (Sec. 4, post-processing): repeatedly the orientation
+* Greedy machining plan (Sec. 3.4.1, post-processing): repeatedly the orientation
   whose accessible set covers the most of the remaining negative space.
 
 Only the tests may import this module.
@@ -61,7 +61,7 @@ def filtered_sensitivity(sens_phi, filt, w: float, omega0) -> np.ndarray:
 
 
 def plan_greedy(masks_bool, design, tau: float = 0.5, omega0=None, max_steps=None):
-    """Greedy machining plan (Sec. 4): from the negative space
+    """Greedy machining plan (Sec. 3.4.1): from the negative space
     N = Omega_0 and [rho <= tau], repeatedly take the orientation whose
     accessible set covers the most of what remains (lowest index on ties),
     remove it, until nothing more is removable.  masks_bool: [n_orient, ...]

@@ -289,7 +289,7 @@ hipError_t imf_launch_masks_from_gamma(const float* gamma_stack, int nq, const u
                                        const unsigned long long* keep, int shape,
                                        long long kstride, hipStream_t s);
 
-// coupling to the TO loop (Sec. 3)
+// coupling to the TO loop (Sec. 2.2)
 hipError_t imf_launch_heaviside(const float* xi, long long n, double beta, float* rho,
                                 hipStream_t s);
 struct imf_couple_args {
@@ -302,7 +302,7 @@ struct imf_couple_args {
   unsigned int* smax;                    // device scratch: max |S_phi| over Omega_0
 };
 hipError_t imf_launch_access_filter(const imf_couple_args& a, hipStream_t s);
-// greedy machining plan (Sec. 4)
+// greedy machining plan (Sec. 3.4.1)
 hipError_t imf_launch_negative_bits(const void* design, int density, double tau,
                                     const uint8_t* fixture, const uint8_t* domain, int nx,
                                     long long rows, uint64_t* R, hipStream_t s);

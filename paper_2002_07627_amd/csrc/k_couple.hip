@@ -1,4 +1,4 @@
-// Steps that couple the IMF to a density-based TO loop (Sec. 3): the
+// Steps that couple the IMF to a density-based TO loop (Sec. 2.2): the
 // Heaviside projection of the design variables (Eq. Heaviside), the
 // accessibility filter (Eq. accFilter) and the filtered sensitivity
 // (Eq. filtered_sens).  Pointwise and HBM-bound; float64 arithmetic, compiled
@@ -104,7 +104,7 @@ hipError_t imf_launch_access_filter(const imf_couple_args& a, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Greedy machining plan (Sec. 4, post-processing): the negative space to
+// Greedy machining plan (Sec. 3.4.1, post-processing): the negative space to
 // remove, N = Omega_0 and [rho <= tau], as a bitset laid out like the masks;
 // per step the popcount of (A_q and R) for every orientation q, then
 // R = R and not A_q for the chosen one.

@@ -1,4 +1,4 @@
-"""Pins of the TO-coupling oracle (Sec. 3: Eqs. Heaviside, accFilter,
+"""Pins of the TO-coupling oracle (Sec. 2.2: Eqs. Heaviside, accFilter,
 filtered_sens) against closed forms, limits and hand-checked cases."""
 import math
 
@@ -92,3 +92,17 @@ def test_greedy_plan_invariants():
     # the removed counts sum to the reachable part and never increase
     assert sum(r for _, r in steps) == int(np.count_nonzero(N & A.any(0)))
     assert all(steps[i][1] >= steps[i + 1][1] for i in range(len(steps) - 1))
+
+
+def test_filtered_sensitivity_hand_case_intermediate_weight():
+    """Eq. filtered_sens at w = 0.35 on five values worked by hand: the
+    normalization is the largest |S_phi| over Omega_0 only (element 3, outside
+    Omega_0, holds the global largest, 8, and is not used: the divisor is 4);
+    Sbar = [0.5, -1, 0.25, 2, -0.75]; the result is 0.65 Sbar + 0.35 filter."""
+    s = np.array([2.0, -4.0, 1.0, 8.0, -3.0], np.float32)
+    filt = np.array([0.2, 1.0, 0.0, 0.5, 0.8], np.float32)
+    om = np.array([1, 1, 1, 0, 1], bool)
+    out = cp.filtered_sensitivity(s, filt, 0.35, om)
+    expect = [0.395, -0.3, 0.1625, 1.475, -0.2075]
+    assert out.dtype == np.float32
+    assert out.tolist() == [float(np.float32(v)) for v in expect]

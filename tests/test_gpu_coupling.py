@@ -1,4 +1,4 @@
-"""GPU parity of the TO-coupling steps (Sec. 3) through the C interface:
+"""GPU parity of the TO-coupling steps (Sec. 2.2) through the C interface:
 Heaviside projection bit-exact against the float64 oracle (outside the
 rounding-tie zone, where a last-bit difference of exp could flip the 2^-24
 rounding), accessibility filter and filtered sensitivity bit-exact, and a short

@@ -563,3 +563,132 @@ def test_identical_fixture_sets_reduce_to_one_fixture():
                                   fixture_of=fof))
     for k in ("imf", "imf_norm", "secluded", "masks"):
         assert np.array_equal(a[k], b[k]), k
+
+
+# ---------------------------------------------------------------------------
+# float64 raster at oblique directions (the path of every Fibonacci request)
+# ---------------------------------------------------------------------------
+
+def _grid_of(offs, sel, lo, shape):
+    g = np.zeros(shape, bool)
+    o = offs[sel]
+    g[o[:, 2] - lo[2], o[:, 1] - lo[1], o[:, 0] - lo[0]] = True
+    return g
+
+
+@pytest.mark.parametrize("tl", [tool(TOOL_BALL, 4, 60, 14, 60), tool(TOOL_FLAT, 3, 40, 10, 40),
+                                tool(TOOL_FLAT, 3, 80, 12, 80)])
+def test_raster_f64_oblique_equals_exact_lattice_up_to_ties(tl):
+    """The float64 predicate at d = v / |v| against an independent exact integer
+    evaluation of the raster definition (Algorithm 1, Rotate; reading of the
+    analytic raster) for oblique lattice vectors v: the two agree at every
+    offset where no boundary test holds with equality, and the oracle's own
+    exact lattice mode agrees with the independent one everywhere."""
+    for v in [(1, 1, 1), (1, 2, 2), (2, -1, 1), (1, -2, 3), (0, 1, 2), (-3, 1, 2)]:
+        v = np.array(v)
+        offs, cut = oracle.raster(tl, v / np.sqrt(float((v * v).sum())), 0)
+        lo, hi = offs.min(0) - 2, offs.max(0) + 2
+        T, K, tie = brute.raster_exact_box(tl, v, lo, hi)
+        F = _grid_of(offs, slice(None), lo, T.shape)
+        Fk = _grid_of(offs, cut, lo, T.shape)
+        diff = (F != T) | (Fk != K)
+        assert not (diff & ~tie).any(), (v, int((diff & ~tie).sum()))
+        assert diff.sum() <= max(2, T.sum() // 200)
+        lo2, cut2 = oracle.raster(tl, v.astype(np.int32), 1)
+        assert np.array_equal(_grid_of(lo2, slice(None), lo, T.shape), T)
+        assert np.array_equal(_grid_of(lo2, cut2, lo, T.shape), K)
+
+
+@pytest.mark.parametrize("tl,n", [(tool(TOOL_BALL, 4, 60, 14, 60), 130),
+                                  (tool(TOOL_FLAT, 3, 80, 12, 80), 512)])
+def test_raster_f64_fibonacci_equals_extended_precision(tl, n):
+    """Fibonacci-hemisphere directions (no lattice form): the float64 raster
+    equals the same definition evaluated in extended precision at every offset
+    more than 1e-9 from a boundary of the predicate."""
+    from workloads import fib_hemisphere
+    dirs = fib_hemisphere(n)
+    for q in (0, 1, 5, n // 3, n // 2, n - 2, n - 1):
+        offs, cut = oracle.raster(tl, dirs[q], 0)
+        lo, hi = offs.min(0) - 2, offs.max(0) + 2
+        T, K, near = brute.raster_margin_box(tl, dirs[q], lo, hi)
+        F = _grid_of(offs, slice(None), lo, T.shape)
+        Fk = _grid_of(offs, cut, lo, T.shape)
+        diff = (F != T) | (Fk != K)
+        assert not (diff & ~near).any(), q
+        # the box holds the whole raster (two voxels of margin on each side)
+        assert not T[[0, -1]].any() and not T[:, [0, -1]].any() and not T[..., [0, -1]].any()
+
+
+def test_raster_extended_reference_catches_a_dropped_term():
+    """The extended-precision reference is sensitive to the predicate: a radial
+    distance that drops the z term of o - a d disagrees with it far from any
+    boundary (a mistake the comparison above would flag)."""
+    tl = tool(TOOL_FLAT, 3, 40, 10, 40)
+    d = np.array([1.0, 2.0, 2.0]) / 3.0
+    offs, _ = oracle.raster(tl, d, 0)
+    lo, hi = offs.min(0) - 2, offs.max(0) + 2
+    T, _, near = brute.raster_margin_box(tl, d, lo, hi)
+    z, y, x = np.meshgrid(*(np.arange(lo[a], hi[a] + 1) for a in (2, 1, 0)), indexing="ij")
+    a = x * d[0] + y * d[1] + z * d[2]
+    q2_wrong = (x - a * d[0]) ** 2 + (y - a * d[1]) ** 2
+    wrong = ((a >= 0) & (a < 40) & (q2_wrong <= 9)) | ((a >= 40) & (a < 80) & (q2_wrong <= 100))
+    assert ((wrong != T) & ~near).sum() > 1000
+
+
+# ---------------------------------------------------------------------------
+# several tools (Eq. imf_3: the minimum over tools and their orientations)
+# ---------------------------------------------------------------------------
+
+def test_two_tools_equal_the_minimum_of_single_tool_brute_force():
+    """Binary, lambda = 0: f of tools [t1, t2] is the element-wise minimum of
+    the single-tool brute-force IMFs, the masks are theirs concatenated, and
+    B, fbar and Gamma follow from that minimum."""
+    rng = np.random.default_rng(31)
+    d = (rng.random((8, 9, 10)) < 0.3).astype(np.uint8)
+    fx = fixture_plate(d.shape, 1)
+    t1, t2 = tool(TOOL_FLAT, 1, 3, 2, 2), tool(TOOL_BALL, 1.5, 4, 2, 2)
+    D1, D2 = lattice26()[::4], lattice26()[1::5]
+    both = oracle.imf(oracle.Request(d, fx, tools=[t1, t2], dirs=[D1, D2], dir_kind=1))
+    b1 = brute.imf(d.astype(np.int64), fx, t1, D1)
+    b2 = brute.imf(d.astype(np.int64), fx, t2, D2)
+    f = np.minimum(b1["imf"], b2["imf"])
+    assert np.array_equal(both["imf"], f.astype(np.float64))
+    om = fx == 0
+    fmax = int(f[om].max())
+    assert both["F_max"] == fmax
+    B = om & (f > 0)
+    assert np.array_equal(both["secluded"].astype(bool), B & (d == 0))
+    assert np.array_equal(both["imf_norm"], np.where(B, f / fmax, 0).astype(np.float32))
+    m = oracle.unpack_masks(both["masks"], d.shape[2])
+    assert np.array_equal(m, np.concatenate([b1["masks"], b2["masks"]]))
+
+
+def test_two_tools_density_with_allowance_threshold_of_the_joint_maximum():
+    """Density, lambda > 0: the masks of a two-tool request use lambda times the
+    joint F_max (the maximum of the minimum over both tools), not either
+    tool's own; checked against the brute-force gammas of each tool."""
+    rng = np.random.default_rng(32)
+    Q = 1 << 24
+    d = (rng.integers(0, Q + 1, size=(7, 8, 9)) / float(Q)).astype(np.float32)
+    fx = fixture_plate(d.shape, 1)
+    t1, t2 = tool(TOOL_FLAT, 1, 3, 2, 2), tool(TOOL_BALL, 1.5, 3, 2, 2)
+    D1, D2 = lattice26()[2::5], lattice26()[::6]
+    lam = 0.3
+    both = oracle.imf(oracle.Request(d, fx, tools=[t1, t2], dirs=[D1, D2], dir_kind=1,
+                                     lam=lam))
+    di = (d.astype(np.float64) * Q).astype(np.int64)
+    g = np.concatenate([brute.imf(di, fx, t1, D1, scale=Q)["gammas"],
+                        brute.imf(di, fx, t2, D2, scale=Q)["gammas"]])
+    f = g.min(0)
+    om = fx == 0
+    fmax = int(f[om].max())
+    assert both["F_max"] * Q == fmax
+    theta = lam * float(fmax)
+    B = om & (f.astype(np.float64) > theta)
+    assert np.array_equal(both["imf"] * Q, f.astype(np.float64))
+    assert np.array_equal(both["imf_norm"], np.where(B, f / float(fmax), 0).astype(np.float32))
+    m = oracle.unpack_masks(both["masks"], d.shape[2])
+    assert np.array_equal(m, om[None] & (g.astype(np.float64) <= theta))
+    assert np.array_equal(oracle.unpack_masks(both["masks_dil"], d.shape[2]), m)
+    # the second tool's masks use the joint threshold, which differs from its own here
+    assert fmax < int(g[len(D1):].min(0)[om].max())
