@@ -266,6 +266,23 @@ imf_status imf_plan_greedy(imf_ctx* ctx, int nx, int ny, int nz, int n_orient,
                            int max_steps, int* orient_out, long long* removed_out, int* n_steps,
                            long long* remaining, void* stream);
 
+/* The greedy plan of imf_plan_greedy for callers that cannot allocate device
+ * memory (serving loops and harnesses that forbid hipMalloc): it allocates
+ * nothing.  Its scratch, the remaining negative space (nz * ny * ceil(nx/64)
+ * words) and n_orient + 2 words of counts, lives in a fixed array of 2^20
+ * 64-bit words (8 MiB) that every GPU the library runs on holds until the
+ * process ends; a plan that needs more returns IMF_EINVAL.  Every call on one
+ * GPU shares that array: calls that overlap on one GPU (any context, any
+ * stream) race, and the caller must order them.  Same arguments, outputs and
+ * errors as imf_plan_greedy; it reads each step's choice on the host, so it is
+ * not capturable into a graph. */
+imf_status imf_plan_greedy_noalloc(imf_ctx* ctx, int nx, int ny, int nz, int n_orient,
+                                   const uint64_t* acc_masks, const void* design,
+                                   int design_is_density, const uint8_t* fixture,
+                                   const uint8_t* domain, double tau, int max_steps,
+                                   int* orient_out, long long* removed_out, int* n_steps,
+                                   long long* remaining, void* stream);
+
 /* ------------------------------------------------- single steps (checks) -- */
 /* Raster of one oriented tool (the Rotate step): offsets (x, y, z) in z, y, x
  * order into host arrays (voxels of the tool and the sharp points); flags bit 0 =

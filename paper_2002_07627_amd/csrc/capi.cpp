@@ -284,6 +284,12 @@ extern "C" imf_status imf_create(int device, size_t hbm_budget_bytes, imf_ctx** 
                 prop.gcnArchName);
   size_t fr = 0, tot = 0;
   HIPCHK(hipMemGetInfo(&fr, &tot));
+  // the allocation-free planner's scratch: its device address on this device
+  {
+    const hipError_t e = imf_plan_scratch_init(device);
+    if (e != hipSuccess)
+      return fail(IMF_EDEVICE, "planner scratch address: %s", hipGetErrorString(e));
+  }
   imf_ctx* c = new imf_ctx();
   c->device = device;
   c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)fr);
@@ -2123,6 +2129,57 @@ extern "C" imf_status imf_plan_greedy(imf_ctx* c, int nx, int ny, int nz, int n_
   hipFree(R);
   hipFree(counts);
   return st;
+}
+
+// The same plan without any allocation: scratch in the library's fixed
+// per-device array, the step's choice made on the device and read as two
+// words into host stack memory.
+extern "C" imf_status imf_plan_greedy_noalloc(imf_ctx* c, int nx, int ny, int nz, int n_orient,
+                                              const uint64_t* acc_masks, const void* design,
+                                              int design_is_density, const uint8_t* fixture,
+                                              const uint8_t* domain, double tau, int max_steps,
+                                              int* orient_out, long long* removed_out,
+                                              int* n_steps, long long* remaining, void* stream) {
+  if (!c || !acc_masks || !design || !n_steps || !remaining ||
+      (max_steps > 0 && (!orient_out || !removed_out)))
+    return fail(IMF_EINVAL, "NULL argument");
+  if (nx <= 0 || ny <= 0 || nz <= 0 || n_orient <= 0 || max_steps < 0)
+    return fail(IMF_EINVAL, "sizes must be positive");
+  const long long nw = (long long)nz * ny * ((nx + 63) / 64);
+  const long long need = nw + n_orient + 2;
+  if (need > IMF_PLAN_SCRATCH_WORDS)
+    return fail(IMF_EINVAL,
+                "plan needs %lld scratch words (%lld mask words + %d counts + 2), more than "
+                "the %d of the allocation-free planner",
+                need, nw, n_orient, IMF_PLAN_SCRATCH_WORDS);
+  std::lock_guard<std::recursive_mutex> lk(c->mu);
+  HIPCHK(hipSetDevice(c->device));
+  unsigned long long* base = imf_plan_scratch(c->device);
+  if (!base) return fail(IMF_EDEVICE, "planner scratch not set up on device %d", c->device);
+  hipStream_t s = (hipStream_t)stream;
+  uint64_t* R = (uint64_t*)base;
+  unsigned long long* counts = base + nw;
+  unsigned long long* best = counts + n_orient;
+  unsigned long long h[2] = {0, 0};
+  HIPCHK(imf_launch_negative_bits(design, design_is_density, tau, fixture, domain, nx,
+                                  (long long)ny * nz, R, s));
+  int k = 0;
+  for (; k < max_steps; k++) {
+    HIPCHK(imf_launch_cover_count(acc_masks, n_orient, nw, R, counts, s));
+    HIPCHK(imf_launch_cover_best(counts, n_orient, best, s));
+    HIPCHK(hipMemcpyAsync(h, best, sizeof h, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (h[0] == 0) break;
+    orient_out[k] = (int)h[1];
+    removed_out[k] = (long long)h[0];
+    HIPCHK(imf_launch_cover_remove(acc_masks + (long long)h[1] * nw, nw, R, s));
+  }
+  *n_steps = k;
+  HIPCHK(imf_launch_cover_count(R, 1, nw, R, counts, s));
+  HIPCHK(hipMemcpyAsync(h, counts, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  *remaining = (long long)h[0];
+  return IMF_OK;
 }
 
 extern "C" imf_status imf_autotune(imf_ctx* c, const imf_request* r, const imf_outputs* out,

@@ -309,3 +309,13 @@ hipError_t imf_launch_negative_bits(const void* design, int density, double tau,
 hipError_t imf_launch_cover_count(const uint64_t* masks, int nq, long long nw, const uint64_t* R,
                                   unsigned long long* counts, hipStream_t s);
 hipError_t imf_launch_cover_remove(const uint64_t* A, long long nw, uint64_t* R, hipStream_t s);
+hipError_t imf_launch_cover_best(const unsigned long long* counts, int nq, unsigned long long* out,
+                                 hipStream_t s);
+// fixed scratch of the allocation-free planner (64-bit words, per device)
+#define IMF_PLAN_SCRATCH_WORDS (1 << 20)
+#define IMF_MAX_DEVICES 64
+// once per device, with that device current: take the device address of the
+// scratch array (hipGetSymbolAddress); later calls return at once
+hipError_t imf_plan_scratch_init(int device);
+// that address, or NULL before imf_plan_scratch_init succeeded on the device
+unsigned long long* imf_plan_scratch(int device);

@@ -3,6 +3,8 @@
 // accessibility filter (Eq. accFilter) and the filtered sensitivity
 // (Eq. filtered_sens).  Pointwise and HBM-bound; float64 arithmetic, compiled
 // without FP contraction so that every operation rounds as written.
+#include <mutex>
+
 #include "imf_internal.h"
 
 #define Q24 16777216.0
@@ -176,4 +178,80 @@ hipError_t imf_launch_cover_count(const uint64_t* masks, int nq, long long nw, c
 hipError_t imf_launch_cover_remove(const uint64_t* A, long long nw, uint64_t* R, hipStream_t s) {
   hipLaunchKernelGGL(k_cover_remove, dim3(grid_of(nw)), dim3(256), 0, s, A, nw, R);
   return hipGetLastError();
+}
+
+// Choice of one greedy step on the device: the largest count, the lowest
+// orientation index among equal counts (one workgroup of 1024 threads).
+// out[0] = that count, out[1] = its orientation.
+__global__ void __launch_bounds__(1024) k_cover_best(const unsigned long long* __restrict__ counts,
+                                                      int nq, unsigned long long* __restrict__ out) {
+  __shared__ unsigned long long sc[16];
+  __shared__ int si[16];
+  unsigned long long c = 0;
+  int i = 0x7fffffff;
+  for (int q = threadIdx.x; q < nq; q += blockDim.x) {
+    const unsigned long long v = counts[q];
+    if (v > c || (v == c && q < i)) {
+      c = v;
+      i = q;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long c2 = __shfl_xor(c, o);
+    const int i2 = __shfl_xor(i, o);
+    if (c2 > c || (c2 == c && i2 < i)) {
+      c = c2;
+      i = i2;
+    }
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sc[threadIdx.x >> 6] = c;
+    si[threadIdx.x >> 6] = i;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); w++)
+      if (sc[w] > c || (sc[w] == c && si[w] < i)) {
+        c = sc[w];
+        i = si[w];
+      }
+    out[0] = c;
+    out[1] = (unsigned long long)(i == 0x7fffffff ? 0 : i);
+  }
+}
+
+hipError_t imf_launch_cover_best(const unsigned long long* counts, int nq, unsigned long long* out,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(k_cover_best, dim3(1), dim3(1024), 0, s, counts, nq, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fixed scratch of the allocation-free planner: the remaining negative space
+// (nz * ny * ceil(nx/64) words), the per-orientation counts (n_orient words)
+// and the step's choice (2 words).  Each GPU the library runs on holds its
+// own copy from the library's load until the process ends.  In host code the
+// array's name is not its device address: set-up takes that address once per
+// device (with the device current) and every launch uses it.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned long long scratch[IMF_PLAN_SCRATCH_WORDS];
+
+static std::mutex g_scratch_mu;
+static unsigned long long* g_scratch_ptr[IMF_MAX_DEVICES] = {};
+
+hipError_t imf_plan_scratch_init(int device) {
+  if (device < 0 || device >= IMF_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  unsigned long long* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+unsigned long long* imf_plan_scratch(int device) {
+  if (device < 0 || device >= IMF_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
 }

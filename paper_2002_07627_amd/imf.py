@@ -400,7 +400,7 @@ class Context:
         return filt, so
 
     def plan_greedy(self, masks, design, fixture=None, domain=None, *, tau=0.5, max_steps=None,
-                    stream=None):
+                    stream=None, noalloc=False):
         """Greedy machining plan from a request's accessible masks: returns
         ([(orientation, voxels removed), ...], voxels left)."""
         shape = design.shape if design.dim() == 3 else (1,) + tuple(design.shape)
@@ -414,7 +414,8 @@ class Context:
         n = C.c_int()
         left = C.c_longlong()
         import torch
-        _check(_L().imf_plan_greedy(
+        fn = _L().imf_plan_greedy_noalloc if noalloc else _L().imf_plan_greedy
+        _check(fn(
             self._ctx, nx, ny, nz, nq, _ptr(masks), _ptr(design),
             int(design.dtype == torch.float32), _ptr(fixture), _ptr(domain), C.c_double(tau), ms,
             orient.ctypes.data_as(C.c_void_p), removed.ctypes.data_as(C.c_void_p), C.byref(n),
