@@ -51,7 +51,8 @@ typedef enum {
   IMF_EBUSY = 4,       /* serving queue full */
   IMF_ETIMEOUT = 5,    /* imf_wait timed out (the request keeps running) */
   IMF_ECANCELLED = 6,  /* the request was cancelled */
-  IMF_EACCURACY = 7,   /* the guard band overflowed its recheck buffer */
+  IMF_EACCURACY = 7,   /* the guard band overflowed its recheck buffer, or an exact
+                          recomputation found a float32 overlap error above half the band */
   IMF_ENOTIMPL = 8
 } imf_status;
 
@@ -151,10 +152,13 @@ typedef struct {
 } imf_outputs;
 
 typedef struct {
-  double F_max;          /* max of f over Omega_0 */
+  double F_max;          /* max of f over Omega_0: exact (binary, and density with
+                            lambda > 0); the float32 maximum for density with lambda = 0,
+                            where no decision depends on it */
   long long guard_flags; /* overlaps recomputed exactly (guard band) */
   float max_frac_err;    /* max |g - rint g| seen before rounding (binary) */
-  double guard_band;     /* density: band around theta that is rechecked */
+  double guard_band;     /* density: E, the bound on |g32 - g| (voxel units); overlaps
+                            within E of a threshold are recomputed exactly */
   double t_ms[8];        /* raster, forward, tool spectra, inverse, recheck, min, finalize, total */
   double model_bytes;    /* algorithmic HBM bytes of the request (cost model) */
   int P[3];              /* transform sizes */
@@ -179,6 +183,12 @@ typedef struct {
   int mf_shape;            /* block shape of the sharp-point minimum (0: 64x1x1, 1: 32x2x1,
                               2: 16x2x2, 3: 16x4x1, 4: 8x4x2 voxels per wave) */
   int mf_wg_per_cu;        /* resident workgroups per CU of its list pass */
+  /* density: the largest |g32 - g| (voxel units) that an exact recomputation
+   * found (the request fails with IMF_EACCURACY above guard_band / 2) */
+  float max_abs_err;
+  long long post_exact;    /* exact overlaps computed after the first pass (F_max, band) */
+  long long band_entries;  /* overlaps within guard_band of lambda F_max */
+  int passes;              /* 2 when theta = lambda F_max was decided by a second pass */
 } imf_stats;
 
 /* Bytes of device workspace the request needs (admission control).  The

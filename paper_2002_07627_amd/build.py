@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libimf.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["capi.cpp", "k_raster.hip", "k_fft.hip", "k_imf.hip", "k_couple.hip"]
+SOURCES = ["capi.cpp", "k_raster.hip", "k_fft.hip", "k_imf.hip", "k_couple.hip", "k_exact.hip"]
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
           "-Wno-unused-function", "-Wno-unused-value", "-Wno-unused-result", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 # the rasterization predicate and the coupling arithmetic are evaluated exactly
@@ -19,7 +19,7 @@ COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
 # k_imf.hip never sees a NaN (overlaps, minima and +inf padding only): without
 # NaN semantics its minima need no input canonicalization
 EXTRA = {"k_raster.hip": ["-ffp-contract=off"], "k_couple.hip": ["-ffp-contract=off"],
-         "k_imf.hip": ["-fno-honor-nans"]}
+         "k_imf.hip": ["-fno-honor-nans"], "k_exact.hip": ["-ffp-contract=off"]}
 
 
 def _compile(src: str) -> str:

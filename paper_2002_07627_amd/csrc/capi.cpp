@@ -221,6 +221,9 @@ struct imf_ctx {
   // neighbours) gather the same runs in step, so they share L1 lines:
   // 0 off, 1 four waves, 2 eight waves per workgroup
   int mf_sync = 2;
+  // density requests at lambda F_max keep the overlaps of every orientation
+  // when they fit (otherwise a second pass decides the band)
+  bool overlap_stack = true;
 };
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -300,6 +303,7 @@ extern "C" imf_status imf_create(int device, size_t hbm_budget_bytes, imf_ctx** 
   if (const char* e = std::getenv("IMF_AXIS_RUNS")) c->lattice_runs = std::atoi(e) == 0;
   if (const char* e = std::getenv("IMF_GIVEN_ORDER")) c->spread_order = std::atoi(e) == 0;
   if (const char* e = std::getenv("IMF_MINFILTER_SYNC")) c->mf_sync = std::atoi(e);
+  if (const char* e = std::getenv("IMF_OVERLAP_STACK")) c->overlap_stack = std::atoi(e) != 0;
   if (const char* e = std::getenv("IMF_MINFILTER_WG_PER_CU"))
     c->mf_wg_per_cu = std::max(1, std::min(16, std::atoi(e)));
   if (hipStreamCreateWithFlags(&c->internal, hipStreamNonBlocking) != hipSuccess) {
@@ -946,6 +950,24 @@ struct Plan {
   int debug_pos = -1;  // processing position of the orientation whose overlaps are copied
   double theta;
   double band;
+  // Exact decisions at the threshold theta_B = lambda F_max of B (and of
+  // two-phase masks).  E bounds |g32 - g| (voxel units; 0 for binary); scale
+  // is the fixed-point unit (2^-24 for density, 1 for binary).  thB_known:
+  // theta_B is known before the request runs (lambda = 0, or a second pass
+  // given the exact F_max) and the first-pass recheck decides it too;
+  // otherwise (exact) F_max is found exactly after all orientations and the
+  // band around theta_B is decided from the stored overlaps (gst) or, without
+  // room for them, by a second pass.
+  double E = 0, scale = 1;
+  bool thB_known = true;
+  double thB = 0;                 // theta_B in voxel units when known
+  unsigned long long known_Fq = 0;
+  bool known = false;             // a second pass: F_max given
+  bool exact = false;             // F_max and the band decided after the first pass
+  bool gam = false;               // gamma stack (two-phase masks or exact)
+  bool intmask = false;           // masks at theta_B in the workspace (exact, no such output)
+  bool gst = false;               // g of every orientation kept (band scan)
+  int band_cap = 0, cand_cap = 0;
   // workspace layout (bytes)
   size_t ws_bytes;
   long long spec_elems;
@@ -1005,7 +1027,8 @@ static void ctx_tuned_params(imf_ctx* c, Plan& p) {
 }
 
 static imf_status make_plan(imf_ctx* c, const imf_request* r, const imf_outputs* out,
-                            const std::vector<Orient>& os, Plan& p) {
+                            const std::vector<Orient>& os, Plan& p,
+                            const unsigned long long* known_Fq = nullptr) {
   p.nd = r->ndim;
   p.n[0] = r->nx;
   p.n[1] = r->ny;
@@ -1091,6 +1114,7 @@ static imf_status make_plan(imf_ctx* c, const imf_request* r, const imf_outputs*
     const int set = p.nsets ? r->fixture_of[os[q].index] : 0;
     int e = q + 1;
     while (e < p.nO && e - q < p.B && (!p.nsets || r->fixture_of[os[e].index] == set)) e++;
+    for (int k = q; k < e; k++) p.desc[k].set = set;
     p.bset.push_back(set);
     p.bstart.push_back(e);
     q = e;
@@ -1112,15 +1136,42 @@ static imf_status make_plan(imf_ctx* c, const imf_request* r, const imf_outputs*
   p.two_phase = p.masks && !p.theta_known;
   if (p.two_phase && p.sweep)
     return fail(IMF_EINVAL, "the sweep mask route needs a known threshold (mask_theta_abs >= 0 or lambda = 0)");
-  // density guard band: 2 E with E a bound on the float32 transform error,
-  // u * log2(P^3) * sqrt(N |T|) (|rho| <= 1)
-  p.band = 0;
-  if (r->design_is_density && p.method == IMF_METHOD_FFT) {
+  // Error model of the float32 overlaps (density; binary overlaps are rounded
+  // to exact integers).  Transform path: the error of a float32 transform
+  // correlation is relative to the magnitude of its outputs, at most |T|
+  // (rho <= 1), growing like the square root of the number of radix stages;
+  // E = 8 u sqrt(log2 P^3) |T| (u = 2^-24) holds measured errors with a
+  // margin of about ten (256^3 x 130: largest of 10^5 sampled errors 8.5e-3,
+  // E = 0.097), and every exact recomputation checks it (IMF_EACCURACY when
+  // one exceeds E / 2).  Direct path: exact sums rounded once to float32,
+  // |g32 - g| <= 2^-24 |T|.
+  p.E = 0;
+  p.scale = r->design_is_density ? 1.0 / 16777216.0 : 1.0;
+  if (r->design_is_density) {
     long long maxT = 1;
     for (auto* e : p.ent) maxT = std::max<long long>(maxT, e->ext[12]);
-    const double u = 5.96e-8;
-    const double lg = std::log2((double)p.P[0] * p.P[1] * p.P[2]);
-    p.band = 2.0 * u * lg * std::sqrt((double)p.N * (double)maxT);
+    const double u = 1.0 / 16777216.0;
+    if (p.method == IMF_METHOD_FFT) {
+      const double lg = std::log2((double)p.P[0] * p.P[1] * p.P[2]);
+      p.E = 8.0 * u * std::sqrt(lg) * (double)maxT;
+    } else {
+      p.E = u * (double)maxT;
+    }
+  }
+  p.band = p.E;  // half-width of the first-pass recheck around a known threshold
+  // the threshold of B
+  p.known = known_Fq != nullptr;
+  p.known_Fq = known_Fq ? *known_Fq : 0;
+  p.thB_known = r->lambda == 0 || p.known || !r->design_is_density;
+  p.thB = p.known ? r->lambda * (double)p.known_Fq * p.scale : 0.0;
+  p.exact = r->design_is_density && !p.thB_known;
+  p.gam = p.two_phase || p.exact;
+  p.intmask = p.exact && !p.two_phase;
+  if (p.known && p.two_phase) {  // second pass: the masks' threshold is theta_B
+    p.two_phase = false;
+    p.gam = false;
+    p.theta_known = true;
+    p.theta = p.thB;
   }
   // branch and bound for the sharp-point minimum (not in the plain comparator)
   p.bnb = !plain && !(r->flags & IMF_FLAG_NO_BOUND) && p.N >= c->bound_min_voxels;
@@ -1163,7 +1214,14 @@ static imf_status make_plan(imf_ctx* c, const imf_request* r, const imf_outputs*
   add(sizeof(imf_orient_desc) * p.nO * 2);             // descriptors (+ sweep)
   add(sizeof(float) * p.B * p.max_vol);                // g
   add(sizeof(float) * p.B * std::max(p.nlvl, 1) * p.max_vol);  // levels
-  if (p.two_phase) add(sizeof(float) * N * p.nO);      // gamma stack
+  if (p.gam) add(sizeof(float) * N * p.nO);            // gamma stack
+  if (p.intmask) add(sizeof(uint64_t) * p.nO * (long long)r->nz * r->ny * p.words);  // masks at theta_B
+  if (p.exact) {
+    p.cand_cap = 1 << 16;
+    p.band_cap = 1 << 23;
+    add(sizeof(int) * (size_t)p.cand_cap);               // candidates of the maximum
+    add(sizeof(int4) * (size_t)p.band_cap);              // band entries
+  }
   if (p.bnb) {
     add(sizeof(float) * p.B * p.cell_stride);           // cell minima
     add(sizeof(int) * p.B * (long long)(kFpCap + 1));   // footprints
@@ -1173,7 +1231,7 @@ static imf_status make_plan(imf_ctx* c, const imf_request* r, const imf_outputs*
     add(sizeof(int) * p.nO);                            // kept blocks per orientation
     add(sizeof(uint64_t) * p.B * p.nwords_blk);         // kept-block bits
     add(sizeof(int) * p.B * p.nwords_blk);              // list offsets
-    if (p.two_phase) add(sizeof(uint64_t) * p.nO * p.nwords_blk);  // kept-block bits per orientation
+    if (p.gam) add(sizeof(uint64_t) * p.nO * p.nwords_blk);  // kept-block bits per orientation
   }
   if (p.sweep) add(sizeof(uint64_t) * p.B * ((p.max_m[0] + 63) / 64) * (long long)p.max_m[1] * p.max_m[2]);
   if (p.method == IMF_METHOD_FFT) {
@@ -1186,6 +1244,18 @@ static imf_status make_plan(imf_ctx* c, const imf_request* r, const imf_outputs*
     add(sizeof(float2) * p.B * (long long)p.max_m[2] * p.P[1] * h);      // inverse w1
     add(sizeof(float2) * p.B * (long long)p.max_m[2] * p.max_m[1] * h);  // inverse w2
     add(sizeof(imf_orient_desc) * (size_t)nb * p.B);                      // per-batch miss lists
+  }
+  // the overlaps of every orientation (instead of one batch's) when there is
+  // room beside the cached spectra of the request: the band around theta_B is
+  // then read from them once F_max is known
+  p.gst = false;
+  if (p.exact && c->overlap_stack) {
+    const size_t extra = sizeof(float) * (size_t)(p.nO - p.B) * (size_t)p.max_vol;
+    const size_t spectra = p.cache ? (size_t)p.nO * 8 * (size_t)p.spec_elems : 0;
+    if (b + extra + spectra + c->raster_bytes + (size_t)(1 << 30) <= c->budget) {
+      p.gst = true;
+      b += align256(extra);
+    }
   }
   p.ws_bytes = b + 4096;
   return IMF_OK;
@@ -1316,12 +1386,14 @@ struct Pending {
   std::vector<double> mf_ops, mf_bytes;
   int kept_at = -1;         // offset of the kept counts in host[], or -1
   int graph = 0;            // 0 kernel by kernel, 1 captured and launched, 2 replayed
+  unsigned long long Fq = 0;  // exact F_max (fixed point) once finished
 };
 
 // Enqueue the whole request on stream s (no host synchronization after the
 // rasters exist).  The caller holds the context lock.
 static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_outputs* out,
-                                 hipStream_t s, Arena& ar, Pending& pd) {
+                                 hipStream_t s, Arena& ar, Pending& pd,
+                                 const unsigned long long* known_Fq = nullptr) {
   STCHK(validate(r));
   if (!out) return fail(IMF_EINVAL, "outputs is NULL");
   HIPCHK(hipSetDevice(c->device));
@@ -1337,7 +1409,7 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
   STCHK(ensure_rasters(c, r, os, s));
   tm.mark(0);
   Plan& p = pd.p;
-  STCHK(make_plan(c, r, out, os, p));
+  STCHK(make_plan(c, r, out, os, p, known_Fq));
   if (out->debug_overlap && (out->debug_orient < 0 || out->debug_orient >= p.nO))
     return fail(IMF_EINVAL, "debug_orient out of range");
   STCHK(arena_reserve(c, ar, p.ws_bytes));
@@ -1345,7 +1417,7 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
   const int h = p.P[0] / 2 + 1;
   const int nb = (int)p.bset.size();
   pd.nb = nb;
-  if (nb + 2 > (1 << 14)) return fail(IMF_EINVAL, "too many batches");
+  if (nb + 34 > (1 << 14)) return fail(IMF_EINVAL, "too many batches");
   const int nps = std::max(p.nsets, 1);
   // carve the workspace (same order as make_plan)
   float* f = carve<float>(ar, N);
@@ -1354,17 +1426,29 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
   long long* ps = carve<long long>(ar, ps_stride * nps);
   uint8_t* setfix = p.nsets ? carve<uint8_t>(ar, N * (p.nsets + 1)) : nullptr;
   unsigned int* misc = carve<unsigned int>(ar, 64);
+  // misc: [0] float32 max of f over Omega_0, [1] max |g - rint g| (binary),
+  // [4] max f at a batch's start, [8..9] skipped pairs, [16..17] F_max in
+  // fixed point, [18] candidates of the maximum, [19] band entries, [20] max
+  // |g32 - g| of exact recomputations (density), [21] exact recomputations of
+  // the post pass
   unsigned int* fmax_bits = misc;
   unsigned int* maxerr_bits = misc + 1;
+  unsigned long long* Fq = (unsigned long long*)(misc + 16);
+  unsigned int* derr_bits = misc + 20;
   int* flag_cnt = carve<int>(ar, nb + 1);
   const int flag_cap = 1 << 20;
   pd.flag_cap = flag_cap;
   int2* flags = carve<int2>(ar, flag_cap);
   imf_orient_desc* d_desc = carve<imf_orient_desc>(ar, (size_t)p.nO * 2);
   imf_orient_desc* d_sweep = d_desc + p.nO;
-  float* g = carve<float>(ar, p.B * p.max_vol);
+  // overlaps of one batch, or with gst of every orientation (processing order)
+  float* g = carve<float>(ar, (size_t)(p.gst ? p.nO : p.B) * p.max_vol);
   float* lvl = carve<float>(ar, (size_t)p.B * std::max(p.nlvl, 1) * p.max_vol);
-  float* gstack = p.two_phase ? carve<float>(ar, (size_t)N * p.nO) : nullptr;
+  float* gstack = p.gam ? carve<float>(ar, (size_t)N * p.nO) : nullptr;
+  uint64_t* intmask =
+      p.intmask ? carve<uint64_t>(ar, (size_t)p.nO * r->nz * r->ny * p.words) : nullptr;
+  int* cand = p.exact ? carve<int>(ar, p.cand_cap) : nullptr;
+  int4* band = p.exact ? carve<int4>(ar, p.band_cap) : nullptr;
   unsigned int* cellmin = p.bnb ? carve<unsigned int>(ar, p.B * p.cell_stride) : nullptr;
   // the bound's cell minima come from the inverse x pass (and the recheck)
   // on the transform path, from a pass over g on the direct path
@@ -1379,7 +1463,7 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
   unsigned long long* wmask = p.bnb ? carve<unsigned long long>(ar, p.B * p.nwords_blk) : nullptr;
   int* woff = p.bnb ? carve<int>(ar, p.B * p.nwords_blk) : nullptr;
   unsigned long long* keepbits =
-      p.bnb && p.two_phase ? carve<unsigned long long>(ar, (size_t)p.nO * p.nwords_blk) : nullptr;
+      p.bnb && p.gam ? carve<unsigned long long>(ar, (size_t)p.nO * p.nwords_blk) : nullptr;
   const long long dc_stride = ((p.max_m[0] + 63) / 64) * (long long)p.max_m[1] * p.max_m[2];
   uint64_t* dc = p.sweep ? carve<uint64_t>(ar, p.B * dc_stride) : nullptr;
   float2 *rho_hat = nullptr, *fw1 = nullptr, *fw2 = nullptr, *tw1 = nullptr, *tw2 = nullptr,
@@ -1485,6 +1569,8 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
     }
     put(&p.B, sizeof(p.B));
     put(p.P, sizeof(p.P));
+    put(&p.gst, sizeof(p.gst));
+    put(&p.known_Fq, sizeof(p.known_Fq));
     put(&ar.base, sizeof(ar.base));
     put(&ar.host, sizeof(ar.host));
     const void* tws[3] = {twx, twy, twz};
@@ -1543,6 +1629,8 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
     const int nq = p.bstart[b + 1] - q0;
     // the obstacle of this batch's setup: its spectrum and prefix sums
     const long long* ps_b = ps + ps_stride * p.bset[b];
+    // this batch's overlaps: its slice of the stack, or the one batch buffer
+    float* const gb = p.gst ? g + (size_t)q0 * p.max_vol : g;
     const float2* rho_hat_b = rho_hat ? rho_hat + p.spec_elems * p.bset[b] : nullptr;
     const imf_orient_desc* bd = d_desc + q0;
     // algorithmic bytes of this batch, per kernel class
@@ -1605,12 +1693,18 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
       ia.w1_stride = w1_stride;
       ia.w2 = w2;
       ia.w2_stride = w2_stride;
-      ia.g = g;
+      ia.g = gb;
       ia.g_stride = p.max_vol;
       ia.binary = !r->design_is_density;
       ia.delta = 0.25f;
-      ia.theta_known = r->design_is_density && p.theta_known && p.masks;
-      ia.theta = p.theta;
+      // density: thresholds known before the request runs, each decided
+      // exactly by recomputing the overlaps within E of it (first-pass masks
+      // at theta; B at theta_B when lambda = 0 or F_max is given)
+      ia.nth = 0;
+      if (r->design_is_density) {
+        if (p.theta_known) ia.th[ia.nth++] = p.theta;
+        if (p.thB_known && !(p.theta_known && p.thB == p.theta)) ia.th[ia.nth++] = p.thB;
+      }
       ia.band = p.band;
       ia.max_err_bits = maxerr_bits;
       ia.flag_cnt = flag_cnt + b;
@@ -1625,28 +1719,35 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
         HIPCHK(imf_launch_inverse(ia, p.fl[0], p.fl[1], p.fl[2], twx, twy, twz, s, stage));
         tm.mark(6 + stage);
       }
-      if (ia.binary || ia.theta_known) {
+      if (ia.binary || ia.nth) {
         HIPCHK(imf_launch_recheck(bd, ps_b, r->nx, r->ny, r->nz, r->design_is_density, flag_cnt + b,
-                                  flags, flag_cap, ia.theta_known, p.theta, g, p.max_vol,
-                                  ia.cellmin, p.cell_stride, cwx, cwy, cwz, s));
+                                  flags, flag_cap, ia.nth, ia.th[0], ia.th[1], gb, p.max_vol,
+                                  ia.cellmin, p.cell_stride, cwx, cwy, cwz, derr_bits, s));
         tm.mark(9);
       }
     } else {
-      HIPCHK(imf_launch_direct(bd, nq, ps_b, r->nx, r->ny, r->nz, r->design_is_density, g,
-                               p.max_vol, (int)p.max_vol, s));
+      // exact sums rounded to float32, each known threshold's decision kept
+      int nth = 0;
+      double th[2] = {0, 0};
+      if (r->design_is_density) {
+        if (p.theta_known) th[nth++] = p.theta;
+        if (p.thB_known && !(p.theta_known && p.thB == p.theta)) th[nth++] = p.thB;
+      }
+      HIPCHK(imf_launch_direct(bd, nq, ps_b, r->nx, r->ny, r->nz, r->design_is_density, gb,
+                               p.max_vol, (int)p.max_vol, nth, th[0], th[1], s));
       tm.mark(8);
     }
     if (out->debug_overlap && p.debug_pos >= q0 && p.debug_pos < q0 + nq) {
       const imf_orient_desc& d = p.desc[p.debug_pos];
       const long long vol = (long long)d.box_dim[0] * d.box_dim[1] * d.box_dim[2];
-      HIPCHK(hipMemcpyAsync(out->debug_overlap, g + (long long)(p.debug_pos - q0) * p.max_vol,
+      HIPCHK(hipMemcpyAsync(out->debug_overlap, gb + (long long)(p.debug_pos - q0) * p.max_vol,
                             sizeof(float) * vol, hipMemcpyDeviceToDevice, s));
       tm.mark(14);
     }
     imf_min_args ma{};
     ma.desc = bd;
     ma.nq = nq;
-    ma.g = g;
+    ma.g = gb;
     ma.g_stride = p.max_vol;
     ma.lvl = lvl;
     ma.lvl_stride = (long long)std::max(p.nlvl, 1) * p.max_vol;
@@ -1703,6 +1804,8 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
     ma.wstride = p.nwords_blk;
     ma.fmax_up = gstack ? misc + 4 : nullptr;
     ma.theta_lambda = r->lambda;
+    ma.e_theta = p.E;
+    ma.fmargin = p.exact ? 2.0 * p.E : 0.0;
     ma.theta_known = p.theta_known;
     ma.q0 = q0;
     ma.n_cu = c->n_cu;
@@ -1721,28 +1824,78 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
       tm.mark(11);
     }
     if (p.sweep) {
-      imf_sweep_args sa{d_sweep + q0, nq, g, p.max_vol, p.theta, r->nx, r->ny, r->nz, om, dc,
+      imf_sweep_args sa{d_sweep + q0, nq, gb, p.max_vol, p.theta, r->nx, r->ny, r->nz, om, dc,
                         dc_stride, out->acc_masks};
       HIPCHK(imf_launch_sweep(sa, s));
       tm.mark(12);
     }
   }
+  // F_max, theta_B = lambda F_max, masks at theta_B, B, fbar, Gamma
   HIPCHK(imf_launch_fmax(f, om, N, fmax_bits, s));
-  HIPCHK(imf_launch_finalize(f, om, r->design, r->design_is_density, N, fmax_bits, r->lambda,
-                             r->tau, out->imf, out->imf_norm, out->secluded, s));
-  if (p.two_phase)
-    HIPCHK(imf_launch_masks_from_gamma(gstack, p.nO, om, r->nx, r->ny, r->nz, fmax_bits,
-                                       r->lambda, out->acc_masks, keepbits, p.shape,
+  imf_exact_args ea{};
+  ea.desc = d_desc;
+  ea.nO = p.nO;
+  ea.nx = r->nx;
+  ea.ny = r->ny;
+  ea.nz = r->nz;
+  ea.N = N;
+  ea.ps = ps;
+  ea.ps_stride = ps_stride;
+  ea.f = f;
+  ea.omega0 = om;
+  ea.gamma = gstack;
+  ea.keep = keepbits;
+  ea.kstride = p.nwords_blk;
+  imf_block_dims(p.shape, ea.WX, ea.WY, ea.WZ);
+  ea.gst = p.gst ? g : nullptr;
+  ea.gst_stride = p.max_vol;
+  ea.E = p.E;
+  ea.scale = p.scale;
+  ea.lambda = r->lambda;
+  ea.fmax_bits = fmax_bits;
+  ea.Fq = Fq;
+  ea.cand = cand;
+  ea.cand_cnt = misc + 18;
+  ea.cand_cap = p.cand_cap;
+  ea.band = band;
+  ea.band_cnt = misc + 19;
+  ea.band_cap = p.band_cap;
+  ea.err_bits = derr_bits;
+  ea.n_exact = misc + 21;
+  uint64_t* const mB = p.two_phase ? out->acc_masks : intmask;  // masks at theta_B
+  ea.masks = mB;
+  // without room for the overlaps the band is decided by a second pass that
+  // knows theta_B from this pass's exact F_max: this pass stops at F_max
+  const bool second = p.exact && !p.gst;
+  if (p.known) {
+    HIPCHK(imf_launch_fill_u32(misc + 16, 1, (unsigned)(p.known_Fq & 0xffffffffu), s));
+    HIPCHK(imf_launch_fill_u32(misc + 17, 1, (unsigned)(p.known_Fq >> 32), s));
+  } else if (p.exact) {
+    HIPCHK(imf_launch_exact_fmax(ea, s));
+  } else {
+    HIPCHK(imf_launch_fq_from_fmax(fmax_bits, 1.0 / p.scale, Fq, s));
+  }
+  if (p.gam && !second && mB)
+    HIPCHK(imf_launch_masks_from_gamma(gstack, p.nO, om, r->nx, r->ny, r->nz, Fq, p.scale,
+                                       r->lambda, p.exact ? p.E : 0.0, mB, keepbits, p.shape,
                                        p.nwords_blk, s));
+  if (p.exact && p.gst) {
+    HIPCHK(imf_launch_band_scan(ea, p.max_vol, s));
+    HIPCHK(imf_launch_band_exact(ea, s));
+  }
+  if (!second)
+    HIPCHK(imf_launch_finalize_exact(ea, r->design, r->design_is_density, r->tau,
+                                     p.exact ? p.E : 0.0, out->imf, out->imf_norm,
+                                     out->secluded, s));
   tm.mark(13);
   pd.kbytes[13] = (double)N * (4 + 1 + esz + (out->imf ? 4 : 0) + (out->imf_norm ? 4 : 0) +
                                (out->secluded ? 1 : 0)) +
-                  (p.two_phase ? (4.0 * N + N / 8.0) * p.nO : 0.0);
+                  (p.gam ? (4.0 * N + N / 8.0) * p.nO : 0.0);
   pd.host = ar.host;
-  HIPCHK(hipMemcpyAsync(pd.host, misc, 16 * sizeof(unsigned int), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(pd.host + 16, flag_cnt, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
-  if (kept && 16 + nb + p.nO <= (1 << 14)) {
-    pd.kept_at = 16 + nb;
+  HIPCHK(hipMemcpyAsync(pd.host, misc, 32 * sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(pd.host + 32, flag_cnt, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
+  if (kept && 32 + nb + p.nO <= (1 << 14)) {
+    pd.kept_at = 32 + nb;
     HIPCHK(hipMemcpyAsync(pd.host + pd.kept_at, kept, sizeof(int) * p.nO, hipMemcpyDeviceToHost,
                           s));
   }
@@ -1821,7 +1974,7 @@ static imf_status compute_finish(Pending& pd, imf_stats* st) {
   const Plan& p = pd.p;
   long long total_flags = 0;
   for (int b = 0; b < pd.nb; b++) {
-    const int n = (int)pd.host[16 + b];
+    const int n = (int)pd.host[32 + b];
     if (n > pd.flag_cap) {
       pd.tm.release();
       return fail(IMF_EACCURACY, "guard band of batch %d flagged %d overlaps (capacity %d)", b, n,
@@ -1829,26 +1982,45 @@ static imf_status compute_finish(Pending& pd, imf_stats* st) {
     }
     total_flags += n;
   }
-  auto ord2f = [](unsigned u) {
-    unsigned b = (u & 0x80000000u) ? (u & 0x7fffffffu) : ~u;
-    float f;
-    std::memcpy(&f, &b, 4);
-    return f;
-  };
+  std::memcpy(&pd.Fq, &pd.host[16], 8);
+  float derr;
+  std::memcpy(&derr, &pd.host[20], 4);
+  if (p.exact && pd.host[18] > (unsigned)p.cand_cap) {
+    pd.tm.release();
+    return fail(IMF_EACCURACY,
+                "%u voxels have f within 2E of the float32 maximum (capacity %d): F_max cannot "
+                "be decided exactly", pd.host[18], p.cand_cap);
+  }
+  if (p.exact && pd.host[19] > (unsigned)p.band_cap) {
+    pd.tm.release();
+    return fail(IMF_EACCURACY, "%u overlaps lie within E of lambda F_max (capacity %d)",
+                pd.host[19], p.band_cap);
+  }
+  // the error model: every exact recomputation must lie well inside the band
+  if (p.E > 0 && (double)derr > 0.5 * p.E) {
+    pd.tm.release();
+    return fail(IMF_EACCURACY,
+                "a float32 overlap is %.3g from its exact value, more than half the guard band "
+                "E = %.3g: the error model does not hold for this request", (double)derr, p.E);
+  }
   if (st) {
     std::memset(st, 0, sizeof *st);
-    st->F_max = ord2f(pd.host[0]);
+    st->F_max = (double)pd.Fq * p.scale;
     float me;
     std::memcpy(&me, &pd.host[1], 4);
     st->max_frac_err = me;
-    st->guard_flags = total_flags;
+    st->max_abs_err = derr;
+    st->post_exact = pd.host[21];
+    st->band_entries = pd.host[19];
+    st->guard_flags = total_flags + pd.host[21];
+    st->passes = 1;
     if (p.bnb) {
       unsigned long long sk;
       std::memcpy(&sk, &pd.host[8], 8);
       st->bound_skipped = (long long)sk;
       st->bound_blocks = p.nblocks * p.nO;
     }
-    st->guard_band = p.band;
+    st->guard_band = p.E;
     pd.tm.collect(st);
     if (pd.tm.fine) {
       if (pd.kept_at >= 0 && p.nblocks > 0) {  // the minimum pass ran on the kept blocks only
@@ -1883,16 +2055,52 @@ static imf_status compute_finish(Pending& pd, imf_stats* st) {
   return IMF_OK;
 }
 
+// Launch and wait for one request.  A density request at lambda F_max whose
+// overlaps had no room to stay in the workspace ends its first pass at the
+// exact F_max; a second pass then runs with theta_B = lambda F_max known, so
+// its first-pass recheck decides the masks and B exactly.  The context lock is
+// taken while a pass is planned and launched (recursively when the caller
+// holds it), not while it runs.
+static imf_status run_request(imf_ctx* c, const imf_request* r, const imf_outputs* out,
+                              imf_stats* st, hipStream_t s, Arena& ar) {
+  unsigned long long known = 0;
+  double t_first = 0;
+  long long flags_first = 0;
+  for (int pass = 0; pass < 2; pass++) {
+    Pending pd;
+    imf_status e;
+    {
+      std::lock_guard<std::recursive_mutex> lk(c->mu);
+      e = compute_launch(c, r, out, s, ar, pd, pass ? &known : nullptr);
+      if (e != IMF_OK) {
+        hipStreamSynchronize(s);
+        pd.tm.release();
+        return e;
+      }
+    }
+    imf_stats tmp{};
+    e = compute_finish(pd, st ? st : &tmp);
+    if (e != IMF_OK) return e;
+    if (!(pd.p.exact && !pd.p.gst)) {
+      if (st && pass) {
+        st->passes = 2;
+        st->t_ms[7] += t_first;
+        st->guard_flags += flags_first;
+      }
+      return IMF_OK;
+    }
+    known = pd.Fq;
+    if (st) {
+      t_first = st->t_ms[7];
+      flags_first = st->guard_flags;
+    }
+  }
+  return fail(IMF_EDEVICE, "second pass did not settle the threshold");
+}
+
 static imf_status compute_impl(imf_ctx* c, const imf_request* r, const imf_outputs* out,
                                imf_stats* st, hipStream_t s, Arena& ar) {
-  Pending pd;
-  imf_status e = compute_launch(c, r, out, s, ar, pd);
-  if (e != IMF_OK) {
-    hipStreamSynchronize(s);
-    pd.tm.release();
-    return e;
-  }
-  return compute_finish(pd, st);
+  return run_request(c, r, out, st, s, ar);
 }
 
 extern "C" imf_status imf_compute(imf_ctx* c, const imf_request* r, const imf_outputs* out,
@@ -2348,16 +2556,7 @@ static void serve_worker(imf_ctx* c) {
       // planning and caches are shared: hold the context lock while the
       // request is planned and launched, then wait without it, so kernels of
       // different workers overlap on the device through their streams
-      Pending pd;
-      {
-        std::lock_guard<std::recursive_mutex> lk(c->mu);
-        st = compute_launch(c, &rq->req, &rq->out, s, ar, pd);
-        if (st != IMF_OK) {
-          hipStreamSynchronize(s);
-          pd.tm.release();
-        }
-      }
-      if (st == IMF_OK) st = compute_finish(pd, &rq->stats);
+      st = run_request(c, &rq->req, &rq->out, &rq->stats, s, ar);
     }
     {
       std::lock_guard<std::mutex> lk(c->smu);

@@ -100,10 +100,80 @@ struct imf_orient_desc {
   int nlvl;            // sparse-table levels this orientation's runs need
   unsigned lvl_used;   // bit s-1 set: some run reads level s (others are not stored)
   int out_q;           // index of the orientation in the request (masks, gamma stack)
+  int set;             // fixture set of the orientation (its prefix sums)
   const imf_run* sruns;  // sharp-point runs along sv (x-runs for the sweep route)
   const imf_run* truns;  // x-runs of the tool T, row order (z, y)
   float2* spec;          // this orientation's tool spectrum [py][px/2+1][pz]
 };
+
+// Logical block order of the sharp-point minimum: bricks of 128 x 16 x 16
+// voxels (x chunk slowest, then z, y fastest), blocks of WX x WY x WZ voxels
+// inside a brick x, y, z fastest first.
+struct mf_geom {
+  int WX, WY, WZ;
+  int nbx, nby, nbz;      // blocks per axis
+  int brx, bry, brz;      // blocks per brick and axis
+  int nry, nrz;           // bricks along y, z
+  long long nlog;         // logical indices (bricks x blocks per brick)
+  __host__ __device__ mf_geom(int wx, int wy, int wz, int nx, int ny, int nz)
+      : WX(wx), WY(wy), WZ(wz) {
+    nbx = (nx + wx - 1) / wx;
+    nby = (ny + wy - 1) / wy;
+    nbz = (nz + wz - 1) / wz;
+    brx = 128 / wx;
+    bry = 16 / wy < nby ? 16 / wy : nby;
+    brz = 16 / wz < nbz ? 16 / wz : nbz;
+    const int nrx = (nbx + brx - 1) / brx;
+    nry = (nby + bry - 1) / bry;
+    nrz = (nbz + brz - 1) / brz;
+    nlog = (long long)nrx * nry * nrz * brx * bry * brz;
+  }
+  // block -> logical index (the inverse of block())
+  __device__ __forceinline__ long long logical(int bx, int by, int bz) const {
+    const long long brick = ((long long)(bx / brx) * nrz + bz / brz) * nry + by / bry;
+    const int wib = ((bz % brz) * bry + by % bry) * brx + bx % brx;
+    return brick * (brx * bry * brz) + wib;
+  }
+  // logical index -> block (false for the padding of partial bricks)
+  __device__ __forceinline__ bool block(long long lg, int& bx, int& by, int& bz) const {
+    const int br = brx * bry * brz;
+    const long long brick = lg / br;
+    const int wib = (int)(lg - brick * br);
+    const int ry = (int)(brick % nry);
+    const long long r = brick / nry;
+    const int rz = (int)(r % nrz);
+    const int rx = (int)(r / nrz);
+    bx = rx * brx + wib % brx;
+    by = ry * bry + (wib / brx) % bry;
+    bz = rz * brz + wib / (brx * bry);
+    return bx < nbx && by < nby && bz < nbz;
+  }
+};
+
+// exact overlap at translation t: sum over x-runs of T of row sums (Eq. ident)
+__device__ __forceinline__ long long exact_overlap(const imf_orient_desc& d,
+                                                   const long long* __restrict__ ps, int nx,
+                                                   int ny, int nz, int tx, int ty, int tz) {
+  const imf_run* rl = d.truns;
+  long long s = 0;
+  for (int r = 0; r < d.n_truns; r++) {
+    const imf_run u = rl[r];
+    const int y = ty + u.y, z = tz + u.z;
+    if (y < 0 || y >= ny || z < 0 || z >= nz) continue;
+    int x0 = tx + u.x, x1 = x0 + u.len;
+    x0 = max(x0, 0);
+    x1 = min(x1, nx);
+    if (x1 <= x0) continue;
+    const long long* row = ps + ((long long)z * ny + y) * (nx + 1);
+    s += row[x1] - row[x0];
+  }
+  return s;
+}
+
+__device__ __forceinline__ float wave_max_f(float v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
+}
 
 // FFT plan for one transform length: stages of the self-sorting transform.
 // Stage s has radix[s], Ns[s] = product of the earlier radices, and
@@ -181,8 +251,8 @@ struct imf_inv_args {
   // epilogue
   int binary;           // 1: round to integers and flag |g - rint g| > delta
   float delta;
-  int theta_known;      // density: flag |g - theta| <= band
-  double theta, band;
+  int nth;              // density: thresholds known in advance (0-2); flag |g - th| <= band
+  double th[2], band;
   unsigned int* max_err_bits;        // atomic max of |g - rint g| (binary)
   int* flag_cnt; int flag_cap; int2* flags;   // (q, linear box index)
   // optional: minima of g over the bound's cells (cwx x cwy x cwz, aligned to
@@ -198,13 +268,16 @@ hipError_t imf_launch_inverse(const imf_inv_args& a, const imf_fft_len& fx,
 // exact overlap by prefix sums along x (direct correlation and guard-band recheck)
 hipError_t imf_launch_prefix_x(const void* design, int density, const uint8_t* fixture, int nx,
                                int ny, int nz, long long* ps, hipStream_t s);
-hipError_t imf_launch_direct(const imf_orient_desc* desc, int nq, const long long* ps, int nx, int ny, int nz, int density, float* g,
-                             long long g_stride, int max_vol, hipStream_t s);
+// density: the exact value rounded to float32, then moved by ulps where needed
+// so that g32 <= th equals g <= th for each of the nth known thresholds
+hipError_t imf_launch_direct(const imf_orient_desc* desc, int nq, const long long* ps, int nx,
+                             int ny, int nz, int density, float* g, long long g_stride,
+                             int max_vol, int nth, double th0, double th1, hipStream_t s);
 hipError_t imf_launch_recheck(const imf_orient_desc* desc, const long long* ps, int nx, int ny, int nz, int density,
                               const int* flag_cnt, const int2* flags, int flag_cap,
-                              int theta_known, double theta, float* g, long long g_stride,
+                              int nth, double th0, double th1, float* g, long long g_stride,
                               unsigned int* cellmin, long long cell_stride, int cwx, int cwy,
-                              int cwz, hipStream_t s);
+                              int cwz, unsigned int* err_bits, hipStream_t s);
 
 // sharp-point min filter with running minimum, masks, optional gamma stack
 struct imf_min_args {
@@ -243,6 +316,8 @@ struct imf_min_args {
   unsigned int* fmax_up;    // two-phase: max of f over all voxels at the start of the batch
                             // (order-preserving bits; lambda times it bounds the threshold)
   double theta_lambda;      // lambda of the threshold bound lambda * fmax_up
+  double e_theta;           // bound E on the float32 overlap error (0: exact overlaps)
+  double fmargin;           // skip only where the bound exceeds max f by this (0: >=)
   int theta_known;
   int q0;                   // global index of the batch's first orientation
   int n_cu, wg_per_cu;      // resident workgroups of the list pass: CUs x per CU
@@ -270,6 +345,40 @@ struct imf_sweep_args {
 };
 hipError_t imf_launch_sweep(const imf_sweep_args& a, hipStream_t s);
 
+// exact threshold decisions of density requests at lambda F_max (k_exact.hip)
+struct imf_exact_args {
+  const imf_orient_desc* desc;  // [2 nO]: processing order, then the same orientations
+                                // with the x-runs of S as sruns
+  int nO;
+  int nx, ny, nz;
+  long long N;
+  const long long* ps; long long ps_stride;   // x prefix sums of rho_O, per fixture set
+  const float* f; const uint8_t* omega0;
+  const float* gamma;            // gamma stack [request orientation][N], or NULL
+  const unsigned long long* keep; long long kstride;  // kept-block bits per orientation or NULL
+  int WX, WY, WZ;                // block shape of those bits
+  const float* gst; long long gst_stride;   // g of every orientation (processing index), or NULL
+  double E;                      // bound on |g32 - g| (voxel units)
+  double scale;                  // voxel units per fixed-point unit (2^-24, or 1)
+  double lambda;
+  const unsigned int* fmax_bits; // float32 maximum of f over Omega_0 (order-preserving bits)
+  unsigned long long* Fq;        // exact F_max in fixed-point units
+  int* cand; unsigned int* cand_cnt; int cand_cap;    // candidate voxels of the maximum
+  int4* band; unsigned int* band_cnt; int band_cap;   // band entries (q, box index, g bits, 0)
+  unsigned int* err_bits;        // largest |g32 - g| seen by an exact recomputation (float bits)
+  unsigned int* n_exact;         // exact recomputations
+  uint64_t* masks;               // masks at lambda F_max, [request orientation][nz][ny][words]
+  const unsigned int* skip_scan; // nonzero: the band list is already complete, or NULL
+};
+hipError_t imf_launch_exact_fmax(const imf_exact_args& a, hipStream_t s);
+hipError_t imf_launch_fq_from_fmax(const unsigned int* fmax_bits, double inv_scale,
+                                   unsigned long long* Fq, hipStream_t s);
+hipError_t imf_launch_band_scan(const imf_exact_args& a, long long max_vol, hipStream_t s);
+hipError_t imf_launch_band_exact(const imf_exact_args& a, hipStream_t s);
+hipError_t imf_launch_finalize_exact(const imf_exact_args& a, const void* design, int density,
+                                     double tau, double Efin, float* imf_out, float* imf_norm,
+                                     uint8_t* secluded, hipStream_t s);
+
 // finalize
 hipError_t imf_launch_fill_f(float* f, long long n, float v, hipStream_t s);
 hipError_t imf_launch_fill_u32(unsigned int* p, long long n, unsigned int v, hipStream_t s);
@@ -279,13 +388,9 @@ hipError_t imf_launch_or_u8(const uint8_t* a, const uint8_t* b, uint8_t* out, lo
                             hipStream_t s);
 hipError_t imf_launch_fmax(const float* f, const uint8_t* omega0, long long n,
                            unsigned int* fmax_bits, hipStream_t s);
-hipError_t imf_launch_finalize(const float* f, const uint8_t* omega0, const void* design,
-                               int density, long long n, const unsigned int* fmax_bits,
-                               double lambda, double tau, float* imf_out, float* imf_norm,
-                               uint8_t* secluded, hipStream_t s);
 hipError_t imf_launch_masks_from_gamma(const float* gamma_stack, int nq, const uint8_t* omega0,
-                                       int nx, int ny, int nz, const unsigned int* fmax_bits,
-                                       double lambda, uint64_t* masks,
+                                       int nx, int ny, int nz, const unsigned long long* Fq,
+                                       double scale, double lambda, double E, uint64_t* masks,
                                        const unsigned long long* keep, int shape,
                                        long long kstride, hipStream_t s);
 

@@ -653,8 +653,9 @@ __global__ void __launch_bounds__(NTH) k_inv_x_c2r(imf_inv_args a, imf_fft_len L
         if (slot < a.flag_cap) a.flags[slot] = make_int2(q, (int)li);
       }
       v = G;
-    } else if (a.theta_known) {
-      if (fabs((double)v - a.theta) <= a.band) {
+    } else if (a.nth) {
+      if (fabs((double)v - a.th[0]) <= a.band ||
+          (a.nth > 1 && fabs((double)v - a.th[1]) <= a.band)) {
         const int slot = atomicAdd(a.flag_cnt, 1);
         if (slot < a.flag_cap) a.flags[slot] = make_int2(q, (int)li);
       }

@@ -5,10 +5,6 @@
 
 #define Q24 16777216.0
 
-__device__ __forceinline__ float wave_max_f(float v) {
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-  return v;
-}
 
 
 // ---------------------------------------------------------------------------
@@ -56,33 +52,35 @@ hipError_t imf_launch_prefix_x(const void* design, int density, const uint8_t* f
   return hipGetLastError();
 }
 
-// exact overlap at translation t: sum over x-runs of T of row sums (Eq. ident)
-__device__ __forceinline__ long long exact_overlap(const imf_orient_desc& d,
-                                                   const long long* __restrict__ ps, int nx,
-                                                   int ny, int nz, int tx, int ty, int tz) {
-  const imf_run* rl = d.truns;
-  long long s = 0;
-  for (int r = 0; r < d.n_truns; r++) {
-    const imf_run u = rl[r];
-    const int y = ty + u.y, z = tz + u.z;
-    if (y < 0 || y >= ny || z < 0 || z >= nz) continue;
-    int x0 = tx + u.x, x1 = x0 + u.len;
-    x0 = max(x0, 0);
-    x1 = min(x1, nx);
-    if (x1 <= x0) continue;
-    const long long* row = ps + ((long long)z * ny + y) * (nx + 1);
-    s += row[x1] - row[x0];
-  }
-  return s;
-}
-
 // ---------------------------------------------------------------------------
 // direct correlation over the query box (exact)
 // ---------------------------------------------------------------------------
+// float32 value of an exact overlap e (voxel units): rounded, then moved by
+// ulps so that the decision v <= th is the exact one for each known threshold
+__device__ __forceinline__ float decided_float(double e, int nth, double th0, double th1) {
+  float v = (float)e;
+  for (int it = 0; it < 4; it++) {
+    bool moved = false;
+    for (int k = 0; k < nth; k++) {
+      const double th = k ? th1 : th0;
+      if (e <= th && (double)v > th) {
+        v = nextafterf(v, -INFINITY);
+        moved = true;
+      } else if (e > th && (double)v <= th) {
+        v = nextafterf(v, INFINITY);
+        moved = true;
+      }
+    }
+    if (!moved) break;
+  }
+  return v;
+}
+
 __global__ void __launch_bounds__(IMF_WG) k_direct(const imf_orient_desc* __restrict__ desc,
                                                    const long long* __restrict__ ps, int nx,
                                                    int ny, int nz, int density,
-                                                   float* __restrict__ g, long long g_stride) {
+                                                   float* __restrict__ g, long long g_stride,
+                                                   int nth, double th0, double th1) {
   const int q = blockIdx.y;
   const imf_orient_desc& d = desc[q];
   const long long vol = (long long)d.box_dim[0] * d.box_dim[1] * d.box_dim[2];
@@ -93,14 +91,16 @@ __global__ void __launch_bounds__(IMF_WG) k_direct(const imf_orient_desc* __rest
   const int bz = (int)(i / ((long long)d.box_dim[0] * d.box_dim[1]));
   const long long s = exact_overlap(d, ps, nx, ny, nz, bx + d.box_lo[0],
                                     by + d.box_lo[1], bz + d.box_lo[2]);
-  g[q * g_stride + i] = density ? (float)((double)s * (1.0 / Q24)) : (float)s;
+  g[q * g_stride + i] =
+      density ? decided_float((double)s * (1.0 / Q24), nth, th0, th1) : (float)s;
 }
 
-hipError_t imf_launch_direct(const imf_orient_desc* desc, int nq, const long long* ps, int nx, int ny, int nz, int density, float* g,
-                             long long g_stride, int max_vol, hipStream_t s) {
+hipError_t imf_launch_direct(const imf_orient_desc* desc, int nq, const long long* ps, int nx,
+                             int ny, int nz, int density, float* g, long long g_stride,
+                             int max_vol, int nth, double th0, double th1, hipStream_t s) {
   dim3 grid((max_vol + IMF_WG - 1) / IMF_WG, nq);
   hipLaunchKernelGGL(k_direct, grid, dim3(IMF_WG), 0, s, desc, ps, nx, ny, nz, density, g,
-                     g_stride);
+                     g_stride, nth, th0, th1);
   return hipGetLastError();
 }
 
@@ -114,11 +114,11 @@ __global__ void __launch_bounds__(IMF_WG) k_recheck(const imf_orient_desc* __res
                                                     int ny, int nz, int density,
                                                     const int* __restrict__ flag_cnt,
                                                     const int2* __restrict__ flags, int flag_cap,
-                                                    int theta_known, double theta,
+                                                    int nth, double th0, double th1,
                                                     float* __restrict__ g, long long g_stride,
                                                     unsigned int* __restrict__ cellmin,
                                                     long long cell_stride, int cwx, int cwy,
-                                                    int cwz) {
+                                                    int cwz, unsigned int* __restrict__ err_bits) {
   const int n = min(*flag_cnt, flag_cap);
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
     const int2 f = flags[k];
@@ -134,15 +134,12 @@ __global__ void __launch_bounds__(IMF_WG) k_recheck(const imf_orient_desc* __res
       v = (float)s;
     } else {
       const double e = (double)s * (1.0 / Q24);
-      v = (float)e;
-      if (theta_known) {
-        const bool free_ = e <= theta;
-        for (int it = 0; it < 4; it++) {
-          if (free_ && (double)v > theta) v = nextafterf(v, -INFINITY);
-          else if (!free_ && (double)v <= theta) v = nextafterf(v, INFINITY);
-          else break;
-        }
+      if (err_bits) {  // the float32 transform's error at this overlap
+        const float er = (float)fabs((double)g[(long long)f.x * g_stride + i] - e);
+        if (__float_as_uint(er) > __atomic_load_n(err_bits, __ATOMIC_RELAXED))
+          atomicMax(err_bits, __float_as_uint(er));
       }
+      v = decided_float(e, nth, th0, th1);
     }
     g[(long long)f.x * g_stride + i] = v;
     if (cellmin) {  // the corrected value may lie below its cell's minimum
@@ -157,13 +154,13 @@ __global__ void __launch_bounds__(IMF_WG) k_recheck(const imf_orient_desc* __res
 
 hipError_t imf_launch_recheck(const imf_orient_desc* desc, const long long* ps, int nx, int ny, int nz, int density,
                               const int* flag_cnt, const int2* flags, int flag_cap,
-                              int theta_known, double theta, float* g, long long g_stride,
+                              int nth, double th0, double th1, float* g, long long g_stride,
                               unsigned int* cellmin, long long cell_stride, int cwx, int cwy,
-                              int cwz, hipStream_t s) {
+                              int cwz, unsigned int* err_bits, hipStream_t s) {
   const int blocks = flag_cap < 256 * 1024 ? (flag_cap + IMF_WG - 1) / IMF_WG : 1024;
   hipLaunchKernelGGL(k_recheck, dim3(blocks > 0 ? blocks : 1), dim3(IMF_WG), 0, s, desc, ps,
-                     nx, ny, nz, density, flag_cnt, flags, flag_cap, theta_known, theta, g,
-                     g_stride, cellmin, cell_stride, cwx, cwy, cwz);
+                     nx, ny, nz, density, flag_cnt, flags, flag_cap, nth, th0, th1, g,
+                     g_stride, cellmin, cell_stride, cwx, cwy, cwz, err_bits);
   return hipGetLastError();
 }
 
@@ -659,47 +656,6 @@ struct mf_run {
   long long off2;  // the second (overlapping) window
 };
 
-struct mf_geom {
-  int WX, WY, WZ;
-  int nbx, nby, nbz;      // blocks per axis
-  int brx, bry, brz;      // blocks per brick and axis
-  int nry, nrz;           // bricks along y, z
-  long long nlog;         // logical indices (bricks x blocks per brick)
-  __host__ __device__ mf_geom(int wx, int wy, int wz, int nx, int ny, int nz)
-      : WX(wx), WY(wy), WZ(wz) {
-    nbx = (nx + wx - 1) / wx;
-    nby = (ny + wy - 1) / wy;
-    nbz = (nz + wz - 1) / wz;
-    brx = 128 / wx;
-    bry = 16 / wy < nby ? 16 / wy : nby;
-    brz = 16 / wz < nbz ? 16 / wz : nbz;
-    const int nrx = (nbx + brx - 1) / brx;
-    nry = (nby + bry - 1) / bry;
-    nrz = (nbz + brz - 1) / brz;
-    nlog = (long long)nrx * nry * nrz * brx * bry * brz;
-  }
-  // block -> logical index (the inverse of block())
-  __device__ __forceinline__ long long logical(int bx, int by, int bz) const {
-    const long long brick = ((long long)(bx / brx) * nrz + bz / brz) * nry + by / bry;
-    const int wib = ((bz % brz) * bry + by % bry) * brx + bx % brx;
-    return brick * (brx * bry * brz) + wib;
-  }
-  // logical index -> block (false for the padding of partial bricks)
-  __device__ __forceinline__ bool block(long long lg, int& bx, int& by, int& bz) const {
-    const int br = brx * bry * brz;
-    const long long brick = lg / br;
-    const int wib = (int)(lg - brick * br);
-    const int ry = (int)(brick % nry);
-    const long long r = brick / nry;
-    const int rz = (int)(r % nrz);
-    const int rx = (int)(r / nrz);
-    bx = rx * brx + wib % brx;
-    by = ry * bry + (wib / brx) % bry;
-    bz = rz * brz + wib / (brx * bry);
-    return bx < nbx && by < nby && bz < nbz;
-  }
-};
-
 template <int WX>
 __device__ __forceinline__ void mf_store_chunk(uint64_t* row_words, int bx, uint64_t chunk) {
   if (WX == 64) row_words[bx] = chunk;
@@ -760,10 +716,19 @@ __global__ void __launch_bounds__(IMF_WG) k_bound(imf_min_args a, int qi) {
   const float lb = nfp < 0 ? -INFINITY : ord2f(lbo);
   const long long blk = ((long long)bz * G.nby + by) * G.nbx + bx;
   const float fb = live ? a.fblock[blk] : -INFINITY;
-  const bool need_mask = a.masks_on || a.gamma_stack;
-  double thu = a.theta;
-  if (need_mask && !a.theta_known) thu = a.theta_lambda * (double)ord2f(*a.fmax_up);
-  const bool sk = live && lb >= fb && (!need_mask || (double)lb > thu);
+  // f: no voxel's running minimum can fall (by more than fmargin below it:
+  // the candidates of an exact F_max need every gamma within 2E of f)
+  bool sk = live && (a.fmargin > 0 ? (double)lb > (double)fb + a.fmargin : lb >= fb);
+  // masks at a known threshold (exact after the recheck): no bit
+  if (a.masks_on) sk = sk && (double)lb > a.theta;
+  // masks or B at lambda F_max: F_max is at most the current maximum of f
+  // (plus E), so above that bound (plus E) no bit is set and no overlap of the
+  // band reaches the block
+  if (a.gamma_stack) {
+    double thu = a.theta_lambda * ((double)ord2f(*a.fmax_up) + a.e_theta) + a.e_theta;
+    if (a.e_theta > 0) thu *= 1.0 + 1e-12;
+    sk = sk && (double)lb > thu;
+  }
   const unsigned long long mw = __ballot(live && !sk);
   if ((threadIdx.x & 63) == 0 && lg < G.nlog) {
     a.wmask[(long long)qi * a.wstride + (lg >> 6)] = mw;
@@ -1296,48 +1261,15 @@ hipError_t imf_launch_fmax(const float* f, const uint8_t* omega0, long long n,
   return hipGetLastError();
 }
 
-// B = Omega_0 and f > lambda F_max; fbar = f / F_max on B, 0 elsewhere;
-// Gamma = B and not Omega, Omega = [rho_Omega > tau]   (Algorithm 1, Eq. gamma)
-__global__ void __launch_bounds__(IMF_WG) k_finalize(const float* __restrict__ f,
-                                                     const uint8_t* __restrict__ om,
-                                                     const void* __restrict__ design, int density,
-                                                     long long n,
-                                                     const unsigned int* __restrict__ fmax_bits,
-                                                     double lambda, double tau,
-                                                     float* __restrict__ imf_out,
-                                                     float* __restrict__ imf_norm,
-                                                     uint8_t* __restrict__ secluded) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double fmax = (double)ord2f(*fmax_bits);
-  const float v = f[i];
-  const bool inB = om[i] && (double)v > lambda * fmax;
-  if (imf_out) imf_out[i] = v;
-  if (imf_norm) imf_norm[i] = inB ? (float)((double)v / fmax) : 0.0f;
-  if (secluded) {
-    const double rho = density ? (double)((const float*)design)[i]
-                               : (double)((const uint8_t*)design)[i];
-    secluded[i] = (uint8_t)(inB && !(rho > tau));
-  }
-}
-hipError_t imf_launch_finalize(const float* f, const uint8_t* omega0, const void* design,
-                               int density, long long n, const unsigned int* fmax_bits,
-                               double lambda, double tau, float* imf_out, float* imf_norm,
-                               uint8_t* secluded, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3((unsigned)((n + IMF_WG - 1) / IMF_WG)), dim3(IMF_WG), 0, s,
-                     f, omega0, design, density, n, fmax_bits, lambda, tau, imf_out, imf_norm,
-                     secluded);
-  return hipGetLastError();
-}
-
 // masks from stored gamma once theta = lambda F_max is known.  One wave per
 // 64-voxel word of a row: Omega_0 is read once and the wave walks all
 // orientations (independent coalesced loads, one mask word each).
 __global__ void __launch_bounds__(IMF_WG) k_masks_gamma(const float* __restrict__ gs, int nq,
                                                         const uint8_t* __restrict__ om, int nx,
                                                         int ny, int nz,
-                                                        const unsigned int* __restrict__ fmax_bits,
-                                                        double lambda, uint64_t* __restrict__ masks,
+                                                        const unsigned long long* __restrict__ Fq,
+                                                        double scale, double lambda, double E,
+                                                        uint64_t* __restrict__ masks,
                                                         const unsigned long long* __restrict__ keep,
                                                         int WX, int WY, int WZ, long long kstride) {
   const int words = (nx + 63) >> 6;
@@ -1348,7 +1280,10 @@ __global__ void __launch_bounds__(IMF_WG) k_masks_gamma(const float* __restrict_
   const int w = (int)(wave % words);
   const long long yz = wave / words;
   const int x = w * 64 + lane;
-  const double theta = lambda * (double)ord2f(*fmax_bits);
+  // theta = lambda F_max as the definition takes it (fixed point), in voxel
+  // units; a bit is set here only where it is certain (gamma + E <= theta),
+  // the band around theta is decided from exact overlaps afterwards
+  const double theta = lambda * (double)*Fq * scale;
   const long long N = (long long)nx * ny * nz;
   const long long vi = yz * nx + (x < nx ? x : nx - 1);
   const bool in = x < nx && om[vi];
@@ -1385,20 +1320,20 @@ __global__ void __launch_bounds__(IMF_WG) k_masks_gamma(const float* __restrict_
         v[i] = (word_of(j + i) >> kbit) & 1 ? g[(long long)(qc + j + i) * N] : INFINITY;
 #pragma unroll
       for (int i = 0; i < 4; i++) {
-        const unsigned long long bits = __ballot(in && (double)v[i] <= theta);
+        const unsigned long long bits = __ballot(in && (double)v[i] + E <= theta);
         if (lane == 0) masks[(long long)(qc + j + i) * per_q + wave] = bits;
       }
     }
     for (; j < nc; j++) {
       const float v = (word_of(j) >> kbit) & 1 ? g[(long long)(qc + j) * N] : INFINITY;
-      const unsigned long long bits = __ballot(in && (double)v <= theta);
+      const unsigned long long bits = __ballot(in && (double)v + E <= theta);
       if (lane == 0) masks[(long long)(qc + j) * per_q + wave] = bits;
     }
   }
 }
 hipError_t imf_launch_masks_from_gamma(const float* gamma_stack, int nq, const uint8_t* omega0,
-                                       int nx, int ny, int nz, const unsigned int* fmax_bits,
-                                       double lambda, uint64_t* masks,
+                                       int nx, int ny, int nz, const unsigned long long* Fq,
+                                       double scale, double lambda, double E, uint64_t* masks,
                                        const unsigned long long* keep, int shape,
                                        long long kstride, hipStream_t s) {
   const int words = (nx + 63) >> 6;
@@ -1407,7 +1342,7 @@ hipError_t imf_launch_masks_from_gamma(const float* gamma_stack, int nq, const u
   int wx, wy, wz;
   imf_block_dims(shape, wx, wy, wz);
   hipLaunchKernelGGL(k_masks_gamma, dim3((unsigned)((waves + per - 1) / per)), dim3(IMF_WG), 0, s,
-                     gamma_stack, nq, omega0, nx, ny, nz, fmax_bits, lambda, masks, keep, wx, wy,
-                     wz, kstride);
+                     gamma_stack, nq, omega0, nx, ny, nz, Fq, scale, lambda, E, masks, keep, wx,
+                     wy, wz, kstride);
   return hipGetLastError();
 }

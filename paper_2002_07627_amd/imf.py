@@ -67,7 +67,9 @@ class _Stats(C.Structure):
                 ("k_bytes", C.c_double * 16), ("k_ops", C.c_double * 16),
                 ("bound_blocks", C.c_longlong), ("bound_skipped", C.c_longlong),
                 ("graph", C.c_int), ("lattice_runs", C.c_int), ("mf_shape", C.c_int),
-                ("mf_wg_per_cu", C.c_int)]
+                ("mf_wg_per_cu", C.c_int), ("max_abs_err", C.c_float),
+                ("post_exact", C.c_longlong), ("band_entries", C.c_longlong),
+                ("passes", C.c_int)]
 
 
 @dataclass
@@ -94,6 +96,10 @@ class Stats:
     lattice_runs: int  # orientations with sharp-point runs along a lattice vector
     mf_shape: int      # block shape of the sharp-point minimum (imf.h)
     mf_wg_per_cu: int  # resident workgroups per CU of its list pass
+    max_abs_err: float  # density: largest |g32 - g| an exact recomputation found
+    post_exact: int     # exact overlaps computed after the first pass
+    band_entries: int   # overlaps within guard_band of lambda F_max
+    passes: int         # 2 when lambda F_max was decided by a second pass
 
     @classmethod
     def _from(cls, s: _Stats):
@@ -104,7 +110,8 @@ class Stats:
         return cls(s.F_max, s.guard_flags, s.max_frac_err, s.guard_band, list(s.t_ms),
                    s.model_bytes, tuple(s.P), s.n_orient, s.method, s.batch, s.cache_hits,
                    s.cache_misses, kms, kn, kb, ko, s.bound_blocks, s.bound_skipped, s.graph,
-                   s.lattice_runs, s.mf_shape, s.mf_wg_per_cu)
+                   s.lattice_runs, s.mf_shape, s.mf_wg_per_cu, s.max_abs_err, s.post_exact,
+                   s.band_entries, s.passes)
 
 
 _lib = None

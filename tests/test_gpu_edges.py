@@ -85,6 +85,12 @@ def test_thin_grids_density_with_bound(shape, monkeypatch):
     fr = ref["imf"].reshape(f.shape)
     tol = 1e-4 * np.maximum(np.abs(fr), lam * ref["F_max"])
     assert np.all(np.abs(f - fr) <= tol)
+    # two-phase masks, F_max, B and Gamma: exact
+    assert st.F_max == ref["F_max"]
+    mk = host(out["masks"]).view(np.uint64)
+    assert np.array_equal(mk, ref["masks"].reshape(mk.shape))
+    assert np.array_equal(host(out["imf_norm"]) > 0, ref["imf_norm"].reshape(f.shape) > 0)
+    assert np.array_equal(host(out["secluded"]), ref["secluded"].reshape(f.shape))
 
 
 @pytest.mark.parametrize("radius", [13, 19])

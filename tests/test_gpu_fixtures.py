@@ -99,7 +99,7 @@ def test_identical_sets_equal_one_fixture(ctx):
 
 def test_density_sets_with_bound(monkeypatch):
     """Density design, absolute mask threshold, the branch-and-bound pass on:
-    f within 1e-4 relative, masks bit-exact."""
+    f within 1e-4 relative; masks, F_max, B and Gamma bit-exact."""
     import paper_2002_07627_amd as imf
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
@@ -130,6 +130,10 @@ def test_density_sets_with_bound(monkeypatch):
     tol = 1e-4 * np.maximum(np.abs(fref), lam * ref["F_max"])
     assert (np.abs(f - fref) <= tol).all(), np.abs(f - fref).max()
     assert np.array_equal(host(out["masks"]).view(np.uint64), ref["masks"])
+    # F_max, B and Gamma at lambda F_max: exact
+    assert st.F_max == ref["F_max"]
+    assert np.array_equal(host(out["imf_norm"]) > 0, ref["imf_norm"] > 0)
+    assert np.array_equal(host(out["secluded"]), ref["secluded"])
 
 
 def test_serving_and_graph_replay_follow_the_sets(ctx):

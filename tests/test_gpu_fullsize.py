@@ -115,8 +115,8 @@ def test_c3_256_density_130_sampled_within_tolerance(ctx):
     t = np.stack([rng.integers(0, box[a], 2048) for a in range(3)], axis=1)
     ref = oracle.overlap_at(req, qd, t + lo) / Q
     got = g[t[:, 2], t[:, 1], t[:, 0]]
-    # FP32 transform error model of the guard band: E = u log2(P^3) sqrt(N |T|)
-    E = st.guard_band / 2
+    # float32 transform error model of the guard band (E = 8 u sqrt(log2 P^3) |T|)
+    E = st.guard_band
     assert 0 < E < 0.5 * theta_of(w, F_max)
     assert (np.abs(got - ref) <= np.maximum(1e-4 * np.abs(ref), E)).all()
     # f at one voxel of Omega_0 against all 130 exact gammas
