@@ -67,26 +67,44 @@ def measured_traffic(kernel):
 
 
 # on-chip vector memory rate: 16 lanes (4-byte dwords) per clock per CU,
-# 256 CUs at 2.4 GHz -> 9.83e12 lane loads/s = 39.3 TB/s of gathered data
-GATHER_PEAK_GBS = 256 * 16 * 4 * 2.4
+# 256 CUs at 2.4 GHz -> 9.83e12 lane loads/s = 39.3 TB/s of gathered data.
+# Derived from unit counts, not a published peak: reported beside the HBM
+# roofline only, as the rate at which the sharp-point minimum gathers.
+GATHER_RATE_GBS = 256 * 16 * 4 * 2.4
 
 
-def roofline_of(cls, kms, kn, kb, ko):
-    """Roofline of one kernel class: the sharp-point minimum is bound by its
-    gathers (vector memory lane rate), every other class by HBM."""
+def minfilter_bytes_per_launch(st, N):
+    """Algorithmic HBM bytes of one launch of the sharp-point minimum (one
+    orientation): the query box of g read once (4 M^3, M^3 the orientation's box
+    volume), the running minimum f read and written (8 N^3), the orientation's
+    mask bits (N^3 / 8) and, for masks at lambda F_max, its gamma written (4 N^3)."""
+    return 4.0 * st.box_voxels / st.n_orient + N * (8.0 + 1.0 / 8.0 + 4.0)
+
+
+def roofline_of(cls, kms, kn, kb, ko, st=None, N=None):
+    """HBM roofline of one kernel class: algorithmic bytes per launch (the
+    minimum pass by the model above, the others by the library's count of
+    their compulsory reads and writes) over the event-timed launch duration."""
     avg_ms = kms[cls] / kn[cls]
     if cls == "minfilter":
-        work = 4.0 * ko[cls] / kn[cls]          # gathered bytes per launch
-        bound, peak = "alu", GATHER_PEAK_GBS
+        work = minfilter_bytes_per_launch(st, N)
     else:
-        work = kb[cls] / kn[cls]                # algorithmic HBM bytes per launch
-        bound, peak = "hbm", HBM_PEAK_GBS
+        work = kb[cls] / kn[cls]
     achieved = work / (avg_ms * 1e-3) / 1e9
-    return {"bound": bound, "achieved": round(achieved, 1), "peak": peak, "unit": "GB/s",
-            "frac": round(achieved / peak, 4), "traffic": measured_traffic(cls),
-            "kernel": cls, "avg_launch_ms": round(avg_ms, 4),
-            ("gathered_bytes_per_launch" if cls == "minfilter"
-             else "algorithmic_bytes_per_launch"): work}
+    traffic = measured_traffic(cls)
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+           "traffic_over_algorithmic": round(traffic / work, 3) if traffic else None,
+           "kernel": cls, "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": work}
+    if cls == "minfilter":
+        out["bytes_model"] = "4 M^3 + 8 N^3 + N^3/8 + 4 N^3 per orientation"
+        g = 4.0 * ko[cls] / kn[cls] / (avg_ms * 1e-3) / 1e9
+        out["gather_rate"] = {"achieved": round(g, 1), "unit": "GB/s",
+                              "vector_memory_lane_rate": GATHER_RATE_GBS,
+                              "frac": round(g / GATHER_RATE_GBS, 4),
+                              "note": "gathered lane bytes of the computed blocks; the lane "
+                                      "rate is derived from unit counts and clock"}
+    return out
 
 
 def serving_leg(imf, W, torch, n_req=64, load=0.7, seed=7627004):
@@ -169,8 +187,47 @@ def cpu_baseline(w, target_s=15.0):
     omp = os.environ.get("OMP_NUM_THREADS")
     if omp:
         cores = min(cores, int(omp))
+    # one core: the same pipeline in a child process with one OpenMP thread, on
+    # the smallest crop (its cost is the overlaps over the query box, whose
+    # sides are the crop plus the cutter's extent); scaled to the all-core
+    # sample by the ratio of the two query boxes
+    def box(m):
+        d = np.ascontiguousarray(w.design[:m, :m, :m])
+        info = oracle.orient_info(oracle.Request(d, None, tools=w.tool, dirs=w.dirs[k:k + 1],
+                                                 dir_kind=0), 0)
+        return float(np.prod([m + info["kmax"][a] - info["kmin"][a] for a in range(3)]))
+    n1 = 16
+    import subprocess
+    code = ("import sys, time; sys.path.insert(0, %r); import numpy as np; import oracle; "
+            "import workloads as W; w = W.c3(); n = %d; k = %d; "
+            "req = oracle.Request(np.ascontiguousarray(w.design[:n, :n, :n]), "
+            "np.ascontiguousarray(w.fixture[:n, :n, :n]), tools=w.tool, dirs=w.dirs[k:k + 1], "
+            "dir_kind=0, lam=w.lam); t = time.perf_counter(); oracle.imf(req, masks=False); "
+            "print(time.perf_counter() - t)" % (ROOT, n1, k))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    one = None
+    try:
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                           timeout=600)
+        t1c = float(r.stdout.strip().splitlines()[-1])
+        t_scaled = t1c * box(n) / box(n1)
+        one = {"value": n ** 3 / t_scaled, "cores": 1, "measured_s": round(t1c, 2),
+               "sample": "%d^3 corner crop, orientation %d, %.1f s on one core, scaled to the "
+                         "%d^3 sample by the query-box volume (%.0f s)"
+                         % (n1, k, t1c, n, t_scaled),
+               "parallel_speedup": round(t_scaled / t, 1)}
+    except Exception as e:  # the all-core figure stands alone
+        log("one-core oracle run failed: %s" % e)
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": n ** 3 / t, "unit": "voxel-orientations/s", "cores": cores,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": model, "one_core": one,
             "sample": "%d^3 corner crop of the 256^3 design + fixture, orientation %d of 130, "
                       "full oracle pipeline (int64 overlaps over the query box, sharp-point "
                       "min), %.1f s" % (n, k, t)}
@@ -274,7 +331,7 @@ def main():
             (k, v["ms_per_step"], v["launches_per_step"],
              "%.0f" % v["GBps"] if v["GBps"] else "-"))
     RUN_KERNELS.update(minfilter_kernels(stats[-1].mf_shape))
-    roofline = roofline_of(dom, kms, kn, kb, ko)
+    roofline = roofline_of(dom, kms, kn, kb, ko, stats[-1], N)
     # measured HBM traffic of the whole request: per-launch FETCH + WRITE bytes
     # of the committed counter runs times this run's launches, for the kernel
     # classes those runs cover (null when any of them changed since)
@@ -307,13 +364,17 @@ def main():
 
     plain = None
     if not args.no_plain:
-        t1 = time.perf_counter()
-        _, sp = ctx.compute(design, fixture, **dict(kw, batch=0), flags=imf.FLAG_PLAIN)
-        torch.cuda.synchronize()
-        tp = time.perf_counter() - t1
-        plain = {"value": N * nR / tp, "ms_per_step": 1000 * tp,
+        tps = []
+        for i in range(3):
+            t1 = time.perf_counter()
+            _, sp = ctx.compute(design, fixture, **dict(kw, batch=0), flags=imf.FLAG_PLAIN)
+            torch.cuda.synchronize()
+            tps.append(time.perf_counter() - t1)
+        tp = float(np.median(tps))
+        plain = {"value": N * nR / tp, "ms_per_step": 1000 * tp, "runs": 3,
+                 "ms_each": [round(1000 * t, 2) for t in tps],
                  "speedup": (N * nR / (el / args.steps)) / (N * nR / tp)}
-        log("plain path: %.1f ms" % (1000 * tp))
+        log("plain path: %.1f ms (median of 3)" % (1000 * tp))
     # TO-coupling steps on the same grid (pointwise, HBM-bound) and the greedy
     # machining plan from the request's masks
     coupling = None
@@ -420,8 +481,9 @@ def main():
         "setups": setups,
         "serving": serving,
         "kernels": kernels,
-        "guard": {"F_max": last.F_max, "max_frac_err": last.max_frac_err,
-                  "flags": last.guard_flags},
+        "guard": {"F_max": last.F_max, "E": last.guard_band, "max_abs_err": last.max_abs_err,
+                  "flags": last.guard_flags, "band_entries": last.band_entries,
+                  "post_exact": last.post_exact, "passes": last.passes},
         "bound": {"blocks": last.bound_blocks, "skipped": last.bound_skipped,
                   "frac": (last.bound_skipped / last.bound_blocks) if last.bound_blocks else None},
         "stream_copy_GBps": copy_gbs,

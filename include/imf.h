@@ -189,6 +189,7 @@ typedef struct {
   long long post_exact;    /* exact overlaps computed after the first pass (F_max, band) */
   long long band_entries;  /* overlaps within guard_band of lambda F_max */
   int passes;              /* 2 when theta = lambda F_max was decided by a second pass */
+  double box_voxels;       /* sum over orientations of the query-box volume M_x M_y M_z */
 } imf_stats;
 
 /* Bytes of device workspace the request needs (admission control).  The

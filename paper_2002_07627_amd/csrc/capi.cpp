@@ -1867,21 +1867,26 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
   // without room for the overlaps the band is decided by a second pass that
   // knows theta_B from this pass's exact F_max: this pass stops at F_max
   const bool second = p.exact && !p.gst;
+  tm.mark(13);
   if (p.known) {
     HIPCHK(imf_launch_fill_u32(misc + 16, 1, (unsigned)(p.known_Fq & 0xffffffffu), s));
     HIPCHK(imf_launch_fill_u32(misc + 17, 1, (unsigned)(p.known_Fq >> 32), s));
   } else if (p.exact) {
     HIPCHK(imf_launch_exact_fmax(ea, s));
+    tm.mark(9);
   } else {
     HIPCHK(imf_launch_fq_from_fmax(fmax_bits, 1.0 / p.scale, Fq, s));
   }
-  if (p.gam && !second && mB)
+  if (p.gam && !second && mB) {
     HIPCHK(imf_launch_masks_from_gamma(gstack, p.nO, om, r->nx, r->ny, r->nz, Fq, p.scale,
                                        r->lambda, p.exact ? p.E : 0.0, mB, keepbits, p.shape,
                                        p.nwords_blk, s));
+    tm.mark(13);
+  }
   if (p.exact && p.gst) {
     HIPCHK(imf_launch_band_scan(ea, p.max_vol, s));
     HIPCHK(imf_launch_band_exact(ea, s));
+    tm.mark(9);
   }
   if (!second)
     HIPCHK(imf_launch_finalize_exact(ea, r->design, r->design_is_density, r->tau,
@@ -2046,7 +2051,10 @@ static imf_status compute_finish(Pending& pd, imf_stats* st) {
     st->cache_hits = pd.hits;
     st->cache_misses = pd.misses;
     st->graph = pd.graph;
-    for (int q = 0; q < p.nO; q++) st->lattice_runs += p.desc[q].s_axis == 3;
+    for (int q = 0; q < p.nO; q++) {
+      st->lattice_runs += p.desc[q].s_axis == 3;
+      st->box_voxels += (double)p.desc[q].box_dim[0] * p.desc[q].box_dim[1] * p.desc[q].box_dim[2];
+    }
     st->mf_shape = p.shape;
     st->mf_wg_per_cu = p.wg_per_cu;
   } else {
