@@ -187,9 +187,13 @@ typedef struct {
    * found (the request fails with IMF_EACCURACY above guard_band / 2) */
   float max_abs_err;
   long long post_exact;    /* exact overlaps computed after the first pass (F_max, band) */
-  long long band_entries;  /* overlaps within guard_band of lambda F_max */
+  long long band_entries;  /* overlaps listed around lambda F_max: the band (within
+                              guard_band), or the wider bracket of an expected threshold */
   int passes;              /* 2 when theta = lambda F_max was decided by a second pass */
   double box_voxels;       /* sum over orientations of the query-box volume M_x M_y M_z */
+  int hinted;              /* lambda F_max expected from the last request of this shape:
+                              1 the listed bracket held the band, 2 it missed (the band was
+                              then scanned, or decided by a second pass), 0 no expectation */
 } imf_stats;
 
 /* Bytes of device workspace the request needs (admission control).  The

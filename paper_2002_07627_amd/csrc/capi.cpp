@@ -224,6 +224,15 @@ struct imf_ctx {
   // density requests at lambda F_max keep the overlaps of every orientation
   // when they fit (otherwise a second pass decides the band)
   bool overlap_stack = true;
+  // the exact F_max of the last density request at lambda F_max of each
+  // request shape (grid, tools, orientations, fixtures; not the design), and
+  // the relative width of the bracket listed around lambda times it next time
+  struct Hint {
+    unsigned long long Fq = 0;
+    double delta = 0;
+  };
+  std::map<std::string, Hint> hints;
+  bool use_hints = true;
 };
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -304,6 +313,7 @@ extern "C" imf_status imf_create(int device, size_t hbm_budget_bytes, imf_ctx** 
   if (const char* e = std::getenv("IMF_GIVEN_ORDER")) c->spread_order = std::atoi(e) == 0;
   if (const char* e = std::getenv("IMF_MINFILTER_SYNC")) c->mf_sync = std::atoi(e);
   if (const char* e = std::getenv("IMF_OVERLAP_STACK")) c->overlap_stack = std::atoi(e) != 0;
+  if (const char* e = std::getenv("IMF_THRESHOLD_HINTS")) c->use_hints = std::atoi(e) != 0;
   if (const char* e = std::getenv("IMF_MINFILTER_WG_PER_CU"))
     c->mf_wg_per_cu = std::max(1, std::min(16, std::atoi(e)));
   if (hipStreamCreateWithFlags(&c->internal, hipStreamNonBlocking) != hipSuccess) {
@@ -968,6 +978,12 @@ struct Plan {
   bool intmask = false;           // masks at theta_B in the workspace (exact, no such output)
   bool gst = false;               // g of every orientation kept (band scan)
   int band_cap = 0, cand_cap = 0;
+  // an expected threshold (the last exact F_max of this request shape): the
+  // inverse x pass lists the overlaps of the bracket (blo, bhi] (voxel units),
+  // which replaces the band scan (or the second pass) when it holds the band
+  std::string hint_key;
+  bool hinted = false;
+  double blo = 0, bhi = 0, hint_delta = 0;
   // workspace layout (bytes)
   size_t ws_bytes;
   long long spec_elems;
@@ -1167,6 +1183,30 @@ static imf_status make_plan(imf_ctx* c, const imf_request* r, const imf_outputs*
   p.exact = r->design_is_density && !p.thB_known;
   p.gam = p.two_phase || p.exact;
   p.intmask = p.exact && !p.two_phase;
+  // expected threshold: transform path, no first-pass recheck (the listed
+  // values are the ones the minimum pass reads)
+  p.hinted = false;
+  if (p.exact && p.method == IMF_METHOD_FFT && !p.theta_known) {
+    std::string k;
+    auto put = [&](const void* v, size_t n) { k.append((const char*)v, n); };
+    const long long ki[] = {r->nx, r->ny, r->nz, r->dir_kind, r->sharp, r->n_tools,
+                            r->n_fixture_sets};
+    put(ki, sizeof ki);
+    put(&r->lambda, sizeof(double));
+    const void* kp[] = {r->fixture, r->domain, r->fixture_sets};
+    put(kp, sizeof kp);
+    for (const auto& key : p.keys) k += key + "|";
+    if (r->n_fixture_sets) put(r->fixture_of, sizeof(int) * (size_t)p.nO);
+    p.hint_key = k;
+    auto it = c->hints.find(k);
+    if (c->use_hints && it != c->hints.end()) {
+      p.hinted = true;
+      p.hint_delta = it->second.delta;
+      const double th = r->lambda * (double)it->second.Fq * p.scale;
+      p.blo = th * (1.0 - p.hint_delta) - p.E;
+      p.bhi = th * (1.0 + p.hint_delta) + p.E;
+    }
+  }
   if (p.known && p.two_phase) {  // second pass: the masks' threshold is theta_B
     p.two_phase = false;
     p.gam = false;
@@ -1218,9 +1258,10 @@ static imf_status make_plan(imf_ctx* c, const imf_request* r, const imf_outputs*
   if (p.intmask) add(sizeof(uint64_t) * p.nO * (long long)r->nz * r->ny * p.words);  // masks at theta_B
   if (p.exact) {
     p.cand_cap = 1 << 16;
-    p.band_cap = 1 << 23;
+    p.band_cap = 1 << 24;
     add(sizeof(int) * (size_t)p.cand_cap);               // candidates of the maximum
     add(sizeof(int4) * (size_t)p.band_cap);              // band entries
+    add(sizeof(unsigned) * (size_t)p.nO * IMF_BR_SLICES);  // bracket list counts
   }
   if (p.bnb) {
     add(sizeof(float) * p.B * p.cell_stride);           // cell minima
@@ -1387,6 +1428,7 @@ struct Pending {
   int kept_at = -1;         // offset of the kept counts in host[], or -1
   int graph = 0;            // 0 kernel by kernel, 1 captured and launched, 2 replayed
   unsigned long long Fq = 0;  // exact F_max (fixed point) once finished
+  bool hint_ok = false;       // the listed bracket held the band of lambda F_max
 };
 
 // Enqueue the whole request on stream s (no host synchronization after the
@@ -1430,7 +1472,8 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
   // [4] max f at a batch's start, [8..9] skipped pairs, [16..17] F_max in
   // fixed point, [18] candidates of the maximum, [19] band entries, [20] max
   // |g32 - g| of exact recomputations (density), [21] exact recomputations of
-  // the post pass
+  // the post pass, [22] 1 when the expected threshold's bracket held the band,
+  // [23] entries of the bracket lists
   unsigned int* fmax_bits = misc;
   unsigned int* maxerr_bits = misc + 1;
   unsigned long long* Fq = (unsigned long long*)(misc + 16);
@@ -1449,6 +1492,8 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
       p.intmask ? carve<uint64_t>(ar, (size_t)p.nO * r->nz * r->ny * p.words) : nullptr;
   int* cand = p.exact ? carve<int>(ar, p.cand_cap) : nullptr;
   int4* band = p.exact ? carve<int4>(ar, p.band_cap) : nullptr;
+  unsigned* bcnt = p.exact ? carve<unsigned>(ar, (size_t)p.nO * IMF_BR_SLICES) : nullptr;
+  const int bslot = p.exact ? (int)(p.band_cap / ((long long)p.nO * IMF_BR_SLICES)) : 0;
   unsigned int* cellmin = p.bnb ? carve<unsigned int>(ar, p.B * p.cell_stride) : nullptr;
   // the bound's cell minima come from the inverse x pass (and the recheck)
   // on the transform path, from a pass over g on the direct path
@@ -1571,6 +1616,9 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
     put(p.P, sizeof(p.P));
     put(&p.gst, sizeof(p.gst));
     put(&p.known_Fq, sizeof(p.known_Fq));
+    put(&p.hinted, sizeof(p.hinted));
+    const double br[2] = {p.blo, p.bhi};
+    put(br, sizeof br);
     put(&ar.base, sizeof(ar.base));
     put(&ar.host, sizeof(ar.host));
     const void* tws[3] = {twx, twy, twz};
@@ -1593,6 +1641,7 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
     fix_all = uni;
   }
   HIPCHK(imf_launch_omega0(fix_all, r->domain, om, N, s));
+  if (p.hinted) HIPCHK(imf_launch_fill_u32(bcnt, (long long)p.nO * IMF_BR_SLICES, 0u, s));
   HIPCHK(imf_launch_fill_f(f, N, INFINITY, s));
   if (fblock) HIPCHK(imf_launch_fill_f(fblock, p.nblocks, INFINITY, s));
   // the minimum pass writes the mask chunks of the blocks it computes: clear
@@ -1710,6 +1759,14 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
       ia.flag_cnt = flag_cnt + b;
       ia.flag_cap = flag_cap;
       ia.flags = flags;
+      if (p.hinted) {
+        ia.blist = band;
+        ia.bcnt = bcnt;
+        ia.bslot = bslot;
+        ia.blo = p.blo;
+        ia.bhi = p.bhi;
+        ia.q0 = q0;
+      }
       ia.cellmin = cm_fused ? cellmin : nullptr;
       ia.cell_stride = p.cell_stride;
       ia.cwx = cwx;
@@ -1864,15 +1921,25 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
   ea.n_exact = misc + 21;
   uint64_t* const mB = p.two_phase ? out->acc_masks : intmask;  // masks at theta_B
   ea.masks = mB;
-  // without room for the overlaps the band is decided by a second pass that
-  // knows theta_B from this pass's exact F_max: this pass stops at F_max
-  const bool second = p.exact && !p.gst;
+  // without room for the overlaps (and no expected threshold) the band is
+  // decided by a second pass that knows theta_B from this pass's exact F_max:
+  // this pass stops at F_max
+  const bool second = p.exact && !p.gst && !p.hinted;
+  // misc[22]: 1 when the listed bracket holds the band (no scan, no second pass)
+  ea.skip_scan = p.hinted ? misc + 22 : nullptr;
+  if (p.hinted) {
+    ea.blist = band;
+    ea.bcnt = bcnt;
+    ea.bslot = bslot;
+  }
+  ea.blisted = misc + 23;
   tm.mark(13);
   if (p.known) {
     HIPCHK(imf_launch_fill_u32(misc + 16, 1, (unsigned)(p.known_Fq & 0xffffffffu), s));
     HIPCHK(imf_launch_fill_u32(misc + 17, 1, (unsigned)(p.known_Fq >> 32), s));
   } else if (p.exact) {
     HIPCHK(imf_launch_exact_fmax(ea, s));
+    if (p.hinted) HIPCHK(imf_launch_bracket_check(ea, p.blo, p.bhi, misc + 22, s));
     tm.mark(9);
   } else {
     HIPCHK(imf_launch_fq_from_fmax(fmax_bits, 1.0 / p.scale, Fq, s));
@@ -1883,8 +1950,10 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
                                        p.nwords_blk, s));
     tm.mark(13);
   }
-  if (p.exact && p.gst) {
-    HIPCHK(imf_launch_band_scan(ea, p.max_vol, s));
+  if (p.exact && (p.gst || p.hinted)) {
+    // the band: from the listed bracket when it holds it, else from a scan of
+    // the stored overlaps (without them a second pass follows)
+    if (p.gst) HIPCHK(imf_launch_band_scan(ea, p.max_vol, s));
     HIPCHK(imf_launch_band_exact(ea, s));
     tm.mark(9);
   }
@@ -1988,6 +2057,7 @@ static imf_status compute_finish(Pending& pd, imf_stats* st) {
     total_flags += n;
   }
   std::memcpy(&pd.Fq, &pd.host[16], 8);
+  pd.hint_ok = p.hinted && pd.host[22] == 1u;
   float derr;
   std::memcpy(&derr, &pd.host[20], 4);
   if (p.exact && pd.host[18] > (unsigned)p.cand_cap) {
@@ -2016,9 +2086,10 @@ static imf_status compute_finish(Pending& pd, imf_stats* st) {
     st->max_frac_err = me;
     st->max_abs_err = derr;
     st->post_exact = pd.host[21];
-    st->band_entries = pd.host[19];
+    st->band_entries = pd.hint_ok ? pd.host[23] : pd.host[19];
     st->guard_flags = total_flags + pd.host[21];
     st->passes = 1;
+    st->hinted = p.hinted ? (pd.hint_ok ? 1 : 2) : 0;
     if (p.bnb) {
       unsigned long long sk;
       std::memcpy(&sk, &pd.host[8], 8);
@@ -2074,6 +2145,7 @@ static imf_status run_request(imf_ctx* c, const imf_request* r, const imf_output
   unsigned long long known = 0;
   double t_first = 0;
   long long flags_first = 0;
+  int hinted_first = 0;
   for (int pass = 0; pass < 2; pass++) {
     Pending pd;
     imf_status e;
@@ -2089,11 +2161,22 @@ static imf_status run_request(imf_ctx* c, const imf_request* r, const imf_output
     imf_stats tmp{};
     e = compute_finish(pd, st ? st : &tmp);
     if (e != IMF_OK) return e;
-    if (!(pd.p.exact && !pd.p.gst)) {
+    if (pd.p.exact && !pd.p.hint_key.empty()) {
+      // remember the exact F_max; a bracket that missed widens next time
+      std::lock_guard<std::recursive_mutex> lk(c->mu);
+      imf_ctx::Hint h;
+      h.Fq = pd.Fq;
+      h.delta = !pd.p.hinted ? 0.004 : pd.hint_ok ? pd.p.hint_delta
+                                                  : std::min(0.06, 4.0 * pd.p.hint_delta);
+      c->hints[pd.p.hint_key] = h;
+      if (c->hints.size() > 4096) c->hints.clear();
+    }
+    if (!(pd.p.exact && !pd.p.gst && !pd.hint_ok)) {
       if (st && pass) {
         st->passes = 2;
         st->t_ms[7] += t_first;
         st->guard_flags += flags_first;
+        st->hinted = hinted_first;
       }
       return IMF_OK;
     }
@@ -2101,6 +2184,7 @@ static imf_status run_request(imf_ctx* c, const imf_request* r, const imf_output
     if (st) {
       t_first = st->t_ms[7];
       flags_first = st->guard_flags;
+      hinted_first = st->hinted;
     }
   }
   return fail(IMF_EDEVICE, "second pass did not settle the threshold");

@@ -258,7 +258,13 @@ struct imf_inv_args {
   // optional: minima of g over the bound's cells (cwx x cwy x cwz, aligned to
   // the box), per q [cdz][cdy][cdx] as f2ord values, lowered by atomic min
   unsigned int* cellmin; long long cell_stride; int cwx, cwy, cwz;
+  // optional (density at lambda F_max with an expected threshold): overlaps
+  // with blo < g <= bhi appended as (q0 + q, box index, g bits, 0) to one of
+  // IMF_BR_SLICES lists per orientation (slice of the workgroup: the appends
+  // spread over many counters), list s at blist + s * bslot, count bcnt[s]
+  int4* blist; unsigned int* bcnt; int bslot; double blo, bhi; int q0;
 };
+#define IMF_BR_SLICES 64
 // stage: -1 all, 0 product + z pass, 1 y pass, 2 x pass (complex-to-real) + epilogue
 hipError_t imf_launch_inverse(const imf_inv_args& a, const imf_fft_len& fx,
                               const imf_fft_len& fy, const imf_fft_len& fz, const float2* twx,
@@ -369,11 +375,19 @@ struct imf_exact_args {
   unsigned int* n_exact;         // exact recomputations
   uint64_t* masks;               // masks at lambda F_max, [request orientation][nz][ny][words]
   const unsigned int* skip_scan; // nonzero: the band list is already complete, or NULL
+  // bracket lists of the inverse x pass (IMF_BR_SLICES per orientation), or NULL
+  const int4* blist; const unsigned int* bcnt; int bslot;
+  unsigned int* blisted;         // total entries the bracket lists hold
 };
 hipError_t imf_launch_exact_fmax(const imf_exact_args& a, hipStream_t s);
 hipError_t imf_launch_fq_from_fmax(const unsigned int* fmax_bits, double inv_scale,
                                    unsigned long long* Fq, hipStream_t s);
 hipError_t imf_launch_band_scan(const imf_exact_args& a, long long max_vol, hipStream_t s);
+// after the exact F_max: the listed bracket (blo, bhi] holds the band of lambda
+// F_max (and did not overflow) -> *ok = 1; otherwise *ok = 0 and the list is
+// emptied for the scan
+hipError_t imf_launch_bracket_check(const imf_exact_args& a, double blo, double bhi,
+                                    unsigned int* ok, hipStream_t s);
 hipError_t imf_launch_band_exact(const imf_exact_args& a, hipStream_t s);
 hipError_t imf_launch_finalize_exact(const imf_exact_args& a, const void* design, int density,
                                      double tau, double Efin, float* imf_out, float* imf_norm,

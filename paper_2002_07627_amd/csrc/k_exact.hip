@@ -200,6 +200,40 @@ __global__ void __launch_bounds__(IMF_WG) k_band_scan(imf_exact_args a) {
   }
 }
 
+// one workgroup: no bracket list overflowed, and the band (thv - E, thv + E]
+// lies inside the listed bracket (blo, bhi]
+__global__ void __launch_bounds__(1024) k_bracket_check(imf_exact_args a, double blo, double bhi,
+                                                        unsigned int* ok) {
+  __shared__ unsigned int over, total;
+  if (threadIdx.x == 0) {
+    over = 0;
+    total = 0;
+  }
+  __syncthreads();
+  const long long nsl = (long long)a.nO * IMF_BR_SLICES;
+  unsigned o = 0, t = 0;
+  for (long long i = threadIdx.x; i < nsl; i += blockDim.x) {
+    const unsigned c = a.bcnt[i];
+    o |= c > (unsigned)a.bslot;
+    t += c;
+  }
+  if (o) atomicOr(&over, 1u);
+  atomicAdd(&total, t);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double thq, thv;
+    thresholds(a, thq, thv);
+    const bool in = !over && thv - a.E >= blo && thv + a.E <= bhi;
+    *ok = in ? 1u : 0u;
+    *a.blisted = total;
+  }
+}
+hipError_t imf_launch_bracket_check(const imf_exact_args& a, double blo, double bhi,
+                                    unsigned int* ok, hipStream_t s) {
+  hipLaunchKernelGGL(k_bracket_check, dim3(1), dim3(1024), 0, s, a, blo, bhi, ok);
+  return hipGetLastError();
+}
+
 hipError_t imf_launch_band_scan(const imf_exact_args& a, long long max_vol, hipStream_t s) {
   const long long per = (max_vol + IMF_WG - 1) / IMF_WG;
   const unsigned gx = (unsigned)(per < 512 ? (per > 0 ? per : 1) : 512);
@@ -207,22 +241,21 @@ hipError_t imf_launch_band_scan(const imf_exact_args& a, long long max_vol, hipS
   return hipGetLastError();
 }
 
-// One wave per band entry: the exact overlap; at or below theta, the cutter
+// One band entry on one wave: the exact overlap; at or below theta, the cutter
 // swept from that translation (the x-runs of S) sets the mask bits of the
 // voxels of Omega_0 it covers (atomic or; these voxels have gamma within E of
-// theta or below, so no bit set here is a certain zero).
-__global__ void __launch_bounds__(IMF_WG) k_band_exact(imf_exact_args a) {
+// theta or below, so no bit set here is a certain zero).  Bracket entries
+// outside the band are left alone.
+__device__ __forceinline__ void band_entry(const imf_exact_args& a, const int4 ent, double thq,
+                                           double thv, float& err, unsigned int& evals) {
   const int lane = threadIdx.x & 63;
-  const long long n = min((long long)*a.band_cnt, (long long)a.band_cap);
-  double thq, thv;
-  thresholds(a, thq, thv);
   const int words = (a.nx + 63) >> 6;
   const long long per_q = (long long)words * a.ny * a.nz;
-  float err = 0.f;
-  unsigned int evals = 0;
-  for (long long e = (long long)blockIdx.x * (IMF_WG / 64) + (threadIdx.x >> 6); e < n;
-       e += (long long)gridDim.x * (IMF_WG / 64)) {
-    const int4 ent = a.band[e];
+  {
+    const double g = (double)__int_as_float(ent.z);
+    if (g + a.E <= thv || g - a.E > thv) return;
+  }
+  {
     const int q = ent.x;
     const long long li = ent.y;
     const imf_orient_desc& d = a.desc[q];
@@ -234,7 +267,7 @@ __global__ void __launch_bounds__(IMF_WG) k_band_exact(imf_exact_args a) {
                                            ty, tz);
     evals++;
     err = fmaxf(err, (float)fabs((double)__int_as_float(ent.z) - (double)s * a.scale));
-    if (!((double)s <= thq)) continue;
+    if (!((double)s <= thq)) return;
     const imf_orient_desc& sd = a.desc[a.nO + q];
     uint64_t* mq = a.masks + (long long)d.out_q * per_q;
     for (int r = lane; r < sd.n_sruns; r += 64) {
@@ -254,6 +287,28 @@ __global__ void __launch_bounds__(IMF_WG) k_band_exact(imf_exact_args a) {
           atomicOr((unsigned long long*)(row + w), (unsigned long long)bits);
         x = xe;
       }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(IMF_WG) k_band_exact(imf_exact_args a) {
+  const int lane = threadIdx.x & 63;
+  double thq, thv;
+  thresholds(a, thq, thv);
+  float err = 0.f;
+  unsigned int evals = 0;
+  const long long wave = (long long)blockIdx.x * (IMF_WG / 64) + (threadIdx.x >> 6);
+  const long long nwaves = (long long)gridDim.x * (IMF_WG / 64);
+  // the scanned list
+  const long long n = min((long long)*a.band_cnt, (long long)a.band_cap);
+  for (long long e = wave; e < n; e += nwaves) band_entry(a, a.band[e], thq, thv, err, evals);
+  // the bracket lists, when they hold the band (a wave per list)
+  if (a.blist && *a.skip_scan) {
+    const long long nsl = (long long)a.nO * IMF_BR_SLICES;
+    for (long long sl = wave; sl < nsl; sl += nwaves) {
+      const unsigned c = min(a.bcnt[sl], (unsigned)a.bslot);
+      for (unsigned e = 0; e < c; e++)
+        band_entry(a, a.blist[sl * a.bslot + e], thq, thv, err, evals);
     }
   }
   for (int o = 32; o > 0; o >>= 1) err = fmaxf(err, __shfl_xor(err, o));

@@ -292,6 +292,39 @@ def test_density_second_pass_without_stored_overlaps(masks, monkeypatch):
     assert st.passes == 2
 
 
+@pytest.mark.parametrize("stack", ["1", "0"])
+def test_density_expected_threshold_bracket(stack, monkeypatch):
+    """A request shape seen before lists the overlaps around lambda times its
+    last F_max during the inverse transform: the same request again holds the
+    band in that bracket (no scan, no second pass); a different design of the
+    same shape may miss it and then takes the scan (or the second pass).  Every
+    result is exact."""
+    import paper_2002_07627_amd as imf
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    monkeypatch.setenv("IMF_OVERLAP_STACK", stack)
+    tl = W.tool(W.TOOL_BALL, 2, 7, 3, 5)
+    dirs = W.fib_hemisphere(9)
+    lam = 0.04
+    d1 = W.design_density(30, seed=17)
+    d2 = W.quantize_q24(np.clip(d1 * 0.7, 0, 1).astype(np.float32))
+    fx = W.fixture_plate(d1.shape, 2)
+    c = imf.Context(0)
+    try:
+        seen = []
+        for d in (d1, d1, d2, d2):
+            out, st = c.compute(dev(d), dev(fx), tools=tl, dirs=dirs, lam=lam,
+                                method=imf.METHOD_FFT, flags=imf.FLAG_NO_GRAPH)
+            ref = oracle.imf(oracle.Request(d, fx, tools=tl, dirs=dirs, dir_kind=0, lam=lam))
+            check_density(out, st, ref, lam)
+            seen.append((st.hinted, st.passes))
+    finally:
+        c.close()
+    assert seen[0] == (0, 1 if stack == "1" else 2)
+    assert seen[1] == (1, 1)
+    assert seen[2][0] in (1, 2) and seen[3] == (1, 1)
+
+
 def test_density_lambda_zero_and_no_masks(ctx):
     """lambda = 0: B = [f > 0] decided by the first-pass recheck around 0; and
     lambda > 0 without mask outputs: B from masks kept in the workspace."""
