@@ -21,6 +21,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -154,6 +156,56 @@ def serving_leg(imf, W, torch, n_req=64, load=0.7, seed=7627004):
             "saturation_vo_per_s": vo / t_sat}
 
 
+def to_loop_leg(imf, W, torch, iters):
+    """The TO-loop workload: a 384^3 density design with fixture plate and two
+    clamp blocks, flat cutter r3 L80 + holder r12 L80, 512 Fibonacci-hemisphere
+    orientations, lambda 0.01, masks at lambda F_max; every iteration perturbs
+    rho by seeded smooth noise (amplitude 0.05, generated on the device) and
+    recomputes the IMF on one context, so tool spectra are reused (those that
+    fit the cache) and lambda times the last F_max is the expected threshold.
+    Reports seconds per iteration and each iteration's cache hits, passes and
+    whether the expected threshold's bracket held."""
+    w = W.c5()
+    dev = torch.device("cuda:0")
+    fx = torch.from_numpy(w.fixture).to(dev)
+    rho = torch.from_numpy(w.design).to(dev)
+    kw = dict(tools=w.tool, dirs=w.dirs, dir_kind=imf.DIR_F64, lam=w.lam, tau=w.tau,
+              method=imf.METHOD_FFT)
+    ctx = imf.Context(0)
+    its = []
+    out = None
+    try:
+        for i in range(iters):
+            if i:
+                rho = W.perturb_density_device(rho, seed=7627005 + i)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            out, st = ctx.compute(rho, fx, **kw, out=out)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            its.append({"s": round(dt, 4), "hits": st.cache_hits, "misses": st.cache_misses,
+                        "passes": st.passes, "hinted": st.hinted, "F_max": st.F_max,
+                        "listed": st.band_entries})
+            log("TO loop iteration %d: %.2f s (spectra cached %d, computed %d, passes %d, "
+                "bracket %s, %d listed, F_max %.4f)" % (
+                    i, dt, st.cache_hits, st.cache_misses, st.passes,
+                    {0: "-", 1: "held", 2: "missed", 3: "overflowed"}[st.hinted],
+                    st.band_entries, st.F_max))
+    finally:
+        ctx.close()
+        del out
+        torch.cuda.empty_cache()
+    N = int(np.prod(w.design.shape))
+    steady = [x["s"] for x in its[1:]] or [its[0]["s"]]
+    return {"workload": "384^3 density, fixture plate + clamps, flat r3 L80 + holder r12 L80, "
+                        "512 Fibonacci-hemisphere orientations, lambda 0.01, masks at "
+                        "lambda*F_max, rho perturbed each iteration (amplitude 0.05)",
+            "iterations": len(its), "s_per_iteration_median": float(np.median(steady)),
+            "s_first_iteration": its[0]["s"], "s_total": float(sum(x["s"] for x in its)),
+            "voxel_orientations_per_s": N * len(w.dirs) / float(np.median(steady)),
+            "per_iteration": its}
+
+
 def cpu_baseline(w, target_s=15.0):
     """The CPU oracle as it stands on a crop of the same workload: the full
     pipeline (exact overlaps over the query box, sharp-point minimum, masks off)
@@ -248,6 +300,9 @@ def main():
                          "kernel for the FETCH_SIZE / WRITE_SIZE counter scale); on by default "
                          "unless --no-copy-probe")
     ap.add_argument("--no-copy-probe", action="store_true")
+    ap.add_argument("--to-loop-iters", type=int, default=50,
+                    help="iterations of the 384^3 x 512 TO loop (0: skip the leg)")
+    ap.add_argument("--only-to-loop", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the IMF path here runs on a single MI355X "
@@ -255,11 +310,14 @@ def main():
               "note, not built)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_2002_07627_amd as imf
     import workloads as W
+
+    if args.only_to_loop:
+        print(json.dumps({"to_loop": to_loop_leg(imf, W, torch, args.to_loop_iters)}), flush=True)
+        return
 
     copy_gbs = None
     if args.copy_probe or not args.no_copy_probe:
@@ -448,6 +506,13 @@ def main():
             serving["p50_ms"], serving["p99_ms"], serving["throughput_vo_per_s"]))
         torch.cuda.empty_cache()
 
+    to_loop = None
+    if args.to_loop_iters > 0:
+        log("TO loop: 384^3 x 512 orientations, %d iterations" % args.to_loop_iters)
+        to_loop = to_loop_leg(imf, W, torch, args.to_loop_iters)
+        log("TO loop: %.2f s per iteration (median), first %.2f s" % (
+            to_loop["s_per_iteration_median"], to_loop["s_first_iteration"]))
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
@@ -480,6 +545,7 @@ def main():
         "coupling": coupling,
         "setups": setups,
         "serving": serving,
+        "to_loop": to_loop,
         "kernels": kernels,
         "guard": {"F_max": last.F_max, "E": last.guard_band, "max_abs_err": last.max_abs_err,
                   "flags": last.guard_flags, "band_entries": last.band_entries,

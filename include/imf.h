@@ -191,9 +191,10 @@ typedef struct {
                               guard_band), or the wider bracket of an expected threshold */
   int passes;              /* 2 when theta = lambda F_max was decided by a second pass */
   double box_voxels;       /* sum over orientations of the query-box volume M_x M_y M_z */
-  int hinted;              /* lambda F_max expected from the last request of this shape:
-                              1 the listed bracket held the band, 2 it missed (the band was
-                              then scanned, or decided by a second pass), 0 no expectation */
+  int hinted;              /* lambda F_max expected from the last requests of this shape:
+                              1 the listed bracket held the band, 2 it missed, 3 its lists
+                              overflowed (2, 3: the band was then scanned, or decided by a
+                              second pass), 0 no expectation */
 } imf_stats;
 
 /* Bytes of device workspace the request needs (admission control).  The

@@ -228,8 +228,8 @@ struct imf_ctx {
   // request shape (grid, tools, orientations, fixtures; not the design), and
   // the relative width of the bracket listed around lambda times it next time
   struct Hint {
-    unsigned long long Fq = 0;
-    double delta = 0;
+    unsigned long long F[3] = {0, 0, 0};  // the last three exact maxima, newest first (0: none)
+    double delta = 0;                     // relative half-width of the next bracket
   };
   std::map<std::string, Hint> hints;
   bool use_hints = true;
@@ -984,6 +984,7 @@ struct Plan {
   std::string hint_key;
   bool hinted = false;
   double blo = 0, bhi = 0, hint_delta = 0;
+  double hint_pred = 0;  // the expected F_max (fixed point)
   // workspace layout (bytes)
   size_t ws_bytes;
   long long spec_elems;
@@ -1200,9 +1201,18 @@ static imf_status make_plan(imf_ctx* c, const imf_request* r, const imf_outputs*
     p.hint_key = k;
     auto it = c->hints.find(k);
     if (c->use_hints && it != c->hints.end()) {
+      // the next maximum extrapolated from the last two (a TO loop's design
+      // drifts), the bracket as wide as recent predictions erred (twice)
+      const imf_ctx::Hint& h = it->second;
+      double pred = (double)h.F[0];
+      if (h.F[2]) {  // a drift over the last three continues by its mean step
+        const double d1 = (double)h.F[0] - (double)h.F[1], d2 = (double)h.F[1] - (double)h.F[2];
+        if (d1 * d2 > 0) pred = std::max(0.0, (double)h.F[0] + 0.5 * (d1 + d2));
+      }
       p.hinted = true;
-      p.hint_delta = it->second.delta;
-      const double th = r->lambda * (double)it->second.Fq * p.scale;
+      p.hint_pred = pred;
+      p.hint_delta = h.delta;
+      const double th = r->lambda * pred * p.scale;
       p.blo = th * (1.0 - p.hint_delta) - p.E;
       p.bhi = th * (1.0 + p.hint_delta) + p.E;
     }
@@ -1258,7 +1268,10 @@ static imf_status make_plan(imf_ctx* c, const imf_request* r, const imf_outputs*
   if (p.intmask) add(sizeof(uint64_t) * p.nO * (long long)r->nz * r->ny * p.words);  // masks at theta_B
   if (p.exact) {
     p.cand_cap = 1 << 16;
-    p.band_cap = 1 << 24;
+    // room for 8192 bracket entries per list (64 lists per orientation)
+    p.band_cap = (int)std::min<long long>(std::max<long long>(1LL << 20, (long long)p.nO *
+                                                                          IMF_BR_SLICES * 8192),
+                                          1LL << 28);
     add(sizeof(int) * (size_t)p.cand_cap);               // candidates of the maximum
     add(sizeof(int4) * (size_t)p.band_cap);              // band entries
     add(sizeof(unsigned) * (size_t)p.nO * IMF_BR_SLICES);  // bracket list counts
@@ -2089,7 +2102,7 @@ static imf_status compute_finish(Pending& pd, imf_stats* st) {
     st->band_entries = pd.hint_ok ? pd.host[23] : pd.host[19];
     st->guard_flags = total_flags + pd.host[21];
     st->passes = 1;
-    st->hinted = p.hinted ? (pd.hint_ok ? 1 : 2) : 0;
+    st->hinted = p.hinted ? (pd.hint_ok ? 1 : pd.host[22] == 2u ? 3 : 2) : 0;
     if (p.bnb) {
       unsigned long long sk;
       std::memcpy(&sk, &pd.host[8], 8);
@@ -2165,9 +2178,19 @@ static imf_status run_request(imf_ctx* c, const imf_request* r, const imf_output
       // remember the exact F_max; a bracket that missed widens next time
       std::lock_guard<std::recursive_mutex> lk(c->mu);
       imf_ctx::Hint h;
-      h.Fq = pd.Fq;
-      h.delta = !pd.p.hinted ? 0.004 : pd.hint_ok ? pd.p.hint_delta
-                                                  : std::min(0.06, 4.0 * pd.p.hint_delta);
+      auto old = c->hints.find(pd.p.hint_key);
+      if (old != c->hints.end()) {
+        h.F[1] = old->second.F[0];
+        h.F[2] = old->second.F[1];
+      }
+      h.F[0] = pd.Fq;
+      // next half-width: twice this prediction's relative error, decaying by
+      // half per request, within [0.4%, 4%]
+      double err = 0;
+      if (pd.p.hinted && pd.Fq > 0)
+        err = std::fabs((double)pd.Fq - pd.p.hint_pred) / (double)pd.Fq;
+      const double prev = old != c->hints.end() ? old->second.delta : 0.0;
+      h.delta = std::min(0.04, std::max(0.004, std::max(0.5 * prev, 2.0 * err)));
       c->hints[pd.p.hint_key] = h;
       if (c->hints.size() > 4096) c->hints.clear();
     }

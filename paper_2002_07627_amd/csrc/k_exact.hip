@@ -169,7 +169,7 @@ hipError_t imf_launch_fq_from_fmax(const unsigned int* fmax_bits, double inv_sca
 // the band around theta: stored overlaps theta - E < g <= theta + E
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(IMF_WG) k_band_scan(imf_exact_args a) {
-  if (a.skip_scan && *a.skip_scan) return;
+  if (a.skip_scan && *a.skip_scan == 1u) return;
   const int q = blockIdx.y;
   const imf_orient_desc& d = a.desc[q];
   const long long vol = (long long)d.box_dim[0] * d.box_dim[1] * d.box_dim[2];
@@ -224,7 +224,7 @@ __global__ void __launch_bounds__(1024) k_bracket_check(imf_exact_args a, double
     double thq, thv;
     thresholds(a, thq, thv);
     const bool in = !over && thv - a.E >= blo && thv + a.E <= bhi;
-    *ok = in ? 1u : 0u;
+    *ok = in ? 1u : (over ? 2u : 0u);
     *a.blisted = total;
   }
 }
@@ -303,7 +303,7 @@ __global__ void __launch_bounds__(IMF_WG) k_band_exact(imf_exact_args a) {
   const long long n = min((long long)*a.band_cnt, (long long)a.band_cap);
   for (long long e = wave; e < n; e += nwaves) band_entry(a, a.band[e], thq, thv, err, evals);
   // the bracket lists, when they hold the band (a wave per list)
-  if (a.blist && *a.skip_scan) {
+  if (a.blist && *a.skip_scan == 1u) {
     const long long nsl = (long long)a.nO * IMF_BR_SLICES;
     for (long long sl = wave; sl < nsl; sl += nwaves) {
       const unsigned c = min(a.bcnt[sl], (unsigned)a.bslot);

@@ -427,3 +427,33 @@ def setup_of_dirs(dirs, n_sets: int) -> np.ndarray:
     d = np.asarray(dirs, np.float64).reshape(len(dirs), -1)
     phi = np.arctan2(d[:, 1], d[:, 0]) % (2 * np.pi)
     return np.minimum((phi / (2 * np.pi) * n_sets).astype(np.int32), n_sets - 1)
+
+
+def perturb_density_device(rho, seed: int, amp: float = 0.05, sigma: float = 4.0):
+    """``perturb_density`` on the device (torch): rho + amp * standardized smooth
+    noise (the same periodic Gaussian filter, truncated at 4 sigma, applied by
+    FFT), clipped to [0, 1] and rounded to the 2**-24 grid.  The white noise is
+    torch's seeded normal generator on the device, so the values differ from the
+    numpy recipe; the TO-loop benchmark uses it to keep host time out of the
+    loop."""
+    import torch
+    dev = rho.device
+    g = torch.Generator(device=dev).manual_seed(int(seed))
+    w = torch.randn(rho.shape, generator=g, device=dev, dtype=torch.float64)
+    half = int(math.ceil(4 * sigma))
+    taps = np.exp(-0.5 * (np.arange(-half, half + 1) / sigma) ** 2)
+    taps /= taps.sum()
+    spec = torch.fft.rfftn(w)
+    for ax in range(rho.dim()):
+        n = rho.shape[ax]
+        ker = np.zeros(n)
+        for j, t in zip(range(-half, half + 1), taps):
+            ker[j % n] += t
+        kf = np.fft.rfft(ker) if ax == rho.dim() - 1 else np.fft.fft(ker)
+        shape = [1] * rho.dim()
+        shape[ax] = kf.shape[0]
+        spec = spec * torch.from_numpy(kf.reshape(shape)).to(dev)
+    noise = torch.fft.irfftn(spec, s=rho.shape)
+    noise = (noise - noise.mean()) / noise.std(unbiased=False)
+    out = (rho.double() + amp * noise).clamp_(0.0, 1.0)
+    return (torch.round(out * Q24) / Q24).float()
