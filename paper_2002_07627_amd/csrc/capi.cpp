@@ -1273,6 +1273,7 @@ static imf_status make_plan(imf_ctx* c, const imf_request* r, const imf_outputs*
                                                                           IMF_BR_SLICES * 8192),
                                           1LL << 28);
     add(sizeof(int) * (size_t)p.cand_cap);               // candidates of the maximum
+    add(sizeof(unsigned long long) * (size_t)p.cand_cap);  // their exact f
     add(sizeof(int4) * (size_t)p.band_cap);              // band entries
     add(sizeof(unsigned) * (size_t)p.nO * IMF_BR_SLICES);  // bracket list counts
   }
@@ -1504,6 +1505,7 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
   uint64_t* intmask =
       p.intmask ? carve<uint64_t>(ar, (size_t)p.nO * r->nz * r->ny * p.words) : nullptr;
   int* cand = p.exact ? carve<int>(ar, p.cand_cap) : nullptr;
+  unsigned long long* cmin = p.exact ? carve<unsigned long long>(ar, p.cand_cap) : nullptr;
   int4* band = p.exact ? carve<int4>(ar, p.band_cap) : nullptr;
   unsigned* bcnt = p.exact ? carve<unsigned>(ar, (size_t)p.nO * IMF_BR_SLICES) : nullptr;
   const int bslot = p.exact ? (int)(p.band_cap / ((long long)p.nO * IMF_BR_SLICES)) : 0;
@@ -1951,7 +1953,7 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
     HIPCHK(imf_launch_fill_u32(misc + 16, 1, (unsigned)(p.known_Fq & 0xffffffffu), s));
     HIPCHK(imf_launch_fill_u32(misc + 17, 1, (unsigned)(p.known_Fq >> 32), s));
   } else if (p.exact) {
-    HIPCHK(imf_launch_exact_fmax(ea, s));
+    HIPCHK(imf_launch_exact_fmax(ea, cmin, s));
     if (p.hinted) HIPCHK(imf_launch_bracket_check(ea, p.blo, p.bhi, misc + 22, s));
     tm.mark(9);
   } else {
@@ -2185,12 +2187,12 @@ static imf_status run_request(imf_ctx* c, const imf_request* r, const imf_output
       }
       h.F[0] = pd.Fq;
       // next half-width: twice this prediction's relative error, decaying by
-      // half per request, within [0.4%, 4%]
+      // half per request, within [0.05%, 4%]
       double err = 0;
       if (pd.p.hinted && pd.Fq > 0)
         err = std::fabs((double)pd.Fq - pd.p.hint_pred) / (double)pd.Fq;
       const double prev = old != c->hints.end() ? old->second.delta : 0.0;
-      h.delta = std::min(0.04, std::max(0.004, std::max(0.5 * prev, 2.0 * err)));
+      h.delta = std::min(0.04, std::max(0.0005, std::max(0.5 * prev, 2.0 * err)));
       c->hints[pd.p.hint_key] = h;
       if (c->hints.size() > 4096) c->hints.clear();
     }

@@ -379,7 +379,10 @@ struct imf_exact_args {
   const int4* blist; const unsigned int* bcnt; int bslot;
   unsigned int* blisted;         // total entries the bracket lists hold
 };
-hipError_t imf_launch_exact_fmax(const imf_exact_args& a, hipStream_t s);
+// candidates of the maximum, their exact f (cmin: cand_cap words of scratch),
+// and F_max = the largest of those
+hipError_t imf_launch_exact_fmax(const imf_exact_args& a, unsigned long long* cmin,
+                                 hipStream_t s);
 hipError_t imf_launch_fq_from_fmax(const unsigned int* fmax_bits, double inv_scale,
                                    unsigned long long* Fq, hipStream_t s);
 hipError_t imf_launch_band_scan(const imf_exact_args& a, long long max_vol, hipStream_t s);

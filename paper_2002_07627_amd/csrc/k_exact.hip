@@ -72,55 +72,84 @@ __global__ void __launch_bounds__(IMF_WG) k_fmax_cand(imf_exact_args a) {
   }
 }
 
-// One workgroup per candidate voxel x: its waves take the orientations in
-// turn, keep those whose gamma_R(x) is within 2E of f(x) (blocks the bound
-// skipped have gamma > f + 2E), and recompute exactly every g(x - k), k in S_R,
-// whose float32 value is within 2E of f(x) (all of them without a stored g).
-__global__ void __launch_bounds__(IMF_WG) k_exact_f(imf_exact_args a) {
+// Exact f at the candidates, spread over the whole device: a work item is a
+// (candidate x, orientation R, chunk of S_R's points); items whose gamma_R(x)
+// is not within 2E of f(x) end at once (blocks the bound skipped have gamma >
+// f + 2E).  The item's threads take the points k of S_R (the x-runs of S,
+// flattened by a prefix sum in LDS) and recompute exactly every g(x - k) whose
+// float32 value is within 2E of f(x) (all of them without a stored g); the
+// smallest lowers the candidate's exact f (atomic min).
+#define EXF_CHUNKS 8
+#define EXF_RUNS 2048
+__global__ void __launch_bounds__(IMF_WG) k_exact_f(imf_exact_args a,
+                                                    unsigned long long* __restrict__ cmin) {
+  __shared__ int pref[EXF_RUNS + 1];
   __shared__ unsigned long long wmin[IMF_WG / 64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int nc = min((int)*a.cand_cnt, a.cand_cap);
+  const long long nc = min((long long)*a.cand_cnt, (long long)a.cand_cap);
+  const long long items = nc * a.nO * EXF_CHUNKS;
   const long long nxy = (long long)a.nx * a.ny;
-  for (int c = blockIdx.x; c < nc; c += gridDim.x) {
+  for (long long it = blockIdx.x; it < items; it += gridDim.x) {
+    const int ch = (int)(it % EXF_CHUNKS);
+    const int q = (int)((it / EXF_CHUNKS) % a.nO);
+    const long long c = it / ((long long)EXF_CHUNKS * a.nO);
     const long long vi = a.cand[c];
     const int z = (int)(vi / nxy), y = (int)((vi / a.nx) % a.ny), x = (int)(vi % a.nx);
     const double lim = (double)a.f[vi] + 2.0 * a.E;
+    const imf_orient_desc& d = a.desc[q];
+    const imf_orient_desc& sd = a.desc[a.nO + q];  // x-runs of S
+    if (a.gamma) {  // uniform over the workgroup
+      if (a.keep) {
+        const mf_geom G(a.WX, a.WY, a.WZ, a.nx, a.ny, a.nz);
+        const long long lg = G.logical(x / a.WX, y / a.WY, z / a.WZ);
+        if (!((a.keep[(long long)d.out_q * a.kstride + (lg >> 6)] >> (lg & 63)) & 1ull)) continue;
+      }
+      if ((double)a.gamma[(long long)d.out_q * a.N + vi] > lim) continue;
+    }
+    const int nr = min(sd.n_sruns, EXF_RUNS);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int acc = 0;
+      for (int r = 0; r < nr; r++) {
+        pref[r] = acc;
+        acc += sd.sruns[r].len;
+      }
+      pref[nr] = acc;
+    }
+    __syncthreads();
+    const int npts = pref[nr];
+    const long long* ps = a.ps + a.ps_stride * d.set;
+    const float* gq = a.gst ? a.gst + (long long)q * a.gst_stride : nullptr;
     unsigned long long best = ~0ull;
     unsigned int evals = 0;
     float err = 0.f;
-    long long kw = 0;
-    int kb = 0;
-    if (a.keep) {
-      const mf_geom G(a.WX, a.WY, a.WZ, a.nx, a.ny, a.nz);
-      const long long lg = G.logical(x / a.WX, y / a.WY, z / a.WZ);
-      kw = lg >> 6;
-      kb = (int)(lg & 63);
-    }
-    for (int q = wv; q < a.nO; q += IMF_WG / 64) {
-      const imf_orient_desc& d = a.desc[q];
-      const imf_orient_desc& sd = a.desc[a.nO + q];  // x-runs of S
-      if (a.gamma) {
-        if (a.keep && !((a.keep[(long long)d.out_q * a.kstride + kw] >> kb) & 1ull)) continue;
-        if ((double)a.gamma[(long long)d.out_q * a.N + vi] > lim) continue;
+    for (int p = ch * IMF_WG + threadIdx.x; p < npts; p += EXF_CHUNKS * IMF_WG) {
+      int lo = 0, hi = nr - 1;  // the run holding point p
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pref[mid] <= p) lo = mid; else hi = mid - 1;
       }
-      const long long* ps = a.ps + a.ps_stride * d.set;
-      const float* gq = a.gst ? a.gst + (long long)q * a.gst_stride : nullptr;
-      for (int r = lane; r < sd.n_sruns; r += 64) {
-        const imf_run u = sd.sruns[r];
-        for (int j = 0; j < u.len; j++) {
-          const int tx = x - (u.x + j), ty = y - u.y, tz = z - u.z;
-          float g32 = 0.f;
-          if (gq) {
-            g32 = gq[((long long)(tz - d.box_lo[2]) * d.box_dim[1] + (ty - d.box_lo[1])) *
-                         d.box_dim[0] +
-                     (tx - d.box_lo[0])];
-            if ((double)g32 > lim) continue;
-          }
-          const long long s = exact_overlap(d, ps, a.nx, a.ny, a.nz, tx, ty, tz);
-          evals++;
-          if (gq) err = fmaxf(err, (float)fabs((double)g32 - (double)s * a.scale));
-          if ((unsigned long long)s < best) best = (unsigned long long)s;
-        }
+      const imf_run u = sd.sruns[lo];
+      const int tx = x - (u.x + (p - pref[lo])), ty = y - u.y, tz = z - u.z;
+      float g32 = 0.f;
+      if (gq) {
+        g32 = gq[((long long)(tz - d.box_lo[2]) * d.box_dim[1] + (ty - d.box_lo[1])) * d.box_dim[0] +
+                 (tx - d.box_lo[0])];
+        if ((double)g32 > lim) continue;
+      }
+      const long long s = exact_overlap(d, ps, a.nx, a.ny, a.nz, tx, ty, tz);
+      evals++;
+      if (gq) err = fmaxf(err, (float)fabs((double)g32 - (double)s * a.scale));
+      if ((unsigned long long)s < best) best = (unsigned long long)s;
+    }
+    // runs beyond the LDS prefix (very wide cutters): one thread per run
+    for (int r = EXF_RUNS + ch * IMF_WG + threadIdx.x; r < sd.n_sruns; r += EXF_CHUNKS * IMF_WG) {
+      const imf_run u = sd.sruns[r];
+      for (int j = 0; j < u.len; j++) {
+        const int tx = x - (u.x + j), ty = y - u.y, tz = z - u.z;
+        const long long s = exact_overlap(d, ps, a.nx, a.ny, a.nz, tx, ty, tz);
+        evals++;
+        if ((unsigned long long)s < best) best = (unsigned long long)s;
       }
     }
     for (int o = 32; o > 0; o >>= 1) {
@@ -138,18 +167,40 @@ __global__ void __launch_bounds__(IMF_WG) k_exact_f(imf_exact_args a) {
     if (threadIdx.x == 0) {
       unsigned long long m = wmin[0];
       for (int w = 1; w < IMF_WG / 64; w++) m = wmin[w] < m ? wmin[w] : m;
-      if (m != ~0ull) atomicMax(a.Fq, m);
+      if (m != ~0ull) atomicMin(cmin + c, m);
     }
-    __syncthreads();
   }
 }
 
-hipError_t imf_launch_exact_fmax(const imf_exact_args& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_fmax_cand, dim3(grid_cap(a.N, 4096)), dim3(IMF_WG), 0, s, a);
+__global__ void k_cmin_init(unsigned long long* cmin, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    cmin[i] = ~0ull;
+}
+
+// F_max = the largest exact f among the candidates
+__global__ void __launch_bounds__(IMF_WG) k_cmin_max(imf_exact_args a,
+                                                     const unsigned long long* cmin) {
+  const long long nc = min((long long)*a.cand_cnt, (long long)a.cand_cap);
+  unsigned long long m = 0;
+  for (long long c = threadIdx.x; c < nc; c += IMF_WG)
+    if (cmin[c] != ~0ull && cmin[c] > m) m = cmin[c];
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long m2 = __shfl_xor(m, o);
+    m = m2 > m ? m2 : m;
+  }
+  if ((threadIdx.x & 63) == 0 && m) atomicMax(a.Fq, m);
+}
+
+hipError_t imf_launch_exact_fmax(const imf_exact_args& a, unsigned long long* cmin,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(k_cmin_init, dim3(64), dim3(IMF_WG), 0, s, cmin, a.cand_cap);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_exact_f, dim3((unsigned)(a.cand_cap < 2048 ? a.cand_cap : 2048)),
-                     dim3(IMF_WG), 0, s, a);
+  hipLaunchKernelGGL(k_fmax_cand, dim3(grid_cap(a.N, 4096)), dim3(IMF_WG), 0, s, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_exact_f, dim3(2048), dim3(IMF_WG), 0, s, a, cmin);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_cmin_max, dim3(1), dim3(IMF_WG), 0, s, a, (const unsigned long long*)cmin);
   return hipGetLastError();
 }
 

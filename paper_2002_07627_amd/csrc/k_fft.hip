@@ -660,22 +660,13 @@ __global__ void __launch_bounds__(NTH) k_inv_x_c2r(imf_inv_args a, imf_fft_len L
         if (slot < a.flag_cap) a.flags[slot] = make_int2(q, (int)li);
       }
     }
-    if (a.blist) {  // the expected threshold's bracket: one atomic per wave
-      const bool in = (double)v > a.blo && (double)v <= a.bhi;
-      const unsigned long long m = __ballot(in);
-      if (m) {
-        const int lane = threadIdx.x & 63;
-        const int leader = __ffsll((long long)m) - 1;
-        const long long sl = (long long)(a.q0 + q) * IMF_BR_SLICES + (blockIdx.x % IMF_BR_SLICES);
-        unsigned base = 0;
-        if (lane == leader) base = atomicAdd(a.bcnt + sl, (unsigned)__popcll(m));
-        base = __shfl(base, leader);
-        if (in) {
-          const unsigned slot = base + (unsigned)__popcll(m & ((1ull << lane) - 1ull));
-          if (slot < (unsigned)a.bslot)
-            a.blist[sl * a.bslot + slot] = make_int4(a.q0 + q, (int)li, __float_as_int(v), 0);
-        }
-      }
+    // the expected threshold's bracket (rare: about one entry per workgroup,
+    // spread over the workgroups' lists)
+    if (a.blist && (double)v > a.blo && (double)v <= a.bhi) {
+      const long long sl = (long long)(a.q0 + q) * IMF_BR_SLICES + (blockIdx.x % IMF_BR_SLICES);
+      const unsigned slot = atomicAdd(a.bcnt + sl, 1u);
+      if (slot < (unsigned)a.bslot)
+        a.blist[sl * a.bslot + slot] = make_int4(a.q0 + q, (int)li, __float_as_int(v), 0);
     }
     dst[li] = v;
   }
