@@ -20,7 +20,10 @@
  *     voxel centres (radial test closed, axial test half-open).
  *   - Outside the grid is empty space.  Translations are integer voxel
  *     offsets on the same grid.
- *   - Density designs are float32 in [0, 1] on the 2^-24 grid (k / 2^24).
+ *   - Density designs are float32 in [0, 1] on the 2^-24 grid (k / 2^24);
+ *     binary designs are uint8 0 or 1.  A request whose design holds any
+ *     other value (fixture voxels included) fails with IMF_EINVAL once its
+ *     prefix-sum pass has read the design (the outputs are then undefined).
  *
  * Ownership: every input and output pointer is owned by the caller and only
  * used during the call (imf_compute) or until imf_wait returns (imf_submit).

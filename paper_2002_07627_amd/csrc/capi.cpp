@@ -1487,7 +1487,7 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
   // fixed point, [18] candidates of the maximum, [19] band entries, [20] max
   // |g32 - g| of exact recomputations (density), [21] exact recomputations of
   // the post pass, [22] 1 when the expected threshold's bracket held the band,
-  // [23] entries of the bracket lists
+  // [23] entries of the bracket lists, [24] design voxels outside the value set
   unsigned int* fmax_bits = misc;
   unsigned int* maxerr_bits = misc + 1;
   unsigned long long* Fq = (unsigned long long*)(misc + 16);
@@ -1629,6 +1629,11 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
     }
     put(&p.B, sizeof(p.B));
     put(p.P, sizeof(p.P));
+    // launch parameters the autotuner may change after a capture
+    const int lp[5] = {p.shape, p.tuned_batch, p.tuned_shape, p.wg_per_cu, c->mf_sync};
+    put(lp, sizeof lp);
+    const int sw[3] = {(int)c->lattice_runs, (int)c->spread_order, (int)c->overlap_stack};
+    put(sw, sizeof sw);
     put(&p.gst, sizeof(p.gst));
     put(&p.known_Fq, sizeof(p.known_Fq));
     put(&p.hinted, sizeof(p.hinted));
@@ -1668,7 +1673,7 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
   for (int k = 0; k < nps; k++)
     HIPCHK(imf_launch_prefix_x(r->design, r->design_is_density,
                                p.nsets ? setfix + N * k : r->fixture, r->nx, r->ny, r->nz,
-                               ps + ps_stride * k, s));
+                               ps + ps_stride * k, k == 0 ? misc + 24 : nullptr, s));
   tm.mark(1);
   const double esz = r->design_is_density ? 4.0 : 1.0;
   const double S = 8.0 * (double)p.spec_elems;
@@ -2061,6 +2066,12 @@ static imf_status compute_finish(Pending& pd, imf_stats* st) {
     return fail(IMF_EDEVICE, "request failed on the device: %s", hipGetErrorString(e));
   }
   const Plan& p = pd.p;
+  if (pd.host[24]) {
+    pd.tm.release();
+    return fail(IMF_EINVAL,
+                "%u design voxels lie outside the design's value set ({0, 1} for binary designs, "
+                "multiples of 2^-24 in [0, 1] for densities)", pd.host[24]);
+  }
   long long total_flags = 0;
   for (int b = 0; b < pd.nb; b++) {
     const int n = (int)pd.host[32 + b];

@@ -272,8 +272,10 @@ hipError_t imf_launch_inverse(const imf_inv_args& a, const imf_fft_len& fx,
                               int stage = -1);
 
 // exact overlap by prefix sums along x (direct correlation and guard-band recheck)
+// bad (may be null): counts design voxels outside the representable value
+// set (binary: > 1; density: outside [0, 1] or off the 2^-24 grid)
 hipError_t imf_launch_prefix_x(const void* design, int density, const uint8_t* fixture, int nx,
-                               int ny, int nz, long long* ps, hipStream_t s);
+                               int ny, int nz, long long* ps, unsigned int* bad, hipStream_t s);
 // density: the exact value rounded to float32, then moved by ulps where needed
 // so that g32 <= th equals g <= th for each of the nth known thresholds
 hipError_t imf_launch_direct(const imf_orient_desc* desc, int nq, const long long* ps, int nx,

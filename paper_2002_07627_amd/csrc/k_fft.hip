@@ -307,6 +307,14 @@ static inline unsigned xcd_grid(long long GX, long long GY, long long GZ) {
   return (unsigned)((GX * GY * GZ + 7) / 8 * 8);
 }
 
+// the value of the lane n below in the same 16-lane row, +inf for the row's
+// first n lanes (a DPP row shift: no LDS traffic)
+template <int N>
+__device__ __forceinline__ float dpp_row_shr(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(INFINITY), __float_as_int(v),
+                                                    0x110 | N, 0xf, 0xf, false));
+}
+
 __device__ __forceinline__ int pmod(long long a, int n) {
   long long r = a % n;
   return (int)(r < 0 ? r + n : r);
@@ -560,25 +568,34 @@ __global__ void __launch_bounds__(NTH) k_inv_z_product(imf_inv_args a, imf_fft_l
     const int i = threadIdx.x + e * NTH;
     rho[e] = i < ncol * n ? rsrc[i] : make_float2(0.f, 0.f);
   }
+  // the next orientation's tool spectrum tile is loaded into registers while
+  // the current one is transformed
+  float2 tp[RE];
+  auto fetch = [&](int q) {
+    const float2* tsrc = a.desc[q].spec + ((long long)ky * h + c0) * n;
+#pragma unroll
+    for (int e = 0; e < RE; e++) {
+      const int i = threadIdx.x + e * NTH;
+      tp[e] = i < ncol * n ? tsrc[i] : make_float2(0.f, 0.f);
+    }
+  };
+  if (a.nq > 0) fetch(0);
   for (int q = 0; q < a.nq; q++) {
     const imf_orient_desc& d = a.desc[q];
-    const float2* tsrc = d.spec + ((long long)ky * h + c0) * n;
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < RE; e++) {
       const int i = threadIdx.x + e * NTH;
       if (i < CT * n) {
         const int c = i / n, k = i - c * n;
-        float2 v = make_float2(0.f, 0.f);
-        if (c < ncol) {
-          const float2 t = tsrc[i];
-          const float2 r = rho[e];
-          // r * conj(t) * scale
-          v = make_float2((r.x * t.x + r.y * t.y) * scale, (r.y * t.x - r.x * t.y) * scale);
-        }
-        X[LIDX(k, c)] = v;
+        const float2 t = tp[e];
+        const float2 r = rho[e];
+        // r * conj(t) * scale (zero past the last column: both are zero there)
+        X[LIDX(k, c)] =
+            make_float2((r.x * t.x + r.y * t.y) * scale, (r.y * t.x - r.x * t.y) * scale);
       }
     }
+    if (q + 1 < a.nq) fetch(q + 1);
     __syncthreads();
     fft_tile<CT, MAXE, NT, NTH>(X, tw, L, true);
     const int mz = d.box_dim[2];
@@ -599,16 +616,20 @@ __global__ void __launch_bounds__(NTH) k_inv_z_product(imf_inv_args a, imf_fft_l
 // (6) inverse x pass (complex-to-real, two rows per complex column) with the
 //     rounding / guard-band epilogue.  Writes g over the query box.
 // ---------------------------------------------------------------------------
+// The compile-time plans are held to 8 waves per SIMD: the epilogue's scalar
+// state would otherwise take the SGPR count just past that occupancy's limit
+// (the few scalars over it live in vector lanes instead).
 template <int CT, int MAXE, int NT, int NTH = IMF_WG>
-__global__ void __launch_bounds__(NTH) k_inv_x_c2r(imf_inv_args a, imf_fft_len L,
-                                                      const float2* __restrict__ twg) {
+__global__ void __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(NT > 0 ? 8 : 1)))
+k_inv_x_c2r(imf_inv_args a, imf_fft_len L, const float2* __restrict__ twg) {
   extern __shared__ float2 smem[];
-  const int n = L.n, h = n / 2 + 1;
+  const int n = NT > 0 ? NT : L.n, h = n / 2 + 1;
   const int q = blockIdx.z;
   const imf_orient_desc& d = a.desc[q];
+  // box rows (my mz <= 2^20) and voxels (< 2^31) fit 32-bit indices
   const int mx = d.box_dim[0], my = d.box_dim[1], mz = d.box_dim[2];
-  const long long rows = (long long)my * mz;
-  const long long row0 = (long long)blockIdx.x * 2 * CT;
+  const int rows = my * mz;
+  const int row0 = blockIdx.x * 2 * CT;
   if (row0 >= rows) return;
   float2* X = smem;
   float2* tw = smem + (CT + 1) * n;
@@ -616,16 +637,13 @@ __global__ void __launch_bounds__(NTH) k_inv_x_c2r(imf_inv_args a, imf_fft_len L
   const float2* src = a.w2 + q * a.w2_stride;
   for (int i = threadIdx.x; i < CT * h; i += NTH) {
     const int c = i / h, k = i - c * h;
-    const long long ra = row0 + 2 * c, rb = ra + 1;
+    const int ra = row0 + 2 * c;
+    // rows ra and ra + 1 of the box: (z, y) of the first, the second follows
+    const int za = ra / my, ya = ra - za * my;
+    const int zb = ya + 1 == my ? za + 1 : za, yb = ya + 1 == my ? 0 : ya + 1;
     float2 A = make_float2(0.f, 0.f), B = make_float2(0.f, 0.f);
-    if (ra < rows) {
-      const long long zz = ra / my, yy = ra - zz * my;
-      A = src[(zz * a.max_my + yy) * h + k];
-    }
-    if (rb < rows) {
-      const long long zz = rb / my, yy = rb - zz * my;
-      B = src[(zz * a.max_my + yy) * h + k];
-    }
+    if (ra < rows) A = src[((long long)za * a.max_my + ya) * h + k];
+    if (ra + 1 < rows) B = src[((long long)zb * a.max_my + yb) * h + k];
     // Z(k) = A + iB;  Z(n-k) = conj(A) + i conj(B)
     X[LIDX(k, c)] = make_float2(A.x - B.y, A.y + B.x);
     if (k > 0 && k < n - k) X[LIDX(n - k, c)] = make_float2(A.x + B.y, B.x - A.y);
@@ -635,65 +653,72 @@ __global__ void __launch_bounds__(NTH) k_inv_x_c2r(imf_inv_args a, imf_fft_len L
   const int sh = pmod(d.box_lo[0], n);
   float* dst = a.g + q * a.g_stride;
   float local_err = 0.f;
-  for (int i = threadIdx.x; i < 2 * CT * mx; i += NTH) {
-    const int rr = i / mx, x = i - rr * mx;
-    const long long row = row0 + rr;
-    if (row >= rows) continue;
-    int pos = x + sh;
-    if (pos >= n) pos -= n;
-    const float2 z = X[LIDX(pos, rr >> 1)];
-    float v = (rr & 1) ? z.y : z.x;
-    const long long li = row * mx + x;
-    if (a.binary) {
-      const float G = rintf(v);
-      const float e = fabsf(v - G);
-      local_err = fmaxf(local_err, e);
-      if (e > a.delta) {
-        const int slot = atomicAdd(a.flag_cnt, 1);
-        if (slot < a.flag_cap) a.flags[slot] = make_int2(q, (int)li);
-      }
-      v = G;
-    } else if (a.nth) {
-      if (fabs((double)v - a.th[0]) <= a.band ||
-          (a.nth > 1 && fabs((double)v - a.th[1]) <= a.band)) {
-        const int slot = atomicAdd(a.flag_cnt, 1);
-        if (slot < a.flag_cap) a.flags[slot] = make_int2(q, (int)li);
-      }
-    }
-    // the expected threshold's bracket (rare: about one entry per workgroup,
-    // spread over the workgroups' lists)
-    if (a.blist && (double)v > a.blo && (double)v <= a.bhi) {
-      const long long sl = (long long)(a.q0 + q) * IMF_BR_SLICES + (blockIdx.x % IMF_BR_SLICES);
-      const unsigned slot = atomicAdd(a.bcnt + sl, 1u);
-      if (slot < (unsigned)a.bslot)
-        a.blist[sl * a.bslot + slot] = make_int4(a.q0 + q, (int)li, __float_as_int(v), 0);
-    }
-    dst[li] = v;
-  }
-  if (a.cellmin) {
-    // minima of this tile's rows over the bound's cells, from the transformed
-    // tile still in LDS (the values just written: rounded when binary), one
-    // atomic min per (row, cell); the recheck lowers a cell again when it
-    // corrects a value
-    const int cwx = a.cwx, cwy = a.cwy, cwz = a.cwz;
-    const int ncx = (mx + cwx - 1) / cwx;
-    const int cdx = ncx + 1, cdy = (my + cwy - 1) / cwy + 1;
-    unsigned int* cm = a.cellmin + q * a.cell_stride;
-    for (int i = threadIdx.x; i < 2 * CT * ncx; i += NTH) {
-      const int rr = i / ncx, cx = i - rr * ncx;
-      const long long row = row0 + rr;
-      if (row >= rows) continue;
-      float m = INFINITY;
-      const int x1 = min(cx * cwx + cwx, mx);
-      for (int x = cx * cwx; x < x1; x++) {
+  // Each wave takes whole rows, 64 consecutive x at a time (chunks aligned to
+  // the box's x = 0, so the bound's cells, whose widths divide 64, never
+  // straddle a chunk); the row's coordinates are wave-uniform (scalar) and the
+  // cell minima are reduced across lanes by DPP row shifts.
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nch = (mx + 63) >> 6;
+  const int gl = a.cellmin ? min(a.cwx, 16) : 16;  // lanes per reduced group
+  const int cwx = a.cwx, cwy = a.cwy, cwz = a.cwz;
+  const int cdx = (mx + cwx - 1) / cwx + 1, cdy = (my + cwy - 1) / cwy + 1;
+  for (int rr = wave; rr < 2 * CT; rr += NTH / 64) {
+    const int row = row0 + rr;
+    if (row >= rows) break;
+    const int zz = row / my, yy = row - zz * my;
+    const bool odd = rr & 1;
+    const float2* Xc = X + (rr >> 1);
+    float* drow = dst + (long long)row * mx;
+    unsigned int* cmrow =
+        a.cellmin ? a.cellmin + q * a.cell_stride + ((zz / cwz) * cdy + yy / cwy) * cdx : nullptr;
+    for (int ch = 0; ch < nch; ch++) {
+      const int x = ch * 64 + lane;
+      float v = INFINITY;
+      if (x < mx) {
         int pos = x + sh;
         if (pos >= n) pos -= n;
-        const float2 z = X[LIDX(pos, rr >> 1)];
-        const float v = (rr & 1) ? z.y : z.x;
-        m = fminf(m, a.binary ? rintf(v) : v);
+        const float2 z = Xc[pos * (CT + 1)];
+        v = odd ? z.y : z.x;
+        const int li = row * mx + x;
+        if (a.binary) {
+          const float G = rintf(v);
+          const float e = fabsf(v - G);
+          local_err = fmaxf(local_err, e);
+          if (e > a.delta) {
+            const int slot = atomicAdd(a.flag_cnt, 1);
+            if (slot < a.flag_cap) a.flags[slot] = make_int2(q, li);
+          }
+          v = G;
+        } else if (a.nth) {
+          if (fabs((double)v - a.th[0]) <= a.band ||
+              (a.nth > 1 && fabs((double)v - a.th[1]) <= a.band)) {
+            const int slot = atomicAdd(a.flag_cnt, 1);
+            if (slot < a.flag_cap) a.flags[slot] = make_int2(q, li);
+          }
+        }
+        // the expected threshold's bracket (rare: about one entry per
+        // workgroup, spread over the workgroups' lists)
+        if (a.blist && (double)v > a.blo && (double)v <= a.bhi) {
+          const long long sl =
+              (long long)(a.q0 + q) * IMF_BR_SLICES + (blockIdx.x % IMF_BR_SLICES);
+          const unsigned slot = atomicAdd(a.bcnt + sl, 1u);
+          if (slot < (unsigned)a.bslot)
+            a.blist[sl * a.bslot + slot] = make_int4(a.q0 + q, li, __float_as_int(v), 0);
+        }
+        drow[x] = v;
       }
-      const long long zz = row / my, yy = row - zz * my;
-      atomicMin(&cm[((zz / cwz) * cdy + yy / cwy) * cdx + cx], f2ord(m));
+      if (cmrow) {
+        // minima of the row's cells over the values just written (rounded
+        // when binary; +inf past the row's end), one atomic min per group of
+        // gl lanes; the recheck lowers a cell again when it corrects a value
+        float m = v;
+        m = fminf(m, dpp_row_shr<1>(m));
+        m = fminf(m, dpp_row_shr<2>(m));
+        m = fminf(m, dpp_row_shr<4>(m));
+        if (gl == 16) m = fminf(m, dpp_row_shr<8>(m));
+        if ((lane & (gl - 1)) == gl - 1 && x - (gl - 1) < mx) atomicMin(&cmrow[x / cwx], f2ord(m));
+      }
     }
   }
   if (a.binary) {

@@ -13,7 +13,8 @@
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(IMF_WG) k_prefix_x(const void* __restrict__ design, int density,
                                                      const uint8_t* __restrict__ fixture, int nx,
-                                                     long long rows, long long* __restrict__ ps) {
+                                                     long long rows, long long* __restrict__ ps,
+                                                     unsigned int* __restrict__ bad) {
   const long long row = (long long)blockIdx.x * (IMF_WG / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= rows) return;
@@ -23,15 +24,26 @@ __global__ void __launch_bounds__(IMF_WG) k_prefix_x(const void* __restrict__ de
   for (int x0 = 0; x0 < nx; x0 += 64) {
     const int x = x0 + lane;
     long long v = 0;
+    bool ok = true;
     if (x < nx) {
       const long long idx = row * nx + x;
-      if (fixture && fixture[idx]) {
-        v = density ? (long long)Q24 : 1;
-      } else if (density) {
-        v = (long long)((double)((const float*)design)[idx] * Q24);
+      // the design must lie in the value set the fixed-point arithmetic
+      // represents exactly: {0, 1} for binary designs, multiples of 2^-24 in
+      // [0, 1] for densities (fixture voxels included)
+      if (density) {
+        const float d = ((const float*)design)[idx];
+        const float sc = d * 16777216.0f;  // exact: a power-of-two scaling
+        ok = d >= 0.f && d <= 1.f && rintf(sc) == sc;
+        v = ok ? (long long)sc : 0;
       } else {
         v = ((const uint8_t*)design)[idx];
+        ok = v <= 1;
       }
+      if (fixture && fixture[idx]) v = density ? (long long)Q24 : 1;
+    }
+    if (bad) {
+      const unsigned long long m = __ballot(!ok);
+      if (lane == 0 && m) atomicAdd(bad, (unsigned)__popcll(m));
     }
     // inclusive wave scan
     for (int o = 1; o < 64; o <<= 1) {
@@ -44,11 +56,11 @@ __global__ void __launch_bounds__(IMF_WG) k_prefix_x(const void* __restrict__ de
 }
 
 hipError_t imf_launch_prefix_x(const void* design, int density, const uint8_t* fixture, int nx,
-                               int ny, int nz, long long* ps, hipStream_t s) {
+                               int ny, int nz, long long* ps, unsigned int* bad, hipStream_t s) {
   const long long rows = (long long)ny * nz;
   const int per = IMF_WG / 64;
   hipLaunchKernelGGL(k_prefix_x, dim3((unsigned)((rows + per - 1) / per)), dim3(IMF_WG), 0, s,
-                     design, density, fixture, nx, rows, ps);
+                     design, density, fixture, nx, rows, ps, bad);
   return hipGetLastError();
 }
 

@@ -112,3 +112,38 @@ def test_wide_cutter_run_lists_beyond_the_staging(ctx, radius):
     assert np.array_equal(f, ref["imf"].reshape(f.shape))
     mk = host(out["masks"]).view(np.uint64)
     assert np.array_equal(mk, ref["masks"].reshape(mk.shape))
+
+
+@pytest.mark.parametrize("case", ["off_grid", "above_one", "negative", "nan", "binary_two",
+                                  "under_fixture"])
+def test_design_outside_the_value_set_is_rejected(ctx, case):
+    """A design value the fixed-point overlaps cannot hold exactly (a density
+    off the 2^-24 grid or outside [0, 1], a binary value above 1) fails the
+    request with EINVAL, under a fixture voxel too, as the oracle's input check
+    does; the context then serves a valid request unchanged."""
+    import paper_2002_07627_amd as imf
+    shape = (12, 10, 70)
+    rng = np.random.default_rng(7627150)
+    tl = W.tool(W.TOOL_BALL, 1.5, 5, 2.5, 4)
+    dirs = W.lattice26()
+    fx = np.zeros(shape, np.uint8)
+    if case == "binary_two":
+        d = (rng.random(shape) < 0.3).astype(np.uint8)
+        d[5, 4, 33] = 2
+    else:
+        d = (np.floor(rng.random(shape) * 2 ** 24) / 2 ** 24).astype(np.float32)
+        bad = {"off_grid": np.float32(0.25 + 2.0 ** -25), "above_one": np.float32(1.5),
+               "negative": np.float32(-2.0 ** -24), "nan": np.float32(np.nan),
+               "under_fixture": np.float32(2.0 ** -30)}[case]
+        d[5, 4, 33] = bad
+        if case == "under_fixture":
+            fx[5, 4, 33] = 1
+    print("invalid design", case, flush=True)
+    with pytest.raises(imf.IMFError) as ei:
+        ctx.compute(dev(d), dev(fx), tools=tl, dirs=dirs, dir_kind=imf.DIR_LATTICE)
+    assert ei.value.status == 1
+    d[5, 4, 33] = 1
+    out, _ = ctx.compute(dev(d), dev(fx), tools=tl, dirs=dirs, dir_kind=imf.DIR_LATTICE)
+    ref = oracle.imf(oracle.Request(d, fx, tools=tl, dirs=dirs, dir_kind=1))
+    mk = host(out["masks"]).view(np.uint64)
+    assert np.array_equal(mk, ref["masks"].reshape(mk.shape))
