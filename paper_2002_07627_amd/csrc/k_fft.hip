@@ -125,6 +125,135 @@ __device__ __forceinline__ void dft<5>(float2* v, bool inv) { dft_generic<5>(v, 
 template <>
 __device__ __forceinline__ void dft<7>(float2* v, bool inv) { dft_generic<7>(v, inv); }
 
+// Composite radices R = R1 R2 computed in registers (a two-level
+// Cooley-Tukey split: R2 DFTs of length R1 over the stride-R2 elements,
+// twiddles exp(-+2 pi i n2 k1 / R), then R1 DFTs of length R2), so one
+// Stockham stage through LDS does the work of two.  The twiddles are
+// compile-time constants: cos and sin of 2 pi m / R from their Taylor series
+// in double precision (|angle| <= pi / 4 after octant reduction, 14 terms),
+// rounded once to float.
+constexpr double kpi = 3.14159265358979323846;
+constexpr double taylor_sin(double x) {
+  double t = x, s = x;
+  for (int k = 1; k < 14; k++) {
+    t *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+    s += t;
+  }
+  return s;
+}
+constexpr double taylor_cos(double x) {
+  double t = 1.0, s = 1.0;
+  for (int k = 1; k < 14; k++) {
+    t *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+    s += t;
+  }
+  return s;
+}
+// cos and sin of 2 pi m / R, exact at the multiples of pi / 4 that need it
+constexpr void cis_of(int m, int R, double& c, double& s) {
+  m %= R;
+  // angle 2 pi m / R = (pi / 4) * (8 m / R): octant o and remainder r (in
+  // units of pi / 4) from the exact rational 8 m / R
+  const int o = (8 * m) / R;
+  const double r = (double)(8 * m - o * R) / (double)R;  // in [0, 1)
+  double a = r * kpi / 4.0, cr = 0, sr = 0;
+  if (r > 0.5) {  // reflect within the octant: keeps |angle| <= pi / 8
+    a = (1.0 - r) * kpi / 4.0;
+    // cos(pi/4 - a) and sin(pi/4 - a)
+    const double h = 0.70710678118654752440;
+    const double ca = taylor_cos(a), sa = taylor_sin(a);
+    cr = h * (ca + sa);
+    sr = h * (ca - sa);
+  } else {
+    cr = taylor_cos(a);
+    sr = taylor_sin(a);
+  }
+  // rotate by o * pi / 4
+  const double h = 0.70710678118654752440;
+  double oc = 1, os = 0;
+  switch (o) {
+    case 0: oc = 1; os = 0; break;
+    case 1: oc = h; os = h; break;
+    case 2: oc = 0; os = 1; break;
+    case 3: oc = -h; os = h; break;
+    case 4: oc = -1; os = 0; break;
+    case 5: oc = -h; os = -h; break;
+    case 6: oc = 0; os = -1; break;
+    default: oc = h; os = -h; break;
+  }
+  if (r == 0.0) {
+    c = oc;
+    s = os;
+  } else {
+    c = oc * cr - os * sr;
+    s = os * cr + oc * sr;
+  }
+}
+template <int R>
+struct cis_table {
+  float c[R], s[R];
+  constexpr cis_table() : c(), s() {
+    for (int m = 0; m < R; m++) {
+      double cc = 0, ss = 0;
+      cis_of(m, R, cc, ss);
+      c[m] = (float)cc;
+      s[m] = (float)ss;
+    }
+  }
+};
+template <int R>
+struct cis_const {
+  static constexpr cis_table<R> t{};
+};
+
+template <int R1, int R2>
+__device__ __forceinline__ void dft_split(float2* v, bool inv) {
+  constexpr int R = R1 * R2;
+  float2 t[R];
+#pragma unroll
+  for (int n2 = 0; n2 < R2; n2++) {
+    float2 u[R1];
+#pragma unroll
+    for (int n1 = 0; n1 < R1; n1++) u[n1] = v[n2 + R2 * n1];
+    dft<R1>(u, inv);
+#pragma unroll
+    for (int k1 = 0; k1 < R1; k1++) {
+      const int m = (n2 * k1) % R;
+      if (m == 0) {
+        t[k1 * R2 + n2] = u[k1];
+      } else {
+        // exp(-+2 pi i m / R)
+        const float c = cis_const<R>::t.c[m];
+        const float s = inv ? cis_const<R>::t.s[m] : -cis_const<R>::t.s[m];
+        t[k1 * R2 + n2] = cmul(u[k1], make_float2(c, s));
+      }
+    }
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < R1; k1++) {
+    float2 w[R2];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; n2++) w[n2] = t[k1 * R2 + n2];
+    dft<R2>(w, inv);
+#pragma unroll
+    for (int k2 = 0; k2 < R2; k2++) v[k1 + R1 * k2] = w[k2];
+  }
+}
+template <>
+__device__ __forceinline__ void dft<6>(float2* v, bool inv) { dft_split<2, 3>(v, inv); }
+template <>
+__device__ __forceinline__ void dft<9>(float2* v, bool inv) { dft_split<3, 3>(v, inv); }
+template <>
+__device__ __forceinline__ void dft<10>(float2* v, bool inv) { dft_split<2, 5>(v, inv); }
+template <>
+__device__ __forceinline__ void dft<12>(float2* v, bool inv) { dft_split<4, 3>(v, inv); }
+template <>
+__device__ __forceinline__ void dft<14>(float2* v, bool inv) { dft_split<2, 7>(v, inv); }
+template <>
+__device__ __forceinline__ void dft<15>(float2* v, bool inv) { dft_split<3, 5>(v, inv); }
+template <>
+__device__ __forceinline__ void dft<16>(float2* v, bool inv) { dft_split<4, 4>(v, inv); }
+
 // ---------------------------------------------------------------------------
 // LDS tile: CT columns of length n, interleaved: element j of column c at
 // j * (CT + 1) + c.  Threads take (column, row) = (t % CT, t / CT), so both the
@@ -185,17 +314,52 @@ __device__ __forceinline__ void fft_stage(float2* X, const float2* tw, const imf
   __syncthreads();
 }
 
-// compile-time stage plan of a length n: radices 8, 4, 2, 3, 5, 7 in that order
+// compile-time stage plan of a length n = 2^a 3^b 5^c 7^d: radix 8 while
+// three factors of 2 remain, then the leftover power of two (1, 2 or 4) joined
+// to the smallest odd prime when the product is at most 16 (2x3, 2x5, 2x7,
+// 4x3), the odd primes paired while their product is at most 16 (3x3, 3x5),
+// and a leftover 2 with no odd prime joined to the last 8 (16): three stages
+// for most lengths up to 1024 (384 = 8 8 6, 288 = 8 12 3, 1024 = 8 8 16)
 constexpr int ct_radix(int n, int idx) {
-  int s = 0;
-  const int rs[6] = {8, 4, 2, 3, 5, 7};
-  for (int r = 0; r < 6; r++)
-    while (n % rs[r] == 0) {
-      if (s == idx) return rs[r];
-      n /= rs[r];
-      s++;
+  int e2 = 0;
+  while (n % 2 == 0) {
+    n /= 2;
+    e2++;
+  }
+  int odd[16] = {0}, no = 0;
+  for (int p = 3; p <= 7; p += 2)
+    while (n % p == 0) {
+      n /= p;
+      odd[no++] = p;
     }
-  return 1;
+  if (n != 1) return 1;
+  int rs[24] = {0}, ns = 0;
+  while (e2 >= 3) {
+    rs[ns++] = 8;
+    e2 -= 3;
+  }
+  int lf = 1 << e2;
+  int i = 0;
+  if (lf > 1 && no > 0 && lf * odd[0] <= 16) {
+    rs[ns++] = lf * odd[0];
+    lf = 1;
+    i = 1;
+  }
+  while (i < no) {
+    if (i + 1 < no && odd[i] * odd[i + 1] <= 16) {
+      rs[ns++] = odd[i] * odd[i + 1];
+      i += 2;
+    } else {
+      rs[ns++] = odd[i++];
+    }
+  }
+  if (lf > 1) {
+    if (lf == 2 && ns > 0 && rs[0] == 8 && no == 0)
+      rs[0] = 16;
+    else
+      rs[ns++] = lf;
+  }
+  return idx < ns ? rs[idx] : 1;
 }
 constexpr int ct_nstages(int n) {
   int s = 0;
