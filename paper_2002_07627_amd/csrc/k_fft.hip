@@ -590,26 +590,67 @@ __global__ void __launch_bounds__(NTH) k_pass_strided(strided_io io, imf_fft_len
   if (plane >= planes) return;
   float2* X = smem;
   float2* tw = smem + (CT + 1) * n;
-  load_twiddles(tw, twg, n);
   const int c0 = bx * CT;
   const float2* in = io.in + q * io.in_q + plane * io.in_plane + c0;
-  for (int i = threadIdx.x; i < CT * n; i += NTH) {
-    const int j = i / CT, c = i - j * CT;
-    float2 v = make_float2(0.f, 0.f);
-    if (j < n_in && c0 + c < io.ncols) v = in[j * io.in_j + c];
-    int pos = j + sh_in;
-    if (pos >= n) pos -= n;
-    X[LIDX(pos, c)] = v;
-  }
-  __syncthreads();
-  fft_tile<CT, MAXE, NT, NTH>(X, tw, L, inv != 0);
   float2* out = io.out + q * io.out_q + plane * io.out_plane + c0;
-  for (int i = threadIdx.x; i < CT * n_out; i += NTH) {
-    const int j = i / CT, c = i - j * CT;
-    if (c0 + c >= io.ncols) continue;
-    int pos = j + sh_out;
-    if (pos >= n) pos -= n;
-    out[j * io.out_j + c] = X[LIDX(pos, c)];
+  if constexpr (NT > 0) {
+    // every load of the tile in flight at once (registers), the twiddles
+    // behind them, then into LDS
+    constexpr int PE = (CT * NT + NTH - 1) / NTH;
+    float2 v[PE];
+#pragma unroll
+    for (int e = 0; e < PE; e++) {
+      const int i = threadIdx.x + e * NTH;
+      const int j = i / CT, c = i - j * CT;
+      v[e] = make_float2(0.f, 0.f);
+      if (j < n_in && c0 + c < io.ncols) v[e] = in[(long long)j * io.in_j + c];
+    }
+    load_twiddles(tw, twg, n);
+#pragma unroll
+    for (int e = 0; e < PE; e++) {
+      const int i = threadIdx.x + e * NTH;
+      const int j = i / CT, c = i - j * CT;
+      if (j < NT) {
+        int pos = j + sh_in;
+        if (pos >= NT) pos -= NT;
+        X[LIDX(pos, c)] = v[e];
+      }
+    }
+    __syncthreads();
+    fft_tile<CT, MAXE, NT, NTH>(X, tw, L, inv != 0);
+#pragma unroll
+    for (int e = 0; e < PE; e++) {
+      const int i = threadIdx.x + e * NTH;
+      const int j = i / CT, c = i - j * CT;
+      int pos = j + sh_out;
+      if (pos >= NT) pos -= NT;
+      if (j < n_out) v[e] = X[LIDX(pos, c)];
+    }
+#pragma unroll
+    for (int e = 0; e < PE; e++) {
+      const int i = threadIdx.x + e * NTH;
+      const int j = i / CT, c = i - j * CT;
+      if (j < n_out && c0 + c < io.ncols) out[(long long)j * io.out_j + c] = v[e];
+    }
+  } else {
+    load_twiddles(tw, twg, n);
+    for (int i = threadIdx.x; i < CT * n; i += NTH) {
+      const int j = i / CT, c = i - j * CT;
+      float2 v = make_float2(0.f, 0.f);
+      if (j < n_in && c0 + c < io.ncols) v = in[j * io.in_j + c];
+      int pos = j + sh_in;
+      if (pos >= n) pos -= n;
+      X[LIDX(pos, c)] = v;
+    }
+    __syncthreads();
+    fft_tile<CT, MAXE, NT, NTH>(X, tw, L, inv != 0);
+    for (int i = threadIdx.x; i < CT * n_out; i += NTH) {
+      const int j = i / CT, c = i - j * CT;
+      if (c0 + c >= io.ncols) continue;
+      int pos = j + sh_out;
+      if (pos >= n) pos -= n;
+      out[j * io.out_j + c] = X[LIDX(pos, c)];
+    }
   }
 }
 
@@ -797,20 +838,36 @@ k_inv_x_c2r(imf_inv_args a, imf_fft_len L, const float2* __restrict__ twg) {
   if (row0 >= rows) return;
   float2* X = smem;
   float2* tw = smem + (CT + 1) * n;
-  load_twiddles(tw, twg, n);
   const float2* src = a.w2 + q * a.w2_stride;
-  for (int i = threadIdx.x; i < CT * h; i += NTH) {
+  // the tile's 2 CT half-spectrum rows: every load in flight at once
+  // (registers), the twiddles behind them, then into LDS
+  constexpr int PE = NT > 0 ? (CT * (NT / 2 + 1) + NTH - 1) / NTH : MAXE;
+  float2 A[PE], B[PE];
+#pragma unroll
+  for (int e = 0; e < PE; e++) {
+    const int i = threadIdx.x + e * NTH;
     const int c = i / h, k = i - c * h;
     const int ra = row0 + 2 * c;
     // rows ra and ra + 1 of the box: (z, y) of the first, the second follows
     const int za = ra / my, ya = ra - za * my;
     const int zb = ya + 1 == my ? za + 1 : za, yb = ya + 1 == my ? 0 : ya + 1;
-    float2 A = make_float2(0.f, 0.f), B = make_float2(0.f, 0.f);
-    if (ra < rows) A = src[((long long)za * a.max_my + ya) * h + k];
-    if (ra + 1 < rows) B = src[((long long)zb * a.max_my + yb) * h + k];
-    // Z(k) = A + iB;  Z(n-k) = conj(A) + i conj(B)
-    X[LIDX(k, c)] = make_float2(A.x - B.y, A.y + B.x);
-    if (k > 0 && k < n - k) X[LIDX(n - k, c)] = make_float2(A.x + B.y, B.x - A.y);
+    A[e] = make_float2(0.f, 0.f);
+    B[e] = make_float2(0.f, 0.f);
+    if (i < CT * h) {
+      if (ra < rows) A[e] = src[((long long)za * a.max_my + ya) * h + k];
+      if (ra + 1 < rows) B[e] = src[((long long)zb * a.max_my + yb) * h + k];
+    }
+  }
+  load_twiddles(tw, twg, n);
+#pragma unroll
+  for (int e = 0; e < PE; e++) {
+    const int i = threadIdx.x + e * NTH;
+    const int c = i / h, k = i - c * h;
+    if (i < CT * h) {
+      // Z(k) = A + iB;  Z(n-k) = conj(A) + i conj(B)
+      X[LIDX(k, c)] = make_float2(A[e].x - B[e].y, A[e].y + B[e].x);
+      if (k > 0 && k < n - k) X[LIDX(n - k, c)] = make_float2(A[e].x + B[e].y, B[e].x - A[e].y);
+    }
   }
   __syncthreads();
   fft_tile<CT, MAXE, NT, NTH>(X, tw, L, true);
