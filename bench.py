@@ -534,6 +534,9 @@ def main():
                    "grid": list(w.design.shape), "orientations": nR, "P": list(last.P),
                    "batch": last.batch, "autotuned": tuned is not None,
                    "minfilter_block_shape": last.mf_shape, "minfilter_wg_per_cu": last.mf_wg_per_cu,
+                   "fft_plan": {"inv_z": last.fft_plan & 3, "inv_y": (last.fft_plan >> 2) & 3,
+                                "inv_x": (last.fft_plan >> 4) & 3,
+                                "bits": "1: one stage per radix 8,4,2,3,5,7; 2: half-width tiles"},
                    "lattice_run_orientations": last.lattice_runs,
                    "spectra": "cached (warm)"},
         "roofline": roofline,

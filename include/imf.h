@@ -198,6 +198,9 @@ typedef struct {
                               1 the listed bracket held the band, 2 it missed, 3 its lists
                               overflowed (2, 3: the band was then scanned, or decided by a
                               second pass), 0 no expectation */
+  int fft_plan;            /* transform plans of the inverse z, y and x passes, 2 bits each
+                              (z | y << 2 | x << 4): bit 0 one stage per radix 8, 4, 2, 3,
+                              5, 7 instead of composite radices, bit 1 half-width tiles */
 } imf_stats;
 
 /* Bytes of device workspace the request needs (admission control).  The
@@ -229,14 +232,21 @@ imf_status imf_cancel(imf_ctx* ctx, uint64_t ticket);
 /* Autotune a request shape (method, grid, transform sizes) on a real request:
  * time candidate batch widths, then block shapes (64x1x1, 32x2x1, 16x2x2,
  * 16x4x1, 8x4x2) and resident workgroups per CU (4, 6, 8) of the sharp-point
- * minimum, each kernel by kernel after a warm-up, and remember the fastest
- * (another shape replaces the default only when 2% faster); later
- * requests of that shape with batch = 0 use it.  Results do not depend on the
- * choice.  *best_batch receives the batch width. */
+ * minimum, then (FFT method, transform lengths 192-768) the transform plan of
+ * each inverse pass z, y, x in turn: composite radices or one stage per radix
+ * 8, 4, 2, 3, 5, 7, full- or half-width tiles (imf_stats.fft_plan).  Each
+ * candidate runs kernel by kernel after a warm-up; the fastest is remembered
+ * (an alternative replaces the current choice only when 2% faster), and
+ * later requests of that shape with batch = 0 use it.  Captured graphs are
+ * dropped.  Results do not depend on the choice beyond float32 rounding of
+ * the overlaps (integer and thresholded outputs are exact under every plan).
+ * *best_batch receives the batch width. */
 imf_status imf_autotune(imf_ctx* ctx, const imf_request* req, const imf_outputs* out,
                         int* best_batch);
 /* The context's autotuned table as a text file (host file IO only): save
- * writes every tuned request shape; load merges a saved table into the
+ * writes every tuned request shape (format 2: "imf-autotune 2", then per
+ * shape "<method>|<nx>,<ny>,<nz>|<px>,<py>,<pz> <batch> <shape> <wg> <fft>";
+ * format 1 tables, without <fft>, also load); load merges a saved table into the
  * context (an entry replaces the one for the same shape), so a new process
  * skips the tuning.  A malformed file is rejected whole with IMF_EINVAL and
  * leaves the context unchanged.  *n_loaded (may be NULL) receives the number

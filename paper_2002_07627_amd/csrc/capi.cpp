@@ -176,9 +176,11 @@ struct imf_ctx {
     int batch = 8;     // orientations per batch
     int shape = -1;    // block shape of the sharp-point minimum (-1: context default)
     int wg = 0;        // resident workgroups per CU of its list pass (0: context default)
+    int fft = 0;       // transform plans of the inverse z, y, x passes (2 bits each)
   };
   std::map<std::string, Tuned> tuned;
   int force_shape = -1, force_wg = 0;  // set while the autotuner times a candidate
+  int force_fft = -1;
   uint64_t tick = 0;
   Arena arena;
   hipStream_t internal = nullptr;
@@ -953,6 +955,7 @@ struct Plan {
   int shape;
   long long cell_stride, nblocks, cell_waves, nwords_blk;
   int tuned_batch = 8, tuned_shape = 2, wg_per_cu = 8;  // launch parameters in effect
+  int fft_plan = 0;  // inverse transform plans: z | y << 2 | x << 4 (imf_inv_args.fplan)
   // batches: orientations [bstart[b], bstart[b+1]), all seeing fixture set bset[b]
   // (0 without fixture sets); at most B wide, split wherever the set changes
   std::vector<int> bstart, bset;
@@ -1038,9 +1041,11 @@ static void ctx_tuned_params(imf_ctx* c, Plan& p) {
     p.tuned_batch = it->second.batch;
     if (it->second.shape >= 0) p.tuned_shape = it->second.shape;
     if (it->second.wg > 0) p.wg_per_cu = it->second.wg;
+    p.fft_plan = it->second.fft;
   }
   if (c->force_shape >= 0) p.tuned_shape = c->force_shape;
   if (c->force_wg > 0) p.wg_per_cu = c->force_wg;
+  if (c->force_fft >= 0) p.fft_plan = c->force_fft;
 }
 
 static imf_status make_plan(imf_ctx* c, const imf_request* r, const imf_outputs* out,
@@ -1630,7 +1635,8 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
     put(&p.B, sizeof(p.B));
     put(p.P, sizeof(p.P));
     // launch parameters the autotuner may change after a capture
-    const int lp[5] = {p.shape, p.tuned_batch, p.tuned_shape, p.wg_per_cu, c->mf_sync};
+    const int lp[6] = {p.shape, p.tuned_batch, p.tuned_shape, p.wg_per_cu, c->mf_sync,
+                       p.fft_plan};
     put(lp, sizeof lp);
     const int sw[3] = {(int)c->lattice_runs, (int)c->spread_order, (int)c->overlap_stack};
     put(sw, sizeof sw);
@@ -1788,6 +1794,7 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
         ia.q0 = q0;
       }
       ia.cellmin = cm_fused ? cellmin : nullptr;
+      for (int k = 0; k < 3; k++) ia.fplan[k] = (p.fft_plan >> (2 * k)) & 3;
       ia.cell_stride = p.cell_stride;
       ia.cwx = cwx;
       ia.cwy = cwy;
@@ -2154,6 +2161,7 @@ static imf_status compute_finish(Pending& pd, imf_stats* st) {
     }
     st->mf_shape = p.shape;
     st->mf_wg_per_cu = p.wg_per_cu;
+    st->fft_plan = p.fft_plan;
   } else {
     pd.tm.release();
   }
@@ -2529,13 +2537,14 @@ extern "C" imf_status imf_autotune(imf_ctx* c, const imf_request* r, const imf_o
   STCHK(make_plan(c, r, out, os, p0));
   // time one candidate: a warm-up request (fills the spectrum cache), then the
   // faster of two timed ones, kernel by kernel
-  auto time_one = [&](int B, int shape, int wg, double& ms) -> imf_status {
+  auto time_one = [&](int B, int shape, int wg, int fft, double& ms) -> imf_status {
     imf_request rr = *r;
     rr.batch = B;
     rr.flags |= IMF_FLAG_NO_GRAPH;
     rr.flags &= ~(unsigned)IMF_FLAG_PROFILE;
     c->force_shape = shape;
     c->force_wg = wg;
+    c->force_fft = fft;
     imf_stats st;
     ms = 1e300;
     imf_status s1 = IMF_OK;
@@ -2545,17 +2554,19 @@ extern "C" imf_status imf_autotune(imf_ctx* c, const imf_request* r, const imf_o
     }
     c->force_shape = -1;
     c->force_wg = 0;
+    c->force_fft = -1;
     return s1;
   };
   imf_ctx::Tuned best;
   best.shape = p0.tuned_shape;
   best.wg = p0.wg_per_cu;
+  best.fft = 0;
   double best_ms = 1e300;
   // batch width with the current tile shapes
   for (int B : {1, 2, 4, 8, 12, 16}) {
     if (B > p0.nO && B != 1) break;
     double ms;
-    const imf_status s1 = time_one(B, best.shape, best.wg, ms);
+    const imf_status s1 = time_one(B, best.shape, best.wg, best.fft, ms);
     if (s1 == IMF_ENOMEM) break;
     STCHK(s1);
     if (ms < best_ms) {
@@ -2571,29 +2582,49 @@ extern "C" imf_status imf_autotune(imf_ctx* c, const imf_request* r, const imf_o
       for (int wg : {4, 6, 8}) {
         if (shape == best.shape && wg == best.wg) continue;
         double ms;
-        STCHK(time_one(best.batch, shape, wg, ms));
+        STCHK(time_one(best.batch, shape, wg, best.fft, ms));
         if (ms < 0.98 * best_ms) {
           best_ms = ms;
           best.shape = shape;
           best.wg = wg;
         }
       }
+  // transform plan of each inverse pass (radix split, tile width), one pass
+  // at a time with the others held (FFT method only); the same 2% margin
+  if (p0.method == IMF_METHOD_FFT)
+    for (int pass = 0; pass < 3; pass++)
+      for (int v = 1; v < 4 && imf_fft_plan_variants(p0.P[2 - pass]); v++) {
+        const int cand = (best.fft & ~(3 << (2 * pass))) | (v << (2 * pass));
+        double ms;
+        STCHK(time_one(best.batch, best.shape, best.wg, cand, ms));
+        if (ms < 0.98 * best_ms) {
+          best_ms = ms;
+          best.fft = cand;
+        }
+      }
   c->tuned[tune_key(p0)] = best;
+  // requests captured before the tuning keep replaying their old launch
+  // parameters: drop the captured graphs
+  for (auto& kv : c->graphs)
+    if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
+  c->graphs.clear();
+  c->graph_seen.clear();
   if (best_batch) *best_batch = best.batch;
   return IMF_OK;
 }
 
 // The autotuned table as text: a header line, then one line per request shape
-// "<method>|<nx>,<ny>,<nz>|<px>,<py>,<pz> <batch> <shape> <wg>".
+// "<method>|<nx>,<ny>,<nz>|<px>,<py>,<pz> <batch> <shape> <wg> <fft>" (version
+// 1 tables, without <fft>, load with the default transform plans).
 extern "C" imf_status imf_autotune_save(imf_ctx* c, const char* path) {
   if (!c || !path) return fail(IMF_EINVAL, "NULL argument");
   std::lock_guard<std::recursive_mutex> lk(c->mu);
   FILE* f = std::fopen(path, "w");
   if (!f) return fail(IMF_EINVAL, "cannot write %s", path);
-  bool ok = std::fprintf(f, "imf-autotune 1\n") > 0;
+  bool ok = std::fprintf(f, "imf-autotune 2\n") > 0;
   for (const auto& kv : c->tuned)
-    ok = ok && std::fprintf(f, "%s %d %d %d\n", kv.first.c_str(), kv.second.batch,
-                            kv.second.shape, kv.second.wg) > 0;
+    ok = ok && std::fprintf(f, "%s %d %d %d %d\n", kv.first.c_str(), kv.second.batch,
+                            kv.second.shape, kv.second.wg, kv.second.fft) > 0;
   ok = (std::fclose(f) == 0) && ok;
   return ok ? IMF_OK : fail(IMF_EINVAL, "writing %s failed", path);
 }
@@ -2604,22 +2635,30 @@ extern "C" imf_status imf_autotune_load(imf_ctx* c, const char* path, int* n_loa
   if (!f) return fail(IMF_EINVAL, "cannot read %s", path);
   std::map<std::string, imf_ctx::Tuned> got;
   char line[256];
-  int ln = 0;
+  int ln = 0, version = 0;
   imf_status st = IMF_OK;
   while (st == IMF_OK && std::fgets(line, sizeof line, f)) {
     ln++;
     if (ln == 1) {
-      if (std::strncmp(line, "imf-autotune 1", 14) != 0)
+      if (std::strncmp(line, "imf-autotune 1", 14) == 0 && (line[14] == '\n' || !line[14]))
+        version = 1;
+      else if (std::strncmp(line, "imf-autotune 2", 14) == 0 && (line[14] == '\n' || !line[14]))
+        version = 2;
+      else
         st = fail(IMF_EINVAL, "%s: not an autotune table", path);
       continue;
     }
     char key[128];
-    int m, n[3], P[3], batch, shape, wg, used = 0;
-    if (std::sscanf(line, "%127s %d %d %d %n", key, &batch, &shape, &wg, &used) != 4 ||
-        line[used] != '\0' ||
+    int m, n[3], P[3], batch, shape, wg, fft = 0, used = 0;
+    const int nf = version == 1
+                       ? std::sscanf(line, "%127s %d %d %d %n", key, &batch, &shape, &wg, &used)
+                       : std::sscanf(line, "%127s %d %d %d %d %n", key, &batch, &shape, &wg,
+                                     &fft, &used);
+    if (nf != (version == 1 ? 4 : 5) || line[used] != '\0' ||
         std::sscanf(key, "%d|%d,%d,%d|%d,%d,%d", &m, &n[0], &n[1], &n[2], &P[0], &P[1], &P[2]) !=
             7 ||
-        batch < 1 || batch > 64 || shape < -1 || shape > 4 || wg < 0 || wg > 16) {
+        batch < 1 || batch > 64 || shape < -1 || shape > 4 || wg < 0 || wg > 16 || fft < 0 ||
+        fft > 63) {
       st = fail(IMF_EINVAL, "%s:%d: malformed autotune entry", path, ln);
       break;
     }
@@ -2627,6 +2666,7 @@ extern "C" imf_status imf_autotune_load(imf_ctx* c, const char* path, int* n_loa
     t.batch = batch;
     t.shape = shape;
     t.wg = wg;
+    t.fft = fft;
     got[key] = t;
   }
   std::fclose(f);

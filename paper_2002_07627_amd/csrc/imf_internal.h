@@ -263,8 +263,13 @@ struct imf_inv_args {
   // IMF_BR_SLICES lists per orientation (slice of the workgroup: the appends
   // spread over many counters), list s at blist + s * bslot, count bcnt[s]
   int4* blist; unsigned int* bcnt; int bslot; double blo, bhi; int q0;
+  // transform plan of the z, y and x passes (0-3: bit 0 base radices instead
+  // of composite ones, bit 1 half-width tiles); 0 is the default
+  int fplan[3];
 };
 #define IMF_BR_SLICES 64
+// true when the inverse passes of length n have transform plans other than 0
+bool imf_fft_plan_variants(int n);
 // stage: -1 all, 0 product + z pass, 1 y pass, 2 x pass (complex-to-real) + epilogue
 hipError_t imf_launch_inverse(const imf_inv_args& a, const imf_fft_len& fx,
                               const imf_fft_len& fy, const imf_fft_len& fz, const float2* twx,

@@ -320,7 +320,7 @@ __device__ __forceinline__ void fft_stage(float2* X, const float2* tw, const imf
 // 4x3), the odd primes paired while their product is at most 16 (3x3, 3x5),
 // and a leftover 2 with no odd prime joined to the last 8 (16): three stages
 // for most lengths up to 1024 (384 = 8 8 6, 288 = 8 12 3, 1024 = 8 8 16)
-constexpr int ct_radix(int n, int idx) {
+constexpr int ct_radix_split(int n, int idx) {
   int e2 = 0;
   while (n % 2 == 0) {
     n /= 2;
@@ -361,14 +361,31 @@ constexpr int ct_radix(int n, int idx) {
   }
   return idx < ns ? rs[idx] : 1;
 }
-constexpr int ct_nstages(int n) {
+// the base plan: radices 8, 4, 2, 3, 5, 7 in that order (one stage per
+// factor, no composite radices)
+constexpr int ct_radix_base(int n, int idx) {
   int s = 0;
-  while (ct_radix(n, s) > 1) s++;
+  const int rs[6] = {8, 4, 2, 3, 5, 7};
+  for (int r = 0; r < 6; r++)
+    while (n % rs[r] == 0) {
+      if (s == idx) return rs[r];
+      n /= rs[r];
+      s++;
+    }
+  return 1;
+}
+// radix of stage idx of length n under split 0 (composite) or 1 (base)
+constexpr int ct_radix(int n, int idx, int split) {
+  return split ? ct_radix_base(n, idx) : ct_radix_split(n, idx);
+}
+constexpr int ct_nstages(int n, int split) {
+  int s = 0;
+  while (ct_radix(n, s, split) > 1) s++;
   return s;
 }
-constexpr int ct_ns(int n, int idx) {
+constexpr int ct_ns(int n, int idx, int split) {
   int p = 1;
-  for (int i = 0; i < idx; i++) p *= ct_radix(n, i);
+  for (int i = 0; i < idx; i++) p *= ct_radix(n, i, split);
   return p;
 }
 
@@ -417,20 +434,20 @@ __device__ __forceinline__ void fft_stage_ct(float2* X, const float2* tw, bool i
   __syncthreads();
 }
 
-template <int N, int CT, int S, int NTH = IMF_WG>
+template <int N, int CT, int S, int NTH, int SPLIT>
 __device__ __forceinline__ void fft_stages_ct(float2* X, const float2* tw, bool inv) {
-  if constexpr (S < ct_nstages(N)) {
-    fft_stage_ct<ct_radix(N, S), N, ct_ns(N, S), CT, NTH>(X, tw, inv);
-    fft_stages_ct<N, CT, S + 1, NTH>(X, tw, inv);
+  if constexpr (S < ct_nstages(N, SPLIT)) {
+    fft_stage_ct<ct_radix(N, S, SPLIT), N, ct_ns(N, S, SPLIT), CT, NTH>(X, tw, inv);
+    fft_stages_ct<N, CT, S + 1, NTH, SPLIT>(X, tw, inv);
   }
 }
 
-// Transform all CT columns of the tile: NT > 0 is a compile-time length,
-// NT == 0 the run-time plan L.
-template <int CT, int MAXE, int NT, int NTH = IMF_WG>
+// Transform all CT columns of the tile: NT > 0 is a compile-time length
+// (stage plan SPLIT), NT == 0 the run-time plan L.
+template <int CT, int MAXE, int NT, int NTH = IMF_WG, int SPLIT = 0>
 __device__ void fft_tile(float2* X, const float2* tw, const imf_fft_len& L, bool inv) {
   if constexpr (NT > 0) {
-    fft_stages_ct<NT, CT, 0, NTH>(X, tw, inv);
+    fft_stages_ct<NT, CT, 0, NTH, SPLIT>(X, tw, inv);
   } else {
     for (int s = 0; s < L.nstages; s++) {
       switch (L.radix[s]) {
@@ -566,7 +583,7 @@ struct strided_io {
 // pass kinds for the per-orientation geometry
 enum { PASS_DESIGN_Y = 0, PASS_TOOL_Y = 1, PASS_INV_Y = 2 };
 
-template <int CT, int MAXE, int NT, int KIND, int NTH = IMF_WG>
+template <int CT, int MAXE, int NT, int KIND, int NTH = IMF_WG, int SPLIT = 0>
 __global__ void __launch_bounds__(NTH) k_pass_strided(strided_io io, imf_fft_len L,
                                                          const float2* __restrict__ twg,
                                                          const imf_orient_desc* __restrict__ desc,
@@ -617,7 +634,7 @@ __global__ void __launch_bounds__(NTH) k_pass_strided(strided_io io, imf_fft_len
       }
     }
     __syncthreads();
-    fft_tile<CT, MAXE, NT, NTH>(X, tw, L, inv != 0);
+    fft_tile<CT, MAXE, NT, NTH, SPLIT>(X, tw, L, inv != 0);
 #pragma unroll
     for (int e = 0; e < PE; e++) {
       const int i = threadIdx.x + e * NTH;
@@ -643,7 +660,7 @@ __global__ void __launch_bounds__(NTH) k_pass_strided(strided_io io, imf_fft_len
       X[LIDX(pos, c)] = v;
     }
     __syncthreads();
-    fft_tile<CT, MAXE, NT, NTH>(X, tw, L, inv != 0);
+    fft_tile<CT, MAXE, NT, NTH, SPLIT>(X, tw, L, inv != 0);
     for (int i = threadIdx.x; i < CT * n_out; i += NTH) {
       const int j = i / CT, c = i - j * CT;
       if (c0 + c >= io.ncols) continue;
@@ -744,7 +761,7 @@ __global__ void __launch_bounds__(IMF_WG) k_tool_x(const imf_orient_desc* __rest
 //     The rho_hat tile is kept in registers and reused for every orientation
 //     of the batch.
 // ---------------------------------------------------------------------------
-template <int CT, int MAXE, int NT, int NTH = IMF_WG>
+template <int CT, int MAXE, int NT, int NTH = IMF_WG, int SPLIT = 0>
 __global__ void __launch_bounds__(NTH) k_inv_z_product(imf_inv_args a, imf_fft_len L,
                                                           const float2* __restrict__ twg, int GX,
                                                           int GY) {
@@ -802,7 +819,7 @@ __global__ void __launch_bounds__(NTH) k_inv_z_product(imf_inv_args a, imf_fft_l
     }
     if (q + 1 < a.nq) fetch(q + 1);
     __syncthreads();
-    fft_tile<CT, MAXE, NT, NTH>(X, tw, L, true);
+    fft_tile<CT, MAXE, NT, NTH, SPLIT>(X, tw, L, true);
     const int mz = d.box_dim[2];
     const int sh = pmod(d.box_lo[2], n);
     float2* dst = a.w1 + q * a.w1_stride + (long long)ky * h + c0;
@@ -824,7 +841,7 @@ __global__ void __launch_bounds__(NTH) k_inv_z_product(imf_inv_args a, imf_fft_l
 // The compile-time plans are held to 8 waves per SIMD: the epilogue's scalar
 // state would otherwise take the SGPR count just past that occupancy's limit
 // (the few scalars over it live in vector lanes instead).
-template <int CT, int MAXE, int NT, int NTH = IMF_WG>
+template <int CT, int MAXE, int NT, int NTH = IMF_WG, int SPLIT = 0>
 __global__ void __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(NT > 0 ? 8 : 1)))
 k_inv_x_c2r(imf_inv_args a, imf_fft_len L, const float2* __restrict__ twg) {
   extern __shared__ float2 smem[];
@@ -870,7 +887,7 @@ k_inv_x_c2r(imf_inv_args a, imf_fft_len L, const float2* __restrict__ twg) {
     }
   }
   __syncthreads();
-  fft_tile<CT, MAXE, NT, NTH>(X, tw, L, true);
+  fft_tile<CT, MAXE, NT, NTH, SPLIT>(X, tw, L, true);
   const int sh = pmod(d.box_lo[0], n);
   float* dst = a.g + q * a.g_stride;
   float local_err = 0.f;
@@ -1004,6 +1021,64 @@ k_inv_x_c2r(imf_inv_args a, imf_fft_len L, const float2* __restrict__ twg) {
 #define IMF_INV_NTH 512
 #endif
 
+// Transform plans of the inverse passes, chosen per pass by the autotuner:
+// bit 0 the stage plan (0: composite radices, three stages for most lengths;
+// 1: one stage per factor 8, 4, 2, 3, 5, 7), bit 1 the tile (0: the default
+// CT columns with IMF_INV_NTH threads; 1: half the columns with half the
+// threads, twice the workgroups per CU).  Plans other than 0 exist for the
+// lengths 192 to 768; elsewhere every plan is plan 0.  Inside, NTHP and SPLIT
+// are the workgroup size and the stage plan.
+#define CASE_P(NV, CTV, MAXEV, NTHV, SPV, ...)                              \
+  case NV: {                                                                \
+    constexpr int NT = NV, CT = CTV, MAXE = MAXEV, NTHP = NTHV, SPLIT = SPV; \
+    __VA_ARGS__;                                                            \
+  }                                                                         \
+    done = true;                                                            \
+    break;
+#define PLAN_LENGTHS(SPV, NTHV, HALF, ...)                                      \
+  CASE_P(192, 16 / HALF, 16, NTHV, SPV, __VA_ARGS__)                            \
+  CASE_P(216, 16 / HALF, 16, NTHV, SPV, __VA_ARGS__)                            \
+  CASE_P(256, 16 / HALF, 16, NTHV, SPV, __VA_ARGS__)                            \
+  CASE_P(288, 8 / HALF, 16, NTHV, SPV, __VA_ARGS__)                             \
+  CASE_P(320, 8 / HALF, 16, NTHV, SPV, __VA_ARGS__)                             \
+  CASE_P(384, 8 / HALF, 16, NTHV, SPV, __VA_ARGS__)                             \
+  CASE_P(448, 8 / HALF, 16, NTHV, SPV, __VA_ARGS__)                             \
+  CASE_P(512, 8 / HALF, 16, NTHV, SPV, __VA_ARGS__)                             \
+  CASE_P(576, 8 / HALF, 32, NTHV, SPV, __VA_ARGS__)                             \
+  CASE_P(640, 8 / HALF, 32, NTHV, SPV, __VA_ARGS__)                             \
+  CASE_P(768, 8 / HALF, 32, NTHV, SPV, __VA_ARGS__)
+#define DISPATCH_PLAN(n, plan, ...)                                   \
+  do {                                                                \
+    bool done = false;                                                \
+    switch ((plan) & 3) {                                             \
+      case 1:                                                         \
+        switch (n) { PLAN_LENGTHS(1, IMF_INV_NTH, 1, __VA_ARGS__) }   \
+        break;                                                        \
+      case 2:                                                         \
+        switch (n) { PLAN_LENGTHS(0, IMF_INV_NTH / 2, 2, __VA_ARGS__) } \
+        break;                                                        \
+      case 3:                                                         \
+        switch (n) { PLAN_LENGTHS(1, IMF_INV_NTH / 2, 2, __VA_ARGS__) } \
+        break;                                                        \
+      default: break;                                                 \
+    }                                                                 \
+    if (!done) {                                                      \
+      constexpr int NTHP = IMF_INV_NTH, SPLIT = 0;                    \
+      DISPATCH(n, __VA_ARGS__);                                       \
+    }                                                                 \
+  } while (0)
+
+// transform lengths with plans other than 0 (the lengths of PLAN_LENGTHS)
+bool imf_fft_plan_variants(int n) {
+  switch (n) {
+    case 192: case 216: case 256: case 288: case 320: case 384: case 448: case 512: case 576:
+    case 640: case 768:
+      return true;
+    default:
+      return false;
+  }
+}
+
 static size_t smem_bytes(int n, int ct) { return (size_t)((ct + 1) * n + n) * sizeof(float2); }
 
 static hipError_t set_smem(const void* fn, size_t bytes) {
@@ -1092,33 +1167,32 @@ hipError_t imf_launch_inverse(const imf_inv_args& a, const imf_fft_len& fx,
                               const float2* twy, const float2* twz, hipStream_t s, int stage) {
   const int h = a.px / 2 + 1;
   hipError_t e = hipSuccess;
-  if (stage < 0 || stage == 0) DISPATCH(fz.n, {
+  if (stage < 0 || stage == 0) DISPATCH_PLAN(fz.n, a.fplan[0], {
     const size_t sm = smem_bytes(fz.n, CT);
-    auto k = k_inv_z_product<CT, MAXE, NT, IMF_INV_NTH>;
+    auto k = k_inv_z_product<CT, MAXE, NT, NTHP, SPLIT>;
     if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
     const int GX = (h + CT - 1) / CT;
-    hipLaunchKernelGGL(k, dim3(xcd_grid(GX, a.py, 1)), dim3(IMF_INV_NTH), sm, s, a, fz, twz, GX,
-                       a.py);
+    hipLaunchKernelGGL(k, dim3(xcd_grid(GX, a.py, 1)), dim3(NTHP), sm, s, a, fz, twz, GX, a.py);
   });
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if (stage < 0 || stage == 1) DISPATCH(fy.n, {
+  if (stage < 0 || stage == 1) DISPATCH_PLAN(fy.n, a.fplan[1], {
     strided_io io{a.w1, a.w1_stride, (long long)a.py * h, h,
                   a.w2, a.w2_stride, (long long)a.max_my * h, h, h};
     const size_t sm = smem_bytes(fy.n, CT);
-    auto k = k_pass_strided<CT, MAXE, NT, PASS_INV_Y, IMF_INV_NTH>;
+    auto k = k_pass_strided<CT, MAXE, NT, PASS_INV_Y, NTHP, SPLIT>;
     if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
     const int GX = (h + CT - 1) / CT;
-    hipLaunchKernelGGL(k, dim3(xcd_grid(GX, a.max_mz, a.nq)), dim3(IMF_INV_NTH), sm, s, io, fy, twy,
+    hipLaunchKernelGGL(k, dim3(xcd_grid(GX, a.max_mz, a.nq)), dim3(NTHP), sm, s, io, fy, twy,
                        a.desc, 0, a.py, 0, 1, GX, a.max_mz, a.nq);
   });
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if (stage < 0 || stage == 2) DISPATCH(fx.n, {
+  if (stage < 0 || stage == 2) DISPATCH_PLAN(fx.n, a.fplan[2], {
     const size_t sm = smem_bytes(fx.n, CT);
-    auto k = k_inv_x_c2r<CT, MAXE, NT, IMF_INV_NTH>;
+    auto k = k_inv_x_c2r<CT, MAXE, NT, NTHP, SPLIT>;
     if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
     const long long rows = (long long)a.max_my * a.max_mz;
-    hipLaunchKernelGGL(k, dim3((unsigned)((rows + 2 * CT - 1) / (2 * CT)), 1, a.nq),
-                       dim3(IMF_INV_NTH), sm, s, a, fx, twx);
+    hipLaunchKernelGGL(k, dim3((unsigned)((rows + 2 * CT - 1) / (2 * CT)), 1, a.nq), dim3(NTHP),
+                       sm, s, a, fx, twx);
   });
   return hipGetLastError();
 }
