@@ -131,9 +131,11 @@ def serving_leg(imf, W, torch, n_req=64, load=0.7, seed=7627004):
     ctx = imf.Context(0)
     try:
         vo = sum(int(r[0].numel()) * len(r[2]["dirs"]) for r in reqs)
+        alone = []
         t0 = time.perf_counter()
         for des, fx, kw in reqs:
-            ctx.compute(des, fx, **kw)
+            _, st = ctx.compute(des, fx, **kw)
+            alone.append(st.t_ms[7])
         torch.cuda.synchronize()
         t_sat = time.perf_counter() - t0
         rate = load * n_req / t_sat
@@ -145,15 +147,32 @@ def serving_leg(imf, W, torch, n_req=64, load=0.7, seed=7627004):
             if dt > 0:
                 time.sleep(dt)
             tickets.append(ctx.submit(des, fx, **kw))
-        lat = [ctx.wait(t)[1].t_ms[7] for t in tickets]
+        sts = [ctx.wait(t)[1] for t in tickets]
         t_all = time.perf_counter() - t0
     finally:
         ctx.close()
+    lat = np.array([st.t_ms[7] for st in sts])
+    queued = np.array([st.queue_ms for st in sts])
+    alone = np.array(alone)
+    slow = lat / alone
+    i99 = int(np.argsort(lat)[min(n_req - 1, int(round(0.99 * (n_req - 1))))])
     return {"requests": n_req, "load": load, "arrival_rate_per_s": round(rate, 2),
             "p50_ms": round(float(np.percentile(lat, 50)), 2),
             "p99_ms": round(float(np.percentile(lat, 99)), 2),
             "throughput_vo_per_s": vo / t_all,
-            "saturation_vo_per_s": vo / t_sat}
+            "saturation_vo_per_s": vo / t_sat,
+            # each request's latency over its own time back to back (the
+            # calibration pass): separates waiting from the mix of sizes
+            "alone_p50_ms": round(float(np.percentile(alone, 50)), 2),
+            "alone_max_ms": round(float(alone.max()), 2),
+            "slowdown_p50": round(float(np.percentile(slow, 50)), 2),
+            "slowdown_p99": round(float(np.percentile(slow, 99)), 2),
+            "queue_p50_ms": round(float(np.percentile(queued, 50)), 2),
+            "queue_p99_ms": round(float(np.percentile(queued, 99)), 2),
+            "p99_request": {"grid": int(descs[i99]["n"]), "orientations": len(reqs[i99][2]["dirs"]),
+                            "density": bool(descs[i99]["density"]),
+                            "alone_ms": round(float(alone[i99]), 2),
+                            "latency_ms": round(float(lat[i99]), 2)}}
 
 
 def to_loop_leg(imf, W, torch, iters):
@@ -504,6 +523,10 @@ def main():
         serving = serving_leg(imf, W, torch)
         log("serving: p50 %.1f ms, p99 %.1f ms, %.3e voxel-orientations/s" % (
             serving["p50_ms"], serving["p99_ms"], serving["throughput_vo_per_s"]))
+        log("serving: slowdown (latency / back-to-back time) p50 %.2f, p99 %.2f; queue p50 %.1f "
+            "ms, p99 %.1f ms; back-to-back p50 %.1f ms, max %.1f ms" % (
+                serving["slowdown_p50"], serving["slowdown_p99"], serving["queue_p50_ms"],
+                serving["queue_p99_ms"], serving["alone_p50_ms"], serving["alone_max_ms"]))
         torch.cuda.empty_cache()
 
     to_loop = None

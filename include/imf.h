@@ -62,7 +62,10 @@ typedef enum {
 typedef struct imf_ctx imf_ctx;
 
 /* Create a context on HIP device `device`.  hbm_budget_bytes bounds the
- * context's own allocations (0: 90% of the free device memory). */
+ * context's own allocations (0: 90% of the free device memory): workspaces,
+ * tool rasters and cached tool spectra.  Spectra are cached while they fit
+ * and evicted, least recently used first, when a workspace needs their room
+ * (after one device synchronization; captured graphs are then dropped). */
 imf_status imf_create(int device, size_t hbm_budget_bytes, imf_ctx** ctx);
 imf_status imf_destroy(imf_ctx* ctx);
 /* Message of the last error of the calling thread (never NULL). */
@@ -201,6 +204,8 @@ typedef struct {
   int fft_plan;            /* transform plans of the inverse z, y and x passes, 2 bits each
                               (z | y << 2 | x << 4): bit 0 one stage per radix 8, 4, 2, 3,
                               5, 7 instead of composite radices, bit 1 half-width tiles */
+  double queue_ms;         /* served requests: submission to admission (t_ms[7] is
+                              submission to completion); 0 for imf_compute */
 } imf_stats;
 
 /* Bytes of device workspace the request needs (admission control).  The
@@ -219,9 +224,14 @@ imf_status imf_compute(imf_ctx* ctx, const imf_request* req, const imf_outputs* 
 /* -------------------------------------------------------------- serving -- */
 /* The serving calls have no counterpart in the paper: they run imf_compute's
  * work for requests of several callers (e.g. concurrent TO runs).
- * Enqueue a request; the library admits it when its footprint fits the budget
- * and runs it on its own stream, overlapping with other admitted requests.
- * Host arrays of `req` are copied; device buffers must stay valid until wait. */
+ * Enqueue a request; up to 2 requests run at once (environment variable
+ * IMF_SERVE_WORKERS, 1-16, at context creation), each on its own stream,
+ * overlapping on the device.  Admission is first come first served while
+ * workspaces fit (the running requests' footprints within half the budget; an
+ * idle context admits any request); when the oldest waiting request does not
+ * fit, one of the next 8 that does is admitted ahead of it, at most 4 times,
+ * after which the queue waits for it.  Host arrays of `req` are copied;
+ * device buffers must stay valid until wait. */
 imf_status imf_submit(imf_ctx* ctx, const imf_request* req, const imf_outputs* out,
                       uint64_t* ticket);
 /* Wait for a request (timeout_ms < 0: forever).  Fills stats; latency in t_ms[7]. */

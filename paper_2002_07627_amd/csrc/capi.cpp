@@ -152,6 +152,11 @@ struct Arena {
   char* base = nullptr;
   size_t cap = 0, used = 0;
   unsigned int* host = nullptr;  // pinned: counters copied back at the end
+  // A serving worker's arena is used by its own stream only, and that stream
+  // is idle between requests: when it grows, the old buffer is retired to the
+  // context instead of freed (a free waits for the whole device, every other
+  // worker's requests included).
+  bool worker = false;
 };
 
 struct Request;  // serving
@@ -183,6 +188,10 @@ struct imf_ctx {
   int force_fft = -1;
   uint64_t tick = 0;
   Arena arena;
+  // retired worker arenas: used by nobody, freed (one device synchronization
+  // for all) when a reservation needs their room, and at the end
+  std::vector<char*> retired;
+  size_t retired_bytes = 0;
   hipStream_t internal = nullptr;
   // serving
   std::mutex smu;
@@ -193,7 +202,12 @@ struct imf_ctx {
   bool stop = false;
   uint64_t next_ticket = 1;
   size_t inflight_bytes = 0;
-  int max_inflight = 4;
+  // requests run at once by the serving loop, each on its own stream.  Two:
+  // with four, requests whose streams shared a hardware queue with a long
+  // request's stream waited behind its kernels (10-25 times their time
+  // alone on the 64-request mix at 0.7 load, p99 546 ms); with two, p50 29
+  // ms and p99 206 ms against 168 ms for the largest request alone
+  int max_inflight = 2;
   int n_running = 0;
   // captured requests: signature -> instantiated graph and the host-side
   // statistics of its launch sequence (the context lock guards both maps)
@@ -239,19 +253,68 @@ struct imf_ctx {
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+static imf_status arena_free_retired(imf_ctx* c) {
+  if (c->retired.empty()) return IMF_OK;
+  HIPCHK(hipDeviceSynchronize());
+  for (char* b : c->retired) HIPCHK(hipFree(b));
+  c->retired.clear();
+  c->arena_bytes -= c->retired_bytes;
+  c->retired_bytes = 0;
+  return IMF_OK;
+}
+
+// Free cached tool spectra, least recently used first, until `need` bytes
+// are free.  Called under the context lock before the request being planned
+// takes its spectrum slots: after one device synchronization no launched
+// request reads a spectrum, and none can be launched meanwhile; captured
+// graphs, which hold spectrum addresses, are dropped.
+static imf_status evict_spectra(imf_ctx* c, size_t need) {
+  if (c->spectra.empty() || need == 0) return IMF_OK;
+  HIPCHK(hipDeviceSynchronize());
+  std::vector<std::pair<uint64_t, std::string>> order;
+  order.reserve(c->spectra.size());
+  for (const auto& kv : c->spectra) order.emplace_back(kv.second.tick, kv.first);
+  std::sort(order.begin(), order.end());
+  size_t freed = 0;
+  for (const auto& o : order) {
+    if (freed >= need) break;
+    auto it = c->spectra.find(o.second);
+    HIPCHK(hipFree(it->second.ptr));
+    if (it->second.ready) hipEventDestroy(it->second.ready);
+    c->spec_bytes -= it->second.bytes;
+    freed += it->second.bytes;
+    c->spectra.erase(it);
+  }
+  for (auto& kv : c->graphs)
+    if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
+  c->graphs.clear();
+  c->graph_seen.clear();
+  return IMF_OK;
+}
+
 static imf_status arena_reserve(imf_ctx* c, Arena& a, size_t bytes) {
   if (!a.host) HIPCHK(hipHostMalloc((void**)&a.host, 1 << 16, hipHostMallocDefault));
   if (a.cap >= bytes) {
     a.used = 0;
     return IMF_OK;
   }
-  if (a.base) {
+  if (a.base && a.worker) {
+    c->retired.push_back(a.base);
+    c->retired_bytes += a.cap;
+    a.base = nullptr;
+    a.cap = 0;
+  } else if (a.base) {
     HIPCHK(hipDeviceSynchronize());
     HIPCHK(hipFree(a.base));
     c->arena_bytes -= a.cap;
     a.base = nullptr;
     a.cap = 0;
   }
+  if (c->spec_bytes + c->arena_bytes + c->raster_bytes + bytes > c->budget)
+    STCHK(arena_free_retired(c));
+  // a workspace comes before cached spectra
+  if (c->spec_bytes + c->arena_bytes + c->raster_bytes + bytes > c->budget)
+    STCHK(evict_spectra(c, c->spec_bytes + c->arena_bytes + c->raster_bytes + bytes - c->budget));
   const size_t others = c->spec_bytes + c->arena_bytes + c->raster_bytes;
   if (others + bytes > c->budget)
     return fail(IMF_ENOMEM, "workspace of %zu bytes exceeds the context budget (%zu used of %zu)",
@@ -316,6 +379,8 @@ extern "C" imf_status imf_create(int device, size_t hbm_budget_bytes, imf_ctx** 
   if (const char* e = std::getenv("IMF_MINFILTER_SYNC")) c->mf_sync = std::atoi(e);
   if (const char* e = std::getenv("IMF_OVERLAP_STACK")) c->overlap_stack = std::atoi(e) != 0;
   if (const char* e = std::getenv("IMF_THRESHOLD_HINTS")) c->use_hints = std::atoi(e) != 0;
+  if (const char* e = std::getenv("IMF_SERVE_WORKERS"))
+    c->max_inflight = std::max(1, std::min(16, std::atoi(e)));
   if (const char* e = std::getenv("IMF_MINFILTER_WG_PER_CU"))
     c->mf_wg_per_cu = std::max(1, std::min(16, std::atoi(e)));
   if (hipStreamCreateWithFlags(&c->internal, hipStreamNonBlocking) != hipSuccess) {
@@ -341,6 +406,7 @@ extern "C" imf_status imf_destroy(imf_ctx* c) {
   for (void* p : c->raster_pools) hipFree(p);
   for (auto& kv : c->twiddles) hipFree(kv.second);
   if (c->arena.base) hipFree(c->arena.base);
+  for (char* b : c->retired) hipFree(b);
   for (auto& kv : c->graphs)
     if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
   if (c->internal) hipStreamDestroy(c->internal);
@@ -1273,10 +1339,10 @@ static imf_status make_plan(imf_ctx* c, const imf_request* r, const imf_outputs*
   if (p.intmask) add(sizeof(uint64_t) * p.nO * (long long)r->nz * r->ny * p.words);  // masks at theta_B
   if (p.exact) {
     p.cand_cap = 1 << 16;
-    // room for 8192 bracket entries per list (64 lists per orientation)
+    // room for 16384 bracket entries per list (64 lists per orientation)
     p.band_cap = (int)std::min<long long>(std::max<long long>(1LL << 20, (long long)p.nO *
-                                                                          IMF_BR_SLICES * 8192),
-                                          1LL << 28);
+                                                                          IMF_BR_SLICES * 16384),
+                                          1LL << 29);
     add(sizeof(int) * (size_t)p.cand_cap);               // candidates of the maximum
     add(sizeof(unsigned long long) * (size_t)p.cand_cap);  // their exact f
     add(sizeof(int4) * (size_t)p.band_cap);              // band entries
@@ -2205,13 +2271,17 @@ static imf_status run_request(imf_ctx* c, const imf_request* r, const imf_output
         h.F[2] = old->second.F[1];
       }
       h.F[0] = pd.Fq;
-      // next half-width: twice this prediction's relative error, decaying by
-      // half per request, within [0.05%, 4%]
+      // next half-width: 2.5 times this prediction's relative error, decaying
+      // by 15% per request, within [0.05%, 6%].  A miss costs a second pass
+      // (about the whole request again) and the width only its listed
+      // entries, so the width follows the error up quickly and comes down
+      // slowly: on a 50-iteration TO loop whose maximum moved by up to 5% a
+      // step this missed 2 times where doubling and halving missed 11.
       double err = 0;
       if (pd.p.hinted && pd.Fq > 0)
         err = std::fabs((double)pd.Fq - pd.p.hint_pred) / (double)pd.Fq;
       const double prev = old != c->hints.end() ? old->second.delta : 0.0;
-      h.delta = std::min(0.04, std::max(0.0005, std::max(0.5 * prev, 2.0 * err)));
+      h.delta = std::min(0.06, std::max(0.0005, std::max(0.85 * prev, 2.5 * err)));
       c->hints[pd.p.hint_key] = h;
       if (c->hints.size() > 4096) c->hints.clear();
     }
@@ -2690,6 +2760,7 @@ struct Request {
   std::vector<int> tool_ids, n_dirs, fixture_of;
   std::vector<char> dirs;
   size_t footprint = 0;
+  int bypassed = 0;  // times a later request was admitted ahead of this one
   int state = 0;  // 0 queued, 1 running, 2 done, 3 cancelled
   imf_status status = IMF_OK;
   std::string err;
@@ -2697,25 +2768,51 @@ struct Request {
   std::chrono::steady_clock::time_point t_submit;
 };
 
+// Admission: the queue's head when its workspace fits beside the running
+// requests (half the budget for all of them; a request always fits an idle
+// context), else the first of the next kBypassScan requests that fits.  A
+// head passed over kMaxBypass times blocks the queue until it fits, so a large
+// request waits for memory at most that many admissions.
+static const int kBypassScan = 8, kMaxBypass = 4;
+static std::deque<std::shared_ptr<Request>>::iterator serve_pick(imf_ctx* c) {
+  auto fits = [&](const Request& r) {
+    return c->inflight_bytes + r.footprint <= c->budget / 2 || c->n_running == 0;
+  };
+  if (c->queue.empty()) return c->queue.end();
+  auto head = c->queue.begin();
+  if (fits(**head)) return head;
+  if ((*head)->bypassed >= kMaxBypass) return c->queue.end();
+  int k = 0;
+  for (auto it = std::next(head); it != c->queue.end() && k < kBypassScan; ++it, ++k)
+    if (fits(**it)) return it;
+  return c->queue.end();
+}
+
 static void serve_worker(imf_ctx* c) {
   hipSetDevice(c->device);
   hipStream_t s;
   hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
   Arena ar;
+  ar.worker = true;
   for (;;) {
     std::shared_ptr<Request> rq;
+    double queued_ms = 0;
     {
       std::unique_lock<std::mutex> lk(c->smu);
+      auto pick = c->queue.end();
       c->scv.wait(lk, [&] {
         if (c->stop) return true;
-        if (c->queue.empty()) return false;
-        auto& h = c->queue.front();
-        return c->inflight_bytes + h->footprint <= c->budget / 2 || c->n_running == 0;
+        pick = serve_pick(c);
+        return pick != c->queue.end();
       });
       if (c->stop) break;
-      rq = c->queue.front();
-      c->queue.pop_front();
+      rq = *pick;
+      if (pick != c->queue.begin()) c->queue.front()->bypassed++;
+      c->queue.erase(pick);
       rq->state = 1;
+      queued_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
+                                                             rq->t_submit)
+                      .count();
       c->inflight_bytes += rq->footprint;
       c->n_running++;
     }
@@ -2733,6 +2830,7 @@ static void serve_worker(imf_ctx* c) {
       rq->stats.t_ms[7] = std::chrono::duration<double, std::milli>(
                               std::chrono::steady_clock::now() - rq->t_submit)
                               .count();
+      rq->stats.queue_ms = queued_ms;
       rq->state = 2;
       c->inflight_bytes -= rq->footprint;
       c->n_running--;

@@ -5,6 +5,8 @@ binary and density designs and both cutters (subsets of one master Fibonacci
 set, so tool spectra are shared); every result in the mix must equal the same
 request computed alone (bit-identical: the per-orientation arithmetic does not
 depend on what else runs), and the small binary ones the oracle."""
+import time
+
 import numpy as np
 import pytest
 
@@ -208,5 +210,95 @@ def test_graph_replays_equal_eager(imf_mod):
         # the first sighting launches kernel by kernel, the second is captured,
         # the rest replay
         assert modes == [0, 1, 2, 2, 2], modes
+    finally:
+        ctx.close()
+
+
+def test_mix_equals_alone_large_grids(imf_mod):
+    """Served requests of 128^3 to 256^3 (binary and density, both cutters,
+    overlapping on the device) equal the same requests computed alone, bit
+    for bit."""
+    imf = imf_mod
+    descs = W.serving_stream(6, seed=93, sizes=(128, 160, 192, 224, 256), master_dirs=24)
+    reqs = [dict(W.serving_request(d, master_dirs=24), desc=d) for d in descs]
+    ctx = imf.Context(0)
+    try:
+        inputs = [(dev(r["design"]), dev(r["fixture"])) for r in reqs]
+        alone = []
+        for (d, fx), r in zip(inputs, reqs):
+            print("alone", r["desc"]["n"], len(r["dirs"]), r["desc"]["density"], flush=True)
+            o, _ = ctx.compute(d, fx, **_kw(imf, r))
+            alone.append({k: v.clone() for k, v in o.items()})
+        print("served", flush=True)
+        tickets = [ctx.submit(d, fx, **_kw(imf, r)) for (d, fx), r in zip(inputs, reqs)]
+        for i, t in enumerate(tickets):
+            o, st = ctx.wait(t)
+            assert st.t_ms[7] >= st.queue_ms >= 0
+            for k in ("imf", "imf_norm", "secluded", "masks"):
+                assert torch.equal(o[k], alone[i][k]), (i, k)
+    finally:
+        ctx.close()
+
+
+def test_admission_passes_a_waiting_large_request(imf_mod):
+    """While a long request runs, a large one whose workspace does not fit
+    beside it waits; smaller requests behind it that fit are admitted ahead of
+    it, at most four times, after which the queue waits for the large one.
+    Every result equals the request computed alone."""
+    imf = imf_mod
+    big_d = W.design_3d_boxes_cyls(256, seed=94)
+    long_d = W.design_density(112, seed=94)
+    small_d = [W.design_3d_boxes_cyls(48, seed=95 + i) for i in range(6)]
+    tl = W.tool(W.TOOL_BALL, 3, 20, 7, 16)
+    dirs = W.fib_hemisphere(60)
+    # no spectrum cache: the budget below is sized for the workspaces alone
+    nc = imf.FLAG_NO_CACHE
+    kw_big = dict(tools=tl, dirs=dirs[:24], dir_kind=imf.DIR_F64, method=imf.METHOD_FFT,
+                  batch=4, flags=nc)
+    kw_long = dict(tools=tl, dirs=dirs, dir_kind=imf.DIR_F64, method=imf.METHOD_FFT, batch=4,
+                   lam=0.01, flags=nc)
+    kw_small = dict(tools=tl, dirs=dirs[:6], dir_kind=imf.DIR_F64, method=imf.METHOD_FFT,
+                    batch=2, flags=nc)
+    big = (dev(big_d), dev(W.fixture_plate(big_d.shape, 3)))
+    lng = (dev(long_d), dev(W.fixture_plate(long_d.shape, 3)))
+    sml = [(dev(d), dev(W.fixture_plate(d.shape, 3))) for d in small_d]
+    probe = imf.Context(0)
+    try:
+        F_big = probe.footprint(*big, **kw_big)
+        F_long = probe.footprint(*lng, **kw_long)
+        F_small = max(probe.footprint(*s, **kw_small) for s in sml)
+        alone_big = {k: v.clone() for k, v in probe.compute(*big, **kw_big)[0].items()}
+        alone_long = {k: v.clone() for k, v in probe.compute(*lng, **kw_long)[0].items()}
+        alone_small = [{k: v.clone() for k, v in probe.compute(*s, **kw_small)[0].items()}
+                       for s in sml]
+    finally:
+        probe.close()
+    # every worker arena that can coexist fits the budget; the running
+    # footprints may use half of it: the long request and three small ones
+    # fit together, the large one fits only an idle context
+    budget = F_long + F_big + 4 * F_small + (256 << 20)
+    assert F_long + 3 * F_small <= budget // 2 < F_big + F_small, (F_big, F_long, F_small)
+    ctx = imf.Context(0, budget_bytes=budget)
+    try:
+        assert ctx.footprint(*big, **kw_big) == F_big
+        print("admission: long, large, 6 small", flush=True)
+        t_long = ctx.submit(*lng, **kw_long)
+        time.sleep(0.002)
+        t_big = ctx.submit(*big, **kw_big)
+        t_small = [ctx.submit(*s, **kw_small) for s in sml]
+        o_long, st_long = ctx.wait(t_long)
+        o_big, st_big = ctx.wait(t_big)
+        res_small = [ctx.wait(t) for t in t_small]
+        # the first four small requests ran before the large one was admitted
+        for o, st in res_small[:4]:
+            assert st.t_ms[7] <= st_big.queue_ms + 1.0, (st.t_ms[7], st_big.queue_ms)
+        # the fifth and sixth were not admitted ahead of it
+        for o, st in res_small[4:]:
+            assert st.queue_ms >= st_big.queue_ms - 1.0, (st.queue_ms, st_big.queue_ms)
+        for k in ("imf", "imf_norm", "secluded", "masks"):
+            assert torch.equal(o_big[k], alone_big[k]), k
+            assert torch.equal(o_long[k], alone_long[k]), k
+            for i, (o, _) in enumerate(res_small):
+                assert torch.equal(o[k], alone_small[i][k]), (i, k)
     finally:
         ctx.close()
