@@ -266,6 +266,11 @@ struct imf_inv_args {
   // transform plan of the z, y and x passes (0-3: bit 0 base radices instead
   // of composite ones, bit 1 half-width tiles); 0 is the default
   int fplan[3];
+  // set by imf_launch_inverse from the fields above: float bounds rounded
+  // outward, so float compares select a superset of the double intervals
+  // (th[k] - band, th[k] + band) and (blo, bhi]; log2 of cwx
+  float fth_lo[2], fth_hi[2], fblo, fbhi;
+  int lcwx;
 };
 #define IMF_BR_SLICES 64
 // true when the inverse passes of length n have transform plans other than 0

@@ -14,6 +14,8 @@
 // image) is the complex conjugate of its spectrum (Algorithm 1's Reflect).
 #include "imf_internal.h"
 
+#include <cmath>
+
 #define CT_MAX 16
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
@@ -860,13 +862,17 @@ k_inv_x_c2r(imf_inv_args a, imf_fft_len L, const float2* __restrict__ twg) {
   // (registers), the twiddles behind them, then into LDS
   constexpr int PE = NT > 0 ? (CT * (NT / 2 + 1) + NTH - 1) / NTH : MAXE;
   float2 A[PE], B[PE];
+  // ra / my through a float reciprocal: ra < 2^21 (box rows <= 2^20), so the
+  // float (ra + 1/2) / my is within 2^-23 ra / my < 1 / (4 my) of its value,
+  // less than the 1 / (2 my) that separates it from an integer
+  const float inv_my = 1.0f / (float)my;
 #pragma unroll
   for (int e = 0; e < PE; e++) {
     const int i = threadIdx.x + e * NTH;
     const int c = i / h, k = i - c * h;
     const int ra = row0 + 2 * c;
     // rows ra and ra + 1 of the box: (z, y) of the first, the second follows
-    const int za = ra / my, ya = ra - za * my;
+    const int za = (int)(((float)ra + 0.5f) * inv_my), ya = ra - za * my;
     const int zb = ya + 1 == my ? za + 1 : za, yb = ya + 1 == my ? 0 : ya + 1;
     A[e] = make_float2(0.f, 0.f);
     B[e] = make_float2(0.f, 0.f);
@@ -929,15 +935,15 @@ k_inv_x_c2r(imf_inv_args a, imf_fft_len L, const float2* __restrict__ twg) {
           }
           v = G;
         } else if (a.nth) {
-          if (fabs((double)v - a.th[0]) <= a.band ||
-              (a.nth > 1 && fabs((double)v - a.th[1]) <= a.band)) {
+          if ((v >= a.fth_lo[0] && v <= a.fth_hi[0]) ||
+              (a.nth > 1 && v >= a.fth_lo[1] && v <= a.fth_hi[1])) {
             const int slot = atomicAdd(a.flag_cnt, 1);
             if (slot < a.flag_cap) a.flags[slot] = make_int2(q, li);
           }
         }
         // the expected threshold's bracket (rare: about one entry per
         // workgroup, spread over the workgroups' lists)
-        if (a.blist && (double)v > a.blo && (double)v <= a.bhi) {
+        if (a.blist && v > a.fblo && v <= a.fbhi) {
           const long long sl =
               (long long)(a.q0 + q) * IMF_BR_SLICES + (blockIdx.x % IMF_BR_SLICES);
           const unsigned slot = atomicAdd(a.bcnt + sl, 1u);
@@ -955,7 +961,8 @@ k_inv_x_c2r(imf_inv_args a, imf_fft_len L, const float2* __restrict__ twg) {
         m = fminf(m, dpp_row_shr<2>(m));
         m = fminf(m, dpp_row_shr<4>(m));
         if (gl == 16) m = fminf(m, dpp_row_shr<8>(m));
-        if ((lane & (gl - 1)) == gl - 1 && x - (gl - 1) < mx) atomicMin(&cmrow[x / cwx], f2ord(m));
+        if ((lane & (gl - 1)) == gl - 1 && x - (gl - 1) < mx)
+          atomicMin(&cmrow[x >> a.lcwx], f2ord(m));
       }
     }
   }
@@ -1162,9 +1169,31 @@ hipError_t imf_launch_tool_fft(const imf_tool_fft_args& a, const imf_fft_len& fy
   return hipGetLastError();
 }
 
-hipError_t imf_launch_inverse(const imf_inv_args& a, const imf_fft_len& fx,
+// float nearest below / above a double (outward rounding of a bound)
+static float f_down(double x) {
+  float f = (float)x;
+  if ((double)f > x) f = std::nextafter(f, -INFINITY);
+  return f;
+}
+static float f_up(double x) {
+  float f = (float)x;
+  if ((double)f < x) f = std::nextafter(f, INFINITY);
+  return f;
+}
+
+hipError_t imf_launch_inverse(const imf_inv_args& a_in, const imf_fft_len& fx,
                               const imf_fft_len& fy, const imf_fft_len& fz, const float2* twx,
                               const float2* twy, const float2* twz, hipStream_t s, int stage) {
+  imf_inv_args a = a_in;
+  for (int k = 0; k < 2; k++) {
+    a.fth_lo[k] = f_down(a.th[k] - a.band);
+    a.fth_hi[k] = f_up(a.th[k] + a.band);
+  }
+  a.fblo = f_down(a.blo);
+  a.fbhi = f_up(a.bhi);
+  a.lcwx = 0;
+  while ((1 << a.lcwx) < a.cwx) a.lcwx++;
+  if (a.cellmin && (1 << a.lcwx) != a.cwx) return hipErrorInvalidValue;
   const int h = a.px / 2 + 1;
   hipError_t e = hipSuccess;
   if (stage < 0 || stage == 0) DISPATCH_PLAN(fz.n, a.fplan[0], {
