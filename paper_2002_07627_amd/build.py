@@ -16,10 +16,12 @@ COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
           "-Wno-unused-function", "-Wno-unused-value", "-Wno-unused-result", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 # the rasterization predicate and the coupling arithmetic are evaluated exactly
 # in the order written
-# k_imf.hip never sees a NaN (overlaps, minima and +inf padding only): without
-# NaN semantics its minima need no input canonicalization
+# k_imf.hip and k_fft.hip never see a NaN (overlaps, minima and +inf padding
+# only; a design holding one fails the request): without NaN semantics their
+# minima and maxima need no input canonicalization
 EXTRA = {"k_raster.hip": ["-ffp-contract=off"], "k_couple.hip": ["-ffp-contract=off"],
-         "k_imf.hip": ["-fno-honor-nans"], "k_exact.hip": ["-ffp-contract=off"]}
+         "k_imf.hip": ["-fno-honor-nans"], "k_exact.hip": ["-ffp-contract=off"],
+         "k_fft.hip": ["-fno-honor-nans"]}
 
 
 def _compile(src: str) -> str:

@@ -262,7 +262,7 @@ __device__ __forceinline__ void dft<16>(float2* v, bool inv) { dft_split<4, 4>(v
 // strided global accesses (CT consecutive columns) and the butterflies touch
 // consecutive LDS words.
 // ---------------------------------------------------------------------------
-#define LIDX(j, c) ((j) * (CT + 1) + (c))
+#define LIDX(j, c) (__umul24((j), CT + 1) + (c))  // j < 1024: a 24-bit multiply
 
 // one self-sorting (Stockham) stage, in place: every thread keeps its
 // butterflies in registers across the barrier
@@ -590,10 +590,13 @@ __global__ void __launch_bounds__(NTH) k_pass_strided(strided_io io, imf_fft_len
                                                          const float2* __restrict__ twg,
                                                          const imf_orient_desc* __restrict__ desc,
                                                          int planes_fixed, int n_in_fixed,
-                                                         int n_out_fixed, int inv, int GX, int GY,
-                                                         int GZ) {
+                                                         int n_out_fixed, int inv_arg, int GX,
+                                                         int GY, int GZ) {
   extern __shared__ float2 smem[];
-  const int n = L.n;
+  // the inverse y pass and the tool's forward y pass have a fixed direction
+  // (compile time: no per-twiddle select); the design pass takes it as given
+  const int inv = KIND == PASS_INV_Y ? 1 : (KIND == PASS_TOOL_Y ? 0 : inv_arg);
+  const int n = NT > 0 ? NT : L.n;
   int bx, plane, q;
   if (!xcd_blocks(GX, GY, GZ, bx, plane, q)) return;
   int planes = planes_fixed, n_in = n_in_fixed, n_out = n_out_fixed, sh_in = 0, sh_out = 0;
@@ -622,7 +625,9 @@ __global__ void __launch_bounds__(NTH) k_pass_strided(strided_io io, imf_fft_len
       const int i = threadIdx.x + e * NTH;
       const int j = i / CT, c = i - j * CT;
       v[e] = make_float2(0.f, 0.f);
-      if (j < n_in && c0 + c < io.ncols) v[e] = in[(long long)j * io.in_j + c];
+      if (j < n_in && c0 + c < io.ncols)
+        v[e] = KIND == PASS_DESIGN_Y ? in[(long long)j * io.in_j + c]
+                                     : in[__umul24(j, (unsigned)io.in_j) + c];
     }
     load_twiddles(tw, twg, n);
 #pragma unroll
@@ -649,7 +654,12 @@ __global__ void __launch_bounds__(NTH) k_pass_strided(strided_io io, imf_fft_len
     for (int e = 0; e < PE; e++) {
       const int i = threadIdx.x + e * NTH;
       const int j = i / CT, c = i - j * CT;
-      if (j < n_out && c0 + c < io.ncols) out[(long long)j * io.out_j + c] = v[e];
+      if (j < n_out && c0 + c < io.ncols) {
+        if (KIND == PASS_DESIGN_Y)
+          out[(long long)j * io.out_j + c] = v[e];
+        else
+          out[__umul24(j, (unsigned)io.out_j) + c] = v[e];
+      }
     }
   } else {
     load_twiddles(tw, twg, n);
@@ -768,7 +778,7 @@ __global__ void __launch_bounds__(NTH) k_inv_z_product(imf_inv_args a, imf_fft_l
                                                           const float2* __restrict__ twg, int GX,
                                                           int GY) {
   extern __shared__ float2 smem[];
-  const int n = L.n;
+  const int n = NT > 0 ? NT : L.n;
   const int h = a.px / 2 + 1;
   if (a.cellmin) {  // the x pass lowers these cell minima by atomic min
     const long long nc = (long long)a.nq * a.cell_stride;
@@ -825,13 +835,15 @@ __global__ void __launch_bounds__(NTH) k_inv_z_product(imf_inv_args a, imf_fft_l
     const int mz = d.box_dim[2];
     const int sh = pmod(d.box_lo[2], n);
     float2* dst = a.w1 + q * a.w1_stride + (long long)ky * h + c0;
-    const long long zs = (long long)a.py * h;
+    // a plane of w1 holds py (px/2 + 1) < 2^24 elements, an orientation's
+    // planes fewer than 2^31: 24-bit multiplies, 32-bit offsets
+    const unsigned zs = (unsigned)(a.py * h);
     for (int i = threadIdx.x; i < CT * mz; i += NTH) {
       const int z = i / CT, c = i - z * CT;
       if (c >= ncol) continue;
       int pos = z + sh;
       if (pos >= n) pos -= n;
-      dst[z * zs + c] = X[LIDX(pos, c)];
+      dst[__umul24(z, zs) + c] = X[LIDX(pos, c)];
     }
   }
 }
@@ -872,13 +884,15 @@ k_inv_x_c2r(imf_inv_args a, imf_fft_len L, const float2* __restrict__ twg) {
     const int c = i / h, k = i - c * h;
     const int ra = row0 + 2 * c;
     // rows ra and ra + 1 of the box: (z, y) of the first, the second follows
-    const int za = (int)(((float)ra + 0.5f) * inv_my), ya = ra - za * my;
+    const int za = (int)(((float)ra + 0.5f) * inv_my), ya = ra - (int)__umul24(za, my);
     const int zb = ya + 1 == my ? za + 1 : za, yb = ya + 1 == my ? 0 : ya + 1;
     A[e] = make_float2(0.f, 0.f);
     B[e] = make_float2(0.f, 0.f);
+    // element indices of one orientation's rows: max_mz max_my (px/2 + 1) <
+    // 2^31, rows and row lengths < 2^24 (24-bit multiplies)
     if (i < CT * h) {
-      if (ra < rows) A[e] = src[((long long)za * a.max_my + ya) * h + k];
-      if (ra + 1 < rows) B[e] = src[((long long)zb * a.max_my + yb) * h + k];
+      if (ra < rows) A[e] = src[__umul24(__umul24(za, a.max_my) + ya, h) + k];
+      if (ra + 1 < rows) B[e] = src[__umul24(__umul24(zb, a.max_my) + yb, h) + k];
     }
   }
   load_twiddles(tw, twg, n);
@@ -922,7 +936,7 @@ k_inv_x_c2r(imf_inv_args a, imf_fft_len L, const float2* __restrict__ twg) {
       if (x < mx) {
         int pos = x + sh;
         if (pos >= n) pos -= n;
-        const float2 z = Xc[pos * (CT + 1)];
+        const float2 z = Xc[__umul24(pos, CT + 1)];
         v = odd ? z.y : z.x;
         const int li = row * mx + x;
         if (a.binary) {
