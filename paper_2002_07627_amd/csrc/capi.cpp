@@ -248,7 +248,16 @@ struct imf_ctx {
     double delta = 0;                     // relative half-width of the next bracket
   };
   std::map<std::string, Hint> hints;
+  // fraction of (block, orientation) pairs the bound kept in the last request
+  // with a gamma stack of each shape: sizes the next compact stack
+  std::map<std::string, double> gkept;
   bool use_hints = true;
+  // gamma stack of the kept blocks only, at this fraction of all blocks for
+  // a request shape not seen before (0: always the full stack), used when
+  // the full stack would take more than 1/16 of the budget (room for cached
+  // spectra) or always when set from the environment
+  double compact_gamma = 0.5;
+  bool compact_forced = false;
 };
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -379,6 +388,10 @@ extern "C" imf_status imf_create(int device, size_t hbm_budget_bytes, imf_ctx** 
   if (const char* e = std::getenv("IMF_MINFILTER_SYNC")) c->mf_sync = std::atoi(e);
   if (const char* e = std::getenv("IMF_OVERLAP_STACK")) c->overlap_stack = std::atoi(e) != 0;
   if (const char* e = std::getenv("IMF_THRESHOLD_HINTS")) c->use_hints = std::atoi(e) != 0;
+  if (const char* e = std::getenv("IMF_COMPACT_GAMMA")) {
+    c->compact_gamma = std::max(0.0, std::min(1.0, std::atof(e)));
+    c->compact_forced = true;
+  }
   if (const char* e = std::getenv("IMF_SERVE_WORKERS"))
     c->max_inflight = std::max(1, std::min(16, std::atoi(e)));
   if (const char* e = std::getenv("IMF_MINFILTER_WG_PER_CU"))
@@ -1046,6 +1059,11 @@ struct Plan {
   bool gam = false;               // gamma stack (two-phase masks or exact)
   bool intmask = false;           // masks at theta_B in the workspace (exact, no such output)
   bool gst = false;               // g of every orientation kept (band scan)
+  // gamma stack of the kept blocks only (with the bound): gcap floats, sized
+  // from the kept fraction of the last request of this shape (gkey)
+  bool gcomp = false;
+  long long gcap = 0;
+  std::string gkey;
   int band_cap = 0, cand_cap = 0;
   // an expected threshold (the last exact F_max of this request shape): the
   // inverse x pass lists the overlaps of the bracket (blo, bhi] (voxel units),
@@ -1306,6 +1324,24 @@ static imf_status make_plan(imf_ctx* c, const imf_request* r, const imf_outputs*
     p.nwords_blk = (imf_block_logical(p.shape, r->nx, r->ny, r->nz) + 63) / 64;
     // work lists hold packed block coordinates
     if (nbx >= 1024 || nby >= 2048 || nbz >= 2048) p.bnb = false;
+    // the gamma stack holds the blocks the bound keeps, 64 values each, at a
+    // capacity of 1.25 times the kept fraction seen last time for this shape
+    // (half the blocks before that); above 80% the full stack is kept.  Where
+    // the full stack is small against the budget it is kept too: the compact
+    // one costs a slot lookup per value in the mask pass (256^3 x 130, 8.7 GB
+    // of full stack: +0.8 ms per request)
+    const bool big = 4.0 * (double)p.nO * (double)r->nx * r->ny * r->nz > (double)c->budget / 16;
+    if (p.gam && p.bnb && c->compact_gamma > 0 && (big || c->compact_forced)) {
+      char k[64];
+      snprintf(k, sizeof k, "|%d|%d", p.nO, p.shape);
+      p.gkey = tune_key(p) + k;
+      auto it = c->gkept.find(p.gkey);
+      const double fr = it == c->gkept.end() ? c->compact_gamma
+                                             : std::min(1.0, 1.25 * it->second + 0.01);
+      const long long full = (long long)p.nO * p.nblocks;
+      p.gcomp = fr < 0.8 && full < (1LL << 40);
+      p.gcap = p.gcomp ? 64 * (long long)std::ceil(fr * (double)full) : 0;
+    }
     p.cell_stride = 1;
     p.cell_waves = 1;
     for (int q = 0; q < p.nO; q++) {
@@ -1335,7 +1371,11 @@ static imf_status make_plan(imf_ctx* c, const imf_request* r, const imf_outputs*
   add(sizeof(imf_orient_desc) * p.nO * 2);             // descriptors (+ sweep)
   add(sizeof(float) * p.B * p.max_vol);                // g
   add(sizeof(float) * p.B * std::max(p.nlvl, 1) * p.max_vol);  // levels
-  if (p.gam) add(sizeof(float) * N * p.nO);            // gamma stack
+  if (p.gam) add(sizeof(float) * (p.gcomp ? p.gcap : N * p.nO));  // gamma stack
+  if (p.gcomp) {
+    add(sizeof(long long) * p.nO);                     // each orientation's first slot
+    add(sizeof(int) * (size_t)p.nO * p.nwords_blk);    // list offsets per 64 blocks
+  }
   if (p.intmask) add(sizeof(uint64_t) * p.nO * (long long)r->nz * r->ny * p.words);  // masks at theta_B
   if (p.exact) {
     p.cand_cap = 1 << 16;
@@ -1514,6 +1554,7 @@ struct Pending {
   int graph = 0;            // 0 kernel by kernel, 1 captured and launched, 2 replayed
   unsigned long long Fq = 0;  // exact F_max (fixed point) once finished
   bool hint_ok = false;       // the listed bracket held the band of lambda F_max
+  bool gover = false;         // the compact gamma stack overflowed: a second pass decides
 };
 
 // Enqueue the whole request on stream s (no host synchronization after the
@@ -1558,7 +1599,8 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
   // fixed point, [18] candidates of the maximum, [19] band entries, [20] max
   // |g32 - g| of exact recomputations (density), [21] exact recomputations of
   // the post pass, [22] 1 when the expected threshold's bracket held the band,
-  // [23] entries of the bracket lists, [24] design voxels outside the value set
+  // [23] entries of the bracket lists, [24] design voxels outside the value set,
+  // [25] the compact gamma stack overflowed, [26..27] its slots taken
   unsigned int* fmax_bits = misc;
   unsigned int* maxerr_bits = misc + 1;
   unsigned long long* Fq = (unsigned long long*)(misc + 16);
@@ -1572,7 +1614,9 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
   // overlaps of one batch, or with gst of every orientation (processing order)
   float* g = carve<float>(ar, (size_t)(p.gst ? p.nO : p.B) * p.max_vol);
   float* lvl = carve<float>(ar, (size_t)p.B * std::max(p.nlvl, 1) * p.max_vol);
-  float* gstack = p.gam ? carve<float>(ar, (size_t)N * p.nO) : nullptr;
+  float* gstack = p.gam ? carve<float>(ar, p.gcomp ? (size_t)p.gcap : (size_t)N * p.nO) : nullptr;
+  long long* gbase = p.gcomp ? carve<long long>(ar, p.nO) : nullptr;
+  int* koff = p.gcomp ? carve<int>(ar, (size_t)p.nO * p.nwords_blk) : nullptr;
   uint64_t* intmask =
       p.intmask ? carve<uint64_t>(ar, (size_t)p.nO * r->nz * r->ny * p.words) : nullptr;
   int* cand = p.exact ? carve<int>(ar, p.cand_cap) : nullptr;
@@ -1706,6 +1750,8 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
     put(lp, sizeof lp);
     const int sw[3] = {(int)c->lattice_runs, (int)c->spread_order, (int)c->overlap_stack};
     put(sw, sizeof sw);
+    // the compact gamma stack's capacity moves every workspace offset after it
+    put(&p.gcap, sizeof(p.gcap));
     put(&p.gst, sizeof(p.gst));
     put(&p.known_Fq, sizeof(p.known_Fq));
     put(&p.hinted, sizeof(p.hinted));
@@ -1963,6 +2009,13 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
     ma.skipped = (unsigned long long*)(misc + 8);
     ma.sync_waves = c->mf_sync;
     ma.keepbits = keepbits;
+    if (p.gcomp) {
+      ma.gbase = gbase;
+      ma.koff = koff;
+      ma.gused = (unsigned long long*)(misc + 26);
+      ma.gover = misc + 25;
+      ma.gcap = p.gcap;
+    }
     HIPCHK(imf_launch_minfilter(ma, s, 0));
     tm.mark(10);
     for (int q = 0; q < nq; q++) {
@@ -1995,6 +2048,8 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
   ea.omega0 = om;
   ea.gamma = gstack;
   ea.keep = keepbits;
+  ea.gbase = gbase;
+  ea.koff = koff;
   ea.kstride = p.nwords_blk;
   imf_block_dims(p.shape, ea.WX, ea.WY, ea.WZ);
   ea.gst = p.gst ? g : nullptr;
@@ -2040,7 +2095,7 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
   if (p.gam && !second && mB) {
     HIPCHK(imf_launch_masks_from_gamma(gstack, p.nO, om, r->nx, r->ny, r->nz, Fq, p.scale,
                                        r->lambda, p.exact ? p.E : 0.0, mB, keepbits, p.shape,
-                                       p.nwords_blk, s));
+                                       p.nwords_blk, gbase, koff, s));
     tm.mark(13);
   }
   if (p.exact && (p.gst || p.hinted)) {
@@ -2157,6 +2212,7 @@ static imf_status compute_finish(Pending& pd, imf_stats* st) {
   }
   std::memcpy(&pd.Fq, &pd.host[16], 8);
   pd.hint_ok = p.hinted && pd.host[22] == 1u;
+  pd.gover = p.gcomp && pd.host[25] != 0u;
   float derr;
   std::memcpy(&derr, &pd.host[20], 4);
   if (p.exact && pd.host[18] > (unsigned)p.cand_cap) {
@@ -2261,6 +2317,14 @@ static imf_status run_request(imf_ctx* c, const imf_request* r, const imf_output
     imf_stats tmp{};
     e = compute_finish(pd, st ? st : &tmp);
     if (e != IMF_OK) return e;
+    if (!pd.p.gkey.empty() && pd.kept_at >= 0 && pd.p.nblocks > 0) {
+      // the kept fraction sizes the next compact gamma stack of this shape
+      double kept = 0;
+      for (int q = 0; q < pd.p.nO; q++) kept += (double)(int)pd.host[pd.kept_at + q];
+      std::lock_guard<std::recursive_mutex> lk(c->mu);
+      c->gkept[pd.p.gkey] = kept / ((double)pd.p.nO * (double)pd.p.nblocks);
+      if (c->gkept.size() > 4096) c->gkept.clear();
+    }
     if (pd.p.exact && !pd.p.hint_key.empty()) {
       // remember the exact F_max; a bracket that missed widens next time
       std::lock_guard<std::recursive_mutex> lk(c->mu);
@@ -2285,7 +2349,9 @@ static imf_status run_request(imf_ctx* c, const imf_request* r, const imf_output
       c->hints[pd.p.hint_key] = h;
       if (c->hints.size() > 4096) c->hints.clear();
     }
-    if (!(pd.p.exact && !pd.p.gst && !pd.hint_ok)) {
+    // a second pass with the threshold known: the band of lambda F_max was
+    // neither stored nor listed, or the compact gamma stack overflowed
+    if (!((pd.p.exact && !pd.p.gst && !pd.hint_ok) || pd.gover)) {
       if (st && pass) {
         st->passes = 2;
         st->t_ms[7] += t_first;

@@ -342,6 +342,13 @@ struct imf_min_args {
   unsigned long long* skipped;  // statistics: skipped (block, orientation) pairs
   unsigned long long* keepbits;  // per orientation (request order): kept-block bits, or NULL
   int sync_waves;               // list pass: 0, or 1 / 2 for 4 / 8 waves per workgroup in step
+  // compact gamma stack (with keepbits): the kept blocks of each orientation
+  // only, 64 values per block in list order from gbase[out_q] (-1: the pool
+  // of gcap floats overflowed, *gover set, no values stored); koff[out_q]
+  // holds the list offset of every 64 logical blocks (their exclusive
+  // prefix of kept blocks).  gbase NULL: gamma_stack is [out_q][N].
+  long long* gbase; int* koff; unsigned long long* gused; unsigned int* gover;
+  long long gcap;
 };
 // stage 0: sparse-table levels of the batch (and cell minima, footprints and
 // the threshold bound with branch and bound); stage 1: the bound pass of
@@ -374,6 +381,7 @@ struct imf_exact_args {
   const float* f; const uint8_t* omega0;
   const float* gamma;            // gamma stack [request orientation][N], or NULL
   const unsigned long long* keep; long long kstride;  // kept-block bits per orientation or NULL
+  const long long* gbase; const int* koff;  // compact gamma stack (imf_min_args), or NULL
   int WX, WY, WZ;                // block shape of those bits
   const float* gst; long long gst_stride;   // g of every orientation (processing index), or NULL
   double E;                      // bound on |g32 - g| (voxel units)
@@ -421,7 +429,8 @@ hipError_t imf_launch_masks_from_gamma(const float* gamma_stack, int nq, const u
                                        int nx, int ny, int nz, const unsigned long long* Fq,
                                        double scale, double lambda, double E, uint64_t* masks,
                                        const unsigned long long* keep, int shape,
-                                       long long kstride, hipStream_t s);
+                                       long long kstride, const long long* gbase,
+                                       const int* koff, hipStream_t s);
 
 // coupling to the TO loop (Sec. 2.2)
 hipError_t imf_launch_heaviside(const float* xi, long long n, double beta, float* rho,

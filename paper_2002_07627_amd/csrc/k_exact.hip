@@ -99,12 +99,21 @@ __global__ void __launch_bounds__(IMF_WG) k_exact_f(imf_exact_args a,
     const imf_orient_desc& d = a.desc[q];
     const imf_orient_desc& sd = a.desc[a.nO + q];  // x-runs of S
     if (a.gamma) {  // uniform over the workgroup
+      long long gi = (long long)d.out_q * a.N + vi;  // where gamma is stored, or -1
       if (a.keep) {
         const mf_geom G(a.WX, a.WY, a.WZ, a.nx, a.ny, a.nz);
         const long long lg = G.logical(x / a.WX, y / a.WY, z / a.WZ);
-        if (!((a.keep[(long long)d.out_q * a.kstride + (lg >> 6)] >> (lg & 63)) & 1ull)) continue;
+        const unsigned long long word = a.keep[(long long)d.out_q * a.kstride + (lg >> 6)];
+        if (!((word >> (lg & 63)) & 1ull)) continue;
+        if (a.gbase) {  // compact stack: the block's slot, none after an overflow
+          const long long gb = a.gbase[d.out_q];
+          const int slot = a.koff[(long long)d.out_q * a.kstride + (lg >> 6)] +
+                           __popcll(word & ((1ull << (lg & 63)) - 1));
+          const int li = x % a.WX + a.WX * (y % a.WY + a.WY * (z % a.WZ));
+          gi = gb < 0 ? -1 : gb + (long long)slot * 64 + li;
+        }
       }
-      if ((double)a.gamma[(long long)d.out_q * a.N + vi] > lim) continue;
+      if (gi >= 0 && (double)a.gamma[gi] > lim) continue;
     }
     const int nr = min(sd.n_sruns, EXF_RUNS);
     __syncthreads();

@@ -758,6 +758,8 @@ __global__ void __launch_bounds__(1024) k_scan_masks(imf_min_args a, int qi, int
   __shared__ int carry;
   const unsigned long long* m = a.wmask + (long long)qi * a.wstride;
   int* off = a.woff + (long long)qi * a.wstride;
+  // the offsets again per request orientation, for the compact gamma stack
+  int* koff = a.koff ? a.koff + (long long)a.desc[qi].out_q * a.wstride : nullptr;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (threadIdx.x == 0) carry = 0;
   __syncthreads();
@@ -789,7 +791,10 @@ __global__ void __launch_bounds__(1024) k_scan_masks(imf_min_args a, int qi, int
 #pragma unroll
     for (int j = 0; j < 4; j++) {
       const int i = c0 + threadIdx.x * 4 + j;
-      if (i < nw) off[i] = ex;
+      if (i < nw) {
+        off[i] = ex;
+        if (koff) koff[i] = ex;
+      }
       ex += v[j];
     }
     __syncthreads();
@@ -799,6 +804,13 @@ __global__ void __launch_bounds__(1024) k_scan_masks(imf_min_args a, int qi, int
   if (threadIdx.x == 0) {
     a.count[qi] = carry;
     if (a.kept) a.kept[a.q0 + qi] = carry;
+    if (a.gbase) {  // this orientation's slots in the compact gamma stack
+      const unsigned long long need = 64ull * (unsigned long long)carry;
+      const unsigned long long base = atomicAdd(a.gused, need);
+      const bool over = base + need > (unsigned long long)a.gcap;
+      a.gbase[a.desc[qi].out_q] = over ? -1LL : (long long)base;
+      if (over) atomicOr(a.gover, 1u);
+    }
   }
 }
 
@@ -825,7 +837,8 @@ __global__ void __launch_bounds__(IMF_WG) k_scatter(imf_min_args a, int qi) {
 template <int WX, int WY, int WZ, bool SYNC = false>
 __device__ __forceinline__ void mf_block(const imf_min_args& a, const imf_orient_desc& d,
                                          const mf_run* rr, int qi, int bx, int by, int bz,
-                                         long long blk, bool act = true) {
+                                         long long blk, bool act = true,
+                                         long long slot = -1, long long gb = -1) {
   const int nr = d.n_sruns;
   const long long sx = 1, sy = d.box_dim[0], sz = (long long)d.box_dim[0] * d.box_dim[1];
   const long long sa = d.sv[0] * sx + d.sv[1] * sy + d.sv[2] * sz;  // box offset of sv
@@ -893,8 +906,13 @@ __device__ __forceinline__ void mf_block(const imf_min_args& a, const imf_orient
     const float fo = a.f[vi];
     fnew = fminf(fo, gam);
     if (gam < fo) a.f[vi] = gam;
-    if (a.gamma_stack)
-      a.gamma_stack[(long long)d.out_q * a.nx * a.ny * a.nz + vi] = gam;
+    if (a.gamma_stack) {
+      if (!a.gbase) {
+        a.gamma_stack[(long long)d.out_q * a.nx * a.ny * a.nz + vi] = gam;
+      } else if (gb >= 0 && slot >= 0) {  // compact: the block's slot is its place in
+        a.gamma_stack[gb + slot * 64 + lane] = gam;  // the list, from the orientation's base
+      }
+    }
   }
   if (a.bnb) {
     fnew = wave_max_f(fnew);
@@ -975,6 +993,8 @@ __global__ void __launch_bounds__(64 * NW) k_minfilter_list(imf_min_args a, int 
   mf_stage_runs(a, d, qi, rr);
   __syncthreads();
   const int* list = a.list + (long long)qi * a.list_stride;
+  // the orientation's first slot in a compact gamma stack, read once
+  const long long gb = a.gbase ? a.gbase[d.out_q] : -1;
   const long long per = (M + 7) / 8;
   const long long lo = (long long)(blockIdx.x & 7) * per;
   const long long hi = lo + per < M ? lo + per : M;
@@ -987,7 +1007,7 @@ __global__ void __launch_bounds__(64 * NW) k_minfilter_list(imf_min_args a, int 
       const unsigned int pk = act ? (unsigned int)list[e] : 0u;
       const int bx = (int)(pk & 1023u), by = (int)((pk >> 10) & 2047u), bz = (int)(pk >> 21);
       mf_block<WX, WY, WZ, true>(a, d, rr, qi, bx, by, bz,
-                                 ((long long)bz * G.nby + by) * G.nbx + bx, act);
+                                 ((long long)bz * G.nby + by) * G.nbx + bx, act, e, gb);
     }
     return;
   }
@@ -995,7 +1015,8 @@ __global__ void __launch_bounds__(64 * NW) k_minfilter_list(imf_min_args a, int 
        e += step) {
     const unsigned int pk = (unsigned int)list[e];
     const int bx = (int)(pk & 1023u), by = (int)((pk >> 10) & 2047u), bz = (int)(pk >> 21);
-    mf_block<WX, WY, WZ>(a, d, rr, qi, bx, by, bz, ((long long)bz * G.nby + by) * G.nbx + bx);
+    mf_block<WX, WY, WZ>(a, d, rr, qi, bx, by, bz, ((long long)bz * G.nby + by) * G.nbx + bx,
+                         true, e, gb);
   }
 }
 
@@ -1283,7 +1304,9 @@ __global__ void __launch_bounds__(IMF_WG) k_masks_gamma(const float* __restrict_
                                                         double scale, double lambda, double E,
                                                         uint64_t* __restrict__ masks,
                                                         const unsigned long long* __restrict__ keep,
-                                                        int WX, int WY, int WZ, long long kstride) {
+                                                        int WX, int WY, int WZ, long long kstride,
+                                                        const long long* __restrict__ gbase,
+                                                        const int* __restrict__ koff) {
   const int words = (nx + 63) >> 6;
   const long long wave = (long long)blockIdx.x * (IMF_WG / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -1305,15 +1328,26 @@ __global__ void __launch_bounds__(IMF_WG) k_masks_gamma(const float* __restrict_
   // are 128 voxels wide, blocks x fastest), so one keep word per orientation,
   // the same for the whole wave, holds their bits from (lg0 & 63) on.
   long long kw = 0;
-  int kb0 = 0;
+  int kb0 = 0, li = 0;
   if (keep) {
     const mf_geom G(WX, WY, WZ, nx, ny, nz);
     const int y = (int)(yz % ny), z = (int)(yz / ny);
     const long long lg0 = G.logical((w * 64) / WX, y / WY, z / WZ);
     kw = lg0 >> 6;
     kb0 = (int)(lg0 & 63);
+    li = x % WX + WX * (y % WY + WY * (z % WZ));  // lane of the voxel in its block
   }
   const int kbit = kb0 + (WX < 64 ? lane / WX : 0);
+  // gamma of orientation q here, +inf where its block was skipped (and where
+  // a compact stack overflowed: a second pass then decides the request)
+  auto gamma_at = [&](int q, unsigned long long word) -> float {
+    if (!((word >> kbit) & 1)) return INFINITY;
+    if (!gbase) return g[(long long)q * N];
+    const long long gb = gbase[q];
+    if (gb < 0) return INFINITY;
+    const int slot = koff[(long long)q * kstride + kw] + __popcll(word & ((1ull << kbit) - 1));
+    return gs[gb + (long long)slot * 64 + li];
+  };
   // keep words of 64 orientations at a time, one per lane, then broadcast
   for (int qc = 0; qc < nq; qc += 64) {
     const int nc = nq - qc < 64 ? nq - qc : 64;
@@ -1328,8 +1362,7 @@ __global__ void __launch_bounds__(IMF_WG) k_masks_gamma(const float* __restrict_
     for (; j + 4 <= nc; j += 4) {
       float v[4];
 #pragma unroll
-      for (int i = 0; i < 4; i++)
-        v[i] = (word_of(j + i) >> kbit) & 1 ? g[(long long)(qc + j + i) * N] : INFINITY;
+      for (int i = 0; i < 4; i++) v[i] = gamma_at(qc + j + i, word_of(j + i));
 #pragma unroll
       for (int i = 0; i < 4; i++) {
         const unsigned long long bits = __ballot(in && (double)v[i] + E <= theta);
@@ -1337,7 +1370,7 @@ __global__ void __launch_bounds__(IMF_WG) k_masks_gamma(const float* __restrict_
       }
     }
     for (; j < nc; j++) {
-      const float v = (word_of(j) >> kbit) & 1 ? g[(long long)(qc + j) * N] : INFINITY;
+      const float v = gamma_at(qc + j, word_of(j));
       const unsigned long long bits = __ballot(in && (double)v + E <= theta);
       if (lane == 0) masks[(long long)(qc + j) * per_q + wave] = bits;
     }
@@ -1347,7 +1380,8 @@ hipError_t imf_launch_masks_from_gamma(const float* gamma_stack, int nq, const u
                                        int nx, int ny, int nz, const unsigned long long* Fq,
                                        double scale, double lambda, double E, uint64_t* masks,
                                        const unsigned long long* keep, int shape,
-                                       long long kstride, hipStream_t s) {
+                                       long long kstride, const long long* gbase,
+                                       const int* koff, hipStream_t s) {
   const int words = (nx + 63) >> 6;
   const long long waves = (long long)words * ny * nz;
   const int per = IMF_WG / 64;
@@ -1355,6 +1389,6 @@ hipError_t imf_launch_masks_from_gamma(const float* gamma_stack, int nq, const u
   imf_block_dims(shape, wx, wy, wz);
   hipLaunchKernelGGL(k_masks_gamma, dim3((unsigned)((waves + per - 1) / per)), dim3(IMF_WG), 0, s,
                      gamma_stack, nq, omega0, nx, ny, nz, Fq, scale, lambda, E, masks, keep, wx,
-                     wy, wz, kstride);
+                     wy, wz, kstride, gbase, koff);
   return hipGetLastError();
 }

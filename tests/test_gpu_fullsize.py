@@ -204,9 +204,20 @@ def test_c5_384_density_512_loop_sampled():
     torch.cuda.empty_cache()
     fresh_ctx = imf.Context(0)
     try:
-        o2, _ = fresh_ctx.compute(dev(d1), fx, **kw)
-        for k in warm:
-            assert torch.equal(o2[k].cpu(), warm[k]), k
+        o2, s2 = fresh_ctx.compute(dev(d1), fx, **kw)
+        # bit for bit when both took the same number of passes; otherwise f
+        # may move by up to the guard band where a second pass replaced the
+        # overlaps it rechecked by their exact values (both sides within the
+        # parity tolerance of the exact f), and B, Gamma stay exact
+        assert torch.equal(o2["secluded"].cpu(), warm["secluded"])
+        assert torch.equal(o2["imf_norm"].cpu() > 0, warm["imf_norm"] > 0)
+        if s2.passes == s1.passes:
+            for k in ("imf", "imf_norm"):
+                assert torch.equal(o2[k].cpu(), warm[k]), k
+        else:
+            f, g = o2["imf"].cpu().double(), warm["imf"].double()
+            tol = 2e-4 * torch.clamp(g.abs(), min=w.lam * s1.F_max)
+            assert bool(((f - g).abs() <= tol).all())
         del o2
     finally:
         fresh_ctx.close()

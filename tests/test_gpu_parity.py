@@ -628,3 +628,53 @@ def test_minimum_pass_wave_modes_equal(monkeypatch):
     for o in outs[1:]:
         for k in ("imf", "imf_norm", "secluded", "masks"):
             assert torch.equal(o[k], outs[0][k]), k
+
+
+@pytest.mark.parametrize("design", ["density", "binary"])
+@pytest.mark.parametrize("frac", ["0", "0.5", "0.01"])
+def test_compact_gamma_stack(design, frac, monkeypatch):
+    """With the bound, the two-phase gamma stack holds only the blocks the
+    bound keeps (the others have no mask bit), in a pool sized from the kept
+    fraction of the last request of the shape.  Off (0), at the default first
+    capacity (0.5) and at one too small for this request (0.01: the pool
+    overflows and a second pass with the threshold known decides the
+    request), every result is exact; the repeated request, with the pool sized
+    from the first one's kept fraction, takes one pass."""
+    import paper_2002_07627_amd as imf
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    d, fx, tl, dirs = _bound_case()
+    lam = 0.02
+    if design == "density":  # a crop of a density design, same shape
+        d = np.ascontiguousarray(W.design_density(max(d.shape), seed=23)[:d.shape[0], :d.shape[1],
+                                                                        :d.shape[2]])
+    key = "compact_" + design
+    if key not in _BND_REF:
+        _BND_REF[key] = oracle.imf(oracle.Request(d, fx, tools=tl, dirs=dirs, dir_kind=0,
+                                                  lam=lam))
+    ref = _BND_REF[key]
+    monkeypatch.setenv("IMF_BOUND_MIN_VOXELS", "0")
+    monkeypatch.setenv("IMF_COMPACT_GAMMA", frac)
+    monkeypatch.setenv("IMF_OVERLAP_STACK", "1")
+    c = imf.Context(0)
+    try:
+        passes = []
+        for rep in range(2):
+            print("compact gamma", design, frac, rep, flush=True)
+            out, st = c.compute(dev(d), dev(fx), tools=tl, dirs=dirs, lam=lam,
+                                method=imf.METHOD_FFT, flags=imf.FLAG_NO_GRAPH)
+            if design == "density":
+                check_density(out, st, ref, lam)
+            else:
+                check_binary(out, ref)
+            assert 0 < st.bound_skipped < st.bound_blocks
+            passes.append(st.passes)
+    finally:
+        c.close()
+    # the one-pass repeat's bound kept what the first request's first pass
+    # kept: the first pool overflowed exactly when that exceeds its capacity
+    kept = st.bound_blocks - st.bound_skipped
+    over = float(frac) > 0 and kept > int(np.ceil(float(frac) * st.bound_blocks))
+    assert passes == [2 if over else 1, 1], (passes, kept, st.bound_blocks)
+    if frac == "0.01":
+        assert over

@@ -4,7 +4,9 @@ The serving mix takes requests of different grid sizes, orientation counts,
 binary and density designs and both cutters (subsets of one master Fibonacci
 set, so tool spectra are shared); every result in the mix must equal the same
 request computed alone (bit-identical: the per-orientation arithmetic does not
-depend on what else runs), and the small binary ones the oracle."""
+depend on what else runs; f of density requests up to float rounding where
+the two took a different number of passes), and the small binary ones the
+oracle."""
 import time
 
 import numpy as np
@@ -39,23 +41,43 @@ def _kw(imf, r):
                 method=imf.METHOD_FFT)
 
 
+def _same(o, a, same_passes, i, F_max=0.0, lam=0.0):
+    """A served result against the same request alone: bit for bit, except
+    f of a density request decided in two passes on one side and in one on
+    the other: the second pass replaces the overlaps it rechecks by their
+    exact values (float32 rounded), so f may move by up to the guard band
+    there; both sides are within the parity tolerance of the exact f, so
+    within twice it of each other.  The masks, B and Gamma are exact either
+    way."""
+    for k in ("secluded", "masks"):
+        assert torch.equal(o[k], a[k]), (i, k)
+    if same_passes:
+        for k in ("imf", "imf_norm"):
+            assert torch.equal(o[k], a[k]), (i, k)
+    else:
+        assert torch.equal(o["imf_norm"] > 0, a["imf_norm"] > 0), i
+        f, g = o["imf"].double(), a["imf"].double()
+        tol = 2e-4 * torch.clamp(g.abs(), min=lam * F_max)
+        assert bool(((f - g).abs() <= tol).all()), i
+
+
 def test_mix_equals_alone(imf_mod):
     imf = imf_mod
     reqs = _mix()
     ctx = imf.Context(0)
     try:
-        alone = []
+        alone, passes = [], []
         for r in reqs:
-            o, _ = ctx.compute(dev(r["design"]), dev(r["fixture"]), **_kw(imf, r))
+            o, st = ctx.compute(dev(r["design"]), dev(r["fixture"]), **_kw(imf, r))
             alone.append({k: v.clone() for k, v in o.items()})
+            passes.append(st.passes)
         inputs = [(dev(r["design"]), dev(r["fixture"])) for r in reqs]
         tickets = [ctx.submit(d, fx, **_kw(imf, r)) for (d, fx), r in zip(inputs, reqs)]
         lat = []
         for i, t in enumerate(tickets):
             o, st = ctx.wait(t)
             lat.append(st.t_ms[7])
-            for k in ("imf", "imf_norm", "secluded", "masks"):
-                assert torch.equal(o[k], alone[i][k]), (i, k)
+            _same(o, alone[i], st.passes == passes[i], i, st.F_max, reqs[i]["lam"])
         assert all(x > 0 for x in lat)
     finally:
         ctx.close()
@@ -224,18 +246,18 @@ def test_mix_equals_alone_large_grids(imf_mod):
     ctx = imf.Context(0)
     try:
         inputs = [(dev(r["design"]), dev(r["fixture"])) for r in reqs]
-        alone = []
+        alone, passes = [], []
         for (d, fx), r in zip(inputs, reqs):
             print("alone", r["desc"]["n"], len(r["dirs"]), r["desc"]["density"], flush=True)
-            o, _ = ctx.compute(d, fx, **_kw(imf, r))
+            o, st = ctx.compute(d, fx, **_kw(imf, r))
             alone.append({k: v.clone() for k, v in o.items()})
+            passes.append(st.passes)
         print("served", flush=True)
         tickets = [ctx.submit(d, fx, **_kw(imf, r)) for (d, fx), r in zip(inputs, reqs)]
         for i, t in enumerate(tickets):
             o, st = ctx.wait(t)
             assert st.t_ms[7] >= st.queue_ms >= 0
-            for k in ("imf", "imf_norm", "secluded", "masks"):
-                assert torch.equal(o[k], alone[i][k]), (i, k)
+            _same(o, alone[i], st.passes == passes[i], i, st.F_max, reqs[i]["lam"])
     finally:
         ctx.close()
 
