@@ -1685,6 +1685,25 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
       }
     }
   }
+  // Batches whose computed spectra all stay transient (no room in the
+  // cache): the tool's z transform is left to the product pass, which reads
+  // the tool after its x and y transforms (tdim z planes of them) instead of
+  // a whole spectrum written and read back (App. B's pruned transform, fused).
+  std::vector<char> fused(nb, 0);
+  if (p.method == IMF_METHOD_FFT)
+    for (int b = 0; b < nb; b++) {
+      int nm = 0;
+      bool transient = true;
+      for (int q = p.bstart[b]; q < p.bstart[b + 1]; q++)
+        if (need_fft[q]) {
+          nm++;
+          if (fresh[q]) transient = false;
+        }
+      fused[b] = nm > 0 && transient;
+      if (fused[b])
+        for (int q = p.bstart[b], m = 0; q < p.bstart[b + 1]; q++)
+          if (need_fft[q]) p.desc[q].tmid = tw2 + (long long)(m++) * tw2_stride;
+    }
   p.sweep_desc = p.desc;
   for (int q = 0; q < p.nO; q++) {
     p.sweep_desc[q].sruns = p.ent[q]->sxruns;
@@ -1859,7 +1878,7 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
       if (nmiss[b]) {
         imf_tool_fft_args ta{d_miss + (size_t)b * p.B, nmiss[b], p.P[0], p.P[1], p.P[2],
                              p.max_t[1], p.max_t[2], tw1, tw2, tw1_stride, tw2_stride};
-        for (int stage = 0; stage < 3; stage++) {
+        for (int stage = 0; stage < (fused[b] ? 2 : 3); stage++) {
           HIPCHK(imf_launch_tool_fft(ta, p.fl[1], p.fl[2], twx, twy, twz, s, stage));
           tm.mark(3 + stage);
         }
@@ -1907,6 +1926,7 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
       }
       ia.cellmin = cm_fused ? cellmin : nullptr;
       for (int k = 0; k < 3; k++) ia.fplan[k] = (p.fft_plan >> (2 * k)) & 3;
+      ia.fused = fused[b];
       ia.cell_stride = p.cell_stride;
       ia.cwx = cwx;
       ia.cwy = cwy;

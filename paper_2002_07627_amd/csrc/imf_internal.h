@@ -104,6 +104,10 @@ struct imf_orient_desc {
   const imf_run* sruns;  // sharp-point runs along sv (x-runs for the sweep route)
   const imf_run* truns;  // x-runs of the tool T, row order (z, y)
   float2* spec;          // this orientation's tool spectrum [py][px/2+1][pz]
+  // or (spectrum not kept): the tool after its x and y transforms,
+  // [tdim z][py][px/2+1] at this address; the product pass finishes the z
+  // transform of each column tile in LDS instead of reading a spectrum
+  const float2* tmid;
 };
 
 // Logical block order of the sharp-point minimum: bricks of 128 x 16 x 16
@@ -266,6 +270,8 @@ struct imf_inv_args {
   // transform plan of the z, y and x passes (0-3: bit 0 base radices instead
   // of composite ones, bit 1 half-width tiles); 0 is the default
   int fplan[3];
+  // 1: some descriptors of the batch carry tmid (no spectrum)
+  int fused;
   // set by imf_launch_inverse from the fields above: float bounds rounded
   // outward, so float compares select a superset of the double intervals
   // (th[k] - band, th[k] + band) and (blo, bhi]; log2 of cwx

@@ -773,7 +773,9 @@ __global__ void __launch_bounds__(IMF_WG) k_tool_x(const imf_orient_desc* __rest
 //     The rho_hat tile is kept in registers and reused for every orientation
 //     of the batch.
 // ---------------------------------------------------------------------------
-template <int CT, int MAXE, int NT, int NTH = IMF_WG, int SPLIT = 0>
+// FUSE: some orientations of the batch have no spectrum (desc.tmid set);
+// the instance without it is the all-cached path
+template <int CT, int MAXE, int NT, int NTH = IMF_WG, int SPLIT = 0, bool FUSE = false>
 __global__ void __launch_bounds__(NTH) k_inv_z_product(imf_inv_args a, imf_fft_len L,
                                                           const float2* __restrict__ twg, int GX,
                                                           int GY) {
@@ -806,6 +808,7 @@ __global__ void __launch_bounds__(NTH) k_inv_z_product(imf_inv_args a, imf_fft_l
   // the current one is transformed
   float2 tp[RE];
   auto fetch = [&](int q) {
+    if (FUSE && a.desc[q].tmid) return;  // generated in LDS instead
     const float2* tsrc = a.desc[q].spec + ((long long)ky * h + c0) * n;
 #pragma unroll
     for (int e = 0; e < RE; e++) {
@@ -817,16 +820,46 @@ __global__ void __launch_bounds__(NTH) k_inv_z_product(imf_inv_args a, imf_fft_l
   for (int q = 0; q < a.nq; q++) {
     const imf_orient_desc& d = a.desc[q];
     __syncthreads();
+    if (FUSE && d.tmid) {  // uniform: the tool column tile from its x and y transforms
+      // the tdim z rows it has (the tool placed at z offset tlo), zero
+      // elsewhere, transformed forward along z here: the same transform the
+      // spectrum would have been computed with
+      const float2* src = d.tmid + (long long)ky * h + c0;
+      const int nin = d.tdim[2], shz = pmod(d.tlo[2], n);
+      const unsigned ps = (unsigned)(a.py * h);  // plane stride, < 2^24
+      for (int i = threadIdx.x; i < CT * n; i += NTH) {
+        const int j = i / CT, c = i - j * CT;
+        float2 v = make_float2(0.f, 0.f);
+        if (j < nin && c < ncol) v = src[__umul24(j, ps) + c];
+        int pos = j + shz;
+        if (pos >= n) pos -= n;
+        X[LIDX(pos, c)] = v;
+      }
+      __syncthreads();
+      fft_tile<CT, MAXE, NT, NTH, SPLIT>(X, tw, L, false);
 #pragma unroll
-    for (int e = 0; e < RE; e++) {
-      const int i = threadIdx.x + e * NTH;
-      if (i < CT * n) {
-        const int c = i / n, k = i - c * n;
-        const float2 t = tp[e];
-        const float2 r = rho[e];
-        // r * conj(t) * scale (zero past the last column: both are zero there)
-        X[LIDX(k, c)] =
-            make_float2((r.x * t.x + r.y * t.y) * scale, (r.y * t.x - r.x * t.y) * scale);
+      for (int e = 0; e < RE; e++) {
+        const int i = threadIdx.x + e * NTH;
+        if (i < CT * n) {
+          const int c = i / n, k = i - c * n;
+          const float2 t = X[LIDX(k, c)];
+          const float2 r = rho[e];
+          X[LIDX(k, c)] =
+              make_float2((r.x * t.x + r.y * t.y) * scale, (r.y * t.x - r.x * t.y) * scale);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < RE; e++) {
+        const int i = threadIdx.x + e * NTH;
+        if (i < CT * n) {
+          const int c = i / n, k = i - c * n;
+          const float2 t = tp[e];
+          const float2 r = rho[e];
+          // r * conj(t) * scale (zero past the last column: both are zero there)
+          X[LIDX(k, c)] =
+              make_float2((r.x * t.x + r.y * t.y) * scale, (r.y * t.x - r.x * t.y) * scale);
+        }
       }
     }
     if (q + 1 < a.nq) fetch(q + 1);
@@ -1212,7 +1245,8 @@ hipError_t imf_launch_inverse(const imf_inv_args& a_in, const imf_fft_len& fx,
   hipError_t e = hipSuccess;
   if (stage < 0 || stage == 0) DISPATCH_PLAN(fz.n, a.fplan[0], {
     const size_t sm = smem_bytes(fz.n, CT);
-    auto k = k_inv_z_product<CT, MAXE, NT, NTHP, SPLIT>;
+    auto k = a.fused ? k_inv_z_product<CT, MAXE, NT, NTHP, SPLIT, true>
+                     : k_inv_z_product<CT, MAXE, NT, NTHP, SPLIT, false>;
     if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
     const int GX = (h + CT - 1) / CT;
     hipLaunchKernelGGL(k, dim3(xcd_grid(GX, a.py, 1)), dim3(NTHP), sm, s, a, fz, twz, GX, a.py);
