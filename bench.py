@@ -408,6 +408,10 @@ def main():
             (k, v["ms_per_step"], v["launches_per_step"],
              "%.0f" % v["GBps"] if v["GBps"] else "-"))
     RUN_KERNELS.update(minfilter_kernels(stats[-1].mf_shape))
+    # the committed traffic covers the default transform plan of each pass
+    for i, k in enumerate(("inv_z_product", "inv_y", "inv_x_c2r")):
+        if (stats[-1].fft_plan >> (2 * i)) & 3:
+            RUN_KERNELS[k] = "plan %d" % ((stats[-1].fft_plan >> (2 * i)) & 3)
     roofline = roofline_of(dom, kms, kn, kb, ko, stats[-1], N)
     # measured HBM traffic of the whole request: per-launch FETCH + WRITE bytes
     # of the committed counter runs times this run's launches, for the kernel
