@@ -153,6 +153,8 @@ def serving_leg(imf, W, torch, n_req=64, load=0.7, seed=7627004):
         ctx.close()
     lat = np.array([st.t_ms[7] for st in sts])
     queued = np.array([st.queue_ms for st in sts])
+    lockw = np.array([st.lock_ms for st in sts])
+    hold = np.array([st.hold_ms for st in sts])
     alone = np.array(alone)
     slow = lat / alone
     i99 = int(np.argsort(lat)[min(n_req - 1, int(round(0.99 * (n_req - 1))))])
@@ -169,6 +171,12 @@ def serving_leg(imf, W, torch, n_req=64, load=0.7, seed=7627004):
             "slowdown_p99": round(float(np.percentile(slow, 99)), 2),
             "queue_p50_ms": round(float(np.percentile(queued, 50)), 2),
             "queue_p99_ms": round(float(np.percentile(queued, 99)), 2),
+            # host time waiting for the context lock / holding it (planning
+            # and enqueueing), per request
+            "lock_wait_p50_ms": round(float(np.percentile(lockw, 50)), 2),
+            "lock_wait_p99_ms": round(float(np.percentile(lockw, 99)), 2),
+            "lock_hold_p50_ms": round(float(np.percentile(hold, 50)), 2),
+            "lock_hold_p99_ms": round(float(np.percentile(hold, 99)), 2),
             "p99_request": {"grid": int(descs[i99]["n"]), "orientations": len(reqs[i99][2]["dirs"]),
                             "density": bool(descs[i99]["density"]),
                             "alone_ms": round(float(alone[i99]), 2),

@@ -206,6 +206,10 @@ typedef struct {
                               5, 7 instead of composite radices, bit 1 half-width tiles */
   double queue_ms;         /* served requests: submission to admission (t_ms[7] is
                               submission to completion); 0 for imf_compute */
+  double lock_ms;          /* host time spent waiting for the context lock (served
+                              requests: behind the other workers' planning) */
+  double hold_ms;          /* host time holding it: planning the request, reserving
+                              memory, caches and enqueueing its kernels */
 } imf_stats;
 
 /* Bytes of device workspace the request needs (admission control).  The

@@ -2322,12 +2322,18 @@ static imf_status run_request(imf_ctx* c, const imf_request* r, const imf_output
   double t_first = 0;
   long long flags_first = 0;
   int hinted_first = 0;
+  double lock_ms = 0, hold_ms = 0;  // waiting for the context lock, holding it
+  using clk = std::chrono::steady_clock;
   for (int pass = 0; pass < 2; pass++) {
     Pending pd;
     imf_status e;
     {
+      const auto t0 = clk::now();
       std::lock_guard<std::recursive_mutex> lk(c->mu);
+      const auto t1 = clk::now();
       e = compute_launch(c, r, out, s, ar, pd, pass ? &known : nullptr);
+      lock_ms += std::chrono::duration<double, std::milli>(t1 - t0).count();
+      hold_ms += std::chrono::duration<double, std::milli>(clk::now() - t1).count();
       if (e != IMF_OK) {
         hipStreamSynchronize(s);
         pd.tm.release();
@@ -2337,6 +2343,10 @@ static imf_status run_request(imf_ctx* c, const imf_request* r, const imf_output
     imf_stats tmp{};
     e = compute_finish(pd, st ? st : &tmp);
     if (e != IMF_OK) return e;
+    if (st) {
+      st->lock_ms = lock_ms;
+      st->hold_ms = hold_ms;
+    }
     if (!pd.p.gkey.empty() && pd.kept_at >= 0 && pd.p.nblocks > 0) {
       // the kept fraction sizes the next compact gamma stack of this shape
       double kept = 0;

@@ -70,7 +70,8 @@ class _Stats(C.Structure):
                 ("mf_wg_per_cu", C.c_int), ("max_abs_err", C.c_float),
                 ("post_exact", C.c_longlong), ("band_entries", C.c_longlong),
                 ("passes", C.c_int), ("box_voxels", C.c_double), ("hinted", C.c_int),
-                ("fft_plan", C.c_int), ("queue_ms", C.c_double)]
+                ("fft_plan", C.c_int), ("queue_ms", C.c_double),
+                ("lock_ms", C.c_double), ("hold_ms", C.c_double)]
 
 
 @dataclass
@@ -105,6 +106,8 @@ class Stats:
     hinted: int         # 1 expected threshold's bracket held, 2 missed, 0 none
     fft_plan: int       # inverse transform plans, 2 bits per pass (z | y << 2 | x << 4)
     queue_ms: float     # served requests: submission to admission
+    lock_ms: float      # host time waiting for the context lock
+    hold_ms: float      # host time holding it (planning and enqueueing)
 
     @classmethod
     def _from(cls, s: _Stats):
@@ -116,7 +119,8 @@ class Stats:
                    s.model_bytes, tuple(s.P), s.n_orient, s.method, s.batch, s.cache_hits,
                    s.cache_misses, kms, kn, kb, ko, s.bound_blocks, s.bound_skipped, s.graph,
                    s.lattice_runs, s.mf_shape, s.mf_wg_per_cu, s.max_abs_err, s.post_exact,
-                   s.band_entries, s.passes, s.box_voxels, s.hinted, s.fft_plan, s.queue_ms)
+                   s.band_entries, s.passes, s.box_voxels, s.hinted, s.fft_plan, s.queue_ms,
+                   s.lock_ms, s.hold_ms)
 
 
 _lib = None
