@@ -46,8 +46,9 @@ struct imf_raster_desc {
 // Order-preserving map of float to unsigned int (atomic min / max of floats,
 // and cell minima that several workgroups lower).
 __device__ __forceinline__ unsigned int f2ord(float f) {
+  // negative: every bit flipped; otherwise the sign bit set
   const unsigned int b = __float_as_uint(f);
-  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+  return b ^ ((unsigned int)((int)b >> 31) | 0x80000000u);
 }
 __device__ __forceinline__ float ord2f(unsigned int u) {
   return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
@@ -272,11 +273,12 @@ struct imf_inv_args {
   int fplan[3];
   // 1: some descriptors of the batch carry tmid (no spectrum)
   int fused;
-  // set by imf_launch_inverse from the fields above: float bounds rounded
-  // outward, so float compares select a superset of the double intervals
-  // (th[k] - band, th[k] + band) and (blo, bhi]; log2 of cwx
-  float fth_lo[2], fth_hi[2], fblo, fbhi;
-  int lcwx;
+  // set by imf_launch_inverse from the fields above, so float compares
+  // select a superset of the double intervals: |g - fth_c[k]| <= fth_r[k]
+  // for (th[k] - band, th[k] + band), fblo < g <= fbhi (bounds rounded
+  // outward) for (blo, bhi]; log2 of cwx, cwy, cwz
+  float fth_c[2], fth_r[2], fblo, fbhi;
+  int lcwx, lcwy, lcwz;
 };
 #define IMF_BR_SLICES 64
 // true when the inverse passes of length n have transform plans other than 0

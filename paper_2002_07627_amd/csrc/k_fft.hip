@@ -15,6 +15,7 @@
 #include "imf_internal.h"
 
 #include <cmath>
+#include <type_traits>
 
 #define CT_MAX 16
 
@@ -490,12 +491,28 @@ static inline unsigned xcd_grid(long long GX, long long GY, long long GZ) {
   return (unsigned)((GX * GY * GZ + 7) / 8 * 8);
 }
 
-// the value of the lane n below in the same 16-lane row, +inf for the row's
-// first n lanes (a DPP row shift: no LDS traffic)
+// min of v and the value of the lane N below in the same 16-lane row; the
+// row's first N lanes keep v.  One VALU instruction with a DPP row shift on
+// its first operand: without bound_ctrl a lane whose source lies outside its
+// row is not written, so it keeps its own value.  Every lane of the wave must
+// be active.  The nop gives the two wait states a DPP read needs after a
+// VALU write of the same register.
 template <int N>
-__device__ __forceinline__ float dpp_row_shr(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(INFINITY), __float_as_int(v),
-                                                    0x110 | N, 0xf, 0xf, false));
+__device__ __forceinline__ float dpp_min_shr(float v) {
+  static_assert(N == 1 || N == 2 || N == 4 || N == 8, "row shift");
+  if constexpr (N == 1)
+    asm volatile("s_nop 1\n\tv_min_f32_dpp %0, %0, %0 row_shr:1 row_mask:0xf bank_mask:0xf"
+                 : "+v"(v));
+  else if constexpr (N == 2)
+    asm volatile("s_nop 1\n\tv_min_f32_dpp %0, %0, %0 row_shr:2 row_mask:0xf bank_mask:0xf"
+                 : "+v"(v));
+  else if constexpr (N == 4)
+    asm volatile("s_nop 1\n\tv_min_f32_dpp %0, %0, %0 row_shr:4 row_mask:0xf bank_mask:0xf"
+                 : "+v"(v));
+  else
+    asm volatile("s_nop 1\n\tv_min_f32_dpp %0, %0, %0 row_shr:8 row_mask:0xf bank_mask:0xf"
+                 : "+v"(v));
+  return v;
 }
 
 __device__ __forceinline__ int pmod(long long a, int n) {
@@ -952,66 +969,87 @@ k_inv_x_c2r(imf_inv_args a, imf_fft_len L, const float2* __restrict__ twg) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nch = (mx + 63) >> 6;
   const int gl = a.cellmin ? min(a.cwx, 16) : 16;  // lanes per reduced group
-  const int cwx = a.cwx, cwy = a.cwy, cwz = a.cwz;
-  const int cdx = (mx + cwx - 1) / cwx + 1, cdy = (my + cwy - 1) / cwy + 1;
+  const int cdx = (mx + a.cwx - 1) / a.cwx + 1, cdy = (my + a.cwy - 1) / a.cwy + 1;
+  // the row's value at tile position j is float FS j + rr of the tile
+  // (complex column rr / 2, real part for even rr, imaginary for odd)
+  constexpr unsigned FS = 2 * (CT + 1);  // floats per tile row
+  const float* Xf = reinterpret_cast<const float*>(X);
+  const unsigned tile_end = (unsigned)n * FS;
+  // (z, y) of the tile's first row; a wave's rows follow by counting
+  const int z0 = row0 / my, y0 = row0 - z0 * my;
   for (int rr = wave; rr < 2 * CT; rr += NTH / 64) {
     const int row = row0 + rr;
     if (row >= rows) break;
-    const int zz = row / my, yy = row - zz * my;
-    const bool odd = rr & 1;
-    const float2* Xc = X + (rr >> 1);
+    int zz = z0, yy = y0 + rr;
+    while (yy >= my) {
+      yy -= my;
+      zz++;
+    }
     float* drow = dst + (long long)row * mx;
     unsigned int* cmrow =
-        a.cellmin ? a.cellmin + q * a.cell_stride + ((zz / cwz) * cdy + yy / cwy) * cdx : nullptr;
-    for (int ch = 0; ch < nch; ch++) {
+        a.cellmin
+            ? a.cellmin + q * a.cell_stride + ((zz >> a.lcwz) * cdy + (yy >> a.lcwy)) * cdx
+            : nullptr;
+    const unsigned i0 = __umul24((unsigned)(lane + sh), FS) + (unsigned)rr;
+    // one 64-voxel chunk; FULL: every lane lies inside the row
+    auto chunk = [&](int ch, auto full) {
+      constexpr bool FULL = decltype(full)::value;
       const int x = ch * 64 + lane;
-      float v = INFINITY;
-      if (x < mx) {
-        int pos = x + sh;
-        if (pos >= n) pos -= n;
-        const float2 z = Xc[__umul24(pos, CT + 1)];
-        v = odd ? z.y : z.x;
+      const bool in = FULL || x < mx;
+      // tile position (x + sh) mod n: for x < mx, x + sh < 2n and below n
+      // the unsigned difference wraps above the sum (rr < FS); lanes past the
+      // row's end read an in-tile value that is discarded
+      const unsigned t = i0 + (unsigned)ch * (64 * FS);
+      float v = Xf[FULL ? min(t, t - tile_end) : min(min(t, t - tile_end), tile_end - 1)];
+      // overlaps to recompute exactly (guard band) and entries of the
+      // expected threshold's bracket are rare: found per lane, handled on a
+      // branch the wave takes only when some lane has one
+      bool flag = false;
+      if (a.binary) {
+        const float G = rintf(v);
+        const float e = in ? fabsf(v - G) : 0.f;
+        local_err = fmaxf(local_err, e);
+        flag = e > a.delta;
+        v = G;
+      } else if (a.nth) {  // within either band (the second repeats the first for one)
+        flag = in & ((fabsf(v - a.fth_c[0]) <= a.fth_r[0]) | (fabsf(v - a.fth_c[1]) <= a.fth_r[1]));
+      }
+      const bool brk = a.blist && in && v > a.fblo && v <= a.fbhi;
+      if (__builtin_expect(__ballot(flag | brk) != 0, 0)) {
         const int li = row * mx + x;
-        if (a.binary) {
-          const float G = rintf(v);
-          const float e = fabsf(v - G);
-          local_err = fmaxf(local_err, e);
-          if (e > a.delta) {
-            const int slot = atomicAdd(a.flag_cnt, 1);
-            if (slot < a.flag_cap) a.flags[slot] = make_int2(q, li);
-          }
-          v = G;
-        } else if (a.nth) {
-          if ((v >= a.fth_lo[0] && v <= a.fth_hi[0]) ||
-              (a.nth > 1 && v >= a.fth_lo[1] && v <= a.fth_hi[1])) {
-            const int slot = atomicAdd(a.flag_cnt, 1);
-            if (slot < a.flag_cap) a.flags[slot] = make_int2(q, li);
-          }
+        if (flag) {
+          const int slot = atomicAdd(a.flag_cnt, 1);
+          if (slot < a.flag_cap) a.flags[slot] = make_int2(q, li);
         }
-        // the expected threshold's bracket (rare: about one entry per
-        // workgroup, spread over the workgroups' lists)
-        if (a.blist && v > a.fblo && v <= a.fbhi) {
+        if (brk) {  // spread over the orientation's lists by workgroup
           const long long sl =
               (long long)(a.q0 + q) * IMF_BR_SLICES + (blockIdx.x % IMF_BR_SLICES);
           const unsigned slot = atomicAdd(a.bcnt + sl, 1u);
           if (slot < (unsigned)a.bslot)
             a.blist[sl * a.bslot + slot] = make_int4(a.q0 + q, li, __float_as_int(v), 0);
         }
+      }
+      if (FULL) {
         drow[x] = v;
+      } else {
+        if (in) drow[x] = v;
+        v = in ? v : INFINITY;
       }
       if (cmrow) {
         // minima of the row's cells over the values just written (rounded
         // when binary; +inf past the row's end), one atomic min per group of
         // gl lanes; the recheck lowers a cell again when it corrects a value
-        float m = v;
-        m = fminf(m, dpp_row_shr<1>(m));
-        m = fminf(m, dpp_row_shr<2>(m));
-        m = fminf(m, dpp_row_shr<4>(m));
-        if (gl == 16) m = fminf(m, dpp_row_shr<8>(m));
-        if ((lane & (gl - 1)) == gl - 1 && x - (gl - 1) < mx)
-          atomicMin(&cmrow[x >> a.lcwx], f2ord(m));
+        float m = dpp_min_shr<1>(v);
+        m = dpp_min_shr<2>(m);
+        m = dpp_min_shr<4>(m);
+        if (gl == 16) m = dpp_min_shr<8>(m);
+        if ((lane & (gl - 1)) == gl - 1 && (FULL || x - (gl - 1) < mx))
+          atomicMin(cmrow + ((unsigned)x >> a.lcwx), f2ord(m));
       }
-    }
+    };
+    const int nfull = mx >> 6;
+    for (int ch = 0; ch < nfull; ch++) chunk(ch, std::true_type{});
+    if (nfull < nch) chunk(nfull, std::false_type{});
   }
   if (a.binary) {
     for (int o = 32; o > 0; o >>= 1) local_err = fmaxf(local_err, __shfl_xor(local_err, o));
@@ -1232,15 +1270,27 @@ hipError_t imf_launch_inverse(const imf_inv_args& a_in, const imf_fft_len& fx,
                               const imf_fft_len& fy, const imf_fft_len& fz, const float2* twx,
                               const float2* twy, const float2* twz, hipStream_t s, int stage) {
   imf_inv_args a = a_in;
+  // each band (th[k] - band, th[k] + band) as |v - c| <= r in float: c near
+  // its middle, r its half-width from c, widened by 2^-20 so that the rounded
+  // difference of any float inside stays within r (a superset of the band;
+  // what it admits is recomputed exactly); one band: the second repeats it
   for (int k = 0; k < 2; k++) {
-    a.fth_lo[k] = f_down(a.th[k] - a.band);
-    a.fth_hi[k] = f_up(a.th[k] + a.band);
+    const int kk = a.nth < 2 ? 0 : k;
+    const double lo = a.th[kk] - a.band, hi = a.th[kk] + a.band;
+    const float c = (float)(0.5 * (lo + hi));
+    a.fth_c[k] = c;
+    a.fth_r[k] = f_up(std::max(hi - (double)c, (double)c - lo) * (1.0 + 0x1p-20));
   }
   a.fblo = f_down(a.blo);
   a.fbhi = f_up(a.bhi);
-  a.lcwx = 0;
+  // cell widths are powers of two (the block shapes): shifts
+  a.lcwx = a.lcwy = a.lcwz = 0;
   while ((1 << a.lcwx) < a.cwx) a.lcwx++;
-  if (a.cellmin && (1 << a.lcwx) != a.cwx) return hipErrorInvalidValue;
+  while ((1 << a.lcwy) < a.cwy) a.lcwy++;
+  while ((1 << a.lcwz) < a.cwz) a.lcwz++;
+  if (a.cellmin &&
+      ((1 << a.lcwx) != a.cwx || (1 << a.lcwy) != a.cwy || (1 << a.lcwz) != a.cwz))
+    return hipErrorInvalidValue;
   const int h = a.px / 2 + 1;
   hipError_t e = hipSuccess;
   if (stage < 0 || stage == 0) DISPATCH_PLAN(fz.n, a.fplan[0], {
