@@ -109,12 +109,13 @@ def roofline_of(cls, kms, kn, kb, ko, st=None, N=None):
     return out
 
 
-def serving_leg(imf, W, torch, n_req=64, load=0.7, seed=7627004):
+def serving_leg(imf, W, torch, n_req=64, load=0.7, seed=7627004, other_loads=(0.3, 1.0)):
     """The serving mix: n_req requests (grids 64..256^3, binary or density,
     flat or ball cutter, 6-130 orientations of one master Fibonacci set).
     A back-to-back pass calibrates the saturation rate (and fills the spectrum
     cache); the mix is then replayed with Poisson arrivals at `load` times that
-    rate, and the submit-to-completion latencies give p50 / p99."""
+    rate, and the submit-to-completion latencies give p50 / p99.  The same
+    arrivals, rescaled, are replayed at `other_loads` times the rate as well."""
     import numpy as np
     descs = W.serving_stream(n_req, seed=seed)
     cache = {}
@@ -129,16 +130,10 @@ def serving_leg(imf, W, torch, n_req=64, load=0.7, seed=7627004):
         reqs.append((des, fx, dict(tools=d["tool"], dirs=W.fib_hemisphere(130)[d["dir_index"]],
                                    dir_kind=imf.DIR_F64, lam=lam, method=imf.METHOD_FFT)))
     ctx = imf.Context(0)
-    try:
-        vo = sum(int(r[0].numel()) * len(r[2]["dirs"]) for r in reqs)
-        alone = []
-        t0 = time.perf_counter()
-        for des, fx, kw in reqs:
-            _, st = ctx.compute(des, fx, **kw)
-            alone.append(st.t_ms[7])
-        torch.cuda.synchronize()
-        t_sat = time.perf_counter() - t0
-        rate = load * n_req / t_sat
+    vo = sum(int(r[0].numel()) * len(r[2]["dirs"]) for r in reqs)
+
+    def replay(ld, t_sat):
+        rate = ld * n_req / t_sat
         arrive = np.array([d["t"] for d in descs]) * (1.0 / rate) / (descs[-1]["t"] / n_req)
         tickets = []
         t0 = time.perf_counter()
@@ -148,7 +143,28 @@ def serving_leg(imf, W, torch, n_req=64, load=0.7, seed=7627004):
                 time.sleep(dt)
             tickets.append(ctx.submit(des, fx, **kw))
         sts = [ctx.wait(t)[1] for t in tickets]
-        t_all = time.perf_counter() - t0
+        return sts, time.perf_counter() - t0, rate
+
+    try:
+        alone = []
+        t0 = time.perf_counter()
+        for des, fx, kw in reqs:
+            _, st = ctx.compute(des, fx, **kw)
+            alone.append(st.t_ms[7])
+        torch.cuda.synchronize()
+        t_sat = time.perf_counter() - t0
+        sts, t_all, rate = replay(load, t_sat)
+        others = {}
+        for ld in other_loads:
+            s2, t2, r2 = replay(ld, t_sat)
+            lat2 = np.array([st.t_ms[7] for st in s2])
+            others["%.1f" % ld] = {
+                "arrival_rate_per_s": round(r2, 2),
+                "p50_ms": round(float(np.percentile(lat2, 50)), 2),
+                "p99_ms": round(float(np.percentile(lat2, 99)), 2),
+                "throughput_vo_per_s": vo / t2,
+                "slowdown_p50": round(float(np.percentile(lat2 / np.array(alone), 50)), 2),
+                "slowdown_p99": round(float(np.percentile(lat2 / np.array(alone), 99)), 2)}
     finally:
         ctx.close()
     lat = np.array([st.t_ms[7] for st in sts])
@@ -180,7 +196,9 @@ def serving_leg(imf, W, torch, n_req=64, load=0.7, seed=7627004):
             "p99_request": {"grid": int(descs[i99]["n"]), "orientations": len(reqs[i99][2]["dirs"]),
                             "density": bool(descs[i99]["density"]),
                             "alone_ms": round(float(alone[i99]), 2),
-                            "latency_ms": round(float(lat[i99]), 2)}}
+                            "latency_ms": round(float(lat[i99]), 2)},
+            # the same arrivals at other multiples of the saturation rate
+            "other_loads": others}
 
 
 def to_loop_leg(imf, W, torch, iters):
@@ -539,6 +557,9 @@ def main():
             "ms, p99 %.1f ms; back-to-back p50 %.1f ms, max %.1f ms" % (
                 serving["slowdown_p50"], serving["slowdown_p99"], serving["queue_p50_ms"],
                 serving["queue_p99_ms"], serving["alone_p50_ms"], serving["alone_max_ms"]))
+        for ld, v in serving["other_loads"].items():
+            log("serving at %sx saturation: p50 %.1f ms, p99 %.1f ms, %.3e voxel-orientations/s" % (
+                ld, v["p50_ms"], v["p99_ms"], v["throughput_vo_per_s"]))
         torch.cuda.empty_cache()
 
     to_loop = None
