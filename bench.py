@@ -537,7 +537,9 @@ def main():
     del sets
     ctx.close()
     # cold tool-spectrum cache: the same request on a fresh context (every
-    # spectrum, raster and workspace made anew), median of 5 after 2 warm-ups
+    # spectrum, raster and workspace made anew), median of 5 after 2 warm-ups.
+    # A context made right after another one's ~30 GB were released can stall
+    # for seconds; two idle seconds after each destroy avoid that.
     cold_runs = []
     for i in range(7):
         ctx = imf.Context(0)
@@ -548,6 +550,7 @@ def main():
         if i >= 2:
             cold_runs.append(1000 * (time.perf_counter() - t1))
         ctx.close()
+        time.sleep(2.0)
     cold_ms = float(np.median(cold_runs))
     log("cold-cache request: %.1f ms median of %d fresh contexts (%d spectra computed)" % (
         cold_ms, len(cold_runs), sc.cache_misses))
