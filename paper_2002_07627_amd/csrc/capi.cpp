@@ -246,12 +246,16 @@ struct imf_ctx {
   struct Hint {
     unsigned long long F[3] = {0, 0, 0};  // the last three exact maxima, newest first (0: none)
     double delta = 0;                     // relative half-width of the next bracket
+    double listed = 0;                    // bracket entries per orientation last time
   };
   std::map<std::string, Hint> hints;
   // fraction of (block, orientation) pairs the bound kept in the last request
   // with a gamma stack of each shape: sizes the next compact stack
   std::map<std::string, double> gkept;
   bool use_hints = true;
+  // the inverse x pass's appends: -1 deferred after a long bracket, 0 never
+  // deferred, 1 always (IMF_DEFER_APPENDS)
+  int defer_mode = -1;
   // gamma stack of the kept blocks only, at this fraction of all blocks for
   // a request shape not seen before (0: always the full stack), used when
   // the full stack would take more than 1/16 of the budget (room for cached
@@ -388,6 +392,7 @@ extern "C" imf_status imf_create(int device, size_t hbm_budget_bytes, imf_ctx** 
   if (const char* e = std::getenv("IMF_MINFILTER_SYNC")) c->mf_sync = std::atoi(e);
   if (const char* e = std::getenv("IMF_OVERLAP_STACK")) c->overlap_stack = std::atoi(e) != 0;
   if (const char* e = std::getenv("IMF_THRESHOLD_HINTS")) c->use_hints = std::atoi(e) != 0;
+  if (const char* e = std::getenv("IMF_DEFER_APPENDS")) c->defer_mode = std::atoi(e) != 0;
   if (const char* e = std::getenv("IMF_COMPACT_GAMMA")) {
     c->compact_gamma = std::max(0.0, std::min(1.0, std::atof(e)));
     c->compact_forced = true;
@@ -1012,6 +1017,11 @@ static imf_status ensure_rasters(imf_ctx* c, const imf_request* r, const std::ve
 // planning
 // ---------------------------------------------------------------------------
 static const int kFpCap = 16384;  // footprint cells per orientation
+// Bracket entries per orientation above which the inverse x pass defers its
+// appends (measured: 256^3 x 130 lists about 2e3 per orientation, faster
+// appended at once; 384^3 x 512 in a TO loop about 2e5, whose x pass takes
+// 147 instead of 219 ms per iteration with the appends deferred).
+static const double kDeferListed = 2e4;
 
 struct Plan {
   int nd, n[3];
@@ -1072,6 +1082,9 @@ struct Plan {
   bool hinted = false;
   double blo = 0, bhi = 0, hint_delta = 0;
   double hint_pred = 0;  // the expected F_max (fixed point)
+  // the inverse x pass writes its bracket (and guard-band) entries after its
+  // rows, one reservation per wave: the last bracket of this shape was long
+  bool defer_appends = false;
   // workspace layout (bytes)
   size_t ws_bytes;
   long long spec_elems;
@@ -1301,11 +1314,13 @@ static imf_status make_plan(imf_ctx* c, const imf_request* r, const imf_outputs*
       p.hinted = true;
       p.hint_pred = pred;
       p.hint_delta = h.delta;
+      p.defer_appends = c->defer_mode < 0 && h.listed > kDeferListed;
       const double th = r->lambda * pred * p.scale;
       p.blo = th * (1.0 - p.hint_delta) - p.E;
       p.bhi = th * (1.0 + p.hint_delta) + p.E;
     }
   }
+  if (c->defer_mode == 1) p.defer_appends = true;
   if (p.known && p.two_phase) {  // second pass: the masks' threshold is theta_B
     p.two_phase = false;
     p.gam = false;
@@ -1764,8 +1779,8 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
     put(&p.B, sizeof(p.B));
     put(p.P, sizeof(p.P));
     // launch parameters the autotuner may change after a capture
-    const int lp[6] = {p.shape, p.tuned_batch, p.tuned_shape, p.wg_per_cu, c->mf_sync,
-                       p.fft_plan};
+    const int lp[7] = {p.shape, p.tuned_batch, p.tuned_shape, p.wg_per_cu, c->mf_sync,
+                       p.fft_plan, (int)p.defer_appends};
     put(lp, sizeof lp);
     const int sw[3] = {(int)c->lattice_runs, (int)c->spread_order, (int)c->overlap_stack};
     put(sw, sizeof sw);
@@ -1927,6 +1942,7 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
       ia.cellmin = cm_fused ? cellmin : nullptr;
       for (int k = 0; k < 3; k++) ia.fplan[k] = (p.fft_plan >> (2 * k)) & 3;
       ia.fused = fused[b];
+      ia.defer = p.defer_appends ? 1 : 0;
       ia.cell_stride = p.cell_stride;
       ia.cwx = cwx;
       ia.cwy = cwy;
@@ -2365,6 +2381,7 @@ static imf_status run_request(imf_ctx* c, const imf_request* r, const imf_output
         h.F[2] = old->second.F[1];
       }
       h.F[0] = pd.Fq;
+      h.listed = pd.p.hinted ? (double)pd.host[23] / std::max(pd.p.nO, 1) : 0.0;
       // next half-width: 2.5 times this prediction's relative error, decaying
       // by 15% per request, within [0.05%, 6%].  A miss costs a second pass
       // (about the whole request again) and the width only its listed

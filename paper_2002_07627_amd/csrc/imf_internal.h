@@ -273,6 +273,9 @@ struct imf_inv_args {
   int fplan[3];
   // 1: some descriptors of the batch carry tmid (no spectrum)
   int fused;
+  // 1: the x pass counts its guard-band and bracket entries and writes them
+  // after its rows, with one list reservation per wave (many entries expected)
+  int defer;
   // set by imf_launch_inverse from the fields above, so float compares
   // select a superset of the double intervals: |g - fth_c[k]| <= fth_r[k]
   // for (th[k] - band, th[k] + band), fblo < g <= fbhi (bounds rounded

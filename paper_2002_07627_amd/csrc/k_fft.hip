@@ -905,7 +905,7 @@ __global__ void __launch_bounds__(NTH) k_inv_z_product(imf_inv_args a, imf_fft_l
 // The compile-time plans are held to 8 waves per SIMD: the epilogue's scalar
 // state would otherwise take the SGPR count just past that occupancy's limit
 // (the few scalars over it live in vector lanes instead).
-template <int CT, int MAXE, int NT, int NTH = IMF_WG, int SPLIT = 0>
+template <int CT, int MAXE, int NT, int NTH = IMF_WG, int SPLIT = 0, bool DEFER = false>
 __global__ void __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(NT > 0 ? 8 : 1)))
 k_inv_x_c2r(imf_inv_args a, imf_fft_len L, const float2* __restrict__ twg) {
   extern __shared__ float2 smem[];
@@ -977,7 +977,51 @@ k_inv_x_c2r(imf_inv_args a, imf_fft_len L, const float2* __restrict__ twg) {
   const unsigned tile_end = (unsigned)n * FS;
   // (z, y) of the tile's first row; a wave's rows follow by counting
   const int z0 = row0 / my, y0 = row0 - z0 * my;
-  for (int rr = wave; rr < 2 * CT; rr += NTH / 64) {
+  // One 64-voxel chunk of a row: its values (rounded when binary) and which
+  // of them are rare entries, overlaps to recompute exactly (guard band) and
+  // entries of the expected threshold's bracket.  FULL: every lane lies
+  // inside the row.
+  struct ChunkVals {
+    float v;
+    bool in, flag, brk;
+  };
+  auto eval = [&](unsigned i0, int ch, auto full) {
+    constexpr bool FULL = decltype(full)::value;
+    ChunkVals c;
+    const int x = ch * 64 + lane;
+    c.in = FULL || x < mx;
+    // tile position (x + sh) mod n: for x < mx, x + sh < 2n and below n the
+    // unsigned difference wraps above the sum (rr < FS); lanes past the row's
+    // end read an in-tile value that is discarded
+    const unsigned t = i0 + (unsigned)ch * (64 * FS);
+    c.v = Xf[FULL ? min(t, t - tile_end) : min(min(t, t - tile_end), tile_end - 1)];
+    c.flag = false;
+    if (a.binary) {
+      const float G = rintf(c.v);
+      const float e = c.in ? fabsf(c.v - G) : 0.f;
+      local_err = fmaxf(local_err, e);
+      c.flag = e > a.delta;
+      c.v = G;
+    } else if (a.nth) {  // within either band (the second repeats the first for one)
+      c.flag = c.in & ((fabsf(c.v - a.fth_c[0]) <= a.fth_r[0]) |
+                       (fabsf(c.v - a.fth_c[1]) <= a.fth_r[1]));
+    }
+    c.brk = a.blist && c.in && c.v > a.fblo && c.v <= a.fbhi;
+    return c;
+  };
+  // The rare entries are appended where they are found (an atomic per chunk
+  // that has any), or with DEFER only counted here (wave-wide ballots), with
+  // a bit per chunk that has any: the wave then reserves its list slots with
+  // one atomic per list at the end and writes the entries in a second sweep
+  // over those chunks (the tile stays in LDS).  An atomic per chunk makes the
+  // wave wait for its return, and with it for every store it has in flight:
+  // with many entries (a wide bracket) the deferred form is faster, with few
+  // the immediate one, whose loop keeps fewer scalars live.
+  unsigned long long emask = 0;  // bit 16 rowi + chunk (rows of this wave)
+  int nflag = 0, nbrk = 0;
+  const bool track = nch <= 16 && 2 * CT <= 4 * (NTH / 64);  // the mask holds every chunk
+  int rowi = 0;
+  for (int rr = wave; rr < 2 * CT; rr += NTH / 64, rowi++) {
     const int row = row0 + rr;
     if (row >= rows) break;
     int zz = z0, yy = y0 + rr;
@@ -991,49 +1035,36 @@ k_inv_x_c2r(imf_inv_args a, imf_fft_len L, const float2* __restrict__ twg) {
             ? a.cellmin + q * a.cell_stride + ((zz >> a.lcwz) * cdy + (yy >> a.lcwy)) * cdx
             : nullptr;
     const unsigned i0 = __umul24((unsigned)(lane + sh), FS) + (unsigned)rr;
-    // one 64-voxel chunk; FULL: every lane lies inside the row
     auto chunk = [&](int ch, auto full) {
       constexpr bool FULL = decltype(full)::value;
       const int x = ch * 64 + lane;
-      const bool in = FULL || x < mx;
-      // tile position (x + sh) mod n: for x < mx, x + sh < 2n and below n
-      // the unsigned difference wraps above the sum (rr < FS); lanes past the
-      // row's end read an in-tile value that is discarded
-      const unsigned t = i0 + (unsigned)ch * (64 * FS);
-      float v = Xf[FULL ? min(t, t - tile_end) : min(min(t, t - tile_end), tile_end - 1)];
-      // overlaps to recompute exactly (guard band) and entries of the
-      // expected threshold's bracket are rare: found per lane, handled on a
-      // branch the wave takes only when some lane has one
-      bool flag = false;
-      if (a.binary) {
-        const float G = rintf(v);
-        const float e = in ? fabsf(v - G) : 0.f;
-        local_err = fmaxf(local_err, e);
-        flag = e > a.delta;
-        v = G;
-      } else if (a.nth) {  // within either band (the second repeats the first for one)
-        flag = in & ((fabsf(v - a.fth_c[0]) <= a.fth_r[0]) | (fabsf(v - a.fth_c[1]) <= a.fth_r[1]));
-      }
-      const bool brk = a.blist && in && v > a.fblo && v <= a.fbhi;
-      if (__builtin_expect(__ballot(flag | brk) != 0, 0)) {
-        const int li = row * mx + x;
-        if (flag) {
-          const int slot = atomicAdd(a.flag_cnt, 1);
-          if (slot < a.flag_cap) a.flags[slot] = make_int2(q, li);
-        }
-        if (brk) {  // spread over the orientation's lists by workgroup
-          const long long sl =
-              (long long)(a.q0 + q) * IMF_BR_SLICES + (blockIdx.x % IMF_BR_SLICES);
-          const unsigned slot = atomicAdd(a.bcnt + sl, 1u);
-          if (slot < (unsigned)a.bslot)
-            a.blist[sl * a.bslot + slot] = make_int4(a.q0 + q, li, __float_as_int(v), 0);
+      ChunkVals c = eval(i0, ch, full);
+      if (__builtin_expect(__ballot(c.flag | c.brk) != 0, 0)) {
+        if constexpr (DEFER) {
+          nflag += __popcll(__ballot(c.flag));
+          nbrk += __popcll(__ballot(c.brk));
+          if (track) emask |= 1ull << (16 * rowi + ch);
+        } else {
+          const int li = row * mx + x;
+          if (c.flag) {
+            const int slot = atomicAdd(a.flag_cnt, 1);
+            if (slot < a.flag_cap) a.flags[slot] = make_int2(q, li);
+          }
+          if (c.brk) {  // spread over the orientation's lists by workgroup
+            const long long sl =
+                (long long)(a.q0 + q) * IMF_BR_SLICES + (blockIdx.x % IMF_BR_SLICES);
+            const unsigned slot = atomicAdd(a.bcnt + sl, 1u);
+            if (slot < (unsigned)a.bslot)
+              a.blist[sl * a.bslot + slot] = make_int4(a.q0 + q, li, __float_as_int(c.v), 0);
+          }
         }
       }
+      float v = c.v;
       if (FULL) {
         drow[x] = v;
       } else {
-        if (in) drow[x] = v;
-        v = in ? v : INFINITY;
+        if (c.in) drow[x] = v;
+        v = c.in ? v : INFINITY;
       }
       if (cmrow) {
         // minima of the row's cells over the values just written (rounded
@@ -1050,6 +1081,42 @@ k_inv_x_c2r(imf_inv_args a, imf_fft_len L, const float2* __restrict__ twg) {
     const int nfull = mx >> 6;
     for (int ch = 0; ch < nfull; ch++) chunk(ch, std::true_type{});
     if (nfull < nch) chunk(nfull, std::false_type{});
+  }
+  if (DEFER && (nflag | nbrk)) {  // wave-uniform
+    // bracket lists: spread over the orientation's slices by workgroup
+    const long long sl = (long long)(a.q0 + q) * IMF_BR_SLICES + (blockIdx.x % IMF_BR_SLICES);
+    int fbase = 0;
+    unsigned bbase = 0;
+    if (lane == 0) {
+      if (nflag) fbase = atomicAdd(a.flag_cnt, nflag);
+      if (nbrk) bbase = atomicAdd(a.bcnt + sl, (unsigned)nbrk);
+    }
+    fbase = __shfl(fbase, 0);
+    bbase = (unsigned)__shfl((int)bbase, 0);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    rowi = 0;
+    for (int rr = wave; rr < 2 * CT; rr += NTH / 64, rowi++) {
+      const int row = row0 + rr;
+      if (row >= rows) break;
+      const unsigned i0 = __umul24((unsigned)(lane + sh), FS) + (unsigned)rr;
+      for (int ch = 0; ch < nch; ch++) {
+        if (track && !((emask >> (16 * rowi + ch)) & 1ull)) continue;
+        const ChunkVals c = eval(i0, ch, std::false_type{});
+        const unsigned long long bf = __ballot(c.flag), bb = __ballot(c.brk);
+        const int li = row * mx + ch * 64 + lane;
+        if (c.flag) {
+          const int slot = fbase + __popcll(bf & below);
+          if (slot < a.flag_cap) a.flags[slot] = make_int2(q, li);
+        }
+        if (c.brk) {
+          const unsigned slot = bbase + (unsigned)__popcll(bb & below);
+          if (slot < (unsigned)a.bslot)
+            a.blist[sl * a.bslot + slot] = make_int4(a.q0 + q, li, __float_as_int(c.v), 0);
+        }
+        fbase += __popcll(bf);
+        bbase += (unsigned)__popcll(bb);
+      }
+    }
   }
   if (a.binary) {
     for (int o = 32; o > 0; o >>= 1) local_err = fmaxf(local_err, __shfl_xor(local_err, o));
@@ -1315,7 +1382,8 @@ hipError_t imf_launch_inverse(const imf_inv_args& a_in, const imf_fft_len& fx,
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (stage < 0 || stage == 2) DISPATCH_PLAN(fx.n, a.fplan[2], {
     const size_t sm = smem_bytes(fx.n, CT);
-    auto k = k_inv_x_c2r<CT, MAXE, NT, NTHP, SPLIT>;
+    auto k = a.defer ? k_inv_x_c2r<CT, MAXE, NT, NTHP, SPLIT, true>
+                     : k_inv_x_c2r<CT, MAXE, NT, NTHP, SPLIT, false>;
     if ((e = set_smem((const void*)k, sm)) != hipSuccess) return e;
     const long long rows = (long long)a.max_my * a.max_mz;
     hipLaunchKernelGGL(k, dim3((unsigned)((rows + 2 * CT - 1) / (2 * CT)), 1, a.nq), dim3(NTHP),

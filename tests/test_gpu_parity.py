@@ -173,6 +173,29 @@ def test_small_3d_binary_bit_exact(ctx, method):
         assert st.max_frac_err < 0.05
 
 
+def test_binary_deferred_appends_bit_exact(monkeypatch):
+    """The inverse x pass with its guard-band appends written after its rows
+    (IMF_DEFER_APPENDS=1): rounded overlaps, masks and F_max bit-exact, on a
+    grid whose rows take full and partial 64-voxel chunks."""
+    import paper_2002_07627_amd as imf
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    monkeypatch.setenv("IMF_DEFER_APPENDS", "1")
+    d = random_boxes((30, 34, 70), 16, 11)
+    fx = W.fixture_plate(d.shape, 3)
+    tl = W.tool(W.TOOL_FLAT, 1.5, 6, 3, 5)
+    dirs = W.lattice26()
+    c = imf.Context(0)
+    try:
+        out, st = c.compute(dev(d), dev(fx), tools=tl, dirs=dirs, dir_kind=imf.DIR_LATTICE,
+                            method=imf.METHOD_FFT)
+    finally:
+        c.close()
+    ref = oracle.imf(oracle.Request(d, fx, tools=tl, dirs=dirs, dir_kind=1))
+    check_binary(out, ref)
+    assert st.F_max == ref["F_max"] and st.max_frac_err < 0.05
+
+
 def test_plain_batched_and_cached_are_identical(ctx):
     import paper_2002_07627_amd as imf
     d = random_boxes((32, 32, 32), 12, 6)
@@ -267,15 +290,18 @@ def test_density_two_phase_masks(ctx):
     assert not (m.any(axis=0) & B).any() and ((m.any(axis=0) | B) == om).all()
 
 
-@pytest.mark.parametrize("masks", [True, False])
-def test_density_second_pass_without_stored_overlaps(masks, monkeypatch):
+@pytest.mark.parametrize("masks,defer", [(True, "-1"), (False, "-1"), (True, "1")])
+def test_density_second_pass_without_stored_overlaps(masks, defer, monkeypatch):
     """Without room for the overlaps of every orientation, the first pass ends
     at the exact F_max and a second pass decides lambda F_max like a known
-    threshold; with and without mask outputs."""
+    threshold; with and without mask outputs, and with the inverse x pass's
+    guard-band appends written after its rows (IMF_DEFER_APPENDS=1)."""
     import paper_2002_07627_amd as imf
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     monkeypatch.setenv("IMF_OVERLAP_STACK", "0")
+    if defer != "-1":
+        monkeypatch.setenv("IMF_DEFER_APPENDS", defer)
     d = W.design_density(30, seed=14)
     fx = W.fixture_plate(d.shape, 2)
     tl = W.tool(W.TOOL_BALL, 2, 7, 3, 5)
@@ -292,17 +318,20 @@ def test_density_second_pass_without_stored_overlaps(masks, monkeypatch):
     assert st.passes == 2
 
 
-@pytest.mark.parametrize("stack", ["1", "0"])
-def test_density_expected_threshold_bracket(stack, monkeypatch):
+@pytest.mark.parametrize("stack,defer", [("1", "-1"), ("0", "-1"), ("1", "1"), ("0", "1")])
+def test_density_expected_threshold_bracket(stack, defer, monkeypatch):
     """A request shape seen before lists the overlaps around lambda times its
     last F_max during the inverse transform: the same request again holds the
     band in that bracket (no scan, no second pass); a different design of the
     same shape may miss it and then takes the scan (or the second pass).  Every
-    result is exact."""
+    result is exact, with the bracket's appends made where they are found or
+    written after the x pass's rows (IMF_DEFER_APPENDS=1)."""
     import paper_2002_07627_amd as imf
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     monkeypatch.setenv("IMF_OVERLAP_STACK", stack)
+    if defer != "-1":
+        monkeypatch.setenv("IMF_DEFER_APPENDS", defer)
     tl = W.tool(W.TOOL_BALL, 2, 7, 3, 5)
     dirs = W.fib_hemisphere(9)
     lam = 0.04
