@@ -1131,6 +1131,7 @@ static std::string tune_key(const Plan& p) {
 // the context defaults; a candidate being timed by the autotuner overrides both
 static void ctx_tuned_params(imf_ctx* c, Plan& p) {
   p.tuned_batch = 8;
+  p.fft_plan = p.method == IMF_METHOD_FFT ? imf_fft_default_plan(p.P[2], p.P[1], p.P[0]) : 0;
   p.tuned_shape = c->mf_shape;
   p.wg_per_cu = c->mf_wg_per_cu;
   auto it = c->tuned.find(tune_key(p));
@@ -2743,7 +2744,7 @@ extern "C" imf_status imf_autotune(imf_ctx* c, const imf_request* r, const imf_o
   imf_ctx::Tuned best;
   best.shape = p0.tuned_shape;
   best.wg = p0.wg_per_cu;
-  best.fft = 0;
+  best.fft = p0.fft_plan;
   double best_ms = 1e300;
   // batch width with the current tile shapes
   for (int B : {1, 2, 4, 8, 12, 16}) {
@@ -2776,8 +2777,9 @@ extern "C" imf_status imf_autotune(imf_ctx* c, const imf_request* r, const imf_o
   // at a time with the others held (FFT method only); the same 2% margin
   if (p0.method == IMF_METHOD_FFT)
     for (int pass = 0; pass < 3; pass++)
-      for (int v = 1; v < 4 && imf_fft_plan_variants(p0.P[2 - pass]); v++) {
+      for (int v = 0; v < 4 && imf_fft_plan_variants(p0.P[2 - pass]); v++) {
         const int cand = (best.fft & ~(3 << (2 * pass))) | (v << (2 * pass));
+        if (cand == best.fft) continue;
         double ms;
         STCHK(time_one(best.batch, best.shape, best.wg, cand, ms));
         if (ms < 0.98 * best_ms) {

@@ -286,6 +286,9 @@ struct imf_inv_args {
 #define IMF_BR_SLICES 64
 // true when the inverse passes of length n have transform plans other than 0
 bool imf_fft_plan_variants(int n);
+// transform plans (z | y << 2 | x << 4) of the inverse passes used when no
+// autotuned entry sets them (by occupancy of each pass's kernels)
+int imf_fft_default_plan(int pz, int py, int px);
 // stage: -1 all, 0 product + z pass, 1 y pass, 2 x pass (complex-to-real) + epilogue
 hipError_t imf_launch_inverse(const imf_inv_args& a, const imf_fft_len& fx,
                               const imf_fft_len& fy, const imf_fft_len& fz, const float2* twx,

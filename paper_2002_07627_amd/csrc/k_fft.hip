@@ -15,6 +15,8 @@
 #include "imf_internal.h"
 
 #include <cmath>
+#include <mutex>
+#include <map>
 #include <type_traits>
 
 #define CT_MAX 16
@@ -1244,6 +1246,48 @@ static hipError_t set_smem(const void* fn, size_t bytes) {
   if (bytes > 64 * 1024)
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   return hipSuccess;
+}
+
+// Workgroups of one inverse pass (0 product + z, 1 y, 2 x) of length n under
+// a transform plan that fit one CU at once (registers and LDS), 0 if unknown.
+static int inverse_pass_occupancy(int pass, int n, int plan) {
+  int nb = 0;
+  DISPATCH_PLAN(n, plan, {
+    const size_t sm = smem_bytes(n, CT);
+    const void* k = pass == 0 ? (const void*)k_inv_z_product<CT, MAXE, NT, NTHP, SPLIT, false>
+                    : pass == 1
+                        ? (const void*)k_pass_strided<CT, MAXE, NT, PASS_INV_Y, NTHP, SPLIT>
+                        : (const void*)k_inv_x_c2r<CT, MAXE, NT, NTHP, SPLIT, false>;
+    if (set_smem(k, sm) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, NTHP, sm) != hipSuccess)
+      nb = 0;
+  });
+  (void)hipGetLastError();
+  return nb;
+}
+
+// The transform plans of the inverse passes used when no autotuned entry
+// sets them: per pass the base radices (plan 1) where their registers let
+// more workgroups share a CU than the composite radices' do (at length 576
+// the composite y pass holds 85 VGPRs, two workgroups per CU, the base one 80,
+// three: 161 -> 122 ms per 384^3 x 512 iteration), else plan 0.
+int imf_fft_default_plan(int pz, int py, int px) {
+  static std::mutex mu;
+  static std::map<long long, int> memo;
+  const long long key = ((long long)pz << 40) | ((long long)py << 20) | px;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = memo.find(key);
+  if (it != memo.end()) return it->second;
+  int plan = 0;
+  const int len[3] = {pz, py, px};
+  for (int pass = 0; pass < 3; pass++) {
+    if (!imf_fft_plan_variants(len[pass])) continue;
+    const int b0 = inverse_pass_occupancy(pass, len[pass], 0);
+    const int b1 = inverse_pass_occupancy(pass, len[pass], 1);
+    if (b0 > 0 && b1 > b0) plan |= 1 << (2 * pass);
+  }
+  memo[key] = plan;
+  return plan;
 }
 
 hipError_t imf_launch_fwd_design(const imf_fwd_design_args& a, const imf_fft_len& fx,
