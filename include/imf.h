@@ -248,7 +248,9 @@ imf_status imf_cancel(imf_ctx* ctx, uint64_t ticket);
  * 16x4x1, 8x4x2) and resident workgroups per CU (4, 6, 8) of the sharp-point
  * minimum, then (FFT method, transform lengths 192-768) the transform plan of
  * each inverse pass z, y, x in turn: composite radices or one stage per radix
- * 8, 4, 2, 3, 5, 7, full- or half-width tiles (imf_stats.fft_plan).  Each
+ * 8, 4, 2, 3, 5, 7, full- or half-width tiles (imf_stats.fft_plan; untuned
+ * shapes take per pass the radix plan whose kernel fits more workgroups per
+ * CU, the composite one on a tie).  Each
  * candidate runs kernel by kernel after a warm-up; the fastest is remembered
  * (an alternative replaces the current choice only when 2% faster), and
  * later requests of that shape with batch = 0 use it.  Captured graphs are
