@@ -170,14 +170,17 @@ def test_c3_256_density_130_exact_at_stratified_voxels(ctx):
     print("pairs within E of theta: %d" % int((np.abs(gam / Q - theta / Q) <= E).sum()))
 
 
-def test_c5_384_density_512_loop_sampled():
+def test_c5_384_density_512_loop_sampled(monkeypatch):
     """The 384^3 density TO-loop workload (512 orientations, flat cutter,
     fixtures and clamps; the spectra do not all fit the cache): f at a voxel
     against all 512 exact gammas, sampled mask bits, and a perturbed-design
-    iteration on the warm context equal to the same request on a fresh one."""
+    iteration on the warm context equal to the same request on a fresh one.
+    The inverse x pass writes its guard-band and bracket entries after its
+    rows, as a TO loop at this size does once its brackets grow long."""
     import paper_2002_07627_amd as imf
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
+    monkeypatch.setenv("IMF_DEFER_APPENDS", "1")
     w = W.c5()
     kw = dict(tools=w.tool, dirs=w.dirs, dir_kind=imf.DIR_F64, lam=w.lam, tau=w.tau,
               method=imf.METHOD_FFT)
