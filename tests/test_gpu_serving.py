@@ -257,6 +257,10 @@ def test_mix_equals_alone_large_grids(imf_mod):
         for i, t in enumerate(tickets):
             o, st = ctx.wait(t)
             assert st.t_ms[7] >= st.queue_ms >= 0
+            # host time planning and enqueueing under the context lock, and
+            # waiting for it: both part of the time after admission
+            assert st.hold_ms > 0 and st.lock_ms >= 0
+            assert st.queue_ms + st.lock_ms + st.hold_ms <= st.t_ms[7] + 1e-3
             _same(o, alone[i], st.passes == passes[i], i, st.F_max, reqs[i]["lam"])
     finally:
         ctx.close()
