@@ -65,7 +65,13 @@ typedef struct imf_ctx imf_ctx;
  * context's own allocations (0: 90% of the free device memory): workspaces,
  * tool rasters and cached tool spectra.  Spectra are cached while they fit
  * and evicted, least recently used first, when a workspace needs their room
- * (after one device synchronization; captured graphs are then dropped). */
+ * (after one device synchronization; captured graphs are then dropped).
+ * Environment variables read here set launch parameters and never change a
+ * result: IMF_MINFILTER_SHAPE, IMF_MINFILTER_WG_PER_CU, IMF_MINFILTER_SYNC,
+ * IMF_BOUND_MIN_VOXELS, IMF_AXIS_RUNS, IMF_GIVEN_ORDER, IMF_OVERLAP_STACK,
+ * IMF_THRESHOLD_HINTS, IMF_COMPACT_GAMMA, IMF_DEFER_APPENDS (the inverse x
+ * pass's guard-band and bracket entries written after its rows: 1 always, 0
+ * never, unset after a long bracket) and IMF_SERVE_WORKERS. */
 imf_status imf_create(int device, size_t hbm_budget_bytes, imf_ctx** ctx);
 imf_status imf_destroy(imf_ctx* ctx);
 /* Message of the last error of the calling thread (never NULL). */
