@@ -753,8 +753,13 @@ __global__ void __launch_bounds__(IMF_WG) k_bound(imf_min_args a, int qi) {
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += IMF_WG) fpl[i] = fpg[1 + c0 + i];
     __syncthreads();
-    if (live)
-      for (int i = 0; i < n; i++) lbo = min(lbo, cm[cb + fpl[i]]);
+    if (live) {
+      // 32-bit cell indices (an orientation's cell grid is far below 2^32)
+      // off the uniform base: one register per load, 16 loads in flight
+      const unsigned cbu = (unsigned)cb;
+#pragma unroll 16
+      for (int i = 0; i < n; i++) lbo = min(lbo, cm[cbu + (unsigned)fpl[i]]);
+    }
   }
   const float lb = nfp < 0 ? -INFINITY : ord2f(lbo);
   const long long blk = ((long long)bz * G.nby + by) * G.nbx + bx;
