@@ -867,9 +867,10 @@ __global__ void __launch_bounds__(IMF_WG) k_scatter(imf_min_args a, int qi) {
 }
 
 // The minimum over the sharp points for one block (one wave): gathers of the
-// sparse-table levels at the run offsets staged in LDS, 16 independent
-// gathers in flight per wave; then the running minimum f, the gamma stack, the
-// block maximum of f (branch and bound) and the mask chunk.
+// sparse-table levels at the run offsets staged in LDS, 8 independent gathers
+// in flight per wave between the barriers of the in-step walk; then the
+// running minimum f, the gamma stack, the block maximum of f (branch and
+// bound) and the mask chunk.
 template <int WX, int WY, int WZ, bool SYNC = false>
 __device__ __forceinline__ void mf_block(const imf_min_args& a, const imf_orient_desc& d,
                                          const mf_run* rr, int qi, int bx, int by, int bz,
