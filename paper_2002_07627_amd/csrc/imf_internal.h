@@ -155,22 +155,49 @@ struct mf_geom {
   }
 };
 
-// exact overlap at translation t: sum over x-runs of T of row sums (Eq. ident)
+// One x-run of T at translation t: the prefix-sum row and the two indices
+// whose difference is the run's sum.  A run outside the grid (or clipped to
+// nothing) gets row 0 and indices 0, 0 (a difference of 0), so callers load
+// without branching.
+__device__ __forceinline__ void exact_run_terms(const imf_run u, const long long* ps, int nx,
+                                                int ny, int nz, int tx, int ty, int tz,
+                                                const long long*& row, int& a0, int& a1) {
+  const int y = ty + u.y, z = tz + u.z;
+  const int x0 = max(tx + u.x, 0), x1 = min(tx + u.x + u.len, nx);
+  const bool ok = y >= 0 && y < ny && z >= 0 && z < nz && x1 > x0;
+  row = ps + ((long long)(ok ? z : 0) * ny + (ok ? y : 0)) * (nx + 1);
+  a0 = ok ? x0 : 0;
+  a1 = ok ? x1 : 0;
+}
+
+// exact overlap at translation t: sum over x-runs of T of row sums (Eq. ident).
+// Four runs at a time, their loads in flight together (the integer sum does
+// not depend on the order).
 __device__ __forceinline__ long long exact_overlap(const imf_orient_desc& d,
                                                    const long long* __restrict__ ps, int nx,
                                                    int ny, int nz, int tx, int ty, int tz) {
   const imf_run* rl = d.truns;
+  const int n = d.n_truns;
   long long s = 0;
-  for (int r = 0; r < d.n_truns; r++) {
-    const imf_run u = rl[r];
-    const int y = ty + u.y, z = tz + u.z;
-    if (y < 0 || y >= ny || z < 0 || z >= nz) continue;
-    int x0 = tx + u.x, x1 = x0 + u.len;
-    x0 = max(x0, 0);
-    x1 = min(x1, nx);
-    if (x1 <= x0) continue;
-    const long long* row = ps + ((long long)z * ny + y) * (nx + 1);
-    s += row[x1] - row[x0];
+  int r = 0;
+  for (; r + 4 <= n; r += 4) {
+    long long hi[4], lo[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const long long* row;
+      int a0, a1;
+      exact_run_terms(rl[r + k], ps, nx, ny, nz, tx, ty, tz, row, a0, a1);
+      hi[k] = row[a1];
+      lo[k] = row[a0];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; k++) s += hi[k] - lo[k];
+  }
+  for (; r < n; r++) {
+    const long long* row;
+    int a0, a1;
+    exact_run_terms(rl[r], ps, nx, ny, nz, tx, ty, tz, row, a0, a1);
+    s += row[a1] - row[a0];
   }
   return s;
 }

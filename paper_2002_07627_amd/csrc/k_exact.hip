@@ -26,22 +26,29 @@ static unsigned grid_cap(long long n, long long cap) {
   return (unsigned)(b < 1 ? 1 : (b > cap ? cap : b));
 }
 
-// exact overlap at translation t, the tool's x-runs split over the wave's lanes
+// exact overlap at translation t, the tool's x-runs split over the wave's
+// lanes, four runs per lane with their loads in flight together (lanes past
+// the last run read the last one and add 0)
 __device__ __forceinline__ long long exact_overlap_wave(const imf_orient_desc& d,
                                                         const long long* __restrict__ ps, int nx,
                                                         int ny, int nz, int tx, int ty, int tz) {
   const int lane = threadIdx.x & 63;
+  const int n = d.n_truns;
   long long s = 0;
-  for (int r = lane; r < d.n_truns; r += 64) {
-    const imf_run u = d.truns[r];
-    const int y = ty + u.y, z = tz + u.z;
-    if (y < 0 || y >= ny || z < 0 || z >= nz) continue;
-    int x0 = tx + u.x, x1 = x0 + u.len;
-    x0 = max(x0, 0);
-    x1 = min(x1, nx);
-    if (x1 <= x0) continue;
-    const long long* row = ps + ((long long)z * ny + y) * (nx + 1);
-    s += row[x1] - row[x0];
+  for (int r0 = 0; r0 < n; r0 += 4 * 64) {
+    long long hi[4], lo[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const int r = r0 + 64 * k + lane;
+      const long long* row;
+      int a0, a1;
+      exact_run_terms(d.truns[r < n ? r : n - 1], ps, nx, ny, nz, tx, ty, tz, row, a0, a1);
+      if (r >= n) a0 = a1 = 0;
+      hi[k] = row[a1];
+      lo[k] = row[a0];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; k++) s += hi[k] - lo[k];
   }
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
   return s;
