@@ -1403,6 +1403,7 @@ static imf_status make_plan(imf_ctx* c, const imf_request* r, const imf_outputs*
     add(sizeof(unsigned long long) * (size_t)p.cand_cap);  // their exact f
     add(sizeof(int4) * (size_t)p.band_cap);              // band entries
     add(sizeof(unsigned) * (size_t)p.nO * IMF_BR_SLICES);  // bracket list counts
+    add(sizeof(uint64_t) * (size_t)r->nz * r->ny * p.words);  // Omega_0 as row bits
   }
   if (p.bnb) {
     add(sizeof(float) * p.B * p.cell_stride);           // cell minima
@@ -1639,6 +1640,7 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
   unsigned long long* cmin = p.exact ? carve<unsigned long long>(ar, p.cand_cap) : nullptr;
   int4* band = p.exact ? carve<int4>(ar, p.band_cap) : nullptr;
   unsigned* bcnt = p.exact ? carve<unsigned>(ar, (size_t)p.nO * IMF_BR_SLICES) : nullptr;
+  uint64_t* om_bits = p.exact ? carve<uint64_t>(ar, (size_t)r->nz * r->ny * p.words) : nullptr;
   const int bslot = p.exact ? (int)(p.band_cap / ((long long)p.nO * IMF_BR_SLICES)) : 0;
   unsigned int* cellmin = p.bnb ? carve<unsigned int>(ar, p.B * p.cell_stride) : nullptr;
   // the bound's cell minima come from the inverse x pass (and the recheck)
@@ -2139,6 +2141,8 @@ static imf_status compute_launch(imf_ctx* c, const imf_request* r, const imf_out
     // the band: from the listed bracket when it holds it, else from a scan of
     // the stored overlaps (without them a second pass follows)
     if (p.gst) HIPCHK(imf_launch_band_scan(ea, p.max_vol, s));
+    HIPCHK(imf_launch_om_bits(om, r->nx, (long long)r->ny * r->nz, om_bits, s));
+    ea.om_bits = om_bits;
     HIPCHK(imf_launch_band_exact(ea, s));
     tm.mark(9);
   }

@@ -439,7 +439,11 @@ struct imf_exact_args {
   // bracket lists of the inverse x pass (IMF_BR_SLICES per orientation), or NULL
   const int4* blist; const unsigned int* bcnt; int bslot;
   unsigned int* blisted;         // total entries the bracket lists hold
+  const uint64_t* om_bits;       // Omega_0 as row bits [nz][ny][words] (the band's sweep)
 };
+// Omega_0 (one byte per voxel) packed into row words, bit x % 64 of word x / 64
+hipError_t imf_launch_om_bits(const uint8_t* om, int nx, long long rows, uint64_t* out,
+                              hipStream_t s);
 // candidates of the maximum, their exact f (cmin: cand_cap words of scratch),
 // and F_max = the largest of those
 hipError_t imf_launch_exact_fmax(const imf_exact_args& a, unsigned long long* cmin,

@@ -342,14 +342,15 @@ __device__ __forceinline__ void band_entry(const imf_exact_args& a, const int4 e
       const int y = ty + u.y, z = tz + u.z;
       if (y < 0 || y >= a.ny || z < 0 || z >= a.nz) continue;
       const int x0 = max(tx + u.x, 0), x1 = min(tx + u.x + u.len, a.nx);
-      const long long vrow = ((long long)z * a.ny + y) * a.nx;
-      uint64_t* row = mq + ((long long)z * a.ny + y) * words;
+      const long long rw = ((long long)z * a.ny + y) * words;
+      uint64_t* row = mq + rw;
       for (int x = x0; x < x1;) {
         const int w = x >> 6;
         const int xe = min(x1, (w + 1) << 6);
-        uint64_t bits = 0;
-        for (int xx = x; xx < xe; xx++)
-          if (a.omega0[vrow + xx]) bits |= 1ull << (xx & 63);
+        // bits x .. xe - 1 of word w, those of Omega_0
+        const int b0 = x & 63, b1 = xe - (w << 6);
+        const uint64_t span = (b1 == 64 ? ~0ull : (1ull << b1) - 1ull) & ~((1ull << b0) - 1ull);
+        const uint64_t bits = span & a.om_bits[rw + w];
         if (bits && (row[w] & bits) != bits)
           atomicOr((unsigned long long*)(row + w), (unsigned long long)bits);
         x = xe;
@@ -383,6 +384,27 @@ __global__ void __launch_bounds__(IMF_WG) k_band_exact(imf_exact_args a) {
     if (err > 0.f) err_max(a.err_bits, err);
     if (evals) atomicAdd(a.n_exact, evals);
   }
+}
+
+// one wave per 64-voxel row word
+__global__ void __launch_bounds__(IMF_WG) k_om_bits(const uint8_t* __restrict__ om, int nx,
+                                                    long long rows, uint64_t* __restrict__ out) {
+  const int words = (nx + 63) >> 6;
+  const long long wv = (long long)blockIdx.x * (IMF_WG / 64) + (threadIdx.x >> 6);
+  if (wv >= rows * words) return;  // uniform over the wave
+  const long long rr = wv / words;
+  const int x = (int)(wv - rr * words) * 64 + (threadIdx.x & 63);
+  const unsigned long long m = __ballot(x < nx && om[rr * nx + x]);
+  if ((threadIdx.x & 63) == 0) out[wv] = m;
+}
+
+hipError_t imf_launch_om_bits(const uint8_t* om, int nx, long long rows, uint64_t* out,
+                              hipStream_t s) {
+  const long long waves = rows * ((nx + 63) / 64);
+  const long long per = IMF_WG / 64;
+  hipLaunchKernelGGL(k_om_bits, dim3((unsigned)((waves + per - 1) / per)), dim3(IMF_WG), 0, s,
+                     om, nx, rows, out);
+  return hipGetLastError();
 }
 
 hipError_t imf_launch_band_exact(const imf_exact_args& a, hipStream_t s) {
